@@ -1,0 +1,491 @@
+"""FP64 oracle: dynamically screened ISTA / FISTA for the Lasso and the Group-Lasso.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never imported by the
+product path.
+
+Notation follows the paper: dictionary D (N x K) with atoms d_i, observation y,
+penalty lambda, primal x, FISTA auxiliary u, dual variable theta, feasible dual
+point v = mu * theta, sphere centre c and radius r, screened set I_t.
+
+Readings of points the paper leaves open (each one is listed in the design doc):
+
+* Step size: the paper sets L_t by backtracking (Table 1) without constants;
+  here L is a constant >= ||D||_2^2 supplied by the caller (default: the exact
+  largest eigenvalue of D D^T).  A constant L >= ||D_t||_2^2 stays valid after
+  every screening because removing columns cannot increase the spectral norm.
+* Initialisation X_0: x_0 = u_0 = 0 and l_0 = 1.
+* Dual scaling uses the correlations z_t = D_{t-1}^T theta_t of the current,
+  already reduced dictionary, as the turnkey instance (Algorithm 5) does.
+* Stopping: the paper stops on a relative objective change.  Here the
+  iteration stops when the duality gap between the primal point at which
+  theta_t was evaluated (x_{t-1} for ISTA, u_{t-1} for FISTA) and the dual
+  point v_t falls below gap_tol * ||y||^2, or after max_iter iterations.  The
+  iterate returned is x_t, the proximal step taken from that primal point;
+  with L >= ||D_t||^2 its objective is no larger, so the same gap bounds it.
+  The last iteration does not screen, so the returned x_t is supported on the
+  complement of the reported screened set.
+* Tests on atoms that are not exactly unit-norm (storage rounding) use the
+  general sphere bound of the group lemma with singleton groups: the margin of
+  atom i is (1 - |d_i^T c|) / ||d_i||, and the DST3 centre is the projection of
+  y/lambda onto the hyperplane {theta : d_*^T theta = 1}.  Both reduce to
+  Lemmas 1 and 2 for unit atoms.
+* Ties in the arg-max defining i_* / g_* go to the smallest index.  A radius
+  whose square rounds below zero is clamped to zero.  An atom exactly at the
+  threshold is kept (the test is a strict inequality).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class OracleResult:
+    x: np.ndarray            # returned primal point (dense, length K)
+    iters: int               # iterations run (0 in the trivial regime lambda >= lambda_*)
+    converged: bool          # gap certificate reached gap_tol * ||y||^2
+    lam: float
+    lam_max: float
+    gap: float               # P(p_{T-1}) - Dual(v_T): certificate of the last iteration
+    primal_p: float          # P(p_{T-1}), p the point theta_T was evaluated at
+    primal: float            # P(x_T), evaluated explicitly
+    dual: float              # Dual(v_T)
+    mu: float                # dual-scaling factor of the last iteration
+    r_min: float             # smallest radius seen (inf when nothing was tested)
+    screened: np.ndarray     # bool, length K: atoms in the reported screened set
+    screened_groups: np.ndarray | None = None   # bool, length G (group problems)
+    L: float = 0.0
+    history: list = field(default_factory=list)
+
+
+# ----------------------------------------------------------------------------
+# Problem-level quantities
+# ----------------------------------------------------------------------------
+
+def lambda_max_lasso(D: np.ndarray, y: np.ndarray) -> tuple[float, int]:
+    """lambda_* = ||D^T y||_inf and the first index attaining it.
+
+    Section "Dynamic screening for the Lasso": for lambda >= lambda_* the
+    solution is x = 0.  The signed atom d_* of Lemma 2 is sign(d_{i*}^T y) d_{i*}.
+    """
+    corr = np.abs(D.T @ y)
+    i_star = int(np.argmax(corr))
+    return float(corr[i_star]), i_star
+
+
+def lambda_max_group(D: np.ndarray, y: np.ndarray, groups, w) -> tuple[float, int]:
+    """Equation (gstar): g_* = argmax_g ||D_g^T y|| / w_g and lambda_* its value."""
+    vals = np.array([np.linalg.norm(D[:, g].T @ y) / w[k] for k, g in enumerate(groups)])
+    g_star = int(np.argmax(vals))
+    return float(vals[g_star]), g_star
+
+
+def spectral_norm_sq(D: np.ndarray) -> float:
+    """||D||_2^2, the largest eigenvalue of D D^T (Lipschitz constant of the gradient)."""
+    G = D @ D.T if D.shape[0] <= D.shape[1] else D.T @ D
+    return float(np.linalg.eigvalsh(G)[-1])
+
+
+def group_spectral_norms(D: np.ndarray, groups) -> np.ndarray:
+    """||D_g||_2, the largest singular value of each sub-dictionary (Lemma 6)."""
+    return np.array([np.linalg.norm(D[:, g], 2) if len(g) else 0.0 for g in groups])
+
+
+# ----------------------------------------------------------------------------
+# Proximal operators
+# ----------------------------------------------------------------------------
+
+def soft_threshold(v: np.ndarray, t: float) -> np.ndarray:
+    """Equation (softTh): sign(v) * max(|v| - t, 0)."""
+    return np.sign(v) * np.maximum(np.abs(v) - t, 0.0)
+
+
+def group_soft_threshold(v: np.ndarray, t: float, groups, w) -> np.ndarray:
+    """Equation (gr_softTh): v_g * max(0, (||v_g|| - t w_g) / ||v_g||), 0 when v_g = 0."""
+    out = np.zeros_like(v)
+    for k, g in enumerate(groups):
+        nv = np.linalg.norm(v[g])
+        if nv > 0.0:
+            out[g] = max(0.0, (nv - t * w[k]) / nv) * v[g]
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Duality
+# ----------------------------------------------------------------------------
+
+def primal_objective(D, y, x, lam, omega) -> float:
+    """Equation (1): 1/2 ||D x - y||^2 + lambda * Omega(x)."""
+    res = D @ x - y
+    return 0.5 * float(res @ res) + lam * omega
+
+
+def dual_objective(v, y, lam) -> float:
+    """Equations (dual) / (dual_glasso): 1/2 ||y||^2 - lambda^2/2 ||v - y/lambda||^2."""
+    d = v - y / lam
+    return 0.5 * float(y @ y) - 0.5 * lam * lam * float(d @ d)
+
+
+def dual_scaling(theta: np.ndarray, y: np.ndarray, lam: float, s_bound: float) -> float:
+    """Lemma 7 (and the mu of Lemmas 1-5): mu = [theta^T y / (lambda ||theta||^2)] clipped to [-s, s].
+
+    s is 1/||D^T theta||_inf (Lasso) or min_g w_g / ||D_g^T theta|| (Group-Lasso);
+    it is +inf when those correlations vanish.  theta = 0 gives mu = 0 (v = 0 is
+    feasible).
+    """
+    nt2 = float(theta @ theta)
+    if nt2 == 0.0:
+        return 0.0
+    return float(np.clip(float(theta @ y) / (lam * nt2), -s_bound, s_bound))
+
+
+# ----------------------------------------------------------------------------
+# Sphere centres and margins (Lemmas 1, 2, 4, 5, 6)
+# ----------------------------------------------------------------------------
+
+def lasso_center(D, y, lam, test, lam_max, i_star):
+    """Centre c and rho^2 = ||y/lambda - c||^2 of the Lasso sphere tests.
+
+    SAFE (Lemma 1): c = y/lambda, rho = 0, radius r = ||y/lambda - v||.
+    DST3 (Lemma 2): c is the projection of y/lambda onto the hyperplane
+    d_*^T theta = 1 bounding the half-space that contains the dual feasible set,
+    r^2 = ||y/lambda - v||^2 - rho^2.  For a unit d_* this is
+    c = y/lambda - (lambda_*/lambda - 1) d_*.
+    """
+    c0 = y / lam
+    if test in ("none", "safe"):
+        return c0, 0.0
+    assert test == "dst3"
+    d = D[:, i_star]
+    d_star = d if float(d @ y) >= 0.0 else -d
+    nd2 = float(d_star @ d_star)
+    c = c0 - (float(d_star @ y) / lam - 1.0) * d_star / nd2
+    e = c0 - c
+    return c, float(e @ e)
+
+
+def group_center(D, y, lam, test, groups, w, lam_max, g_star):
+    """Centre c and rho^2 of the Group-Lasso sphere tests.
+
+    GSAFE (Lemma 4): c = y/lambda.
+    DGST3 (Lemma 5): n = D_{g*} D_{g*}^T y / lambda_*,
+    c = (I - n n^T/||n||^2) y/lambda + n w_{g*}^2 / ||n||^2.
+    """
+    c0 = y / lam
+    if test in ("none", "gsafe"):
+        return c0, 0.0
+    assert test == "dgst3"
+    Dg = D[:, groups[g_star]]
+    n = Dg @ (Dg.T @ y) / lam_max
+    nn = float(n @ n)
+    c = c0 - n * float(n @ c0) / nn + n * (w[g_star] ** 2) / nn
+    e = c0 - c
+    return c, float(e @ e)
+
+
+def lasso_margins(D, c, test):
+    """Per-atom margin m_i = (1 - |d_i^T c|) / ||d_i||: atom i is screened when m_i > r.
+
+    Lemmas 1-2 for unit atoms; Lemma 6 with singleton groups otherwise.  A zero
+    atom has margin +inf; with no test every margin is -inf.
+    """
+    K = D.shape[1]
+    if test == "none":
+        return np.full(K, -np.inf)
+    nu = np.linalg.norm(D, axis=0)
+    corr = np.abs(D.T @ c)
+    m = np.full(K, np.inf)
+    nz = nu > 0
+    m[nz] = (1.0 - corr[nz]) / nu[nz]
+    return m
+
+
+def group_margins(D, c, test, groups, w, gnorm):
+    """Per-group margin m_g = (w_g - ||D_g^T c||) / ||D_g||_2 (Lemmas 4, 5 and 6)."""
+    G = len(groups)
+    if test == "none":
+        return np.full(G, -np.inf)
+    m = np.full(G, np.inf)
+    for k, g in enumerate(groups):
+        if gnorm[k] > 0:
+            m[k] = (w[k] - np.linalg.norm(D[:, g].T @ c)) / gnorm[k]
+    return m
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 3 instantiated with ISTA / FISTA (Table 1)
+# ----------------------------------------------------------------------------
+
+def _radius(R2, rho2, test):
+    if test == "none":
+        return np.inf
+    if test in ("safe", "gsafe"):
+        return float(np.sqrt(R2))
+    return float(np.sqrt(max(R2 - rho2, 0.0)))
+
+
+def _trivial(K, lam, lam_max, L, G=None):
+    return OracleResult(
+        x=np.zeros(K), iters=0, converged=True, lam=lam, lam_max=lam_max, gap=0.0,
+        primal_p=0.0, primal=0.0, dual=0.0, mu=0.0, r_min=0.0,
+        screened=np.ones(K, dtype=bool),
+        screened_groups=None if G is None else np.ones(G, dtype=bool), L=L)
+
+
+def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
+                max_iter=1000, gap_tol=1e-6, record=False) -> OracleResult:
+    """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
+
+    Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
+    x_t = prox(p - z_t / L, lambda / L), FISTA momentum), the dual point
+    v_t = mu_t theta_t, the sphere radius r_t of the chosen test (SAFE Lemma 1,
+    DST3 Lemma 2, or none), the screened set I_t = {i : m_i > r_t} U I_{t-1},
+    and the reduction of D and of the primal variables to the complement of I_t.
+    """
+    D = np.asarray(D, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    N, K = D.shape
+    assert test in ("none", "safe", "dst3") and rule in ("ista", "fista")
+    lam_max, i_star = lambda_max_lasso(D, y)
+    if lam is None:
+        lam = float(lam_ratio) * lam_max
+    if L is None:
+        L = spectral_norm_sq(D)
+    if lam >= lam_max:
+        return _trivial(K, lam, lam_max, L)
+
+    c, rho2 = lasso_center(D, y, lam, test, lam_max, i_star)
+    m = lasso_margins(D, c, test)
+    yy = float(y @ y)
+
+    screened = np.zeros(K, dtype=bool)          # I_0 = empty set
+    active = np.arange(K)                       # complement of I_0
+    Dt = D                                      # D_0 = D
+    x = np.zeros(K)                             # x_0
+    u = np.zeros(K)                             # u_0
+    l_prev = 1.0                                # l_0
+    r_min = np.inf
+    hist = []
+    converged = False
+    for t in range(1, max_iter + 1):
+        # ---- optimisation update (Table 1) ----
+        p = u if rule == "fista" else x
+        theta = Dt @ p - y
+        z = Dt.T @ theta
+        x_new = soft_threshold(p - z / L, lam / L)
+        if rule == "fista":
+            l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
+            u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
+        else:
+            l_new = l_prev
+            u_new = x_new
+        # ---- dual point by dual scaling (Lemma 1 / Algorithm 5) ----
+        zinf = float(np.max(np.abs(z))) if z.size else 0.0
+        s_bound = 1.0 / zinf if zinf > 0.0 else np.inf
+        mu = dual_scaling(theta, y, lam, s_bound)
+        v = mu * theta
+        # ---- duality-gap certificate of p ----
+        primal_p = 0.5 * float(theta @ theta) + lam * float(np.abs(p).sum())
+        dual = dual_objective(v, y, lam)
+        gap = primal_p - dual
+        dv = y / lam - v
+        r = _radius(float(dv @ dv), rho2, test)
+        r_min = min(r_min, r)
+        if record:
+            hist.append(dict(t=t, n_active=int(active.size), nnz=int(np.count_nonzero(x_new)),
+                             nnz_p=int(np.count_nonzero(p)), r=r, gap=gap, mu=mu))
+        if gap_tol > 0.0 and gap <= gap_tol * yy:
+            converged = True
+        if converged or t == max_iter:
+            break
+        # ---- screening: I_t = {i : T_v(i)} U I_{t-1}, then reduce D and X ----
+        screened = screened | (m > r)
+        keep = ~screened[active]
+        if not keep.all():
+            Dt = Dt[:, keep]
+            active = active[keep]
+            x_new = x_new[keep]
+            u_new = u_new[keep]
+        x, u, l_prev = x_new, u_new, l_new
+
+    x_full = np.zeros(K)
+    x_full[active] = x_new
+    primal = primal_objective(D, y, x_full, lam, float(np.abs(x_full).sum()))
+    return OracleResult(x=x_full, iters=t, converged=converged, lam=lam, lam_max=lam_max,
+                        gap=gap, primal_p=primal_p, primal=primal, dual=dual, mu=mu,
+                        r_min=r_min, screened=screened, L=L, history=hist)
+
+
+def _as_groups(K, groups):
+    """Accept either a list of index arrays (any partition) or CSR offsets of contiguous groups."""
+    if isinstance(groups, np.ndarray) and groups.ndim == 1 and groups.dtype.kind in "iu" \
+            and groups.size >= 2 and groups[0] == 0 and groups[-1] == K:
+        return [np.arange(groups[k], groups[k + 1]) for k in range(groups.size - 1)]
+    return [np.asarray(g, dtype=np.int64) for g in groups]
+
+
+def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="ista",
+                      test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
+                      record=False) -> OracleResult:
+    """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
+
+    groups: a partition of range(K) (list of index arrays, or contiguous CSR
+    offsets); w: group weights, default sqrt(|g|).  Tests: GSAFE (Lemma 4),
+    DGST3 (Lemma 5) or none; the screening unit is the group.
+    """
+    D = np.asarray(D, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    N, K = D.shape
+    groups = _as_groups(K, groups)
+    G = len(groups)
+    w = np.sqrt([len(g) for g in groups]).astype(np.float64) if w is None else np.asarray(w, np.float64)
+    assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista")
+    lam_max, g_star = lambda_max_group(D, y, groups, w)
+    if lam is None:
+        lam = float(lam_ratio) * lam_max
+    if L is None:
+        L = spectral_norm_sq(D)
+    if lam >= lam_max:
+        return _trivial(K, lam, lam_max, L, G)
+
+    gnorm = group_spectral_norms(D, groups)
+    c, rho2 = group_center(D, y, lam, test, groups, w, lam_max, g_star)
+    m = group_margins(D, c, test, groups, w, gnorm)
+    yy = float(y @ y)
+
+    screened_g = np.zeros(G, dtype=bool)
+    act_g = np.arange(G)
+
+    def layout(ag):
+        cols = np.concatenate([groups[k] for k in ag]) if len(ag) else np.zeros(0, np.int64)
+        local, pos = [], 0
+        for k in ag:
+            local.append(np.arange(pos, pos + len(groups[k])))
+            pos += len(groups[k])
+        return cols, local
+
+    cols, local = layout(act_g)
+    Dt = D[:, cols]
+    x = np.zeros(cols.size)
+    u = np.zeros(cols.size)
+    l_prev = 1.0
+    r_min = np.inf
+    hist = []
+    converged = False
+    for t in range(1, max_iter + 1):
+        wa = w[act_g]
+        p = u if rule == "fista" else x
+        theta = Dt @ p - y
+        z = Dt.T @ theta
+        x_new = group_soft_threshold(p - z / L, lam / L, local, wa)
+        if rule == "fista":
+            l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
+            u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
+        else:
+            l_new = l_prev
+            u_new = x_new
+        zg = np.array([np.linalg.norm(z[lg]) for lg in local])
+        pos = zg > 0.0
+        s_bound = float(np.min(wa[pos] / zg[pos])) if pos.any() else np.inf
+        mu = dual_scaling(theta, y, lam, s_bound)
+        v = mu * theta
+        omega_p = float(sum(wa[j] * np.linalg.norm(p[lg]) for j, lg in enumerate(local)))
+        primal_p = 0.5 * float(theta @ theta) + lam * omega_p
+        dual = dual_objective(v, y, lam)
+        gap = primal_p - dual
+        dv = y / lam - v
+        r = _radius(float(dv @ dv), rho2, {"gsafe": "safe", "dgst3": "dst3"}.get(test, test))
+        r_min = min(r_min, r)
+        if record:
+            hist.append(dict(t=t, n_active=int(cols.size), n_active_groups=int(act_g.size),
+                             nnz=int(np.count_nonzero(x_new)), nnz_p=int(np.count_nonzero(p)),
+                             r=r, gap=gap, mu=mu))
+        if gap_tol > 0.0 and gap <= gap_tol * yy:
+            converged = True
+        if converged or t == max_iter:
+            break
+        screened_g = screened_g | (m > r)
+        keep_g = ~screened_g[act_g]
+        if not keep_g.all():
+            keep_cols = np.concatenate([local[j] for j in range(act_g.size) if keep_g[j]]) \
+                if keep_g.any() else np.zeros(0, np.int64)
+            act_g = act_g[keep_g]
+            cols, local = layout(act_g)
+            Dt = D[:, cols]
+            x_new = x_new[keep_cols]
+            u_new = u_new[keep_cols]
+        x, u, l_prev = x_new, u_new, l_new
+
+    x_full = np.zeros(K)
+    x_full[cols] = x_new
+    omega = float(sum(w[k] * np.linalg.norm(x_full[g]) for k, g in enumerate(groups)))
+    primal = primal_objective(D, y, x_full, lam, omega)
+    screened = np.zeros(K, dtype=bool)
+    for k in np.flatnonzero(screened_g):
+        screened[groups[k]] = True
+    return OracleResult(x=x_full, iters=t, converged=converged, lam=lam, lam_max=lam_max,
+                        gap=gap, primal_p=primal_p, primal=primal, dual=dual, mu=mu,
+                        r_min=r_min, screened=screened, screened_groups=screened_g, L=L,
+                        history=hist)
+
+
+# ----------------------------------------------------------------------------
+# Certified inactive sets (for safety checks) and the flops model
+# ----------------------------------------------------------------------------
+
+def certified_inactive_lasso(D, y, lam, x):
+    """Atoms provably zero at the exact Lasso solution, from a near-optimal x.
+
+    v = mu (D x - y) with mu by dual scaling over the full D is dual feasible;
+    the dual objective is lambda^2-strongly concave, so ||theta_opt - v|| <=
+    sqrt(2 gap)/lambda, and |d_i^T v| + ||d_i|| sqrt(2 gap)/lambda < 1 implies
+    |d_i^T theta_opt| < 1, hence x_opt_i = 0 by the optimality conditions
+    (equation (primaldual)).  Returns (mask, gap).
+    """
+    theta = D @ x - y
+    zinf = float(np.max(np.abs(D.T @ theta)))
+    mu = dual_scaling(theta, y, lam, 1.0 / zinf if zinf > 0 else np.inf)
+    v = mu * theta
+    gap = primal_objective(D, y, x, lam, float(np.abs(x).sum())) - dual_objective(v, y, lam)
+    rad = np.sqrt(2.0 * max(gap, 0.0)) / lam
+    nu = np.linalg.norm(D, axis=0)
+    return np.abs(D.T @ v) + nu * rad < 1.0, gap
+
+
+def certified_inactive_group(D, y, lam, x, groups, w=None):
+    """Group version (equation (primaldualKKT_glasso)); returns (atom mask, group mask, gap)."""
+    N, K = D.shape
+    groups = _as_groups(K, groups)
+    w = np.sqrt([len(g) for g in groups]) if w is None else np.asarray(w, np.float64)
+    theta = D @ x - y
+    zg = np.array([np.linalg.norm(D[:, g].T @ theta) for g in groups])
+    pos = zg > 0
+    mu = dual_scaling(theta, y, lam, float(np.min(w[pos] / zg[pos])) if pos.any() else np.inf)
+    v = mu * theta
+    omega = float(sum(w[k] * np.linalg.norm(x[g]) for k, g in enumerate(groups)))
+    gap = primal_objective(D, y, x, lam, omega) - dual_objective(v, y, lam)
+    rad = np.sqrt(2.0 * max(gap, 0.0)) / lam
+    gnorm = group_spectral_norms(D, groups)
+    gmask = np.array([np.linalg.norm(D[:, g].T @ v) + gnorm[k] * rad < w[k]
+                      for k, g in enumerate(groups)])
+    amask = np.zeros(K, dtype=bool)
+    for k in np.flatnonzero(gmask):
+        amask[groups[k]] = True
+    return amask, gmask, gap
+
+
+def flops_dynamic(history, N, n_groups=None):
+    """Flops model of the experiments section for the dynamic strategy.
+
+    Lasso: sum_t [(|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N];
+    Group-Lasso: sum_t [(|I^c_t| + ||x_t||_0) N + 7 |I^c_t| + 5 N + 5 |G|].
+    """
+    tot = 0
+    for h in history:
+        a, s = h["n_active"], h["nnz"]
+        if n_groups is None:
+            tot += (a + s) * N + 6 * a + 5 * N
+        else:
+            tot += (a + s) * N + 7 * a + 5 * N + 5 * n_groups
+    return tot

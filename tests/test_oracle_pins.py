@@ -1,0 +1,366 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these checks re-types an oracle formula: each compares the oracle with
+a closed form, an invariant, a special case reducing to a library routine or a
+hand computation, or brute-force enumeration.
+"""
+import numpy as np
+import pytest
+from scipy import optimize
+
+import oracle
+from paper_1412_4080_amd import datagen
+
+
+def _problem(N=40, K=120, seed=3, p=0.05, snr=20.0, normalize=True):
+    D = datagen.gaussian_dictionary(N, K, seed)
+    rng = np.random.default_rng(seed + 100)
+    x0 = datagen.bernoulli_gaussian_code(K, p, rng)
+    y = datagen.observation(D, x0, rng, snr_db=snr, normalize=normalize)
+    return D, y
+
+
+# --------------------------------------------------------------------------
+# lambda_* and the trivial regime (Lasso section: lambda >= lambda_* gives x = 0)
+# --------------------------------------------------------------------------
+
+def test_lambda_max_trivial_regime_lasso():
+    D, y = _problem()
+    lam_max, i_star = oracle.lambda_max_lasso(D, y)
+    assert lam_max == pytest.approx(np.max(np.abs(D.T @ y)), rel=1e-15)
+    for ratio in (1.0, 1.3):
+        r = oracle.solve_lasso(D, y, lam_ratio=ratio)
+        assert r.iters == 0 and not r.x.any()
+    # just below lambda_*, the single most correlated atom enters the support
+    r = oracle.solve_lasso(D, y, lam_ratio=0.999, rule="fista", test="none", gap_tol=1e-14,
+                           max_iter=20000)
+    assert np.flatnonzero(r.x).tolist() == [i_star]
+    # one active atom: x = (d^T y - lambda sign) / ||d||^2 in closed form
+    d = D[:, i_star]
+    s = np.sign(d @ y)
+    # the gap bounds the objective error, hence the iterate error by sqrt(2 gap)
+    assert r.x[i_star] == pytest.approx((d @ y - r.lam * s) / (d @ d), abs=2e-7)
+
+
+def test_lambda_max_trivial_regime_group():
+    D, y = _problem(K=120)
+    gp = datagen.contiguous_groups(120, 6)
+    groups = [np.arange(gp[k], gp[k + 1]) for k in range(20)]
+    w = np.sqrt(6.0) * np.ones(20)
+    lam_max, g_star = oracle.lambda_max_group(D, y, groups, w)
+    brute = max(np.linalg.norm(D[:, g].T @ y) / w[k] for k, g in enumerate(groups))
+    assert lam_max == pytest.approx(brute, rel=1e-15)
+    r = oracle.solve_group_lasso(D, y, gp, w, lam_ratio=1.0)
+    assert r.iters == 0 and not r.x.any()
+
+
+# --------------------------------------------------------------------------
+# Proximal operators against their definition, solved by a library minimiser
+# --------------------------------------------------------------------------
+
+def test_soft_threshold_is_the_l1_prox():
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        v, t = rng.normal() * 3, abs(rng.normal())
+        res = optimize.minimize_scalar(lambda z: abs(z) + (v - z) ** 2 / (2 * t),
+                                       bracket=(-10, 10), tol=1e-14)
+        assert oracle.soft_threshold(np.array([v]), t)[0] == pytest.approx(res.x, abs=1e-6)
+
+
+def test_group_soft_threshold_is_the_group_prox():
+    rng = np.random.default_rng(1)
+    groups = [np.arange(0, 3), np.arange(3, 7), np.arange(7, 8)]
+    w = np.array([1.7, 2.0, 1.0])
+    for scale in (0.3, 1.0, 4.0):
+        v = rng.normal(size=8) * scale
+        t = 0.8
+
+        def f(z):
+            return sum(w[k] * np.linalg.norm(z[g]) for k, g in enumerate(groups)) + \
+                np.sum((v - z) ** 2) / (2 * t)
+        res = optimize.minimize(f, x0=v * 0.5, method="Powell",
+                                options=dict(xtol=1e-12, ftol=1e-15, maxiter=200000))
+        out = oracle.group_soft_threshold(v, t, groups, w)
+        assert f(out) <= f(res.x) + 1e-10
+        assert np.allclose(out, res.x, atol=2e-4)
+    # a zero group maps to zero (reading of the 0/0 case)
+    assert not oracle.group_soft_threshold(np.zeros(8), 0.5, groups, w).any()
+
+
+# --------------------------------------------------------------------------
+# Dual scaling (Lemma 7): closest feasible scaled point
+# --------------------------------------------------------------------------
+
+def test_dual_scaling_is_the_closest_feasible_scaling():
+    D, y = _problem(N=30, K=80, seed=5)
+    rng = np.random.default_rng(2)
+    lam = 0.4 * oracle.lambda_max_lasso(D, y)[0]
+    for _ in range(10):
+        theta = rng.normal(size=30) * rng.uniform(0.01, 3)
+        s = 1.0 / np.max(np.abs(D.T @ theta))
+        mu = oracle.dual_scaling(theta, y, lam, s)
+        assert np.max(np.abs(D.T @ (mu * theta))) <= 1 + 1e-12
+        res = optimize.minimize_scalar(lambda a: np.sum((a * theta - y / lam) ** 2),
+                                       bounds=(-s, s), method="bounded",
+                                       options=dict(xatol=1e-14))
+        assert mu == pytest.approx(res.x, abs=1e-7 * max(1.0, abs(res.x)))
+
+
+# --------------------------------------------------------------------------
+# First iteration from x0 = 0 is the static test (Algorithm 4 and ST3)
+# --------------------------------------------------------------------------
+
+def test_first_iteration_equals_static_safe_and_st3():
+    D, y = _problem(N=60, K=300, seed=7)
+    assert np.linalg.norm(y) == pytest.approx(1.0, rel=1e-14)
+    lam_max, _ = oracle.lambda_max_lasso(D, y)
+    for ratio in (0.5, 0.8, 0.95):
+        lam = ratio * lam_max
+        # theta_1 = -y, mu_1 = -1/lambda_*, r_1 = 1/lambda - 1/lambda_*
+        r = oracle.solve_lasso(D, y, lam=lam, rule="ista", test="safe", max_iter=2,
+                               gap_tol=0.0, record=True)
+        h1 = r.history[0]
+        assert h1["mu"] == pytest.approx(-1.0 / lam_max, rel=1e-13)
+        assert h1["r"] == pytest.approx(1.0 / lam - 1.0 / lam_max, rel=1e-12)
+        # after iteration 1 the screened set is the static SAFE set of Algorithm 4
+        static = np.abs(D.T @ y) < lam - 1.0 + lam / lam_max
+        assert np.array_equal(r.screened, static)
+        # ST3 radius for unit y and unit atoms: (1/lambda - 1/lambda_*) sqrt(1 - lambda_*^2)
+        r3 = oracle.solve_lasso(D, y, lam=lam, rule="ista", test="dst3", max_iter=2,
+                                gap_tol=0.0, record=True)
+        assert r3.history[0]["r"] == pytest.approx(
+            (1.0 / lam - 1.0 / lam_max) * np.sqrt(1.0 - lam_max ** 2), rel=1e-10)
+
+
+def test_dst3_center_matches_lemma2_for_unit_atoms():
+    D, y = _problem(N=50, K=200, seed=11)
+    lam_max, i_star = oracle.lambda_max_lasso(D, y)
+    lam = 0.6 * lam_max
+    d = D[:, i_star] * np.sign(D[:, i_star] @ y)
+    c, rho2 = oracle.lasso_center(D, y, lam, "dst3", lam_max, i_star)
+    assert np.allclose(c, y / lam - (lam_max / lam - 1.0) * d, atol=1e-13)
+    assert rho2 == pytest.approx((lam_max / lam - 1.0) ** 2, rel=1e-12)
+
+
+def test_dgst3_center_is_the_projection_onto_the_tangent_hyperplane():
+    D, y = _problem(N=50, K=200, seed=12)
+    gp = datagen.contiguous_groups(200, 5)
+    groups = [np.arange(gp[k], gp[k + 1]) for k in range(40)]
+    w = np.sqrt(5.0) * np.ones(40)
+    lam_max, g_star = oracle.lambda_max_group(D, y, groups, w)
+    lam = 0.5 * lam_max
+    c, rho2 = oracle.group_center(D, y, lam, "dgst3", groups, w, lam_max, g_star)
+    Dg = D[:, groups[g_star]]
+    # normal of the ellipsoid ||D_g*^T theta|| = w at y/lambda_* (gradient of 1/2||D_g*^T theta||^2)
+    n = Dg @ Dg.T @ (y / lam_max)
+    # y/lambda_* lies on that ellipsoid, so the tangent plane is {theta: theta^T n = w^2}
+    assert np.linalg.norm(Dg.T @ (y / lam_max)) == pytest.approx(w[g_star], rel=1e-12)
+    assert c @ n == pytest.approx(w[g_star] ** 2, rel=1e-11)
+    e = y / lam - c
+    assert abs(e @ n) == pytest.approx(np.linalg.norm(e) * np.linalg.norm(n), rel=1e-11)
+    assert rho2 == pytest.approx(e @ e, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Special cases: singleton groups reduce to the Lasso, orthonormal designs
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("gtest,ltest", [("gsafe", "safe"), ("dgst3", "dst3"), ("none", "none")])
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_singleton_groups_reproduce_the_lasso(gtest, ltest, rule):
+    D, y = _problem(N=40, K=150, seed=13)
+    K = D.shape[1]
+    gp = np.arange(K + 1)
+    a = oracle.solve_lasso(D, y, lam_ratio=0.45, rule=rule, test=ltest, max_iter=300,
+                           gap_tol=1e-11, record=True)
+    b = oracle.solve_group_lasso(D, y, gp, np.ones(K), lam_ratio=0.45, rule=rule, test=gtest,
+                                 max_iter=300, gap_tol=1e-11, record=True)
+    assert a.iters == b.iters
+    assert np.allclose(a.x, b.x, atol=1e-12)
+    assert np.array_equal(a.screened, b.screened)
+    assert [h["n_active"] for h in a.history] == [h["n_active"] for h in b.history]
+
+
+def test_orthonormal_design_lasso_and_group():
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.normal(size=(16, 16)))
+    y = rng.normal(size=16)
+    y /= np.linalg.norm(y)
+    lam = 0.3 * np.max(np.abs(Q.T @ y))
+    # ISTA with L = 1 lands on soft-threshold(Q^T y, lambda) in one step
+    r = oracle.solve_lasso(Q, y, lam=lam, rule="ista", test="dst3", L=1.0, max_iter=5,
+                           gap_tol=1e-14)
+    assert np.allclose(r.x, np.sign(Q.T @ y) * np.maximum(np.abs(Q.T @ y) - lam, 0), atol=1e-14)
+    assert r.iters == 2 and r.gap <= 1e-14
+    gp = datagen.contiguous_groups(16, 4)
+    w = np.array([2.0, 1.5, 2.5, 2.0])
+    b = Q.T @ y
+    lamg = 0.4 * max(np.linalg.norm(b[gp[k]:gp[k + 1]]) / w[k] for k in range(4))
+    expect = np.zeros(16)
+    for k in range(4):
+        bg = b[gp[k]:gp[k + 1]]
+        nb = np.linalg.norm(bg)
+        if nb > lamg * w[k]:
+            expect[gp[k]:gp[k + 1]] = (1 - lamg * w[k] / nb) * bg
+    rg = oracle.solve_group_lasso(Q, y, gp, w, lam=lamg, rule="fista", test="dgst3", L=1.0,
+                                  max_iter=10, gap_tol=1e-14)
+    assert np.allclose(rg.x, expect, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# FISTA trajectory computed by hand (Table 1) on a scalar problem
+# --------------------------------------------------------------------------
+
+def test_fista_scalar_trajectory_by_hand():
+    # D = [1], y = 3, lambda = 1, L = 2.  Hand computation with Table 1:
+    # x1 = ST(1.5, 0.5) = 1; l1 = (1+sqrt5)/2; beta1 = 0 -> u1 = 1
+    # x2 = ST((1+3)/2, 0.5) = 1.5; l2 = (1+sqrt(1+4 l1^2))/2 = 2.19353...; beta2 = (l1-1)/l2
+    # beta2 = 0.6180340/2.1935271 = 0.2817535; u2 = 1.5 + 0.5 beta2 = 1.6408768
+    # x3 = ST((u2+3)/2, 0.5) = 2.3204384 - 0.5 = 1.8204384
+    D = np.array([[1.0]])
+    y = np.array([3.0])
+    xs = []
+    for T in (1, 2, 3):
+        r = oracle.solve_lasso(D, y, lam=1.0, rule="fista", test="none", L=2.0, max_iter=T,
+                               gap_tol=0.0)
+        xs.append(r.x[0])
+    assert xs[0] == pytest.approx(1.0, abs=1e-15)
+    assert xs[1] == pytest.approx(1.5, abs=1e-15)
+    assert xs[2] == pytest.approx(1.8204384, abs=1e-7)
+    r = oracle.solve_lasso(D, y, lam=1.0, rule="ista", test="none", L=2.0, max_iter=3,
+                           gap_tol=0.0)
+    # ISTA: 1, 1.5, 1.75
+    assert r.x[0] == pytest.approx(1.75, abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Whole solution: brute-force enumeration, KKT, gap, Theorem 1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("rule,test", [("ista", "safe"), ("fista", "dst3"), ("fista", "none")])
+def test_matches_brute_force_enumeration(seed, rule, test):
+    D = datagen.gaussian_dictionary(6, 10, 50 + seed)
+    rng = np.random.default_rng(60 + seed)
+    y = rng.normal(size=6)
+    y /= np.linalg.norm(y)
+    lam = 0.35 * oracle.lambda_max_lasso(D, y)[0]
+    xb = oracle.brute_force_lasso(D, y, lam)
+    r = oracle.solve_lasso(D, y, lam=lam, rule=rule, test=test, max_iter=200000, gap_tol=1e-15)
+    assert r.converged
+    assert np.allclose(r.x, xb, atol=1e-7)
+    assert np.array_equal(r.x != 0, xb != 0)
+
+
+def _kkt_lasso(D, y, x, lam):
+    g = D.T @ (y - D @ x)
+    act = x != 0
+    return max(np.max(np.abs(g[act] - lam * np.sign(x[act])), initial=0.0),
+               max(np.max(np.abs(g[~act]), initial=0.0) - lam, 0.0))
+
+
+def test_kkt_and_gap_lasso():
+    D, y = _problem(N=80, K=300, seed=17)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.3, rule="fista", test="dst3", max_iter=100000,
+                           gap_tol=1e-13)
+    assert r.converged and r.gap >= -1e-15
+    assert _kkt_lasso(D, y, r.x, r.lam) < 2e-6
+    # the gap certifies the returned point: P(x) - Dual(v) <= gap
+    assert r.primal - r.dual <= r.gap + 1e-15
+
+
+def test_kkt_and_gap_group():
+    D, y = _problem(N=80, K=300, seed=18)
+    gp = datagen.contiguous_groups(300, 10)
+    w = np.sqrt(10.0) * np.ones(30)
+    r = oracle.solve_group_lasso(D, y, gp, w, lam_ratio=0.3, rule="fista", test="dgst3",
+                                 max_iter=100000, gap_tol=1e-13)
+    assert r.converged
+    res = y - D @ r.x
+    for k in range(30):
+        g = slice(gp[k], gp[k + 1])
+        corr = D[:, g].T @ res
+        xg = r.x[g]
+        if np.linalg.norm(xg) > 0:
+            assert np.allclose(corr, r.lam * w[k] * xg / np.linalg.norm(xg), atol=2e-6)
+        else:
+            assert np.linalg.norm(corr) <= r.lam * w[k] * (1 + 1e-6)
+    assert r.primal - r.dual <= r.gap + 1e-15
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_gap_nonnegative_and_decreasing_to_zero(rule):
+    D, y = _problem(N=60, K=200, seed=19)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.5, rule=rule, test="dst3", max_iter=3000,
+                           gap_tol=1e-12, record=True)
+    gaps = np.array([h["gap"] for h in r.history])
+    assert np.all(gaps >= -1e-14)      # weak duality
+    assert r.converged and gaps[-1] <= 1e-12
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_theorem1_screening_does_not_change_the_solution(rule):
+    D, y = _problem(N=60, K=250, seed=21)
+    xs = [oracle.solve_lasso(D, y, lam_ratio=0.4, rule=rule, test=t, max_iter=100000,
+                             gap_tol=1e-14).x for t in ("none", "safe", "dst3")]
+    assert np.allclose(xs[0], xs[1], atol=1e-8) and np.allclose(xs[0], xs[2], atol=1e-8)
+    gp = datagen.contiguous_groups(250, 5)
+    xg = [oracle.solve_group_lasso(D, y, gp, None, lam_ratio=0.4, rule=rule, test=t,
+                                   max_iter=100000, gap_tol=1e-14).x
+          for t in ("none", "gsafe", "dgst3")]
+    assert np.allclose(xg[0], xg[1], atol=1e-8) and np.allclose(xg[0], xg[2], atol=1e-8)
+
+
+def test_screened_sets_monotone_and_safe():
+    D, y = _problem(N=60, K=400, seed=23)
+    for test in ("safe", "dst3"):
+        r = oracle.solve_lasso(D, y, lam_ratio=0.6, rule="fista", test=test, max_iter=5000,
+                               gap_tol=1e-10, record=True)
+        sizes = [h["n_active"] for h in r.history]
+        assert all(a >= b for a, b in zip(sizes, sizes[1:]))
+        # safety: every screened atom is zero in a gap < 1e-12 solution, and certified inactive
+        ref = oracle.solve_lasso(D, y, lam=r.lam, rule="fista", test="none", max_iter=200000,
+                                 gap_tol=1e-14)
+        assert not ref.x[r.screened].any()
+        cert, gap = oracle.certified_inactive_lasso(D, y, r.lam, ref.x)
+        assert gap < 1e-12
+        assert np.all(cert[r.screened])
+    assert r.screened.sum() > 0
+
+
+def test_group_screening_safe():
+    D, y = _problem(N=60, K=400, seed=29)
+    gp = datagen.contiguous_groups(400, 10)
+    for test in ("gsafe", "dgst3"):
+        r = oracle.solve_group_lasso(D, y, gp, None, lam_ratio=0.6, rule="fista", test=test,
+                                     max_iter=5000, gap_tol=1e-10)
+        ref = oracle.solve_group_lasso(D, y, gp, None, lam=r.lam, rule="fista", test="none",
+                                       max_iter=200000, gap_tol=1e-14)
+        amask, gmask, gap = oracle.certified_inactive_group(D, y, r.lam, ref.x, gp)
+        assert gap < 1e-12
+        assert not ref.x[r.screened].any()
+        assert np.all(gmask[r.screened_groups])
+
+
+# --------------------------------------------------------------------------
+# Spectral norms against the SVD
+# --------------------------------------------------------------------------
+
+def test_spectral_norms_match_svd():
+    D, _ = _problem(N=30, K=90, seed=31)
+    assert oracle.spectral_norm_sq(D) == pytest.approx(np.linalg.svd(D, compute_uv=False)[0] ** 2,
+                                                       rel=1e-12)
+    gp = datagen.contiguous_groups(90, 9)
+    groups = [np.arange(gp[k], gp[k + 1]) for k in range(10)]
+    gn = oracle.group_spectral_norms(D, groups)
+    for k, g in enumerate(groups):
+        assert gn[k] == pytest.approx(np.linalg.svd(D[:, g], compute_uv=False)[0], rel=1e-12)
+
+
+def test_flops_model_unscreened_equals_closed_form():
+    D, y = _problem(N=30, K=100, seed=33)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.5, rule="ista", test="none", max_iter=40,
+                           gap_tol=0.0, record=True)
+    # with nothing screened every |I^c_t| = K
+    expect = sum((100 + h["nnz"]) * 30 + 6 * 100 + 5 * 30 for h in r.history)
+    assert oracle.flops_dynamic(r.history, 30) == expect
