@@ -1,0 +1,211 @@
+/*
+ * dynscreen.h - C-ABI of the MI355X dynamic-screening Lasso / Group-Lasso library.
+ *
+ * Problem (paper eq. (1)):  x* = argmin_x 1/2 ||D x - y||_2^2 + lambda * Omega(x)
+ *   Lasso       (eq. (lasso)):        Omega(x) = ||x||_1
+ *   Group-Lasso (eq. (group-lasso)):  Omega(x) = sum_g w_g ||x_g||_2, G a partition of the atoms
+ * solved by Algorithm 3 ("general algorithm with dynamic screening") with the ISTA
+ * or FISTA update of Table 1, and a safe sphere test re-evaluated at every iteration:
+ *   Lasso:       SAFE (Lemma 1) or DST3 (Lemma 2)
+ *   Group-Lasso: GSAFE (Lemma 4) or DGST3 (Lemma 5), through the group sphere test (Lemma 6).
+ *
+ * Conventions shared by every entry point
+ *   - D is column-major, N x K, leading dimension ldd >= N, in DEVICE memory.  Atom i
+ *     is the ldd-strided column i.  Storage type: DS_F64 (double), DS_F32 (float),
+ *     DS_BF16 (bfloat16 bit patterns, uint16).  The stored values define the problem.
+ *   - Vectors y, x live in DEVICE memory.  Their element type is double for DS_F64 and
+ *     float for DS_F32 and DS_BF16.
+ *   - Host arrays (group offsets, weights, lambdas, info) are read or written before
+ *     the call returns; the library keeps no pointer to caller memory after a call.
+ *   - `stream` is a hipStream_t (NULL: the default stream).  Solves are blocking with
+ *     respect to the host: on return every output has been written.
+ *   - Errors: a ds_status code.  Arguments are validated before any device work; a
+ *     rejected call leaves outputs untouched.  ds_last_error() returns a thread-local
+ *     message describing the last failure.
+ *   - Thread safety: calls may come from several host threads; the library serialises
+ *     device work per device internally.
+ */
+#ifndef DYNSCREEN_H
+#define DYNSCREEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DS_OK = 0,             /* solved; for gap_tol > 0 the gap certificate met the tolerance */
+  DS_PENDING = 1,        /* serving: request not finished yet */
+  DS_NOT_CONVERGED = 2,  /* max_iter reached with gap_tol > 0 and the gap above tolerance;
+                            outputs and info are still filled in */
+  DS_EINVAL = -1,        /* invalid argument (nothing was launched) */
+  DS_ENOMEM = -2,        /* device allocation failed, or a request can never fit the budget */
+  DS_EDEVICE = -3,       /* a HIP call failed */
+  DS_ENOTFOUND = -4,     /* unknown request / dictionary id */
+  DS_EBUSY = -5          /* serving: queue full */
+} ds_status;
+
+typedef enum { DS_F64 = 0, DS_F32 = 1, DS_BF16 = 2 } ds_dtype;
+
+/* First-order update p(.) of Table 1, with a constant step 1/L. */
+typedef enum { DS_ISTA = 0, DS_FISTA = 1 } ds_rule;
+
+/* Screening test.  For Group-Lasso problems SAFE means GSAFE (Lemma 4) and DST3 means
+ * DGST3 (Lemma 5).  DS_TEST_NONE runs the plain, unscreened algorithm. */
+typedef enum { DS_TEST_NONE = 0, DS_TEST_SAFE = 1, DS_TEST_DST3 = 2 } ds_test;
+
+/* How `lambdas` is read: absolute penalties, or ratios lambda / lambda_* where
+ * lambda_* = ||D^T y||_inf (Lasso) or max_g ||D_g^T y|| / w_g (eq. (gstar)) is
+ * computed on the device for each signal. */
+typedef enum { DS_LAMBDA_ABSOLUTE = 0, DS_LAMBDA_RELATIVE = 1 } ds_lambda_mode;
+
+typedef struct {
+  ds_dtype dtype;
+  int64_t N;                 /* signal dimension, >= 1 */
+  int64_t K;                 /* number of atoms, >= 1 */
+  int64_t ldd;               /* leading dimension of D, >= N */
+  const void* D;             /* device pointer, column-major N x K */
+  int64_t G;                 /* 0: Lasso.  > 0: Group-Lasso with G groups */
+  const int64_t* group_ptr;  /* host, G+1 offsets: group g = atoms [group_ptr[g], group_ptr[g+1]);
+                                group_ptr[0] = 0, group_ptr[G] = K, strictly increasing.
+                                Any partition is reached by permuting the columns of D. */
+  const double* w;           /* host, G positive weights; NULL means w_g = sqrt(|g|) */
+} ds_problem;
+
+typedef struct {
+  ds_rule rule;
+  ds_test test;
+  ds_lambda_mode lambda_mode;
+  double step_L;     /* > 0: constant step 1/step_L, must be >= ||D||_2^2.
+                        <= 0: the library estimates ||D||_2^2 (ds_spectral_norm_sq). */
+  double gap_tol;    /* > 0: stop once the duality-gap certificate <= gap_tol * ||y||^2.
+                        0: run exactly max_iter iterations. */
+  int32_t max_iter;  /* >= 1 */
+  int32_t reserved;  /* must be 0 */
+} ds_params;
+
+/* Per-signal result.  The gap certificate of iteration t pairs the primal point at which
+ * theta_t = D p - y was evaluated (x_{t-1} for ISTA, u_{t-1} for FISTA) with the dual
+ * point v_t = mu_t theta_t obtained by dual scaling (Lemma 7); the returned x_t has an
+ * objective no larger than that primal point's. */
+typedef struct {
+  int32_t status;      /* ds_status of this signal */
+  int32_t iters;       /* iterations run (0 when lambda >= lambda_*, where x = 0) */
+  int32_t n_active;    /* atoms not screened when the solve ended */
+  int32_t nnz;         /* non-zeros of the returned x */
+  double lambda;       /* absolute penalty used */
+  double lambda_max;   /* lambda_* */
+  double primal;       /* P(p) at the last iteration */
+  double dual;         /* dual objective at v_T (eq. (dual) / (dual_glasso)) */
+  double gap;          /* primal - dual */
+  double radius;       /* smallest sphere radius reached (r_min) */
+  double mu;           /* dual-scaling factor of the last iteration */
+  double L;            /* step constant used */
+  double radius_slack; /* rounding slack added to the radius (>= 0) */
+} ds_info;
+
+/* lasso_solve / glasso_solve
+ *   Solve B independent problems sharing D: column b of Y (N x B, leading dim ldy >= N)
+ *   with penalty lambdas[b] (host array of B values > 0, read per lambda_mode), writing
+ *   column b of X (K x B, leading dim ldx >= K, device) and info[b] (host).
+ *   lasso_solve requires problem->G == 0; glasso_solve requires problem->G > 0.
+ *   B = 1 runs the single-signal streaming path (one GEMV per iteration); B > 1 with
+ *   DS_BF16 storage runs the batched MFMA path; other B > 1 cases run B single solves.
+ *   Returns DS_OK if every signal reached its tolerance (or ran max_iter when gap_tol = 0),
+ *   DS_NOT_CONVERGED if some did not (see info[b].status), or an error code. */
+ds_status lasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                      const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                      ds_info* info, void* stream);
+ds_status glasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                       const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                       ds_info* info, void* stream);
+
+/* One iteration record of a single-signal solve: the quantities the paper's flops model
+ * records per iteration (dictionary size |I^c_t| and ||x_t||_0), plus radius and gap. */
+typedef struct {
+  int32_t n_active;   /* atoms in the (screened) dictionary used by iteration t */
+  int32_t n_units;    /* active atoms (Lasso) or active groups (Group-Lasso) */
+  int32_t n_support;  /* non-zeros of the primal point theta_t was evaluated at */
+  int32_t nnz;        /* non-zeros of x_t */
+  double radius;      /* sphere radius r_t of iteration t (no slack; +inf without a test) */
+  double gap;         /* gap certificate of iteration t */
+} ds_trace;
+
+/* Single-signal solve with optional diagnostic outputs (Lasso if problem->G == 0, else
+ * Group-Lasso).  y, x as in lasso_solve with B = 1.  `screened` (DEVICE, K bytes, may be
+ * NULL) receives 1 for every atom of the final screened set I_T and 0 otherwise, in the
+ * original atom order.  `trace` (HOST, may be NULL) receives min(iters, trace_cap)
+ * records, one per iteration. */
+ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,
+                       const ds_params* params, void* x, uint8_t* screened, ds_trace* trace,
+                       int32_t trace_cap, ds_info* info, void* stream);
+
+/* lambda_* of a single signal y (device, length N) and the first index attaining it
+ * (atom index for the Lasso, group index for the Group-Lasso); FP64 accumulation. */
+ds_status ds_lambda_max(const ds_problem* problem, const void* y, double* lambda_max,
+                        int64_t* argmax, void* stream);
+
+/* Estimate of ||D||_2^2 (largest eigenvalue of D D^T) by FP64 power iteration with a
+ * Krylov-Weinstein residual bound added, so the value is an upper estimate.  Cost:
+ * 2 * iters GEMV passes over D. iters <= 0 selects 200. */
+ds_status ds_spectral_norm_sq(const ds_problem* problem, int32_t iters, double* L,
+                              void* stream);
+
+/* ---------------------------------------------------------------- serving ---------
+ * Continuous-batching request loop (one scheduler thread per server).  Dictionaries are
+ * copied into library-owned device memory at registration; requests carry y on the host,
+ * are admitted when their device footprint fits the HBM budget and a slot is free, and
+ * run interleaved with other requests on the device. */
+typedef struct {
+  int32_t device;           /* HIP device ordinal */
+  int32_t max_slots;        /* maximum requests resident on the device at once (>= 1) */
+  size_t hbm_budget_bytes;  /* device memory the server may use for requests (> 0) */
+  int32_t max_queue;        /* maximum pending requests before DS_EBUSY (>= 1) */
+  int32_t reserved;         /* must be 0 */
+} ds_server_config;
+
+ds_status ds_server_create(const ds_server_config* config, void** server);
+/* Copies D (device or host pointer, detected) into server memory, converting to `store`
+ * precision (DS_F32 or DS_BF16 from DS_F32 input; same type otherwise).  Computes and
+ * caches ||D||_2^2, atom norms and group norms. */
+ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype store,
+                             int32_t* dict_id);
+/* Queue a solve of y (HOST pointer, N floats, or doubles for a DS_F64 dictionary) with
+ * penalty `lambda` (read per params->lambda_mode).  Returns immediately. */
+ds_status ds_submit(void* server, int32_t dict_id, const void* y_host, double lambda,
+                    const ds_params* params, uint64_t* request_id);
+/* Lasso-named alias of ds_submit (the dictionary decides Lasso or Group-Lasso). */
+ds_status lasso_submit(void* server, int32_t dict_id, const void* y_host, double lambda,
+                       const ds_params* params, uint64_t* request_id);
+/* DS_PENDING while running; otherwise copies x (K values, HOST) and info, forgets the
+ * request and returns its final status.  x_host may be NULL to discard x. */
+ds_status lasso_poll(void* server, uint64_t request_id, void* x_host, ds_info* info);
+ds_status ds_server_destroy(void* server);
+
+/* ---------------------------------------------------------------- diagnostics ------ */
+typedef struct {
+  int64_t launches;   /* kernel launches accounted */
+  double ms;          /* summed HIP-event time of those launches */
+  double bytes;       /* summed algorithmic HBM bytes */
+  double flops;       /* summed algorithmic flops */
+} ds_kernel_stat;
+
+enum { DS_STAT_CORR = 0, DS_STAT_RESID = 1, DS_STAT_SETUP = 2, DS_STAT_BATCH = 3,
+       DS_STAT_COUNT = 4 };
+
+/* When enabled, each launch of the instrumented kernels is bracketed by HIP events on
+ * its stream and its algorithmic bytes/flops are added to the counters. */
+void ds_stats_enable(int on);
+void ds_stats_reset(void);
+/* Copies min(n, DS_STAT_COUNT) counters into out; returns the number copied. */
+int ds_stats_read(ds_kernel_stat* out, int n);
+
+const char* ds_last_error(void);
+const char* ds_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DYNSCREEN_H */

@@ -1,0 +1,297 @@
+// C-ABI entry points (include/dynscreen.h): argument validation, workspace management,
+// dispatch to the single-signal and batched engines.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "ds_engine.h"
+
+namespace ds {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+StatAccum& stats() {
+  static StatAccum s;
+  return s;
+}
+
+Workspace::~Workspace() {
+  // Cached per-device workspaces live until process exit, when the HIP runtime may
+  // already be torn down; temporary ones call release() explicitly.
+}
+
+void Workspace::release() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  events.clear();
+  if (base != nullptr) (void)hipFree(base);
+  if (host_pinned != nullptr) (void)hipHostFree(host_pinned);
+  base = nullptr;
+  host_pinned = nullptr;
+  bytes = 0;
+}
+
+ds_status Workspace::reserve(size_t need) {
+  if (host_pinned == nullptr) {
+    if (hipHostMalloc(&host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+      host_pinned = nullptr;
+      set_error("hipHostMalloc of the staging area failed");
+      return DS_ENOMEM;
+    }
+  }
+  if (need <= bytes && base != nullptr) return DS_OK;
+  if (base != nullptr) {
+    DS_HIP(hipDeviceSynchronize());
+    DS_HIP(hipFree(base));
+    base = nullptr;
+    bytes = 0;
+  }
+  const size_t want = need + need / 4;
+  if (hipMalloc(&base, want) != hipSuccess) {
+    (void)hipGetLastError();
+    base = nullptr;
+    set_error("hipMalloc of %zu workspace bytes failed", want);
+    return DS_ENOMEM;
+  }
+  bytes = want;
+  return DS_OK;
+}
+
+DeviceCtx& device_ctx(int device) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<DeviceCtx>> ctx;
+  std::lock_guard<std::mutex> g(mu);
+  auto& p = ctx[device];
+  if (!p) {
+    p = std::make_unique<DeviceCtx>();
+    p->ws.device = device;
+  }
+  return *p;
+}
+
+size_t dtype_size(ds_dtype t) {
+  switch (t) {
+    case DS_F64: return 8;
+    case DS_F32: return 4;
+    case DS_BF16: return 2;
+  }
+  return 0;
+}
+
+ds_status validate_problem(const ds_problem* p, bool group) {
+  if (p == nullptr) { set_error("problem is NULL"); return DS_EINVAL; }
+  if (p->dtype != DS_F64 && p->dtype != DS_F32 && p->dtype != DS_BF16) {
+    set_error("unknown dtype %d", static_cast<int>(p->dtype));
+    return DS_EINVAL;
+  }
+  if (p->N < 1 || p->K < 1 || p->N > (1ll << 24) || p->K > (1ll << 30)) {
+    set_error("bad sizes N=%lld K=%lld", static_cast<long long>(p->N), static_cast<long long>(p->K));
+    return DS_EINVAL;
+  }
+  if (p->ldd < p->N) { set_error("ldd < N"); return DS_EINVAL; }
+  if (p->D == nullptr) { set_error("D is NULL"); return DS_EINVAL; }
+  if (group) {
+    if (p->G < 1 || p->group_ptr == nullptr) { set_error("group problem needs G > 0 and group_ptr"); return DS_EINVAL; }
+    if (p->group_ptr[0] != 0 || p->group_ptr[p->G] != p->K) {
+      set_error("group_ptr must start at 0 and end at K");
+      return DS_EINVAL;
+    }
+    for (int64_t g = 0; g < p->G; ++g) {
+      const int64_t sz = p->group_ptr[g + 1] - p->group_ptr[g];
+      if (sz < 1) { set_error("group %lld is empty", static_cast<long long>(g)); return DS_EINVAL; }
+      if (sz > 64) {
+        set_error("group %lld has %lld atoms; groups of at most 64 atoms are supported",
+                  static_cast<long long>(g), static_cast<long long>(sz));
+        return DS_EINVAL;
+      }
+      if (p->w != nullptr && !(p->w[g] > 0.0 && std::isfinite(p->w[g]))) {
+        set_error("group weight %lld must be positive and finite", static_cast<long long>(g));
+        return DS_EINVAL;
+      }
+    }
+  } else if (p->G != 0) {
+    set_error("lasso_solve needs G == 0 (use glasso_solve for groups)");
+    return DS_EINVAL;
+  }
+  return DS_OK;
+}
+
+ds_status validate_params(const ds_params* p) {
+  if (p == nullptr) { set_error("params is NULL"); return DS_EINVAL; }
+  if (p->rule != DS_ISTA && p->rule != DS_FISTA) { set_error("unknown rule"); return DS_EINVAL; }
+  if (p->test != DS_TEST_NONE && p->test != DS_TEST_SAFE && p->test != DS_TEST_DST3) {
+    set_error("unknown test");
+    return DS_EINVAL;
+  }
+  if (p->lambda_mode != DS_LAMBDA_ABSOLUTE && p->lambda_mode != DS_LAMBDA_RELATIVE) {
+    set_error("unknown lambda mode");
+    return DS_EINVAL;
+  }
+  if (!(p->gap_tol >= 0.0) || !std::isfinite(p->gap_tol)) { set_error("gap_tol must be >= 0"); return DS_EINVAL; }
+  if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return DS_EINVAL; }
+  if (!std::isfinite(p->step_L)) { set_error("step_L must be finite"); return DS_EINVAL; }
+  if (p->reserved != 0) { set_error("reserved field must be 0"); return DS_EINVAL; }
+  return DS_OK;
+}
+
+namespace {
+
+ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                       const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                       ds_info* info, void* stream, bool group) {
+  ds_status e = validate_problem(problem, group);
+  if (e != DS_OK) return e;
+  if ((e = validate_params(params)) != DS_OK) return e;
+  if (Y == nullptr || X == nullptr || info == nullptr || lambdas == nullptr) {
+    set_error("Y, X, lambdas and info must be non-NULL");
+    return DS_EINVAL;
+  }
+  if (B < 1 || ldy < problem->N || ldx < problem->K) {
+    set_error("bad B / ldy / ldx");
+    return DS_EINVAL;
+  }
+  for (int64_t b = 0; b < B; ++b) {
+    if (!(lambdas[b] > 0.0) || !std::isfinite(lambdas[b])) {
+      set_error("lambda[%lld] must be positive and finite", static_cast<long long>(b));
+      return DS_EINVAL;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  DS_HIP(hipGetDevice(&dev));
+  if (B > 1 && problem->dtype == DS_BF16 && !group) {
+    return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, s);
+  }
+  DeviceCtx& ctx = device_ctx(dev);
+  std::lock_guard<std::mutex> g(ctx.mu);
+  const size_t vsz = problem->dtype == DS_F64 ? 8 : 4;
+  ds_status worst = DS_OK;
+  for (int64_t b = 0; b < B; ++b) {
+    const char* yb = static_cast<const char*>(Y) + b * ldy * vsz;
+    char* xb = static_cast<char*>(X) + b * ldx * vsz;
+    std::memset(&info[b], 0, sizeof(ds_info));
+    e = solve_single(*problem, yb, lambdas[b], *params, xb, &info[b], s, ctx.ws, nullptr);
+    if (e < 0) return e;
+    if (e == DS_NOT_CONVERGED) worst = DS_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+}  // namespace
+}  // namespace ds
+
+using namespace ds;
+
+extern "C" {
+
+ds_status lasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                      const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                      ds_info* info, void* stream) {
+  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, stream, false);
+}
+
+ds_status glasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                       const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                       ds_info* info, void* stream) {
+  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, stream, true);
+}
+
+ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,
+                       const ds_params* params, void* x, uint8_t* screened, ds_trace* trace,
+                       int32_t trace_cap, ds_info* info, void* stream) {
+  const bool group = problem != nullptr && problem->G > 0;
+  ds_status e = validate_problem(problem, group);
+  if (e != DS_OK) return e;
+  if ((e = validate_params(params)) != DS_OK) return e;
+  if (y == nullptr || x == nullptr || info == nullptr) {
+    set_error("y, x and info must be non-NULL");
+    return DS_EINVAL;
+  }
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) { set_error("lambda must be positive"); return DS_EINVAL; }
+  if (trace != nullptr && trace_cap < 0) { set_error("trace_cap < 0"); return DS_EINVAL; }
+  int dev = 0;
+  DS_HIP(hipGetDevice(&dev));
+  DeviceCtx& ctx = device_ctx(dev);
+  std::lock_guard<std::mutex> g(ctx.mu);
+  std::memset(info, 0, sizeof(ds_info));
+  std::vector<Telemetry> tl;
+  e = solve_single(*problem, y, lambda, *params, x, info, static_cast<hipStream_t>(stream), ctx.ws,
+                   trace != nullptr ? &tl : nullptr, screened);
+  if (e < 0) return e;
+  if (trace != nullptr) {
+    const size_t n = std::min<size_t>(tl.size(), static_cast<size_t>(trace_cap));
+    for (size_t k = 0; k < n; ++k) {
+      trace[k].n_active = tl[k].n_atoms;
+      trace[k].n_units = tl[k].n_units;
+      trace[k].n_support = tl[k].n_support;
+      trace[k].nnz = tl[k].nnz;
+      trace[k].radius = tl[k].r;
+      trace[k].gap = tl[k].gap;
+    }
+  }
+  return e;
+}
+
+ds_status ds_lambda_max(const ds_problem* problem, const void* y, double* lambda_max,
+                        int64_t* argmax, void* stream) {
+  ds_status e = validate_problem(problem, problem != nullptr && problem->G > 0);
+  if (e != DS_OK) return e;
+  if (y == nullptr || lambda_max == nullptr) { set_error("y and lambda_max must be non-NULL"); return DS_EINVAL; }
+  int dev = 0;
+  DS_HIP(hipGetDevice(&dev));
+  DeviceCtx& ctx = device_ctx(dev);
+  std::lock_guard<std::mutex> g(ctx.mu);
+  return lambda_max_impl(*problem, y, lambda_max, argmax, static_cast<hipStream_t>(stream), ctx.ws);
+}
+
+ds_status ds_spectral_norm_sq(const ds_problem* problem, int32_t iters, double* L, void* stream) {
+  ds_status e = validate_problem(problem, problem != nullptr && problem->G > 0);
+  if (e != DS_OK) return e;
+  if (L == nullptr) { set_error("L is NULL"); return DS_EINVAL; }
+  int dev = 0;
+  DS_HIP(hipGetDevice(&dev));
+  DeviceCtx& ctx = device_ctx(dev);
+  std::lock_guard<std::mutex> g(ctx.mu);
+  return spectral_norm_impl(*problem, iters, L, static_cast<hipStream_t>(stream), ctx.ws);
+}
+
+void ds_stats_enable(int on) {
+  StatAccum& S = stats();
+  std::lock_guard<std::mutex> g(S.mu);
+  S.on = on != 0;
+}
+
+void ds_stats_reset(void) {
+  StatAccum& S = stats();
+  std::lock_guard<std::mutex> g(S.mu);
+  for (auto& k : S.s) k = ds_kernel_stat{};
+}
+
+int ds_stats_read(ds_kernel_stat* out, int n) {
+  if (out == nullptr || n <= 0) return 0;
+  StatAccum& S = stats();
+  std::lock_guard<std::mutex> g(S.mu);
+  const int m = n < DS_STAT_COUNT ? n : DS_STAT_COUNT;
+  for (int k = 0; k < m; ++k) out[k] = S.s[k];
+  return m;
+}
+
+const char* ds_last_error(void) { return g_err.c_str(); }
+
+const char* ds_version(void) { return "dynscreen 0.1 (gfx950)"; }
+
+}  // extern "C"

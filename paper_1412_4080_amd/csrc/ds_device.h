@@ -1,0 +1,174 @@
+// Device-side building blocks shared by the dynamic-screening kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ds {
+
+constexpr int WAVE = 64;
+
+typedef uint16_t bf16_t;  // bfloat16 bit pattern
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// Storage traits.  VEC = elements per 16-byte load; V = vector (y, x, theta) type;
+// A = accumulation type of the streaming GEMVs.  Products of float (or bfloat16) values
+// are exact in FP64, so FP64 accumulation leaves only the summation rounding (~N 2^-53):
+// the rounding slack of the dual scaling becomes negligible, and the extra FP64 FMA per
+// element is far below the FP64 rate of the chip at HBM speed.
+template <typename T> struct Store;
+template <> struct Store<double> { using V = double; using A = double; static constexpr int VEC = 2; };
+template <> struct Store<float>  { using V = float;  using A = double; static constexpr int VEC = 4; };
+template <> struct Store<bf16_t> { using V = float;  using A = double; static constexpr int VEC = 8; };
+
+// 16-byte load of VEC consecutive stored elements, widened to A.
+template <typename T, typename A>
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, A (&out)[Store<T>::VEC]);
+
+template <>
+__device__ __forceinline__ void load_vec<double, double>(const double* __restrict__ p, double (&o)[2]) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  o[0] = v.x; o[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void load_vec<float, float>(const float* __restrict__ p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<bf16_t, float>(const bf16_t* __restrict__ p, float (&o)[8]) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
+  o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);
+  o[4] = __uint_as_float(v.z << 16); o[5] = __uint_as_float(v.z & 0xffff0000u);
+  o[6] = __uint_as_float(v.w << 16); o[7] = __uint_as_float(v.w & 0xffff0000u);
+}
+// Same widths, double accumulation (setup passes: products of stored values are exact
+// in FP64 for float and bfloat16 storage).
+template <>
+__device__ __forceinline__ void load_vec<float, double>(const float* __restrict__ p, double (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<bf16_t, double>(const bf16_t* __restrict__ p, double (&o)[8]) {
+  float f[8];
+  load_vec<bf16_t, float>(p, f);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) o[k] = f[k];
+}
+
+template <typename T> __device__ __forceinline__ double to_double(T v);
+template <> __device__ __forceinline__ double to_double<double>(double v) { return v; }
+template <> __device__ __forceinline__ double to_double<float>(float v) { return v; }
+template <> __device__ __forceinline__ double to_double<bf16_t>(bf16_t v) { return bf16_to_f32(v); }
+
+
+// ---------------------------------------------------------------- reductions ------
+template <typename X>
+__device__ __forceinline__ X wave_sum(X v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+template <typename X>
+__device__ __forceinline__ X wave_max(X v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    X w = __shfl_xor(v, o, WAVE);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+template <typename X>
+__device__ __forceinline__ X wave_min(X v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    X w = __shfl_xor(v, o, WAVE);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// Block-wide reductions with a fixed combination order (deterministic).  `scratch`
+// must hold one X per wave; the result is returned to every thread.
+template <typename X, int NWAVES>
+__device__ __forceinline__ X block_sum(X v, X* scratch) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) scratch[w] = v;
+  __syncthreads();
+  X s = scratch[0];
+#pragma unroll
+  for (int k = 1; k < NWAVES; ++k) s += scratch[k];
+  return s;
+}
+template <typename X, int NWAVES>
+__device__ __forceinline__ X block_max(X v, X* scratch) {
+  v = wave_max(v);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) scratch[w] = v;
+  __syncthreads();
+  X s = scratch[0];
+#pragma unroll
+  for (int k = 1; k < NWAVES; ++k) s = scratch[k] > s ? scratch[k] : s;
+  return s;
+}
+template <typename X, int NWAVES>
+__device__ __forceinline__ X block_min(X v, X* scratch) {
+  v = wave_min(v);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) scratch[w] = v;
+  __syncthreads();
+  X s = scratch[0];
+#pragma unroll
+  for (int k = 1; k < NWAVES; ++k) s = scratch[k] < s ? scratch[k] : s;
+  return s;
+}
+
+// Exclusive block scan of one int per thread (any NWAVES <= 16).  Returns the exclusive
+// prefix; *total receives the block sum.
+template <int NWAVES>
+__device__ __forceinline__ int block_exclusive_scan(int v, int* scratch, int* total) {
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int t = __shfl_up(incl, o, WAVE);
+    if (l >= o) incl += t;
+  }
+  __syncthreads();
+  if (l == WAVE - 1) scratch[w] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NWAVES; ++k) {
+    const int s = scratch[k];
+    if (k < w) base += s;
+    tot += s;
+  }
+  *total = tot;
+  return base + incl - v;
+}
+
+// "Last block" handshake: every block publishes its partials, then increments a
+// counter; the block that brings it to gridDim.x runs the epilogue and re-arms it.
+__device__ __forceinline__ bool last_block_arrive(unsigned* counter, int* flag_lds) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    *flag_lds = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *flag_lds != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+}  // namespace ds

@@ -1,0 +1,83 @@
+// Host-side engine shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dynscreen.h"
+
+namespace ds {
+
+void set_error(const char* fmt, ...);
+
+#define DS_HIP(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ::ds::set_error("HIP error %s at %s:%d: %s", hipGetErrorString(e_), __FILE__,     \
+                      __LINE__, #expr);                                                 \
+      return DS_EDEVICE;                                                                \
+    }                                                                                   \
+  } while (0)
+
+// Per-iteration telemetry written on the device by the last correlation block: the
+// quantities the paper's flops model needs (|I^c_t|, ||x_t||_0) plus radius and gap.
+struct Telemetry {
+  int32_t n_atoms;     // active atoms used by this iteration's update
+  int32_t n_units;     // active units (atoms or groups)
+  int32_t n_support;   // support size of the primal point theta was evaluated at
+  int32_t nnz;         // non-zeros of x_t
+  double r;            // radius r_t (no slack)
+  double gap;          // gap certificate
+};
+static_assert(sizeof(Telemetry) == 32, "telemetry record layout");
+
+// Kernel statistics (diagnostics API).
+struct StatAccum {
+  std::mutex mu;
+  bool on = false;
+  ds_kernel_stat s[DS_STAT_COUNT] = {};
+};
+StatAccum& stats();
+
+// One device allocation carved into the buffers of a single-signal solve.
+struct Workspace {
+  int device = -1;
+  void* base = nullptr;
+  size_t bytes = 0;
+  void* host_pinned = nullptr;  // small pinned staging area for the state
+  std::vector<hipEvent_t> events;
+  ~Workspace();
+  ds_status reserve(size_t need);
+  void release();  // frees everything (temporary workspaces; cached ones live until exit)
+};
+
+// Per-device cache of workspaces (one in use at a time per lock holder).
+struct DeviceCtx {
+  std::mutex mu;
+  Workspace ws;
+};
+DeviceCtx& device_ctx(int device);
+
+ds_status validate_problem(const ds_problem* p, bool group);
+ds_status validate_params(const ds_params* p);
+
+ds_status solve_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
+                       void* x, ds_info* info, hipStream_t stream, Workspace& ws,
+                       std::vector<Telemetry>* tele_out, uint8_t* screened = nullptr);
+ds_status lambda_max_impl(const ds_problem& P, const void* y, double* lmax, int64_t* arg,
+                          hipStream_t stream, Workspace& ws);
+ds_status spectral_norm_impl(const ds_problem& P, int iters, double* L, hipStream_t stream,
+                             Workspace& ws);
+// Batched MFMA path (bfloat16 storage, B > 1).
+ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
+                             const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
+                             ds_info* info, hipStream_t stream);
+
+size_t dtype_size(ds_dtype t);
+
+}  // namespace ds

@@ -1,0 +1,477 @@
+// Single-signal solve: setup on the device, then chunks of iterations enqueued ahead of
+// the device-side stopping decision (see ds_single_kernels.h for the kernels).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ds_engine.h"
+#include "ds_single_kernels.h"
+
+namespace ds {
+
+namespace {
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+  size_t off_state, off_act0, off_act1, off_x, off_u, off_sidx, off_sval, off_theta,
+      off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_bp0,
+      off_bp1, off_bpi, off_cnt, off_gptr, off_w, off_tele, off_pv, off_pw, off_pz, off_pd,
+      total;
+  int64_t npad, nchunks;
+};
+
+Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int64_t tele_cap,
+                   bool power) {
+  Layout l{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += static_cast<size_t>(round_up(static_cast<int64_t>(bytes), 256));
+    return at;
+  };
+  l.npad = round_up(N, 64);
+  l.nchunks = (K + RCH - 1) / RCH;
+  const int64_t units = G > 0 ? G : K;
+  l.off_state = take(sizeof(SolverState));
+  l.off_act0 = take(units * 4);
+  l.off_act1 = take(units * 4);
+  l.off_x = take(K * vsz);
+  l.off_u = take(K * vsz);
+  l.off_sidx = take(K * 4);
+  l.off_sval = take(K * vsz);
+  l.off_theta = take(l.npad * vsz);
+  l.off_partial = take(l.nchunks * l.npad * asz);
+  l.off_z0 = take(K * 8);
+  l.off_g = take(K * 8);
+  l.off_nu = take(K * 8);
+  l.off_fro = take(std::max<int64_t>(G, 1) * 8);
+  l.off_gnorm = take(std::max<int64_t>(G, 1) * 8);
+  l.off_marg = take(units * 8);
+  l.off_nvec = take(l.npad * 8);
+  l.off_bp0 = take(MAXB * 8);
+  l.off_bp1 = take(MAXB * 8);
+  l.off_bpi = take(MAXB * 4);
+  l.off_cnt = take(16 * 4);
+  l.off_gptr = take((std::max<int64_t>(G, 1) + 1) * 8);
+  l.off_w = take(std::max<int64_t>(G, 1) * 8);
+  l.off_tele = take(tele_cap * sizeof(Telemetry));
+  if (power) {
+    l.off_pv = take(K * 8);
+    l.off_pz = take(K * 8);
+    l.off_pw = take(l.npad * 8);
+    l.off_pd = take(((K + PCH - 1) / PCH) * l.npad * 8 + 64);
+  }
+  l.total = o;
+  return l;
+}
+
+template <typename T> struct Types { using V = typename Store<T>::V; using A = typename Store<T>::A; };
+
+template <typename T>
+bool vector_ok(const void* D, int64_t ldd) {
+  return (reinterpret_cast<uintptr_t>(D) % 16 == 0) && ((ldd * sizeof(T)) % 16 == 0);
+}
+
+template <typename T>
+SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_problem& P,
+                                                                    const void* y, char* base,
+                                                                    const Layout& l, int test,
+                                                                    int rule) {
+  using V = typename Types<T>::V;
+  using A = typename Types<T>::A;
+  SingleArgs<T, V, A> a{};
+  a.D = static_cast<const T*>(P.D);
+  a.ldd = P.ldd;
+  a.N = static_cast<int32_t>(P.N);
+  a.K = static_cast<int32_t>(P.K);
+  a.G = static_cast<int32_t>(P.G);
+  a.test = test;
+  a.rule = rule;
+  a.gptr = P.G > 0 ? reinterpret_cast<const int64_t*>(base + l.off_gptr) : nullptr;
+  a.w = P.G > 0 ? reinterpret_cast<const double*>(base + l.off_w) : nullptr;
+  a.y = static_cast<const V*>(y);
+  a.st = reinterpret_cast<SolverState*>(base + l.off_state);
+  a.act[0] = reinterpret_cast<int32_t*>(base + l.off_act0);
+  a.act[1] = reinterpret_cast<int32_t*>(base + l.off_act1);
+  a.x = reinterpret_cast<V*>(base + l.off_x);
+  a.u = reinterpret_cast<V*>(base + l.off_u);
+  a.s_idx = reinterpret_cast<int32_t*>(base + l.off_sidx);
+  a.s_val = reinterpret_cast<V*>(base + l.off_sval);
+  a.theta = reinterpret_cast<V*>(base + l.off_theta);
+  a.partial = reinterpret_cast<A*>(base + l.off_partial);
+  a.npad = l.npad;
+  a.z0 = reinterpret_cast<double*>(base + l.off_z0);
+  a.g = reinterpret_cast<double*>(base + l.off_g);
+  a.nu = reinterpret_cast<double*>(base + l.off_nu);
+  a.fro = reinterpret_cast<double*>(base + l.off_fro);
+  a.gnorm = reinterpret_cast<double*>(base + l.off_gnorm);
+  a.marg = reinterpret_cast<double*>(base + l.off_marg);
+  a.nvec = reinterpret_cast<double*>(base + l.off_nvec);
+  a.bp0 = reinterpret_cast<double*>(base + l.off_bp0);
+  a.bp1 = reinterpret_cast<double*>(base + l.off_bp1);
+  a.bpi = reinterpret_cast<int32_t*>(base + l.off_bpi);
+  a.counters = reinterpret_cast<unsigned*>(base + l.off_cnt);
+  return a;
+}
+
+inline int grid_for(int64_t work, int per_block, int cap) {
+  const int64_t g = (work + per_block - 1) / per_block;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
+}
+
+// Upload group offsets and weights (default w_g = sqrt(|g|)) into the workspace.
+ds_status upload_groups(const ds_problem& P, char* base, const Layout& l, hipStream_t s,
+                        std::vector<double>& wbuf) {
+  if (P.G <= 0) return DS_OK;
+  wbuf.resize(P.G);
+  for (int64_t g = 0; g < P.G; ++g)
+    wbuf[g] = P.w ? P.w[g] : std::sqrt(static_cast<double>(P.group_ptr[g + 1] - P.group_ptr[g]));
+  DS_HIP(hipMemcpyAsync(base + l.off_gptr, P.group_ptr, (P.G + 1) * 8, hipMemcpyHostToDevice, s));
+  DS_HIP(hipMemcpyAsync(base + l.off_w, wbuf.data(), P.G * 8, hipMemcpyHostToDevice, s));
+  return DS_OK;
+}
+
+// Setup passes shared by lambda_max and the solve: z0 = D^T y, atom norms, group norms.
+template <typename T, bool VEC>
+ds_status launch_setup_corr(const ds_problem& P, const void* y, char* base, const Layout& l,
+                            hipStream_t s) {
+  using V = typename Types<T>::V;
+  const int gridK = grid_for(P.K, NW * CPW, 4096);
+  hipLaunchKernelGGL((k_setup_gemv<T, V, VEC, true>), dim3(gridK), dim3(BLK), 0, s,
+                     static_cast<const T*>(P.D), P.ldd, static_cast<int>(P.N),
+                     static_cast<int>(P.K), static_cast<const V*>(y),
+                     reinterpret_cast<double*>(base + l.off_z0),
+                     reinterpret_cast<double*>(base + l.off_nu));
+  DS_HIP(hipGetLastError());
+  if (P.G > 0) {
+    hipLaunchKernelGGL((k_group_norms<T>), dim3(grid_for(P.G, 1, 4096)), dim3(BLK), 0, s,
+                       static_cast<const T*>(P.D), P.ldd, static_cast<int>(P.N),
+                       static_cast<int>(P.G),
+                       reinterpret_cast<const int64_t*>(base + l.off_gptr),
+                       reinterpret_cast<double*>(base + l.off_gnorm),
+                       reinterpret_cast<double*>(base + l.off_fro));
+    DS_HIP(hipGetLastError());
+  }
+  return DS_OK;
+}
+
+template <typename T, bool VEC, int RULE>
+ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
+                     void* x, ds_info* info, hipStream_t s, Workspace& ws,
+                     std::vector<Telemetry>* tele_out, uint8_t* screened) {
+  using V = typename Types<T>::V;
+  using A = typename Types<T>::A;
+  const int64_t tele_cap = std::max<int32_t>(prm.max_iter, 1);
+  const Layout l = make_layout(P.N, P.K, P.G, sizeof(V), sizeof(A), tele_cap, false);
+  ds_status st_ = ws.reserve(l.total);
+  if (st_ != DS_OK) return st_;
+  char* base = static_cast<char*>(ws.base);
+  const int test = static_cast<int>(prm.test), rule = RULE;
+  SingleArgs<T, V, A> a = make_args<T>(P, y, base, l, test, rule);
+  Telemetry* tele = reinterpret_cast<Telemetry*>(base + l.off_tele);
+  a.tele = tele;
+  a.tele_cap = static_cast<int32_t>(tele_cap);
+  std::vector<double> wbuf;
+  if ((st_ = upload_groups(P, base, l, s, wbuf)) != DS_OK) return st_;
+  DS_HIP(hipMemsetAsync(a.counters, 0, 16 * 4, s));
+
+  // ---- setup (no host synchronisation) ----
+  if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
+  // L: given, or estimated here (slow path)
+  double L = prm.step_L;
+  if (!(L > 0.0)) {
+    // the power iteration uses its own (larger) workspace; keep ours intact by running it
+    // on a private one
+    Workspace tmp;
+    tmp.device = ws.device;
+    ds_status e = spectral_norm_impl(P, 0, &L, s, tmp);
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    if (e != DS_OK) return e;
+  }
+  const double u_round = sizeof(A) == 4 ? 0x1p-24 : 0x1p-53;
+  const double kchain = std::ceil(static_cast<double>(P.N) / WAVE) + Store<T>::VEC + 8;
+  const double gamma_z = kchain * u_round / (1.0 - kchain * u_round);
+  const bool relative = prm.lambda_mode == DS_LAMBDA_RELATIVE;
+  hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, lam,
+                     relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z);
+  DS_HIP(hipGetLastError());
+  if (prm.test == DS_TEST_DST3) {
+    hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
+                       0, s, a);
+    DS_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_setup_gemv<T, double, VEC, false>),
+                       dim3(grid_for(P.K, NW * CPW, 4096)), dim3(BLK), 0, s, a.D, a.ldd, a.N,
+                       a.K, static_cast<const double*>(a.nvec), a.g, nullptr);
+    DS_HIP(hipGetLastError());
+  }
+  const int64_t units = P.G > 0 ? P.G : P.K;
+  hipLaunchKernelGGL((k_setup_margins<T, V, A>), dim3(grid_for(std::max(units, P.K), BLK, 1 << 20)),
+                     dim3(BLK), 0, s, a);
+  DS_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_setup_slack<T, V, A>), dim3(1), dim3(CBLK), 0, s, a);
+  DS_HIP(hipGetLastError());
+
+  // ---- iterations ----
+  constexpr int VR = VEC ? Store<T>::VEC : 1;
+  const int nrt = static_cast<int>((P.N + BLK * VR - 1) / (BLK * VR));
+  const int grid_res = grid_for(static_cast<int64_t>(nrt) * l.nchunks, 1, 1024);
+  const int grid_fin = grid_for(P.N, BLK, 1 << 20);
+  const int grid_corr = P.G > 0 ? grid_for(P.G, NW, MAXB) : grid_for(P.K, NW * CPW, MAXB);
+  if (grid_fin > MAXB) {
+    set_error("N too large for the residual finalisation (N <= %d)", MAXB * BLK);
+    return DS_EINVAL;
+  }
+  StatAccum& S = stats();
+  bool stat_on;
+  {
+    std::lock_guard<std::mutex> g(S.mu);
+    stat_on = S.on;
+  }
+  SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<double> ev_bytes;
+  size_t ev_used = 0;
+  auto get_events = [&]() -> std::pair<hipEvent_t, hipEvent_t> {
+    while (ws.events.size() < 2 * (ev_used + 1)) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return {nullptr, nullptr};
+      ws.events.push_back(e);
+    }
+    auto p = std::make_pair(ws.events[2 * ev_used], ws.events[2 * ev_used + 1]);
+    ++ev_used;
+    return p;
+  };
+
+  int it = 0, chunk = 4;
+  bool finished = false;
+  while (!finished && it < prm.max_iter) {
+    const int nrun = std::min(chunk, prm.max_iter - it);
+    for (int k = 0; k < nrun; ++k) {
+      hipLaunchKernelGGL((k_resid<T, V, A, VEC>), dim3(grid_res), dim3(BLK), 0, s, a);
+      hipLaunchKernelGGL((k_resid_finalize<T, V, A>), dim3(grid_fin), dim3(BLK), 0, s, a);
+      std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+      if (stat_on) {
+        e = get_events();
+        if (e.first) DS_HIP(hipEventRecord(e.first, s));
+      }
+      if (P.G > 0)
+        hipLaunchKernelGGL((k_corr_group<T, V, A, VEC, RULE>), dim3(grid_corr), dim3(BLK), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_corr_lasso<T, V, A, VEC, RULE>), dim3(grid_corr), dim3(BLK), 0, s, a);
+      if (stat_on && e.first) {
+        DS_HIP(hipEventRecord(e.second, s));
+        ev.push_back(e);
+      }
+      hipLaunchKernelGGL((k_compact<T, V, A>), dim3(1), dim3(CBLK), 0, s, a);
+    }
+    DS_HIP(hipGetLastError());
+    it += nrun;
+    DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipStreamSynchronize(s));
+    finished = hst->done != 0;
+    chunk = std::min(chunk * 2, 64);
+  }
+
+  // ---- output ----
+  V* X = static_cast<V*>(x);
+  hipLaunchKernelGGL((k_zero_out<T, V, A>), dim3(grid_for(P.K, BLK, 1 << 20)), dim3(BLK), 0, s, X,
+                     static_cast<int>(P.K));
+  hipLaunchKernelGGL((k_scatter_out<T, V, A>), dim3(grid_for(units, BLK, 1 << 20)), dim3(BLK), 0,
+                     s, a, X);
+  DS_HIP(hipGetLastError());
+  if (screened != nullptr) {
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(P.K, BLK, 1 << 20)), dim3(BLK), 0, s, screened,
+                       static_cast<int>(P.K), static_cast<uint8_t>(1));
+    hipLaunchKernelGGL((k_mark_active<T, V, A>), dim3(grid_for(units, BLK, 1 << 20)), dim3(BLK), 0,
+                       s, a, screened);
+    DS_HIP(hipGetLastError());
+  }
+  DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  DS_HIP(hipStreamSynchronize(s));
+
+  const int iters_run = hst->iter;
+  std::vector<Telemetry> tl;
+  if ((stat_on || tele_out) && iters_run > 0) {
+    tl.resize(std::min<int64_t>(iters_run, tele_cap));
+    DS_HIP(hipMemcpy(tl.data(), tele, tl.size() * sizeof(Telemetry), hipMemcpyDeviceToHost));
+  }
+  if (stat_on && !ev.empty()) {
+    // algorithmic bytes of one correlation launch: the active columns of D, theta, the
+    // read-modify-write of x and u on the active atoms and the active list
+    double ms = 0.0, bytes = 0.0, flops = 0.0;
+    const size_t used = std::min(ev.size(), tl.size());
+    for (size_t k = 0; k < used; ++k) {
+      float f = 0.f;
+      if (hipEventElapsedTime(&f, ev[k].first, ev[k].second) == hipSuccess) ms += f;
+      const double na = tl[k].n_atoms, nu = tl[k].n_units;
+      bytes += na * P.N * sizeof(T) + P.N * sizeof(V) + 4.0 * na * sizeof(V) + 4.0 * nu;
+      flops += 2.0 * na * P.N;
+    }
+    std::lock_guard<std::mutex> g(S.mu);
+    S.s[DS_STAT_CORR].launches += static_cast<int64_t>(used);
+    S.s[DS_STAT_CORR].ms += ms;
+    S.s[DS_STAT_CORR].bytes += bytes;
+    S.s[DS_STAT_CORR].flops += flops;
+  }
+  if (tele_out) *tele_out = std::move(tl);
+
+  if (hst->status < 0) {
+    set_error("observation contains NaN or Inf");
+    return DS_EINVAL;
+  }
+  info->iters = hst->iter;
+  info->n_active = hst->status == 1 ? 0 : hst->n_active_atoms;
+  info->nnz = hst->status == 1 ? 0 : hst->nnz;
+  info->lambda = hst->lam;
+  info->lambda_max = hst->lam_max;
+  info->primal = hst->primal;
+  info->dual = hst->dual;
+  info->gap = hst->gap;
+  info->radius = hst->r_min;
+  info->mu = hst->mu;
+  info->L = hst->L;
+  info->radius_slack = hst->r_slack + hst->marg_slack;
+  const bool converged = hst->status == 1 || prm.gap_tol <= 0.0 || hst->gap <= hst->gap_tol_abs;
+  info->status = converged ? DS_OK : DS_NOT_CONVERGED;
+  return converged ? DS_OK : DS_NOT_CONVERGED;
+}
+
+template <typename T>
+ds_status dispatch_rule(const ds_problem& P, const void* y, double lam, const ds_params& prm,
+                        void* x, ds_info* info, hipStream_t s, Workspace& ws,
+                        std::vector<Telemetry>* tele, uint8_t* scr) {
+  const bool vec = vector_ok<T>(P.D, P.ldd);
+  if (prm.rule == DS_FISTA)
+    return vec ? run_single<T, true, RULE_FISTA>(P, y, lam, prm, x, info, s, ws, tele, scr)
+               : run_single<T, false, RULE_FISTA>(P, y, lam, prm, x, info, s, ws, tele, scr);
+  return vec ? run_single<T, true, RULE_ISTA>(P, y, lam, prm, x, info, s, ws, tele, scr)
+             : run_single<T, false, RULE_ISTA>(P, y, lam, prm, x, info, s, ws, tele, scr);
+}
+
+}  // namespace
+
+ds_status solve_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
+                       void* x, ds_info* info, hipStream_t stream, Workspace& ws,
+                       std::vector<Telemetry>* tele_out, uint8_t* scr) {
+  switch (P.dtype) {
+    case DS_F64: return dispatch_rule<double>(P, y, lam, prm, x, info, stream, ws, tele_out, scr);
+    case DS_F32: return dispatch_rule<float>(P, y, lam, prm, x, info, stream, ws, tele_out, scr);
+    case DS_BF16: return dispatch_rule<bf16_t>(P, y, lam, prm, x, info, stream, ws, tele_out, scr);
+  }
+  set_error("unknown dtype");
+  return DS_EINVAL;
+}
+
+// ------------------------------------------------------------------ lambda_max -------
+namespace {
+template <typename T>
+ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t* arg,
+                       hipStream_t s, Workspace& ws) {
+  using V = typename Types<T>::V;
+  using A = typename Types<T>::A;
+  const Layout l = make_layout(P.N, P.K, P.G, sizeof(V), sizeof(A), 1, false);
+  ds_status e = ws.reserve(l.total);
+  if (e != DS_OK) return e;
+  char* base = static_cast<char*>(ws.base);
+  std::vector<double> wbuf;
+  if ((e = upload_groups(P, base, l, s, wbuf)) != DS_OK) return e;
+  SingleArgs<T, V, A> a = make_args<T>(P, y, base, l, TEST_NONE, RULE_ISTA);
+  e = vector_ok<T>(P.D, P.ldd) ? launch_setup_corr<T, true>(P, y, base, l, s)
+                               : launch_setup_corr<T, false>(P, y, base, l, s);
+  if (e != DS_OK) return e;
+  hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, 1.0, 1, 1.0, 0.0,
+                     1, 0.0);
+  DS_HIP(hipGetLastError());
+  SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
+  DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  DS_HIP(hipStreamSynchronize(s));
+  if (hst->status < 0) {
+    set_error("observation contains NaN or Inf");
+    return DS_EINVAL;
+  }
+  *lmax = hst->lam_max;
+  if (arg) *arg = hst->i_star;
+  return DS_OK;
+}
+
+template <typename T>
+ds_status spectral_t(const ds_problem& P, int iters, double* Lout, hipStream_t s, Workspace& ws) {
+  using V = typename Types<T>::V;
+  using A = typename Types<T>::A;
+  const Layout l = make_layout(P.N, P.K, P.G, sizeof(V), sizeof(A), 1, true);
+  ds_status e = ws.reserve(l.total);
+  if (e != DS_OK) return e;
+  char* base = static_cast<char*>(ws.base);
+  double* v = reinterpret_cast<double*>(base + l.off_pv);
+  double* zk = reinterpret_cast<double*>(base + l.off_pz);
+  double* w = reinterpret_cast<double*>(base + l.off_pw);
+  double* part = reinterpret_cast<double*>(base + l.off_pd);
+  double* dots = reinterpret_cast<double*>(base + l.off_bp0);
+  const int N = static_cast<int>(P.N), K = static_cast<int>(P.K);
+  const T* D = static_cast<const T*>(P.D);
+  const int nch = (K + PCH - 1) / PCH;
+  const int nrt = (N + BLK - 1) / BLK;
+  const int gdv = grid_for(static_cast<int64_t>(nrt) * nch, 1, 2048);
+  const bool vec = vector_ok<T>(P.D, P.ldd);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(K, BLK, 1 << 20)), dim3(BLK), 0, s, v, K,
+                     1.0 / std::sqrt(static_cast<double>(K)));
+  auto dv = [&](const double* src) {
+    hipLaunchKernelGGL((k_pow_dv<T>), dim3(gdv), dim3(BLK), 0, s, D, P.ldd, N, K, src, part, l.npad);
+    hipLaunchKernelGGL(k_pow_reduce, dim3(grid_for(N, BLK, 1 << 20)), dim3(BLK), 0, s, part, nch,
+                       l.npad, N, w);
+  };
+  auto dtw = [&](double* dst) {
+    if (vec)
+      hipLaunchKernelGGL((k_setup_gemv<T, double, true, false>), dim3(grid_for(K, NW * CPW, 4096)),
+                         dim3(BLK), 0, s, D, P.ldd, N, K, static_cast<const double*>(w), dst, nullptr);
+    else
+      hipLaunchKernelGGL((k_setup_gemv<T, double, false, false>), dim3(grid_for(K, NW * CPW, 4096)),
+                         dim3(BLK), 0, s, D, P.ldd, N, K, static_cast<const double*>(w), dst, nullptr);
+  };
+  if (iters <= 0) iters = 200;
+  for (int k = 0; k < iters; ++k) {
+    dv(v);        // w = D v
+    dtw(zk);      // zk = D^T D v
+    hipLaunchKernelGGL(k_pow_dots, dim3(1), dim3(CBLK), 0, s, v, zk, K, dots);
+    hipLaunchKernelGGL(k_pow_scale, dim3(grid_for(K, BLK, 1 << 20)), dim3(BLK), 0, s, zk, K, dots, v);
+  }
+  DS_HIP(hipGetLastError());
+  // Rayleigh quotient rho = v^T D^T D v (v unit) and residual ||D^T D v - rho v||
+  dv(v);
+  dtw(zk);
+  hipLaunchKernelGGL(k_pow_dots, dim3(1), dim3(CBLK), 0, s, v, zk, K, dots);
+  double h[3];
+  DS_HIP(hipMemcpyAsync(h, dots, sizeof(h), hipMemcpyDeviceToHost, s));
+  DS_HIP(hipStreamSynchronize(s));
+  const double vv = h[0], rho = h[1] / vv, zz = h[2] / vv;
+  const double res2 = std::max(zz - rho * rho, 0.0);
+  *Lout = (rho + std::sqrt(res2)) * (1.0 + 1e-12);
+  return DS_OK;
+}
+}  // namespace
+
+ds_status lambda_max_impl(const ds_problem& P, const void* y, double* lmax, int64_t* arg,
+                          hipStream_t stream, Workspace& ws) {
+  switch (P.dtype) {
+    case DS_F64: return lambda_max_t<double>(P, y, lmax, arg, stream, ws);
+    case DS_F32: return lambda_max_t<float>(P, y, lmax, arg, stream, ws);
+    case DS_BF16: return lambda_max_t<bf16_t>(P, y, lmax, arg, stream, ws);
+  }
+  return DS_EINVAL;
+}
+
+ds_status spectral_norm_impl(const ds_problem& P, int iters, double* L, hipStream_t stream,
+                             Workspace& ws) {
+  switch (P.dtype) {
+    case DS_F64: return spectral_t<double>(P, iters, L, stream, ws);
+    case DS_F32: return spectral_t<float>(P, iters, L, stream, ws);
+    case DS_BF16: return spectral_t<bf16_t>(P, iters, L, stream, ws);
+  }
+  return DS_EINVAL;
+}
+
+}  // namespace ds

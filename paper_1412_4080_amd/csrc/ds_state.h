@@ -1,0 +1,93 @@
+// Device-resident solver state and kernel argument blocks of the single-signal path.
+#pragma once
+#include <stdint.h>
+
+namespace ds {
+
+enum TestKind { TEST_NONE = 0, TEST_SAFE = 1, TEST_DST3 = 2 };
+enum RuleKind { RULE_ISTA = 0, RULE_FISTA = 1 };
+
+// Every scalar of the iteration lives in device memory so that a whole chunk of
+// iterations can be enqueued (or graph-replayed) without host round trips.
+struct alignas(16) SolverState {
+  // problem scalars (set up on the device)
+  double lam;          // absolute penalty
+  double lam_ratio;    // lambda / lambda_* when the penalty is relative, else <= 0
+  double lam_max;      // lambda_*
+  double L;            // step constant
+  double yy;           // ||y||^2
+  double rho2;         // ||y/lambda - c||^2 of the sphere centre (0 for SAFE)
+  double alpha;        // DST3/DGST3: c = y/lambda - alpha * n
+  double nn;           // ||n||^2 (n = d_* or D_g* D_g*^T y / lambda_*)
+  double ny;           // n^T y
+  double marg_slack;   // bound on the FP64 rounding error of the margins
+  double gamma_z;      // relative rounding bound of one streamed dot product
+  double gap_tol_abs;  // gap_tol * ||y||^2 (0: fixed iteration count)
+  // per-iteration scalars
+  double tt;           // ||theta||^2 (FP64 from the stored theta)
+  double ty;           // theta^T y
+  double zsup;         // upper bound of ||D_A^T theta||_inf (or max_g ||D_g^T theta|| / w_g)
+  double omega;        // Omega(p) of the point theta was evaluated at
+  double mu, gap, primal, dual;
+  double r_last;       // radius of the last iteration (no slack)
+  double r_min;        // smallest radius (no slack), for reporting
+  double r_scr;        // screening radius in use, slack included
+  double r_slack;      // slack part of r_scr
+  double l_prev;       // FISTA l_{t-1}
+  int32_t n_active;    // active units (atoms or groups) in the current list
+  int32_t n_support;   // entries of the support list of the next primal point
+  int32_t iter;        // iterations completed
+  int32_t done;        // 1 once the stopping rule fired (later kernels become no-ops)
+  int32_t cur;         // which active-list buffer is current
+  int32_t i_star;      // arg-max atom / group of lambda_*
+  int32_t nnz;         // non-zeros of x after the last update
+  int32_t status;      // 0 ok, 1 trivial (lambda >= lambda_*), -1 invalid input
+  int32_t max_iter;
+  int32_t n_active_atoms;
+};
+
+template <typename T, typename V, typename A>
+struct SingleArgs {
+  const T* D;            // N x K column-major, leading dimension ldd
+  int64_t ldd;
+  int32_t N, K;
+  int32_t G;             // 0: Lasso; >0 groups
+  int32_t test, rule;
+  const int64_t* gptr;   // device copy of group offsets (G+1), NULL for the Lasso
+  const double* w;       // device group weights (G)
+  const V* y;            // observation
+  SolverState* st;
+  int32_t* act[2];       // active unit lists (double buffered)
+  V* x;                  // primal x, dense K (atom indexed)
+  V* u;                  // FISTA auxiliary u, dense K (ISTA: u == x)
+  int32_t* s_idx;        // support list: atom index
+  V* s_val;              // support list: value of the primal point theta is evaluated at
+  V* theta;              // residual theta = D p - y
+  A* partial;            // residual partial sums, [chunk][Npad]
+  int64_t npad;
+  double* z0;            // D^T y (FP64), K
+  double* g;             // D^T n (FP64), K
+  double* nu;            // atom norms ||d_i||, K
+  double* fro;           // group Frobenius norms (G), or NULL
+  double* gnorm;         // group spectral norms ||D_g||_2 (G), or NULL
+  double* marg;          // margins (K for the Lasso, G for groups)
+  double* nvec;          // d_* (Lasso) or n (groups), N, FP64
+  double* bp0;           // block partials
+  double* bp1;
+  int32_t* bpi;
+  unsigned* counters;    // last-block counters (re-armed by the last block)
+  void* tele;            // per-iteration telemetry records (Telemetry), or NULL
+  int32_t tele_cap;
+};
+
+// Per-iteration telemetry written by the last correlation block.
+struct TeleRec {
+  int32_t n_atoms;
+  int32_t n_units;
+  int32_t n_support;
+  int32_t nnz;
+  double r;
+  double gap;
+};
+
+}  // namespace ds

@@ -1,0 +1,99 @@
+"""The C-ABI library loads on a CPU-only host, exports every declared symbol, and rejects
+invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dynscreen.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_4080_amd import binding
+    return binding
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = _declared_functions()
+    assert len(names) >= 15
+    lib = C.CDLL(B.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(B.EXPORTED) == set(names)
+
+
+def test_version_and_error_string(B):
+    assert "gfx950" in B.version()
+    assert isinstance(B.last_error(), str)
+
+
+def _problem(B, **kw):
+    p = B.Problem(B.DTYPES["f32"], 10, 20, 10, C.c_void_p(0x1000), 0, None, None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [("N", 0), ("K", 0), ("ldd", 5), ("dtype", 7),
+                                         ("G", 3)])
+def test_invalid_problem_rejected(B, field, value):
+    p = _problem(B, **{field: value})
+    prm = B.make_params()
+    lam = (C.c_double * 1)(0.5)
+    info = (B.Info * 1)()
+    st = B._lib.lasso_solve(C.byref(p), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                            C.c_void_p(0x3000), 20, info, None)
+    assert st == B.DS_EINVAL
+    assert B.last_error()
+
+
+@pytest.mark.parametrize("field,value", [("rule", 5), ("test", 9), ("max_iter", 0),
+                                         ("gap_tol", -1.0), ("reserved", 1),
+                                         ("lambda_mode", 4)])
+def test_invalid_params_rejected(B, field, value):
+    p = _problem(B)
+    prm = B.make_params()
+    setattr(prm, field, value)
+    lam = (C.c_double * 1)(0.5)
+    info = (B.Info * 1)()
+    st = B._lib.lasso_solve(C.byref(p), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                            C.c_void_p(0x3000), 20, info, None)
+    assert st == B.DS_EINVAL
+
+
+def test_invalid_lambda_and_groups_rejected(B):
+    p = _problem(B)
+    prm = B.make_params()
+    info = (B.Info * 1)()
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        lam = (C.c_double * 1)(bad)
+        assert B._lib.lasso_solve(C.byref(p), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                                  C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
+    # group offsets that do not cover the atoms, and an over-large group
+    import numpy as np
+    lam = (C.c_double * 1)(0.5)
+    for gp in (np.array([0, 5, 19], np.int64), np.array([1, 10, 20], np.int64),
+               np.array([0, 10, 10, 20], np.int64)):
+        pg = _problem(B, G=gp.size - 1, group_ptr=gp.ctypes.data_as(C.POINTER(C.c_int64)))
+        assert B._lib.glasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                                   C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
+    big = np.array([0, 100], np.int64)
+    pg = _problem(B, K=100, G=1, group_ptr=big.ctypes.data_as(C.POINTER(C.c_int64)))
+    assert B._lib.glasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                               C.c_void_p(0x3000), 100, info, None) == B.DS_EINVAL
+    # Lasso entry point refuses a grouped problem
+    gp = np.array([0, 10, 20], np.int64)
+    pg = _problem(B, G=2, group_ptr=gp.ctypes.data_as(C.POINTER(C.c_int64)))
+    assert B._lib.lasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                              C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL

@@ -1,0 +1,234 @@
+"""Parity of the single-signal HIP path with the FP64 oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4080_amd import datagen
+from tests._util import (dev_matrix, dev_vector, group_margins_ref, instance, lasso_margins_ref,
+                         rel_err, screened_sets_agree)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_4080_amd import binding
+    return binding
+
+
+def _lasso_case(N, K, seed, p=0.02):
+    D = datagen.gaussian_dictionary(N, K, seed)
+    y, _ = datagen.lasso_signal(D, seed, p=p)
+    return D, y
+
+
+def _fixed_iter_parity(B, D, y, dtype, ratio, rule, test, T, tol_x, tol_obj, group=None):
+    """Run T iterations on both sides with the same L and compare everything."""
+    Di, yi = instance(D, y, dtype)
+    L = oracle.spectral_norm_sq(Di)
+    if group is None:
+        ref = oracle.solve_lasso(Di, yi, lam_ratio=ratio, rule=rule, test=test, L=L, max_iter=T,
+                                 gap_tol=0.0, record=True)
+    else:
+        gp, w = group
+        ref = oracle.solve_group_lasso(Di, yi, gp, w, lam_ratio=ratio, rule=rule,
+                                       test={"safe": "gsafe", "dst3": "dgst3"}.get(test, test),
+                                       L=L, max_iter=T, gap_tol=0.0, record=True)
+    Dd, yd = dev_matrix(D, dtype), dev_vector(yi, dtype)
+    x, info, scr, tr = B.solve_one(Dd, yd, ratio, group_ptr=None if group is None else group[0],
+                                   weights=None if group is None else group[1], rule=rule,
+                                   test=test, step_L=L, gap_tol=0.0, max_iter=T)
+    x = x.cpu().numpy().astype(np.float64)
+    scr = scr.cpu().numpy().astype(bool)
+    assert info["iters"] == ref.iters == T
+    assert info["lambda_max"] == pytest.approx(ref.lam_max, rel=1e-12)
+    assert rel_err(x, ref.x) <= tol_x, rel_err(x, ref.x)
+    assert abs(info["primal"] - ref.primal_p) <= tol_obj * max(abs(ref.primal_p), 1e-30)
+    assert abs(info["gap"] - ref.gap) <= tol_obj * max(abs(ref.primal_p), 1e-30) + 1e-12
+    # screened sets: identical except within the threshold band
+    r_ref = min([h["r"] for h in ref.history[:-1]], default=np.inf)
+    r_gpu = min([t["radius"] for t in tr[:-1]], default=np.inf)
+    if group is None:
+        m = lasso_margins_ref(Di, yi, ref.lam, test)
+        assert screened_sets_agree(scr, ref.screened, m, r_ref, r_gpu, info["radius_slack"])
+    else:
+        gp, w = group
+        m = group_margins_ref(Di, yi, ref.lam, {"safe": "gsafe", "dst3": "dgst3"}.get(test, test),
+                              gp, w)
+        unit = np.repeat(np.arange(gp.size - 1), np.diff(gp))
+        assert screened_sets_agree(scr, ref.screened, m, r_ref, r_gpu, info["radius_slack"], unit)
+    return ref, x, info, tr
+
+
+# ------------------------------------------------------------ FP64 small workload
+@pytest.mark.parametrize("test", ["safe", "dst3", "none"])
+def test_small_fp64_500_iterations(B, test):
+    c = datagen.lasso_small_fp64()
+    ref, x, info, tr = _fixed_iter_parity(B, c["D"], c["y"], "f64", 0.5, "ista", test, 500,
+                                          1e-10, 1e-12)
+    assert [t["n_active"] for t in tr] == [h["n_active"] for h in ref.history]
+    assert [t["nnz"] for t in tr] == [h["nnz"] for h in ref.history]
+
+
+# ------------------------------------------------------------ FP32 trajectories
+@pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe"), ("fista", "none"),
+                                       ("ista", "dst3")])
+@pytest.mark.parametrize("ratio", [0.2, 0.6, 0.9])
+def test_fp32_fixed_iteration_parity(B, rule, test, ratio):
+    D, y = _lasso_case(500, 2500, 5)
+    ref, x, info, tr = _fixed_iter_parity(B, D, y, "f32", ratio, rule, test, 60, 1e-5, 1e-6)
+    # active-set trajectory: identical up to band effects of a few atoms
+    na_gpu = np.array([t["n_active"] for t in tr])
+    na_ref = np.array([h["n_active"] for h in ref.history])
+    assert np.max(np.abs(na_gpu - na_ref)) <= 2
+
+
+def test_fp32_full_size_trajectory(B):
+    """2000 x 10000 dictionary, FISTA + DST3: the launch configuration of the benchmark."""
+    D, y = _lasso_case(2000, 10000, 0)
+    for ratio in (0.5, 0.8):
+        ref, x, info, tr = _fixed_iter_parity(B, D, y, "f32", ratio, "fista", "dst3", 40, 1e-5,
+                                              1e-6)
+    assert tr[-1]["n_active"] < 10000  # screening took effect at 0.8 lambda_*
+
+
+@pytest.mark.parametrize("ratio", [0.1, 0.5, 0.9])
+def test_fp32_solve_to_tolerance_is_certified(B, ratio):
+    D, y = _lasso_case(400, 2000, 9)
+    Di, yi = instance(D, y, "f32")
+    L = oracle.spectral_norm_sq(Di)
+    Dd, yd = dev_matrix(D, "f32"), dev_vector(yi, "f32")
+    x, info, scr, tr = B.solve_one(Dd, yd, ratio, rule="fista", test="dst3", step_L=L,
+                                   gap_tol=1e-6, max_iter=20000)
+    assert info["status"] == 0 and info["gap"] <= 1e-6 * float(yi @ yi)
+    x = x.cpu().numpy().astype(np.float64)
+    scr = scr.cpu().numpy().astype(bool)
+    star = oracle.solve_lasso(Di, yi, lam=info["lambda_"], rule="fista", test="none", L=L,
+                              max_iter=200000, gap_tol=1e-13)
+    p_gpu = oracle.primal_objective(Di, yi, x, info["lambda_"], float(np.abs(x).sum()))
+    # the certificate bounds the objective error of the returned point
+    assert p_gpu - star.primal <= info["gap"] + 1e-9
+    # the GPU's own objective evaluation agrees with an FP64 evaluation of its iterate
+    assert star.primal <= p_gpu
+    # safety: every screened atom is certified inactive and zero at the optimum
+    cert, gstar = oracle.certified_inactive_lasso(Di, yi, info["lambda_"], star.x)
+    assert gstar < 1e-11
+    assert np.all(cert[scr]), np.flatnonzero(scr & ~cert)[:10]
+    assert not star.x[scr].any()
+    ref = oracle.solve_lasso(Di, yi, lam=info["lambda_"], rule="fista", test="dst3", L=L,
+                             max_iter=20000, gap_tol=1e-6)
+    assert abs(info["iters"] - ref.iters) <= 3
+
+
+# ------------------------------------------------------------ Group-Lasso
+@pytest.mark.parametrize("rule,test", [("ista", "dst3"), ("ista", "safe"), ("fista", "dst3"),
+                                       ("ista", "none")])
+@pytest.mark.parametrize("ratio", [0.3, 0.7])
+def test_group_fp32_fixed_iteration_parity(B, rule, test, ratio):
+    D = datagen.gaussian_dictionary(500, 2500, 7)
+    gp = datagen.contiguous_groups(2500, 10)
+    y, _ = datagen.group_signal(D, gp, 3)
+    w = np.sqrt(10.0) * np.ones(250)
+    _fixed_iter_parity(B, D, y, "f32", ratio, rule, test, 60, 1e-5, 1e-6, group=(gp, w))
+
+
+@pytest.mark.parametrize("ratio", [0.3, 0.7])
+def test_group_solve_to_tolerance_is_certified(B, ratio):
+    D = datagen.gaussian_dictionary(400, 2000, 8)
+    gp = datagen.contiguous_groups(2000, 10)
+    y, _ = datagen.group_signal(D, gp, 4)
+    Di, yi = instance(D, y, "f32")
+    L = oracle.spectral_norm_sq(Di)
+    x, info, scr, tr = B.solve_one(dev_matrix(D, "f32"), dev_vector(yi, "f32"), ratio,
+                                   group_ptr=gp, rule="ista", test="dgst3", step_L=L,
+                                   gap_tol=1e-6, max_iter=50000)
+    assert info["status"] == 0
+    scr = scr.cpu().numpy().astype(bool)
+    star = oracle.solve_group_lasso(Di, yi, gp, None, lam=info["lambda_"], rule="fista",
+                                    test="none", L=L, max_iter=200000, gap_tol=1e-13)
+    amask, gmask, gstar = oracle.certified_inactive_group(Di, yi, info["lambda_"], star.x, gp)
+    assert gstar < 1e-11
+    assert np.all(amask[scr])
+
+
+# ------------------------------------------------------------ edge cases
+def test_trivial_regime_returns_zero(B):
+    D, y = _lasso_case(200, 800, 2)
+    Dd, yd = dev_matrix(D, "f32"), dev_vector(y, "f32")
+    for ratio in (1.0, 1.5):
+        x, info, scr, tr = B.solve_one(Dd, yd, ratio)
+        assert info["iters"] == 0 and info["status"] == 0
+        assert not x.cpu().numpy().any() and scr.cpu().numpy().all()
+
+
+@pytest.mark.parametrize("N,K,ldd", [(37, 101, 37), (130, 333, 136), (1, 1, 1), (64, 5, 64),
+                                     (257, 1031, 257)])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
+def test_ragged_shapes(B, N, K, ldd, dtype):
+    import torch
+    D = datagen.gaussian_dictionary(N, K, 11)
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(N)
+    y /= np.linalg.norm(y)
+    Di, yi = instance(D, y, dtype)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    buf = torch.zeros(K, ldd, dtype=tdt)
+    buf[:, :N] = torch.from_numpy(np.ascontiguousarray(Di.T))
+    Dd = buf.to("cuda").T[:N, :]
+    assert Dd.stride() == (1, ldd)
+    L = oracle.spectral_norm_sq(Di)
+    ref = oracle.solve_lasso(Di, yi, lam_ratio=0.4, rule="fista", test="dst3", L=L, max_iter=25,
+                             gap_tol=0.0)
+    x, info, scr, tr = B.solve_one(Dd, dev_vector(yi, dtype), 0.4, rule="fista", test="dst3",
+                                   step_L=L, gap_tol=0.0, max_iter=25)
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    if ref.iters == 0:
+        assert info["iters"] == 0 and not x.cpu().numpy().any()
+    else:
+        assert rel_err(x.cpu().numpy(), ref.x) <= tol
+
+
+def test_non_unit_and_zero_atoms(B):
+    D = datagen.gaussian_dictionary(300, 1200, 13)
+    rng = np.random.default_rng(14)
+    D = np.asfortranarray(D * rng.uniform(0.5, 2.0, size=1200)[None, :])
+    D[:, 17] = 0.0
+    y, _ = datagen.lasso_signal(D, 15)
+    ref, x, info, tr = _fixed_iter_parity(B, D, y, "f32", 0.5, "fista", "dst3", 80, 1e-5, 1e-6)
+    assert x[17] == 0.0
+
+
+def test_deterministic(B):
+    D, y = _lasso_case(500, 2500, 16)
+    Dd, yd = dev_matrix(D, "f32"), dev_vector(y, "f32")
+    L = oracle.spectral_norm_sq(instance(D, y, "f32")[0])
+    a = B.solve_one(Dd, yd, 0.3, step_L=L, gap_tol=1e-6)
+    b = B.solve_one(Dd, yd, 0.3, step_L=L, gap_tol=1e-6)
+    assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
+    assert a[1]["iters"] == b[1]["iters"]
+
+
+def test_lambda_max_and_spectral_norm(B):
+    D, y = _lasso_case(700, 3000, 17)
+    Di, yi = instance(D, y, "f32")
+    Dd = dev_matrix(D, "f32")
+    lm, arg = B.lambda_max(Dd, dev_vector(yi, "f32"))
+    ref, iref = oracle.lambda_max_lasso(Di, yi)
+    assert lm == pytest.approx(ref, rel=1e-13) and arg == iref
+    L = B.spectral_norm_sq(Dd, 300)
+    Lx = oracle.spectral_norm_sq(Di)
+    assert Lx * (1 - 1e-12) <= L <= Lx * 1.02
+
+
+def test_batched_call_matches_single(B):
+    import torch
+    D, _ = _lasso_case(300, 1500, 18)
+    Ys = np.stack([datagen.lasso_signal(D, j)[0] for j in range(3)], axis=1)
+    Dd = dev_matrix(D, "f32")
+    Yd = torch.from_numpy(np.ascontiguousarray(Ys.T.astype(np.float32))).cuda().T
+    L = oracle.spectral_norm_sq(instance(D, Ys[:, 0], "f32")[0])
+    X, infos = B.solve(Dd, Yd, [0.3, 0.5, 0.7], step_L=L, gap_tol=1e-6)
+    for j, r in enumerate([0.3, 0.5, 0.7]):
+        x1, i1, _, _ = B.solve_one(Dd, Yd[:, j].contiguous(), r, step_L=L, gap_tol=1e-6)
+        assert np.array_equal(X[:, j].cpu().numpy(), x1.cpu().numpy())
+        assert infos[j]["iters"] == i1["iters"]
