@@ -1,5 +1,6 @@
 // Single-signal solve: setup on the device, then chunks of iterations enqueued ahead of
 // the device-side stopping decision (see ds_single_kernels.h for the kernels).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,11 +17,11 @@ namespace {
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 struct Layout {
-  size_t off_state, off_act0, off_act1, off_x, off_u, off_sidx, off_sval, off_theta,
-      off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_bp0,
-      off_bp1, off_bpi, off_cnt, off_gptr, off_w, off_tele, off_pv, off_pw, off_pz, off_pd,
-      total;
-  int64_t npad, nchunks;
+  size_t off_state, off_act0, off_act1, off_x, off_u, off_sidx, off_sunit, off_sval, off_theta,
+      off_y, off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_bp0,
+      off_bp1, off_bpi, off_rtn, off_rtcnt, off_lba, off_lbb, off_cnt, off_gptr, off_w, off_tele,
+      off_pv, off_pw, off_pz, off_pd, off_actm0, off_actm1, off_accum, off_omp, total;
+  int64_t npad, nchunks, nslots;
 };
 
 Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int64_t tele_cap,
@@ -33,16 +34,23 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
     return at;
   };
   l.npad = round_up(N, 64);
-  l.nchunks = (K + RCH - 1) / RCH;
+  l.nchunks = ((G > 0 ? G : K) + (G > 0 ? RCG : RC) - 1) / (G > 0 ? RCG : RC);
+  l.nslots = K;
   const int64_t units = G > 0 ? G : K;
   l.off_state = take(sizeof(SolverState));
   l.off_act0 = take(units * 4);
   l.off_act1 = take(units * 4);
+  l.off_actm0 = take(units * 8);
+  l.off_actm1 = take(units * 8);
+  l.off_accum = take(8 * 8);
+  l.off_omp = take((l.nchunks + 1) * 8);
   l.off_x = take(K * vsz);
   l.off_u = take(K * vsz);
-  l.off_sidx = take(K * 4);
-  l.off_sval = take(K * vsz);
+  l.off_sidx = take(l.nslots * 4);
+  l.off_sunit = take(l.nslots * 4);
+  l.off_sval = take(l.nslots * vsz);
   l.off_theta = take(l.npad * vsz);
+  l.off_y = take(l.npad * vsz);
   l.off_partial = take(l.nchunks * l.npad * asz);
   l.off_z0 = take(K * 8);
   l.off_g = take(K * 8);
@@ -53,8 +61,12 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.off_nvec = take(l.npad * 8);
   l.off_bp0 = take(MAXB * 8);
   l.off_bp1 = take(MAXB * 8);
-  l.off_bpi = take(MAXB * 4);
-  l.off_cnt = take(16 * 4);
+  l.off_bpi = take(4 * MAXB * 4);
+  l.off_rtn = take(2 * MAXRT * 8);
+  l.off_rtcnt = take(MAXRT * 4);
+  l.off_lba = take(MAXB * 8);
+  l.off_lbb = take(MAXB * 8);
+  l.off_cnt = take(32 * 4);
   l.off_gptr = take((std::max<int64_t>(G, 1) + 1) * 8);
   l.off_w = take(std::max<int64_t>(G, 1) * 8);
   l.off_tele = take(tele_cap * sizeof(Telemetry));
@@ -92,13 +104,19 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.rule = rule;
   a.gptr = P.G > 0 ? reinterpret_cast<const int64_t*>(base + l.off_gptr) : nullptr;
   a.w = P.G > 0 ? reinterpret_cast<const double*>(base + l.off_w) : nullptr;
-  a.y = static_cast<const V*>(y);
+  a.y = reinterpret_cast<const V*>(base + l.off_y);
+  (void)y;
   a.st = reinterpret_cast<SolverState*>(base + l.off_state);
   a.act[0] = reinterpret_cast<int32_t*>(base + l.off_act0);
   a.act[1] = reinterpret_cast<int32_t*>(base + l.off_act1);
+  a.act_m[0] = reinterpret_cast<double*>(base + l.off_actm0);
+  a.act_m[1] = reinterpret_cast<double*>(base + l.off_actm1);
+  a.accum = reinterpret_cast<unsigned long long*>(base + l.off_accum);
+  a.omp = reinterpret_cast<double*>(base + l.off_omp);
   a.x = reinterpret_cast<V*>(base + l.off_x);
   a.u = reinterpret_cast<V*>(base + l.off_u);
   a.s_idx = reinterpret_cast<int32_t*>(base + l.off_sidx);
+  a.s_unit = reinterpret_cast<int32_t*>(base + l.off_sunit);
   a.s_val = reinterpret_cast<V*>(base + l.off_sval);
   a.theta = reinterpret_cast<V*>(base + l.off_theta);
   a.partial = reinterpret_cast<A*>(base + l.off_partial);
@@ -113,6 +131,10 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.bp0 = reinterpret_cast<double*>(base + l.off_bp0);
   a.bp1 = reinterpret_cast<double*>(base + l.off_bp1);
   a.bpi = reinterpret_cast<int32_t*>(base + l.off_bpi);
+  a.rtn = reinterpret_cast<double*>(base + l.off_rtn);
+  a.rt_cnt = reinterpret_cast<unsigned*>(base + l.off_rtcnt);
+  a.lbA = reinterpret_cast<uint64_t*>(base + l.off_lba);
+  a.lbB = reinterpret_cast<uint64_t*>(base + l.off_lbb);
   a.counters = reinterpret_cast<unsigned*>(base + l.off_cnt);
   return a;
 }
@@ -139,10 +161,14 @@ template <typename T, bool VEC>
 ds_status launch_setup_corr(const ds_problem& P, const void* y, char* base, const Layout& l,
                             hipStream_t s) {
   using V = typename Types<T>::V;
+  V* yc = reinterpret_cast<V*>(base + l.off_y);
+  hipLaunchKernelGGL((k_copy_y<V>), dim3(grid_for(l.npad, BLK, 1 << 20)), dim3(BLK), 0, s,
+                     static_cast<const V*>(y), yc, static_cast<int>(P.N),
+                     static_cast<int>(l.npad));
   const int gridK = grid_for(P.K, NW * CPW, 4096);
   hipLaunchKernelGGL((k_setup_gemv<T, V, VEC, true>), dim3(gridK), dim3(BLK), 0, s,
                      static_cast<const T*>(P.D), P.ldd, static_cast<int>(P.N),
-                     static_cast<int>(P.K), static_cast<const V*>(y),
+                     static_cast<int>(P.K), static_cast<const V*>(yc),
                      reinterpret_cast<double*>(base + l.off_z0),
                      reinterpret_cast<double*>(base + l.off_nu));
   DS_HIP(hipGetLastError());
@@ -176,7 +202,11 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   a.tele_cap = static_cast<int32_t>(tele_cap);
   std::vector<double> wbuf;
   if ((st_ = upload_groups(P, base, l, s, wbuf)) != DS_OK) return st_;
-  DS_HIP(hipMemsetAsync(a.counters, 0, 16 * 4, s));
+  DS_HIP(hipMemsetAsync(a.counters, 0, 32 * 4, s));
+  DS_HIP(hipMemsetAsync(a.rt_cnt, 0, MAXRT * 4, s));
+  DS_HIP(hipMemsetAsync(a.lbA, 0, MAXB * 8, s));
+  DS_HIP(hipMemsetAsync(a.lbB, 0, MAXB * 8, s));
+  DS_HIP(hipMemsetAsync(a.accum, 0, 8 * 8, s));
 
   // ---- setup (no host synchronisation) ----
   if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
@@ -217,12 +247,13 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
 
   // ---- iterations ----
   constexpr int VR = VEC ? Store<T>::VEC : 1;
-  const int nrt = static_cast<int>((P.N + BLK * VR - 1) / (BLK * VR));
-  const int grid_res = grid_for(static_cast<int64_t>(nrt) * l.nchunks, 1, 1024);
-  const int grid_fin = grid_for(P.N, BLK, 1 << 20);
-  const int grid_corr = P.G > 0 ? grid_for(P.G, NW, MAXB) : grid_for(P.K, NW * CPW, MAXB);
-  if (grid_fin > MAXB) {
-    set_error("N too large for the residual finalisation (N <= %d)", MAXB * BLK);
+  const int nrt = static_cast<int>((P.N + WAVE * VR - 1) / (WAVE * VR));
+  const int64_t rchunks = (units + (P.G > 0 ? RCG : RC) - 1) / (P.G > 0 ? RCG : RC);
+  const int grid_res = std::max(nrt, grid_for(static_cast<int64_t>(nrt) * rchunks, 1, 2048));
+  const int grid_corr = grid_for(units, CB, MAXB);
+  if (nrt > MAXRT || (units + CB - 1) / CB > MAXB) {
+    set_error("problem too large for one device solve (N <= %d, units <= %d)", MAXRT * WAVE,
+              MAXB * CB);
     return DS_EINVAL;
   }
   StatAccum& S = stats();
@@ -233,7 +264,6 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   }
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-  std::vector<double> ev_bytes;
   size_t ev_used = 0;
   auto get_events = [&]() -> std::pair<hipEvent_t, hipEvent_t> {
     while (ws.events.size() < 2 * (ev_used + 1)) {
@@ -251,22 +281,21 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   while (!finished && it < prm.max_iter) {
     const int nrun = std::min(chunk, prm.max_iter - it);
     for (int k = 0; k < nrun; ++k) {
-      hipLaunchKernelGGL((k_resid<T, V, A, VEC>), dim3(grid_res), dim3(BLK), 0, s, a);
-      hipLaunchKernelGGL((k_resid_finalize<T, V, A>), dim3(grid_fin), dim3(BLK), 0, s, a);
-      std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
-      if (stat_on) {
-        e = get_events();
-        if (e.first) DS_HIP(hipEventRecord(e.first, s));
-      }
       if (P.G > 0)
-        hipLaunchKernelGGL((k_corr_group<T, V, A, VEC, RULE>), dim3(grid_corr), dim3(BLK), 0, s, a);
+        hipLaunchKernelGGL((k_resid<T, V, VEC, true>), dim3(grid_res), dim3(BLK), 0, s, a);
       else
-        hipLaunchKernelGGL((k_corr_lasso<T, V, A, VEC, RULE>), dim3(grid_corr), dim3(BLK), 0, s, a);
-      if (stat_on && e.first) {
-        DS_HIP(hipEventRecord(e.second, s));
-        ev.push_back(e);
-      }
-      hipLaunchKernelGGL((k_compact<T, V, A>), dim3(1), dim3(CBLK), 0, s, a);
+        hipLaunchKernelGGL((k_resid<T, V, VEC, false>), dim3(grid_res), dim3(BLK), 0, s, a);
+      // instrumented launches carry start/stop events in the dispatch itself, so the
+      // measured interval is the kernel's own execution
+      std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+      if (stat_on) e = get_events();
+      if (P.G > 0)
+        hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, true>), dim3(grid_corr), dim3(CBLK_CORR), 0, s,
+                              e.first, e.second, 0, a);
+      else
+        hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, false>), dim3(grid_corr), dim3(CBLK_CORR), 0,
+                              s, e.first, e.second, 0, a);
+      if (stat_on && e.first) ev.push_back(e);
     }
     DS_HIP(hipGetLastError());
     it += nrun;

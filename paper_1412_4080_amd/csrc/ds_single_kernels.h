@@ -22,63 +22,167 @@ namespace ds {
 
 constexpr int BLK = 256;         // threads per block of the streaming kernels
 constexpr int NW = BLK / WAVE;   // waves per block
-constexpr int CPW = 4;           // columns per wave in the correlation kernel
-constexpr int RCH = 16;          // support columns per residual work item
+constexpr int CPW = 2;           // columns streamed at once by one wave (more slows HBM)
+constexpr int CBLK_CORR = 1024;  // threads of a correlation block
+constexpr int NWC = CBLK_CORR / WAVE;
+constexpr int CB = NWC * CPW;    // active-list entries per correlation block (<= 64)
+constexpr int NSUB = 16;         // first-level arrival counters
+constexpr int RC = 256;          // active-list entries per residual work item (Lasso)
+constexpr int RCG = 32;          // active-list entries per residual work item (groups)
+constexpr int RPW = 4;           // support columns one residual wave loads at once
+constexpr int SCH = RC;          // partial-sum chunking unit of the residual
 constexpr int CBLK = 1024;       // threads of the single-block kernels
 constexpr int CNW = CBLK / WAVE;
-constexpr int MAXB = 2048;       // maximum grid of the kernels with block partials
-constexpr int GMAX_REG = 4;      // group kernel: up to GMAX_REG * 64 atoms per group
+constexpr int MAXB = 16384;      // maximum grid of the kernels with block partials
+constexpr int MAXRT = 4096;      // maximum row tiles of the residual
+constexpr int GMAX = 64;         // largest group: one lane per atom in the group epilogue
 
-enum CounterSlot { CNT_FIN = 0, CNT_CORR = 1, CNT_SETUP = 2, CNT_POW = 3 };
+enum CounterSlot { CNT_FIN = 0, CNT_CORR = 1, CNT_VID = 2, CNT_SUB = 8 };
+
+// Cross-block publication without agent-scope fences: an agent-scope atomic store goes
+// to the coherence point directly, and waiting for it before the arrival counter makes
+// it visible to whichever block observes the counter (a release fence would also write
+// back the whole L2, which doubles the runtime of a streaming kernel).
+template <typename X>
+__device__ __forceinline__ void publish(X* p, X v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename X>
+__device__ __forceinline__ X consume(const X* p) {
+  return __hip_atomic_load(const_cast<X*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Two-level arrival for large grids: blocks count on one of NSUB counters (same-address
+// atomics serialise, so a single counter hit by every block costs microseconds); the
+// block completing a sub-counter arrives at the top counter.
+__device__ __forceinline__ bool arrive_last_2l(unsigned* sub, unsigned* top, int vb, int grid,
+                                               int* flag_lds) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int k = vb % NSUB;
+    const unsigned expect_sub = static_cast<unsigned>((grid - k + NSUB - 1) / NSUB);
+    const unsigned nsubs = static_cast<unsigned>(min(grid, NSUB));
+    int last = 0;
+    const unsigned p1 = __hip_atomic_fetch_add(&sub[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p1 == expect_sub - 1u) {
+      sub[k] = 0u;
+      const unsigned p2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = p2 == nsubs - 1u;
+    }
+    *flag_lds = last;
+  }
+  __syncthreads();
+  return *flag_lds != 0;
+}
+// Arrival counter after the block's publications; true in the block that arrives last.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected, int* flag_lds) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *flag_lds = (prev == expected - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  return *flag_lds != 0;
+}
 
 __device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
 
 // ---------------------------------------------------------------- vector loads ------
-template <typename V, int VEC, typename A>
-__device__ __forceinline__ void load_v(const V* __restrict__ p, A (&o)[VEC]) {
+__device__ __forceinline__ uint4 ld16(const void* p) { return *reinterpret_cast<const uint4*>(p); }
+
+// Widen one raw 16-byte load of stored elements to FP64.
+template <typename T> __device__ __forceinline__ void widen(const uint4& r, double (&o)[Store<T>::VEC]);
+template <> __device__ __forceinline__ void widen<double>(const uint4& r, double (&o)[2]) {
+  o[0] = __hiloint2double(static_cast<int>(r.y), static_cast<int>(r.x));
+  o[1] = __hiloint2double(static_cast<int>(r.w), static_cast<int>(r.z));
+}
+template <> __device__ __forceinline__ void widen<float>(const uint4& r, double (&o)[4]) {
+  o[0] = __uint_as_float(r.x); o[1] = __uint_as_float(r.y);
+  o[2] = __uint_as_float(r.z); o[3] = __uint_as_float(r.w);
+}
+template <> __device__ __forceinline__ void widen<bf16_t>(const uint4& r, double (&o)[8]) {
+  o[0] = __uint_as_float(r.x << 16); o[1] = __uint_as_float(r.x & 0xffff0000u);
+  o[2] = __uint_as_float(r.y << 16); o[3] = __uint_as_float(r.y & 0xffff0000u);
+  o[4] = __uint_as_float(r.z << 16); o[5] = __uint_as_float(r.z & 0xffff0000u);
+  o[6] = __uint_as_float(r.w << 16); o[7] = __uint_as_float(r.w & 0xffff0000u);
+}
+// VEC consecutive elements of a 16-byte aligned float / double vector, widened to FP64.
+template <int VEC> __device__ __forceinline__ void load_dv(const float* p, double (&o)[VEC]) {
+  static_assert(VEC % 4 == 0, "float vector loads come in fours");
 #pragma unroll
-  for (int k = 0; k < VEC; ++k) o[k] = static_cast<A>(p[k]);
+  for (int k = 0; k < VEC / 4; ++k) {
+    const float4 f = reinterpret_cast<const float4*>(p)[k];
+    o[4 * k] = f.x; o[4 * k + 1] = f.y; o[4 * k + 2] = f.z; o[4 * k + 3] = f.w;
+  }
+}
+template <int VEC> __device__ __forceinline__ void load_dv(const double* p, double (&o)[VEC]) {
+  static_assert(VEC % 2 == 0, "double vector loads come in twos");
+#pragma unroll
+  for (int k = 0; k < VEC / 2; ++k) {
+    const double2 d = reinterpret_cast<const double2*>(p)[k];
+    o[2 * k] = d.x; o[2 * k + 1] = d.y;
+  }
 }
 
-// Dot products of NC columns with a vector, by one wave.  Columns with c >= ncols are
-// not read.  With VECTOR each lane issues 16-byte loads (columns must be 16-byte
-// aligned); the tail N % VEC is read element-wise.
-template <typename T, typename V, typename A, int NC, bool VECTOR>
-__device__ __forceinline__ void wave_dots(const T* const (&cols)[NC], int ncols,
-                                          const V* __restrict__ v, int N, int lane,
-                                          A (&acc)[NC]) {
+// FP64 dot products of NC columns with a vector v, by one wave.  Branch-free: every
+// column pointer must be valid (callers repeat a valid column for unused slots), so the
+// compiler issues all 2*NC 16-byte loads of an unrolled step before the FMAs.  With
+// VECTOR the columns and v are 16-byte aligned; the tail N % VEC is read element-wise.
+template <typename T, typename VV, int NC, bool VECTOR>
+__device__ __forceinline__ void wave_dots(const T* const (&cols)[NC], const VV* __restrict__ v,
+                                          int N, int lane, double (&acc)[NC]) {
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = A(0);
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if constexpr (VECTOR) {
     constexpr int VEC = Store<T>::VEC;
+    constexpr int US = 4;  // vector steps in flight per column
     const int nfull = N / VEC;
-#pragma unroll 2
-    for (int q = lane; q < nfull; q += WAVE) {
-      A vv[VEC];
-      load_v<V, VEC, A>(v + q * VEC, vv);
+    int q = lane;
+    for (; q + (US - 1) * WAVE < nfull; q += US * WAVE) {
+      uint4 r[US][NC];
+#pragma unroll
+      for (int k = 0; k < US; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[k][c] = ld16(cols[c] + static_cast<int64_t>(q + k * WAVE) * VEC);
+      double t[VEC];
+#pragma unroll
+      for (int k = 0; k < US; ++k) {
+        load_dv<VEC>(v + (q + k * WAVE) * VEC, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          double d[VEC];
+          widen<T>(r[k][c], d);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[c] = fma(d[e], t[e], acc[c]);
+        }
+      }
+    }
+    for (; q < nfull; q += WAVE) {
+      uint4 r0[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) r0[c] = ld16(cols[c] + static_cast<int64_t>(q) * VEC);
+      double t0[VEC];
+      load_dv<VEC>(v + q * VEC, t0);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        if (c < ncols) {
-          A d[VEC];
-          load_vec<T, A>(cols[c] + static_cast<int64_t>(q) * VEC, d);
+        double d[VEC];
+        widen<T>(r0[c], d);
 #pragma unroll
-          for (int k = 0; k < VEC; ++k) acc[c] = fma(d[k], vv[k], acc[c]);
-        }
+        for (int e = 0; e < VEC; ++e) acc[c] = fma(d[e], t0[e], acc[c]);
       }
     }
     const int e = nfull * VEC + lane;
     if (e < N) {
-      const A ve = static_cast<A>(v[e]);
+      const double ve = static_cast<double>(v[e]);
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c < ncols) acc[c] = fma(static_cast<A>(to_double(cols[c][e])), ve, acc[c]);
+      for (int c = 0; c < NC; ++c) acc[c] = fma(to_double(cols[c][e]), ve, acc[c]);
     }
   } else {
     for (int e = lane; e < N; e += WAVE) {
-      const A ve = static_cast<A>(v[e]);
+      const double ve = static_cast<double>(v[e]);
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c < ncols) acc[c] = fma(static_cast<A>(to_double(cols[c][e])), ve, acc[c]);
+      for (int c = 0; c < NC; ++c) acc[c] = fma(to_double(cols[c][e]), ve, acc[c]);
     }
   }
 }
@@ -90,6 +194,38 @@ __device__ __forceinline__ X pick(const X (&a)[NC], int c) {
   for (int k = 1; k < NC; ++k)
     if (c == k) r = a[k];
   return r;
+}
+
+// Decoupled look-back: exclusive prefix of `agg` over virtual blocks 0..vb-1.  Words are
+// [epoch:16 | flag:2 | value:46]; flag 1 = aggregate only, 2 = inclusive prefix.  The
+// virtual block ids are handed out by an atomic counter in arrival order, so every
+// predecessor has started and will publish: the wait always ends.
+__device__ inline int lookback_prefix(uint64_t* status, int vb, int agg, uint32_t epoch) {
+  const uint64_t E = static_cast<uint64_t>(epoch) << 48;
+  constexpr uint64_t FA = 1ull << 46, FI = 2ull << 46, VMASK = (1ull << 46) - 1ull;
+  if (vb == 0) {
+    __hip_atomic_store(&status[0], E | FI | static_cast<uint64_t>(agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  __hip_atomic_store(&status[vb], E | FA | static_cast<uint64_t>(agg), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  int64_t prefix = 0;
+  int j = vb - 1;
+  while (true) {
+    const uint64_t w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t flag = (w >> 46) & 3ull;
+    if ((w >> 48) != epoch || flag == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    prefix += static_cast<int64_t>(w & VMASK);
+    if (flag == 2) break;
+    --j;
+  }
+  __hip_atomic_store(&status[vb], E | FI | static_cast<uint64_t>(prefix + agg), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return static_cast<int>(prefix);
 }
 
 // ============================================================== setup kernels =======
@@ -109,7 +245,7 @@ __global__ __launch_bounds__(BLK) void k_setup_gemv(const T* __restrict__ D, int
 #pragma unroll
     for (int c = 0; c < CPW; ++c) cols[c] = D + static_cast<int64_t>(base + min(c, nc - 1)) * ldd;
     double acc[CPW];
-    wave_dots<T, VV, double, CPW, VECTOR>(cols, nc, v, N, lane, acc);
+    wave_dots<T, VV, CPW, VECTOR>(cols, v, N, lane, acc);
     double sq[CPW];
     if constexpr (NORMS) {
 #pragma unroll
@@ -317,6 +453,8 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     st->status = bad ? -1 : (trivial ? 1 : 0);
     st->done = (bad || trivial) ? 1 : 0;
     st->n_active = (bad || trivial) ? 0 : units;
+    st->n_kept = st->n_active;
+    st->compact = 0;
     st->n_active_atoms = (bad || trivial) ? 0 : K;
   }
 }
@@ -371,6 +509,7 @@ __global__ __launch_bounds__(BLK) void k_setup_margins(SingleArgs<T, V, A> a) {
     m = nu > 0.0 ? (1.0 - fabs(ci)) / nu : dinf();
   }
   a.marg[i] = m;
+  a.act_m[0][i] = m;
 }
 
 // Rounding slack of the margins: a bound on the FP64 error of every m (one block).
@@ -396,87 +535,190 @@ __global__ __launch_bounds__(CBLK) void k_setup_slack(SingleArgs<T, V, A> a) {
 
 // ============================================================== iteration kernels ===
 
-// theta partial sums: item (row tile rt, chunk c) sums the support columns of chunk c.
-template <typename T, typename V, typename A, bool VECTOR>
-__global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, A> a) {
-  const SolverState* st = a.st;
-  if (st->done) return;
+// theta = D p - y over the non-zeros of the primal point p restricted to the active list,
+// FP64 accumulation.  Work item (row tile rt, list chunk c): the block gathers, in list
+// order, the atoms of chunk c that are still active and have p != 0 (units screened at
+// the previous iteration are dropped: Algorithm 3 removes their coordinates from the
+// primal variables), each wave streams the row segment of up to RPW of those columns at
+// a time, and the four waves combine in LDS.  The block completing the last chunk of a
+// tile forms theta on it (fixed summation order) with FP64 ||theta||^2 and theta^T y; the
+// last tile to finish writes the totals.  Partial sums cross blocks through agent-scope
+// atomic stores (see publish/arrive_last).
+template <typename T, typename V, bool VECTOR>
+__device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nch, int nrt,
+                                  double* sd, int* sflag) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
-  const int nS = st->n_support;
-  const int nch = (nS + RCH - 1) / RCH;
-  const int RT = BLK * VR;
-  const int nrt = (a.N + RT - 1) / RT;
-  const int items = nrt * nch;
-  for (int item = blockIdx.x; item < items; item += gridDim.x) {
-    const int rt = item % nrt, c = item / nrt;
-    const int r0 = rt * RT + threadIdx.x * VR;
-    A acc[VR];
+  constexpr int RT = WAVE * VR;
+  double tt = 0.0, ty = 0.0;
+  const int r_end = min((rt + 1) * RT, a.N);
+  for (int r = rt * RT + static_cast<int>(threadIdx.x); r < r_end; r += BLK) {
+    // chunk partials in chunk order, sixteen loads in flight
+    double s = 0.0;
+    int c = 0;
+    for (; c + 16 <= nch; c += 16) {
+      double v[16];
 #pragma unroll
-    for (int k = 0; k < VR; ++k) acc[k] = A(0);
-    const int k0 = c * RCH, k1 = min(k0 + RCH, nS);
-    if (r0 + VR <= a.N) {
-      for (int k = k0; k < k1; ++k) {
-        const A val = static_cast<A>(a.s_val[k]);
-        const T* col = a.D + static_cast<int64_t>(a.s_idx[k]) * a.ldd + r0;
-        if constexpr (VECTOR) {
-          A d[VR];
-          load_vec<T, A>(col, d);
+      for (int k = 0; k < 16; ++k) v[k] = consume(&a.partial[static_cast<int64_t>(c + k) * a.npad + r]);
 #pragma unroll
-          for (int e = 0; e < VR; ++e) acc[e] = fma(d[e], val, acc[e]);
-        } else {
-          acc[0] = fma(static_cast<A>(to_double(col[0])), val, acc[0]);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < VR; ++e) a.partial[static_cast<int64_t>(c) * a.npad + r0 + e] = acc[e];
-    } else if (r0 < a.N) {
-      for (int k = k0; k < k1; ++k) {
-        const A val = static_cast<A>(a.s_val[k]);
-        const T* col = a.D + static_cast<int64_t>(a.s_idx[k]) * a.ldd;
-        for (int e = 0; e < VR; ++e)
-          if (r0 + e < a.N) acc[e] = fma(static_cast<A>(to_double(col[r0 + e])), val, acc[e]);
-      }
-      for (int e = 0; e < VR; ++e)
-        if (r0 + e < a.N) a.partial[static_cast<int64_t>(c) * a.npad + r0 + e] = acc[e];
+      for (int k = 0; k < 16; ++k) s += v[k];
+    }
+    for (; c < nch; ++c) s += consume(&a.partial[static_cast<int64_t>(c) * a.npad + r]);
+    const double yv = static_cast<double>(a.y[r]);
+    const V th = static_cast<V>(s - yv);
+    a.theta[r] = th;
+    const double thd = static_cast<double>(th);
+    tt = fma(thd, thd, tt);
+    ty = fma(thd, yv, ty);
+  }
+  tt = block_sum<double, NW>(tt, sd);
+  ty = block_sum<double, NW>(ty, sd);
+  if (threadIdx.x == 0) {
+    publish(&a.rtn[2 * rt], tt);
+    publish(&a.rtn[2 * rt + 1], ty);
+    a.rt_cnt[rt] = 0u;  // every chunk of this tile has arrived: re-arm
+  }
+  if (arrive_last(&a.counters[CNT_FIN], static_cast<unsigned>(nrt), sflag)) {
+    // all loads in flight at once, fixed combination order
+    double t2 = 0.0, y2 = 0.0, om = 0.0;
+    for (int k = threadIdx.x; k < nrt; k += BLK) {
+      t2 += consume(&a.rtn[2 * k]);
+      y2 += consume(&a.rtn[2 * k + 1]);
+    }
+    for (int c = threadIdx.x; c < nch; c += BLK) om += consume(&a.omp[c]);
+    t2 = block_sum<double, NW>(t2, sd);
+    y2 = block_sum<double, NW>(y2, sd);
+    om = block_sum<double, NW>(om, sd);
+    if (threadIdx.x == 0) {
+      a.st->tt = t2;
+      a.st->ty = y2;
+      a.st->omega = om;
+      a.counters[CNT_FIN] = 0u;
     }
   }
 }
 
-// theta = sum of the chunk partials (fixed order) - y; FP64 ||theta||^2, theta^T y.
-template <typename T, typename V, typename A>
-__global__ __launch_bounds__(BLK) void k_resid_finalize(SingleArgs<T, V, A> a) {
+template <typename T, typename V, bool VECTOR, bool GROUP>
+__global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
+  constexpr int VR = VECTOR ? Store<T>::VEC : 1;
+  constexpr int RT = WAVE * VR;
+  constexpr int CHUNK = GROUP ? RCG : RC;
+  constexpr int LMAX = GROUP ? RCG * GMAX : RC;  // gathered support entries per chunk
+  __shared__ double red[NW][RT];
+  __shared__ int l_idx[LMAX];
+  __shared__ double l_val[LMAX];
   __shared__ double sd[NW];
-  __shared__ int flag;
-  SolverState* st = a.st;
+  __shared__ int scan[NW];
+  __shared__ int s_last, s_flag, s_nl;
+  const SolverState* st = a.st;
   if (st->done) return;
-  const int nch = (st->n_support + RCH - 1) / RCH;
-  const int r = blockIdx.x * BLK + threadIdx.x;
-  double tt = 0.0, ty = 0.0;
-  if (r < a.N) {
-    A s = A(0);
-    for (int c = 0; c < nch; ++c) s += a.partial[static_cast<int64_t>(c) * a.npad + r];
-    const V yv = a.y[r];
-    const V th = static_cast<V>(s - static_cast<A>(yv));
-    a.theta[r] = th;
-    tt = static_cast<double>(th) * static_cast<double>(th);
-    ty = static_cast<double>(th) * static_cast<double>(yv);
+  const int n_list = st->n_active;
+  const int32_t* __restrict__ list = a.act[st->cur];
+  const double* __restrict__ lmarg = a.act_m[st->cur];
+  const double r_keep = st->r_scr + st->marg_slack;
+  const int nrt = (a.N + RT - 1) / RT;
+  const int nch = (n_list + CHUNK - 1) / CHUNK;
+  const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+  if (nch == 0) {  // empty active list: theta = -y
+    if (static_cast<int>(blockIdx.x) < nrt)
+      resid_finish_tile<T, V, VECTOR>(a, blockIdx.x, 0, nrt, sd, &s_flag);
+    return;
   }
-  tt = block_sum<double, NW>(tt, sd);
-  ty = block_sum<double, NW>(ty, sd);
-  if (threadIdx.x == 0) { a.bp0[blockIdx.x] = tt; a.bp1[blockIdx.x] = ty; }
-  if (last_block_arrive(&a.counters[CNT_FIN], &flag)) {
-    double t2 = 0.0, y2 = 0.0;
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += BLK) {
-      t2 += a.bp0[b];
-      y2 += a.bp1[b];
+  for (int item = blockIdx.x; item < nrt * nch; item += gridDim.x) {
+    const int rt = item % nrt, c = item / nrt;
+    // ---- gather the non-zero, still-active atoms of chunk c in list order ----
+    int cntv = 0;
+    int unit = -1;
+    double om = 0.0;  // Omega(p) over this chunk: |p_i| (Lasso) or w_g ||p_g|| (groups)
+    if (tid < CHUNK && c * CHUNK + tid < n_list) {
+      unit = list[c * CHUNK + tid];
+      if (lmarg[c * CHUNK + tid] > r_keep) unit = -1;
     }
-    t2 = block_sum<double, NW>(t2, sd);
-    y2 = block_sum<double, NW>(y2, sd);
-    if (threadIdx.x == 0) {
-      st->tt = t2;
-      st->ty = y2;
-      a.counters[CNT_FIN] = 0u;
+    if (unit >= 0) {
+      if constexpr (GROUP) {
+        double p2 = 0.0;
+        for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) {
+          const double pv = static_cast<double>(a.u[i]);
+          cntv += pv != 0.0 ? 1 : 0;
+          p2 = fma(pv, pv, p2);
+        }
+        om = a.w[unit] * sqrt(p2);
+      } else {
+        const double pv = static_cast<double>(a.u[unit]);
+        cntv = pv != 0.0 ? 1 : 0;
+        om = fabs(pv);
+      }
     }
+    if (rt == 0) {
+      om = block_sum<double, NW>(om, sd);
+      if (tid == 0) publish(&a.omp[c], om);
+    }
+    int total;
+    int off = block_exclusive_scan<NW>(cntv, scan, &total);
+    if (unit >= 0 && cntv > 0) {
+      if constexpr (GROUP) {
+        for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) {
+          const V uv = a.u[i];
+          if (uv != V(0)) { l_idx[off] = static_cast<int>(i); l_val[off] = static_cast<double>(uv); ++off; }
+        }
+      } else {
+        l_idx[off] = unit;
+        l_val[off] = static_cast<double>(a.u[unit]);
+      }
+    }
+    if (tid == 0) s_nl = total;
+    __syncthreads();
+    const int nl = s_nl;
+    // ---- stream the row segments of the gathered columns ----
+    const int r0 = rt * RT + lane * VR;
+    double acc[VR];
+#pragma unroll
+    for (int e = 0; e < VR; ++e) acc[e] = 0.0;
+    for (int k0 = wave * RPW; k0 < nl; k0 += NW * RPW) {
+      int idx[RPW];
+      double val[RPW];
+#pragma unroll
+      for (int p = 0; p < RPW; ++p) {
+        const bool ok = k0 + p < nl;
+        idx[p] = ok ? l_idx[k0 + p] : l_idx[k0];
+        val[p] = ok ? l_val[k0 + p] : 0.0;
+      }
+      if (VECTOR && r0 + VR <= a.N) {
+        if constexpr (VECTOR) {
+          uint4 raw[RPW];
+#pragma unroll
+          for (int p = 0; p < RPW; ++p) raw[p] = ld16(a.D + static_cast<int64_t>(idx[p]) * a.ldd + r0);
+#pragma unroll
+          for (int p = 0; p < RPW; ++p) {
+            double d[VR];
+            widen<T>(raw[p], d);
+#pragma unroll
+            for (int e = 0; e < VR; ++e) acc[e] = fma(d[e], val[p], acc[e]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) {
+          const T* col = a.D + static_cast<int64_t>(idx[p]) * a.ldd;
+          for (int e = 0; e < VR; ++e)
+            if (r0 + e < a.N) acc[e] = fma(to_double(col[r0 + e]), val[p], acc[e]);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VR; ++e) red[wave][lane * VR + e] = acc[e];
+    __syncthreads();
+    for (int rr = tid; rr < RT; rr += BLK) {
+      const int r = rt * RT + rr;
+      if (r < a.N) {
+        double s = red[0][rr];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s += red[w][rr];
+        publish(&a.partial[static_cast<int64_t>(c) * a.npad + r], s);
+      }
+    }
+    if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nch), &s_last))
+      resid_finish_tile<T, V, VECTOR>(a, rt, nch, nrt, sd, &s_flag);
+    __syncthreads();
   }
 }
 
@@ -522,281 +764,251 @@ __device__ inline void scalar_update(SolverState* st, int N, int test, double zs
   }
 }
 
-// Correlation over the active atoms with the fused Lasso epilogue (one wave per CPW atoms).
-template <typename T, typename V, typename A, bool VECTOR, int RULE>
-__global__ __launch_bounds__(BLK) void k_corr_lasso(SingleArgs<T, V, A> a) {
-  __shared__ double sd[NW];
-  __shared__ int si[NW];
-  __shared__ int flag;
-  SolverState* st = a.st;
-  if (st->done) return;
-  const int n = st->n_active;
-  const int32_t* __restrict__ act = a.act[st->cur];
-  const double lam = st->lam, L = st->L;
-  const A invL = static_cast<A>(1.0 / L);
-  const A thr = static_cast<A>(lam / L);
-  const double l_prev = st->l_prev;
-  double l_new = l_prev;
-  A beta = A(0);
-  if (RULE == RULE_FISTA) {
-    l_new = 0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev));
-    beta = static_cast<A>((l_prev - 1.0) / l_new);
-  }
-  const double gz = st->gamma_z * sqrt(st->tt);
-  const int lane = threadIdx.x % WAVE;
-  const int gw = blockIdx.x * NW + threadIdx.x / WAVE;
-  const int nwaves = gridDim.x * NW;
-  double zsup = 0.0, omega = 0.0;
-  int nnz = 0;
-  for (int base = gw * CPW; base < n; base += nwaves * CPW) {
-    const int nc = min(CPW, n - base);
-    int idx[CPW];
-    const T* cols[CPW];
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      idx[c] = act[base + min(c, nc - 1)];
-      cols[c] = a.D + static_cast<int64_t>(idx[c]) * a.ldd;
+// Wave-wide decoupled look-back (all 64 lanes call it): exclusive prefix of `agg` over
+// virtual blocks 0..vb-1, 64 predecessors per probe.  Words are [epoch:16|flag:2|value:46],
+// flag 1 = aggregate, 2 = inclusive prefix.  Virtual block ids are handed out in arrival
+// order, so every predecessor has started and publishes without waiting on later blocks.
+__device__ inline int lookback_wave(uint64_t* status, int vb, int agg, uint32_t epoch, int lane) {
+  const uint64_t E = static_cast<uint64_t>(epoch) << 48;
+  constexpr uint64_t FA = 1ull << 46, FI = 2ull << 46, VMASK = (1ull << 46) - 1ull;
+  if (lane == 0)
+    publish(&status[vb], E | (vb == 0 ? FI : FA) | static_cast<uint64_t>(agg));
+  if (vb == 0) return 0;
+  int64_t prefix = 0;
+  int j0 = vb - 1;
+  while (true) {
+    const int j = j0 - lane;
+    uint64_t w = FI;  // positions before block 0 never matter (block 0 is inclusive)
+    if (j >= 0) w = consume(&status[j]);
+    const uint64_t flag = (w >> 46) & 3ull;
+    const bool valid = j < 0 || ((w >> 48) == epoch && flag != 0);
+    const bool incl = valid && (j < 0 || flag == 2);
+    const unsigned long long inc_mask = __ballot(incl);
+    const unsigned long long bad_mask = __ballot(!valid);
+    const int first_inc = inc_mask ? __ffsll(static_cast<long long>(inc_mask)) - 1 : WAVE;
+    const int first_bad = bad_mask ? __ffsll(static_cast<long long>(bad_mask)) - 1 : WAVE;
+    if (first_bad < first_inc || (first_inc == WAVE && first_bad < WAVE)) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
     }
-    A acc[CPW];
-    wave_dots<T, V, A, CPW, VECTOR>(cols, nc, a.theta, a.N, lane, acc);
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) acc[c] = wave_sum(acc[c]);
-    if (lane < nc) {
-      const A z = pick(acc, lane);
-      const int i = pick(idx, lane);
-      const V p = a.u[i];
-      const A xo = static_cast<A>(a.x[i]);
-      const A vv = static_cast<A>(p) - z * invL;
-      const A mag = fabs(vv) - thr;
-      const A xn = mag > A(0) ? copysign(mag, vv) : A(0);
-      const A un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
-      a.x[i] = static_cast<V>(xn);
-      a.u[i] = static_cast<V>(un);
-      zsup = fmax(zsup, fabs(static_cast<double>(z)) + gz * a.nu[i]);
-      omega += fabs(static_cast<double>(p));
-      nnz += xn != A(0) ? 1 : 0;
-    }
+    const int64_t v = (lane <= first_inc && j >= 0) ? static_cast<int64_t>(w & VMASK) : 0;
+    prefix += wave_sum(v);
+    if (first_inc < WAVE) break;
+    j0 -= WAVE;
   }
-  zsup = block_max<double, NW>(zsup, sd);
-  omega = block_sum<double, NW>(omega, sd);
-  nnz = block_sum<int, NW>(nnz, si);
-  if (threadIdx.x == 0) {
-    a.bp0[blockIdx.x] = zsup;
-    a.bp1[blockIdx.x] = omega;
-    a.bpi[blockIdx.x] = nnz;
-  }
-  if (last_block_arrive(&a.counters[CNT_CORR], &flag)) {
-    double zs = 0.0, om = 0.0;
-    int nz = 0;
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += BLK) {
-      zs = fmax(zs, a.bp0[b]);
-      om += a.bp1[b];
-      nz += a.bpi[b];
-    }
-    zs = block_max<double, NW>(zs, sd);
-    om = block_sum<double, NW>(om, sd);
-    nz = block_sum<int, NW>(nz, si);
-    if (threadIdx.x == 0) {
-      const int t = st->iter;  // index of this iteration's record
-      scalar_update(st, a.N, a.test, zs, om, nz, l_new);
-      if (a.tele != nullptr && t < a.tele_cap) {
-        TeleRec* rec = static_cast<TeleRec*>(a.tele) + t;
-        rec->n_atoms = st->n_active_atoms;
-        rec->n_units = n;
-        rec->n_support = st->n_support;
-        rec->nnz = nz;
-        rec->r = st->r_last;
-        rec->gap = st->gap;
-      }
-      a.counters[CNT_CORR] = 0u;
-    }
-  }
+  if (lane == 0) publish(&status[vb], E | FI | static_cast<uint64_t>(prefix + agg));
+  return static_cast<int>(prefix);
 }
 
-// Correlation over the active groups with the fused Group-Lasso epilogue: one wave per
-// group, the group's v = p - z / L kept in registers (lane k % 64 holds atom k).
-template <typename T, typename V, typename A, bool VECTOR, int RULE>
-__global__ __launch_bounds__(BLK) void k_corr_group(SingleArgs<T, V, A> a) {
-  __shared__ double sd[NW];
-  __shared__ int si[NW];
-  __shared__ int flag;
-  SolverState* st = a.st;
-  if (st->done) return;
-  const int n = st->n_active;
-  const int32_t* __restrict__ act = a.act[st->cur];
-  const double lam = st->lam, L = st->L;
-  const A invL = static_cast<A>(1.0 / L);
-  const double thr = lam / L;
-  const double l_prev = st->l_prev;
-  double l_new = l_prev;
-  A beta = A(0);
-  if (RULE == RULE_FISTA) {
-    l_new = 0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev));
-    beta = static_cast<A>((l_prev - 1.0) / l_new);
-  }
-  const double thn = sqrt(st->tt);
-  const double gz = st->gamma_z * thn;
-  const int lane = threadIdx.x % WAVE;
-  const int gw = blockIdx.x * NW + threadIdx.x / WAVE;
-  const int nwaves = gridDim.x * NW;
-  double zsup = 0.0, omega = 0.0;
-  int nnz = 0;
-  for (int j = gw; j < n; j += nwaves) {
-    const int g = act[j];
-    const int64_t a0 = a.gptr[g];
-    const int m = static_cast<int>(a.gptr[g + 1] - a0);
-    A vreg[GMAX_REG];
-    A preg[GMAX_REG];
-    double z2 = 0.0, p2 = 0.0, v2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < GMAX_REG; ++k) { vreg[k] = A(0); preg[k] = A(0); }
-    for (int base = 0; base < m; base += CPW) {
-      const int nc = min(CPW, m - base);
-      const T* cols[CPW];
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) cols[c] = a.D + (a0 + base + min(c, nc - 1)) * a.ldd;
-      A acc[CPW];
-      wave_dots<T, V, A, CPW, VECTOR>(cols, nc, a.theta, a.N, lane, acc);
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        acc[c] = wave_sum(acc[c]);
-        if (c < nc) z2 += static_cast<double>(acc[c]) * static_cast<double>(acc[c]);
-      }
-      // lane (base + c) % 64 keeps atom base + c
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        const int k = base + c;
-        if (c < nc && (k % WAVE) == lane) {
-          const A p = static_cast<A>(a.u[a0 + k]);
-          const A vv = p - acc[c] * invL;
-#pragma unroll
-          for (int r = 0; r < GMAX_REG; ++r)
-            if (k / WAVE == r) { vreg[r] = vv; preg[r] = p; }
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < GMAX_REG; ++r) {
-      v2 += static_cast<double>(vreg[r]) * static_cast<double>(vreg[r]);
-      p2 += static_cast<double>(preg[r]) * static_cast<double>(preg[r]);
-    }
-    v2 = wave_sum(v2);
-    p2 = wave_sum(p2);
-    const double wg = a.w[g];
-    const double nv = sqrt(v2);
-    const double scale = nv > 0.0 ? fmax(0.0, (nv - thr * wg) / nv) : 0.0;
-    const A sc = static_cast<A>(scale);
-    int gnz = 0;
-#pragma unroll
-    for (int r = 0; r < GMAX_REG; ++r) {
-      const int k = r * WAVE + lane;
-      if (k < m) {
-        const int64_t i = a0 + k;
-        const A xo = static_cast<A>(a.x[i]);
-        const A xn = sc * vreg[r];
-        const A un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
-        a.x[i] = static_cast<V>(xn);
-        a.u[i] = static_cast<V>(un);
-        gnz += xn != A(0) ? 1 : 0;
-      }
-    }
-    gnz = wave_sum(gnz);
-    if (lane == 0) {
-      // rounding-safe bound of ||D_g^T theta|| / w_g
-      zsup = fmax(zsup, (sqrt(z2) + gz * a.fro[g]) / wg);
-      omega += wg * sqrt(p2);
-      nnz += gnz;
-    }
-  }
-  zsup = block_max<double, NW>(zsup, sd);
-  omega = block_sum<double, NW>(omega, sd);
-  nnz = block_sum<int, NW>(nnz, si);
-  if (threadIdx.x == 0) {
-    a.bp0[blockIdx.x] = zsup;
-    a.bp1[blockIdx.x] = omega;
-    a.bpi[blockIdx.x] = nnz;
-  }
-  if (last_block_arrive(&a.counters[CNT_CORR], &flag)) {
-    double zs = 0.0, om = 0.0;
-    int nz = 0;
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += BLK) {
-      zs = fmax(zs, a.bp0[b]);
-      om += a.bp1[b];
-      nz += a.bpi[b];
-    }
-    zs = block_max<double, NW>(zs, sd);
-    om = block_sum<double, NW>(om, sd);
-    nz = block_sum<int, NW>(nz, si);
-    if (threadIdx.x == 0) {
-      const int t = st->iter;  // index of this iteration's record
-      scalar_update(st, a.N, a.test, zs, om, nz, l_new);
-      if (a.tele != nullptr && t < a.tele_cap) {
-        TeleRec* rec = static_cast<TeleRec*>(a.tele) + t;
-        rec->n_atoms = st->n_active_atoms;
-        rec->n_units = n;
-        rec->n_support = st->n_support;
-        rec->nnz = nz;
-        rec->r = st->r_last;
-        rec->gap = st->gap;
-      }
-      a.counters[CNT_CORR] = 0u;
-    }
-  }
-}
+// z = D_A^T theta over the active list with the fused epilogue.  Block b owns list
+// entries [b*CB, b*CB + CB); units screened at the previous iteration (margin above the
+// screening radius) are skipped without touching their columns, the kept ones are
+// streamed (the HBM-bound part, CPW columns per wave), and the prox (eq. softTh /
+// gr_softTh) and FISTA momentum (Table 1) update x and u in place.  When the list has
+// accumulated enough screened entries the kernel also writes the compacted list (order
+// preserved, offsets by decoupled look-back).  Block results are combined with
+// per-block partials read back in block order by the last block to arrive (two-level
+// arrival), so the iteration is deterministic; that block runs the FP64 scalars.
 
-// Order-preserving compaction of the active units against the margins (screened iff
-// m > r_scr + slack, the strict test of the lemmas), and the support list of the new
-// primal point.  One block; thread t handles a contiguous run of units.
-template <typename T, typename V, typename A>
-__global__ __launch_bounds__(CBLK) void k_compact(SingleArgs<T, V, A> a) {
-  __shared__ int sc[CNW];
+template <typename T, typename V, bool VECTOR, int RULE, bool GROUP>
+__global__ __launch_bounds__(CBLK_CORR) void k_corr(SingleArgs<T, V, double> a) {
+  __shared__ int s_vb, s_flag, s_nk, s_kpre;
+  __shared__ int klist[CB];
+  __shared__ double kmarg[CB];
+  __shared__ double sd[NWC];
+  __shared__ int si[NWC];
   SolverState* st = a.st;
   if (st->done) return;
-  const int n = st->n_active;
-  const int cur = st->cur;
-  const int32_t* __restrict__ in = a.act[cur];
-  int32_t* __restrict__ out = a.act[1 - cur];
-  const double thr = st->r_scr + st->marg_slack;
-  const int R = (n + CBLK - 1) / CBLK;
-  const int lo = min(static_cast<int>(threadIdx.x) * R, n), hi = min(lo + R, n);
-  int keep = 0, sup = 0, atoms = 0;
-  for (int j = lo; j < hi; ++j) {
-    const int unit = in[j];
-    if (!(a.marg[unit] > thr)) {
-      ++keep;
-      const int64_t b = a.G > 0 ? a.gptr[unit] : unit;
-      const int64_t e = a.G > 0 ? a.gptr[unit + 1] : unit + 1;
-      atoms += static_cast<int>(e - b);
-      for (int64_t i = b; i < e; ++i) sup += a.u[i] != V(0) ? 1 : 0;
-    }
+  const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+  const bool compact = st->compact != 0;
+  int vb = blockIdx.x;
+  if (compact) {
+    if (tid == 0) s_vb = static_cast<int>(atomicAdd(&a.counters[CNT_VID], 1u));
+    __syncthreads();
+    vb = s_vb;
   }
-  int tk, ts, ta;
-  int pk = block_exclusive_scan<CNW>(keep, sc, &tk);
-  int ps = block_exclusive_scan<CNW>(sup, sc, &ts);
-  block_exclusive_scan<CNW>(atoms, sc, &ta);
-  for (int j = lo; j < hi; ++j) {
-    const int unit = in[j];
-    if (!(a.marg[unit] > thr)) {
-      out[pk++] = unit;
-      const int64_t b = a.G > 0 ? a.gptr[unit] : unit;
-      const int64_t e = a.G > 0 ? a.gptr[unit + 1] : unit + 1;
-      for (int64_t i = b; i < e; ++i) {
-        const V uv = a.u[i];
-        if (uv != V(0)) {
-          a.s_idx[ps] = static_cast<int32_t>(i);
-          a.s_val[ps] = uv;
-          ++ps;
-        }
-      }
+  const int n_old = st->n_active, cur = st->cur;
+  const double r_keep = st->r_scr + st->marg_slack;
+  const uint32_t epoch = static_cast<uint32_t>(st->iter + 1) & 0xffffu;
+  const int base = vb * CB;
+  const int cnt = max(0, min(CB, n_old - base));
+  if (wave == 0) {
+    int unit = 0;
+    double m = 0.0;
+    bool keep = false;
+    if (lane < cnt) {
+      unit = a.act[cur][base + lane];
+      m = a.act_m[cur][base + lane];
+      keep = !(m > r_keep);
     }
+    const unsigned long long bal = __ballot(keep);
+    const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+    if (keep) { klist[pos] = unit; kmarg[pos] = m; }
+    const int nk0 = static_cast<int>(__popcll(bal));
+    if (compact) {
+      const int pre = lookback_wave(a.lbA, vb, nk0, epoch, lane);
+      if (lane == 0) s_kpre = pre;
+    }
+    if (lane == 0) s_nk = nk0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    st->n_active = tk;
-    st->n_support = ts;
-    st->n_active_atoms = ta;
-    st->cur = 1 - cur;
+  const int nk = s_nk;
+  if (compact && tid < nk) {
+    a.act[1 - cur][s_kpre + tid] = klist[tid];
+    a.act_m[1 - cur][s_kpre + tid] = kmarg[tid];
   }
+
+  const double lam = st->lam, L = st->L;
+  const double invL = 1.0 / L, thr = lam / L;
+  const double l_prev = st->l_prev;
+  double beta = 0.0;
+  if (RULE == RULE_FISTA) beta = (l_prev - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev)));
+  const double gz = st->gamma_z * sqrt(st->tt);
+  double zsup = 0.0;
+  int nnz = 0, nsup = 0, natoms = 0;
+  if constexpr (!GROUP) {
+    const int r0 = wave * CPW;
+    if (r0 < nk) {
+      const int nc = min(CPW, nk - r0);
+      const int i_l = klist[r0 + min(lane, nc - 1)];
+      // epilogue operands in flight together with the column stream
+      const double p = static_cast<double>(a.u[i_l]);
+      const double xo = static_cast<double>(a.x[i_l]);
+      const double nuv = a.nu[i_l];
+      const T* cols[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+        cols[c] = a.D + static_cast<int64_t>(klist[r0 + min(c, nc - 1)]) * a.ldd;
+      double acc[CPW];
+      wave_dots<T, V, CPW, VECTOR>(cols, a.theta, a.N, lane, acc);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[c] = wave_sum(acc[c]);
+      if (lane < nc) {
+        const double z = pick(acc, lane);
+        const double vv = p - z * invL;
+        const double mag = fabs(vv) - thr;
+        const double xn = mag > 0.0 ? copysign(mag, vv) : 0.0;
+        const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
+        const V xs = static_cast<V>(xn), us = static_cast<V>(un);
+        a.x[i_l] = xs;
+        a.u[i_l] = us;
+        zsup = fabs(z) + gz * nuv;
+        nnz = xs != V(0) ? 1 : 0;
+        nsup = us != V(0) ? 1 : 0;
+      }
+    }
+    natoms = tid == 0 ? nk : 0;
+  } else {
+    for (int j = wave; j < nk; j += NWC) {
+      const int g = klist[j];
+      const int64_t a0 = a.gptr[g];
+      const int m = static_cast<int>(a.gptr[g + 1] - a0);
+      const int li = min(lane, m - 1);
+      const double p = static_cast<double>(a.u[a0 + li]);
+      const double xo = static_cast<double>(a.x[a0 + li]);
+      double vreg = 0.0, z2 = 0.0;
+      for (int b0 = 0; b0 < m; b0 += CPW) {
+        const int nc = min(CPW, m - b0);
+        const T* cols[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) cols[c] = a.D + (a0 + b0 + min(c, nc - 1)) * a.ldd;
+        double acc[CPW];
+        wave_dots<T, V, CPW, VECTOR>(cols, a.theta, a.N, lane, acc);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          acc[c] = wave_sum(acc[c]);
+          if (c < nc) {
+            z2 = fma(acc[c], acc[c], z2);
+            if (b0 + c == lane) vreg = p - acc[c] * invL;  // lane k keeps atom k (m <= 64)
+          }
+        }
+      }
+      const double v2 = wave_sum(vreg * vreg);
+      const double wg = a.w[g];
+      const double nv = sqrt(v2);
+      const double scale = nv > 0.0 ? fmax(0.0, (nv - thr * wg) / nv) : 0.0;
+      int gnz = 0, gsup = 0;
+      if (lane < m) {
+        const double xn = scale * vreg;
+        const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
+        const V xs = static_cast<V>(xn), us = static_cast<V>(un);
+        a.x[a0 + lane] = xs;
+        a.u[a0 + lane] = us;
+        gnz = xs != V(0) ? 1 : 0;
+        gsup = us != V(0) ? 1 : 0;
+      }
+      gnz = wave_sum(gnz);
+      gsup = wave_sum(gsup);
+      if (lane == 0) {
+        // rounding-safe bound of ||D_g^T theta|| / w_g
+        zsup = fmax(zsup, (sqrt(z2) + gz * a.fro[g]) / wg);
+        nnz += gnz;
+        nsup += gsup;
+        natoms += m;
+      }
+    }
+  }
+  zsup = block_max<double, NWC>(zsup, sd);
+  nnz = block_sum<int, NWC>(nnz, si);
+  nsup = block_sum<int, NWC>(nsup, si);
+  natoms = block_sum<int, NWC>(natoms, si);
+  if (tid == 0) {
+    publish(&a.bp0[vb], zsup);
+    publish(&a.bpi[vb], nnz);
+    publish(&a.bpi[MAXB + vb], nk);
+    publish(&a.bpi[2 * MAXB + vb], nsup);
+    publish(&a.bpi[3 * MAXB + vb], natoms);
+  }
+  if (arrive_last_2l(&a.counters[CNT_SUB], &a.counters[CNT_CORR], vb, gridDim.x, &s_flag)) {
+    double zs = 0.0;
+    int nz = 0, kt = 0, stt = 0, at = 0;
+    for (int b = tid; b < static_cast<int>(gridDim.x); b += CBLK_CORR) {
+      zs = fmax(zs, consume(&a.bp0[b]));
+      nz += consume(&a.bpi[b]);
+      kt += consume(&a.bpi[MAXB + b]);
+      stt += consume(&a.bpi[2 * MAXB + b]);
+      at += consume(&a.bpi[3 * MAXB + b]);
+    }
+    zs = block_max<double, NWC>(zs, sd);
+    nz = block_sum<int, NWC>(nz, si);
+    kt = block_sum<int, NWC>(kt, si);
+    stt = block_sum<int, NWC>(stt, si);
+    at = block_sum<int, NWC>(at, si);
+    if (tid == 0) {
+      const int t = st->iter;  // index of this iteration's record
+      const int nsup_prev = st->n_support;
+      if (compact) {
+        st->n_active = kt;
+        st->cur = 1 - cur;
+      }
+      st->n_kept = kt;
+      st->n_support = stt;
+      st->n_active_atoms = at;
+      // compact next time once a quarter of the list (and at least one block) is stale
+      st->compact = (!compact && (n_old - kt) * 4 > n_old && (n_old - kt) >= CB) ? 1 : 0;
+      const double l_new = RULE == RULE_FISTA ? 0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev)) : l_prev;
+      scalar_update(st, a.N, a.test, zs, st->omega, nz, l_new);
+      if (a.tele != nullptr && t < a.tele_cap) {
+        TeleRec* rec = static_cast<TeleRec*>(a.tele) + t;
+        rec->n_atoms = at;
+        rec->n_units = kt;
+        rec->n_support = nsup_prev;
+        rec->nnz = nz;
+        rec->r = st->r_last;
+        rec->gap = st->gap;
+      }
+      a.counters[CNT_CORR] = 0u;
+      a.counters[CNT_VID] = 0u;
+    }
+  }
+}
+
+// Aligned copy of the observation (the caller's y may have any alignment).
+template <typename V>
+__global__ __launch_bounds__(BLK) void k_copy_y(const V* __restrict__ y, V* __restrict__ yc, int N,
+                                                 int npad) {
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < npad) yc[i] = i < N ? y[i] : V(0);
 }
 
 // Output: X = 0 outside the active units, x on them.
@@ -811,6 +1023,7 @@ __global__ __launch_bounds__(BLK) void k_scatter_out(SingleArgs<T, V, A> a, V* _
   const int j = blockIdx.x * BLK + threadIdx.x;
   if (st->status != 0 || j >= st->n_active) return;
   const int unit = a.act[st->cur][j];
+  if (a.marg[unit] > st->r_scr + st->marg_slack) return;  // screened, not yet compacted away
   if (a.G > 0) {
     for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) X[i] = a.x[i];
   } else {
@@ -829,6 +1042,7 @@ __global__ __launch_bounds__(BLK) void k_mark_active(SingleArgs<T, V, A> a, uint
   const int j = blockIdx.x * BLK + threadIdx.x;
   if (st->status != 0 || j >= st->n_active) return;
   const int unit = a.act[st->cur][j];
+  if (a.marg[unit] > st->r_scr + st->marg_slack) return;
   if (a.G > 0) {
     for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) m[i] = 0;
   } else {

@@ -44,6 +44,8 @@ struct alignas(16) SolverState {
   int32_t status;      // 0 ok, 1 trivial (lambda >= lambda_*), -1 invalid input
   int32_t max_iter;
   int32_t n_active_atoms;
+  int32_t n_kept;      // units kept by the last iteration (list entries may be stale)
+  int32_t compact;     // 1: the next correlation pass rewrites the list without stale entries
 };
 
 template <typename T, typename V, typename A>
@@ -55,15 +57,17 @@ struct SingleArgs {
   int32_t test, rule;
   const int64_t* gptr;   // device copy of group offsets (G+1), NULL for the Lasso
   const double* w;       // device group weights (G)
-  const V* y;            // observation
+  const V* y;            // observation (16-byte aligned copy)
   SolverState* st;
   int32_t* act[2];       // active unit lists (double buffered)
+  double* act_m[2];      // margins of the list entries (same layout as act)
   V* x;                  // primal x, dense K (atom indexed)
   V* u;                  // FISTA auxiliary u, dense K (ISTA: u == x)
   int32_t* s_idx;        // support list: atom index
+  int32_t* s_unit;       // support list: unit (atom or group) of the entry
   V* s_val;              // support list: value of the primal point theta is evaluated at
   V* theta;              // residual theta = D p - y
-  A* partial;            // residual partial sums, [chunk][Npad]
+  A* partial;            // residual partial sums, [support group][npad]
   int64_t npad;
   double* z0;            // D^T y (FP64), K
   double* g;             // D^T n (FP64), K
@@ -72,9 +76,15 @@ struct SingleArgs {
   double* gnorm;         // group spectral norms ||D_g||_2 (G), or NULL
   double* marg;          // margins (K for the Lasso, G for groups)
   double* nvec;          // d_* (Lasso) or n (groups), N, FP64
-  double* bp0;           // block partials
+  double* bp0;           // block partials (MAXB each)
   double* bp1;
-  int32_t* bpi;
+  int32_t* bpi;          // 4 x MAXB: nnz, kept units, support entries, kept atoms
+  double* rtn;           // per row tile (||theta||^2, theta^T y) partials
+  unsigned* rt_cnt;      // per row tile arrival counters
+  uint64_t* lbA;         // look-back words: kept-unit counts
+  unsigned long long* accum;  // correlation reductions: zsup bits, nnz, kept, support, atoms
+  double* omp;           // Omega(p) partial of each residual chunk
+  uint64_t* lbB;         // look-back words: support counts
   unsigned* counters;    // last-block counters (re-armed by the last block)
   void* tele;            // per-iteration telemetry records (Telemetry), or NULL
   int32_t tele_cap;
