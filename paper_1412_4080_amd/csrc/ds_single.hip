@@ -17,12 +17,18 @@ namespace {
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 struct Layout {
-  size_t off_state, off_act0, off_act1, off_x, off_u, off_sidx, off_sunit, off_sval, off_theta,
-      off_y, off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_bp0,
-      off_bp1, off_bpi, off_rtn, off_rtcnt, off_lba, off_lbb, off_cnt, off_gptr, off_w, off_tele,
-      off_pv, off_pw, off_pz, off_pd, off_actm0, off_actm1, off_accum, off_omp, total;
-  int64_t npad, nchunks, nslots;
+  size_t off_state, off_act0, off_act1, off_actm0, off_actm1, off_x, off_u, off_theta, off_y,
+      off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_segcnt,
+      off_segatom, off_segval, off_urm, off_uro, off_urn, off_bp0, off_bpi, off_rtn, off_omp,
+      off_rtcnt, off_lba, off_cnt, off_gptr, off_w, off_tele, off_pv, off_pw, off_pz, off_pd,
+      total;
+  int64_t npad, grid_corr, nsg;
 };
+
+// Correlation grid and residual segment groups for a problem shape.
+inline int64_t corr_blocks(int64_t K, int64_t G) {
+  return G > 0 ? (G + CBG - 1) / CBG : (K + CBL - 1) / CBL;
+}
 
 Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int64_t tele_cap,
                    bool power) {
@@ -30,28 +36,24 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
-    o += static_cast<size_t>(round_up(static_cast<int64_t>(bytes), 256));
+    o += static_cast<size_t>(round_up(static_cast<int64_t>(std::max<size_t>(bytes, 8)), 256));
     return at;
   };
   l.npad = round_up(N, 64);
-  l.nchunks = ((G > 0 ? G : K) + (G > 0 ? RCG : RC) - 1) / (G > 0 ? RCG : RC);
-  l.nslots = K;
+  l.grid_corr = corr_blocks(K, G);
+  const int64_t segcap = G > 0 ? SEGCAP_G : SEGCAP_L, ucap = G > 0 ? CBG : CBL;
+  l.nsg = G > 0 ? l.grid_corr : (l.grid_corr + SGL - 1) / SGL;
   const int64_t units = G > 0 ? G : K;
-  l.off_state = take(sizeof(SolverState));
+  l.off_state = take(2 * sizeof(SolverState));
   l.off_act0 = take(units * 4);
   l.off_act1 = take(units * 4);
   l.off_actm0 = take(units * 8);
   l.off_actm1 = take(units * 8);
-  l.off_accum = take(8 * 8);
-  l.off_omp = take((l.nchunks + 1) * 8);
   l.off_x = take(K * vsz);
   l.off_u = take(K * vsz);
-  l.off_sidx = take(l.nslots * 4);
-  l.off_sunit = take(l.nslots * 4);
-  l.off_sval = take(l.nslots * vsz);
   l.off_theta = take(l.npad * vsz);
   l.off_y = take(l.npad * vsz);
-  l.off_partial = take(l.nchunks * l.npad * asz);
+  l.off_partial = take(l.nsg * l.npad * asz);
   l.off_z0 = take(K * 8);
   l.off_g = take(K * 8);
   l.off_nu = take(K * 8);
@@ -59,13 +61,18 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.off_gnorm = take(std::max<int64_t>(G, 1) * 8);
   l.off_marg = take(units * 8);
   l.off_nvec = take(l.npad * 8);
+  l.off_segcnt = take(l.grid_corr * 4);
+  l.off_segatom = take(l.grid_corr * segcap * 4);
+  l.off_segval = take(l.grid_corr * segcap * vsz);
+  l.off_urm = take(l.grid_corr * ucap * 8);
+  l.off_uro = take(l.grid_corr * ucap * 8);
+  l.off_urn = take(l.grid_corr * ucap * 4);
   l.off_bp0 = take(MAXB * 8);
-  l.off_bp1 = take(MAXB * 8);
   l.off_bpi = take(4 * MAXB * 4);
-  l.off_rtn = take(2 * MAXRT * 8);
+  l.off_rtn = take(2 * 2 * MAXRT * 8);
+  l.off_omp = take(2 * MAXITEM * 8);
   l.off_rtcnt = take(MAXRT * 4);
   l.off_lba = take(MAXB * 8);
-  l.off_lbb = take(MAXB * 8);
   l.off_cnt = take(32 * 4);
   l.off_gptr = take((std::max<int64_t>(G, 1) + 1) * 8);
   l.off_w = take(std::max<int64_t>(G, 1) * 8);
@@ -102,6 +109,8 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.G = static_cast<int32_t>(P.G);
   a.test = test;
   a.rule = rule;
+  a.par = 0;
+  a.grid_corr = static_cast<int32_t>(l.grid_corr);
   a.gptr = P.G > 0 ? reinterpret_cast<const int64_t*>(base + l.off_gptr) : nullptr;
   a.w = P.G > 0 ? reinterpret_cast<const double*>(base + l.off_w) : nullptr;
   a.y = reinterpret_cast<const V*>(base + l.off_y);
@@ -111,13 +120,8 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.act[1] = reinterpret_cast<int32_t*>(base + l.off_act1);
   a.act_m[0] = reinterpret_cast<double*>(base + l.off_actm0);
   a.act_m[1] = reinterpret_cast<double*>(base + l.off_actm1);
-  a.accum = reinterpret_cast<unsigned long long*>(base + l.off_accum);
-  a.omp = reinterpret_cast<double*>(base + l.off_omp);
   a.x = reinterpret_cast<V*>(base + l.off_x);
   a.u = reinterpret_cast<V*>(base + l.off_u);
-  a.s_idx = reinterpret_cast<int32_t*>(base + l.off_sidx);
-  a.s_unit = reinterpret_cast<int32_t*>(base + l.off_sunit);
-  a.s_val = reinterpret_cast<V*>(base + l.off_sval);
   a.theta = reinterpret_cast<V*>(base + l.off_theta);
   a.partial = reinterpret_cast<A*>(base + l.off_partial);
   a.npad = l.npad;
@@ -128,13 +132,18 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.gnorm = reinterpret_cast<double*>(base + l.off_gnorm);
   a.marg = reinterpret_cast<double*>(base + l.off_marg);
   a.nvec = reinterpret_cast<double*>(base + l.off_nvec);
+  a.seg_cnt = reinterpret_cast<int32_t*>(base + l.off_segcnt);
+  a.seg_atom = reinterpret_cast<int32_t*>(base + l.off_segatom);
+  a.seg_val = reinterpret_cast<V*>(base + l.off_segval);
+  a.urec_marg = reinterpret_cast<double*>(base + l.off_urm);
+  a.urec_om = reinterpret_cast<double*>(base + l.off_uro);
+  a.urec_m = reinterpret_cast<int32_t*>(base + l.off_urn);
   a.bp0 = reinterpret_cast<double*>(base + l.off_bp0);
-  a.bp1 = reinterpret_cast<double*>(base + l.off_bp1);
   a.bpi = reinterpret_cast<int32_t*>(base + l.off_bpi);
   a.rtn = reinterpret_cast<double*>(base + l.off_rtn);
+  a.omp = reinterpret_cast<double*>(base + l.off_omp);
   a.rt_cnt = reinterpret_cast<unsigned*>(base + l.off_rtcnt);
   a.lbA = reinterpret_cast<uint64_t*>(base + l.off_lba);
-  a.lbB = reinterpret_cast<uint64_t*>(base + l.off_lbb);
   a.counters = reinterpret_cast<unsigned*>(base + l.off_cnt);
   return a;
 }
@@ -205,8 +214,6 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   DS_HIP(hipMemsetAsync(a.counters, 0, 32 * 4, s));
   DS_HIP(hipMemsetAsync(a.rt_cnt, 0, MAXRT * 4, s));
   DS_HIP(hipMemsetAsync(a.lbA, 0, MAXB * 8, s));
-  DS_HIP(hipMemsetAsync(a.lbB, 0, MAXB * 8, s));
-  DS_HIP(hipMemsetAsync(a.accum, 0, 8 * 8, s));
 
   // ---- setup (no host synchronisation) ----
   if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
@@ -248,12 +255,11 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   // ---- iterations ----
   constexpr int VR = VEC ? Store<T>::VEC : 1;
   const int nrt = static_cast<int>((P.N + WAVE * VR - 1) / (WAVE * VR));
-  const int64_t rchunks = (units + (P.G > 0 ? RCG : RC) - 1) / (P.G > 0 ? RCG : RC);
-  const int grid_res = std::max(nrt, grid_for(static_cast<int64_t>(nrt) * rchunks, 1, 2048));
-  const int grid_corr = grid_for(units, CB, MAXB);
-  if (nrt > MAXRT || (units + CB - 1) / CB > MAXB) {
+  const int grid_res = std::max(nrt, grid_for(static_cast<int64_t>(nrt) * l.nsg, 1, 2048));
+  const int grid_corr = static_cast<int>(l.grid_corr);
+  if (nrt > MAXRT || l.grid_corr > MAXB || l.nsg > MAXITEM) {
     set_error("problem too large for one device solve (N <= %d, units <= %d)", MAXRT * WAVE,
-              MAXB * CB);
+              MAXB * (P.G > 0 ? CBG : CBL));
     return DS_EINVAL;
   }
   StatAccum& S = stats();
@@ -275,35 +281,48 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     ++ev_used;
     return p;
   };
+  auto launch_resid = [&](int par) {
+    a.par = par;
+    if (P.G > 0)
+      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, true>), dim3(grid_res), dim3(BLK), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, false>), dim3(grid_res), dim3(BLK), 0, s, a);
+  };
+  auto launch_corr = [&](int par) {
+    a.par = par;
+    // instrumented launches carry start/stop events in the dispatch itself, so the
+    // measured interval is the kernel's own execution
+    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+    if (stat_on) e = get_events();
+    if (P.G > 0)
+      hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, true>), dim3(grid_corr), dim3(BLK), 0, s,
+                            e.first, e.second, 0, a);
+    else
+      hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, false>), dim3(grid_corr), dim3(BLK), 0, s,
+                            e.first, e.second, 0, a);
+    if (stat_on && e.first) ev.push_back(e);
+  };
 
-  int it = 0, chunk = 4;
+  // iteration t: corr(t) with parity t%2, then resid(t+1) (scalars of t, theta_{t+1});
+  // resid(1) forms theta_1 = -y.
+  launch_resid(1);
+  int t = 0, chunk = 4, last_par = 1;
   bool finished = false;
-  while (!finished && it < prm.max_iter) {
-    const int nrun = std::min(chunk, prm.max_iter - it);
+  while (!finished && t < prm.max_iter) {
+    const int nrun = std::min(chunk, prm.max_iter - t);
     for (int k = 0; k < nrun; ++k) {
-      if (P.G > 0)
-        hipLaunchKernelGGL((k_resid<T, V, VEC, true>), dim3(grid_res), dim3(BLK), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_resid<T, V, VEC, false>), dim3(grid_res), dim3(BLK), 0, s, a);
-      // instrumented launches carry start/stop events in the dispatch itself, so the
-      // measured interval is the kernel's own execution
-      std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
-      if (stat_on) e = get_events();
-      if (P.G > 0)
-        hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, true>), dim3(grid_corr), dim3(CBLK_CORR), 0, s,
-                              e.first, e.second, 0, a);
-      else
-        hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, false>), dim3(grid_corr), dim3(CBLK_CORR), 0,
-                              s, e.first, e.second, 0, a);
-      if (stat_on && e.first) ev.push_back(e);
+      ++t;
+      launch_corr(t % 2);
+      launch_resid((t + 1) % 2);
+      last_par = (t + 1) % 2;
     }
     DS_HIP(hipGetLastError());
-    it += nrun;
-    DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipMemcpyAsync(hst, a.st + last_par, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     DS_HIP(hipStreamSynchronize(s));
     finished = hst->done != 0;
     chunk = std::min(chunk * 2, 64);
   }
+  a.par = last_par;
 
   // ---- output ----
   V* X = static_cast<V*>(x);
@@ -319,7 +338,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
                        s, a, screened);
     DS_HIP(hipGetLastError());
   }
-  DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  DS_HIP(hipMemcpyAsync(hst, a.st + last_par, sizeof(SolverState), hipMemcpyDeviceToHost, s));
   DS_HIP(hipStreamSynchronize(s));
 
   const int iters_run = hst->iter;

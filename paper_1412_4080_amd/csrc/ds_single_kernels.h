@@ -29,7 +29,7 @@ constexpr int CB = NWC * CPW;    // active-list entries per correlation block (<
 constexpr int NSUB = 16;         // first-level arrival counters
 constexpr int RC = 256;          // active-list entries per residual work item (Lasso)
 constexpr int RCG = 32;          // active-list entries per residual work item (groups)
-constexpr int RPW = 4;           // support columns one residual wave loads at once
+constexpr int RPW = 8;           // support columns one residual wave loads at once
 constexpr int SCH = RC;          // partial-sum chunking unit of the residual
 constexpr int CBLK = 1024;       // threads of the single-block kernels
 constexpr int CNW = CBLK / WAVE;
@@ -455,6 +455,8 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     st->n_active = (bad || trivial) ? 0 : units;
     st->n_kept = st->n_active;
     st->compact = 0;
+    st->pending = 0;
+    st->n_omp = 0;
     st->n_active_atoms = (bad || trivial) ? 0 : K;
   }
 }
@@ -527,42 +529,88 @@ __global__ __launch_bounds__(CBLK) void k_setup_slack(SingleArgs<T, V, A> a) {
     }
   }
   kappa = block_max<double, CNW>(kappa, sd);
+  double kz = 0.0;  // scale of the correlation rounding slack
+  for (int u = threadIdx.x; u < units; u += CBLK)
+    kz = fmax(kz, a.G > 0 ? a.fro[u] / a.w[u] : a.nu[u]);
+  kz = block_max<double, CNW>(kz, sd);
   if (threadIdx.x == 0) {
+    st->kappa_z = kz;
     const double eps = (a.N + 16) * 0x1p-53;
     st->marg_slack = eps * kappa * (sqrt(st->yy) / st->lam + fabs(st->alpha) * sqrt(st->nn) + 1.0);
   }
 }
 
 // ============================================================== iteration kernels ===
+//
+// Iteration t runs two kernels.  k_resid(t) forms theta_t = D p_{t-1} - y (p = x for
+// ISTA, u for FISTA), and at its start every block recomputes, identically, the FP64
+// scalars of iteration t-1 from the partials the previous kernels published (dual
+// scaling, gap, radius, stopping rule); block 0 records them.  k_corr(t) streams the
+// active columns, applies the prox and momentum, and hands k_resid(t+1) a support
+// segment per block.  Neither kernel ends with a cross-block handshake except the
+// residual's row-tile reduction: long tails of dependent round trips cost more than the
+// stream itself on this device.  State and partials that a kernel both reads and
+// writes are double-buffered by the iteration parity, which the host passes in.
 
-// theta = D p - y over the non-zeros of the primal point p restricted to the active list,
-// FP64 accumulation.  Work item (row tile rt, list chunk c): the block gathers, in list
-// order, the atoms of chunk c that are still active and have p != 0 (units screened at
-// the previous iteration are dropped: Algorithm 3 removes their coordinates from the
-// primal variables), each wave streams the row segment of up to RPW of those columns at
-// a time, and the four waves combine in LDS.  The block completing the last chunk of a
-// tile forms theta on it (fixed summation order) with FP64 ||theta||^2 and theta^T y; the
-// last tile to finish writes the totals.  Partial sums cross blocks through agent-scope
-// atomic stores (see publish/arrive_last).
+constexpr int LR = 2;                 // correlation rounds per block (Lasso)
+constexpr int CBL = NW * CPW * LR;    // Lasso units per correlation block (16)
+constexpr int CBG = NW * 2;           // groups per correlation block (8)
+constexpr int SEGCAP_L = CBL;         // support slots per block (Lasso)
+constexpr int SEGCAP_G = CBG * GMAX;  // support slots per block (groups)
+constexpr int SGL = 32;               // correlation segments per residual item (Lasso)
+constexpr int MAXITEM = 8192;         // residual segment groups
+
+// FP64 scalars of one iteration from the reduced partials (same arithmetic in every
+// block): dual scaling (Lemma 7), dual point v = mu theta, gap certificate, radius of
+// the chosen test with its rounding slack, stopping rule.
+struct IterScalars {
+  double mu, gap, primal, dual, r, r_safe;
+  bool stop;
+};
+__device__ inline IterScalars iter_scalars(const SolverState& s, int N, int test, int t,
+                                           double tt, double ty, double omega, double zsup) {
+  IterScalars o;
+  const double lam = s.lam, yy = s.yy, rho2 = s.rho2;
+  const double sb = zsup > 0.0 ? 1.0 / zsup : dinf();
+  double mu = 0.0;
+  if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
+  o.mu = mu;
+  o.primal = 0.5 * tt + lam * omega;
+  o.dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
+  o.gap = o.primal - o.dual;
+  const double a1 = yy / (lam * lam), a2 = 2.0 * mu * ty / lam, a3 = mu * mu * tt;
+  const double R2 = a1 - a2 + a3;
+  o.r = dinf();
+  o.r_safe = dinf();
+  if (test != TEST_NONE) {
+    const double q = R2 - (test == TEST_DST3 ? rho2 : 0.0);
+    const double E = (N + 16) * 0x1p-53 * (a1 + fabs(a2) + a3 + rho2);
+    o.r = sqrt(fmax(q, 0.0));
+    o.r_safe = sqrt(fmax(q + E, 0.0));
+  }
+  o.stop = (s.gap_tol_abs > 0.0 && o.gap <= s.gap_tol_abs) || t >= s.max_iter;
+  return o;
+}
+
 template <typename T, typename V, bool VECTOR>
-__device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nch, int nrt,
-                                  double* sd, int* sflag) {
+__device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitems_rt,
+                                  double* sd) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
   constexpr int RT = WAVE * VR;
   double tt = 0.0, ty = 0.0;
   const int r_end = min((rt + 1) * RT, a.N);
   for (int r = rt * RT + static_cast<int>(threadIdx.x); r < r_end; r += BLK) {
-    // chunk partials in chunk order, sixteen loads in flight
+    // item partials in item order, sixteen loads in flight
     double s = 0.0;
     int c = 0;
-    for (; c + 16 <= nch; c += 16) {
+    for (; c + 16 <= nitems_rt; c += 16) {
       double v[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) v[k] = consume(&a.partial[static_cast<int64_t>(c + k) * a.npad + r]);
 #pragma unroll
       for (int k = 0; k < 16; ++k) s += v[k];
     }
-    for (; c < nch; ++c) s += consume(&a.partial[static_cast<int64_t>(c) * a.npad + r]);
+    for (; c < nitems_rt; ++c) s += consume(&a.partial[static_cast<int64_t>(c) * a.npad + r]);
     const double yv = static_cast<double>(a.y[r]);
     const V th = static_cast<V>(s - yv);
     a.theta[r] = th;
@@ -573,101 +621,192 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nch, 
   tt = block_sum<double, NW>(tt, sd);
   ty = block_sum<double, NW>(ty, sd);
   if (threadIdx.x == 0) {
-    publish(&a.rtn[2 * rt], tt);
-    publish(&a.rtn[2 * rt + 1], ty);
-    a.rt_cnt[rt] = 0u;  // every chunk of this tile has arrived: re-arm
-  }
-  if (arrive_last(&a.counters[CNT_FIN], static_cast<unsigned>(nrt), sflag)) {
-    // all loads in flight at once, fixed combination order
-    double t2 = 0.0, y2 = 0.0, om = 0.0;
-    for (int k = threadIdx.x; k < nrt; k += BLK) {
-      t2 += consume(&a.rtn[2 * k]);
-      y2 += consume(&a.rtn[2 * k + 1]);
-    }
-    for (int c = threadIdx.x; c < nch; c += BLK) om += consume(&a.omp[c]);
-    t2 = block_sum<double, NW>(t2, sd);
-    y2 = block_sum<double, NW>(y2, sd);
-    om = block_sum<double, NW>(om, sd);
-    if (threadIdx.x == 0) {
-      a.st->tt = t2;
-      a.st->ty = y2;
-      a.st->omega = om;
-      a.counters[CNT_FIN] = 0u;
-    }
+    double* rtn = a.rtn + a.par * (2 * MAXRT);
+    rtn[2 * rt] = tt;  // read by the next kernels only
+    rtn[2 * rt + 1] = ty;
+    a.rt_cnt[rt] = 0u;  // every item of this tile has arrived: re-arm
   }
 }
 
-template <typename T, typename V, bool VECTOR, bool GROUP>
+template <typename T, typename V, bool VECTOR, int RULE, bool GROUP>
 __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
   constexpr int RT = WAVE * VR;
-  constexpr int CHUNK = GROUP ? RCG : RC;
-  constexpr int LMAX = GROUP ? RCG * GMAX : RC;  // gathered support entries per chunk
+  constexpr int SEGCAP = GROUP ? SEGCAP_G : SEGCAP_L;
+  constexpr int UCAP = GROUP ? CBG : CBL;
+  constexpr int SG = GROUP ? 1 : SGL;             // segments per item
+  constexpr int SPI = SG * SEGCAP;                // slots per item
+  constexpr int SPT = SPI / BLK;                  // slots per thread
+  static_assert(SPI % BLK == 0, "slots must tile the block");
   __shared__ double red[NW][RT];
-  __shared__ int l_idx[LMAX];
-  __shared__ double l_val[LMAX];
+  __shared__ int l_idx[SPI];
+  __shared__ double l_val[SPI];
   __shared__ double sd[NW];
   __shared__ int scan[NW];
-  __shared__ int s_last, s_flag, s_nl;
-  const SolverState* st = a.st;
-  if (st->done) return;
-  const int n_list = st->n_active;
-  const int32_t* __restrict__ list = a.act[st->cur];
-  const double* __restrict__ lmarg = a.act_m[st->cur];
-  const double r_keep = st->r_scr + st->marg_slack;
-  const int nrt = (a.N + RT - 1) / RT;
-  const int nch = (n_list + CHUNK - 1) / CHUNK;
+  __shared__ int si[NW];
+  __shared__ int s_last;
+  __shared__ SolverState S;
+  __shared__ double red8[NW][8];
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-  if (nch == 0) {  // empty active list: theta = -y
-    if (static_cast<int>(blockIdx.x) < nrt)
-      resid_finish_tile<T, V, VECTOR>(a, blockIdx.x, 0, nrt, sd, &s_flag);
+  const SolverState* sin = a.st + (1 - a.par);
+  SolverState* sout = a.st + a.par;
+  {  // parallel copy of the state into LDS
+    constexpr int NWORDS = sizeof(SolverState) / 4;
+    static_assert(NWORDS <= BLK, "state fits one word per thread");
+    if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = reinterpret_cast<const int32_t*>(sin)[tid];
+  }
+  __syncthreads();
+  const int nrt = (a.N + RT - 1) / RT;
+  const int nsg = (a.grid_corr + SG - 1) / SG;
+  if (S.done) {
+    if (blockIdx.x == 0 && tid == 0) *sout = S;
     return;
   }
-  for (int item = blockIdx.x; item < nrt * nch; item += gridDim.x) {
-    const int rt = item % nrt, c = item / nrt;
-    // ---- gather the non-zero, still-active atoms of chunk c in list order ----
-    int cntv = 0;
-    int unit = -1;
-    double om = 0.0;  // Omega(p) over this chunk: |p_i| (Lasso) or w_g ||p_g|| (groups)
-    if (tid < CHUNK && c * CHUNK + tid < n_list) {
-      unit = list[c * CHUNK + tid];
-      if (lmarg[c * CHUNK + tid] > r_keep) unit = -1;
+  // ---- scalars of the previous iteration, from the published partials ----
+  if (S.pending) {
+    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // zs nz kt ns at tt ty om
+    for (int b = tid; b < a.grid_corr; b += BLK) {
+      v[0] = fmax(v[0], a.bp0[b]);
+      v[1] += a.bpi[b];
+      v[2] += a.bpi[MAXB + b];
+      v[3] += a.bpi[2 * MAXB + b];
+      v[4] += a.bpi[3 * MAXB + b];
     }
-    if (unit >= 0) {
-      if constexpr (GROUP) {
-        double p2 = 0.0;
-        for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) {
-          const double pv = static_cast<double>(a.u[i]);
-          cntv += pv != 0.0 ? 1 : 0;
-          p2 = fma(pv, pv, p2);
+    const double* rtp = a.rtn + (1 - a.par) * (2 * MAXRT);
+    const double* omp = a.omp + (1 - a.par) * MAXITEM;
+    for (int k = tid; k < nrt; k += BLK) { v[5] += rtp[2 * k]; v[6] += rtp[2 * k + 1]; }
+    for (int k = tid; k < S.n_omp; k += BLK) v[7] += omp[k];
+    // one-pass block reduction of the eight values (fixed order: lanes, then waves)
+    v[0] = wave_max(v[0]);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) red8[wave][k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      double acc = red8[0][k];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) acc = k == 0 ? fmax(acc, red8[w][k]) : acc + red8[w][k];
+      v[k] = acc;
+    }
+    const double tt = v[5], ty = v[6], om = v[7];
+    const int nz = static_cast<int>(v[1]), kt = static_cast<int>(v[2]);
+    const int ns = static_cast<int>(v[3]), at = static_cast<int>(v[4]);
+    // rounding-safe bound of the largest correlation (FP64 accumulation of exact products)
+    const double zs = v[0] + S.gamma_z * sqrt(tt) * S.kappa_z;
+    const int t = S.iter + 1;
+    const IterScalars o = iter_scalars(S, a.N, a.test, t, tt, ty, om, zs);
+    __syncthreads();
+    if (tid == 0) {
+      const int n_old = S.n_active;
+      if (S.compact) {
+        S.n_active = kt;
+        S.cur = 1 - S.cur;
+      }
+      S.compact = (!S.compact && (n_old - kt) * 4 > n_old && (n_old - kt) >= CBL) ? 1 : 0;
+      S.iter = t;
+      S.tt = tt;
+      S.ty = ty;
+      S.omega = om;
+      S.zsup = zs;
+      S.mu = o.mu;
+      S.gap = o.gap;
+      S.primal = o.primal;
+      S.dual = o.dual;
+      S.nnz = nz;
+      S.n_kept = kt;
+      S.n_support = ns;
+      S.n_active_atoms = at;
+      S.r_last = o.r;
+      S.r_min = fmin(S.r_min, o.r);
+      if (RULE == RULE_FISTA) S.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S.l_prev * S.l_prev));
+      if (o.stop) {
+        S.done = 1;
+      } else if (o.r_safe < S.r_scr) {
+        S.r_scr = o.r_safe;
+        S.r_slack = o.r_safe - o.r;
+      }
+      S.pending = 0;
+      if (blockIdx.x == 0 && a.tele != nullptr && t - 1 < a.tele_cap) {
+        TeleRec* rec = static_cast<TeleRec*>(a.tele) + (t - 1);
+        rec->n_atoms = at;
+        rec->n_units = kt;
+        rec->n_support = ns;
+        rec->nnz = nz;
+        rec->r = o.r;
+        rec->gap = o.gap;
+      }
+    }
+    __syncthreads();
+    if (S.done) {
+      if (blockIdx.x == 0 && tid == 0) *sout = S;
+      return;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    SolverState o = S;
+    o.n_omp = S.iter > 0 ? nsg : 1;  // the Omega partials this pass publishes
+    *sout = o;
+    a.counters[CNT_VID] = 0u;  // the correlation pass that used it has ended
+  }
+  const double r_keep = S.r_scr + S.marg_slack;
+  const bool have_support = S.iter > 0;  // p_0 = 0
+  if (!have_support) {  // theta = -y
+    if (static_cast<int>(blockIdx.x) < nrt) resid_finish_tile<T, V, VECTOR>(a, blockIdx.x, 0, sd);
+    if (blockIdx.x == 0 && tid == 0) a.omp[a.par * MAXITEM] = 0.0;
+    return;
+  }
+  for (int item = blockIdx.x; item < nrt * nsg; item += gridDim.x) {
+    const int rt = item % nrt, sg = item / nrt;
+    // ---- gather the kept, non-zero support entries of segment group sg (in order) ----
+    int cntv = 0;
+    int e_atom[SPT];
+    double e_val[SPT];
+    double om = 0.0;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = tid + q * BLK;  // slot within the item
+      const int b = sg * SG + s / SEGCAP, k = s % SEGCAP;
+      e_atom[q] = -1;
+      e_val[q] = 0.0;
+      if (b < a.grid_corr) {
+        const int nk = a.seg_cnt[b];
+        const int j = GROUP ? k / GMAX : k;
+        const int kk = GROUP ? k % GMAX : 0;
+        if (j < nk) {
+          const int64_t rec = static_cast<int64_t>(b) * UCAP + j;
+          const bool kept = !(a.urec_marg[rec] > r_keep);
+          if (kept && (!GROUP || kk < a.urec_m[rec])) {
+            const int64_t slot = static_cast<int64_t>(b) * SEGCAP + k;
+            const double v = static_cast<double>(a.seg_val[slot]);
+            if (v != 0.0) {
+              e_atom[q] = a.seg_atom[slot];
+              e_val[q] = v;
+              ++cntv;
+            }
+            if (kk == 0) om += a.urec_om[rec];
+          }
         }
-        om = a.w[unit] * sqrt(p2);
-      } else {
-        const double pv = static_cast<double>(a.u[unit]);
-        cntv = pv != 0.0 ? 1 : 0;
-        om = fabs(pv);
       }
     }
     if (rt == 0) {
       om = block_sum<double, NW>(om, sd);
-      if (tid == 0) publish(&a.omp[c], om);
+      if (tid == 0) a.omp[a.par * MAXITEM + sg] = om;
     }
     int total;
     int off = block_exclusive_scan<NW>(cntv, scan, &total);
-    if (unit >= 0 && cntv > 0) {
-      if constexpr (GROUP) {
-        for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) {
-          const V uv = a.u[i];
-          if (uv != V(0)) { l_idx[off] = static_cast<int>(i); l_val[off] = static_cast<double>(uv); ++off; }
-        }
-      } else {
-        l_idx[off] = unit;
-        l_val[off] = static_cast<double>(a.u[unit]);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (e_atom[q] >= 0) {
+        l_idx[off] = e_atom[q];
+        l_val[off] = e_val[q];
+        ++off;
       }
     }
-    if (tid == 0) s_nl = total;
     __syncthreads();
-    const int nl = s_nl;
+    const int nl = total;
     // ---- stream the row segments of the gathered columns ----
     const int r0 = rt * RT + lane * VR;
     double acc[VR];
@@ -713,54 +852,12 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
         double s = red[0][rr];
 #pragma unroll
         for (int w = 1; w < NW; ++w) s += red[w][rr];
-        publish(&a.partial[static_cast<int64_t>(c) * a.npad + r], s);
+        publish(&a.partial[static_cast<int64_t>(sg) * a.npad + r], s);
       }
     }
-    if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nch), &s_last))
-      resid_finish_tile<T, V, VECTOR>(a, rt, nch, nrt, sd, &s_flag);
+    if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nsg), &s_last))
+      resid_finish_tile<T, V, VECTOR>(a, rt, nsg, sd);
     __syncthreads();
-  }
-}
-
-// FP64 scalars of one iteration (thread 0 of the last correlation block).
-// Dual scaling (Lemma 7), dual point v = mu theta, gap certificate, radius of the
-// chosen sphere test, stopping rule; the screening radius carries a rounding slack.
-__device__ inline void scalar_update(SolverState* st, int N, int test, double zsup,
-                                     double omega, int nnz, double l_new) {
-  const int t = st->iter + 1;
-  const double tt = st->tt, ty = st->ty, lam = st->lam, yy = st->yy, rho2 = st->rho2;
-  const double s = zsup > 0.0 ? 1.0 / zsup : dinf();
-  double mu = 0.0;
-  if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -s), s);
-  const double primal = 0.5 * tt + lam * omega;
-  const double dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
-  const double gap = primal - dual;
-  const double a1 = yy / (lam * lam), a2 = 2.0 * mu * ty / lam, a3 = mu * mu * tt;
-  const double R2 = a1 - a2 + a3;
-  double r = dinf(), r_safe = dinf();
-  if (test != TEST_NONE) {
-    const double q = R2 - (test == TEST_DST3 ? rho2 : 0.0);
-    const double E = (N + 16) * 0x1p-53 * (a1 + fabs(a2) + a3 + rho2);
-    r = sqrt(fmax(q, 0.0));
-    r_safe = sqrt(fmax(q + E, 0.0));
-  }
-  st->iter = t;
-  st->zsup = zsup;
-  st->omega = omega;
-  st->mu = mu;
-  st->gap = gap;
-  st->primal = primal;
-  st->dual = dual;
-  st->nnz = nnz;
-  st->l_prev = l_new;
-  st->r_last = r;
-  st->r_min = fmin(st->r_min, r);
-  const bool stop = (st->gap_tol_abs > 0.0 && gap <= st->gap_tol_abs) || t >= st->max_iter;
-  if (stop) {
-    st->done = 1;
-  } else if (r_safe < st->r_scr) {
-    st->r_scr = r_safe;
-    st->r_slack = r_safe - r;
   }
 }
 
@@ -801,23 +898,25 @@ __device__ inline int lookback_wave(uint64_t* status, int vb, int agg, uint32_t 
 }
 
 // z = D_A^T theta over the active list with the fused epilogue.  Block b owns list
-// entries [b*CB, b*CB + CB); units screened at the previous iteration (margin above the
-// screening radius) are skipped without touching their columns, the kept ones are
-// streamed (the HBM-bound part, CPW columns per wave), and the prox (eq. softTh /
-// gr_softTh) and FISTA momentum (Table 1) update x and u in place.  When the list has
-// accumulated enough screened entries the kernel also writes the compacted list (order
-// preserved, offsets by decoupled look-back).  Block results are combined with
-// per-block partials read back in block order by the last block to arrive (two-level
-// arrival), so the iteration is deterministic; that block runs the FP64 scalars.
-
+// entries [b*CBU, b*CBU + CBU); units screened at the previous iteration (margin above
+// the screening radius) are skipped without touching their columns; the kept ones are
+// streamed (the HBM-bound part, CPW columns per wave for the Lasso, one group per wave
+// for the Group-Lasso) and the prox (eq. softTh / gr_softTh) and FISTA momentum
+// (Table 1) update x and u in place.  The block publishes its partials and a support
+// segment (the new u on its kept units, with their margins and Omega terms) for the next
+// residual.  When flagged, it also rewrites the list without the screened entries
+// (order preserved, offsets by decoupled look-back).
 template <typename T, typename V, bool VECTOR, int RULE, bool GROUP>
-__global__ __launch_bounds__(CBLK_CORR) void k_corr(SingleArgs<T, V, double> a) {
-  __shared__ int s_vb, s_flag, s_nk, s_kpre;
-  __shared__ int klist[CB];
-  __shared__ double kmarg[CB];
-  __shared__ double sd[NWC];
-  __shared__ int si[NWC];
-  SolverState* st = a.st;
+__global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
+  constexpr int CBU = GROUP ? CBG : CBL;
+  constexpr int SEGCAP = GROUP ? SEGCAP_G : SEGCAP_L;
+  static_assert(CBU <= WAVE, "one wave decides the block's list entries");
+  __shared__ int s_vb, s_nk, s_kpre;
+  __shared__ int klist[CBU];
+  __shared__ double kmarg[CBU];
+  __shared__ double sd[NW];
+  __shared__ int si[NW];
+  const SolverState* st = a.st + a.par;
   if (st->done) return;
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   const bool compact = st->compact != 0;
@@ -830,8 +929,8 @@ __global__ __launch_bounds__(CBLK_CORR) void k_corr(SingleArgs<T, V, double> a) 
   const int n_old = st->n_active, cur = st->cur;
   const double r_keep = st->r_scr + st->marg_slack;
   const uint32_t epoch = static_cast<uint32_t>(st->iter + 1) & 0xffffu;
-  const int base = vb * CB;
-  const int cnt = max(0, min(CB, n_old - base));
+  const int base = vb * CBU;
+  const int cnt = max(0, min(CBU, n_old - base));
   if (wave == 0) {
     int unit = 0;
     double m = 0.0;
@@ -857,24 +956,23 @@ __global__ __launch_bounds__(CBLK_CORR) void k_corr(SingleArgs<T, V, double> a) 
     a.act[1 - cur][s_kpre + tid] = klist[tid];
     a.act_m[1 - cur][s_kpre + tid] = kmarg[tid];
   }
+  if (tid == 0) a.seg_cnt[vb] = nk;
 
   const double lam = st->lam, L = st->L;
   const double invL = 1.0 / L, thr = lam / L;
   const double l_prev = st->l_prev;
   double beta = 0.0;
   if (RULE == RULE_FISTA) beta = (l_prev - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev)));
-  const double gz = st->gamma_z * sqrt(st->tt);
-  double zsup = 0.0;
+  double zsup = 0.0;  // max |z_i| (Lasso) or max ||z_g|| / w_g; rounding slack added later
   int nnz = 0, nsup = 0, natoms = 0;
   if constexpr (!GROUP) {
-    const int r0 = wave * CPW;
-    if (r0 < nk) {
+    for (int r0 = wave * CPW; r0 < nk; r0 += NW * CPW) {
       const int nc = min(CPW, nk - r0);
-      const int i_l = klist[r0 + min(lane, nc - 1)];
+      const int jl = r0 + min(lane, nc - 1);
+      const int i_l = klist[jl];
       // epilogue operands in flight together with the column stream
       const double p = static_cast<double>(a.u[i_l]);
       const double xo = static_cast<double>(a.x[i_l]);
-      const double nuv = a.nu[i_l];
       const T* cols[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
@@ -892,14 +990,19 @@ __global__ __launch_bounds__(CBLK_CORR) void k_corr(SingleArgs<T, V, double> a) 
         const V xs = static_cast<V>(xn), us = static_cast<V>(un);
         a.x[i_l] = xs;
         a.u[i_l] = us;
-        zsup = fabs(z) + gz * nuv;
-        nnz = xs != V(0) ? 1 : 0;
-        nsup = us != V(0) ? 1 : 0;
+        const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + jl;
+        a.seg_atom[slot] = i_l;
+        a.seg_val[slot] = us;
+        a.urec_marg[slot] = kmarg[jl];
+        a.urec_om[slot] = fabs(static_cast<double>(us));
+        zsup = fmax(zsup, fabs(z));
+        nnz += xs != V(0) ? 1 : 0;
+        nsup += us != V(0) ? 1 : 0;
       }
     }
     natoms = tid == 0 ? nk : 0;
   } else {
-    for (int j = wave; j < nk; j += NWC) {
+    for (int j = wave; j < nk; j += NW) {
       const int g = klist[j];
       const int64_t a0 = a.gptr[g];
       const int m = static_cast<int>(a.gptr[g + 1] - a0);
@@ -928,77 +1031,48 @@ __global__ __launch_bounds__(CBLK_CORR) void k_corr(SingleArgs<T, V, double> a) 
       const double nv = sqrt(v2);
       const double scale = nv > 0.0 ? fmax(0.0, (nv - thr * wg) / nv) : 0.0;
       int gnz = 0, gsup = 0;
+      double un2 = 0.0;
       if (lane < m) {
         const double xn = scale * vreg;
         const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
         const V xs = static_cast<V>(xn), us = static_cast<V>(un);
         a.x[a0 + lane] = xs;
         a.u[a0 + lane] = us;
+        const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + j * GMAX + lane;
+        a.seg_atom[slot] = static_cast<int32_t>(a0 + lane);
+        a.seg_val[slot] = us;
         gnz = xs != V(0) ? 1 : 0;
         gsup = us != V(0) ? 1 : 0;
+        un2 = static_cast<double>(us) * static_cast<double>(us);
       }
       gnz = wave_sum(gnz);
       gsup = wave_sum(gsup);
+      un2 = wave_sum(un2);
       if (lane == 0) {
-        // rounding-safe bound of ||D_g^T theta|| / w_g
-        zsup = fmax(zsup, (sqrt(z2) + gz * a.fro[g]) / wg);
+        const int64_t rec = static_cast<int64_t>(vb) * CBU + j;
+        a.urec_marg[rec] = kmarg[j];
+        a.urec_om[rec] = wg * sqrt(un2);
+        a.urec_m[rec] = m;
+        zsup = fmax(zsup, sqrt(z2) / wg);
         nnz += gnz;
         nsup += gsup;
         natoms += m;
       }
     }
   }
-  zsup = block_max<double, NWC>(zsup, sd);
-  nnz = block_sum<int, NWC>(nnz, si);
-  nsup = block_sum<int, NWC>(nsup, si);
-  natoms = block_sum<int, NWC>(natoms, si);
-  if (tid == 0) {
-    publish(&a.bp0[vb], zsup);
-    publish(&a.bpi[vb], nnz);
-    publish(&a.bpi[MAXB + vb], nk);
-    publish(&a.bpi[2 * MAXB + vb], nsup);
-    publish(&a.bpi[3 * MAXB + vb], natoms);
-  }
-  if (arrive_last_2l(&a.counters[CNT_SUB], &a.counters[CNT_CORR], vb, gridDim.x, &s_flag)) {
-    double zs = 0.0;
-    int nz = 0, kt = 0, stt = 0, at = 0;
-    for (int b = tid; b < static_cast<int>(gridDim.x); b += CBLK_CORR) {
-      zs = fmax(zs, consume(&a.bp0[b]));
-      nz += consume(&a.bpi[b]);
-      kt += consume(&a.bpi[MAXB + b]);
-      stt += consume(&a.bpi[2 * MAXB + b]);
-      at += consume(&a.bpi[3 * MAXB + b]);
-    }
-    zs = block_max<double, NWC>(zs, sd);
-    nz = block_sum<int, NWC>(nz, si);
-    kt = block_sum<int, NWC>(kt, si);
-    stt = block_sum<int, NWC>(stt, si);
-    at = block_sum<int, NWC>(at, si);
-    if (tid == 0) {
-      const int t = st->iter;  // index of this iteration's record
-      const int nsup_prev = st->n_support;
-      if (compact) {
-        st->n_active = kt;
-        st->cur = 1 - cur;
-      }
-      st->n_kept = kt;
-      st->n_support = stt;
-      st->n_active_atoms = at;
-      // compact next time once a quarter of the list (and at least one block) is stale
-      st->compact = (!compact && (n_old - kt) * 4 > n_old && (n_old - kt) >= CB) ? 1 : 0;
-      const double l_new = RULE == RULE_FISTA ? 0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev)) : l_prev;
-      scalar_update(st, a.N, a.test, zs, st->omega, nz, l_new);
-      if (a.tele != nullptr && t < a.tele_cap) {
-        TeleRec* rec = static_cast<TeleRec*>(a.tele) + t;
-        rec->n_atoms = at;
-        rec->n_units = kt;
-        rec->n_support = nsup_prev;
-        rec->nnz = nz;
-        rec->r = st->r_last;
-        rec->gap = st->gap;
-      }
-      a.counters[CNT_CORR] = 0u;
-      a.counters[CNT_VID] = 0u;
+  zsup = block_max<double, NW>(zsup, sd);
+  nnz = block_sum<int, NW>(nnz, si);
+  nsup = block_sum<int, NW>(nsup, si);
+  natoms = block_sum<int, NW>(natoms, si);
+  if (tid == 0) {  // read by the next residual pass only (after this kernel ends)
+    a.bp0[vb] = zsup;
+    a.bpi[vb] = nnz;
+    a.bpi[MAXB + vb] = nk;
+    a.bpi[2 * MAXB + vb] = nsup;
+    a.bpi[3 * MAXB + vb] = natoms;
+    if (vb == 0) {
+      SolverState* sw = a.st + a.par;
+      sw->pending = 1;  // nothing else in this pass reads it
     }
   }
 }
@@ -1019,7 +1093,7 @@ __global__ __launch_bounds__(BLK) void k_zero_out(V* __restrict__ X, int K) {
 }
 template <typename T, typename V, typename A>
 __global__ __launch_bounds__(BLK) void k_scatter_out(SingleArgs<T, V, A> a, V* __restrict__ X) {
-  const SolverState* st = a.st;
+  const SolverState* st = a.st + a.par;
   const int j = blockIdx.x * BLK + threadIdx.x;
   if (st->status != 0 || j >= st->n_active) return;
   const int unit = a.act[st->cur][j];
@@ -1038,7 +1112,7 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, int n, uint8_t v) {
 // Screened mask: 0 on the atoms of the active units (run after k_fill_u8(.., 1)).
 template <typename T, typename V, typename A>
 __global__ __launch_bounds__(BLK) void k_mark_active(SingleArgs<T, V, A> a, uint8_t* __restrict__ m) {
-  const SolverState* st = a.st;
+  const SolverState* st = a.st + a.par;
   const int j = blockIdx.x * BLK + threadIdx.x;
   if (st->status != 0 || j >= st->n_active) return;
   const int unit = a.act[st->cur][j];

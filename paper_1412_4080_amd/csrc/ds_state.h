@@ -22,6 +22,7 @@ struct alignas(16) SolverState {
   double ny;           // n^T y
   double marg_slack;   // bound on the FP64 rounding error of the margins
   double gamma_z;      // relative rounding bound of one streamed dot product
+  double kappa_z;      // max_i ||d_i|| (Lasso) or max_g ||D_g||_F / w_g: scales the slack
   double gap_tol_abs;  // gap_tol * ||y||^2 (0: fixed iteration count)
   // per-iteration scalars
   double tt;           // ||theta||^2 (FP64 from the stored theta)
@@ -46,6 +47,8 @@ struct alignas(16) SolverState {
   int32_t n_active_atoms;
   int32_t n_kept;      // units kept by the last iteration (list entries may be stale)
   int32_t compact;     // 1: the next correlation pass rewrites the list without stale entries
+  int32_t pending;     // 1: a correlation pass ran whose scalars are not computed yet
+  int32_t n_omp;       // Omega(p) partials the last residual pass published
 };
 
 template <typename T, typename V, typename A>
@@ -55,19 +58,18 @@ struct SingleArgs {
   int32_t N, K;
   int32_t G;             // 0: Lasso; >0 groups
   int32_t test, rule;
+  int32_t par;           // iteration parity (host-known): selects the state / partial buffers
+  int32_t grid_corr;     // blocks of the correlation kernel (= support segments)
   const int64_t* gptr;   // device copy of group offsets (G+1), NULL for the Lasso
   const double* w;       // device group weights (G)
   const V* y;            // observation (16-byte aligned copy)
-  SolverState* st;
+  SolverState* st;       // two states, indexed by parity
   int32_t* act[2];       // active unit lists (double buffered)
   double* act_m[2];      // margins of the list entries (same layout as act)
   V* x;                  // primal x, dense K (atom indexed)
   V* u;                  // FISTA auxiliary u, dense K (ISTA: u == x)
-  int32_t* s_idx;        // support list: atom index
-  int32_t* s_unit;       // support list: unit (atom or group) of the entry
-  V* s_val;              // support list: value of the primal point theta is evaluated at
   V* theta;              // residual theta = D p - y
-  A* partial;            // residual partial sums, [support group][npad]
+  A* partial;            // residual partial sums, [item][npad]
   int64_t npad;
   double* z0;            // D^T y (FP64), K
   double* g;             // D^T n (FP64), K
@@ -76,17 +78,22 @@ struct SingleArgs {
   double* gnorm;         // group spectral norms ||D_g||_2 (G), or NULL
   double* marg;          // margins (K for the Lasso, G for groups)
   double* nvec;          // d_* (Lasso) or n (groups), N, FP64
-  double* bp0;           // block partials (MAXB each)
-  double* bp1;
-  int32_t* bpi;          // 4 x MAXB: nnz, kept units, support entries, kept atoms
-  double* rtn;           // per row tile (||theta||^2, theta^T y) partials
+  // correlation -> residual hand-off (one segment per correlation block)
+  int32_t* seg_cnt;      // kept units of the block
+  int32_t* seg_atom;     // SEGCAP slots per block: atom index
+  V* seg_val;            // SEGCAP slots per block: new value of u
+  double* urec_marg;     // UCAP unit records per block: margin
+  double* urec_om;       // UCAP unit records per block: |u_i| or w_g ||u_g||
+  int32_t* urec_m;       // UCAP unit records per block: atoms in the unit
+  double* bp0;           // correlation partials: zsup per block
+  int32_t* bpi;          // 4 x MAXB: nnz, kept units, support, kept atoms per block
+  // residual -> (correlation, next residual) partials, [parity]
+  double* rtn;           // 2 x (2 x MAXRT): per row tile ||theta||^2, theta^T y
+  double* omp;           // 2 x MAXITEM: Omega(p) per segment group
   unsigned* rt_cnt;      // per row tile arrival counters
-  uint64_t* lbA;         // look-back words: kept-unit counts
-  unsigned long long* accum;  // correlation reductions: zsup bits, nnz, kept, support, atoms
-  double* omp;           // Omega(p) partial of each residual chunk
-  uint64_t* lbB;         // look-back words: support counts
-  unsigned* counters;    // last-block counters (re-armed by the last block)
-  void* tele;            // per-iteration telemetry records (Telemetry), or NULL
+  uint64_t* lbA;         // look-back words (list compaction)
+  unsigned* counters;    // arrival / virtual-block counters
+  void* tele;            // per-iteration telemetry records, or NULL
   int32_t tele_cap;
 };
 
