@@ -142,6 +142,17 @@ ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,
                        const ds_params* params, void* x, uint8_t* screened, ds_trace* trace,
                        int32_t trace_cap, ds_info* info, void* stream);
 
+/* lasso_solve with a diagnostic output: `screened` (DEVICE, K x B bytes, column b at
+ * offset b * K, may be NULL) receives 1 for every atom of signal b's final screened set
+ * and 0 otherwise.  For B > 1 with DS_BF16 storage (the batched MFMA path, Lasso only)
+ * the correlations that drive the iteration are FP32-accumulated on the matrix cores;
+ * the sphere radius carries their rounding bound (reported in info[b].radius_slack) and
+ * the gap that ends each solve is recomputed in FP64 at that iteration's primal point.
+ * Other cases run single-signal solves.  Return value and errors as lasso_solve. */
+ds_status ds_solve_batch(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                         const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                         ds_info* info, uint8_t* screened, void* stream);
+
 /* lambda_* of a single signal y (device, length N) and the first index attaining it
  * (atom index for the Lasso, group index for the Group-Lasso); FP64 accumulation. */
 ds_status ds_lambda_max(const ds_problem* problem, const void* y, double* lambda_max,
@@ -192,8 +203,11 @@ typedef struct {
   double flops;       /* summed algorithmic flops */
 } ds_kernel_stat;
 
+/* CORR: single-signal correlation pass; RESID: single-signal residual pass; SETUP:
+ * setup passes; BATCH: batched Z = D^T Theta GEMM with the fused update; BATCH_THETA:
+ * batched Theta = D U GEMM. */
 enum { DS_STAT_CORR = 0, DS_STAT_RESID = 1, DS_STAT_SETUP = 2, DS_STAT_BATCH = 3,
-       DS_STAT_COUNT = 4 };
+       DS_STAT_BATCH_THETA = 4, DS_STAT_COUNT = 5 };
 
 /* When enabled, each launch of the instrumented kernels is bracketed by HIP events on
  * its stream and its algorithmic bytes/flops are added to the counters. */

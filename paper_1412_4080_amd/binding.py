@@ -26,7 +26,7 @@ RULES = {"ista": 0, "fista": 1}
 TESTS = {"none": 0, "safe": 1, "dst3": 2, "gsafe": 1, "dgst3": 2}
 STATUS_NAMES = {0: "DS_OK", 1: "DS_PENDING", 2: "DS_NOT_CONVERGED", -1: "DS_EINVAL",
                 -2: "DS_ENOMEM", -3: "DS_EDEVICE", -4: "DS_ENOTFOUND", -5: "DS_EBUSY"}
-STAT_CORR, STAT_RESID, STAT_SETUP, STAT_BATCH, STAT_COUNT = 0, 1, 2, 3, 4
+STAT_CORR, STAT_RESID, STAT_SETUP, STAT_BATCH, STAT_BATCH_THETA, STAT_COUNT = 0, 1, 2, 3, 4, 5
 
 
 class Problem(C.Structure):
@@ -73,6 +73,9 @@ _sig = {
                               _P(Params), C.c_void_p, C.c_int64, _P(Info), C.c_void_p]),
     "glasso_solve": (C.c_int, [_P(Problem), C.c_void_p, C.c_int64, C.c_int64, _P(C.c_double),
                                _P(Params), C.c_void_p, C.c_int64, _P(Info), C.c_void_p]),
+    "ds_solve_batch": (C.c_int, [_P(Problem), C.c_void_p, C.c_int64, C.c_int64, _P(C.c_double),
+                                 _P(Params), C.c_void_p, C.c_int64, _P(Info), C.c_void_p,
+                                 C.c_void_p]),
     "ds_solve_one": (C.c_int, [_P(Problem), C.c_void_p, C.c_double, _P(Params), C.c_void_p,
                                C.c_void_p, _P(Trace), C.c_int32, _P(Info), C.c_void_p]),
     "ds_lambda_max": (C.c_int, [_P(Problem), C.c_void_p, _P(C.c_double), _P(C.c_int64),
@@ -175,11 +178,14 @@ def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
-          lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None):
+          lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
+          screened=False):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
-    lambda_relative).  Returns (X, infos) with X K x B column-major (or (K,) for 1-D Y).
+    lambda_relative).  Returns (X, infos) with X K x B column-major (or (K,) for 1-D Y);
+    with screened=True (Lasso only) returns (X, infos, mask), mask a K x B uint8 device
+    tensor (1 = screened) from ds_solve_batch.
     """
     torch = _torch()
     one = Y.dim() == 1
@@ -201,6 +207,16 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     infos = (Info * B)()
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter)
+    if screened:
+        if group_ptr is not None:
+            raise ValueError("screened masks of batched solves are for the Lasso")
+        mask = torch.empty(B, K, dtype=torch.uint8, device=Y.device).T
+        st = _lib.ds_solve_batch(C.byref(prob), C.c_void_p(Y2.data_ptr()), B, ldy, lam,
+                                 C.byref(prm), C.c_void_p(X.data_ptr()), ldx, infos,
+                                 C.c_void_p(mask.data_ptr()), _stream_ptr(stream))
+        _check(st, "ds_solve_batch")
+        infos = [i.as_dict() for i in infos]
+        return (X[:, 0] if one else X), infos, (mask[:, 0] if one else mask)
     fn = _lib.glasso_solve if group_ptr is not None else _lib.lasso_solve
     st = fn(C.byref(prob), C.c_void_p(Y2.data_ptr()), B, ldy, lam, C.byref(prm),
             C.c_void_p(X.data_ptr()), ldx, infos, _stream_ptr(stream))

@@ -152,7 +152,7 @@ namespace {
 
 ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
                        const double* lambdas, const ds_params* params, void* X, int64_t ldx,
-                       ds_info* info, void* stream, bool group) {
+                       ds_info* info, uint8_t* screened, void* stream, bool group) {
   ds_status e = validate_problem(problem, group);
   if (e != DS_OK) return e;
   if ((e = validate_params(params)) != DS_OK) return e;
@@ -174,7 +174,7 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   if (B > 1 && problem->dtype == DS_BF16 && !group) {
-    return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, s);
+    return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, screened, s);
   }
   DeviceCtx& ctx = device_ctx(dev);
   std::lock_guard<std::mutex> g(ctx.mu);
@@ -184,7 +184,8 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
     const char* yb = static_cast<const char*>(Y) + b * ldy * vsz;
     char* xb = static_cast<char*>(X) + b * ldx * vsz;
     std::memset(&info[b], 0, sizeof(ds_info));
-    e = solve_single(*problem, yb, lambdas[b], *params, xb, &info[b], s, ctx.ws, nullptr);
+    e = solve_single(*problem, yb, lambdas[b], *params, xb, &info[b], s, ctx.ws, nullptr,
+                     screened != nullptr ? screened + b * problem->K : nullptr);
     if (e < 0) return e;
     if (e == DS_NOT_CONVERGED) worst = DS_NOT_CONVERGED;
   }
@@ -201,13 +202,19 @@ extern "C" {
 ds_status lasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
                       const double* lambdas, const ds_params* params, void* X, int64_t ldx,
                       ds_info* info, void* stream) {
-  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, stream, false);
+  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, nullptr, stream, false);
+}
+
+ds_status ds_solve_batch(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
+                         const double* lambdas, const ds_params* params, void* X, int64_t ldx,
+                         ds_info* info, uint8_t* screened, void* stream) {
+  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, screened, stream, false);
 }
 
 ds_status glasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
                        const double* lambdas, const ds_params* params, void* X, int64_t ldx,
                        ds_info* info, void* stream) {
-  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, stream, true);
+  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, nullptr, stream, true);
 }
 
 ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,

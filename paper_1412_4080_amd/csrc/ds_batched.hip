@@ -1,28 +1,397 @@
-// Batched path for many signals sharing one bfloat16 dictionary (placeholder: sequential
-// single-signal solves until the MFMA engine lands).
+// Batched path for many signals sharing one bfloat16 dictionary (Lasso, B > 1): host
+// side.  Buffers live in one per-device workspace; a run of ITERS_PER_GRAPH iterations
+// (an even number, so that it starts on the same parity of the u double buffer each time)
+// is captured once as a HIP graph and replayed until every signal has finished.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <vector>
 
+#include "ds_batched_kernels.h"
 #include "ds_engine.h"
 
 namespace ds {
+namespace {
+
+using namespace batch;
+
+constexpr int ITERS_PER_GRAPH = 8;  // iterations per graph replay (even)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct BLayout {
+  int N, K, B, Np, Kp, Bp, splitk, klen, nrc, nac;
+  size_t dcm, drm, nu, dsc, Y, X, U0, U1, Us, Thp, Ths, marg, tminm, pz, pom, pact, th64, vtt,
+      vty, vz, inst, ctr, vlist, perm, lam, z0, gn, Vn, total;
+};
+
+// Split of the K reduction of the Theta GEMM: enough slices to give every CU work.
+void pick_split(BLayout& l) {
+  const int tiles = (l.Bp / 64) * (l.Np / 64);
+  int sk = std::max(1, std::min(16, (1024 + tiles - 1) / tiles));
+  l.klen = round_up((l.Kp + sk - 1) / sk, 16);
+  l.splitk = (l.Kp + l.klen - 1) / l.klen;
+}
+
+BLayout make_layout(int N, int K, int B) {
+  BLayout l{};
+  l.N = N; l.K = K; l.B = B;
+  l.Np = round_up(N, 64);
+  l.Kp = round_up(K, 64);
+  l.Bp = round_up(B, 64);
+  pick_split(l);
+  l.nrc = (l.Np + TB - 1) / TB;
+  l.nac = (K + 255) / 256;
+  const size_t np = l.Np, kp = l.Kp, bp = l.Bp, nt = l.Kp / MT;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  l.dcm = take(kp * np * 2);
+  l.drm = take(kp * np * 2);
+  l.nu = take(kp * 8);
+  l.dsc = take(2 * 8);
+  l.Y = take(bp * np * 4);
+  l.X = take(bp * kp * 4);
+  l.U0 = take(bp * kp * 4);
+  l.U1 = take(bp * kp * 4);
+  l.Us = take(3 * bp * kp * 2);
+  l.Thp = take(static_cast<size_t>(l.splitk) * bp * np * 4);
+  l.Ths = take(3 * bp * np * 2);
+  l.marg = take(bp * kp * 4);
+  l.tminm = take(nt * bp * 4);
+  l.pz = take(nt * bp * 4);
+  l.pom = take(nt * bp * 8);
+  l.pact = take(nt * bp * 4);
+  l.th64 = take(bp * np * 8);
+  l.vtt = take(static_cast<size_t>(l.nrc) * bp * 8);
+  l.vty = take(static_cast<size_t>(l.nrc) * bp * 8);
+  l.vz = take(static_cast<size_t>(l.nac) * bp * 8);
+  l.inst = take(bp * sizeof(Inst));
+  l.ctr = take(4 * sizeof(int));
+  l.vlist = take(bp * 4);
+  l.perm = take(bp * 4);
+  l.lam = take(bp * 8);
+  l.z0 = take(bp * kp * 8);
+  l.gn = take(bp * kp * 8);
+  l.Vn = take(bp * np * 4);
+  l.total = o;
+  return l;
+}
+
+// Per-device state of the batched engine: workspace, a private stream (graph capture
+// needs one that is not the legacy default stream), and the last instantiated graph.
+struct BatchCtx {
+  std::mutex mu;
+  Workspace ws;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BArgs key{};
+  int* host_ctr = nullptr;  // pinned: ndone
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evpool;
+  size_t ev_used = 0;
+};
+
+BatchCtx& batch_ctx(int device) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<BatchCtx>> ctx;
+  std::lock_guard<std::mutex> g(mu);
+  auto& p = ctx[device];
+  if (!p) {
+    p = std::make_unique<BatchCtx>();
+    p->ws.device = device;
+  }
+  return *p;
+}
+
+BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
+  BArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.N = l.N; a.K = l.K; a.B = l.B; a.Np = l.Np; a.Kp = l.Kp; a.Bp = l.Bp;
+  a.test = static_cast<int>(prm.test);
+  a.rule = prm.rule == DS_FISTA ? 1 : 0;
+  a.max_iter = prm.max_iter;
+  a.splitk = l.splitk;
+  a.klen = l.klen;
+  a.L = L;
+  // FP32 accumulation of 3 Np exact products (and the MFMA's internal sums) bounded with
+  // unit roundoff 2^-23; the factor 1.02 covers |hi| + |mid| + |lo| <= (1 + 2^-7) |v|
+  const double n = 3.0 * l.Np + 32.0, u = 0x1p-23;
+  a.gamma_acc = 1.02 * n * u / (1.0 - n * u);
+  a.gamma64 = 1.01 * (l.Np + 16) * 0x1p-53;
+  a.dcm = reinterpret_cast<const uint16_t*>(base + l.dcm);
+  a.drm = reinterpret_cast<const uint16_t*>(base + l.drm);
+  a.dsc = reinterpret_cast<const double*>(base + l.dsc);
+  a.nu = reinterpret_cast<const double*>(base + l.nu);
+  a.Y = reinterpret_cast<const float*>(base + l.Y);
+  a.X = reinterpret_cast<float*>(base + l.X);
+  a.U0 = reinterpret_cast<float*>(base + l.U0);
+  a.U1 = reinterpret_cast<float*>(base + l.U1);
+  a.Us = reinterpret_cast<uint16_t*>(base + l.Us);
+  a.Thp = reinterpret_cast<float*>(base + l.Thp);
+  a.Ths = reinterpret_cast<uint16_t*>(base + l.Ths);
+  a.marg = reinterpret_cast<const float*>(base + l.marg);
+  a.tminm = reinterpret_cast<const float*>(base + l.tminm);
+  a.pz = reinterpret_cast<float*>(base + l.pz);
+  a.pom = reinterpret_cast<double*>(base + l.pom);
+  a.pact = reinterpret_cast<int*>(base + l.pact);
+  a.th64 = reinterpret_cast<double*>(base + l.th64);
+  a.vtt = reinterpret_cast<double*>(base + l.vtt);
+  a.vty = reinterpret_cast<double*>(base + l.vty);
+  a.vz = reinterpret_cast<double*>(base + l.vz);
+  a.inst = reinterpret_cast<Inst*>(base + l.inst);
+  a.ndone = reinterpret_cast<int*>(base + l.ctr);
+  a.vcount = reinterpret_cast<int*>(base + l.ctr) + 1;
+  a.vlist = reinterpret_cast<int*>(base + l.vlist);
+  return a;
+}
+
+}  // namespace
 
 ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
                              const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
-                             ds_info* info, hipStream_t stream) {
+                             ds_info* info, uint8_t* screened, hipStream_t stream) {
+  if (P.N > (1 << 24) || P.K > (1 << 24) || B > (1 << 20)) {
+    set_error("batched path: N, K must be <= 2^24 and B <= 2^20");
+    return DS_EINVAL;
+  }
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
-  DeviceCtx& ctx = device_ctx(dev);
-  std::lock_guard<std::mutex> g(ctx.mu);
+  BatchCtx& C = batch_ctx(dev);
+  std::lock_guard<std::mutex> guard(C.mu);
+  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), static_cast<int>(B));
+  ds_status e = C.ws.reserve(l.total);
+  if (e != DS_OK) return e;
+  if (C.stream == nullptr) {
+    DS_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
+    DS_HIP(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming));
+    DS_HIP(hipHostMalloc(reinterpret_cast<void**>(&C.host_ctr), 64, hipHostMallocDefault));
+  }
+  hipStream_t s = C.stream;
+  // inputs written on the caller's stream are visible to ours
+  DS_HIP(hipEventRecord(C.ev, stream));
+  DS_HIP(hipStreamWaitEvent(s, C.ev, 0));
+
+  // step constant
+  double L = prm.step_L;
+  if (!(L > 0.0)) {
+    Workspace tmp;
+    tmp.device = dev;
+    e = spectral_norm_impl(P, 0, &L, s, tmp);
+    tmp.release();
+    if (e != DS_OK) return e;
+  }
+
+  char* base = static_cast<char*>(C.ws.base);
+  const BArgs a = make_args(l, base, prm, L);
+
+  // slots ordered by penalty so that signals finishing together share tiles
+  std::vector<int> perm(l.Bp);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.begin() + B,
+                   [&](int i, int j) { return lambdas[i] > lambdas[j]; });
+  std::vector<double> lam_slot(l.Bp, 1.0);
+  for (int64_t k = 0; k < B; ++k) lam_slot[k] = lambdas[perm[k]];
+  for (int k = static_cast<int>(B); k < l.Bp; ++k) perm[k] = 0;
+  int* d_perm = reinterpret_cast<int*>(base + l.perm);
+  double* d_lam = reinterpret_cast<double*>(base + l.lam);
+  DS_HIP(hipMemcpyAsync(d_perm, perm.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
+  DS_HIP(hipMemcpyAsync(d_lam, lam_slot.data(), l.Bp * sizeof(double), hipMemcpyHostToDevice, s));
+
+  // ---------------------------------------------------------------- setup
+  StatAccum& S = stats();
+  bool stat_on;
+  {
+    std::lock_guard<std::mutex> g(S.mu);
+    stat_on = S.on;
+  }
+  hipEvent_t su0 = nullptr, su1 = nullptr;
+  if (stat_on) {
+    DS_HIP(hipEventCreate(&su0));
+    DS_HIP(hipEventCreate(&su1));
+    DS_HIP(hipEventRecord(su0, s));
+  }
+  DS_HIP(hipMemsetAsync(base + l.ctr, 0, 4 * sizeof(int), s));
+  DS_HIP(hipMemsetAsync(base + l.X, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s));
+  DS_HIP(hipMemsetAsync(base + l.U0, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s));
+  DS_HIP(hipMemsetAsync(base + l.U1, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s));
+  DS_HIP(hipMemsetAsync(base + l.Us, 0, static_cast<size_t>(3) * l.Bp * l.Kp * 2, s));
+  uint16_t* dcm = reinterpret_cast<uint16_t*>(base + l.dcm);
+  uint16_t* drm = reinterpret_cast<uint16_t*>(base + l.drm);
+  hipLaunchKernelGGL(k_b_prep, dim3(l.Kp / 64, l.Np / 64), dim3(TB), 0, s,
+                     static_cast<const uint16_t*>(P.D), P.ldd, l.N, l.K, l.Np, l.Kp, dcm, drm);
+  hipLaunchKernelGGL(k_b_norms, dim3(l.Kp / NWB), dim3(TB), 0, s, dcm, l.Np, l.Kp,
+                     reinterpret_cast<double*>(base + l.nu));
+  hipLaunchKernelGGL(k_b_dict_scalars, dim3(1), dim3(TB), 0, s,
+                     reinterpret_cast<const double*>(base + l.nu), l.K,
+                     reinterpret_cast<double*>(base + l.dsc));
+  hipLaunchKernelGGL(k_b_load_y, dim3((l.Np + TB - 1) / TB, l.Bp), dim3(TB), 0, s,
+                     static_cast<const float*>(Y), ldy, d_perm, l.N, l.B, l.Np,
+                     reinterpret_cast<float*>(base + l.Y));
+  double* z0 = reinterpret_cast<double*>(base + l.z0);
+  double* gn = reinterpret_cast<double*>(base + l.gn);
+  float* Vn = reinterpret_cast<float*>(base + l.Vn);
+  hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 16), dim3(TB), 0, s, dcm, a.Y, l.Np, l.Kp, z0);
+  hipLaunchKernelGGL(k_b_inst_init, dim3(l.Bp), dim3(TB), 0, s, a, z0, d_lam,
+                     prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0, prm.gap_tol, Vn);
+  if (prm.test == DS_TEST_DST3)
+    hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 16), dim3(TB), 0, s, dcm, Vn, l.Np, l.Kp, gn);
+  hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a, z0, gn,
+                     reinterpret_cast<float*>(base + l.marg));
+  hipLaunchKernelGGL(k_b_tile_min, dim3((l.Kp / MT + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a,
+                     reinterpret_cast<float*>(base + l.tminm));
+  DS_HIP(hipGetLastError());
+  if (stat_on) DS_HIP(hipEventRecord(su1, s));
+
+  // ---------------------------------------------------------------- iteration
+  const dim3 g_theta(l.Bp / 64, l.Np / 64, l.splitk);
+  const dim3 g_z(l.Kp / 64, l.Bp / 64);
+  const dim3 g_slot4(l.Bp / NWB);
+  const dim3 g_vth(l.nrc, VY), g_vco(l.nac, VY);
+  const dim3 g_scr((l.Kp / 4 + TB - 1) / TB, l.Bp);
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evz, evt;
+  auto events = [&]() -> std::pair<hipEvent_t, hipEvent_t> {
+    if (C.ev_used == C.evpool.size()) {
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return {nullptr, nullptr};
+      C.evpool.push_back({e0, e1});
+    }
+    return C.evpool[C.ev_used++];
+  };
+  auto iteration = [&](int t, bool timed) {
+    float* Uin = (t % 2 == 1) ? a.U0 : a.U1;
+    float* Uout = (t % 2 == 1) ? a.U1 : a.U0;
+    std::pair<hipEvent_t, hipEvent_t> et{nullptr, nullptr}, ez{nullptr, nullptr};
+    if (timed) { et = events(); ez = events(); }
+    // instrumented launches carry start/stop events in the dispatch itself
+    if (timed)
+      hipExtLaunchKernelGGL(k_b_theta_gemm, g_theta, dim3(TB), 0, s, et.first, et.second, 0, a);
+    else
+      hipLaunchKernelGGL(k_b_theta_gemm, g_theta, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_theta_fin, dim3(l.Bp), dim3(TB), 0, s, a);
+    if (timed)
+      hipExtLaunchKernelGGL(k_b_zgemm, g_z, dim3(TB), 0, s, ez.first, ez.second, 0, a,
+                            static_cast<const float*>(Uin), Uout);
+    else
+      hipLaunchKernelGGL(k_b_zgemm, g_z, dim3(TB), 0, s, a, static_cast<const float*>(Uin), Uout);
+    hipLaunchKernelGGL(k_b_scalars, g_slot4, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_vtheta, g_vth, dim3(TB), 0, s, a, static_cast<const float*>(Uin));
+    hipLaunchKernelGGL(k_b_vcorr, g_vco, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_vfin, g_slot4, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_screen, g_scr, dim3(TB), 0, s, a);
+    if (timed && et.first) { evt.push_back(et); evz.push_back(ez); }
+  };
+
+  int t = 0;
+  if (stat_on) {
+    // instrumented run: direct launches with events in the dispatches
+    C.ev_used = 0;
+    while (t < prm.max_iter) {
+      for (int k = 0; k < ITERS_PER_GRAPH; ++k) iteration(++t, true);
+      DS_HIP(hipGetLastError());
+      DS_HIP(hipMemcpyAsync(C.host_ctr, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+      DS_HIP(hipStreamSynchronize(s));
+      if (*C.host_ctr >= B) break;
+    }
+  } else {
+    if (C.exec == nullptr || std::memcmp(&C.key, &a, sizeof a) != 0) {
+      if (C.exec != nullptr) {
+        DS_HIP(hipGraphExecDestroy(C.exec));
+        C.exec = nullptr;
+      }
+      hipGraph_t graph;
+      DS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int k = 1; k <= ITERS_PER_GRAPH; ++k) iteration(k, false);
+      const hipError_t ce = hipGetLastError();
+      DS_HIP(hipStreamEndCapture(s, &graph));
+      DS_HIP(ce);
+      const hipError_t ie = hipGraphInstantiate(&C.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        C.exec = nullptr;
+        DS_HIP(ie);
+      }
+      C.key = a;
+    }
+    while (t < prm.max_iter) {
+      DS_HIP(hipGraphLaunch(C.exec, s));
+      t += ITERS_PER_GRAPH;
+      DS_HIP(hipMemcpyAsync(C.host_ctr, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+      DS_HIP(hipStreamSynchronize(s));
+      if (*C.host_ctr >= B) break;
+    }
+  }
+
+  // ---------------------------------------------------------------- output
+  hipLaunchKernelGGL(k_b_counts, dim3(l.Bp), dim3(TB), 0, s, a);
+  hipLaunchKernelGGL(k_b_scatter, dim3((l.K + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a, d_perm,
+                     static_cast<float*>(X), ldx, screened);
+  DS_HIP(hipGetLastError());
+  std::vector<Inst> hs(l.Bp);
+  DS_HIP(hipMemcpyAsync(hs.data(), a.inst, l.Bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
+  DS_HIP(hipStreamSynchronize(s));
+
+  if (stat_on) {
+    double ms_z = 0.0, ms_t = 0.0, ms_s = 0.0;
+    for (auto& p : evz) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_z += m; }
+    for (auto& p : evt) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_t += m; }
+    { float m = 0.f; if (hipEventElapsedTime(&m, su0, su1) == hipSuccess) ms_s = m; }
+    double act = 0.0, sup = 0.0;
+    for (int k = 0; k < l.Bp; ++k) { act += hs[k].act_sum; sup += hs[k].sup_sum; }
+    std::lock_guard<std::mutex> g(S.mu);
+    // algorithmic work: 2 N flops per active (atom, signal) pair for Z, per support entry
+    // of the primal point for Theta; bytes: D once plus the per-signal vectors
+    ds_kernel_stat& z = S.s[DS_STAT_BATCH];
+    z.launches += static_cast<int64_t>(evz.size());
+    z.ms += ms_z;
+    z.flops += 2.0 * l.N * act;
+    z.bytes += static_cast<double>(evz.size()) * (2.0 * l.N * l.K) + 22.0 * act;
+    ds_kernel_stat& th = S.s[DS_STAT_BATCH_THETA];
+    th.launches += static_cast<int64_t>(evt.size());
+    th.ms += ms_t;
+    th.flops += 2.0 * l.N * sup;
+    th.bytes += static_cast<double>(evt.size()) * (2.0 * l.N * l.K + 4.0 * l.N * l.B) + 4.0 * sup;
+    S.s[DS_STAT_SETUP].launches += 1;
+    S.s[DS_STAT_SETUP].ms += ms_s;
+  }
+  if (su0) (void)hipEventDestroy(su0);
+  if (su1) (void)hipEventDestroy(su1);
+
   ds_status worst = DS_OK;
-  for (int64_t b = 0; b < B; ++b) {
-    std::memset(&info[b], 0, sizeof(ds_info));
-    const char* yb = static_cast<const char*>(Y) + b * ldy * 4;
-    char* xb = static_cast<char*>(X) + b * ldx * 4;
-    ds_status e = solve_single(P, yb, lambdas[b], prm, xb, &info[b], stream, ctx.ws, nullptr);
-    if (e < 0) return e;
-    if (e == DS_NOT_CONVERGED) worst = e;
+  bool bad = false;
+  for (int k = 0; k < B; ++k) {
+    const Inst& h = hs[k];
+    ds_info& r = info[perm[k]];
+    std::memset(&r, 0, sizeof r);
+    if (h.status < 0) {
+      bad = true;
+      r.status = DS_EINVAL;
+      continue;
+    }
+    r.iters = h.iter;
+    r.n_active = h.n_active;
+    r.nnz = h.nnz;
+    r.lambda = h.lam;
+    r.lambda_max = h.lam_max;
+    r.primal = h.primal;
+    r.dual = h.dual;
+    r.gap = h.gap;
+    r.radius = h.r_min;
+    r.mu = h.mu;
+    r.L = L;
+    r.radius_slack = h.r_slack + h.marg_slack;
+    const bool ok = h.status == 1 || h.converged;
+    r.status = ok ? DS_OK : DS_NOT_CONVERGED;
+    if (!ok) worst = DS_NOT_CONVERGED;
+  }
+  if (bad) {
+    set_error("observation contains NaN or Inf");
+    return DS_EINVAL;
   }
   return worst;
 }

@@ -1,0 +1,796 @@
+// Batched path: B signals sharing one bfloat16 dictionary, Algorithm 3 with the ISTA /
+// FISTA update of Table 1 and the SAFE / DST3 sphere tests (Lemmas 1, 2).  Every signal
+// keeps its own penalty, dual point, radius and active set.
+//
+// The two products of an iteration are dense GEMMs on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
+//   Theta^T = U^T D^T - Y^T   (B x N, reduction over the K atoms)
+//   Z       = D^T Theta       (K x B, reduction over the N rows; only 32 x 32 tiles
+//                              holding an active (atom, signal) pair are computed)
+// D is exactly bfloat16 (the stored instance).  The FP32 operands U and Theta enter as
+// three bfloat16 parts (hi + mid + lo reproduces the FP32 value), so every product is
+// exact and only the FP32 accumulation rounds.
+//
+// Precision.  The MFMA correlations drive the iteration.  Screening stays safe through a
+// rounding slack on the radius: with e a bound on the accumulation error of max|z|, the
+// dual point v = mu theta is within eps = e / max|z| (relative) of a feasible point, so
+// the sphere radius grows by eps ||v||.  The duality gap that decides convergence is
+// recomputed exactly once the estimate reaches tolerance: an FP64 pass rebuilds
+// theta = D p - y from the support of p and takes ||D_A^T theta||_inf over the active
+// atoms, which gives a feasible dual point and the gap in FP64.
+#pragma once
+#include <cmath>
+
+#include "ds_device.h"
+
+namespace ds {
+namespace batch {
+
+constexpr int BW = 64;   // wave size
+constexpr int TB = 256;  // threads per block
+constexpr int NWB = TB / BW;
+constexpr int MT = 32;   // MFMA tile edge (32 x 32 x 16)
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint4& r) { return __builtin_bit_cast(bf16x8, r); }
+__device__ __forceinline__ uint4 ldg16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t lsb = (u >> 16) & 1u;
+  return static_cast<uint16_t>((u + 0x7fffu + lsb) >> 16);
+}
+__device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+// Three-part split v = hi + mid + lo, exact for normal FP32 values: each remainder is
+// a multiple of ulp(v) and needs at most 8 significant bits by the third part.
+__device__ __forceinline__ void split3(float v, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
+  hi = f32_to_bf16(v);
+  const float r1 = v - bf16f(hi);
+  mid = f32_to_bf16(r1);
+  const float r2 = r1 - bf16f(mid);
+  lo = f32_to_bf16(r2);
+}
+__device__ __forceinline__ uint2 pack4(const uint16_t* v) {
+  return make_uint2(static_cast<uint32_t>(v[0]) | (static_cast<uint32_t>(v[1]) << 16),
+                    static_cast<uint32_t>(v[2]) | (static_cast<uint32_t>(v[3]) << 16));
+}
+
+// done: 0 running, 2 finished in the iteration in flight, 1 finished earlier.
+struct alignas(16) Inst {
+  double lam, lam_max, yy, rho2, alpha, nn, marg_slack, gap_tol_abs, vfac;
+  double tt, ty, omega, zmax, mu, gap, primal, dual;
+  double r_min, r_scr, r_keep, r_prev, r_slack, l_prev;
+  double act_sum, sup_sum;  // sums over iterations of |A_t| and |S_t| (work accounting)
+  int32_t iter, done, status, verify, nnz, n_active, i_star, converged;
+};
+
+struct BArgs {
+  int N, K, B, Np, Kp, Bp;
+  int test, rule, max_iter, splitk, klen;
+  double L, gamma_acc, gamma64;
+  const uint16_t* dcm;  // Kp x Np, atom (column) major, zero padded
+  const uint16_t* drm;  // Np x Kp, row major, zero padded
+  const double* dsc;    // dictionary scalars: [0] max nu_i, [1] max (1 + 1/nu_i)
+  const double* nu;     // Kp atom norms
+  const float* Y;       // Bp x Np observations (slot order, zero padded)
+  float* X;             // Bp x Kp
+  float* U0;            // Bp x Kp: u_{t-1} on odd t
+  float* U1;            // Bp x Kp: u_{t-1} on even t
+  uint16_t* Us;         // 3 x Bp x Kp bfloat16 parts of u_t
+  float* Thp;           // splitk x Bp x Np partial products of D u
+  uint16_t* Ths;        // 3 x Bp x Np bfloat16 parts of theta
+  const float* marg;    // Bp x Kp margins, rounded towards -inf
+  const float* tminm;   // (Kp/32) x Bp smallest margin of each 32-atom tile
+  float* pz;            // (Kp/32) x Bp partial max |z| over active pairs
+  double* pom;          // (Kp/32) x Bp partial Omega(p)
+  int* pact;            // (Kp/32) x Bp active pairs | (non-zeros of p << 8)
+  double* th64;         // Bp x Np exact residual (verification)
+  double* vtt;          // (Np/256 rounded up) x Bp partial ||theta||^2 (verification)
+  double* vty;          // same, theta^T y
+  double* vz;           // (K/256 rounded up) x Bp partial max |d_i^T theta| (verification)
+  Inst* inst;           // Bp
+  int* ndone;           // signals finished
+  int* vcount;          // number of signals flagged for verification this iteration
+  int* vlist;           // Bp flagged slots
+};
+
+constexpr int VY = 16;  // flagged signals verified concurrently (grid y of the passes)
+
+// ============================================================== setup kernels
+// Padded copies of D in both layouts (one 64 x 64 tile per block).
+__global__ __launch_bounds__(TB) void k_b_prep(const uint16_t* __restrict__ D, int64_t ldd, int N,
+                                               int K, int Np, int Kp, uint16_t* __restrict__ dcm,
+                                               uint16_t* __restrict__ drm) {
+  __shared__ uint16_t t[64][66];
+  const int a0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += TB) {
+    const int aa = e / 64, nn = e % 64;
+    const int a = a0 + aa, n = n0 + nn;
+    const uint16_t v = (a < K && n < N) ? D[static_cast<int64_t>(a) * ldd + n] : uint16_t(0);
+    t[aa][nn] = v;
+    dcm[static_cast<int64_t>(a) * Np + n] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += TB) {
+    const int nn = e / 64, aa = e % 64;
+    drm[static_cast<int64_t>(n0 + nn) * Kp + a0 + aa] = t[aa][nn];
+  }
+}
+
+// FP64 atom norms nu_i (one wave per atom).
+__global__ __launch_bounds__(TB) void k_b_norms(const uint16_t* __restrict__ dcm, int Np, int Kp,
+                                                double* __restrict__ nu) {
+  const int lane = threadIdx.x % BW;
+  const int a = blockIdx.x * NWB + threadIdx.x / BW;
+  if (a >= Kp) return;
+  double s = 0.0;
+  for (int n = lane; n < Np; n += BW) {
+    const double d = bf16f(dcm[static_cast<int64_t>(a) * Np + n]);
+    s = fma(d, d, s);
+  }
+  s = wave_sum(s);
+  if (lane == 0) nu[a] = sqrt(s);
+}
+
+// Dictionary scalars: max nu_i and max (1 + 1/nu_i) over non-zero atoms (one block).
+__global__ __launch_bounds__(TB) void k_b_dict_scalars(const double* __restrict__ nu, int K,
+                                                       double* __restrict__ dsc) {
+  __shared__ double sd[NWB];
+  double m = 0.0, kap = 0.0;
+  for (int a = threadIdx.x; a < K; a += TB) {
+    m = fmax(m, nu[a]);
+    if (nu[a] > 0.0) kap = fmax(kap, 1.0 + 1.0 / nu[a]);
+  }
+  m = block_max<double, NWB>(m, sd);
+  kap = block_max<double, NWB>(kap, sd);
+  if (threadIdx.x == 0) {
+    dsc[0] = m;
+    dsc[1] = kap;
+  }
+}
+
+// Observations in slot order: Yp[s][n] = Y[perm[s] * ldy + n] (zero padded).
+__global__ __launch_bounds__(TB) void k_b_load_y(const float* __restrict__ Yin, int64_t ldy,
+                                                 const int* __restrict__ perm, int N, int B,
+                                                 int Np, float* __restrict__ Yp) {
+  const int s = blockIdx.y;
+  const int n = blockIdx.x * TB + threadIdx.x;
+  if (n >= Np) return;
+  float v = 0.f;
+  if (s < B && n < N) v = Yin[static_cast<int64_t>(perm[s]) * ldy + n];
+  Yp[static_cast<int64_t>(s) * Np + n] = v;
+}
+
+// FP64 batched products out[b][a] = d_a^T v_b (exact bfloat16 x float products, FP64
+// accumulation).  Block: 64 atoms x 16 signals; thread: 4 atoms x 1 signal.
+__global__ __launch_bounds__(TB) void k_b_dtv64(const uint16_t* __restrict__ dcm,
+                                                const float* __restrict__ V, int Np, int Kp,
+                                                double* __restrict__ out) {
+  __shared__ double sd[64][33];
+  __shared__ double sv[16][33];
+  const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 16;
+  const int ta = threadIdx.x % 16, tb = threadIdx.x / 16;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int n0 = 0; n0 < Np; n0 += 32) {
+    for (int e = threadIdx.x; e < 64 * 32; e += TB) {
+      const int aa = e / 32, nn = e % 32;
+      sd[aa][nn] = bf16f(dcm[static_cast<int64_t>(a0 + aa) * Np + n0 + nn]);
+    }
+    for (int e = threadIdx.x; e < 16 * 32; e += TB) {
+      const int bb = e / 32, nn = e % 32;
+      sv[bb][nn] = V[static_cast<int64_t>(b0 + bb) * Np + n0 + nn];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int nn = 0; nn < 32; ++nn) {
+      const double v = sv[tb][nn];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] = fma(sd[ta + 16 * k][nn], v, acc[k]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[static_cast<int64_t>(b0 + tb) * Kp + a0 + ta + 16 * k] = acc[k];
+}
+
+// Per-signal setup (one block per slot): ||y||^2, finiteness, lambda_* = max_i |z0_i|
+// with the smallest-index tie break, lambda, the trivial case lambda >= lambda_*, and the
+// DST3 hyperplane n = sign(z0_i*) d_i* (Lemma 2; general atom norms): ||n||^2, n^T y,
+// alpha = (n^T y / lambda - 1) / ||n||^2, rho^2 = alpha^2 ||n||^2.  Writes the column
+// Vn[s] = n used to form D^T n.
+__global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __restrict__ z0,
+                                                    const double* __restrict__ lam_in,
+                                                    int lam_relative, double gap_tol,
+                                                    float* __restrict__ Vn) {
+  __shared__ double sd[NWB];
+  __shared__ int si[NWB];
+  __shared__ double s_best;
+  __shared__ int s_arg;
+  const int s = blockIdx.x, tid = threadIdx.x;
+  Inst* st = a.inst + s;
+  const float* y = a.Y + static_cast<int64_t>(s) * a.Np;
+  if (s >= a.B) {
+    for (int n = tid; n < a.Np; n += TB) Vn[static_cast<int64_t>(s) * a.Np + n] = 0.f;
+    if (tid == 0) {
+      Inst z = {};
+      z.done = 1;
+      z.status = 1;
+      *st = z;
+    }
+    return;
+  }
+  double yy = 0.0;
+  int bad = 0;
+  for (int n = tid; n < a.N; n += TB) {
+    const double v = y[n];
+    if (!isfinite(v)) bad = 1;
+    yy = fma(v, v, yy);
+  }
+  yy = block_sum<double, NWB>(yy, sd);
+  bad = block_sum<int, NWB>(bad, si);
+  const double* z = z0 + static_cast<int64_t>(s) * a.Kp;
+  double best = -1.0;
+  int barg = 0x7fffffff;
+  for (int i = tid; i < a.K; i += TB) {
+    const double v = fabs(z[i]);
+    if (v > best) { best = v; barg = i; }
+  }
+  for (int o = BW / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, BW);
+    const int oa = __shfl_xor(barg, o, BW);
+    if (ob > best || (ob == best && oa < barg)) { best = ob; barg = oa; }
+  }
+  __syncthreads();
+  if (tid % BW == 0) { sd[tid / BW] = best; si[tid / BW] = barg; }
+  __syncthreads();
+  if (tid == 0) {
+    double b = sd[0];
+    int ba = si[0];
+    for (int k = 1; k < NWB; ++k)
+      if (sd[k] > b || (sd[k] == b && si[k] < ba)) { b = sd[k]; ba = si[k]; }
+    s_best = b;
+    s_arg = ba;
+  }
+  __syncthreads();
+  const double lam_max = s_best;
+  const int arg = s_arg;
+  if (!(arg >= 0 && arg < a.K) || !isfinite(lam_max)) bad = 1;
+  const double lam = lam_relative ? lam_in[s] * lam_max : lam_in[s];
+  const bool trivial = !(lam < lam_max);
+  const bool dst3 = a.test == 2 && !trivial && !bad;
+  const double sgn = (!bad && z[arg] < 0.0) ? -1.0 : 1.0;
+  double nn = 0.0, ny = 0.0;
+  for (int n = tid; n < a.Np; n += TB) {
+    float v = 0.f;
+    if (dst3) {
+      v = static_cast<float>(sgn * bf16f(a.dcm[static_cast<int64_t>(arg) * a.Np + n]));
+      nn = fma(static_cast<double>(v), static_cast<double>(v), nn);
+      ny = fma(static_cast<double>(v), static_cast<double>(y[n]), ny);
+    }
+    Vn[static_cast<int64_t>(s) * a.Np + n] = v;
+  }
+  nn = block_sum<double, NWB>(nn, sd);
+  ny = block_sum<double, NWB>(ny, sd);
+  if (tid == 0) {
+    Inst t = {};
+    const double alpha = (dst3 && nn > 0.0) ? (ny / lam - 1.0) / nn : 0.0;
+    t.lam = lam;
+    t.lam_max = lam_max;
+    t.yy = yy;
+    t.alpha = alpha;
+    t.nn = nn;
+    t.rho2 = alpha * alpha * nn;
+    t.gap_tol_abs = gap_tol * yy;
+    t.vfac = 1.0;
+    t.r_min = 1e300;
+    t.r_scr = 1e300;
+    t.r_keep = 1e300;
+    t.r_prev = 1e300;
+    t.l_prev = 1.0;
+    t.i_star = bad ? 0 : arg;
+    t.status = bad ? -1 : (trivial ? 1 : 0);
+    t.done = (bad || trivial) ? 1 : 0;
+    t.converged = t.done;
+    // rounding slack of the FP64 margins (products exact, N-term FP64 sums)
+    const double eps = (a.N + 16) * 0x1p-53;
+    t.marg_slack = eps * a.dsc[1] * (sqrt(yy) / lam + fabs(alpha) * sqrt(nn) + 1.0);
+    *st = t;
+    if (t.done) atomicAdd(a.ndone, 1);
+  }
+}
+
+// Margins m_i = (1 - |d_i^T c|) / nu_i with d_i^T c = z0_i / lambda - alpha d_i^T n
+// (SAFE: alpha = 0), stored in FP32 rounded towards -inf so that m32 > r implies m > r.
+// Zero atoms and padding: +inf (screened from the start); no test: -inf.
+__global__ __launch_bounds__(TB) void k_b_margins(BArgs a, const double* __restrict__ z0,
+                                                  const double* __restrict__ gn,
+                                                  float* __restrict__ marg) {
+  const int s = blockIdx.y;
+  const int i = blockIdx.x * TB + threadIdx.x;
+  if (i >= a.Kp) return;
+  const Inst& st = a.inst[s];
+  const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
+  float m;
+  if (i >= a.K || s >= a.B || st.done) {
+    m = INFINITY;
+  } else if (a.test == 0) {
+    m = -INFINITY;
+  } else {
+    const double nu = a.nu[i];
+    const double ci = z0[o] / st.lam - (a.test == 2 ? st.alpha * gn[o] : 0.0);
+    m = nu > 0.0 ? __double2float_rd((1.0 - fabs(ci)) / nu) : INFINITY;
+  }
+  marg[o] = m;
+}
+
+// Smallest margin of each 32-atom tile: tminm[tile][s].
+__global__ __launch_bounds__(TB) void k_b_tile_min(BArgs a, float* __restrict__ tminm) {
+  const int s = blockIdx.y;
+  const int tile = blockIdx.x * TB + threadIdx.x;
+  if (tile >= a.Kp / MT) return;
+  const float* m = a.marg + static_cast<int64_t>(s) * a.Kp + tile * MT;
+  float v = INFINITY;
+  for (int k = 0; k < MT; ++k) v = fminf(v, m[k]);
+  tminm[static_cast<int64_t>(tile) * a.Bp + s] = v;
+}
+
+// ============================================================== iteration kernels
+// Theta partial products: Thp[ks][s][n] = sum over the atoms of slice ks of u_s[k] D[n][k].
+// Wave tile 32 signals x 32 rows, block 2 x 2 wave tiles, K split in `splitk` slices.
+// Waves whose 32 signals have all finished return at once.
+__global__ __launch_bounds__(TB) void k_b_theta_gemm(BArgs a) {
+  const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+  const int b0 = blockIdx.x * 64 + (wave / 2) * MT;
+  const int n0 = blockIdx.y * 64 + (wave % 2) * MT;
+  const int ks = blockIdx.z;
+  const int kbeg = ks * a.klen, kend = min(kbeg + a.klen, a.Kp);
+  const int bi = b0 + (lane % MT);
+  const bool alive = a.inst[bi].done == 0;
+  if (!__ballot(alive)) return;
+  const int kk = (lane / MT) * 8;
+  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Kp;
+  const uint16_t* u0 = a.Us + static_cast<int64_t>(bi) * a.Kp + kk;
+  const uint16_t* drow = a.drm + static_cast<int64_t>(n0 + (lane % MT)) * a.Kp + kk;
+  f32x16 c;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) c[i] = 0.f;
+#pragma unroll 2
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    const bf16x8 bd = as_bf16x8(ldg16(drow + k0));
+    const bf16x8 p0 = as_bf16x8(ldg16(u0 + k0));
+    const bf16x8 p1 = as_bf16x8(ldg16(u0 + plane + k0));
+    const bf16x8 p2 = as_bf16x8(ldg16(u0 + 2 * plane + k0));
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p0, bd, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p1, bd, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p2, bd, c, 0, 0, 0);
+  }
+  float* out = a.Thp + static_cast<int64_t>(ks) * a.Bp * a.Np;
+  const int n = n0 + (lane % MT);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int b = b0 + 8 * (i / 4) + (lane / MT) * 4 + (i % 4);
+    out[static_cast<int64_t>(b) * a.Np + n] = c[i];
+  }
+}
+
+// theta = sum of the slices - y, its bfloat16 parts, FP64 ||theta||^2 and theta^T y.
+// One block per slot.  Also retires signals that finished in the previous iteration.
+__global__ __launch_bounds__(TB) void k_b_theta_fin(BArgs a) {
+  __shared__ double sd[NWB];
+  const int s = blockIdx.x;
+  if (s == 0 && threadIdx.x == 0) *a.vcount = 0;
+  Inst& st = a.inst[s];
+  const int done = st.done;
+  if (done != 0) {
+    if (done == 2 && threadIdx.x == 0) st.done = 1;
+    return;
+  }
+  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
+  double tt = 0.0, ty = 0.0;
+  for (int n = threadIdx.x; n < a.Np; n += TB) {
+    const int64_t o = static_cast<int64_t>(s) * a.Np + n;
+    float acc = 0.f;
+    for (int k = 0; k < a.splitk; ++k) acc += a.Thp[k * plane + o];
+    const float yv = a.Y[o];
+    const float th = n < a.N ? acc - yv : 0.f;
+    uint16_t h, m, l;
+    split3(th, h, m, l);
+    tt = fma(static_cast<double>(th), static_cast<double>(th), tt);
+    ty = fma(static_cast<double>(th), static_cast<double>(yv), ty);
+    a.Ths[o] = h;
+    a.Ths[plane + o] = m;
+    a.Ths[2 * plane + o] = l;
+  }
+  tt = block_sum<double, NWB>(tt, sd);
+  ty = block_sum<double, NWB>(ty, sd);
+  if (threadIdx.x == 0) {
+    st.tt = tt;
+    st.ty = ty;
+  }
+}
+
+// Z = D^T Theta on the 32 x 32 tiles holding an active pair, fused with the update of
+// Table 1 on the active pairs: x_t = ST(p - z / L, lambda / L) (soft threshold), and for
+// FISTA l_t = (1 + sqrt(1 + 4 l_{t-1}^2)) / 2, u_t = x_t + (l_{t-1} - 1) / l_t (x_t - x_{t-1})
+// (ISTA: u_t = x_t).  p = u_{t-1} is read from Uin, u_t written to Uout and to its
+// bfloat16 parts.  Per (32-atom tile, signal): max |z| and Omega(p) = sum |p_i| over the
+// active pairs.  Wave tile 32 atoms x 32 signals; block 2 x 2 wave tiles.
+__global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
+                                                float* __restrict__ Uout) {
+  const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+  const int a0 = blockIdx.x * 64 + (wave / 2) * MT;
+  const int b0 = blockIdx.y * 64 + (wave % 2) * MT;
+  const int bl = b0 + (lane % MT);  // signal of this lane's accumulator column
+  const int at = a0 / MT;
+  const Inst& sl = a.inst[bl];
+  const bool alive = sl.done == 0;
+  const double r_act = sl.r_keep;  // active pairs: margin <= r_act
+  const int64_t tix = static_cast<int64_t>(at) * a.Bp + bl;
+  const bool tile_on = alive && static_cast<double>(a.tminm[tix]) <= r_act;
+  if (!__ballot(tile_on)) {
+    if (lane < MT) {
+      a.pz[tix] = 0.f;
+      a.pom[tix] = 0.0;
+      a.pact[tix] = 0;
+    }
+    return;
+  }
+  const int kk = (lane / MT) * 8;
+  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
+  const uint16_t* dcol = a.dcm + static_cast<int64_t>(a0 + (lane % MT)) * a.Np + kk;
+  const uint16_t* t0 = a.Ths + static_cast<int64_t>(bl) * a.Np + kk;
+  f32x16 c;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) c[i] = 0.f;
+#pragma unroll 2
+  for (int n0 = 0; n0 < a.Np; n0 += 16) {
+    const bf16x8 ad = as_bf16x8(ldg16(dcol + n0));
+    const bf16x8 h = as_bf16x8(ldg16(t0 + n0));
+    const bf16x8 m = as_bf16x8(ldg16(t0 + plane + n0));
+    const bf16x8 l = as_bf16x8(ldg16(t0 + 2 * plane + n0));
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
+  }
+  // epilogue: lane holds signal bl, atoms a0 + 8 q + (lane / 32) * 4 + e
+  float zm = 0.f;
+  double om = 0.0;
+  int nact = 0, nsup = 0;
+  if (tile_on) {
+    const double invL = 1.0 / a.L, thr = sl.lam / a.L;
+    double beta = 0.0;
+    if (a.rule == 1) {
+      const double lp = sl.l_prev;
+      beta = (lp - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * lp * lp)));
+    }
+    const int64_t uplane = static_cast<int64_t>(a.Bp) * a.Kp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ab = a0 + 8 * q + (lane / MT) * 4;
+      const int64_t o = static_cast<int64_t>(bl) * a.Kp + ab;
+      const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
+      const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
+      bool any = false;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) any |= static_cast<double>(mm[e]) <= r_act;
+      if (!any) continue;
+      const float4 u4 = *reinterpret_cast<const float4*>(Uin + o);
+      const float4 x4 = *reinterpret_cast<const float4*>(a.X + o);
+      float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+      float xx[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (!(static_cast<double>(mm[e]) <= r_act)) continue;
+        const float z = c[4 * q + e];
+        zm = fmaxf(zm, fabsf(z));
+        const double p = uu[e];
+        om += fabs(p);
+        ++nact;
+        nsup += uu[e] != 0.f;
+        const double v = p - static_cast<double>(z) * invL;
+        const double mag = fabs(v) - thr;
+        const double xn = mag > 0.0 ? copysign(mag, v) : 0.0;
+        const double un = xn + beta * (xn - static_cast<double>(xx[e]));
+        xx[e] = static_cast<float>(xn);
+        uu[e] = static_cast<float>(un);
+      }
+      *reinterpret_cast<float4*>(a.X + o) = make_float4(xx[0], xx[1], xx[2], xx[3]);
+      *reinterpret_cast<float4*>(Uout + o) = make_float4(uu[0], uu[1], uu[2], uu[3]);
+      uint16_t h[4], m[4], l[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) split3(uu[e], h[e], m[e], l[e]);
+      *reinterpret_cast<uint2*>(a.Us + o) = pack4(h);
+      *reinterpret_cast<uint2*>(a.Us + uplane + o) = pack4(m);
+      *reinterpret_cast<uint2*>(a.Us + 2 * uplane + o) = pack4(l);
+    }
+  }
+  // the two half-waves hold the same signals on different atoms of the tile
+  zm = fmaxf(zm, __shfl_xor(zm, 32, BW));
+  om += __shfl_xor(om, 32, BW);
+  int cnt = nact | (nsup << 8);
+  cnt += __shfl_xor(cnt, 32, BW);
+  if (lane < MT) {
+    a.pz[tix] = zm;
+    a.pom[tix] = om;
+    a.pact[tix] = cnt;
+  }
+}
+
+// FP64 scalars of iteration t, one wave per slot: dual scaling (Lemma 7) from the MFMA
+// correlations, gap estimate, sphere radius (SAFE: R; DST3: sqrt(R^2 - rho^2)) grown by
+// the accumulation slack, screening threshold for the next iteration.  Flags the signal
+// for the exact gap when the estimate meets tolerance or the budget is spent.
+__global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
+  const int lane = threadIdx.x % BW;
+  const int s = blockIdx.x * NWB + threadIdx.x / BW;
+  if (s >= a.Bp) return;
+  Inst& st = a.inst[s];
+  if (st.done != 0) return;
+  const int ntile = a.Kp / MT;
+  double zm = 0.0, om = 0.0;
+  int nact = 0, nsup = 0;
+  for (int t = lane; t < ntile; t += BW) {
+    const int64_t o = static_cast<int64_t>(t) * a.Bp + s;
+    zm = fmax(zm, static_cast<double>(a.pz[o]));
+    om += a.pom[o];
+    const int c = a.pact[o];
+    nact += c & 0xff;
+    nsup += c >> 8;
+  }
+  zm = wave_max(zm);
+  om = wave_sum(om);
+  nact = wave_sum(nact);
+  nsup = wave_sum(nsup);
+  if (lane != 0) return;
+  const int t = st.iter + 1;
+  const double lam = st.lam, tt = st.tt, ty = st.ty, yy = st.yy, rho2 = st.rho2;
+  const double sb = zm > 0.0 ? 1.0 / zm : 1e300;
+  double mu = 0.0;
+  if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
+  const double primal = 0.5 * tt + lam * om;
+  const double dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
+  // R^2 = ||y/lambda - v||^2 expanded; E bounds its FP64 rounding, eps |mu| ||theta|| the
+  // distance from v to the feasible point of the exact correlations
+  const double a1 = yy / (lam * lam), a2 = 2.0 * mu * ty / lam, a3 = mu * mu * tt;
+  const double rr = a.test == 2 ? rho2 : 0.0;
+  const double R2 = a1 - a2 + a3;
+  const double E = (a.N + 16) * 0x1p-53 * (a1 + fabs(a2) + a3 + rr);
+  const double nth = sqrt(tt);
+  const double eps = zm > 0.0 ? a.gamma_acc * a.dsc[0] * nth / zm : 0.0;
+  const double Rup = sqrt(fmax(R2 + E, 0.0)) + eps * fabs(mu) * nth;
+  double r = 1e300, r_safe = 1e300;
+  if (a.test != 0) {
+    r = sqrt(fmax(R2 - rr, 0.0));
+    r_safe = sqrt(fmax(Rup * Rup - rr + E, 0.0));
+  }
+  st.iter = t;
+  st.act_sum += nact;
+  st.sup_sum += nsup;
+  st.zmax = zm;
+  st.omega = om;
+  st.mu = mu;
+  st.gap = primal - dual;
+  st.primal = primal;
+  st.dual = dual;
+  st.r_min = fmin(st.r_min, r);
+  st.r_prev = st.r_keep;
+  if (a.rule == 1) st.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.l_prev * st.l_prev));
+  if (r_safe < st.r_scr) {
+    st.r_scr = r_safe;
+    st.r_slack = r_safe - r;
+  }
+  st.r_keep = fmin(st.r_prev, st.r_scr + st.marg_slack);
+  const bool flag = (st.gap_tol_abs > 0.0 && primal - dual <= st.gap_tol_abs * st.vfac) || t >= a.max_iter;
+  st.verify = flag ? 1 : 0;
+  if (flag) a.vlist[atomicAdd(a.vcount, 1)] = s;
+}
+
+// Verification 1: exact residual theta = D p - y in FP64 for the flagged signals, with
+// p = u_{t-1} (the point this iteration's theta was evaluated at).  Block: 256 rows of
+// one signal; the support of p is compacted through LDS 1024 atoms at a time.
+__device__ __forceinline__ void vtheta_one(const BArgs& a, const float* __restrict__ P, int s) {
+  __shared__ int sidx[TB * 4];
+  __shared__ float sval[TB * 4];
+  __shared__ int scan[NWB];
+  __shared__ double sd[NWB];
+  const int n = blockIdx.x * TB + threadIdx.x;
+  const float* p = P + static_cast<int64_t>(s) * a.Kp;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < a.Kp; k0 += TB * 4) {
+    const int k = k0 + threadIdx.x * 4;
+    float4 p4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < a.Kp) p4 = *reinterpret_cast<const float4*>(p + k);
+    const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cnt += pv[e] != 0.f;
+    int total;
+    int pos = block_exclusive_scan<NWB>(cnt, scan, &total);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (pv[e] != 0.f) { sidx[pos] = k + e; sval[pos] = pv[e]; ++pos; }
+    __syncthreads();
+    if (n < a.Np) {
+      for (int j = 0; j < total; ++j)
+        acc = fma(static_cast<double>(bf16f(a.dcm[static_cast<int64_t>(sidx[j]) * a.Np + n])),
+                  static_cast<double>(sval[j]), acc);
+    }
+    __syncthreads();
+  }
+  double th = 0.0, yv = 0.0;
+  if (n < a.Np) {
+    yv = a.Y[static_cast<int64_t>(s) * a.Np + n];
+    th = n < a.N ? acc - yv : 0.0;
+    a.th64[static_cast<int64_t>(s) * a.Np + n] = th;
+  }
+  const double tt = block_sum<double, NWB>(th * th, sd);
+  const double ty = block_sum<double, NWB>(th * yv, sd);
+  if (threadIdx.x == 0) {
+    a.vtt[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = tt;
+    a.vty[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = ty;
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_b_vtheta(BArgs a, const float* __restrict__ P) {
+  const int nflag = *a.vcount;
+  for (int j = blockIdx.y; j < nflag; j += VY) vtheta_one(a, P, a.vlist[j]);
+}
+
+// Verification 2: FP64 max over the atoms active in this iteration of |d_i^T theta|.
+// Block: 256 atoms of one flagged signal; one wave per atom, 8 rows per lane per step.
+__device__ __forceinline__ void vcorr_one(const BArgs& a, int s) {
+  __shared__ double sd[NWB];
+  const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+  const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
+  const float* mg = a.marg + static_cast<int64_t>(s) * a.Kp;
+  const double r_act = a.inst[s].r_prev;
+  double zm = 0.0;
+  const int c0 = blockIdx.x * 256;
+  const int c1 = min(c0 + 256, a.K);
+  for (int i = c0 + wave; i < c1; i += NWB) {
+    if (!(static_cast<double>(mg[i]) <= r_act)) continue;
+    const uint16_t* col = a.dcm + static_cast<int64_t>(i) * a.Np;
+    double acc = 0.0;
+    for (int n = lane * 8; n < a.Np; n += BW * 8) {
+      const uint4 d = ldg16(col + n);
+      const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double2 t2 = *reinterpret_cast<const double2*>(th + n + 2 * e);
+        acc = fma(static_cast<double>(__uint_as_float(w[e] << 16)), t2.x, acc);
+        acc = fma(static_cast<double>(__uint_as_float(w[e] & 0xffff0000u)), t2.y, acc);
+      }
+    }
+    acc = wave_sum(acc);
+    zm = fmax(zm, fabs(acc));
+  }
+  zm = block_max<double, NWB>(zm, sd);
+  if (threadIdx.x == 0) a.vz[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = zm;
+}
+
+__global__ __launch_bounds__(TB) void k_b_vcorr(BArgs a) {
+  const int nflag = *a.vcount;
+  for (int j = blockIdx.y; j < nflag; j += VY) vcorr_one(a, a.vlist[j]);
+}
+
+// Verification 3 (one wave per slot): the exact gap at the feasible dual point
+// v = mu theta, mu = clip(theta^T y / (lambda ||theta||^2), +-1/zs) with zs the exact
+// maximum plus the FP64 rounding bound of that pass (Lemma 7).  Finishes the signal when
+// the gap meets tolerance or the iteration budget is spent; otherwise the next check
+// waits for a smaller estimate.
+__global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
+  const int lane = threadIdx.x % BW;
+  const int s = blockIdx.x * NWB + threadIdx.x / BW;
+  if (s >= a.Bp) return;
+  Inst& st = a.inst[s];
+  if (st.done != 0 || !st.verify) return;
+  const int nrc = (a.Np + TB - 1) / TB, nac = (a.K + 255) / 256;
+  double tt = 0.0, ty = 0.0, zm = 0.0;
+  for (int c = lane; c < nrc; c += BW) {
+    tt += a.vtt[static_cast<int64_t>(c) * a.Bp + s];
+    ty += a.vty[static_cast<int64_t>(c) * a.Bp + s];
+  }
+  for (int c = lane; c < nac; c += BW) zm = fmax(zm, a.vz[static_cast<int64_t>(c) * a.Bp + s]);
+  tt = wave_sum(tt);
+  ty = wave_sum(ty);
+  zm = wave_max(zm);
+  if (lane != 0) return;
+  const double lam = st.lam;
+  const double zs = zm + a.gamma64 * a.dsc[0] * sqrt(tt);
+  const double sb = zs > 0.0 ? 1.0 / zs : 1e300;
+  double mu = 0.0;
+  if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
+  const double primal = 0.5 * tt + lam * st.omega;
+  const double dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
+  const double gap = primal - dual;
+  st.tt = tt;
+  st.ty = ty;
+  st.zmax = zm;
+  st.mu = mu;
+  st.primal = primal;
+  st.dual = dual;
+  st.gap = gap;
+  st.verify = 0;
+  const bool ok = st.gap_tol_abs > 0.0 && gap <= st.gap_tol_abs;
+  if (ok || st.iter >= a.max_iter) {
+    st.converged = (ok || st.gap_tol_abs <= 0.0) ? 1 : 0;
+    st.done = 2;
+    atomicAdd(a.ndone, 1);
+  } else {
+    st.vfac *= 0.5;
+  }
+}
+
+// Screening (the test of Algorithm 3 for the sphere tests): the pairs with
+// r_keep < margin <= r_prev leave the active set; their x, u (both buffers) and the
+// bfloat16 parts of u are cleared.  Signals that finished this iteration keep x_t.
+// Thread: 4 consecutive atoms of one signal.
+__global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
+  const int s = blockIdx.y;
+  const Inst& st = a.inst[s];
+  if (st.done != 0 || !(st.r_keep < st.r_prev)) return;
+  const int i4 = (blockIdx.x * TB + threadIdx.x) * 4;
+  if (i4 >= a.Kp) return;
+  const double rk = st.r_keep, rp = st.r_prev;
+  if (!(static_cast<double>(a.tminm[static_cast<int64_t>(i4 / MT) * a.Bp + s]) <= rp)) return;
+  const int64_t o = static_cast<int64_t>(s) * a.Kp + i4;
+  const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
+  const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
+  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Kp;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double m = mm[e];
+    if (m > rk && m <= rp) {
+      a.X[o + e] = 0.f;
+      a.U0[o + e] = 0.f;
+      a.U1[o + e] = 0.f;
+      a.Us[o + e] = 0;
+      a.Us[plane + o + e] = 0;
+      a.Us[2 * plane + o + e] = 0;
+    }
+  }
+}
+
+// ============================================================== output
+// Per-slot counts for the report: non-zeros of x and atoms active in the last iteration.
+__global__ __launch_bounds__(TB) void k_b_counts(BArgs a) {
+  __shared__ int si[NWB];
+  const int s = blockIdx.x;
+  Inst& st = a.inst[s];
+  const bool trivial = st.status != 0;
+  int nz = 0, na = 0;
+  for (int i = threadIdx.x; i < a.K; i += TB) {
+    const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
+    nz += a.X[o] != 0.f;
+    na += static_cast<double>(a.marg[o]) <= st.r_prev;
+  }
+  nz = block_sum<int, NWB>(nz, si);
+  na = block_sum<int, NWB>(na, si);
+  if (threadIdx.x == 0) {
+    st.nnz = trivial ? 0 : nz;
+    st.n_active = trivial ? 0 : na;
+  }
+}
+
+// X_out[perm[s] * ldx + i] = X[s][i]; optional screened mask (1 = screened) with leading
+// dimension K.
+__global__ __launch_bounds__(TB) void k_b_scatter(BArgs a, const int* __restrict__ perm,
+                                                  float* __restrict__ Xout, int64_t ldx,
+                                                  uint8_t* __restrict__ scr) {
+  const int s = blockIdx.y;
+  const int i = blockIdx.x * TB + threadIdx.x;
+  if (s >= a.B || i >= a.K) return;
+  const Inst& st = a.inst[s];
+  const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
+  const int b = perm[s];
+  Xout[static_cast<int64_t>(b) * ldx + i] = st.status != 0 ? 0.f : a.X[o];
+  if (scr != nullptr)
+    scr[static_cast<int64_t>(b) * a.K + i] =
+        (st.status != 0 || !(static_cast<double>(a.marg[o]) <= st.r_prev)) ? 1 : 0;
+}
+
+}  // namespace batch
+}  // namespace ds

@@ -76,7 +76,7 @@ ds_status spectral_norm_impl(const ds_problem& P, int iters, double* L, hipStrea
 // Batched MFMA path (bfloat16 storage, B > 1).
 ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
                              const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
-                             ds_info* info, hipStream_t stream);
+                             ds_info* info, uint8_t* screened, hipStream_t stream);
 
 size_t dtype_size(ds_dtype t);
 
