@@ -2,22 +2,24 @@
 // FISTA update of Table 1 and the SAFE / DST3 sphere tests (Lemmas 1, 2).  Every signal
 // keeps its own penalty, dual point, radius and active set.
 //
-// The two products of an iteration are dense GEMMs on the matrix cores
-// (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
-//   Theta^T = U^T D^T - Y^T   (B x N, reduction over the K atoms)
-//   Z       = D^T Theta       (K x B, reduction over the N rows; only 32 x 32 tiles
-//                              holding an active (atom, signal) pair are computed)
-// D is exactly bfloat16 (the stored instance).  The FP32 operands U and Theta enter as
-// three bfloat16 parts (hi + mid + lo reproduces the FP32 value), so every product is
-// exact and only the FP32 accumulation rounds.
+// Per iteration:
+//   theta = D_S p - y   sparse: each signal gathers the columns of its support S (the
+//                       non-zeros of p), FP64 accumulation of exact bfloat16 x FP32
+//                       products, so theta is exact up to FP64 rounding;
+//   Z = D^T Theta       dense GEMM on the matrix cores (v_mfma_f32_32x32x16_bf16, FP32
+//                       accumulation) over the 32 x 32 (atom, signal) tiles that hold an
+//                       active pair.  theta enters as three bfloat16 parts (hi + mid + lo
+//                       reproduces its FP32 rounding), so every product is exact;
+//   the update of Table 1 in the GEMM epilogue, the FP64 scalars per signal, and the
+//   screening of the pairs whose margin passed the new radius.
 //
-// Precision.  The MFMA correlations drive the iteration.  Screening stays safe through a
-// rounding slack on the radius: with e a bound on the accumulation error of max|z|, the
-// dual point v = mu theta is within eps = e / max|z| (relative) of a feasible point, so
-// the sphere radius grows by eps ||v||.  The duality gap that decides convergence is
-// recomputed exactly once the estimate reaches tolerance: an FP64 pass rebuilds
-// theta = D p - y from the support of p and takes ||D_A^T theta||_inf over the active
-// atoms, which gives a feasible dual point and the gap in FP64.
+// Precision.  ||theta||^2, theta^T y and Omega(p) are exact FP64 sums, so the primal
+// value is exact.  max|z| comes from the MFMA correlations of the FP32 rounding of theta;
+// with e a bound on their distance to the exact correlations, the dual point
+// v = mu theta is within eps = e / max|z| (relative) of a feasible point, and the sphere
+// radius grows by eps ||v||: screening stays safe.  The gap that ends a solve is
+// recomputed once its estimate meets tolerance, from ||D_A^T theta||_inf evaluated in
+// FP64, which gives a feasible dual point and the gap in FP64.
 #pragma once
 #include <cmath>
 
@@ -53,14 +55,10 @@ __device__ __forceinline__ void split3(float v, uint16_t& hi, uint16_t& mid, uin
   const float r2 = r1 - bf16f(mid);
   lo = f32_to_bf16(r2);
 }
-__device__ __forceinline__ uint2 pack4(const uint16_t* v) {
-  return make_uint2(static_cast<uint32_t>(v[0]) | (static_cast<uint32_t>(v[1]) << 16),
-                    static_cast<uint32_t>(v[2]) | (static_cast<uint32_t>(v[3]) << 16));
-}
 
 // done: 0 running, 2 finished in the iteration in flight, 1 finished earlier.
 struct alignas(16) Inst {
-  double lam, lam_max, yy, rho2, alpha, nn, marg_slack, gap_tol_abs, vfac;
+  double lam, lam_max, yy, rho2, alpha, nn, marg_slack, gap_tol_abs;
   double tt, ty, omega, zmax, mu, gap, primal, dual;
   double r_min, r_scr, r_keep, r_prev, r_slack, l_prev;
   double act_sum, sup_sum;  // sums over iterations of |A_t| and |S_t| (work accounting)
@@ -68,28 +66,26 @@ struct alignas(16) Inst {
 };
 
 struct BArgs {
-  int N, K, B, Np, Kp, Bp;
-  int test, rule, max_iter, splitk, klen;
+  int N, K, B, Np, Kp, Bp, nrb;
+  int test, rule, max_iter;
   double L, gamma_acc, gamma64;
   const uint16_t* dcm;  // Kp x Np, atom (column) major, zero padded
-  const uint16_t* drm;  // Np x Kp, row major, zero padded
   const double* dsc;    // dictionary scalars: [0] max nu_i, [1] max (1 + 1/nu_i)
   const double* nu;     // Kp atom norms
   const float* Y;       // Bp x Np observations (slot order, zero padded)
   float* X;             // Bp x Kp
   float* U0;            // Bp x Kp: u_{t-1} on odd t
   float* U1;            // Bp x Kp: u_{t-1} on even t
-  uint16_t* Us;         // 3 x Bp x Kp bfloat16 parts of u_t
-  float* Thp;           // splitk x Bp x Np partial products of D u
+  uint32_t* umask;      // (Kp/32) x Bp non-zero bits of u_t per 32-atom tile
   uint16_t* Ths;        // 3 x Bp x Np bfloat16 parts of theta
+  double* th64;         // Bp x Np theta in FP64
+  double* ptt;          // nrb x Bp partial ||theta||^2
+  double* pty;          // nrb x Bp partial theta^T y
   const float* marg;    // Bp x Kp margins, rounded towards -inf
   const float* tminm;   // (Kp/32) x Bp smallest margin of each 32-atom tile
   float* pz;            // (Kp/32) x Bp partial max |z| over active pairs
   double* pom;          // (Kp/32) x Bp partial Omega(p)
   int* pact;            // (Kp/32) x Bp active pairs | (non-zeros of p << 8)
-  double* th64;         // Bp x Np exact residual (verification)
-  double* vtt;          // (Np/256 rounded up) x Bp partial ||theta||^2 (verification)
-  double* vty;          // same, theta^T y
   double* vz;           // (K/256 rounded up) x Bp partial max |d_i^T theta| (verification)
   Inst* inst;           // Bp
   int* ndone;           // signals finished
@@ -97,27 +93,17 @@ struct BArgs {
   int* vlist;           // Bp flagged slots
 };
 
-constexpr int VY = 16;  // flagged signals verified concurrently (grid y of the passes)
+constexpr int VY = 16;          // flagged signals verified concurrently (grid y of the pass)
+constexpr double VWIN = 1.25;   // estimate / tolerance ratio below which the gap is checked
 
 // ============================================================== setup kernels
-// Padded copies of D in both layouts (one 64 x 64 tile per block).
+// Padded atom-major copy of D: dcm[a][n] (zeros beyond N and K).
 __global__ __launch_bounds__(TB) void k_b_prep(const uint16_t* __restrict__ D, int64_t ldd, int N,
-                                               int K, int Np, int Kp, uint16_t* __restrict__ dcm,
-                                               uint16_t* __restrict__ drm) {
-  __shared__ uint16_t t[64][66];
-  const int a0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += TB) {
-    const int aa = e / 64, nn = e % 64;
-    const int a = a0 + aa, n = n0 + nn;
-    const uint16_t v = (a < K && n < N) ? D[static_cast<int64_t>(a) * ldd + n] : uint16_t(0);
-    t[aa][nn] = v;
-    dcm[static_cast<int64_t>(a) * Np + n] = v;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 64 * 64; e += TB) {
-    const int nn = e / 64, aa = e % 64;
-    drm[static_cast<int64_t>(n0 + nn) * Kp + a0 + aa] = t[aa][nn];
-  }
+                                               int K, int Np, uint16_t* __restrict__ dcm) {
+  const int a = blockIdx.x;
+  const int n = blockIdx.y * TB + threadIdx.x;
+  if (n >= Np) return;
+  dcm[static_cast<int64_t>(a) * Np + n] = (a < K && n < N) ? D[static_cast<int64_t>(a) * ldd + n] : uint16_t(0);
 }
 
 // FP64 atom norms nu_i (one wave per atom).
@@ -284,7 +270,6 @@ __global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __res
     t.nn = nn;
     t.rho2 = alpha * alpha * nn;
     t.gap_tol_abs = gap_tol * yy;
-    t.vfac = 1.0;
     t.r_min = 1e300;
     t.r_scr = 1e300;
     t.r_keep = 1e300;
@@ -338,86 +323,110 @@ __global__ __launch_bounds__(TB) void k_b_tile_min(BArgs a, float* __restrict__ 
 }
 
 // ============================================================== iteration kernels
-// Theta partial products: Thp[ks][s][n] = sum over the atoms of slice ks of u_s[k] D[n][k].
-// Wave tile 32 signals x 32 rows, block 2 x 2 wave tiles, K split in `splitk` slices.
-// Waves whose 32 signals have all finished return at once.
-__global__ __launch_bounds__(TB) void k_b_theta_gemm(BArgs a) {
-  const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
-  const int b0 = blockIdx.x * 64 + (wave / 2) * MT;
-  const int n0 = blockIdx.y * 64 + (wave % 2) * MT;
-  const int ks = blockIdx.z;
-  const int kbeg = ks * a.klen, kend = min(kbeg + a.klen, a.Kp);
-  const int bi = b0 + (lane % MT);
-  const bool alive = a.inst[bi].done == 0;
-  if (!__ballot(alive)) return;
-  const int kk = (lane / MT) * 8;
-  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Kp;
-  const uint16_t* u0 = a.Us + static_cast<int64_t>(bi) * a.Kp + kk;
-  const uint16_t* drow = a.drm + static_cast<int64_t>(n0 + (lane % MT)) * a.Kp + kk;
-  f32x16 c;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) c[i] = 0.f;
-#pragma unroll 2
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    const bf16x8 bd = as_bf16x8(ldg16(drow + k0));
-    const bf16x8 p0 = as_bf16x8(ldg16(u0 + k0));
-    const bf16x8 p1 = as_bf16x8(ldg16(u0 + plane + k0));
-    const bf16x8 p2 = as_bf16x8(ldg16(u0 + 2 * plane + k0));
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p0, bd, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p1, bd, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p2, bd, c, 0, 0, 0);
-  }
-  float* out = a.Thp + static_cast<int64_t>(ks) * a.Bp * a.Np;
-  const int n = n0 + (lane % MT);
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int b = b0 + 8 * (i / 4) + (lane / MT) * 4 + (i % 4);
-    out[static_cast<int64_t>(b) * a.Np + n] = c[i];
-  }
-}
+constexpr int TR = 512;  // rows of theta per block (64 lanes x 8 rows)
+constexpr int LW = 64;   // mask words (32 atoms each) per support-list chunk
 
-// theta = sum of the slices - y, its bfloat16 parts, FP64 ||theta||^2 and theta^T y.
-// One block per slot.  Also retires signals that finished in the previous iteration.
-__global__ __launch_bounds__(TB) void k_b_theta_fin(BArgs a) {
+// theta = D_S p - y for every running signal, S the support of p = u_{t-1} (from the
+// non-zero bits the previous update left), FP64 accumulation; writes theta in FP64, the
+// bfloat16 parts of its FP32 rounding, and per-block FP64 ||theta||^2 and theta^T y.
+// Block: 512 rows of one signal; its four waves split the support list and are summed in
+// a fixed order.  Also retires the signals finished in the previous iteration and clears
+// the verification list.
+__global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict__ Uin) {
+  __shared__ int sidx[LW * MT];
+  __shared__ float sval[LW * MT];
+  __shared__ int s_cnt;
+  __shared__ double red[NWB][TR + 8];
   __shared__ double sd[NWB];
-  const int s = blockIdx.x;
-  if (s == 0 && threadIdx.x == 0) *a.vcount = 0;
+  const int s = blockIdx.y;
+  if (blockIdx.x == 0 && s == 0 && threadIdx.x == 0) *a.vcount = 0;
   Inst& st = a.inst[s];
   const int done = st.done;
   if (done != 0) {
-    if (done == 2 && threadIdx.x == 0) st.done = 1;
+    if (done == 2 && blockIdx.x == 0 && threadIdx.x == 0) st.done = 1;
     return;
   }
+  const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+  const int nl = blockIdx.x * TR + lane * 8;  // this lane's 8 rows
+  const bool rows_ok = nl < a.Np;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int nw = a.Kp / MT;
+  const float* u = Uin + static_cast<int64_t>(s) * a.Kp;
+  for (int w0 = 0; w0 < nw; w0 += LW) {
+    if (wave == 0) {
+      const int w = w0 + lane;
+      uint32_t m = w < nw ? a.umask[static_cast<int64_t>(w) * a.Bp + s] : 0u;
+      const int c = __popc(m);
+      int incl = c;
+#pragma unroll
+      for (int o = 1; o < BW; o <<= 1) {
+        const int v = __shfl_up(incl, o, BW);
+        if (lane >= o) incl += v;
+      }
+      int pos = incl - c;
+      while (m != 0u) {
+        const int b = __ffs(m) - 1;
+        m &= m - 1u;
+        const int at = w * MT + b;
+        sidx[pos] = at;
+        sval[pos] = u[at];
+        ++pos;
+      }
+      if (lane == BW - 1) s_cnt = incl;
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    if (rows_ok) {
+#pragma unroll 2
+      for (int j = wave; j < cnt; j += NWB) {
+        const double uv = sval[j];
+        const uint4 d = ldg16(a.dcm + static_cast<int64_t>(sidx[j]) * a.Np + nl);
+        const uint32_t wd[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc[2 * e] = fma(static_cast<double>(__uint_as_float(wd[e] << 16)), uv, acc[2 * e]);
+          acc[2 * e + 1] = fma(static_cast<double>(__uint_as_float(wd[e] & 0xffff0000u)), uv, acc[2 * e + 1]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) red[wave][lane * 8 + k] = acc[k];
+  __syncthreads();
   const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
   double tt = 0.0, ty = 0.0;
-  for (int n = threadIdx.x; n < a.Np; n += TB) {
+  for (int r = threadIdx.x; r < TR; r += TB) {
+    const int n = blockIdx.x * TR + r;
+    if (n >= a.Np) break;
     const int64_t o = static_cast<int64_t>(s) * a.Np + n;
-    float acc = 0.f;
-    for (int k = 0; k < a.splitk; ++k) acc += a.Thp[k * plane + o];
-    const float yv = a.Y[o];
-    const float th = n < a.N ? acc - yv : 0.f;
+    const double v = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
+    const double yv = a.Y[o];
+    const double th = n < a.N ? v - yv : 0.0;
+    a.th64[o] = th;
     uint16_t h, m, l;
-    split3(th, h, m, l);
-    tt = fma(static_cast<double>(th), static_cast<double>(th), tt);
-    ty = fma(static_cast<double>(th), static_cast<double>(yv), ty);
+    split3(static_cast<float>(th), h, m, l);
     a.Ths[o] = h;
     a.Ths[plane + o] = m;
     a.Ths[2 * plane + o] = l;
+    tt = fma(th, th, tt);
+    ty = fma(th, yv, ty);
   }
   tt = block_sum<double, NWB>(tt, sd);
   ty = block_sum<double, NWB>(ty, sd);
   if (threadIdx.x == 0) {
-    st.tt = tt;
-    st.ty = ty;
+    a.ptt[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = tt;
+    a.pty[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = ty;
   }
 }
 
 // Z = D^T Theta on the 32 x 32 tiles holding an active pair, fused with the update of
 // Table 1 on the active pairs: x_t = ST(p - z / L, lambda / L) (soft threshold), and for
 // FISTA l_t = (1 + sqrt(1 + 4 l_{t-1}^2)) / 2, u_t = x_t + (l_{t-1} - 1) / l_t (x_t - x_{t-1})
-// (ISTA: u_t = x_t).  p = u_{t-1} is read from Uin, u_t written to Uout and to its
-// bfloat16 parts.  Per (32-atom tile, signal): max |z| and Omega(p) = sum |p_i| over the
-// active pairs.  Wave tile 32 atoms x 32 signals; block 2 x 2 wave tiles.
+// (ISTA: u_t = x_t).  p = u_{t-1} is read from Uin, u_t written to Uout, and the
+// non-zero bits of u_t per 32-atom tile to umask.  Per (32-atom tile, signal): max |z|
+// and Omega(p) = sum |p_i| over the active pairs, and the pair counts.  Wave tile 32
+// atoms x 32 signals; block 2 x 2 wave tiles.
 __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
                                                 float* __restrict__ Uout) {
   const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
@@ -435,6 +444,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       a.pz[tix] = 0.f;
       a.pom[tix] = 0.0;
       a.pact[tix] = 0;
+      a.umask[tix] = 0u;
     }
     return;
   }
@@ -459,6 +469,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
   float zm = 0.f;
   double om = 0.0;
   int nact = 0, nsup = 0;
+  uint32_t bits = 0u;
   if (tile_on) {
     const double invL = 1.0 / a.L, thr = sl.lam / a.L;
     double beta = 0.0;
@@ -466,7 +477,6 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       const double lp = sl.l_prev;
       beta = (lp - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * lp * lp)));
     }
-    const int64_t uplane = static_cast<int64_t>(a.Bp) * a.Kp;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ab = a0 + 8 * q + (lane / MT) * 4;
@@ -499,12 +509,9 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       }
       *reinterpret_cast<float4*>(a.X + o) = make_float4(xx[0], xx[1], xx[2], xx[3]);
       *reinterpret_cast<float4*>(Uout + o) = make_float4(uu[0], uu[1], uu[2], uu[3]);
-      uint16_t h[4], m[4], l[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) split3(uu[e], h[e], m[e], l[e]);
-      *reinterpret_cast<uint2*>(a.Us + o) = pack4(h);
-      *reinterpret_cast<uint2*>(a.Us + uplane + o) = pack4(m);
-      *reinterpret_cast<uint2*>(a.Us + 2 * uplane + o) = pack4(l);
+      for (int e = 0; e < 4; ++e)
+        if (uu[e] != 0.f) bits |= 1u << (8 * q + (lane / MT) * 4 + e);
     }
   }
   // the two half-waves hold the same signals on different atoms of the tile
@@ -512,10 +519,12 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
   om += __shfl_xor(om, 32, BW);
   int cnt = nact | (nsup << 8);
   cnt += __shfl_xor(cnt, 32, BW);
+  bits |= __shfl_xor(bits, 32, BW);
   if (lane < MT) {
     a.pz[tix] = zm;
     a.pom[tix] = om;
     a.pact[tix] = cnt;
+    a.umask[tix] = bits;
   }
 }
 
@@ -540,13 +549,20 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     nact += c & 0xff;
     nsup += c >> 8;
   }
+  double tt = 0.0, ty = 0.0;
+  for (int c = lane; c < a.nrb; c += BW) {
+    tt += a.ptt[static_cast<int64_t>(c) * a.Bp + s];
+    ty += a.pty[static_cast<int64_t>(c) * a.Bp + s];
+  }
   zm = wave_max(zm);
   om = wave_sum(om);
+  tt = wave_sum(tt);
+  ty = wave_sum(ty);
   nact = wave_sum(nact);
   nsup = wave_sum(nsup);
   if (lane != 0) return;
   const int t = st.iter + 1;
-  const double lam = st.lam, tt = st.tt, ty = st.ty, yy = st.yy, rho2 = st.rho2;
+  const double lam = st.lam, yy = st.yy, rho2 = st.rho2;
   const double sb = zm > 0.0 ? 1.0 / zm : 1e300;
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
@@ -567,6 +583,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     r_safe = sqrt(fmax(Rup * Rup - rr + E, 0.0));
   }
   st.iter = t;
+  st.tt = tt;
+  st.ty = ty;
   st.act_sum += nact;
   st.sup_sum += nsup;
   st.zmax = zm;
@@ -583,134 +601,77 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     st.r_slack = r_safe - r;
   }
   st.r_keep = fmin(st.r_prev, st.r_scr + st.marg_slack);
-  const bool flag = (st.gap_tol_abs > 0.0 && primal - dual <= st.gap_tol_abs * st.vfac) || t >= a.max_iter;
+  // the estimate differs from the exact gap only through max|z|: every iteration whose
+  // estimate is within VWIN of tolerance is checked, so the solve ends at the first
+  // iteration whose exact gap meets it
+  const bool flag = (st.gap_tol_abs > 0.0 && primal - dual <= VWIN * st.gap_tol_abs) || t >= a.max_iter;
   st.verify = flag ? 1 : 0;
   if (flag) a.vlist[atomicAdd(a.vcount, 1)] = s;
 }
 
-// Verification 1: exact residual theta = D p - y in FP64 for the flagged signals, with
-// p = u_{t-1} (the point this iteration's theta was evaluated at).  Block: 256 rows of
-// one signal; the support of p is compacted through LDS 1024 atoms at a time.
-__device__ __forceinline__ void vtheta_one(const BArgs& a, const float* __restrict__ P, int s) {
-  __shared__ int sidx[TB * 4];
-  __shared__ float sval[TB * 4];
-  __shared__ int scan[NWB];
-  __shared__ double sd[NWB];
-  const int n = blockIdx.x * TB + threadIdx.x;
-  const float* p = P + static_cast<int64_t>(s) * a.Kp;
-  double acc = 0.0;
-  for (int k0 = 0; k0 < a.Kp; k0 += TB * 4) {
-    const int k = k0 + threadIdx.x * 4;
-    float4 p4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (k < a.Kp) p4 = *reinterpret_cast<const float4*>(p + k);
-    const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
-    int cnt = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) cnt += pv[e] != 0.f;
-    int total;
-    int pos = block_exclusive_scan<NWB>(cnt, scan, &total);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (pv[e] != 0.f) { sidx[pos] = k + e; sval[pos] = pv[e]; ++pos; }
-    __syncthreads();
-    if (n < a.Np) {
-      for (int j = 0; j < total; ++j)
-        acc = fma(static_cast<double>(bf16f(a.dcm[static_cast<int64_t>(sidx[j]) * a.Np + n])),
-                  static_cast<double>(sval[j]), acc);
-    }
-    __syncthreads();
-  }
-  double th = 0.0, yv = 0.0;
-  if (n < a.Np) {
-    yv = a.Y[static_cast<int64_t>(s) * a.Np + n];
-    th = n < a.N ? acc - yv : 0.0;
-    a.th64[static_cast<int64_t>(s) * a.Np + n] = th;
-  }
-  const double tt = block_sum<double, NWB>(th * th, sd);
-  const double ty = block_sum<double, NWB>(th * yv, sd);
-  if (threadIdx.x == 0) {
-    a.vtt[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = tt;
-    a.vty[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = ty;
-  }
-}
+constexpr int VCH = 2048;  // theta rows staged in LDS per pass of the verification
 
-__global__ __launch_bounds__(TB) void k_b_vtheta(BArgs a, const float* __restrict__ P) {
-  const int nflag = *a.vcount;
-  for (int j = blockIdx.y; j < nflag; j += VY) vtheta_one(a, P, a.vlist[j]);
-}
-
-// Verification 2: FP64 max over the atoms active in this iteration of |d_i^T theta|.
-// Block: 256 atoms of one flagged signal; one wave per atom, 8 rows per lane per step.
-__device__ __forceinline__ void vcorr_one(const BArgs& a, int s) {
-  __shared__ double sd[NWB];
-  const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+// Verification: FP64 max over the atoms active in this iteration of |d_i^T theta| for the
+// flagged signals (one thread per atom, theta staged in LDS).
+__device__ __forceinline__ void vcorr_one(const BArgs& a, int s, double* th_lds, double* sd) {
+  const int i = blockIdx.x * TB + threadIdx.x;
+  const bool act = i < a.K &&
+                   static_cast<double>(a.marg[static_cast<int64_t>(s) * a.Kp + i]) <= a.inst[s].r_prev;
+  const uint16_t* col = a.dcm + static_cast<int64_t>(i < a.K ? i : 0) * a.Np;
   const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
-  const float* mg = a.marg + static_cast<int64_t>(s) * a.Kp;
-  const double r_act = a.inst[s].r_prev;
-  double zm = 0.0;
-  const int c0 = blockIdx.x * 256;
-  const int c1 = min(c0 + 256, a.K);
-  for (int i = c0 + wave; i < c1; i += NWB) {
-    if (!(static_cast<double>(mg[i]) <= r_act)) continue;
-    const uint16_t* col = a.dcm + static_cast<int64_t>(i) * a.Np;
-    double acc = 0.0;
-    for (int n = lane * 8; n < a.Np; n += BW * 8) {
-      const uint4 d = ldg16(col + n);
-      const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+  double acc = 0.0;
+  for (int n0 = 0; n0 < a.Np; n0 += VCH) {
+    const int len = min(VCH, a.Np - n0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < len; e += TB) th_lds[e] = th[n0 + e];
+    __syncthreads();
+    if (act) {
+      for (int n = 0; n < len; n += 8) {
+        const uint4 d = ldg16(col + n0 + n);
+        const uint32_t w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double2 t2 = *reinterpret_cast<const double2*>(th + n + 2 * e);
-        acc = fma(static_cast<double>(__uint_as_float(w[e] << 16)), t2.x, acc);
-        acc = fma(static_cast<double>(__uint_as_float(w[e] & 0xffff0000u)), t2.y, acc);
+        for (int e = 0; e < 4; ++e) {
+          acc = fma(static_cast<double>(__uint_as_float(w[e] << 16)), th_lds[n + 2 * e], acc);
+          acc = fma(static_cast<double>(__uint_as_float(w[e] & 0xffff0000u)), th_lds[n + 2 * e + 1], acc);
+        }
       }
     }
-    acc = wave_sum(acc);
-    zm = fmax(zm, fabs(acc));
   }
-  zm = block_max<double, NWB>(zm, sd);
+  const double zm = block_max<double, NWB>(fabs(acc), sd);
   if (threadIdx.x == 0) a.vz[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = zm;
 }
 
 __global__ __launch_bounds__(TB) void k_b_vcorr(BArgs a) {
+  __shared__ double th_lds[VCH];
+  __shared__ double sd[NWB];
   const int nflag = *a.vcount;
-  for (int j = blockIdx.y; j < nflag; j += VY) vcorr_one(a, a.vlist[j]);
+  for (int j = blockIdx.y; j < nflag; j += VY) vcorr_one(a, a.vlist[j], th_lds, sd);
 }
 
-// Verification 3 (one wave per slot): the exact gap at the feasible dual point
-// v = mu theta, mu = clip(theta^T y / (lambda ||theta||^2), +-1/zs) with zs the exact
-// maximum plus the FP64 rounding bound of that pass (Lemma 7).  Finishes the signal when
-// the gap meets tolerance or the iteration budget is spent; otherwise the next check
-// waits for a smaller estimate.
+// Exact gap of the flagged signals (one wave per slot) at the feasible dual point
+// v = mu theta, mu = clip(theta^T y / (lambda ||theta||^2), +-1/zs) with zs the FP64
+// maximum plus the rounding bound of that pass (Lemma 7).  Finishes the signal when the
+// gap meets tolerance or the iteration budget is spent.
 __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
   const int lane = threadIdx.x % BW;
   const int s = blockIdx.x * NWB + threadIdx.x / BW;
   if (s >= a.Bp) return;
   Inst& st = a.inst[s];
   if (st.done != 0 || !st.verify) return;
-  const int nrc = (a.Np + TB - 1) / TB, nac = (a.K + 255) / 256;
-  double tt = 0.0, ty = 0.0, zm = 0.0;
-  for (int c = lane; c < nrc; c += BW) {
-    tt += a.vtt[static_cast<int64_t>(c) * a.Bp + s];
-    ty += a.vty[static_cast<int64_t>(c) * a.Bp + s];
-  }
+  const int nac = (a.K + TB - 1) / TB;
+  double zm = 0.0;
   for (int c = lane; c < nac; c += BW) zm = fmax(zm, a.vz[static_cast<int64_t>(c) * a.Bp + s]);
-  tt = wave_sum(tt);
-  ty = wave_sum(ty);
   zm = wave_max(zm);
   if (lane != 0) return;
-  const double lam = st.lam;
+  const double lam = st.lam, tt = st.tt, ty = st.ty;
   const double zs = zm + a.gamma64 * a.dsc[0] * sqrt(tt);
   const double sb = zs > 0.0 ? 1.0 / zs : 1e300;
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
-  const double primal = 0.5 * tt + lam * st.omega;
   const double dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
-  const double gap = primal - dual;
-  st.tt = tt;
-  st.ty = ty;
+  const double gap = st.primal - dual;
   st.zmax = zm;
   st.mu = mu;
-  st.primal = primal;
   st.dual = dual;
   st.gap = gap;
   st.verify = 0;
@@ -719,15 +680,13 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
     st.converged = (ok || st.gap_tol_abs <= 0.0) ? 1 : 0;
     st.done = 2;
     atomicAdd(a.ndone, 1);
-  } else {
-    st.vfac *= 0.5;
   }
 }
 
 // Screening (the test of Algorithm 3 for the sphere tests): the pairs with
-// r_keep < margin <= r_prev leave the active set; their x, u (both buffers) and the
-// bfloat16 parts of u are cleared.  Signals that finished this iteration keep x_t.
-// Thread: 4 consecutive atoms of one signal.
+// r_keep < margin <= r_prev leave the active set and their x and u (both buffers) are
+// cleared; a non-zero bit the update left for such an atom then reads a zero u.  Signals
+// that finished this iteration keep x_t.  Thread: 4 consecutive atoms of one signal.
 __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
   const int s = blockIdx.y;
   const Inst& st = a.inst[s];
@@ -739,7 +698,6 @@ __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
   const int64_t o = static_cast<int64_t>(s) * a.Kp + i4;
   const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
   const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
-  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Kp;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const double m = mm[e];
@@ -747,9 +705,6 @@ __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
       a.X[o + e] = 0.f;
       a.U0[o + e] = 0.f;
       a.U1[o + e] = 0.f;
-      a.Us[o + e] = 0;
-      a.Us[plane + o + e] = 0;
-      a.Us[2 * plane + o + e] = 0;
     }
   }
 }
