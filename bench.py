@@ -1,14 +1,19 @@
 """Benchmark: Lasso solves/s to duality gap 1e-6 on one MI355X, screened vs plain.
 
-Workload (one step): a 2000 x 10000 Gaussian dictionary with unit-norm atoms stored in
-FP32, one Bernoulli(0.02)-Gaussian signal at 20 dB SNR (unit norm), solved for
+Headline workload (one step): a 2000 x 10000 Gaussian dictionary with unit-norm atoms
+stored in FP32, one Bernoulli(0.02)-Gaussian signal at 20 dB SNR (unit norm), solved for
 lambda / lambda_* in {0.1, 0.3, 0.5, 0.7, 0.9} by FISTA with dynamic DST3 screening
 until the duality-gap certificate is <= 1e-6 ||y||^2.  Inputs are resident in HBM
 before the timed region; every solve runs through the C-ABI (lasso kernels in HIP).
 
+Batched workload (reported under "batched"): the same dictionary rounded to bfloat16,
+256 signals from the same generator with lambda / lambda_* uniform in [0.1, 0.9], all
+solved together by the matrix-core path to the same gap.
+
 Printed JSON line: solves/s (value), the same solves without screening (plain), p50/p99
 latency per solve, the HBM roofline of the dominant kernel (the screened correlation
-GEMV) from HIP events, and the FP64 oracle timed on the host cores on a bounded sample.
+GEMV) from HIP events, the batched leg with the matrix-core roofline of its Z = D^T Theta
+GEMM, and the FP64 oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -23,10 +28,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1412_4080_amd import datagen  # noqa: E402  (seeded input generators only)
+
 N, K = 2000, 10000
 RATIOS = (0.1, 0.3, 0.5, 0.7, 0.9)
 GAP_TOL = 1e-6
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+NB = 256  # signals of the batched leg
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_corr_lasso_2000x10000_traffic.json")
 
 
 def _dev(D32, y32):
@@ -55,7 +65,114 @@ def run_steps(binding, Dd, ys, steps, test, L, lat=None):
     return n
 
 
-def cpu_baseline(D32, ys_host, L, budget_s=20.0):
+def batched_setup(binding, D):
+    import torch
+    Dbf = datagen.to_storage(D, "bf16")
+    Dd = torch.from_numpy(np.ascontiguousarray(Dbf.T)).to(device="cuda", dtype=torch.bfloat16).T
+    ys = np.stack([datagen.to_storage(datagen.lasso_signal(D, j)[0], "f32") for j in range(NB)])
+    Y = torch.from_numpy(ys.astype(np.float32)).cuda().T
+    ratios = datagen.lambda_ratios(NB, 0.1, 0.9, datagen.LAMBDA_SEED0)
+    L = binding.spectral_norm_sq(Dd, 300)
+
+    def one():
+        _, infos = binding.solve(Dd, Y, ratios, step_L=L, gap_tol=GAP_TOL, max_iter=20000)
+        if any(i["status"] != 0 for i in infos):
+            raise RuntimeError("batched solve did not converge")
+        return infos
+    return one
+
+
+def batched_roofline(binding, one):
+    """One instrumented batched solve: matrix-core roofline of the Z = D^T Theta GEMM."""
+    binding.stats_reset()
+    binding.stats_enable(True)
+    one()
+    binding.stats_enable(False)
+    st = binding.stats_read()
+    z, th = st[binding.STAT_BATCH], st[binding.STAT_BATCH_THETA]
+    z_ms = z["ms"] / max(z["launches"], 1)
+    z_flops = z["flops"] / max(z["launches"], 1)
+    achieved = z_flops / (z_ms * 1e-3) / 1e12 if z_ms > 0 else 0.0
+    return {"bound": "mfma", "kernel": "k_b_zgemm", "achieved": round(achieved, 2),
+            "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+            "avg_launch_us": round(z_ms * 1e3, 3),
+            "event_avg_launch_us": round(z["ms_event"] / max(z["launches"], 1) * 1e3, 3),
+            "algorithmic_flops_per_launch": round(z_flops, 1),
+            "launches": z["launches"],
+            "theta_gather_event_avg_us": round(th["ms"] / max(th["launches"], 1) * 1e3, 3)}
+
+
+def batched_leg(binding, D, steps, warmup):
+    """256 signals solved together on the bfloat16 matrix-core path, `steps` times."""
+    import torch
+    one = batched_setup(binding, D)
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        infos = one()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+    dt = time.perf_counter() - t0
+    iters = [i["iters"] for i in infos]
+    return {
+        "workload": "lasso_fista_dst3_gaussian_2000x10000_bf16_batch256",
+        "signals": NB, "solves_per_s": round(NB * steps / dt, 2),
+        "ms_per_batch": round(dt * 1e3 / steps, 3),
+        "batch_latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+        "iterations": {"max": int(max(iters)), "mean": round(float(np.mean(iters)), 1)},
+        "roofline": batched_roofline(binding, one),
+    }
+
+
+def single_roofline(binding, Dd, ys, steps, L):
+    """Instrumented pass over the timed solves: HBM roofline of the correlation kernel."""
+    binding.stats_reset()
+    binding.stats_enable(True)
+    run_steps(binding, Dd, ys, steps, "dst3", L)
+    binding.stats_enable(False)
+    st = binding.stats_read()[binding.STAT_CORR]
+    avg_ms = st["ms"] / max(st["launches"], 1)
+    ev_ms = st["ms_event"] / max(st["launches"], 1)
+    bytes_per = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "kernel": "k_corr_lasso",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_record(),
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+            "event_avg_launch_us": round(ev_ms * 1e3, 3),
+            "algorithmic_bytes_per_launch": round(bytes_per, 1),
+            "launches": st["launches"]}
+
+
+def kernel_source_sha(paths):
+    """sha256 over the concatenated sources a kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_record():
+    """HBM bytes per launch of the correlation kernel from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        sha = kernel_source_sha(rec["sources"])
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["bytes_per_launch"] if sha == rec["sources_sha256"] else None
+
+
+def cpu_baseline(D, D32, L, budget_s=20.0, max_signals=30):
     """FP64 oracle on the host cores: whole sweeps of consecutive signals until ~budget."""
     import oracle
     try:
@@ -63,19 +180,20 @@ def cpu_baseline(D32, ys_host, L, budget_s=20.0):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         cores = os.cpu_count()
-    t0 = time.perf_counter()
     n = 0
     sig = 0
+    dt = 0.0  # oracle time only (signal generation excluded)
     while True:
-        y = ys_host[sig % len(ys_host)]
+        y = datagen.to_storage(datagen.lasso_signal(D, sig)[0], "f32")
+        t0 = time.perf_counter()
         for r in RATIOS:
             oracle.solve_lasso(D32, y, lam_ratio=r, rule="fista", test="dst3", L=L,
                                max_iter=20000, gap_tol=GAP_TOL)
             n += 1
+        dt += time.perf_counter() - t0
         sig += 1
-        if time.perf_counter() - t0 > budget_s or sig >= len(ys_host):
+        if dt > budget_s or sig >= max_signals:
             break
-    dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{sig} signal(s) x {len(RATIOS)} lambda ratios of the same workload, "
                       f"FP64 NumPy, FISTA + DST3 to gap {GAP_TOL:g}, {dt:.1f} s"}
@@ -88,7 +206,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--legs", default="single,batched",
+                    help="comma list of legs: single (headline), batched.  Profiling "
+                         "helpers (run alone): 'screened' runs only the timed screened "
+                         "solves; 'instrumented' only the instrumented single-signal pass "
+                         "(no warmup); 'batched-instrumented' only one instrumented "
+                         "batched solve")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (a plain copy kernel of known "
+                         "size, for scaling HBM counters)")
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
@@ -96,11 +224,23 @@ def main():
 
     import torch
 
-    from paper_1412_4080_amd import binding, datagen
+    from paper_1412_4080_amd import binding
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     D = datagen.gaussian_dictionary(N, K, datagen.DICT_SEED)
     D32 = datagen.to_storage(D, "f32")
+    if legs == {"batched-instrumented"}:
+        print(json.dumps({"leg": "batched-instrumented",
+                          "roofline": batched_roofline(binding, batched_setup(binding, D))}),
+              flush=True)
+        return
     nsig = max(args.steps, args.warmup, 1)
     ys_host = [datagen.to_storage(datagen.lasso_signal(D, j)[0], "f32") for j in range(nsig)]
     Dd, _ = _dev(D32, ys_host[0])
@@ -108,7 +248,14 @@ def main():
     L = binding.spectral_norm_sq(Dd, 300)   # per-dictionary constant, computed once
     torch.cuda.synchronize()
 
+    if legs == {"instrumented"}:
+        print(json.dumps({"leg": "instrumented",
+                          "roofline": single_roofline(binding, Dd, ys, args.steps, L)}), flush=True)
+        return
     run_steps(binding, Dd, ys, args.warmup, "dst3", L)
+    if legs == {"screened"}:
+        run_steps(binding, Dd, ys, args.steps, "dst3", L)
+        return
     # ---- timed region: screened solves ----
     lat = []
     torch.cuda.synchronize()
@@ -125,15 +272,8 @@ def main():
     torch.cuda.synchronize()
     plain = n_plain / (time.perf_counter() - t1)
 
-    # ---- instrumented pass: HIP events around every correlation launch ----
-    binding.stats_reset()
-    binding.stats_enable(True)
-    run_steps(binding, Dd, ys, args.steps, "dst3", L)
-    binding.stats_enable(False)
-    st = binding.stats_read()[binding.STAT_CORR]
-    avg_ms = st["ms"] / max(st["launches"], 1)
-    bytes_per = st["bytes"] / max(st["launches"], 1)
-    achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    # ---- instrumented pass: kernel execution spans of every correlation launch ----
+    roof = single_roofline(binding, Dd, ys, args.steps, L)
 
     out = {
         "metric": "Lasso solves/sec to gap 1e-6, screened vs plain; HBM GB/s; p50/p99 latency",
@@ -156,17 +296,16 @@ def main():
         "screened_over_plain": round(value / plain, 4),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
-        "roofline": {"bound": "hbm", "kernel": "k_corr_lasso",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_us": round(avg_ms * 1e3, 3),
-                     "algorithmic_bytes_per_launch": round(bytes_per, 1),
-                     "launches": st["launches"]},
+        "roofline": roof,
     }
+    if "batched" in legs:
+        b = batched_leg(binding, D, max(1, args.steps // 2), 1)
+        b["over_plain_single"] = round(b["solves_per_s"] / plain, 2)
+        out["batched"] = b
     if not args.no_cpu:
         import oracle
         L64 = oracle.spectral_norm_sq(D32)
-        out["cpu_baseline"] = cpu_baseline(D32, ys_host, L64, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(D, D32, L64, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -198,9 +198,13 @@ ds_status ds_server_destroy(void* server);
 /* ---------------------------------------------------------------- diagnostics ------ */
 typedef struct {
   int64_t launches;   /* kernel launches accounted */
-  double ms;          /* summed HIP-event time of those launches */
+  double ms;          /* summed execution time of those launches: device wall clock from the
+                         first workgroup's start to the last workgroup's end, read inside
+                         the kernel */
   double bytes;       /* summed algorithmic HBM bytes */
   double flops;       /* summed algorithmic flops */
+  double ms_event;    /* summed time between HIP events carried by the same dispatches
+                         (includes the command processor's dispatch overhead) */
 } ds_kernel_stat;
 
 /* CORR: single-signal correlation pass; RESID: single-signal residual pass; SETUP:

@@ -64,7 +64,7 @@ class ServerConfig(C.Structure):
 
 class KernelStat(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double),
-                ("flops", C.c_double)]
+                ("flops", C.c_double), ("ms_event", C.c_double)]
 
 
 _P = C.POINTER
@@ -283,7 +283,8 @@ def stats_reset():
 def stats_read():
     arr = (KernelStat * STAT_COUNT)()
     n = _lib.ds_stats_read(arr, STAT_COUNT)
-    return [dict(launches=a.launches, ms=a.ms, bytes=a.bytes, flops=a.flops) for a in arr[:n]]
+    return [dict(launches=a.launches, ms=a.ms, bytes=a.bytes, flops=a.flops, ms_event=a.ms_event)
+            for a in arr[:n]]
 
 
 # ------------------------------------------------------------------ serving

@@ -28,10 +28,11 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 struct BLayout {
   int N, K, B, Np, Kp, Bp, nrb, nac;
   size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, vz,
-      inst, ctr, vlist, perm, lam, z0, gn, Vn, total;
+      inst, ctr, vlist, perm, lam, z0, gn, Vn, kclk, spans, total;
+  int nspan;
 };
 
-BLayout make_layout(int N, int K, int B) {
+BLayout make_layout(int N, int K, int B, int max_iter) {
   BLayout l{};
   l.N = N; l.K = K; l.B = B;
   l.Np = round_up(N, 64);
@@ -68,6 +69,9 @@ BLayout make_layout(int N, int K, int B) {
   l.z0 = take(bp * kp * 8);
   l.gn = take(bp * kp * 8);
   l.Vn = take(bp * np * 4);
+  l.kclk = take(2 * static_cast<size_t>(l.Kp / 64) * (l.Bp / 64) * NWB * 8);
+  l.nspan = max_iter + ITERS_PER_GRAPH;
+  l.spans = take(static_cast<size_t>(l.nspan) * 8);
   l.total = o;
   return l;
 }
@@ -150,7 +154,8 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   DS_HIP(hipGetDevice(&dev));
   BatchCtx& C = batch_ctx(dev);
   std::lock_guard<std::mutex> guard(C.mu);
-  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), static_cast<int>(B));
+  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), static_cast<int>(B),
+                                prm.max_iter);
   ds_status e = C.ws.reserve(l.total);
   if (e != DS_OK) return e;
   if (C.stream == nullptr) {
@@ -174,7 +179,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   }
 
   char* base = static_cast<char*>(C.ws.base);
-  const BArgs a = make_args(l, base, prm, L);
+  BArgs a = make_args(l, base, prm, L);
 
   // slots ordered by penalty so that signals finishing together share tiles
   std::vector<int> perm(l.Bp);
@@ -240,6 +245,12 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   const dim3 g_vco(l.nac, VY);
   const dim3 g_scr((l.Kp / 4 + TB - 1) / TB, l.Bp);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evz, evt;
+  // instrumented runs: every Z-GEMM wave stamps the device wall clock at its start and
+  // end; a one-block pass after the launch reduces the stamps to the launch's span
+  uint64_t* spans = reinterpret_cast<uint64_t*>(base + l.spans);
+  int nspan = 0;
+  const int zwaves = static_cast<int>(g_z.x * g_z.y) * NWB;
+  if (stat_on) a.kclk = reinterpret_cast<uint64_t*>(base + l.kclk);
   auto events = [&]() -> std::pair<hipEvent_t, hipEvent_t> {
     if (C.ev_used == C.evpool.size()) {
       hipEvent_t e0, e1;
@@ -264,6 +275,10 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
                             static_cast<const float*>(Uin), Uout);
     else
       hipLaunchKernelGGL(k_b_zgemm, g_z, dim3(TB), 0, s, a, static_cast<const float*>(Uin), Uout);
+    if (timed && nspan < l.nspan) {
+      hipLaunchKernelGGL(k_clock_span<0>, dim3(1), dim3(256), 0, s, a.kclk, zwaves, spans + nspan);
+      ++nspan;
+    }
     hipLaunchKernelGGL(k_b_scalars, g_slot4, dim3(TB), 0, s, a);
     hipLaunchKernelGGL(k_b_vcorr, g_vco, dim3(TB), 0, s, a);
     hipLaunchKernelGGL(k_b_vfin, g_slot4, dim3(TB), 0, s, a);
@@ -321,8 +336,13 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   DS_HIP(hipStreamSynchronize(s));
 
   if (stat_on) {
-    double ms_z = 0.0, ms_t = 0.0, ms_s = 0.0;
-    for (auto& p : evz) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_z += m; }
+    double ms_z = 0.0, ms_zev = 0.0, ms_t = 0.0, ms_s = 0.0;
+    std::vector<uint64_t> ticks(nspan);
+    int rate_khz = 0;
+    DS_HIP(hipMemcpy(ticks.data(), spans, nspan * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    DS_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    for (uint64_t tk : ticks) if (rate_khz > 0) ms_z += static_cast<double>(tk) / rate_khz;
+    for (auto& p : evz) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_zev += m; }
     for (auto& p : evt) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_t += m; }
     { float m = 0.f; if (hipEventElapsedTime(&m, su0, su1) == hipSuccess) ms_s = m; }
     double act = 0.0, sup = 0.0;
@@ -331,13 +351,15 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     // algorithmic work: 2 N flops per active (atom, signal) pair for Z, per support entry
     // of the primal point for Theta; bytes: D once plus the per-signal vectors
     ds_kernel_stat& z = S.s[DS_STAT_BATCH];
-    z.launches += static_cast<int64_t>(evz.size());
+    z.launches += static_cast<int64_t>(nspan);
     z.ms += ms_z;
+    z.ms_event += ms_zev;
     z.flops += 2.0 * l.N * act;
-    z.bytes += static_cast<double>(evz.size()) * (2.0 * l.N * l.K) + 22.0 * act;
+    z.bytes += static_cast<double>(nspan) * (2.0 * l.N * l.K) + 22.0 * act;
     ds_kernel_stat& th = S.s[DS_STAT_BATCH_THETA];
     th.launches += static_cast<int64_t>(evt.size());
     th.ms += ms_t;
+    th.ms_event += ms_t;
     th.flops += 2.0 * l.N * sup;
     th.bytes += 2.0 * l.N * sup + static_cast<double>(evt.size()) * 26.0 * l.N * l.B;
     S.s[DS_STAT_SETUP].launches += 1;

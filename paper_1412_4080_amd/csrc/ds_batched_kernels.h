@@ -91,6 +91,7 @@ struct BArgs {
   int* ndone;           // signals finished
   int* vcount;          // number of signals flagged for verification this iteration
   int* vlist;           // Bp flagged slots
+  uint64_t* kclk;       // NULL, or 2 wall-clock stamps per Z-GEMM wave (start, end)
 };
 
 constexpr int VY = 16;          // flagged signals verified concurrently (grid y of the pass)
@@ -430,6 +431,8 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
 __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
                                                 float* __restrict__ Uout) {
   const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+  const int64_t gw = (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * NWB + wave;
+  if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw] = wall_clock64();
   const int a0 = blockIdx.x * 64 + (wave / 2) * MT;
   const int b0 = blockIdx.y * 64 + (wave % 2) * MT;
   const int bl = b0 + (lane % MT);  // signal of this lane's accumulator column
@@ -446,6 +449,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       a.pact[tix] = 0;
       a.umask[tix] = 0u;
     }
+    if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
     return;
   }
   const int kk = (lane / MT) * 8;
@@ -526,6 +530,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
     a.pact[tix] = cnt;
     a.umask[tix] = bits;
   }
+  if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
 }
 
 // FP64 scalars of iteration t, one wave per slot: dual scaling (Lemma 7) from the MFMA

@@ -156,6 +156,32 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* scratch, int* to
   return base + incl - v;
 }
 
+// Execution span of one launch from per-workgroup wall-clock stamps (start, end pairs):
+// last end minus first start.  One block of up to 256 threads.
+template <int UNUSED = 0>
+__global__ void k_clock_span(const uint64_t* __restrict__ clk, int nblk, uint64_t* __restrict__ out) {
+  __shared__ uint64_t s_lo[4], s_hi[4];
+  uint64_t lo = ~0ull, hi = 0ull;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    lo = min(lo, clk[2 * b]);
+    hi = max(hi, clk[2 * b + 1]);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if (threadIdx.x % WAVE == 0) {
+    s_lo[threadIdx.x / WAVE] = lo;
+    s_hi[threadIdx.x / WAVE] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < static_cast<int>(blockDim.x) / WAVE; ++w) {
+      lo = min(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+    }
+    *out = hi > lo ? hi - lo : 0ull;
+  }
+}
+
 // Arrival handshake: each participant publishes its partials, then increments a
 // counter; the one that brings it to `expected` runs the epilogue (and re-arms it).
 __device__ __forceinline__ bool last_arrive(unsigned* counter, unsigned expected, int* flag_lds) {

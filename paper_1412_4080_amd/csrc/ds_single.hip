@@ -20,8 +20,8 @@ struct Layout {
   size_t off_state, off_act0, off_act1, off_actm0, off_actm1, off_x, off_u, off_theta, off_y,
       off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_segcnt,
       off_segatom, off_segval, off_urm, off_uro, off_urn, off_bp0, off_bpi, off_rtn, off_omp,
-      off_rtcnt, off_lba, off_cnt, off_gptr, off_w, off_tele, off_pv, off_pw, off_pz, off_pd,
-      total;
+      off_rtcnt, off_lba, off_cnt, off_gptr, off_w, off_tele, off_kclk, off_spans, off_pv, off_pw,
+      off_pz, off_pd, total;
   int64_t npad, grid_corr, nsg;
 };
 
@@ -77,6 +77,8 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.off_gptr = take((std::max<int64_t>(G, 1) + 1) * 8);
   l.off_w = take(std::max<int64_t>(G, 1) * 8);
   l.off_tele = take(tele_cap * sizeof(Telemetry));
+  l.off_kclk = take(2 * l.grid_corr * 8);
+  l.off_spans = take((tele_cap + 1) * 8);
   if (power) {
     l.off_pv = take(K * 8);
     l.off_pz = take(K * 8);
@@ -269,6 +271,11 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     stat_on = S.on;
   }
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
+  // instrumented runs: each correlation block stamps the device wall clock at its start
+  // and end; a one-block pass after the launch reduces the stamps to its span
+  uint64_t* spans = reinterpret_cast<uint64_t*>(base + l.off_spans);
+  int64_t nspan = 0;
+  if (stat_on) a.kclk = reinterpret_cast<uint64_t*>(base + l.off_kclk);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t ev_used = 0;
   auto get_events = [&]() -> std::pair<hipEvent_t, hipEvent_t> {
@@ -301,6 +308,10 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
       hipExtLaunchKernelGGL((k_corr<T, V, VEC, RULE, false>), dim3(grid_corr), dim3(BLK), 0, s,
                             e.first, e.second, 0, a);
     if (stat_on && e.first) ev.push_back(e);
+    if (stat_on && nspan < tele_cap) {
+      hipLaunchKernelGGL(k_clock_span<0>, dim3(1), dim3(256), 0, s, a.kclk, grid_corr, spans + nspan);
+      ++nspan;
+    }
   };
 
   // iteration t: corr(t) with parity t%2, then resid(t+1) (scalars of t, theta_{t+1});
@@ -320,7 +331,8 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     DS_HIP(hipMemcpyAsync(hst, a.st + last_par, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     DS_HIP(hipStreamSynchronize(s));
     finished = hst->done != 0;
-    chunk = std::min(chunk * 2, 64);
+    // instrumented runs keep short chunks: at most 3 launches past the last iteration
+    chunk = stat_on ? 4 : std::min(chunk * 2, 64);
   }
   a.par = last_par;
 
@@ -350,11 +362,16 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   if (stat_on && !ev.empty()) {
     // algorithmic bytes of one correlation launch: the active columns of D, theta, the
     // read-modify-write of x and u on the active atoms and the active list
-    double ms = 0.0, bytes = 0.0, flops = 0.0;
-    const size_t used = std::min(ev.size(), tl.size());
+    double ms = 0.0, ms_ev = 0.0, bytes = 0.0, flops = 0.0;
+    const size_t used = std::min({ev.size(), tl.size(), static_cast<size_t>(nspan)});
+    std::vector<uint64_t> ticks(used);
+    int rate_khz = 0;
+    DS_HIP(hipMemcpy(ticks.data(), spans, used * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    DS_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ws.device));
     for (size_t k = 0; k < used; ++k) {
       float f = 0.f;
-      if (hipEventElapsedTime(&f, ev[k].first, ev[k].second) == hipSuccess) ms += f;
+      if (hipEventElapsedTime(&f, ev[k].first, ev[k].second) == hipSuccess) ms_ev += f;
+      if (rate_khz > 0) ms += static_cast<double>(ticks[k]) / rate_khz;
       const double na = tl[k].n_atoms, nu = tl[k].n_units;
       bytes += na * P.N * sizeof(T) + P.N * sizeof(V) + 4.0 * na * sizeof(V) + 4.0 * nu;
       flops += 2.0 * na * P.N;
@@ -362,6 +379,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     std::lock_guard<std::mutex> g(S.mu);
     S.s[DS_STAT_CORR].launches += static_cast<int64_t>(used);
     S.s[DS_STAT_CORR].ms += ms;
+    S.s[DS_STAT_CORR].ms_event += ms_ev;
     S.s[DS_STAT_CORR].bytes += bytes;
     S.s[DS_STAT_CORR].flops += flops;
   }

@@ -916,6 +916,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ double kmarg[CBU];
   __shared__ double sd[NW];
   __shared__ int si[NW];
+  if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
   const SolverState* st = a.st + a.par;
   if (st->done) return;
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
@@ -1074,6 +1075,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       SolverState* sw = a.st + a.par;
       sw->pending = 1;  // nothing else in this pass reads it
     }
+    if (a.kclk != nullptr) a.kclk[2 * blockIdx.x + 1] = wall_clock64();
   }
 }
 

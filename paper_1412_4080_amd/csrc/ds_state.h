@@ -95,6 +95,7 @@ struct SingleArgs {
   unsigned* counters;    // arrival / virtual-block counters
   void* tele;            // per-iteration telemetry records, or NULL
   int32_t tele_cap;
+  uint64_t* kclk;        // NULL, or 2 wall-clock stamps per correlation block (start, end)
 };
 
 // Per-iteration telemetry written by the last correlation block.
