@@ -104,6 +104,8 @@ typedef struct {
   double mu;           /* dual-scaling factor of the last iteration */
   double L;            /* step constant used */
   double radius_slack; /* rounding slack added to the radius (>= 0) */
+  double queue_ms;     /* served requests: submit -> start of the solve; else 0 */
+  double run_ms;       /* served requests: start -> end of the solve; else 0 */
 } ds_info;
 
 /* lasso_solve / glasso_solve
@@ -179,20 +181,26 @@ typedef struct {
 
 ds_status ds_server_create(const ds_server_config* config, void** server);
 /* Copies D (device or host pointer, detected) into server memory, converting to `store`
- * precision (DS_F32 or DS_BF16 from DS_F32 input; same type otherwise).  Computes and
- * caches ||D||_2^2, atom norms and group norms. */
+ * precision (DS_F32 or DS_BF16 from DS_F32 input; same type otherwise), and computes and
+ * caches ||D||_2^2 (used as the step constant unless a request sets step_L > 0).  The
+ * dictionary stays resident until ds_server_destroy; it is not charged to the budget. */
 ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype store,
                              int32_t* dict_id);
 /* Queue a solve of y (HOST pointer, N floats, or doubles for a DS_F64 dictionary) with
- * penalty `lambda` (read per params->lambda_mode).  Returns immediately. */
+ * penalty `lambda` (read per params->lambda_mode).  Returns immediately.  Errors:
+ * DS_ENOTFOUND (unknown dictionary), DS_EBUSY (max_queue requests already waiting),
+ * DS_ENOMEM (the request's device footprint exceeds the whole budget), DS_EINVAL. */
 ds_status ds_submit(void* server, int32_t dict_id, const void* y_host, double lambda,
                     const ds_params* params, uint64_t* request_id);
 /* Lasso-named alias of ds_submit (the dictionary decides Lasso or Group-Lasso). */
 ds_status lasso_submit(void* server, int32_t dict_id, const void* y_host, double lambda,
                        const ds_params* params, uint64_t* request_id);
-/* DS_PENDING while running; otherwise copies x (K values, HOST) and info, forgets the
- * request and returns its final status.  x_host may be NULL to discard x. */
+/* DS_PENDING while queued or running; otherwise copies x (K values, HOST) and info,
+ * forgets the request and returns its final status.  x_host may be NULL to discard x.
+ * DS_ENOTFOUND for an unknown (or already collected) request id. */
 ds_status lasso_poll(void* server, uint64_t request_id, void* x_host, ds_info* info);
+/* Stops the workers (requests still queued are dropped, running ones finish first) and
+ * frees the server's device memory. */
 ds_status ds_server_destroy(void* server);
 
 /* ---------------------------------------------------------------- diagnostics ------ */

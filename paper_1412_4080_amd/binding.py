@@ -46,7 +46,7 @@ class Info(C.Structure):
                 ("nnz", C.c_int32), ("lambda_", C.c_double), ("lambda_max", C.c_double),
                 ("primal", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
                 ("radius", C.c_double), ("mu", C.c_double), ("L", C.c_double),
-                ("radius_slack", C.c_double)]
+                ("radius_slack", C.c_double), ("queue_ms", C.c_double), ("run_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

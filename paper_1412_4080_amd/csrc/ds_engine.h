@@ -80,4 +80,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
 
 size_t dtype_size(ds_dtype t);
 
+// Device bytes a single-signal solve of this shape holds (its workspace).
+size_t single_workspace_bytes(const ds_problem& P, const ds_params& prm);
+
 }  // namespace ds

@@ -420,6 +420,12 @@ ds_status dispatch_rule(const ds_problem& P, const void* y, double lam, const ds
 
 }  // namespace
 
+size_t single_workspace_bytes(const ds_problem& P, const ds_params& prm) {
+  const size_t vsz = P.dtype == DS_F64 ? 8 : 4;
+  const int64_t tele_cap = std::max<int32_t>(prm.max_iter, 1);
+  return make_layout(P.N, P.K, P.G, vsz, sizeof(double), tele_cap, false).total;
+}
+
 ds_status solve_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
                        void* x, ds_info* info, hipStream_t stream, Workspace& ws,
                        std::vector<Telemetry>* tele_out, uint8_t* scr) {

@@ -97,3 +97,26 @@ def test_invalid_lambda_and_groups_rejected(B):
     pg = _problem(B, G=2, group_ptr=gp.ctypes.data_as(C.POINTER(C.c_int64)))
     assert B._lib.lasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
                               C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("max_slots", 0), ("max_queue", 0),
+                                         ("hbm_budget_bytes", 0), ("reserved", 1),
+                                         ("device", -1)])
+def test_server_config_rejected(B, field, value):
+    cfg = B.ServerConfig(0, 4, 1 << 30, 16, 0)
+    setattr(cfg, field, value)
+    h = C.c_void_p()
+    assert B._lib.ds_server_create(C.byref(cfg), C.byref(h)) == B.DS_EINVAL
+    assert not h.value
+
+
+def test_server_calls_need_a_server(B):
+    prm = B.make_params()
+    rid = C.c_uint64()
+    y = (C.c_float * 4)()
+    info = B.Info()
+    assert B._lib.ds_server_create(None, None) == B.DS_EINVAL
+    assert B._lib.lasso_submit(None, 0, y, 0.5, C.byref(prm), C.byref(rid)) == B.DS_EINVAL
+    assert B._lib.ds_submit(None, 0, y, 0.5, C.byref(prm), C.byref(rid)) == B.DS_EINVAL
+    assert B._lib.lasso_poll(None, C.c_uint64(1), None, C.byref(info)) == B.DS_EINVAL
+    assert B._lib.ds_server_destroy(None) == B.DS_EINVAL

@@ -1,0 +1,165 @@
+"""Serving (ds_server_* / lasso_submit / lasso_poll) on the device: every request's result
+is the same solved alone and in a concurrent mix, admission respects the memory budget,
+and the error paths report their codes."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4080_amd import datagen
+from tests._util import dev_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1412_4080_amd import binding
+    return binding
+
+
+def _dicts():
+    """(name, D values (f64), stored dtype, group_ptr) of a small mixed set."""
+    out = []
+    D = datagen.gaussian_dictionary(256, 1000, 21)
+    out.append(("lasso_f32", D, "f32", None))
+    D = datagen.gaussian_dictionary(512, 3000, 22)
+    out.append(("lasso_bf16", D, "bf16", None))
+    D = datagen.gaussian_dictionary(300, 2000, 23)
+    out.append(("group_f32", D, "f32", datagen.contiguous_groups(2000, 10)))
+    return out
+
+
+def _requests(dicts, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        d = int(rng.integers(len(dicts)))
+        _, D, _, gp = dicts[d]
+        if gp is None:
+            y = datagen.lasso_signal(D, 500 + k)[0]
+        else:
+            y = datagen.group_signal(D, gp, 500 + k)[0]
+        reqs.append((d, datagen.to_storage(y, "f32").astype(np.float32), float(rng.uniform(0.1, 0.9))))
+    return reqs
+
+
+def _server(B, dicts, **kw):
+    import torch
+    S = B.Server(**kw)
+    ids = []
+    for _, D, store, gp in dicts:
+        Dd = dev_matrix(D, "f32")  # FP32 input; the server rounds to bfloat16 when asked
+        ids.append(S.add_dict(Dd, group_ptr=gp, store=store))
+    torch.cuda.synchronize()
+    return S, ids
+
+
+def _collect(S, ids, rid_of, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(rid_of):
+        for k, (rid, d) in rid_of.items():
+            if k in out:
+                continue
+            r = S.poll(rid, ids[d])
+            if r is not None:
+                out[k] = r
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.0005)
+    return out
+
+
+def test_results_same_alone_and_in_the_mix(B):
+    dicts = _dicts()
+    reqs = _requests(dicts, 24, 1)
+    # alone: one slot, one request on the device at a time
+    S, ids = _server(B, dicts, max_slots=1)
+    alone = {}
+    for k, (d, y, r) in enumerate(reqs):
+        rid = S.submit(ids[d], y, r, gap_tol=1e-6, max_iter=20000)
+        alone.update(_collect(S, ids, {k: (rid, d)}))
+    S.close()
+    # mix: eight slots, everything submitted at once
+    S, ids = _server(B, dicts, max_slots=8)
+    rid_of = {k: (S.submit(ids[d], y, r, gap_tol=1e-6, max_iter=20000), d)
+              for k, (d, y, r) in enumerate(reqs)}
+    mix = _collect(S, ids, rid_of)
+    S.close()
+    for k in range(len(reqs)):
+        xa, ia = alone[k]
+        xm, im = mix[k]
+        assert ia["status"] == 0 and im["status"] == 0
+        assert np.array_equal(xa, xm), k
+        assert ia["iters"] == im["iters"] and ia["gap"] == im["gap"]
+    # the served solutions are certified against the oracle's optimum of the stored instance
+    for k in (0, 1, 2, 3, 4, 5):
+        d, y, r = reqs[k]
+        _, D, store, gp = dicts[d]
+        Di = datagen.to_storage(D, store)
+        x, info = mix[k]
+        yy = float(y.astype(np.float64) @ y.astype(np.float64))
+        assert info["gap"] <= 1e-6 * yy
+        if gp is None:
+            star = oracle.solve_lasso(Di, y.astype(np.float64), lam=info["lambda_"], rule="fista",
+                                      test="none", L=info["L"], max_iter=200000, gap_tol=1e-12)
+        else:
+            star = oracle.solve_group_lasso(Di, y.astype(np.float64), gp, None, lam=info["lambda_"],
+                                            rule="fista", test="none", L=info["L"],
+                                            max_iter=200000, gap_tol=1e-12)
+        assert info["primal"] - star.primal <= info["gap"] + 1e-9
+        # the primal value comes from theta rounded to FP32 (relative error ~2^-24)
+        assert star.primal <= info["primal"] + 1e-7 * star.primal
+
+
+def test_admission_under_a_tight_budget(B):
+    """A budget that holds about two requests at a time: all finish, results unchanged."""
+    dicts = _dicts()
+    reqs = _requests(dicts, 12, 2)
+    S, ids = _server(B, dicts, max_slots=8)
+    rid_of = {k: (S.submit(ids[d], y, r, gap_tol=1e-6, max_iter=20000), d)
+              for k, (d, y, r) in enumerate(reqs)}
+    ref = _collect(S, ids, rid_of)
+    S.close()
+    S, ids = _server(B, dicts, max_slots=8, hbm_budget_bytes=12 << 20)
+    rid_of = {k: (S.submit(ids[d], y, r, gap_tol=1e-6, max_iter=20000), d)
+              for k, (d, y, r) in enumerate(reqs)}
+    got = _collect(S, ids, rid_of)
+    S.close()
+    for k in range(len(reqs)):
+        assert np.array_equal(ref[k][0], got[k][0])
+
+
+def test_error_codes(B):
+    import ctypes as C
+    dicts = _dicts()[:1]
+    S, ids = _server(B, dicts, max_slots=1, max_queue=1)
+    y = datagen.to_storage(datagen.lasso_signal(dicts[0][1], 7)[0], "f32").astype(np.float32)
+    prm = B.make_params()
+    rid = C.c_uint64()
+    st = B._lib.lasso_submit(S._h, 99, y.ctypes.data_as(C.c_void_p), 0.5, C.byref(prm), C.byref(rid))
+    assert st == B.DS_ENOTFOUND
+    info = B.Info()
+    assert B._lib.lasso_poll(S._h, C.c_uint64(123456), None, C.byref(info)) == B.DS_ENOTFOUND
+    S.close()
+    # a request larger than the whole budget can never be admitted
+    S, ids = _server(B, dicts, max_slots=1, hbm_budget_bytes=64 << 10)
+    st = B._lib.lasso_submit(S._h, ids[0], y.ctypes.data_as(C.c_void_p), 0.5, C.byref(prm), C.byref(rid))
+    assert st == B.DS_ENOMEM
+    S.close()
+    # a full queue: one worker busy on a slow solve, one request waiting, the next refused
+    D = datagen.gaussian_dictionary(2000, 10000, 0)
+    S, ids = _server(B, [("big", D, "f32", None)], max_slots=1, max_queue=1)
+    yb = datagen.to_storage(datagen.lasso_signal(D, 0)[0], "f32").astype(np.float32)
+    codes = []
+    rids = []
+    for _ in range(3):
+        st = B._lib.lasso_submit(S._h, ids[0], yb.ctypes.data_as(C.c_void_p), 0.1, C.byref(prm),
+                                 C.byref(rid))
+        codes.append(st)
+        if st == 0:
+            rids.append(rid.value)
+    assert B.DS_EBUSY in codes, codes
+    _collect(S, ids, {k: (r, 0) for k, r in enumerate(rids)})
+    S.close()
