@@ -150,6 +150,126 @@ def single_roofline(binding, Dd, ys, steps, L):
             "launches": st["launches"]}
 
 
+# Serving mix: (N, K, group size or 0, stored dtype) of the eight resident dictionaries.
+SERVE_DICTS = ((256, 1000, 0, "f32"), (256, 5000, 10, "bf16"), (1024, 5000, 0, "bf16"),
+               (1024, 20000, 10, "f32"), (2048, 20000, 0, "f32"), (2048, 40000, 10, "bf16"),
+               (4096, 20000, 0, "bf16"), (4096, 40000, 10, "f32"))
+SERVE_POOL = 16  # signals per dictionary, reused round-robin by the requests
+
+
+def serve_inputs(seed=datagen.DICT_SEED):
+    """Unit-norm Gaussian dictionaries and pools of unit-norm observations (2% active atoms
+    or groups with N(0,1) coefficients, 20 dB noise), drawn on the device from seeded
+    generators: the serving mix is too large to draw on the host in the bench's time."""
+    import torch
+    g = torch.Generator(device="cuda")
+    out = []
+    for k, (n, kk, gs, dt) in enumerate(SERVE_DICTS):
+        g.manual_seed(seed * 1000 + k)
+        D = torch.randn(kk, n, generator=g, device="cuda")
+        D /= D.norm(dim=1, keepdim=True)
+        Dt = D.T                                   # N x K column-major view
+        units = kk // gs if gs else kk
+        mask = torch.rand(SERVE_POOL, units, generator=g, device="cuda") < 0.02
+        mask[:, 0] |= ~mask.any(dim=1)             # at least one active unit
+        if gs:
+            mask = mask.repeat_interleave(gs, dim=1)
+        X0 = torch.randn(SERVE_POOL, kk, generator=g, device="cuda") * mask
+        Yc = X0 @ D                                # SERVE_POOL x N clean signals
+        noise = torch.randn(Yc.shape, generator=g, device="cuda")
+        noise *= (Yc.norm(dim=1, keepdim=True) / noise.norm(dim=1, keepdim=True)) * 10 ** (-20 / 20)
+        Y = Yc + noise
+        Y /= Y.norm(dim=1, keepdim=True)
+        gp = np.arange(0, kk + 1, gs, dtype=np.int64) if gs else None
+        out.append((Dt, gp, dt, Y.cpu().numpy().astype(np.float32)))
+    torch.cuda.synchronize()
+    return out
+
+
+def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96,
+               seed=datagen.ARRIVAL_SEED):
+    """Closed-loop saturation, then open-loop Poisson arrivals at 0.5x and 0.9x of it; the
+    baseline is requests of the same mix solved one at a time without screening."""
+    inputs = serve_inputs()
+    rng = np.random.default_rng(seed)
+
+    def draw(n):
+        return [(int(rng.integers(len(inputs))), int(rng.integers(SERVE_POOL)),
+                 float(rng.uniform(0.1, 0.9))) for _ in range(n)]
+
+    def server(nslots):
+        S = binding.Server(max_slots=nslots, hbm_budget_bytes=24 << 30, max_queue=1 << 14)
+        return S, [S.add_dict(Dt, group_ptr=gp, store=dt) for (Dt, gp, dt, _) in inputs]
+
+    def drain(S, ids, pending, done):
+        for rid in list(pending):
+            d = pending[rid]
+            got = S.poll(rid, ids[d])
+            if got is not None:
+                if got[1]["status"] != 0:
+                    raise RuntimeError(f"served solve did not converge: {got[1]}")
+                done.append((d, got[1]))
+                del pending[rid]
+
+    def run(S, ids, reqs, gaps=None, skip=0, test="dst3"):
+        """Submit reqs (all at once, or with the given inter-arrival gaps) and wait."""
+        pending, done = {}, []
+        t_next = t_start = time.perf_counter()
+        for k, (d, j, r) in enumerate(reqs):
+            if gaps is not None:
+                t_next += gaps[k]
+                while time.perf_counter() < t_next:
+                    drain(S, ids, pending, done)
+            if k == skip:
+                t_start = time.perf_counter()
+                done.clear()
+            rid = S.submit(ids[d], inputs[d][3][j], r, test=test, gap_tol=GAP_TOL, max_iter=20000)
+            pending[rid] = d
+        while pending:
+            drain(S, ids, pending, done)
+            time.sleep(0.0002)
+        return done, time.perf_counter() - t_start
+
+    def summary(done, dt):
+        lat = np.array([i["queue_ms"] + i["run_ms"] for _, i in done])
+        return {"solves_per_s": round(len(done) / dt, 1), "requests": len(done),
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                               "p99": round(float(np.percentile(lat, 99)), 3)}}
+
+    S, ids = server(slots)
+    done, dt = run(S, ids, draw(n_closed))
+    sat = len(done) / dt
+    per_dict = []
+    for d, (n, k, g, dtp) in enumerate(SERVE_DICTS):
+        infos = [i for dd, i in done if dd == d]
+        if infos:
+            per_dict.append({"dict": f"{n}x{k}{'g' + str(g) if g else ''}_{dtp}", "requests": len(infos),
+                             "mean_run_ms": round(float(np.mean([i["run_ms"] for i in infos])), 3),
+                             "mean_iters": round(float(np.mean([i["iters"] for i in infos])), 1)})
+    opens = []
+    for frac in (0.5, 0.9):
+        reqs = draw(warm + n_open)
+        gaps = rng.exponential(1.0 / (frac * sat), size=len(reqs))
+        done, dt = run(S, ids, reqs, gaps, skip=warm)
+        opens.append(dict(offered_per_s=round(frac * sat, 1), **summary(done, dt)))
+    S.close()
+    # baseline: the plain (unscreened) single-signal path, one request at a time
+    P, pids = server(1)
+    pdone, pdt = [], 0.0
+    for q in draw(n_plain):
+        done, dt = run(P, pids, [q], test="none")
+        pdone += done
+        pdt += dt
+    P.close()
+    plain = len(pdone) / pdt
+    return {"workload": "serving_mix_8_dicts_lasso_group_f32_bf16", "slots": slots,
+            "dictionaries": [f"{n}x{k}{'g' + str(g) if g else ''}_{dt}" for n, k, g, dt in SERVE_DICTS],
+            "saturation_solves_per_s": round(sat, 1),
+            "plain_one_at_a_time_solves_per_s": round(plain, 1),
+            "saturation_over_plain": round(sat / plain, 2),
+            "open_loop": opens, "per_dict_closed_loop": per_dict}
+
+
 def kernel_source_sha(paths):
     """sha256 over the concatenated sources a kernel is built from."""
     import hashlib
@@ -206,8 +326,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched",
-                    help="comma list of legs: single (headline), batched.  Profiling "
+    ap.add_argument("--legs", default="single,batched,served",
+                    help="comma list of legs: single (headline), batched, served.  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
@@ -302,6 +422,8 @@ def main():
         b = batched_leg(binding, D, max(1, args.steps // 2), 1)
         b["over_plain_single"] = round(b["solves_per_s"] / plain, 2)
         out["batched"] = b
+    if "served" in legs:
+        out["served"] = served_leg(binding)
     if not args.no_cpu:
         import oracle
         L64 = oracle.spectral_norm_sq(D32)
