@@ -182,22 +182,4 @@ __global__ void k_clock_span(const uint64_t* __restrict__ clk, int nblk, uint64_
   }
 }
 
-// Arrival handshake: each participant publishes its partials, then increments a
-// counter; the one that brings it to `expected` runs the epilogue (and re-arms it).
-__device__ __forceinline__ bool last_arrive(unsigned* counter, unsigned expected, int* flag_lds) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    *flag_lds = (prev == expected - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *flag_lds != 0;
-  if (last) __threadfence();
-  return last;
-}
-__device__ __forceinline__ bool last_block_arrive(unsigned* counter, int* flag_lds) {
-  return last_arrive(counter, gridDim.x, flag_lds);
-}
-
 }  // namespace ds

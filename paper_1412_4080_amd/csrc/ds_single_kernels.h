@@ -1,15 +1,16 @@
 // Single-signal kernels: Algorithm 3 with ISTA / FISTA (Table 1) and the sphere tests of
 // Lemmas 1, 2, 4, 5 (through Lemma 6), one signal at a time.
 //
-// Per iteration four launches, all on one stream:
-//   k_resid           theta partial sums  D_S p_S over the support S of the primal point p
-//   k_resid_finalize  theta = sum(partials) - y, FP64 ||theta||^2 and theta^T y
-//   k_corr_*          z = D_A^T theta over the active list A (the HBM stream), fused with the
-//                     prox (eq. softTh / gr_softTh), the FISTA momentum, ||z||_inf or the
-//                     group norms, Omega(p) and nnz; the last block to finish runs the
-//                     FP64 screening scalars (dual scaling Lemma 7, radius, gap, stop rule)
-//   k_compact         order-preserving compaction of A against the margins, plus the
-//                     support list of the next primal point
+// Per iteration two launches on one stream:
+//   k_resid  theta = D_S p_S - y over the support S of the primal point p (row tiles x
+//            support segments, FP64 accumulation, per-tile FP64 ||theta||^2, theta^T y);
+//            every block first recomputes the FP64 scalars of the previous iteration
+//            (dual scaling Lemma 7, gap, radius, stopping rule) from published partials.
+//   k_corr   z = D_A^T theta over the active list A (the HBM stream), fused with the prox
+//            (eq. softTh / gr_softTh), the FISTA momentum, ||z||_inf or the group norms,
+//            Omega(p) and nnz; it drops screened entries from A while it reads them and,
+//            when enough are stale, rewrites A in order (decoupled look-back), and it
+//            publishes the support of the new primal point for the next k_resid.
 // Every scalar is in device memory (SolverState); once `done` is set the kernels return
 // immediately, so the host may enqueue iterations ahead of the stopping decision.
 #pragma once
@@ -23,14 +24,7 @@ namespace ds {
 constexpr int BLK = 256;         // threads per block of the streaming kernels
 constexpr int NW = BLK / WAVE;   // waves per block
 constexpr int CPW = 2;           // columns streamed at once by one wave (more slows HBM)
-constexpr int CBLK_CORR = 1024;  // threads of a correlation block
-constexpr int NWC = CBLK_CORR / WAVE;
-constexpr int CB = NWC * CPW;    // active-list entries per correlation block (<= 64)
-constexpr int NSUB = 16;         // first-level arrival counters
-constexpr int RC = 256;          // active-list entries per residual work item (Lasso)
-constexpr int RCG = 32;          // active-list entries per residual work item (groups)
 constexpr int RPW = 8;           // support columns one residual wave loads at once
-constexpr int SCH = RC;          // partial-sum chunking unit of the residual
 constexpr int CBLK = 1024;       // threads of the single-block kernels
 constexpr int CNW = CBLK / WAVE;
 constexpr int MAXB = 16384;      // maximum grid of the kernels with block partials
@@ -50,29 +44,6 @@ __device__ __forceinline__ void publish(X* p, X v) {
 template <typename X>
 __device__ __forceinline__ X consume(const X* p) {
   return __hip_atomic_load(const_cast<X*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Two-level arrival for large grids: blocks count on one of NSUB counters (same-address
-// atomics serialise, so a single counter hit by every block costs microseconds); the
-// block completing a sub-counter arrives at the top counter.
-__device__ __forceinline__ bool arrive_last_2l(unsigned* sub, unsigned* top, int vb, int grid,
-                                               int* flag_lds) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int k = vb % NSUB;
-    const unsigned expect_sub = static_cast<unsigned>((grid - k + NSUB - 1) / NSUB);
-    const unsigned nsubs = static_cast<unsigned>(min(grid, NSUB));
-    int last = 0;
-    const unsigned p1 = __hip_atomic_fetch_add(&sub[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (p1 == expect_sub - 1u) {
-      sub[k] = 0u;
-      const unsigned p2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      last = p2 == nsubs - 1u;
-    }
-    *flag_lds = last;
-  }
-  __syncthreads();
-  return *flag_lds != 0;
 }
 // Arrival counter after the block's publications; true in the block that arrives last.
 __device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected, int* flag_lds) {
