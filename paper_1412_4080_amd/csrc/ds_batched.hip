@@ -26,8 +26,8 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 struct BLayout {
-  int N, K, B, Np, Kp, Bp, nrb, nac;
-  size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, vz,
+  int N, K, B, Np, Kp, Bp, nrb;
+  size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
       inst, ctr, vlist, perm, lam, z0, gn, Vn, kclk, spans, total;
   int nspan;
 };
@@ -39,7 +39,6 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.Kp = round_up(K, 64);
   l.Bp = round_up(B, 64);
   l.nrb = (l.Np + TR - 1) / TR;
-  l.nac = (K + TB - 1) / TB;
   const size_t np = l.Np, kp = l.Kp, bp = l.Bp, nt = l.Kp / MT;
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
@@ -57,10 +56,13 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.pty = take(static_cast<size_t>(l.nrb) * bp * 8);
   l.marg = take(bp * kp * 4);
   l.tminm = take(nt * bp * 4);
-  l.pz = take(nt * bp * 4);
+  l.pz = take(nt * bp * 8);
   l.pom = take(nt * bp * 8);
   l.pact = take(nt * bp * 4);
-  l.vz = take(static_cast<size_t>(l.nac) * bp * 8);
+  l.Z = take(bp * kp * 4);
+  l.ccount = take(bp * 4);
+  l.cidx = take(bp * kp * 4);
+  l.cval = take(bp * kp * 8);
   l.inst = take(bp * sizeof(Inst));
   l.ctr = take(4 * sizeof(int));
   l.vlist = take(bp * 4);
@@ -110,11 +112,12 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
   a.rule = prm.rule == DS_FISTA ? 1 : 0;
   a.max_iter = prm.max_iter;
   a.L = L;
-  // |z_hat - d^T theta| <= gamma_acc ||d|| ||theta||: FP32 accumulation of 3 Np exact
-  // products (and the MFMA's internal sums) bounded with unit roundoff 2^-23, the factor
-  // 1.02 covering |hi| + |mid| + |lo| <= (1 + 2^-7) |v|, plus the FP32 rounding of theta
-  const double n = 3.0 * l.Np + 32.0, u = 0x1p-23;
-  a.gamma_acc = 1.02 * n * u / (1.0 - n * u) + 0x1p-23;
+  // |z_hat - d^T theta| <= gamma_acc ||d|| ||theta||: FP32 accumulation of the 3 x 64
+  // exact products of a row chunk (and the MFMA's internal sums) bounded with unit
+  // roundoff 2^-23, the factor 1.02 covering |hi| + |mid| + |lo| <= (1 + 2^-7) |v|; the
+  // FP64 sum of the chunk results; the FP32 rounding of theta
+  const double n = 3.0 * 64 + 32.0, u = 0x1p-23;
+  a.gamma_acc = 1.02 * n * u / (1.0 - n * u) + (l.Np / 64 + 2) * 0x1p-52 + 0x1p-23;
   a.gamma64 = 1.01 * (l.Np + 16) * 0x1p-53;
   a.dcm = reinterpret_cast<const uint16_t*>(base + l.dcm);
   a.dsc = reinterpret_cast<const double*>(base + l.dsc);
@@ -130,10 +133,13 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
   a.pty = reinterpret_cast<double*>(base + l.pty);
   a.marg = reinterpret_cast<const float*>(base + l.marg);
   a.tminm = reinterpret_cast<const float*>(base + l.tminm);
-  a.pz = reinterpret_cast<float*>(base + l.pz);
+  a.pz = reinterpret_cast<double*>(base + l.pz);
   a.pom = reinterpret_cast<double*>(base + l.pom);
   a.pact = reinterpret_cast<int*>(base + l.pact);
-  a.vz = reinterpret_cast<double*>(base + l.vz);
+  a.Z = reinterpret_cast<float*>(base + l.Z);
+  a.ccount = reinterpret_cast<int*>(base + l.ccount);
+  a.cidx = reinterpret_cast<int*>(base + l.cidx);
+  a.cval = reinterpret_cast<double*>(base + l.cval);
   a.inst = reinterpret_cast<Inst*>(base + l.inst);
   a.ndone = reinterpret_cast<int*>(base + l.ctr);
   a.vcount = reinterpret_cast<int*>(base + l.ctr) + 1;
@@ -242,7 +248,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   const dim3 g_theta(l.nrb, l.Bp);
   const dim3 g_z(l.Kp / 64, l.Bp / 64);
   const dim3 g_slot4(l.Bp / NWB);
-  const dim3 g_vco(l.nac, VY);
+  const dim3 g_vca(64), g_vdot(512);
   const dim3 g_scr((l.Kp / 4 + TB - 1) / TB, l.Bp);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evz, evt;
   // instrumented runs: every Z-GEMM wave stamps the device wall clock at its start and
@@ -280,7 +286,8 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
       ++nspan;
     }
     hipLaunchKernelGGL(k_b_scalars, g_slot4, dim3(TB), 0, s, a);
-    hipLaunchKernelGGL(k_b_vcorr, g_vco, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_vcand, g_vca, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_vdot, g_vdot, dim3(TB), 0, s, a);
     hipLaunchKernelGGL(k_b_vfin, g_slot4, dim3(TB), 0, s, a);
     hipLaunchKernelGGL(k_b_screen, g_scr, dim3(TB), 0, s, a);
     if (timed && et.first) { evt.push_back(et); evz.push_back(ez); }

@@ -83,10 +83,13 @@ struct BArgs {
   double* pty;          // nrb x Bp partial theta^T y
   const float* marg;    // Bp x Kp margins, rounded towards -inf
   const float* tminm;   // (Kp/32) x Bp smallest margin of each 32-atom tile
-  float* pz;            // (Kp/32) x Bp partial max |z| over active pairs
+  double* pz;           // (Kp/32) x Bp partial max |z| over active pairs
   double* pom;          // (Kp/32) x Bp partial Omega(p)
   int* pact;            // (Kp/32) x Bp active pairs | (non-zeros of p << 8)
-  double* vz;           // (K/256 rounded up) x Bp partial max |d_i^T theta| (verification)
+  float* Z;             // Bp x Kp correlations of the pairs computed this iteration
+  int* ccount;          // Bp candidates of the verification per flagged signal
+  int* cidx;            // Bp x Kp candidate atoms
+  double* cval;         // Bp x Kp their exact |d_i^T theta|
   Inst* inst;           // Bp
   int* ndone;           // signals finished
   int* vcount;          // number of signals flagged for verification this iteration
@@ -94,8 +97,7 @@ struct BArgs {
   uint64_t* kclk;       // NULL, or 2 wall-clock stamps per Z-GEMM wave (start, end)
 };
 
-constexpr int VY = 16;          // flagged signals verified concurrently (grid y of the pass)
-constexpr double VWIN = 1.25;   // estimate / tolerance ratio below which the gap is checked
+constexpr double VWIN = 2.0;    // estimate / tolerance ratio below which the gap is checked
 
 // ============================================================== setup kernels
 // Padded atom-major copy of D: dcm[a][n] (zeros beyond N and K).
@@ -444,7 +446,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
   const bool tile_on = alive && static_cast<double>(a.tminm[tix]) <= r_act;
   if (!__ballot(tile_on)) {
     if (lane < MT) {
-      a.pz[tix] = 0.f;
+      a.pz[tix] = 0.0;
       a.pom[tix] = 0.0;
       a.pact[tix] = 0;
       a.umask[tix] = 0u;
@@ -452,25 +454,34 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
     if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
     return;
   }
+  // Each 64-row chunk is accumulated in FP32 on the matrix cores from zero and then added
+  // to FP64 registers, so an FP32 rounding chain spans 3 x 64 products, not 3 N.
   const int kk = (lane / MT) * 8;
   const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
   const uint16_t* dcol = a.dcm + static_cast<int64_t>(a0 + (lane % MT)) * a.Np + kk;
   const uint16_t* t0 = a.Ths + static_cast<int64_t>(bl) * a.Np + kk;
-  f32x16 c;
+  double zacc[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) c[i] = 0.f;
+  for (int i = 0; i < 16; ++i) zacc[i] = 0.0;
+  for (int n0 = 0; n0 < a.Np; n0 += 64) {
+    f32x16 c;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c[i] = 0.f;
 #pragma unroll 2
-  for (int n0 = 0; n0 < a.Np; n0 += 16) {
-    const bf16x8 ad = as_bf16x8(ldg16(dcol + n0));
-    const bf16x8 h = as_bf16x8(ldg16(t0 + n0));
-    const bf16x8 m = as_bf16x8(ldg16(t0 + plane + n0));
-    const bf16x8 l = as_bf16x8(ldg16(t0 + 2 * plane + n0));
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, h, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
+    for (int n1 = n0; n1 < n0 + 64; n1 += 16) {
+      const bf16x8 ad = as_bf16x8(ldg16(dcol + n1));
+      const bf16x8 h = as_bf16x8(ldg16(t0 + n1));
+      const bf16x8 m = as_bf16x8(ldg16(t0 + plane + n1));
+      const bf16x8 l = as_bf16x8(ldg16(t0 + 2 * plane + n1));
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, h, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) zacc[i] += static_cast<double>(c[i]);
   }
   // epilogue: lane holds signal bl, atoms a0 + 8 q + (lane / 32) * 4 + e
-  float zm = 0.f;
+  double zm = 0.0;
   double om = 0.0;
   int nact = 0, nsup = 0;
   uint32_t bits = 0u;
@@ -491,6 +502,9 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) any |= static_cast<double>(mm[e]) <= r_act;
       if (!any) continue;
+      *reinterpret_cast<float4*>(a.Z + o) =
+          make_float4(static_cast<float>(zacc[4 * q]), static_cast<float>(zacc[4 * q + 1]),
+                      static_cast<float>(zacc[4 * q + 2]), static_cast<float>(zacc[4 * q + 3]));
       const float4 u4 = *reinterpret_cast<const float4*>(Uin + o);
       const float4 x4 = *reinterpret_cast<const float4*>(a.X + o);
       float uu[4] = {u4.x, u4.y, u4.z, u4.w};
@@ -498,13 +512,13 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (!(static_cast<double>(mm[e]) <= r_act)) continue;
-        const float z = c[4 * q + e];
-        zm = fmaxf(zm, fabsf(z));
+        const double z = zacc[4 * q + e];
+        zm = fmax(zm, fabs(z));
         const double p = uu[e];
         om += fabs(p);
         ++nact;
         nsup += uu[e] != 0.f;
-        const double v = p - static_cast<double>(z) * invL;
+        const double v = p - z * invL;
         const double mag = fabs(v) - thr;
         const double xn = mag > 0.0 ? copysign(mag, v) : 0.0;
         const double un = xn + beta * (xn - static_cast<double>(xx[e]));
@@ -519,7 +533,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
     }
   }
   // the two half-waves hold the same signals on different atoms of the tile
-  zm = fmaxf(zm, __shfl_xor(zm, 32, BW));
+  zm = fmax(zm, __shfl_xor(zm, 32, BW));
   om += __shfl_xor(om, 32, BW);
   int cnt = nact | (nsup << 8);
   cnt += __shfl_xor(cnt, 32, BW);
@@ -548,7 +562,7 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   int nact = 0, nsup = 0;
   for (int t = lane; t < ntile; t += BW) {
     const int64_t o = static_cast<int64_t>(t) * a.Bp + s;
-    zm = fmax(zm, static_cast<double>(a.pz[o]));
+    zm = fmax(zm, a.pz[o]);
     om += a.pom[o];
     const int c = a.pact[o];
     nact += c & 0xff;
@@ -614,43 +628,78 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   if (flag) a.vlist[atomicAdd(a.vcount, 1)] = s;
 }
 
-constexpr int VCH = 2048;  // theta rows staged in LDS per pass of the verification
-
-// Verification: FP64 max over the atoms active in this iteration of |d_i^T theta| for the
-// flagged signals (one thread per atom, theta staged in LDS).
-__device__ __forceinline__ void vcorr_one(const BArgs& a, int s, double* th_lds, double* sd) {
-  const int i = blockIdx.x * TB + threadIdx.x;
-  const bool act = i < a.K &&
-                   static_cast<double>(a.marg[static_cast<int64_t>(s) * a.Kp + i]) <= a.inst[s].r_prev;
-  const uint16_t* col = a.dcm + static_cast<int64_t>(i < a.K ? i : 0) * a.Np;
-  const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
-  double acc = 0.0;
-  for (int n0 = 0; n0 < a.Np; n0 += VCH) {
-    const int len = min(VCH, a.Np - n0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < len; e += TB) th_lds[e] = th[n0 + e];
-    __syncthreads();
-    if (act) {
-      for (int n = 0; n < len; n += 8) {
-        const uint4 d = ldg16(col + n0 + n);
-        const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+// Verification, step 1: candidates for the FP64 maximum over the atoms active in this
+// iteration of |d_i^T theta|, for the flagged signals.  With e a bound on
+// |z_hat_i - d_i^T theta| for every atom (the accumulation bound plus the FP32 rounding of
+// the stored z_hat), an atom with |z_hat_i| < max_k |z_hat_k| - 2 e cannot attain the
+// maximum; the others are listed in atom order.  One block per flagged signal at a time.
+__global__ __launch_bounds__(TB) void k_b_vcand(BArgs a) {
+  __shared__ int scan[NWB];
+  const int nflag = *a.vcount;
+  for (int j = blockIdx.x; j < nflag; j += gridDim.x) {
+    const int s = a.vlist[j];
+    const Inst& st = a.inst[s];
+    const double r_act = st.r_prev;
+    const double zmax = st.zmax;
+    const double e = a.gamma_acc * a.dsc[0] * sqrt(st.tt) + 0x1p-23 * zmax;
+    const double thr = zmax - 2.0 * e;
+    const float* z = a.Z + static_cast<int64_t>(s) * a.Kp;
+    const float* mg = a.marg + static_cast<int64_t>(s) * a.Kp;
+    int* out = a.cidx + static_cast<int64_t>(s) * a.Kp;
+    int base = 0;
+    for (int i0 = 0; i0 < a.K; i0 += TB * 4) {
+      int mine[4], cnt = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          acc = fma(static_cast<double>(__uint_as_float(w[e] << 16)), th_lds[n + 2 * e], acc);
-          acc = fma(static_cast<double>(__uint_as_float(w[e] & 0xffff0000u)), th_lds[n + 2 * e + 1], acc);
-        }
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + threadIdx.x * 4 + k;
+        const bool c = i < a.K && static_cast<double>(mg[i]) <= r_act &&
+                       fabs(static_cast<double>(z[i])) >= thr;
+        mine[k] = c ? i : -1;
+        cnt += c;
       }
+      int total;
+      int pos = base + block_exclusive_scan<NWB>(cnt, scan, &total);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (mine[k] >= 0) out[pos++] = mine[k];
+      base += total;
     }
+    if (threadIdx.x == 0) a.ccount[s] = base;
   }
-  const double zm = block_max<double, NWB>(fabs(acc), sd);
-  if (threadIdx.x == 0) a.vz[static_cast<int64_t>(blockIdx.x) * a.Bp + s] = zm;
 }
 
-__global__ __launch_bounds__(TB) void k_b_vcorr(BArgs a) {
-  __shared__ double th_lds[VCH];
-  __shared__ double sd[NWB];
+// Verification, step 2: exact FP64 |d_i^T theta| of every candidate of every flagged
+// signal, one wave per candidate (rows across the lanes), all waves of the grid sharing
+// the work in a fixed order.
+__global__ __launch_bounds__(TB) void k_b_vdot(BArgs a) {
   const int nflag = *a.vcount;
-  for (int j = blockIdx.y; j < nflag; j += VY) vcorr_one(a, a.vlist[j], th_lds, sd);
+  const int lane = threadIdx.x % BW;
+  const int nw = gridDim.x * NWB;
+  const int gw = blockIdx.x * NWB + threadIdx.x / BW;
+  int off = 0;
+  for (int j = 0; j < nflag; ++j) {
+    const int s = a.vlist[j];
+    const int cnt = a.ccount[s];
+    const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
+    for (int c = ((gw - off) % nw + nw) % nw; c < cnt; c += nw) {
+      const int64_t slot = static_cast<int64_t>(s) * a.Kp + c;
+      const uint16_t* col = a.dcm + static_cast<int64_t>(a.cidx[slot]) * a.Np;
+      double acc = 0.0;
+      for (int n = lane * 8; n < a.Np; n += BW * 8) {
+        const uint4 d = ldg16(col + n);
+        const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 t2 = *reinterpret_cast<const double2*>(th + n + 2 * q);
+          acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2.x, acc);
+          acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2.y, acc);
+        }
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) a.cval[slot] = fabs(acc);
+    }
+    off += cnt;
+  }
 }
 
 // Exact gap of the flagged signals (one wave per slot) at the feasible dual point
@@ -663,9 +712,9 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
   if (s >= a.Bp) return;
   Inst& st = a.inst[s];
   if (st.done != 0 || !st.verify) return;
-  const int nac = (a.K + TB - 1) / TB;
+  const int cnt = a.ccount[s];
   double zm = 0.0;
-  for (int c = lane; c < nac; c += BW) zm = fmax(zm, a.vz[static_cast<int64_t>(c) * a.Bp + s]);
+  for (int c = lane; c < cnt; c += BW) zm = fmax(zm, a.cval[static_cast<int64_t>(s) * a.Kp + c]);
   zm = wave_max(zm);
   if (lane != 0) return;
   const double lam = st.lam, tt = st.tt, ty = st.ty;

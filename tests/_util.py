@@ -53,3 +53,16 @@ def screened_sets_agree(gpu_mask, ref_mask, margins_units, r_ref, r_gpu, slack, 
     units = diff if unit_of_atom is None else np.unique(unit_of_atom[diff])
     tol = band + abs(r_gpu - r_ref) + slack
     return bool(np.all(np.abs(margins_units[units] - r_ref) <= tol))
+
+
+def stop_iteration_bracket(D, y, lam, L, tol_abs, rule="fista", test="dst3", lo=1.3, hi=0.7):
+    """First iterations at which the oracle's gap certificate falls below lo * tol and below
+    hi * tol.  FISTA's gap oscillates near convergence, so a device run whose gap differs
+    from the oracle's by a fraction of the tolerance can stop at a later dip; its stopping
+    iteration must fall within this bracket."""
+    ref = oracle.solve_lasso(D, y, lam=lam, rule=rule, test=test, L=L, max_iter=50000,
+                             gap_tol=hi * tol_abs / float(y @ y), record=True)
+    gaps = [h["gap"] for h in ref.history]
+    t_lo = next(k + 1 for k, g in enumerate(gaps) if g <= lo * tol_abs)
+    t_hi = next(k + 1 for k, g in enumerate(gaps) if g <= hi * tol_abs)
+    return t_lo, t_hi
