@@ -430,13 +430,21 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
 // non-zero bits of u_t per 32-atom tile to umask.  Per (32-atom tile, signal): max |z|
 // and Omega(p) = sum |p_i| over the active pairs, and the pair counts.  Wave tile 32
 // atoms x 32 signals; block 2 x 2 wave tiles.
+constexpr int ZR = 64;       // rows of D and Theta staged in LDS per step
+constexpr int ZP = ZR + 8;   // padded LDS row (144 bytes: fragment reads free of bank conflicts)
+
 __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
                                                 float* __restrict__ Uout) {
+  __shared__ __align__(16) uint16_t sA[64][ZP];     // 64 atoms x 64 rows
+  __shared__ __align__(16) uint16_t sB[3][64][ZP];  // 3 parts x 64 signals x 64 rows
+  __shared__ int s_on[NWB];
   const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
   const int64_t gw = (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * NWB + wave;
   if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw] = wall_clock64();
-  const int a0 = blockIdx.x * 64 + (wave / 2) * MT;
-  const int b0 = blockIdx.y * 64 + (wave % 2) * MT;
+  const int a0b = blockIdx.x * 64, b0b = blockIdx.y * 64;
+  const int wa = (wave / 2) * MT, wb = (wave % 2) * MT;  // this wave's 32 x 32 sub-tile
+  const int a0 = a0b + wa;
+  const int b0 = b0b + wb;
   const int bl = b0 + (lane % MT);  // signal of this lane's accumulator column
   const int at = a0 / MT;
   const Inst& sl = a.inst[bl];
@@ -444,41 +452,69 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
   const double r_act = sl.r_keep;  // active pairs: margin <= r_act
   const int64_t tix = static_cast<int64_t>(at) * a.Bp + bl;
   const bool tile_on = alive && static_cast<double>(a.tminm[tix]) <= r_act;
-  if (!__ballot(tile_on)) {
+  const bool wave_on = __ballot(tile_on) != 0;
+  if (lane == 0) s_on[wave] = wave_on ? 1 : 0;
+  __syncthreads();
+  const bool block_on = (s_on[0] | s_on[1] | s_on[2] | s_on[3]) != 0;
+  if (!wave_on) {
     if (lane < MT) {
       a.pz[tix] = 0.0;
       a.pom[tix] = 0.0;
       a.pact[tix] = 0;
       a.umask[tix] = 0u;
     }
+  }
+  if (!block_on) {
     if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
     return;
   }
-  // Each 64-row chunk is accumulated in FP32 on the matrix cores from zero and then added
-  // to FP64 registers, so an FP32 rounding chain spans 3 x 64 products, not 3 N.
-  const int kk = (lane / MT) * 8;
+  // The block stages 64-row chunks of its 64 atoms and of the three parts of its 64
+  // signals' theta through LDS with 128-byte coalesced loads; each wave reads its MFMA
+  // fragments from LDS.  Each chunk is accumulated in FP32 on the matrix cores from zero
+  // and then added to FP64 registers, so an FP32 rounding chain spans 3 x 64 products.
   const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
-  const uint16_t* dcol = a.dcm + static_cast<int64_t>(a0 + (lane % MT)) * a.Np + kk;
-  const uint16_t* t0 = a.Ths + static_cast<int64_t>(bl) * a.Np + kk;
+  const int kk = (lane / MT) * 8;
   double zacc[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) zacc[i] = 0.0;
-  for (int n0 = 0; n0 < a.Np; n0 += 64) {
-    f32x16 c;
+  for (int n0 = 0; n0 < a.Np; n0 += ZR) {
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) c[i] = 0.f;
-#pragma unroll 2
-    for (int n1 = n0; n1 < n0 + 64; n1 += 16) {
-      const bf16x8 ad = as_bf16x8(ldg16(dcol + n1));
-      const bf16x8 h = as_bf16x8(ldg16(t0 + n1));
-      const bf16x8 m = as_bf16x8(ldg16(t0 + plane + n1));
-      const bf16x8 l = as_bf16x8(ldg16(t0 + 2 * plane + n1));
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, h, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
+    for (int r = 0; r < 2; ++r) {  // 64 rows x 128 bytes of D: 512 16-byte pieces
+      const int e = threadIdx.x + r * TB;
+      const int row = e / 8, col = (e % 8) * 8;
+      *reinterpret_cast<uint4*>(&sA[row][col]) =
+          ldg16(a.dcm + static_cast<int64_t>(a0b + row) * a.Np + n0 + col);
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) zacc[i] += static_cast<double>(c[i]);
+    for (int r = 0; r < 6; ++r) {  // 3 x 64 rows x 128 bytes of theta
+      const int e = threadIdx.x + r * TB;
+      const int p = e / 512, row = (e % 512) / 8, col = (e % 8) * 8;
+      *reinterpret_cast<uint4*>(&sB[p][row][col]) =
+          ldg16(a.Ths + p * plane + static_cast<int64_t>(b0b + row) * a.Np + n0 + col);
+    }
+    __syncthreads();
+    if (wave_on) {
+      f32x16 c;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) c[i] = 0.f;
+#pragma unroll
+      for (int s16 = 0; s16 < ZR; s16 += 16) {
+        const bf16x8 ad = as_bf16x8(*reinterpret_cast<const uint4*>(&sA[wa + lane % MT][s16 + kk]));
+        const bf16x8 h = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[0][wb + lane % MT][s16 + kk]));
+        const bf16x8 m = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[1][wb + lane % MT][s16 + kk]));
+        const bf16x8 l = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[2][wb + lane % MT][s16 + kk]));
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) zacc[i] += static_cast<double>(c[i]);
+    }
+  }
+  if (!wave_on) {
+    if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
+    return;
   }
   // epilogue: lane holds signal bl, atoms a0 + 8 q + (lane / 32) * 4 + e
   double zm = 0.0;
