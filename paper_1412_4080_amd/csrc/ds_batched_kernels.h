@@ -477,23 +477,36 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
   double zacc[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) zacc[i] = 0.0;
-  for (int n0 = 0; n0 < a.Np; n0 += ZR) {
-    __syncthreads();
+  // chunk n0 + ZR is fetched into registers while chunk n0 is multiplied
+  uint4 pa[2], pb[6];
+  auto fetch = [&](int n0) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {  // 64 rows x 128 bytes of D: 512 16-byte pieces
       const int e = threadIdx.x + r * TB;
-      const int row = e / 8, col = (e % 8) * 8;
-      *reinterpret_cast<uint4*>(&sA[row][col]) =
-          ldg16(a.dcm + static_cast<int64_t>(a0b + row) * a.Np + n0 + col);
+      pa[r] = ldg16(a.dcm + static_cast<int64_t>(a0b + e / 8) * a.Np + n0 + (e % 8) * 8);
     }
 #pragma unroll
     for (int r = 0; r < 6; ++r) {  // 3 x 64 rows x 128 bytes of theta
       const int e = threadIdx.x + r * TB;
-      const int p = e / 512, row = (e % 512) / 8, col = (e % 8) * 8;
-      *reinterpret_cast<uint4*>(&sB[p][row][col]) =
-          ldg16(a.Ths + p * plane + static_cast<int64_t>(b0b + row) * a.Np + n0 + col);
+      pb[r] = ldg16(a.Ths + (e / 512) * plane + static_cast<int64_t>(b0b + (e % 512) / 8) * a.Np + n0 +
+                    (e % 8) * 8);
+    }
+  };
+  fetch(0);
+  for (int n0 = 0; n0 < a.Np; n0 += ZR) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = threadIdx.x + r * TB;
+      *reinterpret_cast<uint4*>(&sA[e / 8][(e % 8) * 8]) = pa[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const int e = threadIdx.x + r * TB;
+      *reinterpret_cast<uint4*>(&sB[e / 512][(e % 512) / 8][(e % 8) * 8]) = pb[r];
     }
     __syncthreads();
+    if (n0 + ZR < a.Np) fetch(n0 + ZR);
     if (wave_on) {
       f32x16 c;
 #pragma unroll
