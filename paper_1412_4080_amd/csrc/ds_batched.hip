@@ -60,7 +60,7 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.pom = take(nt * bp * 8);
   l.pact = take(nt * bp * 4);
   l.Z = take(bp * kp * 4);
-  l.ccount = take(bp * 4);
+  l.ccount = take(bp * ((K + VC - 1) / VC) * 4);
   l.cidx = take(bp * kp * 4);
   l.cval = take(bp * kp * 8);
   l.inst = take(bp * sizeof(Inst));
@@ -248,7 +248,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   const dim3 g_theta(l.nrb, l.Bp);
   const dim3 g_z(l.Kp / 64, l.Bp / 64);
   const dim3 g_slot4(l.Bp / NWB);
-  const dim3 g_vca(64), g_vdot(512);
+  const dim3 g_vca((l.K + VC - 1) / VC, VG), g_vdot(512);
   const dim3 g_scr((l.Kp / 4 + TB - 1) / TB, l.Bp);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evz, evt;
   // instrumented runs: every Z-GEMM wave stamps the device wall clock at its start and

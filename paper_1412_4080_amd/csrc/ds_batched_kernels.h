@@ -87,7 +87,7 @@ struct BArgs {
   double* pom;          // (Kp/32) x Bp partial Omega(p)
   int* pact;            // (Kp/32) x Bp active pairs | (non-zeros of p << 8)
   float* Z;             // Bp x Kp correlations of the pairs computed this iteration
-  int* ccount;          // Bp candidates of the verification per flagged signal
+  int* ccount;          // Bp x (K/1024 rounded up) candidates per flagged signal and range
   int* cidx;            // Bp x Kp candidate atoms
   double* cval;         // Bp x Kp their exact |d_i^T theta|
   Inst* inst;           // Bp
@@ -97,7 +97,7 @@ struct BArgs {
   uint64_t* kclk;       // NULL, or 2 wall-clock stamps per Z-GEMM wave (start, end)
 };
 
-constexpr double VWIN = 2.0;    // estimate / tolerance ratio below which the gap is checked
+constexpr double VWIN = 1.25;   // estimate / tolerance ratio below which the gap is checked
 
 // ============================================================== setup kernels
 // Padded atom-major copy of D: dcm[a][n] (zeros beyond N and K).
@@ -327,18 +327,18 @@ __global__ __launch_bounds__(TB) void k_b_tile_min(BArgs a, float* __restrict__ 
 
 // ============================================================== iteration kernels
 constexpr int TR = 512;  // rows of theta per block (64 lanes x 8 rows)
-constexpr int LW = 64;   // mask words (32 atoms each) per support-list chunk
+constexpr int TW = 128;  // mask words (32 atoms each) per support-list round
 
 // theta = D_S p - y for every running signal, S the support of p = u_{t-1} (from the
 // non-zero bits the previous update left), FP64 accumulation; writes theta in FP64, the
 // bfloat16 parts of its FP32 rounding, and per-block FP64 ||theta||^2 and theta^T y.
-// Block: 512 rows of one signal; its four waves split the support list and are summed in
-// a fixed order.  Also retires the signals finished in the previous iteration and clears
-// the verification list.
+// Block: 512 rows of one signal.  The support list (atom indices) is built through LDS
+// 4096 atoms at a time by the whole block; the four waves split it, each lane
+// accumulating 8 rows, and the waves are summed in a fixed order.  Also retires the
+// signals finished in the previous iteration and clears the verification list.
 __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict__ Uin) {
-  __shared__ int sidx[LW * MT];
-  __shared__ float sval[LW * MT];
-  __shared__ int s_cnt;
+  __shared__ int sidx[TW * MT];
+  __shared__ int scan[NWB];
   __shared__ double red[NWB][TR + 8];
   __shared__ double sd[NWB];
   const int s = blockIdx.y;
@@ -355,35 +355,22 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int nw = a.Kp / MT;
   const float* u = Uin + static_cast<int64_t>(s) * a.Kp;
-  for (int w0 = 0; w0 < nw; w0 += LW) {
-    if (wave == 0) {
-      const int w = w0 + lane;
-      uint32_t m = w < nw ? a.umask[static_cast<int64_t>(w) * a.Bp + s] : 0u;
-      const int c = __popc(m);
-      int incl = c;
-#pragma unroll
-      for (int o = 1; o < BW; o <<= 1) {
-        const int v = __shfl_up(incl, o, BW);
-        if (lane >= o) incl += v;
-      }
-      int pos = incl - c;
-      while (m != 0u) {
-        const int b = __ffs(m) - 1;
-        m &= m - 1u;
-        const int at = w * MT + b;
-        sidx[pos] = at;
-        sval[pos] = u[at];
-        ++pos;
-      }
-      if (lane == BW - 1) s_cnt = incl;
+  for (int w0 = 0; w0 < nw; w0 += TW) {
+    const int w = w0 + threadIdx.x;
+    uint32_t m = (threadIdx.x < TW && w < nw) ? a.umask[static_cast<int64_t>(w) * a.Bp + s] : 0u;
+    int total;
+    int pos = block_exclusive_scan<NWB>(__popc(m), scan, &total);
+    while (m != 0u) {
+      sidx[pos++] = w * MT + __ffs(m) - 1;
+      m &= m - 1u;
     }
     __syncthreads();
-    const int cnt = s_cnt;
     if (rows_ok) {
 #pragma unroll 2
-      for (int j = wave; j < cnt; j += NWB) {
-        const double uv = sval[j];
-        const uint4 d = ldg16(a.dcm + static_cast<int64_t>(sidx[j]) * a.Np + nl);
+      for (int j = wave; j < total; j += NWB) {
+        const int at = sidx[j];
+        const double uv = u[at];
+        const uint4 d = ldg16(a.dcm + static_cast<int64_t>(at) * a.Np + nl);
         const uint32_t wd[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -407,10 +394,10 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
     const double yv = a.Y[o];
     const double th = n < a.N ? v - yv : 0.0;
     a.th64[o] = th;
-    uint16_t h, m, l;
-    split3(static_cast<float>(th), h, m, l);
+    uint16_t h, mm, l;
+    split3(static_cast<float>(th), h, mm, l);
     a.Ths[o] = h;
-    a.Ths[plane + o] = m;
+    a.Ths[plane + o] = mm;
     a.Ths[2 * plane + o] = l;
     tt = fma(th, th, tt);
     ty = fma(th, yv, ty);
@@ -423,13 +410,6 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
   }
 }
 
-// Z = D^T Theta on the 32 x 32 tiles holding an active pair, fused with the update of
-// Table 1 on the active pairs: x_t = ST(p - z / L, lambda / L) (soft threshold), and for
-// FISTA l_t = (1 + sqrt(1 + 4 l_{t-1}^2)) / 2, u_t = x_t + (l_{t-1} - 1) / l_t (x_t - x_{t-1})
-// (ISTA: u_t = x_t).  p = u_{t-1} is read from Uin, u_t written to Uout, and the
-// non-zero bits of u_t per 32-atom tile to umask.  Per (32-atom tile, signal): max |z|
-// and Omega(p) = sum |p_i| over the active pairs, and the pair counts.  Wave tile 32
-// atoms x 32 signals; block 2 x 2 wave tiles.
 constexpr int ZR = 64;       // rows of D and Theta staged in LDS per step
 constexpr int ZP = ZR + 8;   // padded LDS row (144 bytes: fragment reads free of bank conflicts)
 
@@ -677,15 +657,20 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   if (flag) a.vlist[atomicAdd(a.vcount, 1)] = s;
 }
 
+constexpr int VC = TB * 4;  // atoms per candidate block
+constexpr int VG = 16;      // groups of flagged signals compacted at once (grid y)
+
 // Verification, step 1: candidates for the FP64 maximum over the atoms active in this
 // iteration of |d_i^T theta|, for the flagged signals.  With e a bound on
 // |z_hat_i - d_i^T theta| for every atom (the accumulation bound plus the FP32 rounding of
 // the stored z_hat), an atom with |z_hat_i| < max_k |z_hat_k| - 2 e cannot attain the
-// maximum; the others are listed in atom order.  One block per flagged signal at a time.
+// maximum; the others are listed in atom order.  Block: 1024 atoms of one flagged signal.
 __global__ __launch_bounds__(TB) void k_b_vcand(BArgs a) {
   __shared__ int scan[NWB];
   const int nflag = *a.vcount;
-  for (int j = blockIdx.x; j < nflag; j += gridDim.x) {
+  const int nch = (a.K + VC - 1) / VC;
+  const int i0 = blockIdx.x * VC;
+  for (int j = blockIdx.y; j < nflag; j += gridDim.y) {
     const int s = a.vlist[j];
     const Inst& st = a.inst[s];
     const double r_act = st.r_prev;
@@ -694,60 +679,73 @@ __global__ __launch_bounds__(TB) void k_b_vcand(BArgs a) {
     const double thr = zmax - 2.0 * e;
     const float* z = a.Z + static_cast<int64_t>(s) * a.Kp;
     const float* mg = a.marg + static_cast<int64_t>(s) * a.Kp;
-    int* out = a.cidx + static_cast<int64_t>(s) * a.Kp;
-    int base = 0;
-    for (int i0 = 0; i0 < a.K; i0 += TB * 4) {
-      int mine[4], cnt = 0;
+    int* out = a.cidx + static_cast<int64_t>(s) * a.Kp + i0;
+    int mine[4], cnt = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = i0 + threadIdx.x * 4 + k;
-        const bool c = i < a.K && static_cast<double>(mg[i]) <= r_act &&
-                       fabs(static_cast<double>(z[i])) >= thr;
-        mine[k] = c ? i : -1;
-        cnt += c;
-      }
-      int total;
-      int pos = base + block_exclusive_scan<NWB>(cnt, scan, &total);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (mine[k] >= 0) out[pos++] = mine[k];
-      base += total;
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + threadIdx.x * 4 + k;
+      const bool c = i < a.K && static_cast<double>(mg[i]) <= r_act &&
+                     fabs(static_cast<double>(z[i])) >= thr;
+      mine[k] = c ? i : -1;
+      cnt += c;
     }
-    if (threadIdx.x == 0) a.ccount[s] = base;
+    int total;
+    int pos = block_exclusive_scan<NWB>(cnt, scan, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (mine[k] >= 0) out[pos++] = mine[k];
+    if (threadIdx.x == 0) a.ccount[static_cast<int64_t>(s) * nch + blockIdx.x] = total;
+    __syncthreads();
   }
 }
 
 // Verification, step 2: exact FP64 |d_i^T theta| of every candidate of every flagged
 // signal, one wave per candidate (rows across the lanes), all waves of the grid sharing
 // the work in a fixed order.
+constexpr int VLDS = 2048;  // (signal, range) pairs staged in LDS per round
+
 __global__ __launch_bounds__(TB) void k_b_vdot(BArgs a) {
+  __shared__ int ssig[VLDS];
+  __shared__ int scnt[VLDS];
   const int nflag = *a.vcount;
   const int lane = threadIdx.x % BW;
   const int nw = gridDim.x * NWB;
   const int gw = blockIdx.x * NWB + threadIdx.x / BW;
-  int off = 0;
-  for (int j = 0; j < nflag; ++j) {
-    const int s = a.vlist[j];
-    const int cnt = a.ccount[s];
-    const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
-    for (int c = ((gw - off) % nw + nw) % nw; c < cnt; c += nw) {
-      const int64_t slot = static_cast<int64_t>(s) * a.Kp + c;
-      const uint16_t* col = a.dcm + static_cast<int64_t>(a.cidx[slot]) * a.Np;
-      double acc = 0.0;
-      for (int n = lane * 8; n < a.Np; n += BW * 8) {
-        const uint4 d = ldg16(col + n);
-        const uint32_t w[4] = {d.x, d.y, d.z, d.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double2 t2 = *reinterpret_cast<const double2*>(th + n + 2 * q);
-          acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2.x, acc);
-          acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2.y, acc);
-        }
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) a.cval[slot] = fabs(acc);
+  const int nch = (a.K + VC - 1) / VC;
+  const int npair = nflag * nch;
+  int off = 0;  // work items before the current pair, in the fixed order of all waves
+  for (int p0 = 0; p0 < npair; p0 += VLDS) {
+    const int np = min(VLDS, npair - p0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < np; e += TB) {
+      const int jc = p0 + e;
+      const int sg = a.vlist[jc / nch];
+      ssig[e] = sg;
+      scnt[e] = a.ccount[static_cast<int64_t>(sg) * nch + jc % nch];
     }
-    off += cnt;
+    __syncthreads();
+    for (int e = 0; e < np; ++e) {
+      const int s = ssig[e], ch = (p0 + e) % nch, cnt = scnt[e];
+      const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
+      for (int c = ((gw - off) % nw + nw) % nw; c < cnt; c += nw) {
+        const int64_t slot = static_cast<int64_t>(s) * a.Kp + ch * VC + c;
+        const uint16_t* col = a.dcm + static_cast<int64_t>(a.cidx[slot]) * a.Np;
+        double acc = 0.0;
+        for (int n = lane * 8; n < a.Np; n += BW * 8) {
+          const uint4 d = ldg16(col + n);
+          const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double2 t2 = *reinterpret_cast<const double2*>(th + n + 2 * q);
+            acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2.x, acc);
+            acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2.y, acc);
+          }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) a.cval[slot] = fabs(acc);
+      }
+      off += cnt;
+    }
   }
 }
 
@@ -761,9 +759,13 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
   if (s >= a.Bp) return;
   Inst& st = a.inst[s];
   if (st.done != 0 || !st.verify) return;
-  const int cnt = a.ccount[s];
+  const int nch = (a.K + VC - 1) / VC;
   double zm = 0.0;
-  for (int c = lane; c < cnt; c += BW) zm = fmax(zm, a.cval[static_cast<int64_t>(s) * a.Kp + c]);
+  for (int ch = 0; ch < nch; ++ch) {
+    const int cnt = a.ccount[static_cast<int64_t>(s) * nch + ch];
+    for (int c = lane; c < cnt; c += BW)
+      zm = fmax(zm, a.cval[static_cast<int64_t>(s) * a.Kp + ch * VC + c]);
+  }
   zm = wave_max(zm);
   if (lane != 0) return;
   const double lam = st.lam, tt = st.tt, ty = st.ty;
