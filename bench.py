@@ -270,6 +270,43 @@ def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96
             "open_loop": opens, "per_dict_closed_loop": per_dict}
 
 
+def flops_leg(binding, Dd, ys, L, nsig=3):
+    """The experiments section's cost model, normalised by the unscreened run: per
+    iteration (|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N flops, plus K N for the screening
+    set-up, from the per-iteration trace of each solve; wall time normalised the same way.
+    Dynamic and static DST3 with FISTA on the headline workload."""
+    import torch
+
+    def run(y, r, test, screening):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, _, tr = binding.solve_one(Dd, y, r, rule="fista", test=test, step_L=L,
+                                           gap_tol=GAP_TOL, max_iter=20000, trace=True,
+                                           screened=False, screening=screening)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fl = sum((t["n_active"] + t["nnz"]) * N + 6 * t["n_active"] + 5 * N for t in tr)
+        if test != "none":
+            fl += K * N
+        return fl, dt, info["iters"]
+
+    out = []
+    for r in RATIOS:
+        acc = {"dynamic": [0.0, 0.0], "static": [0.0, 0.0], "none": [0.0, 0.0]}
+        for j in range(nsig):
+            for mode, test, scr in (("dynamic", "dst3", "dynamic"), ("static", "dst3", "static"),
+                                    ("none", "none", "dynamic")):
+                fl, dt, _ = run(ys[j], r, test, scr)
+                acc[mode][0] += fl
+                acc[mode][1] += dt
+        out.append({"lambda_ratio": r,
+                    "flops_dynamic_over_plain": round(acc["dynamic"][0] / acc["none"][0], 4),
+                    "flops_static_over_plain": round(acc["static"][0] / acc["none"][0], 4),
+                    "time_dynamic_over_plain": round(acc["dynamic"][1] / acc["none"][1], 4),
+                    "time_static_over_plain": round(acc["static"][1] / acc["none"][1], 4)})
+    return {"workload": "lasso_fista_dst3_gaussian_2000x10000_f32", "signals": nsig, "per_ratio": out}
+
+
 def kernel_source_sha(paths):
     """sha256 over the concatenated sources a kernel is built from."""
     import hashlib
@@ -326,8 +363,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served",
-                    help="comma list of legs: single (headline), batched, served.  Profiling "
+    ap.add_argument("--legs", default="single,batched,served,flops",
+                    help="comma list of legs: single (headline), batched, served, flops.  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
@@ -422,6 +459,8 @@ def main():
         b = batched_leg(binding, D, max(1, args.steps // 2), 1)
         b["over_plain_single"] = round(b["solves_per_s"] / plain, 2)
         out["batched"] = b
+    if "flops" in legs:
+        out["flops_model"] = flops_leg(binding, Dd, ys, L, nsig=min(3, len(ys)))
     if "served" in legs:
         out["served"] = served_leg(binding)
     if not args.no_cpu:

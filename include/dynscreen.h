@@ -83,7 +83,9 @@ typedef struct {
   double gap_tol;    /* > 0: stop once the duality-gap certificate <= gap_tol * ||y||^2.
                         0: run exactly max_iter iterations. */
   int32_t max_iter;  /* >= 1 */
-  int32_t reserved;  /* must be 0 */
+  int32_t screening; /* 0: dynamic (Algorithm 3: the test is re-run at every iteration).
+                        1: static (Algorithms 1 and 4: the test is run once, with the dual
+                        point of the first iteration, i.e. the static SAFE / ST3 rules). */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which

@@ -234,7 +234,7 @@ def _trivial(K, lam, lam_max, L, G=None):
 
 
 def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
-                max_iter=1000, gap_tol=1e-6, record=False) -> OracleResult:
+                max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic") -> OracleResult:
     """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
@@ -242,6 +242,10 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     v_t = mu_t theta_t, the sphere radius r_t of the chosen test (SAFE Lemma 1,
     DST3 Lemma 2, or none), the screened set I_t = {i : m_i > r_t} U I_{t-1},
     and the reduction of D and of the primal variables to the complement of I_t.
+
+    screening="static" runs the test once, at the first iteration, where the dual point
+    from x_0 = 0 makes it the static test of Algorithms 1 and 4 (static SAFE, ST3); the
+    first update does not depend on the atoms that test removes (their prox output is 0).
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -300,7 +304,8 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         if converged or t == max_iter:
             break
         # ---- screening: I_t = {i : T_v(i)} U I_{t-1}, then reduce D and X ----
-        screened = screened | (m > r)
+        if screening == "dynamic" or t == 1:
+            screened = screened | (m > r)
         keep = ~screened[active]
         if not keep.all():
             Dt = Dt[:, keep]
@@ -327,12 +332,13 @@ def _as_groups(K, groups):
 
 def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="ista",
                       test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
-                      record=False) -> OracleResult:
+                      record=False, screening="dynamic") -> OracleResult:
     """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
 
     groups: a partition of range(K) (list of index arrays, or contiguous CSR
     offsets); w: group weights, default sqrt(|g|).  Tests: GSAFE (Lemma 4),
-    DGST3 (Lemma 5) or none; the screening unit is the group.
+    DGST3 (Lemma 5) or none; the screening unit is the group.  screening="static"
+    runs the test once, at the first iteration (the static group tests).
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -341,6 +347,7 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     G = len(groups)
     w = np.sqrt([len(g) for g in groups]).astype(np.float64) if w is None else np.asarray(w, np.float64)
     assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista")
+    assert screening in ("dynamic", "static")
     lam_max, g_star = lambda_max_group(D, y, groups, w)
     if lam is None:
         lam = float(lam_ratio) * lam_max
@@ -405,7 +412,8 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
             converged = True
         if converged or t == max_iter:
             break
-        screened_g = screened_g | (m > r)
+        if screening == "dynamic" or t == 1:
+            screened_g = screened_g | (m > r)
         keep_g = ~screened_g[act_g]
         if not keep_g.all():
             keep_cols = np.concatenate([local[j] for j in range(act_g.size) if keep_g[j]]) \

@@ -38,7 +38,7 @@ class Problem(C.Structure):
 class Params(C.Structure):
     _fields_ = [("rule", C.c_int), ("test", C.c_int), ("lambda_mode", C.c_int),
                 ("step_L", C.c_double), ("gap_tol", C.c_double), ("max_iter", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("screening", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -171,15 +171,18 @@ def make_problem(D, group_ptr=None, weights=None):
     return p
 
 
+SCREENING = {"dynamic": 0, "static": 1}
+
+
 def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap_tol=1e-6,
-                max_iter=10000):
+                max_iter=10000, screening="dynamic"):
     return Params(RULES[rule], TESTS[test], 1 if lambda_relative else 0, float(step_L),
-                  float(gap_tol), int(max_iter), 0)
+                  float(gap_tol), int(max_iter), SCREENING[screening])
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
           lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
-          screened=False):
+          screened=False, screening="dynamic"):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
@@ -206,7 +209,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     lam = (C.c_double * B)(*[float(v) for v in (lambdas if hasattr(lambdas, "__len__") else [lambdas])])
     infos = (Info * B)()
     prob = make_problem(D, group_ptr, weights)
-    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter)
+    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening)
     if screened:
         if group_ptr is not None:
             raise ValueError("screened masks of batched solves are for the Lasso")
@@ -227,7 +230,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
 
 def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="dst3",
               lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, trace=True,
-              screened=True, stream=None):
+              screened=True, stream=None, screening="dynamic"):
     """Single-signal solve returning (x, info, screened_mask or None, trace list or None)."""
     torch = _torch()
     K = D.shape[1]
@@ -240,7 +243,7 @@ def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="ds
     tr = (Trace * max(cap, 1))()
     info = Info()
     prob = make_problem(D, group_ptr, weights)
-    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter)
+    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening)
     st = _lib.ds_solve_one(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam), C.byref(prm),
                            C.c_void_p(x.data_ptr()),
                            C.c_void_p(scr.data_ptr()) if scr is not None else None,
@@ -308,12 +311,12 @@ class Server:
         return did.value
 
     def submit(self, dict_id, y_host, lam, *, rule="fista", test="dst3", lambda_relative=True,
-               step_L=0.0, gap_tol=1e-6, max_iter=10000):
+               step_L=0.0, gap_tol=1e-6, max_iter=10000, screening="dynamic"):
         import numpy as np
         N, K, dt, store = self._dicts[dict_id]
         y = np.ascontiguousarray(y_host, dtype=np.float64 if store == 0 else np.float32)
         assert y.size == N
-        prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter)
+        prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening)
         rid = C.c_uint64()
         st = _lib.lasso_submit(self._h, int(dict_id), y.ctypes.data_as(C.c_void_p), float(lam),
                                C.byref(prm), C.byref(rid))

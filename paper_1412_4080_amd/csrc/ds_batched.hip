@@ -111,6 +111,7 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
   a.test = static_cast<int>(prm.test);
   a.rule = prm.rule == DS_FISTA ? 1 : 0;
   a.max_iter = prm.max_iter;
+  a.screen_static = prm.screening;
   a.L = L;
   // |z_hat - d^T theta| <= gamma_acc ||d|| ||theta||: FP32 accumulation of the 3 x 64
   // exact products of a row chunk (and the MFMA's internal sums) bounded with unit

@@ -67,7 +67,7 @@ struct alignas(16) Inst {
 
 struct BArgs {
   int N, K, B, Np, Kp, Bp, nrb;
-  int test, rule, max_iter;
+  int test, rule, max_iter, screen_static;
   double L, gamma_acc, gamma64;
   const uint16_t* dcm;  // Kp x Np, atom (column) major, zero padded
   const double* dsc;    // dictionary scalars: [0] max nu_i, [1] max (1 + 1/nu_i)
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   st.r_min = fmin(st.r_min, r);
   st.r_prev = st.r_keep;
   if (a.rule == 1) st.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.l_prev * st.l_prev));
-  if (r_safe < st.r_scr) {
+  if (r_safe < st.r_scr && (!a.screen_static || t == 1)) {  // static: first radius only
     st.r_scr = r_safe;
     st.r_slack = r_safe - r;
   }

@@ -211,6 +211,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   Telemetry* tele = reinterpret_cast<Telemetry*>(base + l.off_tele);
   a.tele = tele;
   a.tele_cap = static_cast<int32_t>(tele_cap);
+  a.screen_static = prm.screening;
   std::vector<double> wbuf;
   if ((st_ = upload_groups(P, base, l, s, wbuf)) != DS_OK) return st_;
   DS_HIP(hipMemsetAsync(a.counters, 0, 32 * 4, s));

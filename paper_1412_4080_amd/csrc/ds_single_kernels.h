@@ -695,7 +695,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       if (RULE == RULE_FISTA) S.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S.l_prev * S.l_prev));
       if (o.stop) {
         S.done = 1;
-      } else if (o.r_safe < S.r_scr) {
+      } else if (o.r_safe < S.r_scr && (!a.screen_static || t == 1)) {
         S.r_scr = o.r_safe;
         S.r_slack = o.r_safe - o.r;
       }

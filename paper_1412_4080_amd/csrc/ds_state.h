@@ -96,6 +96,7 @@ struct SingleArgs {
   void* tele;            // per-iteration telemetry records, or NULL
   int32_t tele_cap;
   uint64_t* kclk;        // NULL, or 2 wall-clock stamps per correlation block (start, end)
+  int32_t screen_static; // 1: the radius is taken from the first iteration only
 };
 
 // Per-iteration telemetry written by the last correlation block.

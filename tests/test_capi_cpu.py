@@ -59,7 +59,7 @@ def test_invalid_problem_rejected(B, field, value):
 
 
 @pytest.mark.parametrize("field,value", [("rule", 5), ("test", 9), ("max_iter", 0),
-                                         ("gap_tol", -1.0), ("reserved", 1),
+                                         ("gap_tol", -1.0), ("screening", 2),
                                          ("lambda_mode", 4)])
 def test_invalid_params_rejected(B, field, value):
     p = _problem(B)

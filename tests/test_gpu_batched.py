@@ -176,3 +176,24 @@ def test_batched_full_size_sampled(B):
         cert, _ = oracle.certified_inactive_lasso(Dbf, y, ref.lam, ref.x)
         assert np.all(cert[mask[:, j]])
         assert not X[mask[:, j], j].any()
+
+
+def test_batched_static_screening(B):
+    T = 30
+    D, Dbf, ys, _ = _batch(320, 1500, 8, 4)
+    ratios = np.linspace(0.3, 0.9, 8)
+    L = oracle.spectral_norm_sq(Dbf)
+    X, infos, mask = B.solve(dev_matrix(D, "bf16"), _dev_Y(ys), ratios, test="dst3", step_L=L,
+                             gap_tol=0.0, max_iter=T, screened=True, screening="static")
+    X = X.cpu().numpy().astype(np.float64)
+    mask = mask.cpu().numpy().astype(bool)
+    for j, (y, r) in enumerate(zip(ys, ratios)):
+        ref = oracle.solve_lasso(Dbf, y, lam_ratio=r, test="dst3", L=L, max_iter=T, gap_tol=0.0,
+                                 record=True, screening="static")
+        assert rel_err(X[:, j], ref.x) <= 1e-5, (j, rel_err(X[:, j], ref.x))
+        assert abs(infos[j]["gap"] - ref.gap) <= 1e-6 * ref.primal_p
+        m = lasso_margins_ref(Dbf, y, ref.lam, "dst3")
+        diff = np.flatnonzero(mask[:, j] != ref.screened)
+        tol = 1e-6 + infos[j]["radius_slack"] + 1e-9
+        assert np.all(np.abs(m[diff] - ref.history[0]["r"]) <= tol), (j, diff[:5])
+        assert not X[mask[:, j], j].any()

@@ -231,3 +231,28 @@ def test_batched_call_matches_single(B):
         x1, i1, _, _ = B.solve_one(Dd, Yd[:, j].contiguous(), r, step_L=L, gap_tol=1e-6)
         assert np.array_equal(X[:, j].cpu().numpy(), x1.cpu().numpy())
         assert infos[j]["iters"] == i1["iters"]
+
+
+@pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe")])
+def test_static_screening_parity(B, rule, test):
+    """Static mode (the test once, with the first dual point): same iterates, gap and
+    screened set as the oracle's static run."""
+    D, y = _lasso_case(500, 2500, 31)
+    Di, yi = instance(D, y, "f32")
+    L = oracle.spectral_norm_sq(Di)
+    T = 40
+    ref = oracle.solve_lasso(Di, yi, lam_ratio=0.6, rule=rule, test=test, L=L, max_iter=T,
+                             gap_tol=0.0, record=True, screening="static")
+    x, info, scr, tr = B.solve_one(dev_matrix(D, "f32"), dev_vector(yi, "f32"), 0.6, rule=rule,
+                                   test=test, step_L=L, gap_tol=0.0, max_iter=T,
+                                   screening="static")
+    x = x.cpu().numpy().astype(np.float64)
+    scr = scr.cpu().numpy().astype(bool)
+    assert info["iters"] == T
+    assert rel_err(x, ref.x) <= 1e-5
+    assert abs(info["gap"] - ref.gap) <= 1e-6 * ref.primal_p + 1e-12
+    m = lasso_margins_ref(Di, yi, ref.lam, test)
+    assert screened_sets_agree(scr, ref.screened, m, ref.history[0]["r"], tr[0]["radius"],
+                               info["radius_slack"])
+    # the active set never changes after the first iteration
+    assert len({t["n_active"] for t in tr[1:]}) == 1

@@ -364,3 +364,62 @@ def test_flops_model_unscreened_equals_closed_form():
     # with nothing screened every |I^c_t| = K
     expect = sum((100 + h["nnz"]) * 30 + 6 * 100 + 5 * 30 for h in r.history)
     assert oracle.flops_dynamic(r.history, 30) == expect
+
+
+# --------------------------------------------------------------------------
+# Static screening (Algorithms 1 and 4): the test once, with the first dual point
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_static_mode_screens_the_closed_form_static_safe_set(rule):
+    """For unit y and unit atoms the static SAFE rule of Algorithm 4 removes
+    {i : |d_i^T y| < lambda - 1 + lambda / lambda_*}; static mode keeps exactly that set
+    for the whole run, and the solution is that of the unscreened problem (Theorem 1)."""
+    D, y = _problem(N=60, K=300, seed=11)
+    lam_max, _ = oracle.lambda_max_lasso(D, y)
+    lam = 0.7 * lam_max
+    static = np.abs(D.T @ y) < lam - 1.0 + lam / lam_max
+    assert static.any()
+    r = oracle.solve_lasso(D, y, lam=lam, rule=rule, test="safe", screening="static",
+                           max_iter=20000, gap_tol=1e-12)
+    assert np.array_equal(r.screened, static)
+    ref = oracle.solve_lasso(D, y, lam=lam, rule=rule, test="none", max_iter=20000, gap_tol=1e-12)
+    assert np.max(np.abs(r.x - ref.x)) <= 1e-7
+    assert not r.x[static].any()
+
+
+@pytest.mark.parametrize("test", ["safe", "dst3"])
+def test_static_set_is_contained_in_the_dynamic_set(test):
+    """The dynamic radius is a running minimum started at the static one (Algorithm 3), so
+    the dynamic screened set contains the static one at every iteration count."""
+    D, y = _problem(N=60, K=300, seed=12)
+    for ratio in (0.4, 0.7, 0.9):
+        for T in (1, 5, 40):
+            s = oracle.solve_lasso(D, y, lam_ratio=ratio, test=test, screening="static",
+                                   max_iter=T + 1, gap_tol=0.0)
+            d = oracle.solve_lasso(D, y, lam_ratio=ratio, test=test, screening="dynamic",
+                                   max_iter=T + 1, gap_tol=0.0)
+            assert not (s.screened & ~d.screened).any()
+            if T == 1:
+                assert np.array_equal(s.screened, d.screened)
+
+
+def test_static_group_mode_keeps_the_first_set():
+    D, y = _problem(N=50, K=200, seed=13)
+    gp = datagen.contiguous_groups(200, 10)
+    r1 = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.8, test="gsafe", screening="static",
+                                  max_iter=2, gap_tol=0.0)
+    r = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.8, test="gsafe", screening="static",
+                                 max_iter=300, gap_tol=0.0)
+    assert np.array_equal(r1.screened_groups, r.screened_groups)
+
+
+def test_flops_model_matches_hand_counts():
+    """The experiments section's per-iteration cost (|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N
+    (Lasso) and (...) + 7 |I^c_t| + 5 N + 5 |G| (groups), summed over two recorded
+    iterations written out by hand."""
+    hist = [dict(n_active=100, nnz=3), dict(n_active=40, nnz=5)]
+    N = 30
+    assert oracle.flops_dynamic(hist, N) == (103 * 30 + 600 + 150) + (45 * 30 + 240 + 150)
+    assert oracle.flops_dynamic(hist, N, n_groups=7) == \
+        (103 * 30 + 700 + 150 + 35) + (45 * 30 + 280 + 150 + 35)
