@@ -4,6 +4,8 @@ None of these checks re-types an oracle formula: each compares the oracle with
 a closed form, an invariant, a special case reducing to a library routine or a
 hand computation, or brute-force enumeration.
 """
+import os
+
 import numpy as np
 import pytest
 from scipy import optimize
@@ -423,3 +425,39 @@ def test_flops_model_matches_hand_counts():
     assert oracle.flops_dynamic(hist, N) == (103 * 30 + 600 + 150) + (45 * 30 + 240 + 150)
     assert oracle.flops_dynamic(hist, N, n_groups=7) == \
         (103 * 30 + 700 + 150 + 35) + (45 * 30 + 280 + 150 + 35)
+
+
+# --------------------------------------------------------------------------
+# Stored reference values of the small FP64 configuration (tests/golden/)
+# --------------------------------------------------------------------------
+
+def _golden():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "small_fp64_ista_safe.txt")
+    vals, x = {}, {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, *rest = line.split()
+        if key == "x":
+            x[int(rest[0])] = float(rest[1])
+        elif key in ("n_active", "nnz"):
+            vals[key] = [int(v) for v in rest]
+        else:
+            vals[key] = float(rest[0])
+    return vals, x
+
+
+def test_small_fp64_configuration_matches_stored_values():
+    g, gx = _golden()
+    c = datagen.lasso_small_fp64()
+    L = oracle.spectral_norm_sq(c["D"])
+    assert L == pytest.approx(g["L"], rel=1e-13)
+    r = oracle.solve_lasso(c["D"], c["y"], lam_ratio=c["lam_ratio"], rule=c["rule"], test=c["test"],
+                           L=L, max_iter=c["max_iter"], gap_tol=c["gap_tol"], record=True)
+    assert r.iters == int(g["iters"]) == 500
+    assert [h["n_active"] for h in r.history] == g["n_active"]
+    assert [h["nnz"] for h in r.history] == g["nnz"]
+    assert r.primal_p == pytest.approx(g["primal_p"], rel=1e-12)
+    assert sorted(np.flatnonzero(r.x).tolist()) == sorted(gx)
+    for i, v in gx.items():
+        assert r.x[i] == pytest.approx(v, rel=1e-9, abs=1e-13)
