@@ -27,7 +27,7 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 struct BLayout {
   int N, K, B, Np, Kp, Bp, nrb;
-  size_t dcm, nu, dsc, Y, X, U0, U1, umask, Thf, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
+  size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
       inst, ctr, vlist, perm, lam, z0, gn, Vn, kclk, spans, total;
   int nspan;
 };
@@ -50,7 +50,7 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.U0 = take(bp * kp * 4);
   l.U1 = take(bp * kp * 4);
   l.umask = take(nt * bp * 4);
-  l.Thf = take(bp * np * 4);
+  l.Ths = take(3 * bp * np * 2);
   l.th64 = take(bp * np * 8);
   l.ptt = take(static_cast<size_t>(l.nrb) * bp * 8);
   l.pty = take(static_cast<size_t>(l.nrb) * bp * 8);
@@ -128,7 +128,7 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
   a.U0 = reinterpret_cast<float*>(base + l.U0);
   a.U1 = reinterpret_cast<float*>(base + l.U1);
   a.umask = reinterpret_cast<uint32_t*>(base + l.umask);
-  a.Thf = reinterpret_cast<float*>(base + l.Thf);
+  a.Ths = reinterpret_cast<uint16_t*>(base + l.Ths);
   a.th64 = reinterpret_cast<double*>(base + l.th64);
   a.ptt = reinterpret_cast<double*>(base + l.ptt);
   a.pty = reinterpret_cast<double*>(base + l.pty);

@@ -56,11 +56,6 @@ __device__ __forceinline__ void split3(float v, uint16_t& hi, uint16_t& mid, uin
   lo = f32_to_bf16(r2);
 }
 
-__device__ __forceinline__ uint2 pack4(const uint16_t* v) {
-  return make_uint2(static_cast<uint32_t>(v[0]) | (static_cast<uint32_t>(v[1]) << 16),
-                    static_cast<uint32_t>(v[2]) | (static_cast<uint32_t>(v[3]) << 16));
-}
-
 // done: 0 running, 2 finished in the iteration in flight, 1 finished earlier.
 struct alignas(16) Inst {
   double lam, lam_max, yy, rho2, alpha, nn, marg_slack, gap_tol_abs;
@@ -82,7 +77,7 @@ struct BArgs {
   float* U0;            // Bp x Kp: u_{t-1} on odd t
   float* U1;            // Bp x Kp: u_{t-1} on even t
   uint32_t* umask;      // (Kp/32) x Bp non-zero bits of u_t per 32-atom tile
-  float* Thf;           // Bp x Np theta rounded to FP32 (split into bfloat16 parts on use)
+  uint16_t* Ths;        // 3 x Bp x Np bfloat16 parts of theta
   double* th64;         // Bp x Np theta in FP64
   double* ptt;          // nrb x Bp partial ||theta||^2
   double* pty;          // nrb x Bp partial theta^T y
@@ -335,8 +330,8 @@ constexpr int TR = 512;  // rows of theta per block (64 lanes x 8 rows)
 constexpr int TW = 128;  // mask words (32 atoms each) per support-list round
 
 // theta = D_S p - y for every running signal, S the support of p = u_{t-1} (from the
-// non-zero bits the previous update left), FP64 accumulation; writes theta in FP64 and
-// rounded to FP32, and per-block FP64 ||theta||^2 and theta^T y.
+// non-zero bits the previous update left), FP64 accumulation; writes theta in FP64, the
+// bfloat16 parts of its FP32 rounding, and per-block FP64 ||theta||^2 and theta^T y.
 // Block: 512 rows of one signal.  The support list (atom indices) is built through LDS
 // 4096 atoms at a time by the whole block; the four waves split it, each lane
 // accumulating 8 rows, and the waves are summed in a fixed order.  Also retires the
@@ -389,6 +384,7 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
 #pragma unroll
   for (int k = 0; k < 8; ++k) red[wave][lane * 8 + k] = acc[k];
   __syncthreads();
+  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
   double tt = 0.0, ty = 0.0;
   for (int r = threadIdx.x; r < TR; r += TB) {
     const int n = blockIdx.x * TR + r;
@@ -398,7 +394,11 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
     const double yv = a.Y[o];
     const double th = n < a.N ? v - yv : 0.0;
     a.th64[o] = th;
-    a.Thf[o] = static_cast<float>(th);
+    uint16_t h, mm, l;
+    split3(static_cast<float>(th), h, mm, l);
+    a.Ths[o] = h;
+    a.Ths[plane + o] = mm;
+    a.Ths[2 * plane + o] = l;
     tt = fma(th, th, tt);
     ty = fma(th, yv, ty);
   }
@@ -452,14 +452,13 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
   // signals' theta through LDS with 128-byte coalesced loads; each wave reads its MFMA
   // fragments from LDS.  Each chunk is accumulated in FP32 on the matrix cores from zero
   // and then added to FP64 registers, so an FP32 rounding chain spans 3 x 64 products.
+  const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
   const int kk = (lane / MT) * 8;
   double zacc[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) zacc[i] = 0.0;
-  // chunk n0 + ZR is fetched into registers while chunk n0 is multiplied; theta comes in
-  // FP32 and is split into its three bfloat16 parts on the way into LDS
-  uint4 pa[2];
-  float4 pb[4];
+  // chunk n0 + ZR is fetched into registers while chunk n0 is multiplied
+  uint4 pa[2], pb[6];
   auto fetch = [&](int n0) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {  // 64 rows x 128 bytes of D: 512 16-byte pieces
@@ -467,10 +466,10 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       pa[r] = ldg16(a.dcm + static_cast<int64_t>(a0b + e / 8) * a.Np + n0 + (e % 8) * 8);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {  // 64 rows x 256 bytes of FP32 theta: 1024 pieces
+    for (int r = 0; r < 6; ++r) {  // 3 x 64 rows x 128 bytes of theta
       const int e = threadIdx.x + r * TB;
-      pb[r] = *reinterpret_cast<const float4*>(a.Thf + static_cast<int64_t>(b0b + e / 16) * a.Np + n0 +
-                                               (e % 16) * 4);
+      pb[r] = ldg16(a.Ths + (e / 512) * plane + static_cast<int64_t>(b0b + (e % 512) / 8) * a.Np + n0 +
+                    (e % 8) * 8);
     }
   };
   fetch(0);
@@ -482,16 +481,9 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       *reinterpret_cast<uint4*>(&sA[e / 8][(e % 8) * 8]) = pa[r];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 6; ++r) {
       const int e = threadIdx.x + r * TB;
-      const int row = e / 16, col = (e % 16) * 4;
-      const float v[4] = {pb[r].x, pb[r].y, pb[r].z, pb[r].w};
-      uint16_t h[4], m[4], l[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) split3(v[q], h[q], m[q], l[q]);
-      *reinterpret_cast<uint2*>(&sB[0][row][col]) = pack4(h);
-      *reinterpret_cast<uint2*>(&sB[1][row][col]) = pack4(m);
-      *reinterpret_cast<uint2*>(&sB[2][row][col]) = pack4(l);
+      *reinterpret_cast<uint4*>(&sB[e / 512][(e % 512) / 8][(e % 8) * 8]) = pb[r];
     }
     __syncthreads();
     if (n0 + ZR < a.Np) fetch(n0 + ZR);
