@@ -369,6 +369,7 @@ def main():
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
                          "batched solve")
+    ap.add_argument("--serve-slots", type=int, default=8, help="worker slots of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (a plain copy kernel of known "
                          "size, for scaling HBM counters)")
@@ -462,7 +463,7 @@ def main():
     if "flops" in legs:
         out["flops_model"] = flops_leg(binding, Dd, ys, L, nsig=min(3, len(ys)))
     if "served" in legs:
-        out["served"] = served_leg(binding)
+        out["served"] = served_leg(binding, slots=args.serve_slots)
     if not args.no_cpu:
         import oracle
         L64 = oracle.spectral_norm_sq(D32)
