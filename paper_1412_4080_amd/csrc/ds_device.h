@@ -67,29 +67,77 @@ template <> __device__ __forceinline__ double to_double<bf16_t>(bf16_t v) { retu
 
 
 // ---------------------------------------------------------------- reductions ------
+// Wave reductions on the data-parallel primitives of the vector ALU: two quad
+// permutations and the half-row and row mirrors leave the sum (max, min) of each row of
+// 16 lanes in every lane of the row, then the four row results are combined with lane
+// reads in row order.  The combination tree is fixed, so the result is deterministic and
+// the same in every lane.  All 64 lanes must be active.
+namespace dpp {
+constexpr int QUAD_1032 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int QUAD_2301 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int HALF_MIRROR = 0x141;  // lane j of 8 reads lane 7 - j
+constexpr int ROW_MIRROR = 0x140;   // lane j of 16 reads lane 15 - j
+
+template <int C> __device__ __forceinline__ int mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, C, 0xf, 0xf, false);
+}
+template <int C> __device__ __forceinline__ int64_t mov(int64_t v) {
+  const int lo = mov<C>(static_cast<int>(v)), hi = mov<C>(static_cast<int>(v >> 32));
+  return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                              static_cast<uint32_t>(lo));
+}
+template <int C> __device__ __forceinline__ uint64_t mov(uint64_t v) {
+  return static_cast<uint64_t>(mov<C>(static_cast<int64_t>(v)));
+}
+template <int C> __device__ __forceinline__ unsigned mov(unsigned v) {
+  return static_cast<unsigned>(mov<C>(static_cast<int>(v)));
+}
+template <int C> __device__ __forceinline__ float mov(float v) {
+  return __int_as_float(mov<C>(__float_as_int(v)));
+}
+template <int C> __device__ __forceinline__ double mov(double v) {
+  return __hiloint2double(mov<C>(__double2hiint(v)), mov<C>(__double2loint(v)));
+}
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ unsigned lane_read(unsigned v, int l) {
+  return static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+}
+__device__ __forceinline__ int64_t lane_read(int64_t v, int l) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v >> 32), l));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ uint64_t lane_read(uint64_t v, int l) {
+  return static_cast<uint64_t>(lane_read(static_cast<int64_t>(v), l));
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <typename X, typename Op>
+__device__ __forceinline__ X reduce(X v, Op op) {
+  v = op(v, mov<QUAD_1032>(v));
+  v = op(v, mov<QUAD_2301>(v));
+  v = op(v, mov<HALF_MIRROR>(v));
+  v = op(v, mov<ROW_MIRROR>(v));
+  return op(op(op(lane_read(v, 0), lane_read(v, 16)), lane_read(v, 32)), lane_read(v, 48));
+}
+}  // namespace dpp
+
 template <typename X>
 __device__ __forceinline__ X wave_sum(X v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
+  return dpp::reduce(v, [](X p, X q) { return p + q; });
 }
 template <typename X>
 __device__ __forceinline__ X wave_max(X v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    X w = __shfl_xor(v, o, WAVE);
-    v = w > v ? w : v;
-  }
-  return v;
+  return dpp::reduce(v, [](X p, X q) { return q > p ? q : p; });
 }
 template <typename X>
 __device__ __forceinline__ X wave_min(X v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    X w = __shfl_xor(v, o, WAVE);
-    v = w < v ? w : v;
-  }
-  return v;
+  return dpp::reduce(v, [](X p, X q) { return q < p ? q : p; });
 }
 
 // Block-wide reductions with a fixed combination order (deterministic).  `scratch`

@@ -568,21 +568,22 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitem
                                   double* sd) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
   constexpr int RT = WAVE * VR;
+  constexpr int FB = 32;  // item partials loaded at once
   double tt = 0.0, ty = 0.0;
   const int r_end = min((rt + 1) * RT, a.N);
   for (int r = rt * RT + static_cast<int>(threadIdx.x); r < r_end; r += BLK) {
-    // item partials in item order, sixteen loads in flight
-    double s = 0.0;
-    int c = 0;
-    for (; c + 16 <= nitems_rt; c += 16) {
-      double v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = consume(&a.partial[static_cast<int64_t>(c + k) * a.npad + r]);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s += v[k];
-    }
-    for (; c < nitems_rt; ++c) s += consume(&a.partial[static_cast<int64_t>(c) * a.npad + r]);
     const double yv = static_cast<double>(a.y[r]);
+    // item partials in item order, FB loads in flight (unconditional loads at clamped
+    // indices: a guarded load would wait for its value before the next one is issued)
+    double s = 0.0;
+    for (int c = 0; c < nitems_rt; c += FB) {
+      double v[FB];
+#pragma unroll
+      for (int k = 0; k < FB; ++k)
+        v[k] = consume(&a.partial[static_cast<int64_t>(min(c + k, nitems_rt - 1)) * a.npad + r]);
+#pragma unroll
+      for (int k = 0; k < FB; ++k) s += c + k < nitems_rt ? v[k] : 0.0;
+    }
     const V th = static_cast<V>(s - yv);
     a.theta[r] = th;
     const double thd = static_cast<double>(th);
@@ -599,6 +600,12 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitem
   }
 }
 
+// Raw support records of one residual slot, loaded before the kept / non-zero decision.
+struct SlotRaw {
+  int nk, m, atom;
+  double marg, om, val;
+};
+
 template <typename T, typename V, bool VECTOR, int RULE, bool GROUP>
 __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
@@ -608,45 +615,97 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   constexpr int SG = GROUP ? 1 : SGL;             // segments per item
   constexpr int SPI = SG * SEGCAP;                // slots per item
   constexpr int SPT = SPI / BLK;                  // slots per thread
+  constexpr int PB = 4;                           // block partials per thread per step
   static_assert(SPI % BLK == 0, "slots must tile the block");
   __shared__ double red[NW][RT];
   __shared__ int l_idx[SPI];
   __shared__ double l_val[SPI];
   __shared__ double sd[NW];
   __shared__ int scan[NW];
-  __shared__ int si[NW];
   __shared__ int s_last;
   __shared__ SolverState S;
   __shared__ double red8[NW][8];
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   const SolverState* sin = a.st + (1 - a.par);
   SolverState* sout = a.st + a.par;
-  {  // parallel copy of the state into LDS
-    constexpr int NWORDS = sizeof(SolverState) / 4;
-    static_assert(NWORDS <= BLK, "state fits one word per thread");
-    if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = reinterpret_cast<const int32_t*>(sin)[tid];
-  }
-  __syncthreads();
   const int nrt = (a.N + RT - 1) / RT;
   const int nsg = (a.grid_corr + SG - 1) / SG;
+  const int nitems = nrt * nsg;
+
+  // The support records a slot of `item` may use.  Every address is in bounds whatever
+  // the segment counts are (blocks past the grid read the last block's records and are
+  // discarded later), so the loads need neither the counts nor the new radius, and none
+  // of them is guarded: a guarded load waits for its value before the next is issued.
+  auto load_slots = [&](int item, SlotRaw (&raw)[SPT]) {
+    const int sg = item / nrt;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int s = tid + q * BLK;  // slot within the item
+      const int b = min(sg * SG + s / SEGCAP, a.grid_corr - 1), k = s % SEGCAP;
+      const int j = GROUP ? k / GMAX : k;
+      const int64_t rec = static_cast<int64_t>(b) * UCAP + j;
+      const int64_t slot = static_cast<int64_t>(b) * SEGCAP + k;
+      raw[q].nk = a.seg_cnt[b];
+      raw[q].marg = a.urec_marg[rec];
+      raw[q].om = a.urec_om[rec];
+      raw[q].m = GROUP ? a.urec_m[rec] : 0;
+      raw[q].val = static_cast<double>(a.seg_val[slot]);
+      raw[q].atom = a.seg_atom[slot];
+    }
+  };
+
+  // ---- one round trip for the state, the previous pass's partials and the first
+  // item's support records: all of them are issued before the first wait ----
+  constexpr int NWORDS = sizeof(SolverState) / 4;
+  static_assert(NWORDS <= BLK, "state fits one word per thread");
+  const int32_t sword = reinterpret_cast<const int32_t*>(sin)[min(tid, NWORDS - 1)];
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // zs nz kt ns at tt ty om
+  const double* rtp = a.rtn + (1 - a.par) * (2 * MAXRT);
+  const double* omp = a.omp + (1 - a.par) * MAXITEM;
+  double p0[PB], p1[PB], p2[PB], p3[PB], p4[PB];
+#pragma unroll
+  for (int k = 0; k < PB; ++k) {  // block partials tid, tid + BLK, ... in that order
+    const int b = min(k * BLK + tid, a.grid_corr - 1);
+    p0[k] = a.bp0[b];
+    p1[k] = a.bpi[b];
+    p2[k] = a.bpi[MAXB + b];
+    p3[k] = a.bpi[2 * MAXB + b];
+    p4[k] = a.bpi[3 * MAXB + b];
+  }
+  const int kr = min(tid, nrt - 1), ko = min(tid, nsg - 1);
+  const double q5 = rtp[2 * kr], q6 = rtp[2 * kr + 1], q7 = omp[ko];
+  SlotRaw raw[SPT];
+  if (static_cast<int>(blockIdx.x) < nitems) load_slots(blockIdx.x, raw);
+#pragma unroll
+  for (int k = 0; k < PB; ++k) {
+    const bool ok = k * BLK + tid < a.grid_corr;
+    v[0] = fmax(v[0], ok ? p0[k] : 0.0);
+    v[1] += ok ? p1[k] : 0.0;
+    v[2] += ok ? p2[k] : 0.0;
+    v[3] += ok ? p3[k] : 0.0;
+    v[4] += ok ? p4[k] : 0.0;
+  }
+  v[5] += tid < nrt ? q5 : 0.0;
+  v[6] += tid < nrt ? q6 : 0.0;
+  v[7] += tid < nsg ? q7 : 0.0;
+  // larger grids: the remaining partials, in the same order
+  for (int b = PB * BLK + tid; b < a.grid_corr; b += BLK) {
+    v[0] = fmax(v[0], a.bp0[b]);
+    v[1] += a.bpi[b];
+    v[2] += a.bpi[MAXB + b];
+    v[3] += a.bpi[2 * MAXB + b];
+    v[4] += a.bpi[3 * MAXB + b];
+  }
+  for (int k = BLK + tid; k < nrt; k += BLK) { v[5] += rtp[2 * k]; v[6] += rtp[2 * k + 1]; }
+  for (int k = BLK + tid; k < nsg; k += BLK) v[7] += omp[k];
+  if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = sword;
+  __syncthreads();
   if (S.done) {
     if (blockIdx.x == 0 && tid == 0) *sout = S;
     return;
   }
   // ---- scalars of the previous iteration, from the published partials ----
   if (S.pending) {
-    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // zs nz kt ns at tt ty om
-    for (int b = tid; b < a.grid_corr; b += BLK) {
-      v[0] = fmax(v[0], a.bp0[b]);
-      v[1] += a.bpi[b];
-      v[2] += a.bpi[MAXB + b];
-      v[3] += a.bpi[2 * MAXB + b];
-      v[4] += a.bpi[3 * MAXB + b];
-    }
-    const double* rtp = a.rtn + (1 - a.par) * (2 * MAXRT);
-    const double* omp = a.omp + (1 - a.par) * MAXITEM;
-    for (int k = tid; k < nrt; k += BLK) { v[5] += rtp[2 * k]; v[6] += rtp[2 * k + 1]; }
-    for (int k = tid; k < S.n_omp; k += BLK) v[7] += omp[k];
     // one-pass block reduction of the eight values (fixed order: lanes, then waves)
     v[0] = wave_max(v[0]);
 #pragma unroll
@@ -718,20 +777,22 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   }
   if (blockIdx.x == 0 && tid == 0) {
     SolverState o = S;
-    o.n_omp = S.iter > 0 ? nsg : 1;  // the Omega partials this pass publishes
+    o.n_omp = nsg;  // the Omega partials this pass publishes
     *sout = o;
     a.counters[CNT_VID] = 0u;  // the correlation pass that used it has ended
   }
   const double r_keep = S.r_scr + S.marg_slack;
   const bool have_support = S.iter > 0;  // p_0 = 0
-  if (!have_support) {  // theta = -y
+  if (!have_support) {  // theta = -y, Omega(p_0) = 0
     if (static_cast<int>(blockIdx.x) < nrt) resid_finish_tile<T, V, VECTOR>(a, blockIdx.x, 0, sd);
-    if (blockIdx.x == 0 && tid == 0) a.omp[a.par * MAXITEM] = 0.0;
+    if (blockIdx.x == 0)
+      for (int k = tid; k < nsg; k += BLK) a.omp[a.par * MAXITEM + k] = 0.0;
     return;
   }
-  for (int item = blockIdx.x; item < nrt * nsg; item += gridDim.x) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int rt = item % nrt, sg = item / nrt;
-    // ---- gather the kept, non-zero support entries of segment group sg (in order) ----
+    if (item != static_cast<int>(blockIdx.x)) load_slots(item, raw);
+    // ---- the kept, non-zero support entries of segment group sg (in order) ----
     int cntv = 0;
     int e_atom[SPT];
     double e_val[SPT];
@@ -740,25 +801,19 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     for (int q = 0; q < SPT; ++q) {
       const int s = tid + q * BLK;  // slot within the item
       const int b = sg * SG + s / SEGCAP, k = s % SEGCAP;
+      const int j = GROUP ? k / GMAX : k;
+      const int kk = GROUP ? k % GMAX : 0;
       e_atom[q] = -1;
       e_val[q] = 0.0;
-      if (b < a.grid_corr) {
-        const int nk = a.seg_cnt[b];
-        const int j = GROUP ? k / GMAX : k;
-        const int kk = GROUP ? k % GMAX : 0;
-        if (j < nk) {
-          const int64_t rec = static_cast<int64_t>(b) * UCAP + j;
-          const bool kept = !(a.urec_marg[rec] > r_keep);
-          if (kept && (!GROUP || kk < a.urec_m[rec])) {
-            const int64_t slot = static_cast<int64_t>(b) * SEGCAP + k;
-            const double v = static_cast<double>(a.seg_val[slot]);
-            if (v != 0.0) {
-              e_atom[q] = a.seg_atom[slot];
-              e_val[q] = v;
-              ++cntv;
-            }
-            if (kk == 0) om += a.urec_om[rec];
+      if (b < a.grid_corr && j < raw[q].nk) {
+        const bool kept = !(raw[q].marg > r_keep);
+        if (kept && (!GROUP || kk < raw[q].m)) {
+          if (raw[q].val != 0.0) {
+            e_atom[q] = raw[q].atom;
+            e_val[q] = raw[q].val;
+            ++cntv;
           }
+          if (kk == 0) om += raw[q].om;
         }
       }
     }
@@ -794,13 +849,13 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       }
       if (VECTOR && r0 + VR <= a.N) {
         if constexpr (VECTOR) {
-          uint4 raw[RPW];
+          uint4 cv[RPW];
 #pragma unroll
-          for (int p = 0; p < RPW; ++p) raw[p] = ld16(a.D + static_cast<int64_t>(idx[p]) * a.ldd + r0);
+          for (int p = 0; p < RPW; ++p) cv[p] = ld16(a.D + static_cast<int64_t>(idx[p]) * a.ldd + r0);
 #pragma unroll
           for (int p = 0; p < RPW; ++p) {
             double d[VR];
-            widen<T>(raw[p], d);
+            widen<T>(cv[p], d);
 #pragma unroll
             for (int e = 0; e < VR; ++e) acc[e] = fma(d[e], val[p], acc[e]);
           }
