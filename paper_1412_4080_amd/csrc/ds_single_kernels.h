@@ -940,12 +940,24 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ int s_vb, s_nk, s_kpre;
   __shared__ int klist[CBU];
   __shared__ double kmarg[CBU];
-  __shared__ double sd[NW];
-  __shared__ int si[NW];
+  __shared__ double sred[NW][4];
   if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
   const SolverState* st = a.st + a.par;
-  if (st->done) return;
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+  // The list entries of virtual block blockIdx.x are read from both lists together with
+  // the state (the state says which list is current), at clamped indices so that no
+  // load waits for another; a compacting pass reloads them for the block it draws.
+  const int n_units = GROUP ? a.G : a.K;
+  int e_unit0 = 0, e_unit1 = 0;
+  double e_marg0 = 0.0, e_marg1 = 0.0;
+  if (wave == 0) {
+    const int e = min(static_cast<int>(blockIdx.x) * CBU + lane, n_units - 1);
+    e_unit0 = a.act[0][e];
+    e_unit1 = a.act[1][e];
+    e_marg0 = a.act_m[0][e];
+    e_marg1 = a.act_m[1][e];
+  }
+  if (st->done) return;
   const bool compact = st->compact != 0;
   int vb = blockIdx.x;
   if (compact) {
@@ -959,14 +971,14 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   const int base = vb * CBU;
   const int cnt = max(0, min(CBU, n_old - base));
   if (wave == 0) {
-    int unit = 0;
-    double m = 0.0;
-    bool keep = false;
-    if (lane < cnt) {
-      unit = a.act[cur][base + lane];
-      m = a.act_m[cur][base + lane];
-      keep = !(m > r_keep);
+    int unit = cur ? e_unit1 : e_unit0;
+    double m = cur ? e_marg1 : e_marg0;
+    if (vb != static_cast<int>(blockIdx.x)) {
+      const int e = min(base + lane, n_units - 1);
+      unit = a.act[cur][e];
+      m = a.act_m[cur][e];
     }
+    const bool keep = lane < cnt && !(m > r_keep);
     const unsigned long long bal = __ballot(keep);
     const int pos = __popcll(bal & ((1ull << lane) - 1ull));
     if (keep) { klist[pos] = unit; kmarg[pos] = m; }
@@ -1087,11 +1099,30 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       }
     }
   }
-  zsup = block_max<double, NW>(zsup, sd);
-  nnz = block_sum<int, NW>(nnz, si);
-  nsup = block_sum<int, NW>(nsup, si);
-  natoms = block_sum<int, NW>(natoms, si);
+  // block partials in one LDS pass (counts are exact in FP64)
+  zsup = wave_max(zsup);
+  const double cnz = wave_sum(static_cast<double>(nnz)), csup = wave_sum(static_cast<double>(nsup));
+  const double cat = wave_sum(static_cast<double>(natoms));
+  if (lane == 0) {
+    sred[wave][0] = zsup;
+    sred[wave][1] = cnz;
+    sred[wave][2] = csup;
+    sred[wave][3] = cat;
+  }
+  __syncthreads();
   if (tid == 0) {  // read by the next residual pass only (after this kernel ends)
+    double r0 = sred[0][0], r1 = sred[0][1], r2 = sred[0][2], r3 = sred[0][3];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      r0 = fmax(r0, sred[w][0]);
+      r1 += sred[w][1];
+      r2 += sred[w][2];
+      r3 += sred[w][3];
+    }
+    zsup = r0;
+    nnz = static_cast<int>(r1);
+    nsup = static_cast<int>(r2);
+    natoms = static_cast<int>(r3);
     a.bp0[vb] = zsup;
     a.bpi[vb] = nnz;
     a.bpi[MAXB + vb] = nk;
