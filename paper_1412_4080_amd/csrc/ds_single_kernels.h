@@ -941,12 +941,16 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ int klist[CBU];
   __shared__ double kmarg[CBU];
   __shared__ double sred[NW][4];
+  __shared__ SolverState S;
   if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
-  const SolverState* st = a.st + a.par;
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-  // The list entries of virtual block blockIdx.x are read from both lists together with
-  // the state (the state says which list is current), at clamped indices so that no
-  // load waits for another; a compacting pass reloads them for the block it draws.
+  // One round trip for the state (one word per thread into LDS) and for the list entries
+  // of virtual block blockIdx.x in both lists (the state says which list is current), at
+  // clamped indices so that no load waits for another; a compacting pass reloads the
+  // entries of the block it draws.
+  constexpr int NWORDS = sizeof(SolverState) / 4;
+  static_assert(NWORDS <= BLK, "state fits one word per thread");
+  const int32_t sword = reinterpret_cast<const int32_t*>(a.st + a.par)[min(tid, NWORDS - 1)];
   const int n_units = GROUP ? a.G : a.K;
   int e_unit0 = 0, e_unit1 = 0;
   double e_marg0 = 0.0, e_marg1 = 0.0;
@@ -957,6 +961,9 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
     e_marg0 = a.act_m[0][e];
     e_marg1 = a.act_m[1][e];
   }
+  if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = sword;
+  __syncthreads();
+  const SolverState* st = &S;
   if (st->done) return;
   const bool compact = st->compact != 0;
   int vb = blockIdx.x;
@@ -1130,7 +1137,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
     a.bpi[3 * MAXB + vb] = natoms;
     if (vb == 0) {
       SolverState* sw = a.st + a.par;
-      sw->pending = 1;  // nothing else in this pass reads it
+      sw->pending = 1;  // no block of this pass reads it after its prologue
     }
     if (a.kclk != nullptr) a.kclk[2 * blockIdx.x + 1] = wall_clock64();
   }
