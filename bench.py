@@ -270,6 +270,77 @@ def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96
             "open_loop": opens, "per_dict_closed_loop": per_dict}
 
 
+# The largest dictionary of the serving mix: 4096 x 40000 FP32 is 655 MB, more than the
+# 256 MB last-level cache, so every correlation pass streams it from HBM.
+LARGE = (4096, 40000)
+LARGE_RATIOS = (0.3, 0.5, 0.7)
+
+
+def large_inputs(group, seed=datagen.DICT_SEED):
+    """Unit-norm Gaussian 4096 x 40000 FP32 dictionary and one unit-norm observation (2%
+    active atoms, or groups of 10, with N(0,1) coefficients, 20 dB noise), drawn on the
+    device from a seeded generator (655 MB is slow to draw on the host)."""
+    import torch
+    n, kk = LARGE
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed * 1000 + 100 + int(group))
+    D = torch.randn(kk, n, generator=g, device="cuda")
+    D /= D.norm(dim=1, keepdim=True)
+    gs = 10 if group else 0
+    units = kk // gs if gs else kk
+    mask = torch.rand(units, generator=g, device="cuda") < 0.02
+    mask[0] |= ~mask.any()
+    if gs:
+        mask = mask.repeat_interleave(gs)
+    x0 = torch.randn(kk, generator=g, device="cuda") * mask
+    yc = x0 @ D
+    noise = torch.randn(n, generator=g, device="cuda")
+    noise *= yc.norm() / noise.norm() * 10 ** (-20 / 20)
+    y = yc + noise
+    y /= y.norm()
+    gp = np.arange(0, kk + 1, gs, dtype=np.int64) if gs else None
+    torch.cuda.synchronize()
+    return D.T, y.contiguous(), gp
+
+
+def large_leg(binding):
+    """HBM roofline of the correlation kernel where the dictionary cannot stay in the
+    last-level cache: one signal on 4096 x 40000 FP32, Lasso (FISTA + DST3) and
+    Group-Lasso (groups of 10, FISTA + DGST3), lambda / lambda_* in LARGE_RATIOS, gap 1e-6.
+    Kernel spans from the device wall clock, algorithmic bytes as in the headline."""
+    out = {}
+    for group in (False, True):
+        Dt, y, gp = large_inputs(group)
+        L = binding.spectral_norm_sq(Dt, 300)
+        binding.stats_reset()
+        binding.stats_enable(True)
+        iters = []
+        for r in LARGE_RATIOS:
+            _, info, _, _ = binding.solve_one(Dt, y, r, group_ptr=gp, rule="fista", test="dst3",
+                                              step_L=L, gap_tol=GAP_TOL, max_iter=20000,
+                                              trace=False, screened=False)
+            if info["status"] != 0:
+                raise RuntimeError(f"large solve did not converge: {info}")
+            iters.append(info["iters"])
+        binding.stats_enable(False)
+        st = binding.stats_read()[binding.STAT_CORR]
+        n = max(st["launches"], 1)
+        avg_ms = st["ms"] / n
+        achieved = st["bytes"] / max(st["ms"] * 1e-3, 1e-12) / 1e9
+        name = "group" if group else "lasso"
+        out[name] = {"kernel": f"k_corr_{name}",
+                     "workload": f"{name}_fista_{'dgst3' if group else 'dst3'}_gaussian_"
+                                 f"{LARGE[0]}x{LARGE[1]}_f32",
+                     "lambda_ratios": list(LARGE_RATIOS), "iters": iters,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "avg_launch_us": round(avg_ms * 1e3, 3),
+                     "algorithmic_bytes_per_launch": round(st["bytes"] / n, 1),
+                     "launches": st["launches"]}
+        del Dt, y
+    return out
+
+
 def flops_leg(binding, Dd, ys, L, nsig=3):
     """The experiments section's cost model, normalised by the unscreened run: per
     iteration (|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N flops, plus K N for the screening
@@ -363,12 +434,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served,flops",
-                    help="comma list of legs: single (headline), batched, served, flops.  Profiling "
+    ap.add_argument("--legs", default="single,batched,served,flops,large",
+                    help="comma list of legs: single (headline), batched, served, flops, large "
+                         "(correlation roofline on 4096 x 40000 FP32).  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
-                         "batched solve")
+                         "batched solve; 'large-instrumented' only the large-dictionary leg")
     ap.add_argument("--serve-slots", type=int, default=8, help="worker slots of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (a plain copy kernel of known "
@@ -392,6 +464,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if legs == {"large-instrumented"}:
+        print(json.dumps({"leg": "large-instrumented", "roofline_large_dictionary": large_leg(binding)}),
+              flush=True)
+        return
     D = datagen.gaussian_dictionary(N, K, datagen.DICT_SEED)
     D32 = datagen.to_storage(D, "f32")
     if legs == {"batched-instrumented"}:
@@ -462,6 +538,8 @@ def main():
         out["batched"] = b
     if "flops" in legs:
         out["flops_model"] = flops_leg(binding, Dd, ys, L, nsig=min(3, len(ys)))
+    if "large" in legs:
+        out["roofline_large_dictionary"] = large_leg(binding)
     if "served" in legs:
         out["served"] = served_leg(binding, slots=args.serve_slots)
     if not args.no_cpu:
