@@ -42,7 +42,7 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.npad = round_up(N, 64);
   l.grid_corr = corr_blocks(K, G);
   const int64_t segcap = G > 0 ? SEGCAP_G : SEGCAP_L, ucap = G > 0 ? CBG : CBL;
-  l.nsg = G > 0 ? l.grid_corr : (l.grid_corr + SGL - 1) / SGL;
+  l.nsg = (l.grid_corr + (G > 0 ? SGG : SGL) - 1) / (G > 0 ? SGG : SGL);
   const int64_t units = G > 0 ? G : K;
   l.off_state = take(2 * sizeof(SolverState));
   l.off_act0 = take(units * 4);

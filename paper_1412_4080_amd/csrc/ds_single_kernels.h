@@ -529,6 +529,8 @@ constexpr int CBG = NW * 2;           // groups per correlation block (8)
 constexpr int SEGCAP_L = CBL;         // support slots per block (Lasso)
 constexpr int SEGCAP_G = CBG * GMAX;  // support slots per block (groups)
 constexpr int SGL = 32;               // correlation segments per residual item (Lasso)
+constexpr int SGG = 32;               // correlation blocks per residual item (groups)
+constexpr int LCAP = 512;             // residual list entries streamed per chunk
 constexpr int MAXITEM = 8192;         // residual segment groups
 
 // FP64 scalars of one iteration from the reduced partials (same arithmetic in every
@@ -610,16 +612,17 @@ template <typename T, typename V, bool VECTOR, int RULE, bool GROUP>
 __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
   constexpr int RT = WAVE * VR;
-  constexpr int SEGCAP = GROUP ? SEGCAP_G : SEGCAP_L;
-  constexpr int UCAP = GROUP ? CBG : CBL;
-  constexpr int SG = GROUP ? 1 : SGL;             // segments per item
-  constexpr int SPI = SG * SEGCAP;                // slots per item
-  constexpr int SPT = SPI / BLK;                  // slots per thread
+  constexpr int SG = GROUP ? SGG : SGL;           // correlation blocks per item
+  // Lasso: one support slot per list entry; groups: one group record per thread
+  constexpr int SPI = GROUP ? SGG * CBG : SGL * SEGCAP_L;
+  constexpr int SPT = SPI / BLK;                  // slots (records) per thread
   constexpr int PB = 4;                           // block partials per thread per step
   static_assert(SPI % BLK == 0, "slots must tile the block");
+  static_assert(GROUP ? SPI == BLK : SPI <= LCAP, "group records: one per thread");
   __shared__ double red[NW][RT];
-  __shared__ int l_idx[SPI];
-  __shared__ double l_val[SPI];
+  __shared__ int l_idx[LCAP];
+  __shared__ double l_val[LCAP];
+  __shared__ int s_goff[GROUP ? BLK : 1], s_gbase[GROUP ? BLK : 1];
   __shared__ double sd[NW];
   __shared__ int scan[NW];
   __shared__ int s_last;
@@ -632,25 +635,36 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   const int nsg = (a.grid_corr + SG - 1) / SG;
   const int nitems = nrt * nsg;
 
-  // The support records a slot of `item` may use.  Every address is in bounds whatever
-  // the segment counts are (blocks past the grid read the last block's records and are
-  // discarded later), so the loads need neither the counts nor the new radius, and none
-  // of them is guarded: a guarded load waits for its value before the next is issued.
+  // The support records a slot of `item` may use (groups: the record of one group, its
+  // atoms' slots start at `atom`).  Every address is in bounds whatever the segment counts
+  // are (blocks past the grid read the last block's records and are discarded later), so
+  // the loads need neither the counts nor the new radius, and none of them is guarded: a
+  // guarded load waits for its value before the next is issued.
   auto load_slots = [&](int item, SlotRaw (&raw)[SPT]) {
     const int sg = item / nrt;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
-      const int s = tid + q * BLK;  // slot within the item
-      const int b = min(sg * SG + s / SEGCAP, a.grid_corr - 1), k = s % SEGCAP;
-      const int j = GROUP ? k / GMAX : k;
-      const int64_t rec = static_cast<int64_t>(b) * UCAP + j;
-      const int64_t slot = static_cast<int64_t>(b) * SEGCAP + k;
-      raw[q].nk = a.seg_cnt[b];
-      raw[q].marg = a.urec_marg[rec];
-      raw[q].om = a.urec_om[rec];
-      raw[q].m = GROUP ? a.urec_m[rec] : 0;
-      raw[q].val = static_cast<double>(a.seg_val[slot]);
-      raw[q].atom = a.seg_atom[slot];
+      const int s = tid + q * BLK;  // slot (record) within the item
+      if constexpr (GROUP) {
+        const int b = min(sg * SG + s / CBG, a.grid_corr - 1), j = s % CBG;
+        const int64_t rec = static_cast<int64_t>(b) * CBG + j;
+        raw[q].nk = a.seg_cnt[b];
+        raw[q].marg = a.urec_marg[rec];
+        raw[q].om = a.urec_om[rec];
+        raw[q].m = a.urec_m[rec];
+        raw[q].val = 0.0;
+        raw[q].atom = b * SEGCAP_G + j * GMAX;
+      } else {
+        const int b = min(sg * SG + s / SEGCAP_L, a.grid_corr - 1), k = s % SEGCAP_L;
+        const int64_t rec = static_cast<int64_t>(b) * CBL + k;
+        const int64_t slot = static_cast<int64_t>(b) * SEGCAP_L + k;
+        raw[q].nk = a.seg_cnt[b];
+        raw[q].marg = a.urec_marg[rec];
+        raw[q].om = a.urec_om[rec];
+        raw[q].m = 0;
+        raw[q].val = static_cast<double>(a.seg_val[slot]);
+        raw[q].atom = a.seg_atom[slot];
+      }
     }
   };
 
@@ -789,55 +803,9 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       for (int k = tid; k < nsg; k += BLK) a.omp[a.par * MAXITEM + k] = 0.0;
     return;
   }
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int rt = item % nrt, sg = item / nrt;
-    if (item != static_cast<int>(blockIdx.x)) load_slots(item, raw);
-    // ---- the kept, non-zero support entries of segment group sg (in order) ----
-    int cntv = 0;
-    int e_atom[SPT];
-    double e_val[SPT];
-    double om = 0.0;
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-      const int s = tid + q * BLK;  // slot within the item
-      const int b = sg * SG + s / SEGCAP, k = s % SEGCAP;
-      const int j = GROUP ? k / GMAX : k;
-      const int kk = GROUP ? k % GMAX : 0;
-      e_atom[q] = -1;
-      e_val[q] = 0.0;
-      if (b < a.grid_corr && j < raw[q].nk) {
-        const bool kept = !(raw[q].marg > r_keep);
-        if (kept && (!GROUP || kk < raw[q].m)) {
-          if (raw[q].val != 0.0) {
-            e_atom[q] = raw[q].atom;
-            e_val[q] = raw[q].val;
-            ++cntv;
-          }
-          if (kk == 0) om += raw[q].om;
-        }
-      }
-    }
-    if (rt == 0) {
-      om = block_sum<double, NW>(om, sd);
-      if (tid == 0) a.omp[a.par * MAXITEM + sg] = om;
-    }
-    int total;
-    int off = block_exclusive_scan<NW>(cntv, scan, &total);
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-      if (e_atom[q] >= 0) {
-        l_idx[off] = e_atom[q];
-        l_val[off] = e_val[q];
-        ++off;
-      }
-    }
-    __syncthreads();
-    const int nl = total;
-    // ---- stream the row segments of the gathered columns ----
-    const int r0 = rt * RT + lane * VR;
-    double acc[VR];
-#pragma unroll
-    for (int e = 0; e < VR; ++e) acc[e] = 0.0;
+  // Row segment r0 .. r0 + VR of the first nl list entries (columns, coefficients) in
+  // LDS, accumulated into acc; RPW columns per wave in flight.
+  auto stream_list = [&](int r0, int nl, double (&acc)[VR]) {
     for (int k0 = wave * RPW; k0 < nl; k0 += NW * RPW) {
       int idx[RPW];
       double val[RPW];
@@ -867,6 +835,105 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
           for (int e = 0; e < VR; ++e)
             if (r0 + e < a.N) acc[e] = fma(to_double(col[r0 + e]), val[p], acc[e]);
         }
+      }
+    }
+  };
+
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int rt = item % nrt, sg = item / nrt;
+    if (item != static_cast<int>(blockIdx.x)) load_slots(item, raw);
+    const int r0 = rt * RT + lane * VR;
+    double acc[VR];
+#pragma unroll
+    for (int e = 0; e < VR; ++e) acc[e] = 0.0;
+    double om = 0.0;
+    if constexpr (!GROUP) {
+      // ---- the kept, non-zero support entries of segment group sg (in order) ----
+      int cntv = 0;
+      int e_atom[SPT];
+      double e_val[SPT];
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = tid + q * BLK;  // slot within the item
+        const int b = sg * SG + s / SEGCAP_L, j = s % SEGCAP_L;
+        e_atom[q] = -1;
+        e_val[q] = 0.0;
+        if (b < a.grid_corr && j < raw[q].nk && !(raw[q].marg > r_keep)) {
+          if (raw[q].val != 0.0) {
+            e_atom[q] = raw[q].atom;
+            e_val[q] = raw[q].val;
+            ++cntv;
+          }
+          om += raw[q].om;
+        }
+      }
+      if (rt == 0) {
+        om = block_sum<double, NW>(om, sd);
+        if (tid == 0) a.omp[a.par * MAXITEM + sg] = om;
+      }
+      int total;
+      int off = block_exclusive_scan<NW>(cntv, scan, &total);
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        if (e_atom[q] >= 0) {
+          l_idx[off] = e_atom[q];
+          l_val[off] = e_val[q];
+          ++off;
+        }
+      }
+      __syncthreads();
+      stream_list(r0, total, acc);
+    } else {
+      // ---- groups: the atoms of the kept groups with a non-zero u_g, in order ----
+      // Thread tid holds group record tid of the item; its m atoms occupy list positions
+      // [off, off + m) after a block scan, and a chunk of positions is filled by locating
+      // each position's record (binary search over the offsets) and reading its slot.
+      const int b = sg * SG + tid / CBG, j = tid % CBG;
+      int na = 0;
+      if (b < a.grid_corr && j < raw[0].nk && !(raw[0].marg > r_keep)) {
+        om += raw[0].om;
+        if (raw[0].om > 0.0) na = raw[0].m;
+      }
+      if (rt == 0) {
+        om = block_sum<double, NW>(om, sd);
+        if (tid == 0) a.omp[a.par * MAXITEM + sg] = om;
+      }
+      int total;
+      const int off = block_exclusive_scan<NW>(na, scan, &total);
+      s_goff[tid] = off;
+      s_gbase[tid] = raw[0].atom;
+      __syncthreads();
+      constexpr int FPT = LCAP / BLK;  // list positions filled per thread per chunk
+      for (int c0 = 0; c0 < total; c0 += LCAP) {
+        const int nl = min(LCAP, total - c0);
+        int slot[FPT];
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) {
+          const int pp = c0 + min(tid + q * BLK, nl - 1);
+          int lo = 0, hi = BLK;  // first record whose offset exceeds pp
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_goff[mid] <= pp) lo = mid + 1; else hi = mid;
+          }
+          slot[q] = s_gbase[lo - 1] + (pp - s_goff[lo - 1]);
+        }
+        int at[FPT];
+        V vv[FPT];
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) {
+          at[q] = a.seg_atom[slot[q]];
+          vv[q] = a.seg_val[slot[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) {
+          if (tid + q * BLK < nl) {
+            l_idx[tid + q * BLK] = at[q];
+            l_val[tid + q * BLK] = static_cast<double>(vv[q]);
+          }
+        }
+        __syncthreads();
+        stream_list(r0, nl, acc);
+        __syncthreads();
       }
     }
 #pragma unroll
