@@ -487,13 +487,17 @@ ds_status spectral_t(const ds_problem& P, int iters, double* Lout, hipStream_t s
   const int N = static_cast<int>(P.N), K = static_cast<int>(P.K);
   const T* D = static_cast<const T*>(P.D);
   const int nch = (K + PCH - 1) / PCH;
-  const int nrt = (N + BLK - 1) / BLK;
-  const int gdv = grid_for(static_cast<int64_t>(nrt) * nch, 1, 2048);
   const bool vec = vector_ok<T>(P.D, P.ldd);
+  const int rt_rows = vec ? WAVE * Store<T>::VEC : WAVE;
+  const int nrt = (N + rt_rows - 1) / rt_rows;
+  const int gdv = grid_for(static_cast<int64_t>(nrt) * nch, 1, 4096);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(K, BLK, 1 << 20)), dim3(BLK), 0, s, v, K,
                      1.0 / std::sqrt(static_cast<double>(K)));
   auto dv = [&](const double* src) {
-    hipLaunchKernelGGL((k_pow_dv<T>), dim3(gdv), dim3(BLK), 0, s, D, P.ldd, N, K, src, part, l.npad);
+    if (vec)
+      hipLaunchKernelGGL((k_pow_dv<T, true>), dim3(gdv), dim3(BLK), 0, s, D, P.ldd, N, K, src, part, l.npad);
+    else
+      hipLaunchKernelGGL((k_pow_dv<T, false>), dim3(gdv), dim3(BLK), 0, s, D, P.ldd, N, K, src, part, l.npad);
     hipLaunchKernelGGL(k_pow_reduce, dim3(grid_for(N, BLK, 1 << 20)), dim3(BLK), 0, s, part, nch,
                        l.npad, N, w);
   };

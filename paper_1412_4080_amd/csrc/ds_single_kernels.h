@@ -270,14 +270,16 @@ __global__ __launch_bounds__(BLK) void k_group_norms(const T* __restrict__ D, in
       if (lane == 0) { gram[a * GM + b] = s; gram[b * GM + a] = s; }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double f2 = 0.0;
-      for (int a = 0; a < m; ++a) f2 += gram[a * GM + a];
-      // cyclic Jacobi sweeps until the off-diagonal mass is negligible
+    // cyclic Jacobi sweeps on wave 0, lane k owning row k: for each rotation (p, q) the
+    // lanes update their entries of columns p and q, then of rows p and q (the same
+    // arithmetic per entry as a serial sweep; LDS accesses of one wave stay in order)
+    if (wv == 0) {
+      const double f2 = wave_sum(lane < m ? gram[lane * GM + lane] : 0.0);
       for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0;
-        for (int p = 0; p < m; ++p)
-          for (int q = p + 1; q < m; ++q) off += gram[p * GM + q] * gram[p * GM + q];
+        if (lane < m)
+          for (int q = lane + 1; q < m; ++q) off += gram[lane * GM + q] * gram[lane * GM + q];
+        off = wave_sum(off);
         if (off <= 1e-30 * f2 * f2) break;
         for (int p = 0; p < m; ++p) {
           for (int q = p + 1; q < m; ++q) {
@@ -287,23 +289,27 @@ __global__ __launch_bounds__(BLK) void k_group_norms(const T* __restrict__ D, in
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-            for (int k = 0; k < m; ++k) {
-              const double akp = gram[k * GM + p], akq = gram[k * GM + q];
-              gram[k * GM + p] = c * akp - s * akq;
-              gram[k * GM + q] = s * akp + c * akq;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < m) {
+              const double akp = gram[lane * GM + p], akq = gram[lane * GM + q];
+              gram[lane * GM + p] = c * akp - s * akq;
+              gram[lane * GM + q] = s * akp + c * akq;
             }
-            for (int k = 0; k < m; ++k) {
-              const double apk = gram[p * GM + k], aqk = gram[q * GM + k];
-              gram[p * GM + k] = c * apk - s * aqk;
-              gram[q * GM + k] = s * apk + c * aqk;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < m) {
+              const double apk = gram[p * GM + lane], aqk = gram[q * GM + lane];
+              gram[p * GM + lane] = c * apk - s * aqk;
+              gram[q * GM + lane] = s * apk + c * aqk;
             }
+            __builtin_amdgcn_wave_barrier();
           }
         }
       }
-      double lmax = 0.0;
-      for (int a = 0; a < m; ++a) lmax = fmax(lmax, gram[a * GM + a]);
-      gnorm[g] = sqrt(lmax);
-      fro[g] = sqrt(f2);
+      const double lmax = wave_max(lane < m ? gram[lane * GM + lane] : 0.0);
+      if (lane == 0) {
+        gnorm[g] = sqrt(lmax);
+        fro[g] = sqrt(f2);
+      }
     }
     __syncthreads();
   }
@@ -1259,33 +1265,89 @@ __global__ __launch_bounds__(BLK) void k_mark_active(SingleArgs<T, V, A> a, uint
 
 // ============================================================== power iteration =====
 
-// w = D v over all K columns: partial sums over column chunks of PCH, FP64.
-constexpr int PCH = 64;
-template <typename T>
+// w = D v over all K columns, FP64: work items (row tile x chunk of PCH columns); each
+// wave streams its share of the chunk's columns RPW at a time (16-byte loads when
+// aligned), the block adds the waves' row partials in wave order and writes one partial
+// per (chunk, row); k_pow_reduce adds the chunks in order.
+constexpr int PCH = 512;
+template <typename T, bool VECTOR>
 __global__ __launch_bounds__(BLK) void k_pow_dv(const T* __restrict__ D, int64_t ldd, int N,
                                                  int K, const double* __restrict__ v,
                                                  double* __restrict__ part, int64_t npad) {
-  const int nrt = (N + BLK - 1) / BLK;
+  constexpr int VR = VECTOR ? Store<T>::VEC : 1;
+  constexpr int RT = WAVE * VR;
+  __shared__ double red[NW][RT];
+  const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+  const int nrt = (N + RT - 1) / RT;
   const int nch = (K + PCH - 1) / PCH;
   for (int item = blockIdx.x; item < nrt * nch; item += gridDim.x) {
     const int rt = item % nrt, c = item / nrt;
-    const int r = rt * BLK + threadIdx.x;
-    if (r >= N) continue;
-    double s = 0.0;
+    const int r0 = rt * RT + lane * VR;
     const int k1 = min((c + 1) * PCH, K);
-    for (int k = c * PCH; k < k1; ++k) s = fma(to_double(D[static_cast<int64_t>(k) * ldd + r]), v[k], s);
-    part[static_cast<int64_t>(c) * npad + r] = s;
+    double acc[VR];
+#pragma unroll
+    for (int e = 0; e < VR; ++e) acc[e] = 0.0;
+    for (int kb = c * PCH + wave * RPW; kb < k1; kb += NW * RPW) {
+      int idx[RPW];
+      double val[RPW];
+#pragma unroll
+      for (int p = 0; p < RPW; ++p) {
+        const bool ok = kb + p < k1;
+        idx[p] = ok ? kb + p : kb;
+        val[p] = ok ? v[kb + p] : 0.0;
+      }
+      if (VECTOR && r0 + VR <= N) {
+        if constexpr (VECTOR) {
+          uint4 cv[RPW];
+#pragma unroll
+          for (int p = 0; p < RPW; ++p) cv[p] = ld16(D + static_cast<int64_t>(idx[p]) * ldd + r0);
+#pragma unroll
+          for (int p = 0; p < RPW; ++p) {
+            double d[VR];
+            widen<T>(cv[p], d);
+#pragma unroll
+            for (int e = 0; e < VR; ++e) acc[e] = fma(d[e], val[p], acc[e]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) {
+          const T* col = D + static_cast<int64_t>(idx[p]) * ldd;
+          for (int e = 0; e < VR; ++e)
+            if (r0 + e < N) acc[e] = fma(to_double(col[r0 + e]), val[p], acc[e]);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VR; ++e) red[wave][lane * VR + e] = acc[e];
+    __syncthreads();
+    for (int rr = tid; rr < RT; rr += BLK) {
+      const int r = rt * RT + rr;
+      if (r < N) {
+        double s = red[0][rr];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s += red[w][rr];
+        part[static_cast<int64_t>(c) * npad + r] = s;
+      }
+    }
+    __syncthreads();
   }
 }
 __global__ __launch_bounds__(BLK) void k_pow_reduce(const double* __restrict__ part, int nch,
                                                      int64_t npad, int N, double* __restrict__ w) {
+  constexpr int FB = 16;  // chunk partials loaded at once (clamped indices, in order)
   const int r = blockIdx.x * BLK + threadIdx.x;
   if (r >= N) return;
   double s = 0.0;
-  for (int c = 0; c < nch; ++c) s += part[static_cast<int64_t>(c) * npad + r];
+  for (int c0 = 0; c0 < nch; c0 += FB) {
+    double q[FB];
+#pragma unroll
+    for (int k = 0; k < FB; ++k) q[k] = part[static_cast<int64_t>(min(c0 + k, nch - 1)) * npad + r];
+#pragma unroll
+    for (int k = 0; k < FB; ++k) s += c0 + k < nch ? q[k] : 0.0;
+  }
   w[r] = s;
 }
-// out = [sum a_i^2, sum a_i b_i, sum b_i^2] over n (single block, FP64).
 __global__ __launch_bounds__(CBLK) void k_pow_dots(const double* __restrict__ a,
                                                     const double* __restrict__ b, int n,
                                                     double* __restrict__ out) {
