@@ -9,10 +9,20 @@ point v = mu * theta, sphere centre c and radius r, screened set I_t.
 
 Readings of points the paper leaves open (each one is listed in the design doc):
 
-* Step size: the paper sets L_t by backtracking (Table 1) without constants;
-  here L is a constant >= ||D||_2^2 supplied by the caller (default: the exact
-  largest eigenvalue of D D^T).  A constant L >= ||D_t||_2^2 stays valid after
-  every screening because removing columns cannot increase the spectral norm.
+* Step size: the paper sets L_t by the backtracking rule of Beck and Teboulle
+  (Table 1) without constants.  step="constant" (the default) uses a constant
+  L >= ||D||_2^2 supplied by the caller (default: the exact largest eigenvalue of
+  D D^T); it stays valid after every screening because removing columns cannot
+  increase the spectral norm.  step="backtracking" starts from L_0 (the caller's L,
+  default the largest squared atom norm, or the largest ||D_g||_2^2 for groups)
+  and, at every iteration, accepts the proximal point x' = prox(p - z / L) when
+  ||D_t (x' - p)||^2 <= L ||x' - p||^2 -- for the quadratic data term this is exactly
+  the condition F(x') <= Q_L(x', p) of that rule -- and otherwise multiplies L by
+  eta (default 2) and repeats the iteration from the same p: such a rejected pass
+  still produces its dual point, gap and screening radius (they do not depend on
+  L), the FISTA sequence l_t does not advance, and the next pass evaluates theta at
+  p restricted to the atoms that remain.  The solve stops only at an accepted step,
+  so the returned x_t again has an objective no larger than the certified p.
 * Initialisation X_0: x_0 = u_0 = 0 and l_0 = 1.
 * Dual scaling uses the correlations z_t = D_{t-1}^T theta_t of the current,
   already reduced dictionary, as the turnkey instance (Algorithm 5) does.
@@ -234,7 +244,8 @@ def _trivial(K, lam, lam_max, L, G=None):
 
 
 def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
-                max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic") -> OracleResult:
+                max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic",
+                step="constant", eta=2.0) -> OracleResult:
     """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
@@ -246,16 +257,18 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     screening="static" runs the test once, at the first iteration, where the dual point
     from x_0 = 0 makes it the static test of Algorithms 1 and 4 (static SAFE, ST3); the
     first update does not depend on the atoms that test removes (their prox output is 0).
+    step="backtracking" sets L_t by the backtracking rule (module docstring); L is then L_0.
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     N, K = D.shape
     assert test in ("none", "safe", "dst3") and rule in ("ista", "fista")
+    assert step in ("constant", "backtracking") and eta > 1.0
     lam_max, i_star = lambda_max_lasso(D, y)
     if lam is None:
         lam = float(lam_ratio) * lam_max
     if L is None:
-        L = spectral_norm_sq(D)
+        L = spectral_norm_sq(D) if step == "constant" else float(np.max(np.sum(D * D, axis=0)))
     if lam >= lam_max:
         return _trivial(K, lam, lam_max, L)
 
@@ -278,6 +291,11 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         theta = Dt @ p - y
         z = Dt.T @ theta
         x_new = soft_threshold(p - z / L, lam / L)
+        accepted = True
+        if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
+            d = x_new - p
+            Dd = Dt @ d
+            accepted = float(Dd @ Dd) <= L * float(d @ d)
         if rule == "fista":
             l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
             u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
@@ -298,9 +316,16 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         r_min = min(r_min, r)
         if record:
             hist.append(dict(t=t, n_active=int(active.size), nnz=int(np.count_nonzero(x_new)),
-                             nnz_p=int(np.count_nonzero(p)), r=r, gap=gap, mu=mu))
-        if gap_tol > 0.0 and gap <= gap_tol * yy:
-            converged = True
+                             nnz_p=int(np.count_nonzero(p)), r=r, gap=gap, mu=mu, L=L,
+                             accepted=accepted, primal_p=primal_p))
+            if step == "backtracking":   # the candidate and its primal point, active coordinates
+                hist[-1].update(cand=x_new.copy(), p=p.copy(), active=active.copy())
+        converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
+        if not accepted:
+            # rejected step: keep p, grow L; at the iteration limit return the last accepted x
+            x_new, u_new, l_new = x, u, l_prev
+            if t < max_iter:
+                L *= eta
         if converged or t == max_iter:
             break
         # ---- screening: I_t = {i : T_v(i)} U I_{t-1}, then reduce D and X ----
@@ -332,13 +357,15 @@ def _as_groups(K, groups):
 
 def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="ista",
                       test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
-                      record=False, screening="dynamic") -> OracleResult:
+                      record=False, screening="dynamic", step="constant",
+                      eta=2.0) -> OracleResult:
     """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
 
     groups: a partition of range(K) (list of index arrays, or contiguous CSR
     offsets); w: group weights, default sqrt(|g|).  Tests: GSAFE (Lemma 4),
     DGST3 (Lemma 5) or none; the screening unit is the group.  screening="static"
-    runs the test once, at the first iteration (the static group tests).
+    runs the test once, at the first iteration (the static group tests).  step as in
+    solve_lasso (the default L_0 for backtracking is max_g ||D_g||_2^2).
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -348,15 +375,16 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     w = np.sqrt([len(g) for g in groups]).astype(np.float64) if w is None else np.asarray(w, np.float64)
     assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista")
     assert screening in ("dynamic", "static")
+    assert step in ("constant", "backtracking") and eta > 1.0
     lam_max, g_star = lambda_max_group(D, y, groups, w)
     if lam is None:
         lam = float(lam_ratio) * lam_max
+    gnorm = group_spectral_norms(D, groups)
     if L is None:
-        L = spectral_norm_sq(D)
+        L = spectral_norm_sq(D) if step == "constant" else float(np.max(gnorm) ** 2)
     if lam >= lam_max:
         return _trivial(K, lam, lam_max, L, G)
 
-    gnorm = group_spectral_norms(D, groups)
     c, rho2 = group_center(D, y, lam, test, groups, w, lam_max, g_star)
     m = group_margins(D, c, test, groups, w, gnorm)
     yy = float(y @ y)
@@ -386,6 +414,11 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         theta = Dt @ p - y
         z = Dt.T @ theta
         x_new = group_soft_threshold(p - z / L, lam / L, local, wa)
+        accepted = True
+        if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
+            d = x_new - p
+            Dd = Dt @ d
+            accepted = float(Dd @ Dd) <= L * float(d @ d)
         if rule == "fista":
             l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
             u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
@@ -407,9 +440,12 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         if record:
             hist.append(dict(t=t, n_active=int(cols.size), n_active_groups=int(act_g.size),
                              nnz=int(np.count_nonzero(x_new)), nnz_p=int(np.count_nonzero(p)),
-                             r=r, gap=gap, mu=mu))
-        if gap_tol > 0.0 and gap <= gap_tol * yy:
-            converged = True
+                             r=r, gap=gap, mu=mu, L=L, accepted=accepted, primal_p=primal_p))
+        converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
+        if not accepted:
+            x_new, u_new, l_new = x, u, l_prev
+            if t < max_iter:
+                L *= eta
         if converged or t == max_iter:
             break
         if screening == "dynamic" or t == 1:

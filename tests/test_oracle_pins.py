@@ -447,6 +447,112 @@ def _golden():
     return vals, x
 
 
+# --------------------------------------------------------------------------
+# Backtracking step sizes (Table 1: L_t by the rule of Beck and Teboulle)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+@pytest.mark.parametrize("group", [False, True])
+def test_backtracking_from_a_global_bound_never_rejects(rule, group):
+    """Starting at L_0 = ||D||_2^2 every step satisfies the descent condition, so the run is
+    the constant-step run, iterate for iterate."""
+    D, y = _problem(N=50, K=160, seed=61)
+    L = oracle.spectral_norm_sq(D)
+    if group:
+        gp = datagen.contiguous_groups(160, 8)
+        a = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.4, rule=rule, test="dgst3", L=L,
+                                     max_iter=400, gap_tol=1e-9, record=True)
+        b = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.4, rule=rule, test="dgst3", L=L,
+                                     max_iter=400, gap_tol=1e-9, record=True, step="backtracking")
+    else:
+        a = oracle.solve_lasso(D, y, lam_ratio=0.4, rule=rule, test="dst3", L=L, max_iter=400,
+                               gap_tol=1e-9, record=True)
+        b = oracle.solve_lasso(D, y, lam_ratio=0.4, rule=rule, test="dst3", L=L, max_iter=400,
+                               gap_tol=1e-9, record=True, step="backtracking")
+    assert all(h["accepted"] for h in b.history)
+    assert a.iters == b.iters and np.array_equal(a.x, b.x) and b.L == L
+
+
+@pytest.mark.parametrize("group", [False, True])
+def test_backtracking_ista_objective_never_increases(group):
+    """With the descent condition F(x') <= Q_L(x', p) <= F(p) (Beck and Teboulle), ISTA
+    never increases the objective at its iterates; without screening the primal point of
+    each iteration is the previous iterate, so P(p_t) is non-increasing."""
+    D, y = _problem(N=60, K=200, seed=62)
+    kw = dict(lam_ratio=0.3, rule="ista", max_iter=300, gap_tol=0.0, record=True,
+              step="backtracking", L=0.05)
+    if group:
+        r = oracle.solve_group_lasso(D, y, datagen.contiguous_groups(200, 10), test="none", **kw)
+    else:
+        r = oracle.solve_lasso(D, y, test="none", **kw)
+    pp = np.array([h["primal_p"] for h in r.history])
+    assert np.all(np.diff(pp) <= 1e-13 * pp[0])
+    assert not all(h["accepted"] for h in r.history)   # L_0 = 0.05 had to grow
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_backtracking_decisions_follow_the_descent_condition(rule):
+    """Each step is accepted exactly when F(x') <= Q_L(x', p) = f(p) + <x' - p, grad f(p)>
+    + L/2 ||x' - p||^2 + lambda ||x'||_1 holds, evaluated here from its definition."""
+    D, y = _problem(N=50, K=150, seed=65)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.3, rule=rule, test="dst3", L=0.02, max_iter=600,
+                           gap_tol=1e-10, record=True, step="backtracking")
+    n_rej = 0
+    for h in r.history:
+        Da = D[:, h["active"]]
+        p, xc = h["p"], h["cand"]
+        f = lambda v: 0.5 * float((Da @ v - y) @ (Da @ v - y))
+        grad = Da.T @ (Da @ p - y)
+        F = f(xc) + r.lam * np.abs(xc).sum()
+        Q = f(p) + float((xc - p) @ grad) + 0.5 * h["L"] * float((xc - p) @ (xc - p)) \
+            + r.lam * np.abs(xc).sum()
+        margin = 1e-12 * (1.0 + abs(Q))
+        if h["accepted"]:
+            assert F <= Q + margin
+        else:
+            assert F > Q - margin
+            n_rej += 1
+    assert n_rej > 0
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_backtracking_step_sequence(rule):
+    """L stays put on accepted steps, is multiplied by eta exactly on rejected ones, and
+    never exceeds eta ||D||_2^2 (any L >= ||D||_2^2 satisfies the condition)."""
+    D, y = _problem(N=60, K=200, seed=63)
+    eta = 1.7
+    r = oracle.solve_lasso(D, y, lam_ratio=0.2, rule=rule, test="dst3", L=0.01, eta=eta,
+                           max_iter=2000, gap_tol=1e-10, record=True, step="backtracking")
+    Ls = [h["L"] for h in r.history]
+    for h, L_next in zip(r.history[:-1], Ls[1:]):
+        assert L_next == (h["L"] if h["accepted"] else h["L"] * eta)
+    assert max(Ls) <= eta * oracle.spectral_norm_sq(D)
+    assert r.converged and r.history[-1]["accepted"]
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+@pytest.mark.parametrize("group", [False, True])
+def test_backtracking_reaches_the_same_optimum(rule, group):
+    D, y = _problem(N=70, K=240, seed=64)
+    tol = 1e-11
+    if group:
+        gp = datagen.contiguous_groups(240, 10)
+        a = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.35, rule=rule, test="dgst3",
+                                     max_iter=100000, gap_tol=tol)
+        b = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.35, rule=rule, test="dgst3",
+                                     max_iter=100000, gap_tol=tol, step="backtracking")
+    else:
+        a = oracle.solve_lasso(D, y, lam_ratio=0.35, rule=rule, test="dst3", max_iter=100000,
+                               gap_tol=tol)
+        b = oracle.solve_lasso(D, y, lam_ratio=0.35, rule=rule, test="dst3", max_iter=100000,
+                               gap_tol=tol, step="backtracking")
+    yy = float(y @ y)
+    assert a.converged and b.converged
+    # both certified within tol ||y||^2 of the optimum, so their objectives agree to 2 tol
+    assert abs(a.primal - b.primal) <= 2 * tol * yy
+    assert b.primal - b.dual <= b.gap + 1e-15
+
+
 def test_small_fp64_configuration_matches_stored_values():
     g, gx = _golden()
     c = datagen.lasso_small_fp64()
