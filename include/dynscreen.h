@@ -74,18 +74,31 @@ typedef struct {
   const double* w;           /* host, G positive weights; NULL means w_g = sqrt(|g|) */
 } ds_problem;
 
+/* Step size L_t of the proximal update (Table 1). */
+typedef enum { DS_STEP_CONSTANT = 0, DS_STEP_BACKTRACK = 1 } ds_step_rule;
+
 typedef struct {
   ds_rule rule;
   ds_test test;
   ds_lambda_mode lambda_mode;
-  double step_L;     /* > 0: constant step 1/step_L, must be >= ||D||_2^2.
-                        <= 0: the library estimates ||D||_2^2 (ds_spectral_norm_sq). */
+  double step_L;     /* DS_STEP_CONSTANT: > 0: constant step 1/step_L, must be >= ||D||_2^2;
+                        <= 0: the library estimates ||D||_2^2 (ds_spectral_norm_sq).
+                        DS_STEP_BACKTRACK: > 0: L_0; <= 0: L_0 = the largest squared atom
+                        norm (Lasso) or ||D_g||_2^2 (Group-Lasso). */
   double gap_tol;    /* > 0: stop once the duality-gap certificate <= gap_tol * ||y||^2.
                         0: run exactly max_iter iterations. */
   int32_t max_iter;  /* >= 1 */
   int32_t screening; /* 0: dynamic (Algorithm 3: the test is re-run at every iteration).
                         1: static (Algorithms 1 and 4: the test is run once, with the dual
                         point of the first iteration, i.e. the static SAFE / ST3 rules). */
+  int32_t step_rule; /* ds_step_rule.  DS_STEP_BACKTRACK: the rule of Beck and Teboulle that
+                        Table 1 names for ISTA and FISTA.  The proximal point x' of an
+                        iteration is kept when ||D (x' - p)||^2 <= L ||x' - p||^2 (for the
+                        quadratic data term, F(x') <= Q_L(x', p)); otherwise the iteration is
+                        repeated from the same p with L multiplied by bt_eta (the rejected pass
+                        still counts as an iteration and still screens).  Single-signal and
+                        served solves; the batched bfloat16 path returns DS_EINVAL. */
+  double bt_eta;     /* backtracking growth factor, > 1; 0 selects 2 */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which
@@ -104,7 +117,7 @@ typedef struct {
   double gap;          /* primal - dual */
   double radius;       /* smallest sphere radius reached (r_min) */
   double mu;           /* dual-scaling factor of the last iteration */
-  double L;            /* step constant used */
+  double L;            /* step constant used (backtracking: the last L_t) */
   double radius_slack; /* rounding slack added to the radius (>= 0) */
   double queue_ms;     /* served requests: submit -> start of the solve; else 0 */
   double run_ms;       /* served requests: start -> end of the solve; else 0 */

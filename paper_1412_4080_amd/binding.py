@@ -26,6 +26,7 @@ RULES = {"ista": 0, "fista": 1}
 TESTS = {"none": 0, "safe": 1, "dst3": 2, "gsafe": 1, "dgst3": 2}
 STATUS_NAMES = {0: "DS_OK", 1: "DS_PENDING", 2: "DS_NOT_CONVERGED", -1: "DS_EINVAL",
                 -2: "DS_ENOMEM", -3: "DS_EDEVICE", -4: "DS_ENOTFOUND", -5: "DS_EBUSY"}
+STEPS = {"constant": 0, "backtracking": 1}
 STAT_CORR, STAT_RESID, STAT_SETUP, STAT_BATCH, STAT_BATCH_THETA, STAT_COUNT = 0, 1, 2, 3, 4, 5
 
 
@@ -38,7 +39,7 @@ class Problem(C.Structure):
 class Params(C.Structure):
     _fields_ = [("rule", C.c_int), ("test", C.c_int), ("lambda_mode", C.c_int),
                 ("step_L", C.c_double), ("gap_tol", C.c_double), ("max_iter", C.c_int32),
-                ("screening", C.c_int32)]
+                ("screening", C.c_int32), ("step_rule", C.c_int32), ("bt_eta", C.c_double)]
 
 
 class Info(C.Structure):
@@ -175,14 +176,14 @@ SCREENING = {"dynamic": 0, "static": 1}
 
 
 def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap_tol=1e-6,
-                max_iter=10000, screening="dynamic"):
+                max_iter=10000, screening="dynamic", step="constant", bt_eta=0.0):
     return Params(RULES[rule], TESTS[test], 1 if lambda_relative else 0, float(step_L),
-                  float(gap_tol), int(max_iter), SCREENING[screening])
+                  float(gap_tol), int(max_iter), SCREENING[screening], STEPS[step], float(bt_eta))
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
           lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
-          screened=False, screening="dynamic"):
+          screened=False, screening="dynamic", step="constant", bt_eta=0.0):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
@@ -209,7 +210,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     lam = (C.c_double * B)(*[float(v) for v in (lambdas if hasattr(lambdas, "__len__") else [lambdas])])
     infos = (Info * B)()
     prob = make_problem(D, group_ptr, weights)
-    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening)
+    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta)
     if screened:
         if group_ptr is not None:
             raise ValueError("screened masks of batched solves are for the Lasso")
@@ -230,7 +231,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
 
 def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="dst3",
               lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, trace=True,
-              screened=True, stream=None, screening="dynamic"):
+              screened=True, stream=None, screening="dynamic", step="constant", bt_eta=0.0):
     """Single-signal solve returning (x, info, screened_mask or None, trace list or None)."""
     torch = _torch()
     K = D.shape[1]
@@ -243,7 +244,7 @@ def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="ds
     tr = (Trace * max(cap, 1))()
     info = Info()
     prob = make_problem(D, group_ptr, weights)
-    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening)
+    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta)
     st = _lib.ds_solve_one(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam), C.byref(prm),
                            C.c_void_p(x.data_ptr()),
                            C.c_void_p(scr.data_ptr()) if scr is not None else None,
@@ -311,12 +312,14 @@ class Server:
         return did.value
 
     def submit(self, dict_id, y_host, lam, *, rule="fista", test="dst3", lambda_relative=True,
-               step_L=0.0, gap_tol=1e-6, max_iter=10000, screening="dynamic"):
+               step_L=0.0, gap_tol=1e-6, max_iter=10000, screening="dynamic", step="constant",
+               bt_eta=0.0):
         import numpy as np
         N, K, dt, store = self._dicts[dict_id]
         y = np.ascontiguousarray(y_host, dtype=np.float64 if store == 0 else np.float32)
         assert y.size == N
-        prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening)
+        prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step,
+                          bt_eta)
         rid = C.c_uint64()
         st = _lib.lasso_submit(self._h, int(dict_id), y.ctypes.data_as(C.c_void_p), float(lam),
                                C.byref(prm), C.byref(rid))

@@ -145,6 +145,14 @@ ds_status validate_params(const ds_params* p) {
   if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return DS_EINVAL; }
   if (!std::isfinite(p->step_L)) { set_error("step_L must be finite"); return DS_EINVAL; }
   if (p->screening != 0 && p->screening != 1) { set_error("screening must be 0 (dynamic) or 1 (static)"); return DS_EINVAL; }
+  if (p->step_rule != DS_STEP_CONSTANT && p->step_rule != DS_STEP_BACKTRACK) {
+    set_error("step_rule must be DS_STEP_CONSTANT or DS_STEP_BACKTRACK");
+    return DS_EINVAL;
+  }
+  if (p->step_rule == DS_STEP_BACKTRACK && p->bt_eta != 0.0 && !(p->bt_eta > 1.0 && std::isfinite(p->bt_eta))) {
+    set_error("bt_eta must be > 1 (or 0 for the default 2)");
+    return DS_EINVAL;
+  }
   return DS_OK;
 }
 
@@ -174,6 +182,10 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   if (B > 1 && problem->dtype == DS_BF16 && !group) {
+    if (params->step_rule == DS_STEP_BACKTRACK) {
+      set_error("backtracking steps are available on the single-signal path (B = 1 or FP32/FP64 D)");
+      return DS_EINVAL;
+    }
     return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, screened, s);
   }
   DeviceCtx& ctx = device_ctx(dev);

@@ -21,7 +21,7 @@ struct Layout {
       off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_segcnt,
       off_segatom, off_segval, off_urm, off_uro, off_urn, off_bp0, off_bpi, off_rtn, off_omp,
       off_rtcnt, off_lba, off_cnt, off_gptr, off_w, off_tele, off_kclk, off_spans, off_pv, off_pw,
-      off_pz, off_pd, total;
+      off_pz, off_pd, off_segxo, off_segpo, off_segd, off_uromo, off_urdn, off_bpd, off_dtn, total;
   int64_t npad, grid_corr, nsg;
 };
 
@@ -69,6 +69,13 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.off_urn = take(l.grid_corr * ucap * 4);
   l.off_bp0 = take(MAXB * 8);
   l.off_bpi = take(4 * MAXB * 4);
+  l.off_segxo = take(l.grid_corr * segcap * vsz);
+  l.off_segpo = take(l.grid_corr * segcap * vsz);
+  l.off_segd = take(l.grid_corr * segcap * 8);
+  l.off_uromo = take(l.grid_corr * ucap * 8);
+  l.off_urdn = take(l.grid_corr * ucap * 8);
+  l.off_bpd = take(MAXB * 8);
+  l.off_dtn = take(MAXRT * 8);
   l.off_rtn = take(2 * 2 * MAXRT * 8);
   l.off_omp = take(2 * MAXITEM * 8);
   l.off_rtcnt = take(MAXRT * 4);
@@ -142,6 +149,13 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.urec_m = reinterpret_cast<int32_t*>(base + l.off_urn);
   a.bp0 = reinterpret_cast<double*>(base + l.off_bp0);
   a.bpi = reinterpret_cast<int32_t*>(base + l.off_bpi);
+  a.seg_xo = reinterpret_cast<V*>(base + l.off_segxo);
+  a.seg_po = reinterpret_cast<V*>(base + l.off_segpo);
+  a.seg_d = reinterpret_cast<double*>(base + l.off_segd);
+  a.urec_omo = reinterpret_cast<double*>(base + l.off_uromo);
+  a.urec_dn = reinterpret_cast<double*>(base + l.off_urdn);
+  a.bpd = reinterpret_cast<double*>(base + l.off_bpd);
+  a.dtn = reinterpret_cast<double*>(base + l.off_dtn);
   a.rtn = reinterpret_cast<double*>(base + l.off_rtn);
   a.omp = reinterpret_cast<double*>(base + l.off_omp);
   a.rt_cnt = reinterpret_cast<unsigned*>(base + l.off_rtcnt);
@@ -220,9 +234,15 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
 
   // ---- setup (no host synchronisation) ----
   if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
-  // L: given, or estimated here (slow path)
+  // L: given, or estimated here (slow path); backtracking starts from step_L when given,
+  // else from a bound the setup kernel computes on the device
+  const bool bt = prm.step_rule == DS_STEP_BACKTRACK;
+  const double eta = bt ? (prm.bt_eta > 0.0 ? prm.bt_eta : 2.0) : 0.0;
+  a.bt = bt ? 1 : 0;
+  DS_HIP(hipMemsetAsync(a.bpd, 0, MAXB * 8, s));
+  DS_HIP(hipMemsetAsync(a.dtn, 0, MAXRT * 8, s));
   double L = prm.step_L;
-  if (!(L > 0.0)) {
+  if (!(L > 0.0) && !bt) {
     // the power iteration uses its own (larger) workspace; keep ours intact by running it
     // on a private one
     Workspace tmp;
@@ -237,7 +257,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   const double gamma_z = kchain * u_round / (1.0 - kchain * u_round);
   const bool relative = prm.lambda_mode == DS_LAMBDA_RELATIVE;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, lam,
-                     relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z);
+                     relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z, eta);
   DS_HIP(hipGetLastError());
   if (prm.test == DS_TEST_DST3) {
     hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
@@ -296,6 +316,13 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     else
       hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, false>), dim3(grid_res), dim3(BLK), 0, s, a);
   };
+  auto launch_dcheck = [&](int par) {
+    a.par = par;
+    if (P.G > 0)
+      hipLaunchKernelGGL((k_dcheck<T, V, VEC, true>), dim3(grid_res), dim3(BLK), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_dcheck<T, V, VEC, false>), dim3(grid_res), dim3(BLK), 0, s, a);
+  };
   auto launch_corr = [&](int par) {
     a.par = par;
     // instrumented launches carry start/stop events in the dispatch itself, so the
@@ -325,6 +352,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     for (int k = 0; k < nrun; ++k) {
       ++t;
       launch_corr(t % 2);
+      if (bt) launch_dcheck(t % 2);
       launch_resid((t + 1) % 2);
       last_par = (t + 1) % 2;
     }
@@ -457,7 +485,7 @@ ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t
                                : launch_setup_corr<T, false>(P, y, base, l, s);
   if (e != DS_OK) return e;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, 1.0, 1, 1.0, 0.0,
-                     1, 0.0);
+                     1, 0.0, 0.0);
   DS_HIP(hipGetLastError());
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));

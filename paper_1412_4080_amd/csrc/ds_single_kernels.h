@@ -322,7 +322,7 @@ template <typename T, typename V, typename A>
 __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, double lam_in,
                                                          int lam_relative, double L,
                                                          double gap_tol, int max_iter,
-                                                         double gamma_z) {
+                                                         double gamma_z, double bt_eta) {
   __shared__ double sd[CNW];
   __shared__ int si[CNW];
   __shared__ double s_lmax;
@@ -403,12 +403,27 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     nn = block_sum<double, CNW>(nn, sd);
     ny = block_sum<double, CNW>(ny, sd);
   }
+  // backtracking without a caller's L_0: the largest squared atom norm (Lasso) or
+  // ||D_g||_2^2 (groups), the curvature of the data term along one unit
+  const bool l0_dev = bt_eta > 0.0 && !(L > 0.0);
+  double l0 = 0.0;
+  if (l0_dev) {
+    for (int u = tid; u < units; u += CBLK) {
+      const double v = G > 0 ? a.gnorm[u] : a.nu[u];
+      l0 = fmax(l0, v * v);
+    }
+    l0 = block_max<double, CNW>(l0, sd);
+    if (!(l0 > 0.0)) l0 = 1.0;
+  }
   if (tid == 0) {
     const double alpha = (a.test == TEST_DST3 && nn > 0.0) ? (ny / lam - wstar2) / nn : 0.0;
     st->lam = lam;
     st->lam_ratio = lam_relative ? lam_in : lam / lam_max;
     st->lam_max = lam_max;
-    st->L = L;
+    st->L = l0_dev ? l0 : L;
+    st->bt_eta = bt_eta;
+    st->rejected = 0;
+    st->n_reject = 0;
     st->yy = yy;
     st->alpha = alpha;
     st->nn = nn;
@@ -608,10 +623,87 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitem
   }
 }
 
+// Row segment r0 .. r0 + VR of sum_k l_val[k] d_{l_idx[k]} over the first nl list entries
+// in LDS, accumulated into acc (FP64); each wave takes RPW columns at a time.
+template <typename T, typename V, bool VECTOR>
+__device__ __forceinline__ void stream_list(const SingleArgs<T, V, double>& a, const int* l_idx,
+                                            const double* l_val, int r0, int nl, int wave,
+                                            double (&acc)[VECTOR ? Store<T>::VEC : 1]) {
+  constexpr int VR = VECTOR ? Store<T>::VEC : 1;
+  for (int k0 = wave * RPW; k0 < nl; k0 += NW * RPW) {
+    int idx[RPW];
+    double val[RPW];
+#pragma unroll
+    for (int p = 0; p < RPW; ++p) {
+      const bool ok = k0 + p < nl;
+      idx[p] = ok ? l_idx[k0 + p] : l_idx[k0];
+      val[p] = ok ? l_val[k0 + p] : 0.0;
+    }
+    if (VECTOR && r0 + VR <= a.N) {
+      if constexpr (VECTOR) {
+        uint4 cv[RPW];
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) cv[p] = ld16(a.D + static_cast<int64_t>(idx[p]) * a.ldd + r0);
+#pragma unroll
+        for (int p = 0; p < RPW; ++p) {
+          double d[VR];
+          widen<T>(cv[p], d);
+#pragma unroll
+          for (int e = 0; e < VR; ++e) acc[e] = fma(d[e], val[p], acc[e]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < RPW; ++p) {
+        const T* col = a.D + static_cast<int64_t>(idx[p]) * a.ldd;
+        for (int e = 0; e < VR; ++e)
+          if (r0 + e < a.N) acc[e] = fma(to_double(col[r0 + e]), val[p], acc[e]);
+      }
+    }
+  }
+}
+
+// Groups: list positions c0 .. c0 + nl - 1 of the atoms of the item's selected group records
+// (record r owns positions [goff[r], goff[r] + its count), its slots start at gbase[r]),
+// located by binary search and read from the slot arrays into the LDS list.
+template <typename V>
+__device__ __forceinline__ void fill_group_list(const int* s_goff, const int* s_gbase, int c0, int nl,
+                                                const int32_t* __restrict__ seg_atom,
+                                                const V* __restrict__ vals, int* l_idx, double* l_val) {
+  constexpr int FPT = LCAP / BLK;  // list positions filled per thread
+  const int tid = threadIdx.x;
+  int slot[FPT];
+#pragma unroll
+  for (int q = 0; q < FPT; ++q) {
+    const int pp = c0 + min(tid + q * BLK, nl - 1);
+    int lo = 0, hi = BLK;  // first record whose offset exceeds pp
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_goff[mid] <= pp) lo = mid + 1; else hi = mid;
+    }
+    slot[q] = s_gbase[lo - 1] + (pp - s_goff[lo - 1]);
+  }
+  int at[FPT];
+  V vv[FPT];
+#pragma unroll
+  for (int q = 0; q < FPT; ++q) {
+    at[q] = seg_atom[slot[q]];
+    vv[q] = vals[slot[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < FPT; ++q) {
+    if (tid + q * BLK < nl) {
+      l_idx[tid + q * BLK] = at[q];
+      l_val[tid + q * BLK] = static_cast<double>(vv[q]);
+    }
+  }
+}
+
 // Raw support records of one residual slot, loaded before the kept / non-zero decision.
 struct SlotRaw {
   int nk, m, atom;
   double marg, om, val;
+  double omo, valo;  // backtracking: the same for p, before the step
 };
 
 template <typename T, typename V, bool VECTOR, int RULE, bool GROUP>
@@ -633,7 +725,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   __shared__ int scan[NW];
   __shared__ int s_last;
   __shared__ SolverState S;
-  __shared__ double red8[NW][8];
+  __shared__ double red8[NW][10];
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   const SolverState* sin = a.st + (1 - a.par);
   SolverState* sout = a.st + a.par;
@@ -660,6 +752,8 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
         raw[q].m = a.urec_m[rec];
         raw[q].val = 0.0;
         raw[q].atom = b * SEGCAP_G + j * GMAX;
+        raw[q].omo = a.urec_omo[rec];
+        raw[q].valo = 0.0;
       } else {
         const int b = min(sg * SG + s / SEGCAP_L, a.grid_corr - 1), k = s % SEGCAP_L;
         const int64_t rec = static_cast<int64_t>(b) * CBL + k;
@@ -670,6 +764,8 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
         raw[q].m = 0;
         raw[q].val = static_cast<double>(a.seg_val[slot]);
         raw[q].atom = a.seg_atom[slot];
+        raw[q].omo = a.urec_omo[rec];
+        raw[q].valo = static_cast<double>(a.seg_po[slot]);
       }
     }
   };
@@ -679,10 +775,12 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   constexpr int NWORDS = sizeof(SolverState) / 4;
   static_assert(NWORDS <= BLK, "state fits one word per thread");
   const int32_t sword = reinterpret_cast<const int32_t*>(sin)[min(tid, NWORDS - 1)];
-  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // zs nz kt ns at tt ty om
+  // zs nz kt ns at tt ty om; backtracking: ||d||^2 ||D d||^2
+  constexpr int NV = 10;
+  double v[NV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double* rtp = a.rtn + (1 - a.par) * (2 * MAXRT);
   const double* omp = a.omp + (1 - a.par) * MAXITEM;
-  double p0[PB], p1[PB], p2[PB], p3[PB], p4[PB];
+  double p0[PB], p1[PB], p2[PB], p3[PB], p4[PB], p8[PB];
 #pragma unroll
   for (int k = 0; k < PB; ++k) {  // block partials tid, tid + BLK, ... in that order
     const int b = min(k * BLK + tid, a.grid_corr - 1);
@@ -691,9 +789,10 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     p2[k] = a.bpi[MAXB + b];
     p3[k] = a.bpi[2 * MAXB + b];
     p4[k] = a.bpi[3 * MAXB + b];
+    p8[k] = a.bpd[b];
   }
   const int kr = min(tid, nrt - 1), ko = min(tid, nsg - 1);
-  const double q5 = rtp[2 * kr], q6 = rtp[2 * kr + 1], q7 = omp[ko];
+  const double q5 = rtp[2 * kr], q6 = rtp[2 * kr + 1], q7 = omp[ko], q9 = a.dtn[kr];
   SlotRaw raw[SPT];
   if (static_cast<int>(blockIdx.x) < nitems) load_slots(blockIdx.x, raw);
 #pragma unroll
@@ -704,10 +803,12 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     v[2] += ok ? p2[k] : 0.0;
     v[3] += ok ? p3[k] : 0.0;
     v[4] += ok ? p4[k] : 0.0;
+    v[8] += ok ? p8[k] : 0.0;
   }
   v[5] += tid < nrt ? q5 : 0.0;
   v[6] += tid < nrt ? q6 : 0.0;
   v[7] += tid < nsg ? q7 : 0.0;
+  v[9] += tid < nrt ? q9 : 0.0;
   // larger grids: the remaining partials, in the same order
   for (int b = PB * BLK + tid; b < a.grid_corr; b += BLK) {
     v[0] = fmax(v[0], a.bp0[b]);
@@ -715,8 +816,13 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     v[2] += a.bpi[MAXB + b];
     v[3] += a.bpi[2 * MAXB + b];
     v[4] += a.bpi[3 * MAXB + b];
+    v[8] += a.bpd[b];
   }
-  for (int k = BLK + tid; k < nrt; k += BLK) { v[5] += rtp[2 * k]; v[6] += rtp[2 * k + 1]; }
+  for (int k = BLK + tid; k < nrt; k += BLK) {
+    v[5] += rtp[2 * k];
+    v[6] += rtp[2 * k + 1];
+    v[9] += a.dtn[k];
+  }
   for (int k = BLK + tid; k < nsg; k += BLK) v[7] += omp[k];
   if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = sword;
   __syncthreads();
@@ -726,16 +832,18 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   }
   // ---- scalars of the previous iteration, from the published partials ----
   if (S.pending) {
-    // one-pass block reduction of the eight values (fixed order: lanes, then waves)
+    // one-pass block reduction of the values (fixed order: lanes, then waves)
+    const int nv = a.bt ? NV : 8;
     v[0] = wave_max(v[0]);
 #pragma unroll
-    for (int k = 1; k < 8; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 1; k < NV; ++k)
+      if (k < nv) v[k] = wave_sum(v[k]);
     if (lane == 0)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) red8[wave][k] = v[k];
+      for (int k = 0; k < NV; ++k) red8[wave][k] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NV; ++k) {
       double acc = red8[0][k];
 #pragma unroll
       for (int w = 1; w < NW; ++w) acc = k == 0 ? fmax(acc, red8[w][k]) : acc + red8[w][k];
@@ -748,6 +856,11 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     const double zs = v[0] + S.gamma_z * sqrt(tt) * S.kappa_z;
     const int t = S.iter + 1;
     const IterScalars o = iter_scalars(S, a.N, a.test, t, tt, ty, om, zs);
+    // backtracking: the step of this iteration is kept when ||D d||^2 <= L ||d||^2 (the
+    // descent condition F(x') <= Q_L(x', p) for the quadratic data term); the stop needs
+    // an accepted step, except at the iteration limit
+    const bool rej = a.bt && !(v[9] <= S.L * v[8]);
+    const bool stop = (!rej && S.gap_tol_abs > 0.0 && o.gap <= S.gap_tol_abs) || t >= S.max_iter;
     __syncthreads();
     if (tid == 0) {
       const int n_old = S.n_active;
@@ -771,8 +884,13 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       S.n_active_atoms = at;
       S.r_last = o.r;
       S.r_min = fmin(S.r_min, o.r);
-      if (RULE == RULE_FISTA) S.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S.l_prev * S.l_prev));
-      if (o.stop) {
+      if (RULE == RULE_FISTA && !rej) S.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S.l_prev * S.l_prev));
+      S.rejected = rej ? 1 : 0;
+      if (rej) {
+        ++S.n_reject;
+        if (!stop) S.L *= S.bt_eta;
+      }
+      if (stop) {
         S.done = 1;
       } else if (o.r_safe < S.r_scr && (!a.screen_static || t == 1)) {
         S.r_scr = o.r_safe;
@@ -790,11 +908,28 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       }
     }
     __syncthreads();
+    if (S.rejected) {
+      // undo the rejected step: x and u of the units it updated return to x_{t-1} and p
+      constexpr int SEGCAP = GROUP ? SEGCAP_G : SEGCAP_L;
+      const int nslots = a.grid_corr * SEGCAP;
+      for (int s = blockIdx.x * BLK + tid; s < nslots; s += gridDim.x * BLK) {
+        const int b = s / SEGCAP, kk = s % SEGCAP;
+        const int j = GROUP ? kk / GMAX : kk;
+        bool ok = j < a.seg_cnt[b];
+        if (GROUP && ok) ok = kk % GMAX < a.urec_m[b * CBG + j];
+        if (ok) {
+          const int atom = a.seg_atom[s];
+          a.x[atom] = a.seg_xo[s];
+          a.u[atom] = a.seg_po[s];
+        }
+      }
+    }
     if (S.done) {
       if (blockIdx.x == 0 && tid == 0) *sout = S;
       return;
     }
   }
+  const bool rej = S.rejected != 0;
   if (blockIdx.x == 0 && tid == 0) {
     SolverState o = S;
     o.n_omp = nsg;  // the Omega partials this pass publishes
@@ -809,42 +944,6 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       for (int k = tid; k < nsg; k += BLK) a.omp[a.par * MAXITEM + k] = 0.0;
     return;
   }
-  // Row segment r0 .. r0 + VR of the first nl list entries (columns, coefficients) in
-  // LDS, accumulated into acc; RPW columns per wave in flight.
-  auto stream_list = [&](int r0, int nl, double (&acc)[VR]) {
-    for (int k0 = wave * RPW; k0 < nl; k0 += NW * RPW) {
-      int idx[RPW];
-      double val[RPW];
-#pragma unroll
-      for (int p = 0; p < RPW; ++p) {
-        const bool ok = k0 + p < nl;
-        idx[p] = ok ? l_idx[k0 + p] : l_idx[k0];
-        val[p] = ok ? l_val[k0 + p] : 0.0;
-      }
-      if (VECTOR && r0 + VR <= a.N) {
-        if constexpr (VECTOR) {
-          uint4 cv[RPW];
-#pragma unroll
-          for (int p = 0; p < RPW; ++p) cv[p] = ld16(a.D + static_cast<int64_t>(idx[p]) * a.ldd + r0);
-#pragma unroll
-          for (int p = 0; p < RPW; ++p) {
-            double d[VR];
-            widen<T>(cv[p], d);
-#pragma unroll
-            for (int e = 0; e < VR; ++e) acc[e] = fma(d[e], val[p], acc[e]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int p = 0; p < RPW; ++p) {
-          const T* col = a.D + static_cast<int64_t>(idx[p]) * a.ldd;
-          for (int e = 0; e < VR; ++e)
-            if (r0 + e < a.N) acc[e] = fma(to_double(col[r0 + e]), val[p], acc[e]);
-        }
-      }
-    }
-  };
-
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int rt = item % nrt, sg = item / nrt;
     if (item != static_cast<int>(blockIdx.x)) load_slots(item, raw);
@@ -865,12 +964,13 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
         e_atom[q] = -1;
         e_val[q] = 0.0;
         if (b < a.grid_corr && j < raw[q].nk && !(raw[q].marg > r_keep)) {
-          if (raw[q].val != 0.0) {
+          const double val = rej ? raw[q].valo : raw[q].val;  // a rejected step keeps p
+          if (val != 0.0) {
             e_atom[q] = raw[q].atom;
-            e_val[q] = raw[q].val;
+            e_val[q] = val;
             ++cntv;
           }
-          om += raw[q].om;
+          om += rej ? raw[q].omo : raw[q].om;
         }
       }
       if (rt == 0) {
@@ -888,7 +988,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
         }
       }
       __syncthreads();
-      stream_list(r0, total, acc);
+      stream_list<T, V, VECTOR>(a, l_idx, l_val, r0, total, wave, acc);
     } else {
       // ---- groups: the atoms of the kept groups with a non-zero u_g, in order ----
       // Thread tid holds group record tid of the item; its m atoms occupy list positions
@@ -897,8 +997,9 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       const int b = sg * SG + tid / CBG, j = tid % CBG;
       int na = 0;
       if (b < a.grid_corr && j < raw[0].nk && !(raw[0].marg > r_keep)) {
-        om += raw[0].om;
-        if (raw[0].om > 0.0) na = raw[0].m;
+        const double omg = rej ? raw[0].omo : raw[0].om;  // a rejected step keeps p
+        om += omg;
+        if (omg > 0.0) na = raw[0].m;
       }
       if (rt == 0) {
         om = block_sum<double, NW>(om, sd);
@@ -909,36 +1010,11 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       s_goff[tid] = off;
       s_gbase[tid] = raw[0].atom;
       __syncthreads();
-      constexpr int FPT = LCAP / BLK;  // list positions filled per thread per chunk
       for (int c0 = 0; c0 < total; c0 += LCAP) {
         const int nl = min(LCAP, total - c0);
-        int slot[FPT];
-#pragma unroll
-        for (int q = 0; q < FPT; ++q) {
-          const int pp = c0 + min(tid + q * BLK, nl - 1);
-          int lo = 0, hi = BLK;  // first record whose offset exceeds pp
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_goff[mid] <= pp) lo = mid + 1; else hi = mid;
-          }
-          slot[q] = s_gbase[lo - 1] + (pp - s_goff[lo - 1]);
-        }
-        int at[FPT];
-        V vv[FPT];
-#pragma unroll
-        for (int q = 0; q < FPT; ++q) {
-          at[q] = a.seg_atom[slot[q]];
-          vv[q] = a.seg_val[slot[q]];
-        }
-#pragma unroll
-        for (int q = 0; q < FPT; ++q) {
-          if (tid + q * BLK < nl) {
-            l_idx[tid + q * BLK] = at[q];
-            l_val[tid + q * BLK] = static_cast<double>(vv[q]);
-          }
-        }
+        fill_group_list<V>(s_goff, s_gbase, c0, nl, a.seg_atom, rej ? a.seg_po : a.seg_val, l_idx, l_val);
         __syncthreads();
-        stream_list(r0, nl, acc);
+        stream_list<T, V, VECTOR>(a, l_idx, l_val, r0, nl, wave, acc);
         __syncthreads();
       }
     }
@@ -956,6 +1032,124 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     }
     if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nsg), &s_last))
       resid_finish_tile<T, V, VECTOR>(a, rt, nsg, sd);
+    __syncthreads();
+  }
+}
+
+// Backtracking check: ||D d||^2 for the step d = x' - p of the correlation pass that just
+// ran (non-zero entries of its support slots), by the residual's work items: row tile x
+// segment group, FP64 row partials published per item, and the item arriving last for a
+// row tile adds the items' partials row by row and publishes the row tile's sum of squares.
+template <typename T, typename V, bool VECTOR, bool GROUP>
+__global__ __launch_bounds__(BLK) void k_dcheck(SingleArgs<T, V, double> a) {
+  constexpr int VR = VECTOR ? Store<T>::VEC : 1;
+  constexpr int RT = WAVE * VR;
+  constexpr int SG = GROUP ? SGG : SGL;
+  constexpr int SPI = GROUP ? SGG * CBG : SGL * SEGCAP_L;
+  constexpr int SPT = SPI / BLK;
+  __shared__ double red[NW][RT];
+  __shared__ int l_idx[LCAP];
+  __shared__ double l_val[LCAP];
+  __shared__ double sd[NW];
+  __shared__ int scan[NW];
+  __shared__ int s_last;
+  __shared__ int s_goff[GROUP ? BLK : 1], s_gbase[GROUP ? BLK : 1];
+  const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+  if ((a.st + a.par)->done) return;
+  const int nrt = (a.N + RT - 1) / RT;
+  const int nsg = (a.grid_corr + SG - 1) / SG;
+  for (int item = blockIdx.x; item < nrt * nsg; item += gridDim.x) {
+    const int rt = item % nrt, sg = item / nrt;
+    const int r0 = rt * RT + lane * VR;
+    double acc[VR];
+#pragma unroll
+    for (int e = 0; e < VR; ++e) acc[e] = 0.0;
+    if constexpr (!GROUP) {
+      int nk[SPT], atom[SPT];
+      double dv[SPT];
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {  // unconditional loads at clamped indices
+        const int s = tid + q * BLK;
+        const int b = min(sg * SG + s / SEGCAP_L, a.grid_corr - 1);
+        const int64_t slot = static_cast<int64_t>(b) * SEGCAP_L + s % SEGCAP_L;
+        nk[q] = a.seg_cnt[b];
+        atom[q] = a.seg_atom[slot];
+        dv[q] = a.seg_d[slot];
+      }
+      int cnt = 0;
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int s = tid + q * BLK;
+        const bool ok = sg * SG + s / SEGCAP_L < a.grid_corr && s % SEGCAP_L < nk[q] && dv[q] != 0.0;
+        if (!ok) atom[q] = -1;
+        cnt += ok ? 1 : 0;
+      }
+      int total;
+      int off = block_exclusive_scan<NW>(cnt, scan, &total);
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        if (atom[q] >= 0) {
+          l_idx[off] = atom[q];
+          l_val[off] = dv[q];
+          ++off;
+        }
+      }
+      __syncthreads();
+      stream_list<T, V, VECTOR>(a, l_idx, l_val, r0, total, wave, acc);
+    } else {
+      const int b = sg * SG + tid / CBG, j = tid % CBG;
+      const int bc = min(b, a.grid_corr - 1);
+      const int64_t rec = static_cast<int64_t>(bc) * CBG + j;
+      const int nk = a.seg_cnt[bc], m = a.urec_m[rec];
+      const double dn = a.urec_dn[rec];
+      const int na = (b < a.grid_corr && j < nk && dn > 0.0) ? m : 0;
+      int total;
+      const int off = block_exclusive_scan<NW>(na, scan, &total);
+      s_goff[tid] = off;
+      s_gbase[tid] = bc * SEGCAP_G + j * GMAX;
+      __syncthreads();
+      for (int c0 = 0; c0 < total; c0 += LCAP) {
+        const int nl = min(LCAP, total - c0);
+        fill_group_list<double>(s_goff, s_gbase, c0, nl, a.seg_atom, a.seg_d, l_idx, l_val);
+        __syncthreads();
+        stream_list<T, V, VECTOR>(a, l_idx, l_val, r0, nl, wave, acc);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VR; ++e) red[wave][lane * VR + e] = acc[e];
+    __syncthreads();
+    for (int rr = tid; rr < RT; rr += BLK) {
+      const int r = rt * RT + rr;
+      if (r < a.N) {
+        double s = red[0][rr];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s += red[w][rr];
+        publish(&a.partial[static_cast<int64_t>(sg) * a.npad + r], s);
+      }
+    }
+    if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nsg), &s_last)) {
+      constexpr int FB = 32;
+      double q2 = 0.0;
+      const int r_end = min((rt + 1) * RT, a.N);
+      for (int r = rt * RT + tid; r < r_end; r += BLK) {
+        double s = 0.0;
+        for (int c = 0; c < nsg; c += FB) {
+          double pv[FB];
+#pragma unroll
+          for (int k2 = 0; k2 < FB; ++k2)
+            pv[k2] = consume(&a.partial[static_cast<int64_t>(min(c + k2, nsg - 1)) * a.npad + r]);
+#pragma unroll
+          for (int k2 = 0; k2 < FB; ++k2) s += c + k2 < nsg ? pv[k2] : 0.0;
+        }
+        q2 = fma(s, s, q2);
+      }
+      q2 = block_sum<double, NW>(q2, sd);
+      if (tid == 0) {
+        a.dtn[rt] = q2;     // read by the next residual pass only
+        a.rt_cnt[rt] = 0u;  // re-arm
+      }
+    }
     __syncthreads();
   }
 }
@@ -1013,7 +1207,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ int s_vb, s_nk, s_kpre;
   __shared__ int klist[CBU];
   __shared__ double kmarg[CBU];
-  __shared__ double sred[NW][4];
+  __shared__ double sred[NW][5];
   __shared__ SolverState S;
   if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
@@ -1084,6 +1278,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   if (RULE == RULE_FISTA) beta = (l_prev - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev)));
   double zsup = 0.0;  // max |z_i| (Lasso) or max ||z_g|| / w_g; rounding slack added later
   int nnz = 0, nsup = 0, natoms = 0;
+  double dd = 0.0;    // backtracking: ||x' - p||^2 over this block's units
   if constexpr (!GROUP) {
     for (int r0 = wave * CPW; r0 < nk; r0 += NW * CPW) {
       const int nc = min(CPW, nk - r0);
@@ -1114,6 +1309,14 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
         a.seg_val[slot] = us;
         a.urec_marg[slot] = kmarg[jl];
         a.urec_om[slot] = fabs(static_cast<double>(us));
+        if (a.bt) {  // keep p and x_{t-1} so that a rejected step can be undone
+          const double dv = static_cast<double>(xs) - p;  // exact: two stored values
+          a.seg_xo[slot] = static_cast<V>(xo);
+          a.seg_po[slot] = static_cast<V>(p);
+          a.seg_d[slot] = dv;
+          a.urec_omo[slot] = fabs(p);
+          dd = fma(dv, dv, dd);
+        }
         zsup = fmax(zsup, fabs(z));
         nnz += xs != V(0) ? 1 : 0;
         nsup += us != V(0) ? 1 : 0;
@@ -1150,7 +1353,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       const double nv = sqrt(v2);
       const double scale = nv > 0.0 ? fmax(0.0, (nv - thr * wg) / nv) : 0.0;
       int gnz = 0, gsup = 0;
-      double un2 = 0.0;
+      double un2 = 0.0, dn = 0.0, po2 = 0.0;
       if (lane < m) {
         const double xn = scale * vreg;
         const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
@@ -1160,6 +1363,14 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
         const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + j * GMAX + lane;
         a.seg_atom[slot] = static_cast<int32_t>(a0 + lane);
         a.seg_val[slot] = us;
+        if (a.bt) {
+          const double dv = static_cast<double>(xs) - p;
+          a.seg_xo[slot] = static_cast<V>(xo);
+          a.seg_po[slot] = static_cast<V>(p);
+          a.seg_d[slot] = dv;
+          dn = dv * dv;
+          po2 = p * p;
+        }
         gnz = xs != V(0) ? 1 : 0;
         gsup = us != V(0) ? 1 : 0;
         un2 = static_cast<double>(us) * static_cast<double>(us);
@@ -1167,11 +1378,20 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       gnz = wave_sum(gnz);
       gsup = wave_sum(gsup);
       un2 = wave_sum(un2);
+      if (a.bt) {
+        dn = wave_sum(dn);
+        po2 = wave_sum(po2);
+      }
       if (lane == 0) {
         const int64_t rec = static_cast<int64_t>(vb) * CBU + j;
         a.urec_marg[rec] = kmarg[j];
         a.urec_om[rec] = wg * sqrt(un2);
         a.urec_m[rec] = m;
+        if (a.bt) {
+          a.urec_omo[rec] = wg * sqrt(po2);
+          a.urec_dn[rec] = dn;
+          dd += dn;
+        }
         zsup = fmax(zsup, sqrt(z2) / wg);
         nnz += gnz;
         nsup += gsup;
@@ -1183,22 +1403,26 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   zsup = wave_max(zsup);
   const double cnz = wave_sum(static_cast<double>(nnz)), csup = wave_sum(static_cast<double>(nsup));
   const double cat = wave_sum(static_cast<double>(natoms));
+  const double cdd = a.bt ? wave_sum(dd) : 0.0;
   if (lane == 0) {
     sred[wave][0] = zsup;
     sred[wave][1] = cnz;
     sred[wave][2] = csup;
     sred[wave][3] = cat;
+    sred[wave][4] = cdd;
   }
   __syncthreads();
   if (tid == 0) {  // read by the next residual pass only (after this kernel ends)
-    double r0 = sred[0][0], r1 = sred[0][1], r2 = sred[0][2], r3 = sred[0][3];
+    double r0 = sred[0][0], r1 = sred[0][1], r2 = sred[0][2], r3 = sred[0][3], r4 = sred[0][4];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
       r0 = fmax(r0, sred[w][0]);
       r1 += sred[w][1];
       r2 += sred[w][2];
       r3 += sred[w][3];
+      r4 += sred[w][4];
     }
+    if (a.bt) a.bpd[vb] = r4;
     zsup = r0;
     nnz = static_cast<int>(r1);
     nsup = static_cast<int>(r2);

@@ -14,7 +14,8 @@ struct alignas(16) SolverState {
   double lam;          // absolute penalty
   double lam_ratio;    // lambda / lambda_* when the penalty is relative, else <= 0
   double lam_max;      // lambda_*
-  double L;            // step constant
+  double L;            // step constant (backtracking: the current L_t)
+  double bt_eta;       // backtracking: growth factor of L on a rejected step (0: constant step)
   double yy;           // ||y||^2
   double rho2;         // ||y/lambda - c||^2 of the sphere centre (0 for SAFE)
   double alpha;        // DST3/DGST3: c = y/lambda - alpha * n
@@ -49,6 +50,8 @@ struct alignas(16) SolverState {
   int32_t compact;     // 1: the next correlation pass rewrites the list without stale entries
   int32_t pending;     // 1: a correlation pass ran whose scalars are not computed yet
   int32_t n_omp;       // Omega(p) partials the last residual pass published
+  int32_t rejected;    // backtracking: the last step was rejected (x, u were restored)
+  int32_t n_reject;    // backtracking: rejected steps so far
 };
 
 template <typename T, typename V, typename A>
@@ -97,6 +100,16 @@ struct SingleArgs {
   int32_t tele_cap;
   uint64_t* kclk;        // NULL, or 2 wall-clock stamps per correlation block (start, end)
   int32_t screen_static; // 1: the radius is taken from the first iteration only
+  // backtracking (bt = 1): the correlation pass keeps, per support slot, the previous x
+  // and u and the step d = x' - p, so that a rejected step can be undone
+  int32_t bt;
+  V* seg_xo;             // SEGCAP slots per block: x before the step
+  V* seg_po;             // SEGCAP slots per block: p (u, or x for ISTA) before the step
+  double* seg_d;         // SEGCAP slots per block: d = x' - p (exact difference of stored values)
+  double* urec_omo;      // UCAP unit records per block: Omega term of p
+  double* urec_dn;       // UCAP unit records per block: ||d_unit||^2
+  double* bpd;           // ||d||^2 per correlation block
+  double* dtn;           // ||D d||^2 per row tile (the check pass)
 };
 
 // Per-iteration telemetry written by the last correlation block.

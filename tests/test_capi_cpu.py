@@ -60,10 +60,11 @@ def test_invalid_problem_rejected(B, field, value):
 
 @pytest.mark.parametrize("field,value", [("rule", 5), ("test", 9), ("max_iter", 0),
                                          ("gap_tol", -1.0), ("screening", 2),
-                                         ("lambda_mode", 4)])
+                                         ("lambda_mode", 4), ("step_rule", 2),
+                                         ("bt_eta", 0.5), ("bt_eta", float("inf"))])
 def test_invalid_params_rejected(B, field, value):
     p = _problem(B)
-    prm = B.make_params()
+    prm = B.make_params(step="backtracking")
     setattr(prm, field, value)
     lam = (C.c_double * 1)(0.5)
     info = (B.Info * 1)()
