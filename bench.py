@@ -46,20 +46,23 @@ def _dev(D32, y32):
     return Dd, yd
 
 
-def run_steps(binding, Dd, ys, steps, test, L, lat=None):
+def run_steps(binding, Dd, ys, steps, test, L, lat=None, step="constant", iters=None):
     import torch
     n = 0
     for s in range(steps):
         yd = ys[s % len(ys)]
         for r in RATIOS:
             t0 = time.perf_counter()
-            x, info, _, _ = binding.solve_one(Dd, yd, r, rule="fista", test=test, step_L=L,
+            x, info, _, _ = binding.solve_one(Dd, yd, r, rule="fista", test=test,
+                                              step_L=L if step == "constant" else 0.0,
                                               gap_tol=GAP_TOL, max_iter=20000, trace=False,
-                                              screened=False)
+                                              screened=False, step=step)
             if lat is not None:
                 lat.append(time.perf_counter() - t0)
             if info["status"] != 0:
                 raise RuntimeError(f"solve did not converge: {info}")
+            if iters is not None:
+                iters.append(info["iters"])
             n += 1
     torch.cuda.synchronize()
     return n
@@ -270,6 +273,26 @@ def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96
             "open_loop": opens, "per_dict_closed_loop": per_dict}
 
 
+def backtracking_leg(binding, Dd, ys, steps):
+    """The headline workload with the step rule Table 1 gives FISTA (backtracking, L_0 the
+    largest squared atom norm, eta = 2): screened and plain solves/s, iterations per solve."""
+    import torch
+    out = {"step": "backtracking", "eta": 2.0, "L0": "largest squared atom norm"}
+    for test in ("dst3", "none"):
+        run_steps(binding, Dd, ys, 1, test, 0.0, step="backtracking")   # warm-up
+        it = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = run_steps(binding, Dd, ys, steps, test, 0.0, step="backtracking", iters=it)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "screened" if test == "dst3" else "plain"
+        out[f"{key}_solves_per_s"] = round(n / dt, 3)
+        out[f"{key}_mean_iters"] = round(float(np.mean(it)), 1)
+    out["screened_over_plain"] = round(out["screened_solves_per_s"] / out["plain_solves_per_s"], 4)
+    return out
+
+
 # The largest dictionary of the serving mix: 4096 x 40000 FP32 is 655 MB, more than the
 # 256 MB last-level cache, so every correlation pass streams it from HBM.
 LARGE = (4096, 40000)
@@ -434,9 +457,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served,flops,large",
+    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking",
                     help="comma list of legs: single (headline), batched, served, flops, large "
-                         "(correlation roofline on 4096 x 40000 FP32).  Profiling "
+                         "(correlation roofline on 4096 x 40000 FP32), backtracking (the headline "
+                         "workload with backtracking steps).  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
@@ -538,6 +562,13 @@ def main():
         out["batched"] = b
     if "flops" in legs:
         out["flops_model"] = flops_leg(binding, Dd, ys, L, nsig=min(3, len(ys)))
+    if "backtracking" in legs:
+        bt = backtracking_leg(binding, Dd, ys, args.steps)
+        it_c = []
+        run_steps(binding, Dd, ys, 1, "dst3", L, iters=it_c)
+        bt["constant_step_mean_iters"] = round(float(np.mean(it_c)), 1)
+        bt["over_constant_step"] = round(bt["screened_solves_per_s"] / value, 3)
+        out["backtracking"] = bt
     if "large" in legs:
         out["roofline_large_dictionary"] = large_leg(binding)
     if "served" in legs:
