@@ -233,11 +233,11 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   double* z0 = reinterpret_cast<double*>(base + l.z0);
   double* gn = reinterpret_cast<double*>(base + l.gn);
   float* Vn = reinterpret_cast<float*>(base + l.Vn);
-  hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 16), dim3(TB), 0, s, dcm, a.Y, l.Np, l.Kp, z0);
+  hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 64), dim3(TB), 0, s, dcm, a.Y, l.Np, l.Kp, z0);
   hipLaunchKernelGGL(k_b_inst_init, dim3(l.Bp), dim3(TB), 0, s, a, z0, d_lam,
                      prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0, prm.gap_tol, Vn);
   if (prm.test == DS_TEST_DST3)
-    hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 16), dim3(TB), 0, s, dcm, Vn, l.Np, l.Kp, gn);
+    hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 64), dim3(TB), 0, s, dcm, Vn, l.Np, l.Kp, gn);
   hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a, z0, gn,
                      reinterpret_cast<float*>(base + l.marg));
   hipLaunchKernelGGL(k_b_tile_min, dim3((l.Kp / MT + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a,

@@ -154,35 +154,46 @@ __global__ __launch_bounds__(TB) void k_b_load_y(const float* __restrict__ Yin, 
 }
 
 // FP64 batched products out[b][a] = d_a^T v_b (exact bfloat16 x float products, FP64
-// accumulation).  Block: 64 atoms x 16 signals; thread: 4 atoms x 1 signal.
+// accumulation).  Block: 64 atoms x 64 signals; thread: 4 atoms x 4 signals (atoms
+// ta + 16 i, signals tb + 16 j); each output sums its products in row order.
 __global__ __launch_bounds__(TB) void k_b_dtv64(const uint16_t* __restrict__ dcm,
                                                 const float* __restrict__ V, int Np, int Kp,
                                                 double* __restrict__ out) {
   __shared__ double sd[64][33];
-  __shared__ double sv[16][33];
-  const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 16;
+  __shared__ double sv[64][33];
+  const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
   const int ta = threadIdx.x % 16, tb = threadIdx.x / 16;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (int n0 = 0; n0 < Np; n0 += 32) {
     for (int e = threadIdx.x; e < 64 * 32; e += TB) {
-      const int aa = e / 32, nn = e % 32;
-      sd[aa][nn] = bf16f(dcm[static_cast<int64_t>(a0 + aa) * Np + n0 + nn]);
-    }
-    for (int e = threadIdx.x; e < 16 * 32; e += TB) {
-      const int bb = e / 32, nn = e % 32;
-      sv[bb][nn] = V[static_cast<int64_t>(b0 + bb) * Np + n0 + nn];
+      const int r = e / 32, nn = e % 32;
+      sd[r][nn] = bf16f(dcm[static_cast<int64_t>(a0 + r) * Np + n0 + nn]);
+      sv[r][nn] = V[static_cast<int64_t>(b0 + r) * Np + n0 + nn];
     }
     __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
     for (int nn = 0; nn < 32; ++nn) {
-      const double v = sv[tb][nn];
+      double dv[4], vv[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] = fma(sd[ta + 16 * k][nn], v, acc[k]);
+      for (int i = 0; i < 4; ++i) dv[i] = sd[ta + 16 * i][nn];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vv[j] = sv[tb + 16 * j][nn];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(dv[i], vv[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) out[static_cast<int64_t>(b0 + tb) * Kp + a0 + ta + 16 * k] = acc[k];
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      out[static_cast<int64_t>(b0 + tb + 16 * j) * Kp + a0 + ta + 16 * i] = acc[i][j];
 }
 
 // Per-signal setup (one block per slot): ||y||^2, finiteness, lambda_* = max_i |z0_i|

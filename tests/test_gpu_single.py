@@ -150,6 +150,57 @@ def test_group_solve_to_tolerance_is_certified(B, ratio):
     assert np.all(amask[scr])
 
 
+# ------------------------------------------------------------ group sizes and partitions
+@pytest.mark.parametrize("sizes", [(5,), (50,), (64,), (3, 17, 64, 1, 9)])
+def test_group_sizes_fixed_iteration_parity(B, sizes):
+    """Group sizes of the paper's sweep and the largest supported (64 atoms: one lane per
+    atom), and groups of mixed sizes, with the default weights sqrt(|g|)."""
+    sz = np.resize(np.array(sizes, dtype=np.int64), 2400 // int(np.mean(sizes)))
+    gp = np.concatenate([[0], np.cumsum(sz)]).astype(np.int64)
+    K = int(gp[-1])
+    D = datagen.gaussian_dictionary(400, K, 21)
+    y, _ = datagen.group_signal(D, gp, 5)
+    w = np.sqrt(np.diff(gp).astype(np.float64))
+    for rule, test in (("fista", "dst3"), ("ista", "safe")):
+        _fixed_iter_parity(B, D, y, "f32", 0.5, rule, test, 50, 1e-5, 1e-6, group=(gp, w))
+
+
+def test_non_contiguous_partition_through_a_column_permutation(B):
+    """Any partition of the atoms is solved by permuting the columns of D so that each group
+    is contiguous; the oracle solves the partition as given."""
+    K = 1500
+    rng = np.random.default_rng(77)
+    perm = rng.permutation(K)
+    sizes = np.resize(np.array([4, 11, 7, 20]), 200)
+    sizes = sizes[np.cumsum(sizes) <= K]
+    sizes = np.append(sizes, K - sizes.sum())
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    groups = [perm[bounds[g]:bounds[g + 1]] for g in range(sizes.size)]
+    D = datagen.gaussian_dictionary(300, K, 23)
+    Di = datagen.to_storage(D, "f32")
+    rng2 = np.random.default_rng(78)
+    x0 = np.zeros(K)
+    for g in groups[::25]:
+        x0[g] = rng2.standard_normal(g.size)
+    y = Di @ x0 + 0.01 * rng2.standard_normal(300)
+    yi = datagen.to_storage(y / np.linalg.norm(y), "f32")
+    L = oracle.spectral_norm_sq(Di)
+    T = 60
+    ref = oracle.solve_group_lasso(Di, yi, groups, lam_ratio=0.5, rule="fista", test="dgst3",
+                                   L=L, max_iter=T, gap_tol=0.0)
+    order = np.concatenate(groups)                       # column order that makes groups contiguous
+    Dp = dev_matrix(D[:, order], "f32")
+    gp = bounds.astype(np.int64)
+    x, info, _, _ = B.solve_one(Dp, dev_vector(yi, "f32"), 0.5, group_ptr=gp, rule="fista",
+                                test="dst3", step_L=L, gap_tol=0.0, max_iter=T, trace=False,
+                                screened=False)
+    xp = np.zeros(K)
+    xp[order] = x.cpu().numpy().astype(np.float64)
+    assert info["iters"] == ref.iters == T
+    assert rel_err(xp, ref.x) <= 1e-5
+    assert abs(info["gap"] - ref.gap) <= 1e-6 * ref.primal_p + 1e-12
+
+
 # ------------------------------------------------------------ edge cases
 def test_trivial_regime_returns_zero(B):
     D, y = _lasso_case(200, 800, 2)
