@@ -600,7 +600,31 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   const int ntile = a.Kp / MT;
   double zm = 0.0, om = 0.0;
   int nact = 0, nsup = 0;
-  for (int t = lane; t < ntile; t += BW) {
+  // the first QT tiles of every lane (K <= 16384) in one round trip: unconditional loads
+  // at clamped indices, then the lane's sums in tile order
+  constexpr int QT = 8;
+  double qz[QT], qo[QT];
+  int qa[QT];
+#pragma unroll
+  for (int q = 0; q < QT; ++q) {
+    const int64_t o = static_cast<int64_t>(min(lane + q * BW, ntile - 1)) * a.Bp + s;
+    qz[q] = a.pz[o];
+    qo[q] = a.pom[o];
+    qa[q] = a.pact[o];
+  }
+  const int kr = min(lane, a.nrb - 1);
+  const double q_tt = a.ptt[static_cast<int64_t>(kr) * a.Bp + s];
+  const double q_ty = a.pty[static_cast<int64_t>(kr) * a.Bp + s];
+#pragma unroll
+  for (int q = 0; q < QT; ++q) {
+    if (lane + q * BW < ntile) {
+      zm = fmax(zm, qz[q]);
+      om += qo[q];
+      nact += qa[q] & 0xff;
+      nsup += qa[q] >> 8;
+    }
+  }
+  for (int t = lane + QT * BW; t < ntile; t += BW) {
     const int64_t o = static_cast<int64_t>(t) * a.Bp + s;
     zm = fmax(zm, a.pz[o]);
     om += a.pom[o];
@@ -608,8 +632,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     nact += c & 0xff;
     nsup += c >> 8;
   }
-  double tt = 0.0, ty = 0.0;
-  for (int c = lane; c < a.nrb; c += BW) {
+  double tt = lane < a.nrb ? q_tt : 0.0, ty = lane < a.nrb ? q_ty : 0.0;
+  for (int c = lane + BW; c < a.nrb; c += BW) {
     tt += a.ptt[static_cast<int64_t>(c) * a.Bp + s];
     ty += a.pty[static_cast<int64_t>(c) * a.Bp + s];
   }
@@ -771,11 +795,26 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
   Inst& st = a.inst[s];
   if (st.done != 0 || !st.verify) return;
   const int nch = (a.K + VC - 1) / VC;
+  const int64_t cb = static_cast<int64_t>(s) * nch, vb = static_cast<int64_t>(s) * a.Kp;
   double zm = 0.0;
-  for (int ch = 0; ch < nch; ++ch) {
-    const int cnt = a.ccount[static_cast<int64_t>(s) * nch + ch];
-    for (int c = lane; c < cnt; c += BW)
-      zm = fmax(zm, a.cval[static_cast<int64_t>(s) * a.Kp + ch * VC + c]);
+  // round trip 1: every chunk's candidate count (lane ch holds chunk ch); round trip 2: the
+  // first BW candidates of the first QC chunks, unconditional loads at clamped indices
+  constexpr int QC = 16;
+  const int cnt_l = a.ccount[cb + min(lane, nch - 1)];
+  double qv[QC];
+  int qc[QC];
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const int ch = min(q, nch - 1);
+    qc[q] = __builtin_amdgcn_readlane(cnt_l, ch);
+    qv[q] = a.cval[vb + ch * VC + min(lane, max(qc[q] - 1, 0))];
+  }
+#pragma unroll
+  for (int q = 0; q < QC; ++q)
+    if (q < nch && lane < qc[q]) zm = fmax(zm, qv[q]);
+  for (int ch = 0; ch < nch; ++ch) {  // the rest: candidates past BW, chunks past QC
+    const int cnt = ch < BW ? __builtin_amdgcn_readlane(cnt_l, ch) : a.ccount[cb + ch];
+    for (int c = lane + (ch < QC ? BW : 0); c < cnt; c += BW) zm = fmax(zm, a.cval[vb + ch * VC + c]);
   }
   zm = wave_max(zm);
   if (lane != 0) return;
