@@ -113,9 +113,9 @@ ds_status validate_problem(const ds_problem* p, bool group) {
     for (int64_t g = 0; g < p->G; ++g) {
       const int64_t sz = p->group_ptr[g + 1] - p->group_ptr[g];
       if (sz < 1) { set_error("group %lld is empty", static_cast<long long>(g)); return DS_EINVAL; }
-      if (sz > 64) {
-        set_error("group %lld has %lld atoms; groups of at most 64 atoms are supported",
-                  static_cast<long long>(g), static_cast<long long>(sz));
+      if (sz > DS_GROUP_MAX) {
+        set_error("group %lld has %lld atoms; groups of at most %d atoms are supported",
+                  static_cast<long long>(g), static_cast<long long>(sz), DS_GROUP_MAX);
         return DS_EINVAL;
       }
       if (p->w != nullptr && !(p->w[g] > 0.0 && std::isfinite(p->w[g]))) {

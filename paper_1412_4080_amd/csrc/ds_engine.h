@@ -10,6 +10,9 @@
 
 #include "../../include/dynscreen.h"
 
+// Largest group the Group-Lasso kernels handle (two atoms per lane of a 64-wide wave).
+constexpr int DS_GROUP_MAX = 128;
+
 namespace ds {
 
 void set_error(const char* fmt, ...);

@@ -10,6 +10,8 @@
 #include "ds_engine.h"
 #include "ds_single_kernels.h"
 
+static_assert(ds::GMAX == DS_GROUP_MAX, "group limit of the kernels and of the validation");
+
 namespace ds {
 
 namespace {
@@ -198,12 +200,22 @@ ds_status launch_setup_corr(const ds_problem& P, const void* y, char* base, cons
                      reinterpret_cast<double*>(base + l.off_nu));
   DS_HIP(hipGetLastError());
   if (P.G > 0) {
-    hipLaunchKernelGGL((k_group_norms<T>), dim3(grid_for(P.G, 1, 4096)), dim3(BLK), 0, s,
-                       static_cast<const T*>(P.D), P.ldd, static_cast<int>(P.N),
-                       static_cast<int>(P.G),
-                       reinterpret_cast<const int64_t*>(base + l.off_gptr),
-                       reinterpret_cast<double*>(base + l.off_gnorm),
-                       reinterpret_cast<double*>(base + l.off_fro));
+    int64_t mmax = 1;  // largest group (validated: at most GMAX atoms)
+    for (int64_t g = 0; g < P.G; ++g) mmax = std::max(mmax, P.group_ptr[g + 1] - P.group_ptr[g]);
+    auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(grid_for(P.G, 1, 4096)), dim3(BLK), 0, s,
+                         static_cast<const T*>(P.D), P.ldd, static_cast<int>(P.N),
+                         static_cast<int>(P.G),
+                         reinterpret_cast<const int64_t*>(base + l.off_gptr),
+                         reinterpret_cast<double*>(base + l.off_gnorm),
+                         reinterpret_cast<double*>(base + l.off_fro));
+    };
+    switch (gram_edge(static_cast<int>(mmax))) {
+      case 16: launch(k_group_norms<T, 16>); break;
+      case 32: launch(k_group_norms<T, 32>); break;
+      case 64: launch(k_group_norms<T, 64>); break;
+      default: launch(k_group_norms<T, 128>); break;
+    }
     DS_HIP(hipGetLastError());
   }
   return DS_OK;

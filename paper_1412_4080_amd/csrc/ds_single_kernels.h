@@ -29,7 +29,7 @@ constexpr int CBLK = 1024;       // threads of the single-block kernels
 constexpr int CNW = CBLK / WAVE;
 constexpr int MAXB = 16384;      // maximum grid of the kernels with block partials
 constexpr int MAXRT = 4096;      // maximum row tiles of the residual
-constexpr int GMAX = 64;         // largest group: one lane per atom in the group epilogue
+constexpr int GMAX = 128;        // largest group (two atoms per lane in the group epilogue)
 
 enum CounterSlot { CNT_FIN = 0, CNT_CORR = 1, CNT_VID = 2, CNT_SUB = 8 };
 
@@ -243,78 +243,190 @@ __global__ __launch_bounds__(BLK) void k_setup_gemv(const T* __restrict__ D, int
   }
 }
 
-// Group spectral norms ||D_g||_2 (Lemma 6) and Frobenius norms: one block per group
-// forms the Gram matrix D_g^T D_g in FP64 and diagonalises it by cyclic Jacobi.
-template <typename T>
+// Group spectral norms ||D_g||_2 (Lemma 6) and Frobenius norms, one block per group, for
+// groups of at most GM atoms:
+//  1. the Gram matrix D_g^T D_g in FP64: rows of D_g are staged through LDS in chunks of
+//     GRS rows (column-major, padded stride) and thread (ti, tj) of a 16 x 16 grid keeps
+//     the TE x TE tile of columns ti*TE.., tj*TE.. in registers (every entry sums its exact
+//     products in row order, so the matrix is exactly symmetric);
+//  2. Householder reduction to tridiagonal form in LDS (the symmetric rank-2 update of the
+//     trailing block evaluates entries (i, j) and (j, i) with the same expression, so the
+//     block stays exactly symmetric);
+//  3. the largest eigenvalue of the tridiagonal matrix by multisection on one wave: 64
+//     trial points per round split the current interval (Gershgorin bounds at the start),
+//     each lane counting the eigenvalues below its point with the Sturm recurrence; the
+//     first point with every eigenvalue below it becomes the new upper end.  The norm is
+//     the square root of the final upper end.
+constexpr int GRS = 32;  // rows of D_g per staged chunk
+
+template <int GM>
+struct GramLds {
+  static constexpr int TE = GM / 16;
+  static constexpr int NA = GM * GM > GM * (GRS + 1) ? GM * GM : GM * (GRS + 1);
+};
+
+template <typename T, int GM>
 __global__ __launch_bounds__(BLK) void k_group_norms(const T* __restrict__ D, int64_t ldd, int N,
                                                       int G, const int64_t* __restrict__ gptr,
                                                       double* __restrict__ gnorm,
                                                       double* __restrict__ fro) {
-  constexpr int GM = 64;  // largest group handled by this kernel
-  __shared__ double gram[GM * GM];
-  __shared__ double red[NW];
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  constexpr int TE = GramLds<GM>::TE;
+  static_assert(GM % 16 == 0 && BLK == 256, "16 x 16 thread grid of TE x TE tiles");
+  __shared__ double gram[GramLds<GM>::NA];  // staged rows, then the Gram matrix (row-major)
+  __shared__ double s_v[GM], s_w[GM], s_d[GM], s_e[GM], s_e2[GM];
+  __shared__ double sd[NW];
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int ti = tid / 16, tj = tid % 16;
   for (int g = blockIdx.x; g < G; g += gridDim.x) {
     const int64_t a0 = gptr[g];
     const int m = static_cast<int>(gptr[g + 1] - a0);
-    const int npairs = m * (m + 1) / 2;
-    for (int pidx = wv; pidx < npairs; pidx += NW) {
-      int a = 0, rem = pidx;
-      while (rem >= m - a) { rem -= m - a; ++a; }
-      const int b = a + rem;
-      const T* ca = D + (a0 + a) * ldd;
-      const T* cb = D + (a0 + b) * ldd;
-      double s = 0.0;
-      for (int e = lane; e < N; e += WAVE) s = fma(to_double(ca[e]), to_double(cb[e]), s);
-      s = wave_sum(s);
-      if (lane == 0) { gram[a * GM + b] = s; gram[b * GM + a] = s; }
-    }
-    __syncthreads();
-    // cyclic Jacobi sweeps on wave 0, lane k owning row k: for each rotation (p, q) the
-    // lanes update their entries of columns p and q, then of rows p and q (the same
-    // arithmetic per entry as a serial sweep; LDS accesses of one wave stay in order)
-    if (wv == 0) {
-      const double f2 = wave_sum(lane < m ? gram[lane * GM + lane] : 0.0);
-      for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0;
-        if (lane < m)
-          for (int q = lane + 1; q < m; ++q) off += gram[lane * GM + q] * gram[lane * GM + q];
-        off = wave_sum(off);
-        if (off <= 1e-30 * f2 * f2) break;
-        for (int p = 0; p < m; ++p) {
-          for (int q = p + 1; q < m; ++q) {
-            const double apq = gram[p * GM + q];
-            if (apq == 0.0) continue;
-            const double app = gram[p * GM + p], aqq = gram[q * GM + q];
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-            __builtin_amdgcn_wave_barrier();
-            if (lane < m) {
-              const double akp = gram[lane * GM + p], akq = gram[lane * GM + q];
-              gram[lane * GM + p] = c * akp - s * akq;
-              gram[lane * GM + q] = s * akp + c * akq;
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane < m) {
-              const double apk = gram[p * GM + lane], aqk = gram[q * GM + lane];
-              gram[p * GM + lane] = c * apk - s * aqk;
-              gram[q * GM + lane] = s * apk + c * aqk;
-            }
-            __builtin_amdgcn_wave_barrier();
+    // ---- 1. Gram matrix ----
+    double acc[TE][TE];
+#pragma unroll
+    for (int x = 0; x < TE; ++x)
+#pragma unroll
+      for (int y = 0; y < TE; ++y) acc[x][y] = 0.0;
+    const bool act = ti * TE < m && tj * TE < m;
+    // chunk elements of this thread: unconditional loads at clamped indices (all in flight
+    // together), the next chunk fetched while the current one is consumed
+    constexpr int PER = GM * GRS / BLK;
+    static_assert(GM * GRS % BLK == 0, "chunk elements tile the block");
+    double vals[PER];
+    auto fetch = [&](int r0) {
+      const int nr = min(GRS, N - r0);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * BLK, c = min(e / GRS, m - 1), r = min(e % GRS, nr - 1);
+        vals[q] = to_double(D[(a0 + c) * ldd + r0 + r]);
+      }
+    };
+    fetch(0);
+    for (int r0 = 0; r0 < N; r0 += GRS) {
+      const int nr = min(GRS, N - r0);
+      __syncthreads();  // the previous chunk has been consumed
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * BLK, c = e / GRS, r = e % GRS;
+        gram[c * (GRS + 1) + r] = (c < m && r < nr) ? vals[q] : 0.0;
+      }
+      __syncthreads();
+      if (r0 + GRS < N) fetch(r0 + GRS);
+      if (act) {
+        for (int r = 0; r < nr; ++r) {
+          double ca[TE], cb[TE];
+#pragma unroll
+          for (int x = 0; x < TE; ++x) {
+            ca[x] = gram[(ti * TE + x) * (GRS + 1) + r];
+            cb[x] = gram[(tj * TE + x) * (GRS + 1) + r];
           }
+#pragma unroll
+          for (int x = 0; x < TE; ++x)
+#pragma unroll
+            for (int y = 0; y < TE; ++y) acc[x][y] = fma(ca[x], cb[y], acc[x][y]);
         }
       }
-      const double lmax = wave_max(lane < m ? gram[lane * GM + lane] : 0.0);
+    }
+    __syncthreads();  // the staging area becomes the Gram matrix
+#pragma unroll
+    for (int x = 0; x < TE; ++x)
+#pragma unroll
+      for (int y = 0; y < TE; ++y) {
+        const int i = ti * TE + x, j = tj * TE + y;
+        if (i < m && j < m) gram[i * GM + j] = acc[x][y];
+      }
+    __syncthreads();
+    const double f2 = block_sum<double, NW>(tid < m ? gram[tid * GM + tid] : 0.0, sd);
+    // ---- 2. Householder tridiagonalisation: step k reflects rows / columns k+1 .. m-1 ----
+    for (int k = 0; k + 2 < m; ++k) {
+      const int n2 = m - k - 1;
+      const double xi = tid < n2 ? gram[(k + 1 + tid) * GM + k] : 0.0;
+      const double tail = block_sum<double, NW>(tid > 0 && tid < n2 ? xi * xi : 0.0, sd);
+      const double x0 = gram[(k + 1) * GM + k];
+      if (tail == 0.0) {  // already tridiagonal in this column
+        if (tid == 0) s_e[k] = x0;
+        continue;
+      }
+      const double nx = sqrt(fma(x0, x0, tail));
+      const double alpha = x0 > 0.0 ? -nx : nx;
+      const double v0 = x0 - alpha;  // |x0| + ||x||: no cancellation
+      const double beta = 2.0 / fma(v0, v0, tail);
+      if (tid < n2) s_v[tid] = tid == 0 ? v0 : xi;
+      if (tid == 0) s_e[k] = alpha;
+      __syncthreads();
+      double pi = 0.0;  // p = beta A22 v, from column tid of the symmetric trailing block
+      if (tid < n2) {
+        for (int j = 0; j < n2; ++j) pi = fma(gram[(k + 1 + j) * GM + (k + 1 + tid)], s_v[j], pi);
+        pi *= beta;
+      }
+      const double pv = block_sum<double, NW>(tid < n2 ? pi * s_v[tid] : 0.0, sd);
+      if (tid < n2) s_w[tid] = fma(-0.5 * beta * pv, s_v[tid], pi);  // w = p - (beta p.v / 2) v
+      __syncthreads();
+      for (int e = tid; e < n2 * n2; e += BLK) {  // A22 -= v w^T + w v^T
+        const int i = e / n2, j = e % n2;
+        const int lo = min(i, j), hi = max(i, j);
+        gram[(k + 1 + i) * GM + (k + 1 + j)] -= fma(s_v[lo], s_w[hi], s_w[lo] * s_v[hi]);
+      }
+      __syncthreads();
+    }
+    // ---- 3. largest eigenvalue of the tridiagonal matrix (d, e) ----
+    for (int i = tid; i < m; i += BLK) {
+      s_d[i] = gram[i * GM + i];
+      if (i + 1 < m) {
+        const double ei = i + 2 < m ? s_e[i] : gram[(i + 1) * GM + i];
+        s_e[i] = ei;
+        s_e2[i] = ei * ei;
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+      double lo = 0.0, hi = 0.0, e2max = 0.0;
+      bool first = true;
+      for (int i = lane; i < m; i += WAVE) {
+        const double r = (i > 0 ? fabs(s_e[i - 1]) : 0.0) + (i + 1 < m ? fabs(s_e[i]) : 0.0);
+        lo = first ? s_d[i] - r : fmin(lo, s_d[i] - r);
+        hi = first ? s_d[i] + r : fmax(hi, s_d[i] + r);
+        if (i + 1 < m) e2max = fmax(e2max, s_e2[i]);
+        first = false;
+      }
+      // lanes without an index take lane 0's value (m >= 1)
+      const double lo0 = __shfl(lo, 0), hi0 = __shfl(hi, 0);
+      lo = wave_min(first ? lo0 : lo);
+      hi = wave_max(first ? hi0 : hi);
+      e2max = wave_max(e2max);
+      const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
+      for (int round = 0; round < 12; ++round) {
+        const double w = hi - lo;
+        const double xq = lo + w * (static_cast<double>(lane + 1) / 65.0);
+        int cnt = 0;
+        double q = s_d[0] - xq;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0 ? 1 : 0;
+        for (int i = 1; i < m; ++i) {
+          q = (s_d[i] - xq) - s_e2[i - 1] / q;
+          if (fabs(q) < pivmin) q = -pivmin;
+          cnt += q < 0.0 ? 1 : 0;
+        }
+        const unsigned long long above = __ballot(cnt == m);
+        if (above == 0ull) {
+          lo = lo + w * (64.0 / 65.0);
+        } else {
+          const int f = __ffsll(static_cast<long long>(above)) - 1;
+          const double nlo = f > 0 ? lo + w * (static_cast<double>(f) / 65.0) : lo;
+          hi = lo + w * (static_cast<double>(f + 1) / 65.0);
+          lo = nlo;
+        }
+      }
       if (lane == 0) {
-        gnorm[g] = sqrt(lmax);
+        gnorm[g] = sqrt(hi);
         fro[g] = sqrt(f2);
       }
     }
     __syncthreads();
   }
-  (void)red;
 }
+
+// Gram edge of k_group_norms for a largest group of m atoms.
+inline int gram_edge(int m) { return m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128; }
 
 // One block: ||y||^2, lambda_*, arg-max, lambda, centre data, state initialisation.
 // Group problems: lambda_* = max_g ||z0_g|| / w_g (eq. (gstar)).
@@ -1324,14 +1436,20 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
     }
     natoms = tid == 0 ? nk : 0;
   } else {
+    constexpr int NS = GMAX / WAVE;  // atoms per lane: atom k of the group sits on lane k % 64
     for (int j = wave; j < nk; j += NW) {
       const int g = klist[j];
       const int64_t a0 = a.gptr[g];
       const int m = static_cast<int>(a.gptr[g + 1] - a0);
-      const int li = min(lane, m - 1);
-      const double p = static_cast<double>(a.u[a0 + li]);
-      const double xo = static_cast<double>(a.x[a0 + li]);
-      double vreg = 0.0, z2 = 0.0;
+      double p[NS], xo[NS], vreg[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int li = min(lane + s * WAVE, m - 1);
+        p[s] = static_cast<double>(a.u[a0 + li]);
+        xo[s] = static_cast<double>(a.x[a0 + li]);
+        vreg[s] = 0.0;
+      }
+      double z2 = 0.0;
       for (int b0 = 0; b0 < m; b0 += CPW) {
         const int nc = min(CPW, m - b0);
         const T* cols[CPW];
@@ -1344,36 +1462,45 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
           acc[c] = wave_sum(acc[c]);
           if (c < nc) {
             z2 = fma(acc[c], acc[c], z2);
-            if (b0 + c == lane) vreg = p - acc[c] * invL;  // lane k keeps atom k (m <= 64)
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+              if (b0 + c == lane + s * WAVE) vreg[s] = p[s] - acc[c] * invL;
           }
         }
       }
-      const double v2 = wave_sum(vreg * vreg);
+      double vsq = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) vsq += vreg[s] * vreg[s];
+      const double v2 = wave_sum(vsq);
       const double wg = a.w[g];
       const double nv = sqrt(v2);
       const double scale = nv > 0.0 ? fmax(0.0, (nv - thr * wg) / nv) : 0.0;
       int gnz = 0, gsup = 0;
       double un2 = 0.0, dn = 0.0, po2 = 0.0;
-      if (lane < m) {
-        const double xn = scale * vreg;
-        const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
-        const V xs = static_cast<V>(xn), us = static_cast<V>(un);
-        a.x[a0 + lane] = xs;
-        a.u[a0 + lane] = us;
-        const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + j * GMAX + lane;
-        a.seg_atom[slot] = static_cast<int32_t>(a0 + lane);
-        a.seg_val[slot] = us;
-        if (a.bt) {
-          const double dv = static_cast<double>(xs) - p;
-          a.seg_xo[slot] = static_cast<V>(xo);
-          a.seg_po[slot] = static_cast<V>(p);
-          a.seg_d[slot] = dv;
-          dn = dv * dv;
-          po2 = p * p;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int ak = lane + s * WAVE;  // atom of the group
+        if (ak < m) {
+          const double xn = scale * vreg[s];
+          const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo[s]) : xn;
+          const V xs = static_cast<V>(xn), us = static_cast<V>(un);
+          a.x[a0 + ak] = xs;
+          a.u[a0 + ak] = us;
+          const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + j * GMAX + ak;
+          a.seg_atom[slot] = static_cast<int32_t>(a0 + ak);
+          a.seg_val[slot] = us;
+          if (a.bt) {
+            const double dv = static_cast<double>(xs) - p[s];
+            a.seg_xo[slot] = static_cast<V>(xo[s]);
+            a.seg_po[slot] = static_cast<V>(p[s]);
+            a.seg_d[slot] = dv;
+            dn = fma(dv, dv, dn);
+            po2 = fma(p[s], p[s], po2);
+          }
+          gnz += xs != V(0) ? 1 : 0;
+          gsup += us != V(0) ? 1 : 0;
+          un2 = fma(static_cast<double>(us), static_cast<double>(us), un2);
         }
-        gnz = xs != V(0) ? 1 : 0;
-        gsup = us != V(0) ? 1 : 0;
-        un2 = static_cast<double>(us) * static_cast<double>(us);
       }
       gnz = wave_sum(gnz);
       gsup = wave_sum(gsup);

@@ -89,10 +89,11 @@ def test_invalid_lambda_and_groups_rejected(B):
         pg = _problem(B, G=gp.size - 1, group_ptr=gp.ctypes.data_as(C.POINTER(C.c_int64)))
         assert B._lib.glasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
                                    C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
-    big = np.array([0, 100], np.int64)
-    pg = _problem(B, K=100, G=1, group_ptr=big.ctypes.data_as(C.POINTER(C.c_int64)))
+    big = np.array([0, 129], np.int64)  # groups hold at most 128 atoms
+    pg = _problem(B, K=129, G=1, group_ptr=big.ctypes.data_as(C.POINTER(C.c_int64)))
     assert B._lib.glasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
-                               C.c_void_p(0x3000), 100, info, None) == B.DS_EINVAL
+                               C.c_void_p(0x3000), 129, info, None) == B.DS_EINVAL
+    assert "at most 128" in B.last_error()
     # Lasso entry point refuses a grouped problem
     gp = np.array([0, 10, 20], np.int64)
     pg = _problem(B, G=2, group_ptr=gp.ctypes.data_as(C.POINTER(C.c_int64)))

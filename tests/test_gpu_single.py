@@ -151,10 +151,11 @@ def test_group_solve_to_tolerance_is_certified(B, ratio):
 
 
 # ------------------------------------------------------------ group sizes and partitions
-@pytest.mark.parametrize("sizes", [(5,), (50,), (64,), (3, 17, 64, 1, 9)])
+@pytest.mark.parametrize("sizes", [(5,), (50,), (64,), (100,), (128,), (3, 17, 64, 1, 9),
+                                   (1, 128, 37, 100, 65, 2)])
 def test_group_sizes_fixed_iteration_parity(B, sizes):
-    """Group sizes of the paper's sweep and the largest supported (64 atoms: one lane per
-    atom), and groups of mixed sizes, with the default weights sqrt(|g|)."""
+    """Group sizes of the paper's sweep (5, 10, 50, 100), the largest supported (128 atoms:
+    two per lane), and groups of mixed sizes, with the default weights sqrt(|g|)."""
     sz = np.resize(np.array(sizes, dtype=np.int64), 2400 // int(np.mean(sizes)))
     gp = np.concatenate([[0], np.cumsum(sz)]).astype(np.int64)
     K = int(gp[-1])
@@ -163,6 +164,35 @@ def test_group_sizes_fixed_iteration_parity(B, sizes):
     w = np.sqrt(np.diff(gp).astype(np.float64))
     for rule, test in (("fista", "dst3"), ("ista", "safe")):
         _fixed_iter_parity(B, D, y, "f32", 0.5, rule, test, 50, 1e-5, 1e-6, group=(gp, w))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("sizes", [(5,), (3, 16, 9), (20, 32), (50, 7), (100,), (128, 1, 65)])
+def test_group_spectral_norms_give_the_backtracking_start(B, dtype, sizes):
+    """The backtracking rule starts from L_0 = max_g ||D_g||_2^2 and, stopped at the first
+    iteration, returns it unchanged: the largest group spectral norm (Gram matrix,
+    tridiagonal reduction, multisection) against the singular value decomposition.  One
+    group is scaled up so that the maximum falls on a different group each time, and one
+    repeats a column (a rank-deficient Gram matrix)."""
+    sz = np.resize(np.array(sizes, dtype=np.int64), max(8, 1200 // int(np.mean(sizes))))
+    gp = np.concatenate([[0], np.cumsum(sz)]).astype(np.int64)
+    K, G = int(gp[-1]), sz.size
+    D = datagen.gaussian_dictionary(300, K, 31)
+    rng = np.random.default_rng(int(sum(sizes)))
+    big = int(rng.integers(G))
+    D[:, gp[big]:gp[big + 1]] *= 1.5
+    rd = (big + 1) % G
+    if sz[rd] > 1:
+        D[:, gp[rd] + 1] = D[:, gp[rd]]
+        D[:, gp[rd]:gp[rd + 1]] *= 1.7
+    y, _ = datagen.group_signal(D, gp, 6)
+    Di, yi = instance(D, y, dtype)
+    ref = oracle.group_spectral_norms(Di, [np.arange(gp[g], gp[g + 1]) for g in range(G)])
+    _, info, _, _ = B.solve_one(dev_matrix(D, dtype), dev_vector(yi, dtype), 0.5, group_ptr=gp,
+                                rule="fista", test="dst3", gap_tol=0.0, max_iter=1,
+                                step="backtracking", trace=False, screened=False)
+    assert info["iters"] == 1
+    assert info["L"] == pytest.approx(float(np.max(ref)) ** 2, rel=1e-12)
 
 
 def test_non_contiguous_partition_through_a_column_permutation(B):
