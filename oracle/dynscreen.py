@@ -23,6 +23,25 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   L), the FISTA sequence l_t does not advance, and the next pass evaluates theta at
   p restricted to the atoms that remain.  The solve stops only at an accepted step,
   so the returned x_t again has an objective no larger than the certified p.
+* SpaRSA (rule="sparsa"): Table 1 gives it as ISTA whose L_t follows the
+  Barzilai-Borwein rule of Wright, Nowak and Figueiredo, without its constants.
+  Here, at iteration t with primal point p = x_{t-1} and proximal point x', the
+  step d = x' - p is accepted when phi(x') <= max of the memory - (sigma / 2) L
+  ||d||^2 (phi = P, the primal objective; sigma = bb_sigma, default 1e-5).  The
+  memory holds phi at the current primal point and at the M = bb_memory iterates
+  before it (default M = 0: monotone); its newest entry is refreshed when screening
+  after a rejected step changed p.  phi(x') - phi(p) is formed as
+  theta^T D d + ||D d||^2 / 2 + lambda (Omega(x') - Omega(p)), with the Omega
+  difference summed term by term (|x'_i| - |p_i|, or for a group
+  w_g d_g^T (x'_g + p_g) / (||x'_g|| + ||p_g||), the same difference of norms):
+  that is the objective difference exactly, and its rounding error scales with d
+  instead of with the objective, so the test keeps its meaning until the iterates
+  stop moving (it is 0 for d = 0).  A rejected step is handled
+  as in backtracking (L multiplied by eta, same p, the pass still screens and
+  counts).  After an accepted step L becomes the Barzilai-Borwein value
+  ||D_t d||^2 / ||d||^2 (kept when d = 0), clamped to [1e-30, 1e30]; the stopping
+  iteration changes L in neither case.  d is the unscreened step (atoms removed by
+  this iteration's test are cleared afterwards).  L_0 defaults as for backtracking.
 * Initialisation X_0: x_0 = u_0 = 0 and l_0 = 1.
 * Dual scaling uses the correlations z_t = D_{t-1}^T theta_t of the current,
   already reduced dictionary, as the turnkey instance (Algorithm 5) does.
@@ -243,9 +262,18 @@ def _trivial(K, lam, lam_max, L, G=None):
         screened_groups=None if G is None else np.ones(G, dtype=bool), L=L)
 
 
+def _bb_step(Dd, d, L):
+    """Barzilai-Borwein step of SpaRSA after an accepted step d: ||D d||^2 / ||d||^2 (the
+    Rayleigh quotient of D^T D along d), clamped to [1e-30, 1e30]; L is kept when d = 0."""
+    dd = float(d @ d)
+    if not dd > 0.0:
+        return L
+    return float(min(max(float(Dd @ Dd) / dd, 1e-30), 1e30))
+
+
 def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
                 max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic",
-                step="constant", eta=2.0) -> OracleResult:
+                step="constant", eta=2.0, bb_memory=0, bb_sigma=1e-5) -> OracleResult:
     """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
@@ -258,17 +286,21 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     from x_0 = 0 makes it the static test of Algorithms 1 and 4 (static SAFE, ST3); the
     first update does not depend on the atoms that test removes (their prox output is 0).
     step="backtracking" sets L_t by the backtracking rule (module docstring); L is then L_0.
+    rule="sparsa" is ISTA with the Barzilai-Borwein step and its acceptance test (module
+    docstring; bb_memory, bb_sigma, eta); L is then L_0.
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     N, K = D.shape
-    assert test in ("none", "safe", "dst3") and rule in ("ista", "fista")
+    assert test in ("none", "safe", "dst3") and rule in ("ista", "fista", "sparsa")
     assert step in ("constant", "backtracking") and eta > 1.0
+    assert rule != "sparsa" or (step == "constant" and bb_memory >= 0 and bb_sigma >= 0.0)
     lam_max, i_star = lambda_max_lasso(D, y)
     if lam is None:
         lam = float(lam_ratio) * lam_max
     if L is None:
-        L = spectral_norm_sq(D) if step == "constant" else float(np.max(np.sum(D * D, axis=0)))
+        L = spectral_norm_sq(D) if step == "constant" and rule != "sparsa" \
+            else float(np.max(np.sum(D * D, axis=0)))
     if lam >= lam_max:
         return _trivial(K, lam, lam_max, L)
 
@@ -284,6 +316,7 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     l_prev = 1.0                                # l_0
     r_min = np.inf
     hist = []
+    phis, new_point = [], True                  # SpaRSA: phi at the last M + 1 iterates
     converged = False
     for t in range(1, max_iter + 1):
         # ---- optimisation update (Table 1) ----
@@ -291,11 +324,23 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         theta = Dt @ p - y
         z = Dt.T @ theta
         x_new = soft_threshold(p - z / L, lam / L)
+        primal_p = 0.5 * float(theta @ theta) + lam * float(np.abs(p).sum())
         accepted = True
         if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
             d = x_new - p
             Dd = Dt @ d
             accepted = float(Dd @ Dd) <= L * float(d @ d)
+        elif rule == "sparsa":      # sufficient decrease against the memory
+            if new_point:
+                phis = (phis + [primal_p])[-(bb_memory + 1):]
+            else:
+                phis[-1] = primal_p
+            d = x_new - p
+            Dd = Dt @ d
+            dphi = float(theta @ Dd) + 0.5 * float(Dd @ Dd) \
+                + lam * float(np.sum(np.abs(x_new) - np.abs(p)))
+            phi_new = primal_p + dphi
+            accepted = dphi + (primal_p - max(phis)) <= -0.5 * bb_sigma * L * float(d @ d)
         if rule == "fista":
             l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
             u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
@@ -308,7 +353,6 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         mu = dual_scaling(theta, y, lam, s_bound)
         v = mu * theta
         # ---- duality-gap certificate of p ----
-        primal_p = 0.5 * float(theta @ theta) + lam * float(np.abs(p).sum())
         dual = dual_objective(v, y, lam)
         gap = primal_p - dual
         dv = y / lam - v
@@ -318,14 +362,19 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
             hist.append(dict(t=t, n_active=int(active.size), nnz=int(np.count_nonzero(x_new)),
                              nnz_p=int(np.count_nonzero(p)), r=r, gap=gap, mu=mu, L=L,
                              accepted=accepted, primal_p=primal_p))
-            if step == "backtracking":   # the candidate and its primal point, active coordinates
+            if step == "backtracking" or rule == "sparsa":  # candidate, primal point, active set
                 hist[-1].update(cand=x_new.copy(), p=p.copy(), active=active.copy())
+            if rule == "sparsa":
+                hist[-1].update(phi_new=phi_new, phi_ref=max(phis))
         converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
         if not accepted:
             # rejected step: keep p, grow L; at the iteration limit return the last accepted x
             x_new, u_new, l_new = x, u, l_prev
             if t < max_iter:
                 L *= eta
+        elif rule == "sparsa" and not converged and t < max_iter:
+            L = _bb_step(Dd, d, L)
+        new_point = accepted
         if converged or t == max_iter:
             break
         # ---- screening: I_t = {i : T_v(i)} U I_{t-1}, then reduce D and X ----
@@ -358,14 +407,15 @@ def _as_groups(K, groups):
 def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="ista",
                       test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
                       record=False, screening="dynamic", step="constant",
-                      eta=2.0) -> OracleResult:
+                      eta=2.0, bb_memory=0, bb_sigma=1e-5) -> OracleResult:
     """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
 
     groups: a partition of range(K) (list of index arrays, or contiguous CSR
     offsets); w: group weights, default sqrt(|g|).  Tests: GSAFE (Lemma 4),
     DGST3 (Lemma 5) or none; the screening unit is the group.  screening="static"
     runs the test once, at the first iteration (the static group tests).  step as in
-    solve_lasso (the default L_0 for backtracking is max_g ||D_g||_2^2).
+    solve_lasso (the default L_0 for backtracking and SpaRSA is max_g ||D_g||_2^2);
+    rule="sparsa" as in solve_lasso, with phi the Group-Lasso objective.
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -373,15 +423,17 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     groups = _as_groups(K, groups)
     G = len(groups)
     w = np.sqrt([len(g) for g in groups]).astype(np.float64) if w is None else np.asarray(w, np.float64)
-    assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista")
+    assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista", "sparsa")
     assert screening in ("dynamic", "static")
     assert step in ("constant", "backtracking") and eta > 1.0
+    assert rule != "sparsa" or (step == "constant" and bb_memory >= 0 and bb_sigma >= 0.0)
     lam_max, g_star = lambda_max_group(D, y, groups, w)
     if lam is None:
         lam = float(lam_ratio) * lam_max
     gnorm = group_spectral_norms(D, groups)
     if L is None:
-        L = spectral_norm_sq(D) if step == "constant" else float(np.max(gnorm) ** 2)
+        L = spectral_norm_sq(D) if step == "constant" and rule != "sparsa" \
+            else float(np.max(gnorm) ** 2)
     if lam >= lam_max:
         return _trivial(K, lam, lam_max, L, G)
 
@@ -407,6 +459,7 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     l_prev = 1.0
     r_min = np.inf
     hist = []
+    phis, new_point = [], True
     converged = False
     for t in range(1, max_iter + 1):
         wa = w[act_g]
@@ -414,11 +467,28 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         theta = Dt @ p - y
         z = Dt.T @ theta
         x_new = group_soft_threshold(p - z / L, lam / L, local, wa)
+        omega_p = float(sum(wa[j] * np.linalg.norm(p[lg]) for j, lg in enumerate(local)))
+        primal_p = 0.5 * float(theta @ theta) + lam * omega_p
         accepted = True
         if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
             d = x_new - p
             Dd = Dt @ d
             accepted = float(Dd @ Dd) <= L * float(d @ d)
+        elif rule == "sparsa":
+            if new_point:
+                phis = (phis + [primal_p])[-(bb_memory + 1):]
+            else:
+                phis[-1] = primal_p
+            d = x_new - p
+            Dd = Dt @ d
+            domega = 0.0            # Omega(x') - Omega(p), group by group
+            for j, lg in enumerate(local):
+                den = np.linalg.norm(x_new[lg]) + np.linalg.norm(p[lg])
+                if den > 0.0:       # ||a|| - ||b|| = (a - b)^T (a + b) / (||a|| + ||b||)
+                    domega += wa[j] * float(d[lg] @ (x_new[lg] + p[lg])) / den
+            dphi = float(theta @ Dd) + 0.5 * float(Dd @ Dd) + lam * domega
+            phi_new = primal_p + dphi
+            accepted = dphi + (primal_p - max(phis)) <= -0.5 * bb_sigma * L * float(d @ d)
         if rule == "fista":
             l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
             u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
@@ -430,8 +500,6 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         s_bound = float(np.min(wa[pos] / zg[pos])) if pos.any() else np.inf
         mu = dual_scaling(theta, y, lam, s_bound)
         v = mu * theta
-        omega_p = float(sum(wa[j] * np.linalg.norm(p[lg]) for j, lg in enumerate(local)))
-        primal_p = 0.5 * float(theta @ theta) + lam * omega_p
         dual = dual_objective(v, y, lam)
         gap = primal_p - dual
         dv = y / lam - v
@@ -441,11 +509,16 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
             hist.append(dict(t=t, n_active=int(cols.size), n_active_groups=int(act_g.size),
                              nnz=int(np.count_nonzero(x_new)), nnz_p=int(np.count_nonzero(p)),
                              r=r, gap=gap, mu=mu, L=L, accepted=accepted, primal_p=primal_p))
+            if rule == "sparsa":
+                hist[-1].update(phi_new=phi_new, phi_ref=max(phis))
         converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
         if not accepted:
             x_new, u_new, l_new = x, u, l_prev
             if t < max_iter:
                 L *= eta
+        elif rule == "sparsa" and not converged and t < max_iter:
+            L = _bb_step(Dd, d, L)
+        new_point = accepted
         if converged or t == max_iter:
             break
         if screening == "dynamic" or t == 1:

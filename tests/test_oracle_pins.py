@@ -553,6 +553,116 @@ def test_backtracking_reaches_the_same_optimum(rule, group):
     assert b.primal - b.dual <= b.gap + 1e-15
 
 
+# -------------------------------------------------------------------------- SpaRSA
+@pytest.mark.parametrize("group", [False, True])
+def test_sparsa_on_a_scaled_orthonormal_dictionary_reaches_the_closed_form(group):
+    """D = c Q with orthonormal columns: D^T D = c^2 I, so every Barzilai-Borwein value is
+    exactly c^2, and one proximal step with L = c^2 from any point lands on the minimiser,
+    soft-thresholding (or group shrinkage) of Q^T y / c at lambda / c^2 (lambda w_g / c^2).
+    From L_0 = 0.05 c^2 the first steps are rejected."""
+    N, K, c = 90, 60, 1.7
+    rng = np.random.default_rng(91)
+    Q, _ = np.linalg.qr(rng.standard_normal((N, K)))
+    D = c * Q
+    y = rng.standard_normal(N)
+    b = Q.T @ y / c
+    if group:
+        gp = datagen.contiguous_groups(K, 6)
+        w = np.sqrt(np.diff(gp).astype(float))
+        r = oracle.solve_group_lasso(D, y, gp, w, lam_ratio=0.4, rule="sparsa", test="none",
+                                     L=0.05 * c * c, max_iter=200, gap_tol=1e-14, record=True)
+        xs = np.zeros(K)
+        for g in range(gp.size - 1):
+            v = b[gp[g]:gp[g + 1]]
+            nv = np.linalg.norm(v)
+            t = r.lam * w[g] / (c * c)
+            xs[gp[g]:gp[g + 1]] = v * max(0.0, 1.0 - t / nv) if nv > 0 else 0.0
+    else:
+        r = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="sparsa", test="none", L=0.05 * c * c,
+                               max_iter=200, gap_tol=1e-14, record=True)
+        t = r.lam / (c * c)
+        xs = np.sign(b) * np.maximum(np.abs(b) - t, 0.0)
+    acc = [h["accepted"] for h in r.history]
+    first = acc.index(True)
+    assert first >= 1                                    # L_0 = 0.05 c^2 was rejected
+    assert r.history[first + 1]["L"] == pytest.approx(c * c, rel=1e-12)
+    # the step after that lands on the minimiser; at most a few more passes follow, where
+    # d is at the rounding level of x (the acceptance test then sees only rounding)
+    assert r.converged and r.iters <= first + 6
+    assert np.max(np.abs(r.x - xs)) <= 1e-12 * np.max(np.abs(xs))
+
+
+def test_sparsa_step_is_a_rayleigh_quotient():
+    """After an accepted step, L = ||D d||^2 / ||d||^2 lies between the extreme eigenvalues
+    of D^T D (a tall D of full column rank; no screening)."""
+    rng = np.random.default_rng(92)
+    D = rng.standard_normal((120, 60)) * np.linspace(0.3, 2.0, 60)
+    y = rng.standard_normal(120)
+    ev = np.linalg.eigvalsh(D.T @ D)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.1, rule="sparsa", test="none", max_iter=3000,
+                           gap_tol=1e-12, record=True, bb_memory=3)
+    n = 0
+    for h, h_next in zip(r.history[:-1], r.history[1:]):
+        if h["accepted"]:
+            assert ev[0] * (1 - 1e-12) <= h_next["L"] <= ev[-1] * (1 + 1e-12)
+            n += 1
+    assert n >= 10 and r.converged
+
+
+@pytest.mark.parametrize("group", [False, True])
+def test_sparsa_monotone_variant_never_increases_the_objective(group):
+    """Memory 0: every accepted step lowers the objective, so without screening the primal
+    point of each iteration (the previous iterate) has a non-increasing objective."""
+    D, y = _problem(N=60, K=200, seed=93)
+    kw = dict(lam_ratio=0.3, rule="sparsa", max_iter=400, gap_tol=0.0, record=True, L=0.02,
+              test="none", bb_sigma=0.1)
+    if group:
+        r = oracle.solve_group_lasso(D, y, datagen.contiguous_groups(200, 10), **kw)
+    else:
+        r = oracle.solve_lasso(D, y, **kw)
+    pp = np.array([h["primal_p"] for h in r.history])
+    assert np.all(np.diff(pp) <= 1e-13 * pp[0])
+    assert not all(h["accepted"] for h in r.history)
+
+
+def test_sparsa_nonmonotone_window_maximum_never_increases():
+    """Memory M: each accepted objective is below the largest of the last M + 1, hence the
+    maximum over every window of M + 1 consecutive iterates is non-increasing."""
+    D, y = _problem(N=60, K=200, seed=94)
+    M = 4
+    r = oracle.solve_lasso(D, y, lam_ratio=0.25, rule="sparsa", test="none", max_iter=600,
+                           gap_tol=0.0, record=True, bb_memory=M, L=0.05)
+    pts = [h["primal_p"] for h, prev in zip(r.history, [None] + r.history[:-1])
+           if prev is None or prev["accepted"]]          # objective at each new iterate
+    wmax = [max(pts[j - M:j + 1]) for j in range(M, len(pts))]
+    assert np.all(np.diff(wmax) <= 1e-13 * wmax[0])
+    assert len(pts) > 3 * M and not all(h["accepted"] for h in r.history)
+    # the memory is used: some accepted step raises the objective, which memory 0 forbids
+    assert np.max(np.diff(pts)) > 1e-6 * pts[0]
+
+
+@pytest.mark.parametrize("memory", [0, 5])
+@pytest.mark.parametrize("group", [False, True])
+def test_sparsa_reaches_the_same_optimum(memory, group):
+    D, y = _problem(N=70, K=240, seed=95)
+    tol = 1e-11
+    if group:
+        gp = datagen.contiguous_groups(240, 10)
+        a = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.35, rule="fista", test="dgst3",
+                                     max_iter=100000, gap_tol=tol)
+        b = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.35, rule="sparsa", test="dgst3",
+                                     max_iter=100000, gap_tol=tol, bb_memory=memory)
+    else:
+        a = oracle.solve_lasso(D, y, lam_ratio=0.35, rule="fista", test="dst3", max_iter=100000,
+                               gap_tol=tol)
+        b = oracle.solve_lasso(D, y, lam_ratio=0.35, rule="sparsa", test="dst3",
+                               max_iter=100000, gap_tol=tol, bb_memory=memory)
+    yy = float(y @ y)
+    assert a.converged and b.converged
+    assert abs(a.primal - b.primal) <= 2 * tol * yy
+    assert b.iters < a.iters
+
+
 def test_small_fp64_configuration_matches_stored_values():
     g, gx = _golden()
     c = datagen.lasso_small_fp64()
