@@ -46,17 +46,19 @@ def _dev(D32, y32):
     return Dd, yd
 
 
-def run_steps(binding, Dd, ys, steps, test, L, lat=None, step="constant", iters=None):
+def run_steps(binding, Dd, ys, steps, test, L, lat=None, step="constant", iters=None,
+              rule="fista", bb_memory=0):
     import torch
     n = 0
     for s in range(steps):
         yd = ys[s % len(ys)]
         for r in RATIOS:
             t0 = time.perf_counter()
-            x, info, _, _ = binding.solve_one(Dd, yd, r, rule="fista", test=test,
-                                              step_L=L if step == "constant" else 0.0,
+            own_step = step != "constant" or rule == "sparsa"
+            x, info, _, _ = binding.solve_one(Dd, yd, r, rule=rule, test=test,
+                                              step_L=0.0 if own_step else L,
                                               gap_tol=GAP_TOL, max_iter=20000, trace=False,
-                                              screened=False, step=step)
+                                              screened=False, step=step, bb_memory=bb_memory)
             if lat is not None:
                 lat.append(time.perf_counter() - t0)
             if info["status"] != 0:
@@ -293,6 +295,28 @@ def backtracking_leg(binding, Dd, ys, steps):
     return out
 
 
+def sparsa_leg(binding, Dd, ys, steps):
+    """The headline workload with SpaRSA (Table 1: ISTA with the Barzilai-Borwein step;
+    L_0 the largest squared atom norm, eta = 2, sigma = 1e-5), monotone (memory 0) and
+    with a memory of 5 iterates: screened and plain solves/s, iterations per solve."""
+    import torch
+    out = {"rule": "sparsa", "eta": 2.0, "sigma": 1e-5, "L0": "largest squared atom norm"}
+    for mem in (0, 5):
+        for test in ("dst3", "none"):
+            run_steps(binding, Dd, ys, 1, test, 0.0, rule="sparsa", bb_memory=mem)  # warm-up
+            it = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = run_steps(binding, Dd, ys, steps, test, 0.0, iters=it, rule="sparsa",
+                          bb_memory=mem)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            key = f"memory{mem}_" + ("screened" if test == "dst3" else "plain")
+            out[f"{key}_solves_per_s"] = round(n / dt, 3)
+            out[f"{key}_mean_iters"] = round(float(np.mean(it)), 1)
+    return out
+
+
 # The largest dictionary of the serving mix: 4096 x 40000 FP32 is 655 MB, more than the
 # 256 MB last-level cache, so every correlation pass streams it from HBM.
 LARGE = (4096, 40000)
@@ -457,10 +481,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking",
+    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking,sparsa",
                     help="comma list of legs: single (headline), batched, served, flops, large "
                          "(correlation roofline on 4096 x 40000 FP32), backtracking (the headline "
-                         "workload with backtracking steps).  Profiling "
+                         "workload with backtracking steps), sparsa (the headline workload with "
+                         "SpaRSA's Barzilai-Borwein steps).  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
@@ -569,6 +594,10 @@ def main():
         bt["constant_step_mean_iters"] = round(float(np.mean(it_c)), 1)
         bt["over_constant_step"] = round(bt["screened_solves_per_s"] / value, 3)
         out["backtracking"] = bt
+    if "sparsa" in legs:
+        sp = sparsa_leg(binding, Dd, ys, args.steps)
+        sp["over_constant_step_fista"] = round(sp["memory0_screened_solves_per_s"] / value, 3)
+        out["sparsa"] = sp
     if "large" in legs:
         out["roofline_large_dictionary"] = large_leg(binding)
     if "served" in legs:

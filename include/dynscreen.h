@@ -49,8 +49,16 @@ typedef enum {
 
 typedef enum { DS_F64 = 0, DS_F32 = 1, DS_BF16 = 2 } ds_dtype;
 
-/* First-order update p(.) of Table 1, with a constant step 1/L. */
-typedef enum { DS_ISTA = 0, DS_FISTA = 1 } ds_rule;
+/* First-order update of Table 1.  DS_SPARSA is ISTA whose L_t follows the Barzilai-Borwein
+ * rule (the SpaRSA row of Table 1): after an accepted step d = x' - p, L becomes
+ * ||D d||^2 / ||d||^2 (clamped to [1e-30, 1e30]; kept when d = 0), and a step is accepted
+ * when phi(x') <= max(memory) - (bb_sigma / 2) L ||d||^2, phi the primal objective and the
+ * memory its values at the current primal point and the bb_memory iterates before it;
+ * phi(x') - phi(p) is formed as theta^T D d + ||D d||^2 / 2 + lambda (Omega(x') - Omega(p))
+ * with the Omega difference taken unit by unit.  A rejected step is undone and L multiplied
+ * by bt_eta, as for DS_STEP_BACKTRACK.  Single-signal and served solves; step_rule must be
+ * DS_STEP_CONSTANT, and the batched bfloat16 path returns DS_EINVAL. */
+typedef enum { DS_ISTA = 0, DS_FISTA = 1, DS_SPARSA = 2 } ds_rule;
 
 /* Screening test.  For Group-Lasso problems SAFE means GSAFE (Lemma 4) and DST3 means
  * DGST3 (Lemma 5).  DS_TEST_NONE runs the plain, unscreened algorithm. */
@@ -83,8 +91,8 @@ typedef struct {
   ds_lambda_mode lambda_mode;
   double step_L;     /* DS_STEP_CONSTANT: > 0: constant step 1/step_L, must be >= ||D||_2^2;
                         <= 0: the library estimates ||D||_2^2 (ds_spectral_norm_sq).
-                        DS_STEP_BACKTRACK: > 0: L_0; <= 0: L_0 = the largest squared atom
-                        norm (Lasso) or ||D_g||_2^2 (Group-Lasso). */
+                        DS_STEP_BACKTRACK and DS_SPARSA: > 0: L_0; <= 0: L_0 = the largest
+                        squared atom norm (Lasso) or ||D_g||_2^2 (Group-Lasso). */
   double gap_tol;    /* > 0: stop once the duality-gap certificate <= gap_tol * ||y||^2.
                         0: run exactly max_iter iterations. */
   int32_t max_iter;  /* >= 1 */
@@ -98,7 +106,10 @@ typedef struct {
                         repeated from the same p with L multiplied by bt_eta (the rejected pass
                         still counts as an iteration and still screens).  Single-signal and
                         served solves; the batched bfloat16 path returns DS_EINVAL. */
-  double bt_eta;     /* backtracking growth factor, > 1; 0 selects 2 */
+  double bt_eta;     /* backtracking and SpaRSA growth factor of L, > 1; 0 selects 2 */
+  int32_t bb_memory; /* DS_SPARSA: earlier iterates in the acceptance memory, 0..15
+                        (0: monotone) */
+  double bb_sigma;   /* DS_SPARSA: sufficient-decrease constant, >= 0; 0 selects 1e-5 */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which

@@ -132,7 +132,10 @@ ds_status validate_problem(const ds_problem* p, bool group) {
 
 ds_status validate_params(const ds_params* p) {
   if (p == nullptr) { set_error("params is NULL"); return DS_EINVAL; }
-  if (p->rule != DS_ISTA && p->rule != DS_FISTA) { set_error("unknown rule"); return DS_EINVAL; }
+  if (p->rule != DS_ISTA && p->rule != DS_FISTA && p->rule != DS_SPARSA) {
+    set_error("unknown rule");
+    return DS_EINVAL;
+  }
   if (p->test != DS_TEST_NONE && p->test != DS_TEST_SAFE && p->test != DS_TEST_DST3) {
     set_error("unknown test");
     return DS_EINVAL;
@@ -149,9 +152,24 @@ ds_status validate_params(const ds_params* p) {
     set_error("step_rule must be DS_STEP_CONSTANT or DS_STEP_BACKTRACK");
     return DS_EINVAL;
   }
-  if (p->step_rule == DS_STEP_BACKTRACK && p->bt_eta != 0.0 && !(p->bt_eta > 1.0 && std::isfinite(p->bt_eta))) {
+  if (p->rule == DS_SPARSA && p->step_rule != DS_STEP_CONSTANT) {
+    set_error("DS_SPARSA sets its own step: step_rule must be DS_STEP_CONSTANT");
+    return DS_EINVAL;
+  }
+  const bool line_search = p->step_rule == DS_STEP_BACKTRACK || p->rule == DS_SPARSA;
+  if (line_search && p->bt_eta != 0.0 && !(p->bt_eta > 1.0 && std::isfinite(p->bt_eta))) {
     set_error("bt_eta must be > 1 (or 0 for the default 2)");
     return DS_EINVAL;
+  }
+  if (p->rule == DS_SPARSA) {
+    if (p->bb_memory < 0 || p->bb_memory > 15) {
+      set_error("bb_memory must be in 0..15");
+      return DS_EINVAL;
+    }
+    if (!(p->bb_sigma >= 0.0) || !std::isfinite(p->bb_sigma)) {
+      set_error("bb_sigma must be >= 0 (0 selects 1e-5)");
+      return DS_EINVAL;
+    }
   }
   return DS_OK;
 }
@@ -182,8 +200,8 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   if (B > 1 && problem->dtype == DS_BF16 && !group) {
-    if (params->step_rule == DS_STEP_BACKTRACK) {
-      set_error("backtracking steps are available on the single-signal path (B = 1 or FP32/FP64 D)");
+    if (params->step_rule == DS_STEP_BACKTRACK || params->rule == DS_SPARSA) {
+      set_error("backtracking and SpaRSA steps are available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
     }
     return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, screened, s);

@@ -151,7 +151,8 @@ void Server::run(Worker* w, Request* r, const Dict& d) {
     return fail(DS_EDEVICE);
   }
   ds_params prm = r->prm;
-  if (!(prm.step_L > 0.0) && prm.step_rule == DS_STEP_CONSTANT) prm.step_L = d.L;
+  if (!(prm.step_L > 0.0) && prm.step_rule == DS_STEP_CONSTANT && prm.rule != DS_SPARSA)
+    prm.step_L = d.L;
   ds_info info{};
   const ds_status st = solve_single(P, y, r->lam, prm, x, &info, w->stream, w->ws, nullptr);
   if (st < 0) return fail(st);

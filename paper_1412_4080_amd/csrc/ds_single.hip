@@ -76,7 +76,7 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.off_segd = take(l.grid_corr * segcap * 8);
   l.off_uromo = take(l.grid_corr * ucap * 8);
   l.off_urdn = take(l.grid_corr * ucap * 8);
-  l.off_bpd = take(MAXB * 8);
+  l.off_bpd = take(2 * MAXB * 8);  // ||d||^2, then the SpaRSA partials
   l.off_dtn = take(MAXRT * 8);
   l.off_rtn = take(2 * 2 * MAXRT * 8);
   l.off_omp = take(2 * MAXITEM * 8);
@@ -157,6 +157,7 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.urec_omo = reinterpret_cast<double*>(base + l.off_uromo);
   a.urec_dn = reinterpret_cast<double*>(base + l.off_urdn);
   a.bpd = reinterpret_cast<double*>(base + l.off_bpd);
+  a.bpe = a.bpd + MAXB;
   a.dtn = reinterpret_cast<double*>(base + l.off_dtn);
   a.rtn = reinterpret_cast<double*>(base + l.off_rtn);
   a.omp = reinterpret_cast<double*>(base + l.off_omp);
@@ -246,12 +247,13 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
 
   // ---- setup (no host synchronisation) ----
   if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
-  // L: given, or estimated here (slow path); backtracking starts from step_L when given,
-  // else from a bound the setup kernel computes on the device
-  const bool bt = prm.step_rule == DS_STEP_BACKTRACK;
+  // L: given, or estimated here (slow path); backtracking and SpaRSA start from step_L
+  // when given, else from a bound the setup kernel computes on the device.  Both use the
+  // step check and undo machinery (a.bt).
+  const bool bt = prm.step_rule == DS_STEP_BACKTRACK || RULE == RULE_SPARSA;
   const double eta = bt ? (prm.bt_eta > 0.0 ? prm.bt_eta : 2.0) : 0.0;
   a.bt = bt ? 1 : 0;
-  DS_HIP(hipMemsetAsync(a.bpd, 0, MAXB * 8, s));
+  DS_HIP(hipMemsetAsync(a.bpd, 0, 2 * MAXB * 8, s));
   DS_HIP(hipMemsetAsync(a.dtn, 0, MAXRT * 8, s));
   double L = prm.step_L;
   if (!(L > 0.0) && !bt) {
@@ -269,7 +271,9 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   const double gamma_z = kchain * u_round / (1.0 - kchain * u_round);
   const bool relative = prm.lambda_mode == DS_LAMBDA_RELATIVE;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, lam,
-                     relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z, eta);
+                     relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z, eta,
+                     RULE == RULE_SPARSA ? prm.bb_memory : 0,
+                     prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5);
   DS_HIP(hipGetLastError());
   if (prm.test == DS_TEST_DST3) {
     hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
@@ -455,6 +459,9 @@ ds_status dispatch_rule(const ds_problem& P, const void* y, double lam, const ds
   if (prm.rule == DS_FISTA)
     return vec ? run_single<T, true, RULE_FISTA>(P, y, lam, prm, x, info, s, ws, tele, scr)
                : run_single<T, false, RULE_FISTA>(P, y, lam, prm, x, info, s, ws, tele, scr);
+  if (prm.rule == DS_SPARSA)
+    return vec ? run_single<T, true, RULE_SPARSA>(P, y, lam, prm, x, info, s, ws, tele, scr)
+               : run_single<T, false, RULE_SPARSA>(P, y, lam, prm, x, info, s, ws, tele, scr);
   return vec ? run_single<T, true, RULE_ISTA>(P, y, lam, prm, x, info, s, ws, tele, scr)
              : run_single<T, false, RULE_ISTA>(P, y, lam, prm, x, info, s, ws, tele, scr);
 }
@@ -497,7 +504,7 @@ ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t
                                : launch_setup_corr<T, false>(P, y, base, l, s);
   if (e != DS_OK) return e;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, 1.0, 1, 1.0, 0.0,
-                     1, 0.0, 0.0);
+                     1, 0.0, 0.0, 0, 1e-5);
   DS_HIP(hipGetLastError());
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));

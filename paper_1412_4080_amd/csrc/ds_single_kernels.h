@@ -434,7 +434,8 @@ template <typename T, typename V, typename A>
 __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, double lam_in,
                                                          int lam_relative, double L,
                                                          double gap_tol, int max_iter,
-                                                         double gamma_z, double bt_eta) {
+                                                         double gamma_z, double bt_eta,
+                                                         int bb_mem, double bb_sigma) {
   __shared__ double sd[CNW];
   __shared__ int si[CNW];
   __shared__ double s_lmax;
@@ -536,6 +537,12 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     st->bt_eta = bt_eta;
     st->rejected = 0;
     st->n_reject = 0;
+    st->bb_mem = bb_mem;
+    st->phi_n = 0;
+    st->bb_new = 1;
+    st->bb_pad = 0;
+    st->bb_sigma = bb_sigma;
+    for (int j = 0; j <= BB_MEM_MAX; ++j) st->phi_mem[j] = 0.0;
     st->yy = yy;
     st->alpha = alpha;
     st->nn = nn;
@@ -837,7 +844,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   __shared__ int scan[NW];
   __shared__ int s_last;
   __shared__ SolverState S;
-  __shared__ double red8[NW][10];
+  __shared__ double red8[NW][RULE == RULE_SPARSA ? 11 : 10];
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   const SolverState* sin = a.st + (1 - a.par);
   SolverState* sout = a.st + a.par;
@@ -887,12 +894,14 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   constexpr int NWORDS = sizeof(SolverState) / 4;
   static_assert(NWORDS <= BLK, "state fits one word per thread");
   const int32_t sword = reinterpret_cast<const int32_t*>(sin)[min(tid, NWORDS - 1)];
-  // zs nz kt ns at tt ty om; backtracking: ||d||^2 ||D d||^2
-  constexpr int NV = 10;
-  double v[NV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // zs nz kt ns at tt ty om; backtracking: ||d||^2 ||D d||^2; SpaRSA: the correlation
+  // pass's part of phi(x') - phi(p)
+  constexpr int NV = RULE == RULE_SPARSA ? 11 : 10;
+  double v[NV] = {};
   const double* rtp = a.rtn + (1 - a.par) * (2 * MAXRT);
   const double* omp = a.omp + (1 - a.par) * MAXITEM;
   double p0[PB], p1[PB], p2[PB], p3[PB], p4[PB], p8[PB];
+  double p10[RULE == RULE_SPARSA ? PB : 1];
 #pragma unroll
   for (int k = 0; k < PB; ++k) {  // block partials tid, tid + BLK, ... in that order
     const int b = min(k * BLK + tid, a.grid_corr - 1);
@@ -902,6 +911,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     p3[k] = a.bpi[2 * MAXB + b];
     p4[k] = a.bpi[3 * MAXB + b];
     p8[k] = a.bpd[b];
+    if constexpr (RULE == RULE_SPARSA) p10[k] = a.bpe[b];
   }
   const int kr = min(tid, nrt - 1), ko = min(tid, nsg - 1);
   const double q5 = rtp[2 * kr], q6 = rtp[2 * kr + 1], q7 = omp[ko], q9 = a.dtn[kr];
@@ -916,6 +926,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     v[3] += ok ? p3[k] : 0.0;
     v[4] += ok ? p4[k] : 0.0;
     v[8] += ok ? p8[k] : 0.0;
+    if constexpr (RULE == RULE_SPARSA) v[NV - 1] += ok ? p10[k] : 0.0;
   }
   v[5] += tid < nrt ? q5 : 0.0;
   v[6] += tid < nrt ? q6 : 0.0;
@@ -929,6 +940,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     v[3] += a.bpi[2 * MAXB + b];
     v[4] += a.bpi[3 * MAXB + b];
     v[8] += a.bpd[b];
+    if constexpr (RULE == RULE_SPARSA) v[NV - 1] += a.bpe[b];
   }
   for (int k = BLK + tid; k < nrt; k += BLK) {
     v[5] += rtp[2 * k];
@@ -971,7 +983,18 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     // backtracking: the step of this iteration is kept when ||D d||^2 <= L ||d||^2 (the
     // descent condition F(x') <= Q_L(x', p) for the quadratic data term); the stop needs
     // an accepted step, except at the iteration limit
-    const bool rej = a.bt && !(v[9] <= S.L * v[8]);
+    bool rej = a.bt && !(v[9] <= S.L * v[8]);
+    if constexpr (RULE == RULE_SPARSA) {
+      // SpaRSA: the memory takes phi(p) (a new entry when p is a new iterate, else it
+      // replaces the newest); the step is kept when phi(x') - phi(p) = z^T d + ||D d||^2 / 2
+      // + lambda (Omega(x') - Omega(p)) satisfies phi(x') <= max(memory) - sigma/2 L ||d||^2
+      const int keep0 = S.bb_new ? max(0, S.phi_n - S.bb_mem) : 0;  // first entry kept
+      const int keep1 = S.bb_new ? S.phi_n : S.phi_n - 1;            // one past the last
+      double phi_ref = o.primal;
+      for (int j = keep0; j < keep1; ++j) phi_ref = fmax(phi_ref, S.phi_mem[j]);
+      const double dphi = v[NV - 1] + 0.5 * v[9];
+      rej = !(dphi + (o.primal - phi_ref) <= -0.5 * S.bb_sigma * S.L * v[8]);
+    }
     const bool stop = (!rej && S.gap_tol_abs > 0.0 && o.gap <= S.gap_tol_abs) || t >= S.max_iter;
     __syncthreads();
     if (tid == 0) {
@@ -998,6 +1021,20 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       S.r_min = fmin(S.r_min, o.r);
       if (RULE == RULE_FISTA && !rej) S.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S.l_prev * S.l_prev));
       S.rejected = rej ? 1 : 0;
+      if constexpr (RULE == RULE_SPARSA) {
+        // memory update (oldest first), then the Barzilai-Borwein step after an accepted one
+        if (S.bb_new) {
+          if (S.phi_n > S.bb_mem) {
+            for (int j = 1; j < S.phi_n; ++j) S.phi_mem[j - 1] = S.phi_mem[j];
+            --S.phi_n;
+          }
+          S.phi_mem[S.phi_n++] = o.primal;
+        } else {
+          S.phi_mem[S.phi_n - 1] = o.primal;
+        }
+        S.bb_new = rej ? 0 : 1;
+        if (!rej && !stop && v[8] > 0.0) S.L = fmin(fmax(v[9] / v[8], 1e-30), 1e30);
+      }
       if (rej) {
         ++S.n_reject;
         if (!stop) S.L *= S.bt_eta;
@@ -1319,7 +1356,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ int s_vb, s_nk, s_kpre;
   __shared__ int klist[CBU];
   __shared__ double kmarg[CBU];
-  __shared__ double sred[NW][5];
+  __shared__ double sred[NW][6];
   __shared__ SolverState S;
   if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
@@ -1391,6 +1428,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   double zsup = 0.0;  // max |z_i| (Lasso) or max ||z_g|| / w_g; rounding slack added later
   int nnz = 0, nsup = 0, natoms = 0;
   double dd = 0.0;    // backtracking: ||x' - p||^2 over this block's units
+  double de = 0.0;    // SpaRSA: z^T d + lambda (Omega(x') - Omega(p)) over this block's units
   if constexpr (!GROUP) {
     for (int r0 = wave * CPW; r0 < nk; r0 += NW * CPW) {
       const int nc = min(CPW, nk - r0);
@@ -1428,6 +1466,10 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
           a.seg_d[slot] = dv;
           a.urec_omo[slot] = fabs(p);
           dd = fma(dv, dv, dd);
+          // SpaRSA: z_i d_i + lambda (|x'_i| - |p_i|), the first-order and penalty parts of
+          // phi(x') - phi(p), unit by unit
+          if constexpr (RULE == RULE_SPARSA)
+            de += fma(z, dv, lam * (fabs(static_cast<double>(xs)) - fabs(p)));
         }
         zsup = fmax(zsup, fabs(z));
         nnz += xs != V(0) ? 1 : 0;
@@ -1441,13 +1483,14 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       const int g = klist[j];
       const int64_t a0 = a.gptr[g];
       const int m = static_cast<int>(a.gptr[g + 1] - a0);
-      double p[NS], xo[NS], vreg[NS];
+      double p[NS], xo[NS], vreg[NS], zk[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int li = min(lane + s * WAVE, m - 1);
         p[s] = static_cast<double>(a.u[a0 + li]);
         xo[s] = static_cast<double>(a.x[a0 + li]);
         vreg[s] = 0.0;
+        zk[s] = 0.0;
       }
       double z2 = 0.0;
       for (int b0 = 0; b0 < m; b0 += CPW) {
@@ -1464,7 +1507,10 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
             z2 = fma(acc[c], acc[c], z2);
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-              if (b0 + c == lane + s * WAVE) vreg[s] = p[s] - acc[c] * invL;
+              if (b0 + c == lane + s * WAVE) {
+                vreg[s] = p[s] - acc[c] * invL;
+                if constexpr (RULE == RULE_SPARSA) zk[s] = acc[c];
+              }
           }
         }
       }
@@ -1477,6 +1523,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       const double scale = nv > 0.0 ? fmax(0.0, (nv - thr * wg) / nv) : 0.0;
       int gnz = 0, gsup = 0;
       double un2 = 0.0, dn = 0.0, po2 = 0.0;
+      double gzd = 0.0, gds = 0.0;  // SpaRSA: z_g^T d_g and d_g^T (x'_g + p_g)
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int ak = lane + s * WAVE;  // atom of the group
@@ -1496,6 +1543,10 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
             a.seg_d[slot] = dv;
             dn = fma(dv, dv, dn);
             po2 = fma(p[s], p[s], po2);
+            if constexpr (RULE == RULE_SPARSA) {
+              gzd = fma(zk[s], dv, gzd);
+              gds = fma(dv, static_cast<double>(xs) + p[s], gds);
+            }
           }
           gnz += xs != V(0) ? 1 : 0;
           gsup += us != V(0) ? 1 : 0;
@@ -1508,6 +1559,10 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       if (a.bt) {
         dn = wave_sum(dn);
         po2 = wave_sum(po2);
+        if constexpr (RULE == RULE_SPARSA) {
+          gzd = wave_sum(gzd);
+          gds = wave_sum(gds);
+        }
       }
       if (lane == 0) {
         const int64_t rec = static_cast<int64_t>(vb) * CBU + j;
@@ -1518,6 +1573,11 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
           a.urec_omo[rec] = wg * sqrt(po2);
           a.urec_dn[rec] = dn;
           dd += dn;
+          if constexpr (RULE == RULE_SPARSA) {
+            // ||x'_g|| - ||p_g|| = d_g^T (x'_g + p_g) / (||x'_g|| + ||p_g||): no cancellation
+            const double den = sqrt(un2) + sqrt(po2);
+            de += gzd + (den > 0.0 ? lam * wg * (gds / den) : 0.0);
+          }
         }
         zsup = fmax(zsup, sqrt(z2) / wg);
         nnz += gnz;
@@ -1531,12 +1591,14 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   const double cnz = wave_sum(static_cast<double>(nnz)), csup = wave_sum(static_cast<double>(nsup));
   const double cat = wave_sum(static_cast<double>(natoms));
   const double cdd = a.bt ? wave_sum(dd) : 0.0;
+  const double cde = RULE == RULE_SPARSA ? wave_sum(de) : 0.0;
   if (lane == 0) {
     sred[wave][0] = zsup;
     sred[wave][1] = cnz;
     sred[wave][2] = csup;
     sred[wave][3] = cat;
     sred[wave][4] = cdd;
+    if (RULE == RULE_SPARSA) sred[wave][5] = cde;
   }
   __syncthreads();
   if (tid == 0) {  // read by the next residual pass only (after this kernel ends)
@@ -1549,7 +1611,11 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       r3 += sred[w][3];
       r4 += sred[w][4];
     }
+    double r5 = 0.0;
+    if (RULE == RULE_SPARSA)
+      for (int w = 0; w < NW; ++w) r5 += sred[w][5];
     if (a.bt) a.bpd[vb] = r4;
+    if (RULE == RULE_SPARSA) a.bpe[vb] = r5;
     zsup = r0;
     nnz = static_cast<int>(r1);
     nsup = static_cast<int>(r2);

@@ -5,7 +5,8 @@
 namespace ds {
 
 enum TestKind { TEST_NONE = 0, TEST_SAFE = 1, TEST_DST3 = 2 };
-enum RuleKind { RULE_ISTA = 0, RULE_FISTA = 1 };
+enum RuleKind { RULE_ISTA = 0, RULE_FISTA = 1, RULE_SPARSA = 2 };
+constexpr int BB_MEM_MAX = 15;  // SpaRSA: earlier iterates kept in the acceptance memory
 
 // Every scalar of the iteration lives in device memory so that a whole chunk of
 // iterations can be enqueued (or graph-replayed) without host round trips.
@@ -52,6 +53,14 @@ struct alignas(16) SolverState {
   int32_t n_omp;       // Omega(p) partials the last residual pass published
   int32_t rejected;    // backtracking: the last step was rejected (x, u were restored)
   int32_t n_reject;    // backtracking: rejected steps so far
+  // SpaRSA: objective at the current primal point (newest entry) and at up to bb_mem
+  // earlier iterates, oldest first
+  int32_t bb_mem;      // earlier iterates kept
+  int32_t phi_n;       // entries in phi_mem
+  int32_t bb_new;      // 1: the primal point of the next scalar stage is a new iterate
+  int32_t bb_pad;
+  double bb_sigma;     // sufficient-decrease constant
+  double phi_mem[BB_MEM_MAX + 1];
 };
 
 template <typename T, typename V, typename A>
@@ -109,6 +118,7 @@ struct SingleArgs {
   double* urec_omo;      // UCAP unit records per block: Omega term of p
   double* urec_dn;       // UCAP unit records per block: ||d_unit||^2
   double* bpd;           // ||d||^2 per correlation block
+  double* bpe;           // SpaRSA: z^T d + lambda (Omega(x') - Omega(p)) per correlation block
   double* dtn;           // ||D d||^2 per row tile (the check pass)
 };
 

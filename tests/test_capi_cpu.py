@@ -73,6 +73,21 @@ def test_invalid_params_rejected(B, field, value):
     assert st == B.DS_EINVAL
 
 
+@pytest.mark.parametrize("field,value", [("bb_memory", -1), ("bb_memory", 16),
+                                         ("bb_sigma", -1e-5), ("bb_sigma", float("nan")),
+                                         ("step_rule", 1), ("bt_eta", 1.0)])
+def test_invalid_sparsa_params_rejected(B, field, value):
+    """SpaRSA: memory 0..15, sigma >= 0, eta > 1, and no separate step rule."""
+    p = _problem(B)
+    prm = B.make_params(rule="sparsa")
+    setattr(prm, field, value)
+    lam = (C.c_double * 1)(0.5)
+    info = (B.Info * 1)()
+    st = B._lib.lasso_solve(C.byref(p), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                            C.c_void_p(0x3000), 20, info, None)
+    assert st == B.DS_EINVAL, field
+
+
 def test_invalid_lambda_and_groups_rejected(B):
     p = _problem(B)
     prm = B.make_params()
