@@ -24,6 +24,9 @@ from .dynscreen import (  # noqa: F401
     group_center,
     lasso_margins,
     group_margins,
+    dome_max,
+    dome_setup,
+    dome_margins,
     group_spectral_norms,
     spectral_norm_sq,
     solve_lasso,

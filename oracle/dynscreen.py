@@ -58,6 +58,14 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   atom i is (1 - |d_i^T c|) / ||d_i||, and the DST3 centre is the projection of
   y/lambda onto the hyperplane {theta : d_*^T theta = 1}.  Both reduce to
   Lemmas 1 and 2 for unit atoms.
+* Dynamic Dome test (the dome lemma of the section on dynamic tests): the region is the
+  ball B(y/lambda, ||y/lambda - v_t||) cut by the half-space d_*^T theta <= 1.  The
+  printed bounds Q^l, Q^u are those of that region for unit atoms except for their case
+  split, which is written for the static dual point (theta = y, unit y: the split at
+  t = -/+lambda_* with the constant lambda - 1 + lambda/lambda_*); for a general dual
+  point the split falls where the ball's own maximiser leaves the half-space.  The
+  region is used as stated, for atoms of any norm (dome_max, dome_margins), and the
+  printed x^T d_i is read as y^T d_i.  Lasso only (the lemma is stated for the Lasso).
 * Ties in the arg-max defining i_* / g_* go to the smallest index.  A radius
   whose square rounds below zero is clamped to zero.  An atom exactly at the
   threshold is kept (the test is a strict inequality).
@@ -183,7 +191,7 @@ def lasso_center(D, y, lam, test, lam_max, i_star):
     c = y/lambda - (lambda_*/lambda - 1) d_*.
     """
     c0 = y / lam
-    if test in ("none", "safe"):
+    if test in ("none", "safe", "dome"):   # the dome's ball is SAFE's
         return c0, 0.0
     assert test == "dst3"
     d = D[:, i_star]
@@ -230,6 +238,78 @@ def lasso_margins(D, c, test):
     return m
 
 
+def dome_max(U, c, R, n, h, points=False):
+    """Largest u^T theta over the dome {||theta - c|| <= R} cut by {n^T theta <= h} (n a
+    unit vector, R at least the distance n^T c - h from c to the plane, so the dome is not
+    empty), for each column u of U (R a scalar or one radius per column).  If the ball's
+    own maximiser c + R u/||u|| lies in the half-space it is the answer; otherwise the
+    maximum is taken on the cutting plane, over the disc of centre c' = c - (n^T c - h) n
+    and radius sqrt(R^2 - (n^T c - h)^2), at c' plus that radius times the unit component
+    of u orthogonal to n.  With points=True the maximising points are returned too."""
+    U = np.asarray(U, dtype=np.float64)
+    U = U[:, None] if U.ndim == 1 else U
+    R = np.broadcast_to(np.asarray(R, dtype=np.float64), (U.shape[1],))
+    nu = np.linalg.norm(U, axis=0)
+    uc = U.T @ c
+    un = U.T @ n
+    delta = float(n @ c) - h
+    in_half = float(n @ c) + R * un / nu <= h      # n^T (c + R u/||u||) <= h
+    r2 = np.sqrt(np.maximum(R * R - delta * delta, 0.0))
+    npn = np.sqrt(np.maximum(nu * nu - un * un, 0.0))   # ||u - (u^T n) n||
+    val = np.where(in_half, uc + R * nu, uc - delta * un + r2 * npn)
+    if not points:
+        return val
+    up = U - np.outer(n, un)
+    t_ball = c[:, None] + U * (R / nu)
+    t_disc = (c - delta * n)[:, None] + up * (r2 / np.where(npn > 0, npn, 1.0))
+    return val, np.where(in_half, t_ball, t_disc)
+
+
+def dome_setup(D, y, lam, i_star):
+    """The dome of the dynamic Dome test (Lemma 'dynamic dome'): centre y/lambda, and the
+    half-space d_*^T theta <= 1 of the atom attaining lambda_* (signed so that
+    d_*^T y = lambda_*), as a unit normal n and offset h = 1/||d_*||."""
+    d = D[:, i_star]
+    d_star = d if float(d @ y) >= 0.0 else -d
+    nd = float(np.linalg.norm(d_star))
+    return y / lam, d_star / nd, 1.0 / nd
+
+
+def dome_margins(D, y, lam, i_star, iters=200):
+    """Per-atom threshold of the dynamic Dome test: the largest R for which the maximum of
+    |d_i^T theta| over the dome B(y/lambda, R) cut by d_*^T theta <= 1 stays below 1.  That
+    maximum grows with R, so atom i is screened at radius R_t = ||y/lambda - v_t|| exactly
+    when R_t < m_i.  Found by bisection on that definition (both signs of d_i), starting
+    from the smallest radius with a non-empty dome, delta = the distance from y/lambda to
+    the plane: an atom whose bound stays below 1 at every radius has m_i = +inf, one that
+    reaches 1 already at delta has m_i = delta (never screened, since R_t >= delta), as
+    has d_* itself."""
+    c, n, h = dome_setup(D, y, lam, i_star)
+    delta = float(n @ c) - h
+    K = D.shape[1]
+
+    def f(R):
+        return np.maximum(dome_max(D, c, R, n, h), dome_max(-D, c, R, n, h))
+
+    big = (delta + 1.0) * 1e12
+    never = f(np.full(K, delta)) >= 1.0
+    always = f(np.full(K, big)) < 1.0
+    lo = np.full(K, delta)
+    hi = np.full(K, big)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        below = f(mid) < 1.0
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    m = lo
+    m[never] = delta
+    m[always] = np.inf
+    # d_* itself attains d_*^T theta = 1 on the cutting plane at every radius (its bound is
+    # exactly 1, which rounding can put on either side): it is never screened
+    m[i_star] = delta
+    return m
+
+
 def group_margins(D, c, test, groups, w, gnorm):
     """Per-group margin m_g = (w_g - ||D_g^T c||) / ||D_g||_2 (Lemmas 4, 5 and 6)."""
     G = len(groups)
@@ -249,7 +329,7 @@ def group_margins(D, c, test, groups, w, gnorm):
 def _radius(R2, rho2, test):
     if test == "none":
         return np.inf
-    if test in ("safe", "gsafe"):
+    if test in ("safe", "gsafe", "dome"):
         return float(np.sqrt(R2))
     return float(np.sqrt(max(R2 - rho2, 0.0)))
 
@@ -279,8 +359,9 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
     x_t = prox(p - z_t / L, lambda / L), FISTA momentum), the dual point
     v_t = mu_t theta_t, the sphere radius r_t of the chosen test (SAFE Lemma 1,
-    DST3 Lemma 2, or none), the screened set I_t = {i : m_i > r_t} U I_{t-1},
-    and the reduction of D and of the primal variables to the complement of I_t.
+    DST3 Lemma 2, the dynamic Dome test with the SAFE radius and the thresholds of
+    dome_margins, or none), the screened set I_t = {i : m_i > r_t} U I_{t-1}, and the
+    reduction of D and of the primal variables to the complement of I_t.
 
     screening="static" runs the test once, at the first iteration, where the dual point
     from x_0 = 0 makes it the static test of Algorithms 1 and 4 (static SAFE, ST3); the
@@ -292,7 +373,7 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     N, K = D.shape
-    assert test in ("none", "safe", "dst3") and rule in ("ista", "fista", "sparsa")
+    assert test in ("none", "safe", "dst3", "dome") and rule in ("ista", "fista", "sparsa")
     assert step in ("constant", "backtracking") and eta > 1.0
     assert rule != "sparsa" or (step == "constant" and bb_memory >= 0 and bb_sigma >= 0.0)
     lam_max, i_star = lambda_max_lasso(D, y)
@@ -305,7 +386,7 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         return _trivial(K, lam, lam_max, L)
 
     c, rho2 = lasso_center(D, y, lam, test, lam_max, i_star)
-    m = lasso_margins(D, c, test)
+    m = dome_margins(D, y, lam, i_star) if test == "dome" else lasso_margins(D, c, test)
     yy = float(y @ y)
 
     screened = np.zeros(K, dtype=bool)          # I_0 = empty set

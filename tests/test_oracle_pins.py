@@ -553,6 +553,141 @@ def test_backtracking_reaches_the_same_optimum(rule, group):
     assert b.primal - b.dual <= b.gap + 1e-15
 
 
+# -------------------------------------------------------------------------- Dome test
+def test_dome_max_is_attained_and_never_exceeded():
+    """dome_max against the region itself: each returned point lies in the ball and the
+    half-space and attains the value, no point of a dense sample of the dome exceeds it,
+    and a general constrained maximiser (SciPy SLSQP) finds the same value."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(201)
+    N = 4
+    c = rng.standard_normal(N)
+    n = rng.standard_normal(N)
+    n /= np.linalg.norm(n)
+    h = float(n @ c) - 0.7                        # the plane cuts the ball (R > 0.7)
+    R = 1.3
+    U = rng.standard_normal((N, 12))
+    val, pts = oracle.dome_max(U, c, R, n, h, points=True)
+    assert np.all(np.linalg.norm(pts - c[:, None], axis=0) <= R * (1 + 1e-12))
+    assert np.all(n @ pts <= h + 1e-12)
+    assert np.allclose(np.einsum("ij,ij->j", U, pts), val, rtol=0, atol=1e-12)
+    # dense sample of the dome (uniform in the ball, kept if in the half-space)
+    S = rng.standard_normal((N, 400000))
+    S *= R * rng.random(400000) ** (1.0 / N) / np.linalg.norm(S, axis=0)
+    S += c[:, None]
+    S = S[:, n @ S <= h]
+    assert np.all((U.T @ S).max(axis=1) <= val + 1e-12)
+    cons = [{"type": "ineq", "fun": lambda t: R * R - (t - c) @ (t - c)},
+            {"type": "ineq", "fun": lambda t: h - n @ t}]
+    for j in range(U.shape[1]):
+        res = minimize(lambda t: -(U[:, j] @ t), c - 0.7 * n, constraints=cons, method="SLSQP",
+                       options={"ftol": 1e-15, "maxiter": 1000})
+        t = res.x
+        # SLSQP ends slightly outside the region; what it gains is bounded by that
+        viol = max(np.linalg.norm(t - c) - R, 0.0) + max(float(n @ t) - h, 0.0)
+        assert -res.fun <= val[j] + 2.0 * np.linalg.norm(U[:, j]) * viol + 1e-12
+        assert -res.fun >= val[j] - 1e-7
+
+
+def test_dome_static_case_equals_the_printed_dome_test():
+    """Unit atoms, unit y, static dual point theta = y (radius 1/lambda - 1/lambda_*): the
+    thresholds screen exactly the atoms with Q^l(t_i) < y^T d_i < Q^u(t_i), t_i = d_*^T d_i,
+    for the bounds printed in the dome lemma (lower: (lambda_* - lambda) t - lambda +
+    lambda psi sqrt(1 - t^2) for t <= lambda_*, else -(lambda - 1 + lambda / lambda_*);
+    upper: lambda - 1 + lambda / lambda_* for t < -lambda_*, else (lambda_* - lambda) t +
+    lambda - lambda psi sqrt(1 - t^2)), psi^2 = R^2 - (lambda_*/lambda - 1)^2."""
+    N, K = 30, 400
+    D = datagen.gaussian_dictionary(N, K, 202)          # unit columns
+    rng = np.random.default_rng(203)
+    y = D[:, :3] @ rng.standard_normal(3) + 0.3 * rng.standard_normal(N)
+    y /= np.linalg.norm(y)
+    lmax, ist = oracle.lambda_max_lasso(D, y)
+    n_scr = 0
+    for ratio in (0.2, 0.5, 0.8, 0.95):
+        lam = ratio * lmax
+        m = oracle.dome_margins(D, y, lam, ist)
+        R = 1.0 / lam - 1.0 / lmax
+        ds = D[:, ist] * np.sign(D[:, ist] @ y)
+        t = D.T @ ds
+        yd = D.T @ y
+        psi = np.sqrt(max(R * R - (lmax / lam - 1.0) ** 2, 0.0))
+        root = np.sqrt(np.maximum(1.0 - t * t, 0.0))
+        const = lam - 1.0 + lam / lmax
+        Ql = np.where(t <= lmax, (lmax - lam) * t - lam + lam * psi * root, -const)
+        Qu = np.where(t < -lmax, const, (lmax - lam) * t + lam - lam * psi * root)
+        printed = (Ql < yd) & (yd < Qu)
+        ours = m > R
+        band = np.minimum(np.abs(yd - Ql), np.abs(Qu - yd)) < 1e-9   # ties within rounding
+        assert np.array_equal(printed[~band], ours[~band])
+        n_scr += int(ours.sum())
+    assert n_scr > 0
+
+
+def test_dome_thresholds_are_attained():
+    """At its threshold an atom's dome bound equals 1 (both signs, the larger), and the
+    bound is below 1 slightly inside and above 1 slightly outside."""
+    D, y = _problem(N=50, K=300, seed=204)
+    lmax, ist = oracle.lambda_max_lasso(D, y)
+    lam = 0.5 * lmax
+    m = oracle.dome_margins(D, y, lam, ist)
+    c, n, h = oracle.dome_setup(D, y, lam, ist)
+    delta = float(n @ c) - h
+
+    def f(R):
+        return np.maximum(oracle.dome_max(D, c, R, n, h), oracle.dome_max(-D, c, R, n, h))
+
+    fin = np.isfinite(m) & (m > delta)
+    fin[ist] = False
+    assert fin.sum() > 250
+    assert np.max(np.abs(f(m)[fin] - 1.0)) < 1e-12
+    assert np.all(f(m * (1 - 1e-6))[fin] < 1.0) and np.all(f(m * (1 + 1e-6))[fin] > 1.0)
+    assert m[ist] == delta
+
+
+def test_dome_screens_more_than_dst3_and_safe():
+    """The dome is contained in DST3's ball (of radius sqrt(R^2 - delta^2) about the
+    projected centre), which is contained in SAFE's: at every radius R >= delta the dome
+    test screens a superset of DST3's screened atoms, and DST3 a superset of SAFE's.  The
+    dome's bound is smaller by the factor sqrt(1 - t^2) on its radius term (t = d_*^T d_i),
+    so atoms sharing a common direction show strictly more screening."""
+    rng = np.random.default_rng(205)
+    N, K = 50, 300
+    D = 0.8 * rng.standard_normal((N, 1)) + rng.standard_normal((N, K))
+    D /= np.linalg.norm(D, axis=0)
+    y = D[:, :4] @ rng.standard_normal(4) + 0.2 * rng.standard_normal(N)
+    y /= np.linalg.norm(y)
+    lmax, ist = oracle.lambda_max_lasso(D, y)
+    more = 0
+    for ratio in (0.3, 0.6, 0.85):
+        lam = ratio * lmax
+        m_dome = oracle.dome_margins(D, y, lam, ist)
+        c3, rho2 = oracle.lasso_center(D, y, lam, "dst3", lmax, ist)
+        m_dst3 = oracle.lasso_margins(D, c3, "dst3")
+        m_safe = oracle.lasso_margins(D, y / lam, "safe")
+        delta = np.sqrt(rho2)
+        for R in delta + np.linspace(0.0, 3.0, 31)[1:] * (1.0 / lam):
+            s_dome = m_dome > R
+            s_dst3 = m_dst3 > np.sqrt(R * R - rho2)
+            s_safe = m_safe > R
+            assert np.all(s_dome[s_dst3]) and np.all(s_dst3[s_safe])
+            more += int(s_dome.sum() - s_dst3.sum())
+    assert more > 0
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista"])
+def test_dome_solver_is_safe_and_reaches_the_same_optimum(rule):
+    D, y = _problem(N=60, K=240, seed=206)
+    for ratio in (0.3, 0.6):
+        a = oracle.solve_lasso(D, y, lam_ratio=ratio, rule=rule, test="none", max_iter=100000,
+                               gap_tol=1e-11)
+        b = oracle.solve_lasso(D, y, lam_ratio=ratio, rule=rule, test="dome", max_iter=100000,
+                               gap_tol=1e-11)
+        assert a.converged and b.converged
+        assert abs(a.primal - b.primal) <= 2e-11 * float(y @ y)
+        cert, gap = oracle.certified_inactive_lasso(D, y, a.lam, a.x)
+        assert np.all(cert[b.screened])
+
+
 # -------------------------------------------------------------------------- SpaRSA
 @pytest.mark.parametrize("group", [False, True])
 def test_sparsa_on_a_scaled_orthonormal_dictionary_reaches_the_closed_form(group):
