@@ -295,6 +295,30 @@ def backtracking_leg(binding, Dd, ys, steps):
     return out
 
 
+def dome_leg(binding, Dd, ys, steps, L):
+    """The headline workload (FISTA, constant step) with the dynamic Dome test in place of
+    DST3: solves/s and the mean number of atoms still active after 10 iterations."""
+    import torch
+    run_steps(binding, Dd, ys, 1, "dome", L)   # warm-up
+    it = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = run_steps(binding, Dd, ys, steps, "dome", L, iters=it)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    act = {}
+    for test in ("dst3", "dome"):
+        a10 = []
+        for r in RATIOS:
+            _, _, _, tr = binding.solve_one(Dd, ys[0], r, rule="fista", test=test, step_L=L,
+                                            gap_tol=0.0, max_iter=10, screened=False)
+            a10.append(tr[-1]["n_active"])
+        act[test] = round(float(np.mean(a10)), 1)
+    return {"test": "dome", "solves_per_s": round(n / dt, 3),
+            "mean_iters": round(float(np.mean(it)), 1),
+            "mean_active_after_10_iters": act}
+
+
 def sparsa_leg(binding, Dd, ys, steps):
     """The headline workload with SpaRSA (Table 1: ISTA with the Barzilai-Borwein step;
     L_0 the largest squared atom norm, eta = 2, sigma = 1e-5), monotone (memory 0) and
@@ -481,11 +505,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking,sparsa",
+    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking,sparsa,dome",
                     help="comma list of legs: single (headline), batched, served, flops, large "
                          "(correlation roofline on 4096 x 40000 FP32), backtracking (the headline "
                          "workload with backtracking steps), sparsa (the headline workload with "
-                         "SpaRSA's Barzilai-Borwein steps).  Profiling "
+                         "SpaRSA's Barzilai-Borwein steps), dome (the headline workload with "
+                         "the dynamic Dome test).  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
@@ -594,6 +619,10 @@ def main():
         bt["constant_step_mean_iters"] = round(float(np.mean(it_c)), 1)
         bt["over_constant_step"] = round(bt["screened_solves_per_s"] / value, 3)
         out["backtracking"] = bt
+    if "dome" in legs:
+        dm = dome_leg(binding, Dd, ys, args.steps, L)
+        dm["over_dst3"] = round(dm["solves_per_s"] / value, 3)
+        out["dome"] = dm
     if "sparsa" in legs:
         sp = sparsa_leg(binding, Dd, ys, args.steps)
         sp["over_constant_step_fista"] = round(sp["memory0_screened_solves_per_s"] / value, 3)

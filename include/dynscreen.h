@@ -61,8 +61,11 @@ typedef enum { DS_F64 = 0, DS_F32 = 1, DS_BF16 = 2 } ds_dtype;
 typedef enum { DS_ISTA = 0, DS_FISTA = 1, DS_SPARSA = 2 } ds_rule;
 
 /* Screening test.  For Group-Lasso problems SAFE means GSAFE (Lemma 4) and DST3 means
- * DGST3 (Lemma 5).  DS_TEST_NONE runs the plain, unscreened algorithm. */
-typedef enum { DS_TEST_NONE = 0, DS_TEST_SAFE = 1, DS_TEST_DST3 = 2 } ds_test;
+ * DGST3 (Lemma 5).  DS_TEST_DOME is the dynamic Dome test (the dome lemma: the SAFE ball
+ * B(y/lambda, ||y/lambda - v_t||) cut by the half-space d_*^T theta <= 1 of the atom
+ * attaining lambda_*); Lasso only (glasso_solve and the batched bfloat16 path return
+ * DS_EINVAL).  DS_TEST_NONE runs the plain, unscreened algorithm. */
+typedef enum { DS_TEST_NONE = 0, DS_TEST_SAFE = 1, DS_TEST_DST3 = 2, DS_TEST_DOME = 3 } ds_test;
 
 /* How `lambdas` is read: absolute penalties, or ratios lambda / lambda_* where
  * lambda_* = ||D^T y||_inf (Lasso) or max_g ||D_g^T y|| / w_g (eq. (gstar)) is

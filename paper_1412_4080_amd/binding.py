@@ -23,7 +23,7 @@ DS_OK, DS_PENDING, DS_NOT_CONVERGED = 0, 1, 2
 DS_EINVAL, DS_ENOMEM, DS_EDEVICE, DS_ENOTFOUND, DS_EBUSY = -1, -2, -3, -4, -5
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
 RULES = {"ista": 0, "fista": 1, "sparsa": 2}
-TESTS = {"none": 0, "safe": 1, "dst3": 2, "gsafe": 1, "dgst3": 2}
+TESTS = {"none": 0, "safe": 1, "dst3": 2, "gsafe": 1, "dgst3": 2, "dome": 3}
 STATUS_NAMES = {0: "DS_OK", 1: "DS_PENDING", 2: "DS_NOT_CONVERGED", -1: "DS_EINVAL",
                 -2: "DS_ENOMEM", -3: "DS_EDEVICE", -4: "DS_ENOTFOUND", -5: "DS_EBUSY"}
 STEPS = {"constant": 0, "backtracking": 1}

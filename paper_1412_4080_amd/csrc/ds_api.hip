@@ -136,7 +136,8 @@ ds_status validate_params(const ds_params* p) {
     set_error("unknown rule");
     return DS_EINVAL;
   }
-  if (p->test != DS_TEST_NONE && p->test != DS_TEST_SAFE && p->test != DS_TEST_DST3) {
+  if (p->test != DS_TEST_NONE && p->test != DS_TEST_SAFE && p->test != DS_TEST_DST3 &&
+      p->test != DS_TEST_DOME) {
     set_error("unknown test");
     return DS_EINVAL;
   }
@@ -174,6 +175,14 @@ ds_status validate_params(const ds_params* p) {
   return DS_OK;
 }
 
+ds_status validate_test_for(const ds_params* p, bool group) {
+  if (group && p->test == DS_TEST_DOME) {
+    set_error("the Dome test is stated for the Lasso (use DS_TEST_DST3 for groups)");
+    return DS_EINVAL;
+  }
+  return DS_OK;
+}
+
 namespace {
 
 ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
@@ -182,6 +191,7 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   ds_status e = validate_problem(problem, group);
   if (e != DS_OK) return e;
   if ((e = validate_params(params)) != DS_OK) return e;
+  if ((e = validate_test_for(params, group)) != DS_OK) return e;
   if (Y == nullptr || X == nullptr || info == nullptr || lambdas == nullptr) {
     set_error("Y, X, lambdas and info must be non-NULL");
     return DS_EINVAL;
@@ -200,6 +210,10 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   if (B > 1 && problem->dtype == DS_BF16 && !group) {
+    if (params->test == DS_TEST_DOME) {
+      set_error("the Dome test is available on the single-signal path (B = 1 or FP32/FP64 D)");
+      return DS_EINVAL;
+    }
     if (params->step_rule == DS_STEP_BACKTRACK || params->rule == DS_SPARSA) {
       set_error("backtracking and SpaRSA steps are available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
@@ -254,6 +268,7 @@ ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,
   ds_status e = validate_problem(problem, group);
   if (e != DS_OK) return e;
   if ((e = validate_params(params)) != DS_OK) return e;
+  if ((e = validate_test_for(params, group)) != DS_OK) return e;
   if (y == nullptr || x == nullptr || info == nullptr) {
     set_error("y, x and info must be non-NULL");
     return DS_EINVAL;

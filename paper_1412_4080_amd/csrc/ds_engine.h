@@ -68,6 +68,8 @@ DeviceCtx& device_ctx(int device);
 
 ds_status validate_problem(const ds_problem* p, bool group);
 ds_status validate_params(const ds_params* p);
+// The Dome test is stated for the Lasso: DS_EINVAL with a grouped problem.
+ds_status validate_test_for(const ds_params* p, bool group);
 
 ds_status solve_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
                        void* x, ds_info* info, hipStream_t stream, Workspace& ws,

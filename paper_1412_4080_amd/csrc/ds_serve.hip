@@ -244,6 +244,7 @@ ds_status submit_impl(void* server, int32_t dict_id, const void* y_host, double 
     return DS_ENOTFOUND;
   }
   const Dict& d = *it->second;
+  if ((e = validate_test_for(params, d.G > 0)) != DS_OK) return e;
   if (static_cast<int64_t>(S->queue.size()) >= S->cfg.max_queue) {
     set_error("request queue full (%d waiting)", S->cfg.max_queue);
     return DS_EBUSY;

@@ -275,7 +275,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
                      RULE == RULE_SPARSA ? prm.bb_memory : 0,
                      prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5);
   DS_HIP(hipGetLastError());
-  if (prm.test == DS_TEST_DST3) {
+  if (prm.test == DS_TEST_DST3 || prm.test == DS_TEST_DOME) {
     hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
                        0, s, a);
     DS_HIP(hipGetLastError());

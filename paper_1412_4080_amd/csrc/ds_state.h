@@ -4,7 +4,7 @@
 
 namespace ds {
 
-enum TestKind { TEST_NONE = 0, TEST_SAFE = 1, TEST_DST3 = 2 };
+enum TestKind { TEST_NONE = 0, TEST_SAFE = 1, TEST_DST3 = 2, TEST_DOME = 3 };
 enum RuleKind { RULE_ISTA = 0, RULE_FISTA = 1, RULE_SPARSA = 2 };
 constexpr int BB_MEM_MAX = 15;  // SpaRSA: earlier iterates kept in the acceptance memory
 

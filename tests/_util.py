@@ -32,6 +32,8 @@ def rel_err(a, b):
 
 def lasso_margins_ref(D, y, lam, test):
     lam_max, i_star = oracle.lambda_max_lasso(D, y)
+    if test == "dome":
+        return oracle.dome_margins(D, y, lam, i_star)
     c, _ = oracle.lasso_center(D, y, lam, test, lam_max, i_star)
     return oracle.lasso_margins(D, c, test)
 

@@ -88,6 +88,24 @@ def test_invalid_sparsa_params_rejected(B, field, value):
     assert st == B.DS_EINVAL, field
 
 
+def test_dome_test_refused_for_groups(B):
+    """The Dome test is stated for the Lasso: a grouped problem is refused before any
+    device work (glasso_solve and the single-signal entry point)."""
+    import numpy as np
+    gp = np.array([0, 10, 20], np.int64)
+    pg = _problem(B, G=2, group_ptr=gp.ctypes.data_as(C.POINTER(C.c_int64)))
+    prm = B.make_params(test="dome")
+    lam = (C.c_double * 1)(0.5)
+    info = (B.Info * 1)()
+    assert B._lib.glasso_solve(C.byref(pg), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                               C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
+    assert "Lasso" in B.last_error()
+    one = B.Info()
+    assert B._lib.ds_solve_one(C.byref(pg), C.c_void_p(0x2000), C.c_double(0.5), C.byref(prm),
+                               C.c_void_p(0x3000), None, None, 0, C.byref(one),
+                               None) == B.DS_EINVAL
+
+
 def test_invalid_lambda_and_groups_rejected(B):
     p = _problem(B)
     prm = B.make_params()

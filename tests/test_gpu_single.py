@@ -61,7 +61,7 @@ def _fixed_iter_parity(B, D, y, dtype, ratio, rule, test, T, tol_x, tol_obj, gro
 
 
 # ------------------------------------------------------------ FP64 small workload
-@pytest.mark.parametrize("test", ["safe", "dst3", "none"])
+@pytest.mark.parametrize("test", ["safe", "dst3", "none", "dome"])
 def test_small_fp64_500_iterations(B, test):
     c = datagen.lasso_small_fp64()
     ref, x, info, tr = _fixed_iter_parity(B, c["D"], c["y"], "f64", 0.5, "ista", test, 500,
@@ -72,7 +72,7 @@ def test_small_fp64_500_iterations(B, test):
 
 # ------------------------------------------------------------ FP32 trajectories
 @pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe"), ("fista", "none"),
-                                       ("ista", "dst3")])
+                                       ("ista", "dst3"), ("fista", "dome")])
 @pytest.mark.parametrize("ratio", [0.2, 0.6, 0.9])
 def test_fp32_fixed_iteration_parity(B, rule, test, ratio):
     D, y = _lasso_case(500, 2500, 5)
@@ -92,13 +92,14 @@ def test_fp32_full_size_trajectory(B):
     assert tr[-1]["n_active"] < 10000  # screening took effect at 0.8 lambda_*
 
 
+@pytest.mark.parametrize("test", ["dst3", "dome"])
 @pytest.mark.parametrize("ratio", [0.1, 0.5, 0.9])
-def test_fp32_solve_to_tolerance_is_certified(B, ratio):
+def test_fp32_solve_to_tolerance_is_certified(B, ratio, test):
     D, y = _lasso_case(400, 2000, 9)
     Di, yi = instance(D, y, "f32")
     L = oracle.spectral_norm_sq(Di)
     Dd, yd = dev_matrix(D, "f32"), dev_vector(yi, "f32")
-    x, info, scr, tr = B.solve_one(Dd, yd, ratio, rule="fista", test="dst3", step_L=L,
+    x, info, scr, tr = B.solve_one(Dd, yd, ratio, rule="fista", test=test, step_L=L,
                                    gap_tol=1e-6, max_iter=20000)
     assert info["status"] == 0 and info["gap"] <= 1e-6 * float(yi @ yi)
     x = x.cpu().numpy().astype(np.float64)
@@ -117,6 +118,48 @@ def test_fp32_solve_to_tolerance_is_certified(B, ratio):
     assert not star.x[scr].any()
     t_lo, t_hi = stop_iteration_bracket(Di, yi, info["lambda_"], L, 1e-6 * float(yi @ yi))
     assert t_lo <= info["iters"] <= t_hi, (info["iters"], t_lo, t_hi)
+
+
+# ------------------------------------------------------------ Dome test
+def _correlated_case(N, K, seed, corr=0.8):
+    """Unit atoms sharing a common direction (where the dome's cut removes most)."""
+    rng = np.random.default_rng(seed)
+    D = corr * rng.standard_normal((N, 1)) + rng.standard_normal((N, K))
+    D /= np.linalg.norm(D, axis=0)
+    y = D[:, :5] @ rng.standard_normal(5) + 0.1 * rng.standard_normal(N)
+    return D, y / np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("ratio", [0.5, 0.8])
+def test_dome_follows_the_oracle_and_screens_at_least_dst3(B, ratio):
+    """FP64 on correlated atoms: the Dome run's active sets per iteration equal the
+    oracle's, and are never larger than the DST3 run's (the dome lies inside DST3's ball)."""
+    D, y = _correlated_case(300, 1500, 41)
+    T = 150
+    ref, x, info, tr = _fixed_iter_parity(B, D, y, "f64", ratio, "fista", "dome", T, 1e-10,
+                                          1e-12)
+    assert [t["n_active"] for t in tr] == [h["n_active"] for h in ref.history]
+    L = oracle.spectral_norm_sq(D)
+    _, _, _, tr3 = B.solve_one(dev_matrix(D, "f64"), dev_vector(y, "f64"), ratio, rule="fista",
+                               test="dst3", step_L=L, gap_tol=0.0, max_iter=T)
+    na_dome = np.array([t["n_active"] for t in tr])
+    na_dst3 = np.array([t["n_active"] for t in tr3])
+    assert np.all(na_dome <= na_dst3)
+
+
+def test_dome_refused_for_groups_and_on_the_batched_path(B):
+    import torch
+    D = datagen.gaussian_dictionary(256, 1000, 15)
+    gp = datagen.contiguous_groups(1000, 10)
+    y, _ = datagen.group_signal(D, gp, 3)
+    with pytest.raises(B.DsError) as e:
+        B.solve_one(dev_matrix(D, "f32"), dev_vector(y, "f32"), 0.5, group_ptr=gp, test="dome")
+    assert e.value.status == B.DS_EINVAL
+    Dd = dev_matrix(D, "bf16")
+    Y = torch.from_numpy(np.stack([y, y]).astype(np.float32)).cuda().T
+    with pytest.raises(B.DsError) as e:
+        B.solve(Dd, Y, [0.5, 0.6], test="dome")
+    assert e.value.status == B.DS_EINVAL
 
 
 # ------------------------------------------------------------ Group-Lasso
@@ -314,7 +357,7 @@ def test_batched_call_matches_single(B):
         assert infos[j]["iters"] == i1["iters"]
 
 
-@pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe")])
+@pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe"), ("fista", "dome")])
 def test_static_screening_parity(B, rule, test):
     """Static mode (the test once, with the first dual point): same iterates, gap and
     screened set as the oracle's static run."""
