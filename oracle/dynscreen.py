@@ -58,6 +58,18 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   atom i is (1 - |d_i^T c|) / ||d_i||, and the DST3 centre is the projection of
   y/lambda onto the hyperplane {theta : d_*^T theta = 1}.  Both reduce to
   Lemmas 1 and 2 for unit atoms.
+* Chambolle-Pock (rule="cp", Table 1): the dual iterate is carried from one iteration to
+  the next, theta_t = (theta_{t-1} + sigma (D u_{t-1} - y)) / (1 + sigma), the primal step
+  is x_t = prox(x_{t-1} - tau D^T theta_t, lambda tau), and u_t = x_t + phi (x_t - x_{t-1})
+  with phi = 1/sqrt(1 + 2 gamma tau), tau <- phi tau, sigma <- sigma / phi.  The paper
+  gives no gamma, tau_0 or sigma_0.  Reading: gamma = cp_gamma, default 0 (the basic
+  method, constant steps, phi = 1); tau_0 = cp_tau, default 1/sqrt(L), and sigma_0 =
+  cp_sigma, default 1/(tau_0 L), so tau sigma L = 1 with L >= ||D||_2^2 (the convergence
+  condition); theta_0 = 0, x_0 = u_0 = 0.  Screening uses theta_t (dual scaling, Lemma 7).
+  The gap certificate pairs theta_t's dual point with P(u_{t-1}) = ||D u_{t-1} - y||^2/2 +
+  lambda Omega(u_{t-1}) (the residual the update already forms), and the solve returns
+  u_{t-1}, the point so certified (x_t carries no such bound).  Screening removes atoms
+  from x and u as for FISTA; theta, an N-vector, is untouched.
 * Dynamic Dome test (the dome lemma of the section on dynamic tests): the region is the
   ball B(y/lambda, ||y/lambda - v_t||) cut by the half-space d_*^T theta <= 1.  The
   printed bounds Q^l, Q^u are those of that region for unit atoms except for their case
@@ -353,7 +365,8 @@ def _bb_step(Dd, d, L):
 
 def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
                 max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic",
-                step="constant", eta=2.0, bb_memory=0, bb_sigma=1e-5) -> OracleResult:
+                step="constant", eta=2.0, bb_memory=0, bb_sigma=1e-5, cp_tau=None,
+                cp_sigma=None, cp_gamma=0.0) -> OracleResult:
     """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
@@ -368,12 +381,14 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     first update does not depend on the atoms that test removes (their prox output is 0).
     step="backtracking" sets L_t by the backtracking rule (module docstring); L is then L_0.
     rule="sparsa" is ISTA with the Barzilai-Borwein step and its acceptance test (module
-    docstring; bb_memory, bb_sigma, eta); L is then L_0.
+    docstring; bb_memory, bb_sigma, eta); L is then L_0.  rule="cp" is Chambolle-Pock
+    (module docstring; cp_tau, cp_sigma, cp_gamma; L >= ||D||_2^2 sets the default steps).
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     N, K = D.shape
-    assert test in ("none", "safe", "dst3", "dome") and rule in ("ista", "fista", "sparsa")
+    assert test in ("none", "safe", "dst3", "dome") and rule in ("ista", "fista", "sparsa", "cp")
+    assert rule != "cp" or (step == "constant" and cp_gamma >= 0.0)
     assert step in ("constant", "backtracking") and eta > 1.0
     assert rule != "sparsa" or (step == "constant" and bb_memory >= 0 and bb_sigma >= 0.0)
     lam_max, i_star = lambda_max_lasso(D, y)
@@ -398,14 +413,26 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     r_min = np.inf
     hist = []
     phis, new_point = [], True                  # SpaRSA: phi at the last M + 1 iterates
+    if rule == "cp":                            # Chambolle-Pock steps and dual iterate
+        tau = float(cp_tau) if cp_tau else 1.0 / np.sqrt(L)
+        sigma = float(cp_sigma) if cp_sigma else 1.0 / (tau * L)
+        theta_cp = np.zeros(N)
     converged = False
     for t in range(1, max_iter + 1):
         # ---- optimisation update (Table 1) ----
-        p = u if rule == "fista" else x
-        theta = Dt @ p - y
-        z = Dt.T @ theta
-        x_new = soft_threshold(p - z / L, lam / L)
-        primal_p = 0.5 * float(theta @ theta) + lam * float(np.abs(p).sum())
+        p = u if rule in ("fista", "cp") else x
+        if rule == "cp":
+            res = Dt @ p - y
+            theta = (theta_cp + sigma * res) / (1.0 + sigma)
+            z = Dt.T @ theta
+            x_new = soft_threshold(x - tau * z, lam * tau)
+            phi = 1.0 / np.sqrt(1.0 + 2.0 * cp_gamma * tau)
+            primal_p = 0.5 * float(res @ res) + lam * float(np.abs(p).sum())
+        else:
+            theta = Dt @ p - y
+            z = Dt.T @ theta
+            x_new = soft_threshold(p - z / L, lam / L)
+            primal_p = 0.5 * float(theta @ theta) + lam * float(np.abs(p).sum())
         accepted = True
         if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
             d = x_new - p
@@ -425,6 +452,9 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         if rule == "fista":
             l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
             u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
+        elif rule == "cp":
+            l_new = l_prev
+            u_new = x_new + phi * (x_new - x)
         else:
             l_new = l_prev
             u_new = x_new
@@ -447,6 +477,8 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
                 hist[-1].update(cand=x_new.copy(), p=p.copy(), active=active.copy())
             if rule == "sparsa":
                 hist[-1].update(phi_new=phi_new, phi_ref=max(phis))
+            if rule == "cp":
+                hist[-1].update(theta=theta.copy(), tau=tau, sigma=sigma, x_prev=x.copy())
         converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
         if not accepted:
             # rejected step: keep p, grow L; at the iteration limit return the last accepted x
@@ -456,6 +488,11 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         elif rule == "sparsa" and not converged and t < max_iter:
             L = _bb_step(Dd, d, L)
         new_point = accepted
+        if rule == "cp":
+            if converged or t == max_iter:
+                x_new = p.copy()        # the point the certificate is about
+            else:
+                theta_cp, tau, sigma = theta, tau * phi, sigma / phi
         if converged or t == max_iter:
             break
         # ---- screening: I_t = {i : T_v(i)} U I_{t-1}, then reduce D and X ----
@@ -488,7 +525,8 @@ def _as_groups(K, groups):
 def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="ista",
                       test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
                       record=False, screening="dynamic", step="constant",
-                      eta=2.0, bb_memory=0, bb_sigma=1e-5) -> OracleResult:
+                      eta=2.0, bb_memory=0, bb_sigma=1e-5, cp_tau=None, cp_sigma=None,
+                      cp_gamma=0.0) -> OracleResult:
     """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
 
     groups: a partition of range(K) (list of index arrays, or contiguous CSR
@@ -496,7 +534,8 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     DGST3 (Lemma 5) or none; the screening unit is the group.  screening="static"
     runs the test once, at the first iteration (the static group tests).  step as in
     solve_lasso (the default L_0 for backtracking and SpaRSA is max_g ||D_g||_2^2);
-    rule="sparsa" as in solve_lasso, with phi the Group-Lasso objective.
+    rule="sparsa" as in solve_lasso, with phi the Group-Lasso objective; rule="cp" as in
+    solve_lasso, with the group shrinkage as the prox.
     """
     D = np.asarray(D, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -504,7 +543,8 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     groups = _as_groups(K, groups)
     G = len(groups)
     w = np.sqrt([len(g) for g in groups]).astype(np.float64) if w is None else np.asarray(w, np.float64)
-    assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista", "sparsa")
+    assert test in ("none", "gsafe", "dgst3") and rule in ("ista", "fista", "sparsa", "cp")
+    assert rule != "cp" or (step == "constant" and cp_gamma >= 0.0)
     assert screening in ("dynamic", "static")
     assert step in ("constant", "backtracking") and eta > 1.0
     assert rule != "sparsa" or (step == "constant" and bb_memory >= 0 and bb_sigma >= 0.0)
@@ -541,15 +581,27 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
     r_min = np.inf
     hist = []
     phis, new_point = [], True
+    if rule == "cp":
+        tau = float(cp_tau) if cp_tau else 1.0 / np.sqrt(L)
+        sigma = float(cp_sigma) if cp_sigma else 1.0 / (tau * L)
+        theta_cp = np.zeros(N)
     converged = False
     for t in range(1, max_iter + 1):
         wa = w[act_g]
-        p = u if rule == "fista" else x
-        theta = Dt @ p - y
-        z = Dt.T @ theta
-        x_new = group_soft_threshold(p - z / L, lam / L, local, wa)
+        p = u if rule in ("fista", "cp") else x
         omega_p = float(sum(wa[j] * np.linalg.norm(p[lg]) for j, lg in enumerate(local)))
-        primal_p = 0.5 * float(theta @ theta) + lam * omega_p
+        if rule == "cp":
+            res = Dt @ p - y
+            theta = (theta_cp + sigma * res) / (1.0 + sigma)
+            z = Dt.T @ theta
+            x_new = group_soft_threshold(x - tau * z, lam * tau, local, wa)
+            phi = 1.0 / np.sqrt(1.0 + 2.0 * cp_gamma * tau)
+            primal_p = 0.5 * float(res @ res) + lam * omega_p
+        else:
+            theta = Dt @ p - y
+            z = Dt.T @ theta
+            x_new = group_soft_threshold(p - z / L, lam / L, local, wa)
+            primal_p = 0.5 * float(theta @ theta) + lam * omega_p
         accepted = True
         if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
             d = x_new - p
@@ -573,6 +625,9 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         if rule == "fista":
             l_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * l_prev * l_prev))
             u_new = x_new + ((l_prev - 1.0) / l_new) * (x_new - x)
+        elif rule == "cp":
+            l_new = l_prev
+            u_new = x_new + phi * (x_new - x)
         else:
             l_new = l_prev
             u_new = x_new
@@ -592,6 +647,8 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
                              r=r, gap=gap, mu=mu, L=L, accepted=accepted, primal_p=primal_p))
             if rule == "sparsa":
                 hist[-1].update(phi_new=phi_new, phi_ref=max(phis))
+            if rule == "cp":
+                hist[-1].update(theta=theta.copy(), tau=tau, sigma=sigma, x_prev=x.copy())
         converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
         if not accepted:
             x_new, u_new, l_new = x, u, l_prev
@@ -600,6 +657,11 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         elif rule == "sparsa" and not converged and t < max_iter:
             L = _bb_step(Dd, d, L)
         new_point = accepted
+        if rule == "cp":
+            if converged or t == max_iter:
+                x_new = p.copy()
+            else:
+                theta_cp, tau, sigma = theta, tau * phi, sigma / phi
         if converged or t == max_iter:
             break
         if screening == "dynamic" or t == 1:

@@ -553,6 +553,111 @@ def test_backtracking_reaches_the_same_optimum(rule, group):
     assert b.primal - b.dual <= b.gap + 1e-15
 
 
+# -------------------------------------------------------------------------- Chambolle-Pock
+@pytest.mark.parametrize("gamma", [0.0, 0.05])
+@pytest.mark.parametrize("group", [False, True])
+def test_cp_reaches_the_same_optimum_and_certifies_its_point(gamma, group):
+    """Chambolle-Pock reaches FISTA's optimum, the point it returns is the one its gap
+    certifies (P(x) - P* <= gap), and screening stays safe."""
+    D, y = _problem(N=70, K=240, seed=301)
+    tol = 1e-10
+    yy = float(y @ y)
+    if group:
+        gp = datagen.contiguous_groups(240, 10)
+        a = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.4, rule="fista", test="none",
+                                     max_iter=200000, gap_tol=1e-13)
+        b = oracle.solve_group_lasso(D, y, gp, lam_ratio=0.4, rule="cp", test="dgst3",
+                                     max_iter=200000, gap_tol=tol, cp_gamma=gamma)
+        _, cert, _ = oracle.certified_inactive_group(D, y, a.lam, a.x, gp)
+        cert = np.repeat(cert, np.diff(gp))
+    else:
+        a = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="fista", test="none", max_iter=200000,
+                               gap_tol=1e-13)
+        b = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="cp", test="dst3", max_iter=200000,
+                               gap_tol=tol, cp_gamma=gamma)
+        cert, _ = oracle.certified_inactive_lasso(D, y, a.lam, a.x)
+    assert a.converged and b.converged
+    assert b.primal - a.primal <= b.gap + 1e-12 * yy
+    assert b.gap <= tol * yy
+    assert np.all(cert[b.screened])
+
+
+@pytest.mark.parametrize("group", [False, True])
+def test_cp_on_a_scaled_orthonormal_dictionary_reaches_the_closed_form(group):
+    """D = c Q (orthonormal columns): the minimiser is the shrinkage of Q^T y / c at
+    lambda / c^2 (lambda w_g / c^2), and Chambolle-Pock converges to it."""
+    N, K, c = 80, 50, 1.4
+    rng = np.random.default_rng(302)
+    Q, _ = np.linalg.qr(rng.standard_normal((N, K)))
+    D = c * Q
+    y = rng.standard_normal(N)
+    b = Q.T @ y / c
+    if group:
+        gp = datagen.contiguous_groups(K, 5)
+        w = np.sqrt(np.diff(gp).astype(float))
+        r = oracle.solve_group_lasso(D, y, gp, w, lam_ratio=0.4, rule="cp", test="none",
+                                     max_iter=100000, gap_tol=1e-14)
+        xs = np.zeros(K)
+        for g in range(gp.size - 1):
+            v = b[gp[g]:gp[g + 1]]
+            nv = np.linalg.norm(v)
+            xs[gp[g]:gp[g + 1]] = v * max(0.0, 1.0 - r.lam * w[g] / (c * c) / nv)
+    else:
+        r = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="cp", test="none", max_iter=100000,
+                               gap_tol=1e-14)
+        xs = np.sign(b) * np.maximum(np.abs(b) - r.lam / (c * c), 0.0)
+    assert r.converged
+    assert np.max(np.abs(r.x - xs)) <= 1e-6 * np.max(np.abs(xs))
+
+
+def test_cp_scalar_trajectory_computed_by_hand():
+    """D = [1], y = 1, lambda = 1/2, tau = sigma = 1 (tau sigma ||D||^2 = 1), gamma = 0.
+    By hand from theta_0 = x_0 = u_0 = 0:
+      t=1: r = -1,   theta = -1/2,  x = S(1/2, 1/2) = 0,      u = 0
+      t=2: r = -1,   theta = -3/4,  x = S(3/4, 1/2) = 1/4,    u = 1/2
+      t=3: r = -1/2, theta = -5/8,  x = S(7/8, 1/2) = 3/8,    u = 1/2
+      t=4: r = -1/2, theta = -9/16, x = S(15/16, 1/2) = 7/16, u = 1/2
+    (S the soft threshold); P(u_{t-1}) = 1/2, 1/2, 3/8, 3/8; the point returned after four
+    iterations is u_3 = 1/2 (the point the last certificate covers), which is also the
+    minimiser S(1, 1/2)."""
+    D = np.ones((1, 1))
+    y = np.ones(1)
+    r = oracle.solve_lasso(D, y, lam=0.5, rule="cp", test="none", L=1.0, cp_tau=1.0,
+                           cp_sigma=1.0, max_iter=4, gap_tol=0.0, record=True)
+    assert [float(h["theta"][0]) for h in r.history] == [-0.5, -0.75, -0.625, -0.5625]
+    assert [float(h["x_prev"][0]) for h in r.history] == [0.0, 0.0, 0.25, 0.375]
+    assert [h["primal_p"] for h in r.history] == [0.5, 0.5, 0.375, 0.375]
+    assert r.iters == 4 and float(r.x[0]) == 0.5
+
+
+def test_cp_dual_iterate_tends_to_the_optimal_residual():
+    """At the optimum the dual variable of this splitting is D x* - y (the optimality
+    conditions of the Lasso): the carried dual iterate converges to it."""
+    D, y = _problem(N=60, K=200, seed=303)
+    a = oracle.solve_lasso(D, y, lam_ratio=0.3, rule="fista", test="none", max_iter=200000,
+                           gap_tol=1e-14)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.3, rule="cp", test="none", max_iter=200000,
+                           gap_tol=1e-12, record=True)
+    th = r.history[-1]["theta"]
+    res = D @ a.x - y
+    assert np.linalg.norm(th - res) <= 1e-4 * np.linalg.norm(res)
+    assert np.linalg.norm(r.history[5]["theta"] - res) > 1e-2 * np.linalg.norm(res)
+
+
+def test_cp_accelerated_steps_follow_the_known_asymptotics():
+    """With gamma > 0, 1/tau_{t+1}^2 = 1/tau_t^2 + 2 gamma / tau_t, so gamma t tau_t -> 1;
+    tau sigma stays at tau_0 sigma_0."""
+    D, y = _problem(N=40, K=120, seed=304)
+    g = 0.5
+    r = oracle.solve_lasso(D, y, lam_ratio=0.5, rule="cp", test="none", max_iter=4000,
+                           gap_tol=0.0, record=True, cp_gamma=g)
+    taus = np.array([h["tau"] for h in r.history])
+    prod = np.array([h["tau"] * h["sigma"] for h in r.history])
+    assert np.allclose(prod, prod[0], rtol=1e-12)
+    t = np.arange(taus.size)
+    assert 0.97 <= g * t[-1] * taus[-1] <= 1.03
+
+
 # -------------------------------------------------------------------------- Dome test
 def test_dome_max_is_attained_and_never_exceeded():
     """dome_max against the region itself: each returned point lies in the ball and the
