@@ -54,7 +54,7 @@ def run_steps(binding, Dd, ys, steps, test, L, lat=None, step="constant", iters=
         yd = ys[s % len(ys)]
         for r in RATIOS:
             t0 = time.perf_counter()
-            own_step = step != "constant" or rule == "sparsa"
+            own_step = step != "constant" or rule == "sparsa"   # CP takes L (its default steps)
             x, info, _, _ = binding.solve_one(Dd, yd, r, rule=rule, test=test,
                                               step_L=0.0 if own_step else L,
                                               gap_tol=GAP_TOL, max_iter=20000, trace=False,
@@ -319,6 +319,26 @@ def dome_leg(binding, Dd, ys, steps, L):
             "mean_active_after_10_iters": act}
 
 
+def cp_leg(binding, Dd, ys, steps, L):
+    """The headline workload with the Chambolle-Pock update of Table 1 (gamma = 0,
+    tau_0 = 1/sqrt(L), sigma_0 = 1/(tau_0 L), L the headline's bound on ||D||_2^2): screened
+    (DST3) and plain solves/s and iterations per solve."""
+    import torch
+    out = {"rule": "cp", "gamma": 0.0, "tau0": "1/sqrt(L)", "sigma0": "1/(tau0 L)"}
+    for test in ("dst3", "none"):
+        run_steps(binding, Dd, ys, 1, test, L, rule="cp")   # warm-up
+        it = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = run_steps(binding, Dd, ys, steps, test, L, iters=it, rule="cp")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "screened" if test == "dst3" else "plain"
+        out[f"{key}_solves_per_s"] = round(n / dt, 3)
+        out[f"{key}_mean_iters"] = round(float(np.mean(it)), 1)
+    return out
+
+
 def sparsa_leg(binding, Dd, ys, steps):
     """The headline workload with SpaRSA (Table 1: ISTA with the Barzilai-Borwein step;
     L_0 the largest squared atom norm, eta = 2, sigma = 1e-5), monotone (memory 0) and
@@ -505,12 +525,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking,sparsa,dome",
+    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking,sparsa,dome,cp",
                     help="comma list of legs: single (headline), batched, served, flops, large "
                          "(correlation roofline on 4096 x 40000 FP32), backtracking (the headline "
                          "workload with backtracking steps), sparsa (the headline workload with "
                          "SpaRSA's Barzilai-Borwein steps), dome (the headline workload with "
-                         "the dynamic Dome test).  Profiling "
+                         "the dynamic Dome test), cp (the headline workload with the "
+                         "Chambolle-Pock update).  Profiling "
                          "helpers (run alone): 'screened' runs only the timed screened "
                          "solves; 'instrumented' only the instrumented single-signal pass "
                          "(no warmup); 'batched-instrumented' only one instrumented "
@@ -623,6 +644,10 @@ def main():
         dm = dome_leg(binding, Dd, ys, args.steps, L)
         dm["over_dst3"] = round(dm["solves_per_s"] / value, 3)
         out["dome"] = dm
+    if "cp" in legs:
+        cp = cp_leg(binding, Dd, ys, args.steps, L)
+        cp["over_constant_step_fista"] = round(cp["screened_solves_per_s"] / value, 3)
+        out["cp"] = cp
     if "sparsa" in legs:
         sp = sparsa_leg(binding, Dd, ys, args.steps)
         sp["over_constant_step_fista"] = round(sp["memory0_screened_solves_per_s"] / value, 3)

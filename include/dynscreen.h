@@ -58,7 +58,15 @@ typedef enum { DS_F64 = 0, DS_F32 = 1, DS_BF16 = 2 } ds_dtype;
  * with the Omega difference taken unit by unit.  A rejected step is undone and L multiplied
  * by bt_eta, as for DS_STEP_BACKTRACK.  Single-signal and served solves; step_rule must be
  * DS_STEP_CONSTANT, and the batched bfloat16 path returns DS_EINVAL. */
-typedef enum { DS_ISTA = 0, DS_FISTA = 1, DS_SPARSA = 2 } ds_rule;
+typedef enum { DS_ISTA = 0, DS_FISTA = 1, DS_SPARSA = 2, DS_CP = 3 } ds_rule;
+/* DS_CP is the Chambolle-Pock update of Table 1: the dual iterate is carried,
+ * theta_t = (theta_{t-1} + sigma (D u_{t-1} - y)) / (1 + sigma), x_t = prox(x_{t-1} -
+ * tau D^T theta_t, lambda tau), u_t = x_t + phi (x_t - x_{t-1}) with phi = 1/sqrt(1 +
+ * 2 gamma tau), then tau <- phi tau, sigma <- sigma / phi (cp_tau, cp_sigma, cp_gamma).
+ * The screening and the gap use theta_t's dual point; the gap's primal point is u_{t-1},
+ * and that point is what the solve returns.  Single-signal and served solves; step_rule
+ * must be DS_STEP_CONSTANT (step_L is the bound L >= ||D||_2^2 that sets the default
+ * steps), and the batched bfloat16 path returns DS_EINVAL. */
 
 /* Screening test.  For Group-Lasso problems SAFE means GSAFE (Lemma 4) and DST3 means
  * DGST3 (Lemma 5).  DS_TEST_DOME is the dynamic Dome test (the dome lemma: the SAFE ball
@@ -113,6 +121,11 @@ typedef struct {
   int32_t bb_memory; /* DS_SPARSA: earlier iterates in the acceptance memory, 0..15
                         (0: monotone) */
   double bb_sigma;   /* DS_SPARSA: sufficient-decrease constant, >= 0; 0 selects 1e-5 */
+  double cp_tau;     /* DS_CP: initial primal step tau_0 > 0; 0 selects 1/sqrt(L) */
+  double cp_sigma;   /* DS_CP: initial dual step sigma_0 > 0; 0 selects 1/(tau_0 L).  The
+                        method needs tau_0 sigma_0 ||D||_2^2 <= 1 (checked against step_L
+                        when both steps and step_L are given) */
+  double cp_gamma;   /* DS_CP: acceleration gamma >= 0 (0: constant steps) */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which

@@ -22,7 +22,7 @@ _lib = C.CDLL(LIB_PATH)
 DS_OK, DS_PENDING, DS_NOT_CONVERGED = 0, 1, 2
 DS_EINVAL, DS_ENOMEM, DS_EDEVICE, DS_ENOTFOUND, DS_EBUSY = -1, -2, -3, -4, -5
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
-RULES = {"ista": 0, "fista": 1, "sparsa": 2}
+RULES = {"ista": 0, "fista": 1, "sparsa": 2, "cp": 3}
 TESTS = {"none": 0, "safe": 1, "dst3": 2, "gsafe": 1, "dgst3": 2, "dome": 3}
 STATUS_NAMES = {0: "DS_OK", 1: "DS_PENDING", 2: "DS_NOT_CONVERGED", -1: "DS_EINVAL",
                 -2: "DS_ENOMEM", -3: "DS_EDEVICE", -4: "DS_ENOTFOUND", -5: "DS_EBUSY"}
@@ -40,7 +40,8 @@ class Params(C.Structure):
     _fields_ = [("rule", C.c_int), ("test", C.c_int), ("lambda_mode", C.c_int),
                 ("step_L", C.c_double), ("gap_tol", C.c_double), ("max_iter", C.c_int32),
                 ("screening", C.c_int32), ("step_rule", C.c_int32), ("bt_eta", C.c_double),
-                ("bb_memory", C.c_int32), ("bb_sigma", C.c_double)]
+                ("bb_memory", C.c_int32), ("bb_sigma", C.c_double), ("cp_tau", C.c_double),
+                ("cp_sigma", C.c_double), ("cp_gamma", C.c_double)]
 
 
 class Info(C.Structure):
@@ -178,16 +179,17 @@ SCREENING = {"dynamic": 0, "static": 1}
 
 def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap_tol=1e-6,
                 max_iter=10000, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-                bb_sigma=0.0):
+                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
     return Params(RULES[rule], TESTS[test], 1 if lambda_relative else 0, float(step_L),
                   float(gap_tol), int(max_iter), SCREENING[screening], STEPS[step], float(bt_eta),
-                  int(bb_memory), float(bb_sigma))
+                  int(bb_memory), float(bb_sigma), float(cp_tau), float(cp_sigma),
+                  float(cp_gamma))
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
           lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
           screened=False, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-          bb_sigma=0.0):
+          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
@@ -215,7 +217,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     infos = (Info * B)()
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
-                      bb_memory, bb_sigma)
+                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma)
     if screened:
         if group_ptr is not None:
             raise ValueError("screened masks of batched solves are for the Lasso")
@@ -237,7 +239,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
 def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="dst3",
               lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, trace=True,
               screened=True, stream=None, screening="dynamic", step="constant", bt_eta=0.0,
-              bb_memory=0, bb_sigma=0.0):
+              bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
     """Single-signal solve returning (x, info, screened_mask or None, trace list or None)."""
     torch = _torch()
     K = D.shape[1]
@@ -251,7 +253,7 @@ def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="ds
     info = Info()
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
-                      bb_memory, bb_sigma)
+                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma)
     st = _lib.ds_solve_one(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam), C.byref(prm),
                            C.c_void_p(x.data_ptr()),
                            C.c_void_p(scr.data_ptr()) if scr is not None else None,
@@ -320,13 +322,13 @@ class Server:
 
     def submit(self, dict_id, y_host, lam, *, rule="fista", test="dst3", lambda_relative=True,
                step_L=0.0, gap_tol=1e-6, max_iter=10000, screening="dynamic", step="constant",
-               bt_eta=0.0, bb_memory=0, bb_sigma=0.0):
+               bt_eta=0.0, bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
         import numpy as np
         N, K, dt, store = self._dicts[dict_id]
         y = np.ascontiguousarray(y_host, dtype=np.float64 if store == 0 else np.float32)
         assert y.size == N
         prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step,
-                          bt_eta, bb_memory, bb_sigma)
+                          bt_eta, bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma)
         rid = C.c_uint64()
         st = _lib.lasso_submit(self._h, int(dict_id), y.ctypes.data_as(C.c_void_p), float(lam),
                                C.byref(prm), C.byref(rid))

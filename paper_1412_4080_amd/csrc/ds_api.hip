@@ -132,7 +132,7 @@ ds_status validate_problem(const ds_problem* p, bool group) {
 
 ds_status validate_params(const ds_params* p) {
   if (p == nullptr) { set_error("params is NULL"); return DS_EINVAL; }
-  if (p->rule != DS_ISTA && p->rule != DS_FISTA && p->rule != DS_SPARSA) {
+  if (p->rule != DS_ISTA && p->rule != DS_FISTA && p->rule != DS_SPARSA && p->rule != DS_CP) {
     set_error("unknown rule");
     return DS_EINVAL;
   }
@@ -156,6 +156,23 @@ ds_status validate_params(const ds_params* p) {
   if (p->rule == DS_SPARSA && p->step_rule != DS_STEP_CONSTANT) {
     set_error("DS_SPARSA sets its own step: step_rule must be DS_STEP_CONSTANT");
     return DS_EINVAL;
+  }
+  if (p->rule == DS_CP) {
+    if (p->step_rule != DS_STEP_CONSTANT) {
+      set_error("DS_CP sets its own steps: step_rule must be DS_STEP_CONSTANT");
+      return DS_EINVAL;
+    }
+    const double prm[3] = {p->cp_tau, p->cp_sigma, p->cp_gamma};
+    for (double v : prm)
+      if (!(v >= 0.0) || !std::isfinite(v)) {
+        set_error("cp_tau, cp_sigma and cp_gamma must be finite and >= 0");
+        return DS_EINVAL;
+      }
+    if (p->cp_tau > 0.0 && p->cp_sigma > 0.0 && p->step_L > 0.0 &&
+        p->cp_tau * p->cp_sigma * p->step_L > 1.0 + 1e-12) {
+      set_error("cp_tau * cp_sigma * step_L must be <= 1");
+      return DS_EINVAL;
+    }
   }
   const bool line_search = p->step_rule == DS_STEP_BACKTRACK || p->rule == DS_SPARSA;
   if (line_search && p->bt_eta != 0.0 && !(p->bt_eta > 1.0 && std::isfinite(p->bt_eta))) {
@@ -214,8 +231,9 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
       set_error("the Dome test is available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
     }
-    if (params->step_rule == DS_STEP_BACKTRACK || params->rule == DS_SPARSA) {
-      set_error("backtracking and SpaRSA steps are available on the single-signal path (B = 1 or FP32/FP64 D)");
+    if (params->step_rule == DS_STEP_BACKTRACK || params->rule == DS_SPARSA ||
+        params->rule == DS_CP) {
+      set_error("backtracking, SpaRSA and Chambolle-Pock are available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
     }
     return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, screened, s);

@@ -23,7 +23,7 @@ struct Layout {
       off_partial, off_z0, off_g, off_nu, off_fro, off_gnorm, off_marg, off_nvec, off_segcnt,
       off_segatom, off_segval, off_urm, off_uro, off_urn, off_bp0, off_bpi, off_rtn, off_omp,
       off_rtcnt, off_lba, off_cnt, off_gptr, off_w, off_tele, off_kclk, off_spans, off_pv, off_pw,
-      off_pz, off_pd, off_segxo, off_segpo, off_segd, off_uromo, off_urdn, off_bpd, off_dtn, total;
+      off_pz, off_pd, off_segxo, off_segpo, off_segd, off_uromo, off_urdn, off_bpd, off_dtn, off_rtr, total;
   int64_t npad, grid_corr, nsg;
 };
 
@@ -77,6 +77,7 @@ Layout make_layout(int64_t N, int64_t K, int64_t G, size_t vsz, size_t asz, int6
   l.off_uromo = take(l.grid_corr * ucap * 8);
   l.off_urdn = take(l.grid_corr * ucap * 8);
   l.off_bpd = take(2 * MAXB * 8);  // ||d||^2, then the SpaRSA partials
+  l.off_rtr = take(2 * MAXRT * 8);  // Chambolle-Pock ||D u - y||^2 per row tile
   l.off_dtn = take(MAXRT * 8);
   l.off_rtn = take(2 * 2 * MAXRT * 8);
   l.off_omp = take(2 * MAXITEM * 8);
@@ -158,6 +159,7 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.urec_dn = reinterpret_cast<double*>(base + l.off_urdn);
   a.bpd = reinterpret_cast<double*>(base + l.off_bpd);
   a.bpe = a.bpd + MAXB;
+  a.rtr = reinterpret_cast<double*>(base + l.off_rtr);
   a.dtn = reinterpret_cast<double*>(base + l.off_dtn);
   a.rtn = reinterpret_cast<double*>(base + l.off_rtn);
   a.omp = reinterpret_cast<double*>(base + l.off_omp);
@@ -250,13 +252,17 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   // L: given, or estimated here (slow path); backtracking and SpaRSA start from step_L
   // when given, else from a bound the setup kernel computes on the device.  Both use the
   // step check and undo machinery (a.bt).
-  const bool bt = prm.step_rule == DS_STEP_BACKTRACK || RULE == RULE_SPARSA;
-  const double eta = bt ? (prm.bt_eta > 0.0 ? prm.bt_eta : 2.0) : 0.0;
+  // Chambolle-Pock uses the slot copies too (to return the certified point at the stop),
+  // but no step check
+  const bool line_search = prm.step_rule == DS_STEP_BACKTRACK || RULE == RULE_SPARSA;
+  const bool bt = line_search || RULE == RULE_CP;
+  const double eta = line_search ? (prm.bt_eta > 0.0 ? prm.bt_eta : 2.0) : 0.0;
   a.bt = bt ? 1 : 0;
   DS_HIP(hipMemsetAsync(a.bpd, 0, 2 * MAXB * 8, s));
+  DS_HIP(hipMemsetAsync(a.rtr, 0, 2 * MAXRT * 8, s));
   DS_HIP(hipMemsetAsync(a.dtn, 0, MAXRT * 8, s));
   double L = prm.step_L;
-  if (!(L > 0.0) && !bt) {
+  if (!(L > 0.0) && !line_search) {
     // the power iteration uses its own (larger) workspace; keep ours intact by running it
     // on a private one
     Workspace tmp;
@@ -266,6 +272,9 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     tmp.release();
     if (e != DS_OK) return e;
   }
+  // Chambolle-Pock steps: tau_0 sigma_0 L = 1 by default
+  const double cp_tau = prm.cp_tau > 0.0 ? prm.cp_tau : (L > 0.0 ? 1.0 / std::sqrt(L) : 1.0);
+  const double cp_sigma = prm.cp_sigma > 0.0 ? prm.cp_sigma : (L > 0.0 ? 1.0 / (cp_tau * L) : 1.0);
   const double u_round = sizeof(A) == 4 ? 0x1p-24 : 0x1p-53;
   const double kchain = std::ceil(static_cast<double>(P.N) / WAVE) + Store<T>::VEC + 8;
   const double gamma_z = kchain * u_round / (1.0 - kchain * u_round);
@@ -273,7 +282,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, lam,
                      relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z, eta,
                      RULE == RULE_SPARSA ? prm.bb_memory : 0,
-                     prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5);
+                     prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5, cp_tau, cp_sigma, prm.cp_gamma);
   DS_HIP(hipGetLastError());
   if (prm.test == DS_TEST_DST3 || prm.test == DS_TEST_DOME) {
     hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
@@ -368,7 +377,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     for (int k = 0; k < nrun; ++k) {
       ++t;
       launch_corr(t % 2);
-      if (bt) launch_dcheck(t % 2);
+      if (line_search) launch_dcheck(t % 2);
       launch_resid((t + 1) % 2);
       last_par = (t + 1) % 2;
     }
@@ -462,6 +471,9 @@ ds_status dispatch_rule(const ds_problem& P, const void* y, double lam, const ds
   if (prm.rule == DS_SPARSA)
     return vec ? run_single<T, true, RULE_SPARSA>(P, y, lam, prm, x, info, s, ws, tele, scr)
                : run_single<T, false, RULE_SPARSA>(P, y, lam, prm, x, info, s, ws, tele, scr);
+  if (prm.rule == DS_CP)
+    return vec ? run_single<T, true, RULE_CP>(P, y, lam, prm, x, info, s, ws, tele, scr)
+               : run_single<T, false, RULE_CP>(P, y, lam, prm, x, info, s, ws, tele, scr);
   return vec ? run_single<T, true, RULE_ISTA>(P, y, lam, prm, x, info, s, ws, tele, scr)
              : run_single<T, false, RULE_ISTA>(P, y, lam, prm, x, info, s, ws, tele, scr);
 }
@@ -504,7 +516,7 @@ ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t
                                : launch_setup_corr<T, false>(P, y, base, l, s);
   if (e != DS_OK) return e;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, 1.0, 1, 1.0, 0.0,
-                     1, 0.0, 0.0, 0, 1e-5);
+                     1, 0.0, 0.0, 0, 1e-5, 1.0, 1.0, 0.0);
   DS_HIP(hipGetLastError());
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));

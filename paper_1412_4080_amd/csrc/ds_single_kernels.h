@@ -435,7 +435,9 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
                                                          int lam_relative, double L,
                                                          double gap_tol, int max_iter,
                                                          double gamma_z, double bt_eta,
-                                                         int bb_mem, double bb_sigma) {
+                                                         int bb_mem, double bb_sigma,
+                                                         double cp_tau, double cp_sigma,
+                                                         double cp_gamma) {
   __shared__ double sd[CNW];
   __shared__ int si[CNW];
   __shared__ double s_lmax;
@@ -544,6 +546,9 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     st->bb_pad = 0;
     st->bb_sigma = bb_sigma;
     for (int j = 0; j <= BB_MEM_MAX; ++j) st->phi_mem[j] = 0.0;
+    st->cp_tau = cp_tau;
+    st->cp_sigma = cp_sigma;
+    st->cp_gamma = cp_gamma;
     st->yy = yy;
     st->alpha = alpha;
     st->nn = nn;
@@ -734,14 +739,15 @@ struct IterScalars {
   bool stop;
 };
 __device__ inline IterScalars iter_scalars(const SolverState& s, int N, int test, int t,
-                                           double tt, double ty, double omega, double zsup) {
+                                           double tt, double ty, double omega, double zsup,
+                                           double pp) {
   IterScalars o;
   const double lam = s.lam, yy = s.yy, rho2 = s.rho2;
   const double sb = zsup > 0.0 ? 1.0 / zsup : dinf();
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
   o.mu = mu;
-  o.primal = 0.5 * tt + lam * omega;
+  o.primal = 0.5 * pp + lam * omega;  // pp = ||D p - y||^2 (= tt unless theta is carried)
   o.dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
   o.gap = o.primal - o.dual;
   const double a1 = yy / (lam * lam), a2 = 2.0 * mu * ty / lam, a3 = mu * mu * tt;
@@ -758,13 +764,17 @@ __device__ inline IterScalars iter_scalars(const SolverState& s, int N, int test
   return o;
 }
 
-template <typename T, typename V, bool VECTOR>
+// Row tile rt of the residual: r = D p - y from the items' partials.  theta = r, except for
+// Chambolle-Pock (CP), where the dual iterate is carried: theta = (theta_prev + sigma r) /
+// (1 + sigma) (theta_prev = 0 at the first pass) and ||r||^2 is published for the primal
+// objective.  Publishes ||theta||^2 and theta^T y per row tile.
+template <typename T, typename V, bool VECTOR, bool CP = false>
 __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitems_rt,
-                                  double* sd) {
+                                  double* sd, double sigma = 0.0, bool first = false) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
   constexpr int RT = WAVE * VR;
   constexpr int FB = 32;  // item partials loaded at once
-  double tt = 0.0, ty = 0.0;
+  double tt = 0.0, ty = 0.0, rr = 0.0;
   const int r_end = min((rt + 1) * RT, a.N);
   for (int r = rt * RT + static_cast<int>(threadIdx.x); r < r_end; r += BLK) {
     const double yv = static_cast<double>(a.y[r]);
@@ -779,7 +789,13 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitem
 #pragma unroll
       for (int k = 0; k < FB; ++k) s += c + k < nitems_rt ? v[k] : 0.0;
     }
-    const V th = static_cast<V>(s - yv);
+    double res = s - yv;
+    if constexpr (CP) {
+      rr = fma(res, res, rr);
+      const double prev = first ? 0.0 : static_cast<double>(a.theta[r]);
+      res = fma(sigma, res, prev) / (1.0 + sigma);
+    }
+    const V th = static_cast<V>(res);
     a.theta[r] = th;
     const double thd = static_cast<double>(th);
     tt = fma(thd, thd, tt);
@@ -787,10 +803,12 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitem
   }
   tt = block_sum<double, NW>(tt, sd);
   ty = block_sum<double, NW>(ty, sd);
+  if constexpr (CP) rr = block_sum<double, NW>(rr, sd);
   if (threadIdx.x == 0) {
     double* rtn = a.rtn + a.par * (2 * MAXRT);
     rtn[2 * rt] = tt;  // read by the next kernels only
     rtn[2 * rt + 1] = ty;
+    if constexpr (CP) a.rtr[a.par * MAXRT + rt] = rr;
     a.rt_cnt[rt] = 0u;  // every item of this tile has arrived: re-arm
   }
 }
@@ -897,7 +915,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   __shared__ int scan[NW];
   __shared__ int s_last;
   __shared__ SolverState S;
-  __shared__ double red8[NW][RULE == RULE_SPARSA ? 11 : 10];
+  __shared__ double red8[NW][(RULE == RULE_SPARSA || RULE == RULE_CP) ? 11 : 10];
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   const SolverState* sin = a.st + (1 - a.par);
   SolverState* sout = a.st + a.par;
@@ -949,7 +967,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   const int32_t sword = reinterpret_cast<const int32_t*>(sin)[min(tid, NWORDS - 1)];
   // zs nz kt ns at tt ty om; backtracking: ||d||^2 ||D d||^2; SpaRSA: the correlation
   // pass's part of phi(x') - phi(p)
-  constexpr int NV = RULE == RULE_SPARSA ? 11 : 10;
+  constexpr int NV = (RULE == RULE_SPARSA || RULE == RULE_CP) ? 11 : 10;
   double v[NV] = {};
   const double* rtp = a.rtn + (1 - a.par) * (2 * MAXRT);
   const double* omp = a.omp + (1 - a.par) * MAXITEM;
@@ -968,6 +986,8 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   }
   const int kr = min(tid, nrt - 1), ko = min(tid, nsg - 1);
   const double q5 = rtp[2 * kr], q6 = rtp[2 * kr + 1], q7 = omp[ko], q9 = a.dtn[kr];
+  double q10 = 0.0;  // Chambolle-Pock: ||D u - y||^2 of the row tile
+  if constexpr (RULE == RULE_CP) q10 = a.rtr[(1 - a.par) * MAXRT + kr];
   SlotRaw raw[SPT];
   if (static_cast<int>(blockIdx.x) < nitems) load_slots(blockIdx.x, raw);
 #pragma unroll
@@ -985,6 +1005,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   v[6] += tid < nrt ? q6 : 0.0;
   v[7] += tid < nsg ? q7 : 0.0;
   v[9] += tid < nrt ? q9 : 0.0;
+  if constexpr (RULE == RULE_CP) v[NV - 1] += tid < nrt ? q10 : 0.0;
   // larger grids: the remaining partials, in the same order
   for (int b = PB * BLK + tid; b < a.grid_corr; b += BLK) {
     v[0] = fmax(v[0], a.bp0[b]);
@@ -999,6 +1020,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     v[5] += rtp[2 * k];
     v[6] += rtp[2 * k + 1];
     v[9] += a.dtn[k];
+    if constexpr (RULE == RULE_CP) v[NV - 1] += a.rtr[(1 - a.par) * MAXRT + k];
   }
   for (int k = BLK + tid; k < nsg; k += BLK) v[7] += omp[k];
   if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = sword;
@@ -1032,11 +1054,13 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     // rounding-safe bound of the largest correlation (FP64 accumulation of exact products)
     const double zs = v[0] + S.gamma_z * sqrt(tt) * S.kappa_z;
     const int t = S.iter + 1;
-    const IterScalars o = iter_scalars(S, a.N, a.test, t, tt, ty, om, zs);
+    // the primal objective's data term: ||theta||^2, or for Chambolle-Pock ||D u - y||^2
+    const IterScalars o = iter_scalars(S, a.N, a.test, t, tt, ty, om, zs,
+                                       RULE == RULE_CP ? v[NV - 1] : tt);
     // backtracking: the step of this iteration is kept when ||D d||^2 <= L ||d||^2 (the
     // descent condition F(x') <= Q_L(x', p) for the quadratic data term); the stop needs
     // an accepted step, except at the iteration limit
-    bool rej = a.bt && !(v[9] <= S.L * v[8]);
+    bool rej = a.bt && RULE != RULE_CP && !(v[9] <= S.L * v[8]);
     if constexpr (RULE == RULE_SPARSA) {
       // SpaRSA: the memory takes phi(p) (a new entry when p is a new iterate, else it
       // replaces the newest); the step is kept when phi(x') - phi(p) = z^T d + ||D d||^2 / 2
@@ -1092,6 +1116,16 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
         ++S.n_reject;
         if (!stop) S.L *= S.bt_eta;
       }
+      if constexpr (RULE == RULE_CP) {
+        // the certified point is u_{t-1}: at the stop the update of this iteration is undone
+        // (x and u back to the slot copies) and u is returned; otherwise the steps advance
+        S.rejected = stop ? 1 : 0;
+        if (!stop) {
+          const double phi = 1.0 / sqrt(1.0 + 2.0 * S.cp_gamma * S.cp_tau);
+          S.cp_tau *= phi;
+          S.cp_sigma /= phi;
+        }
+      }
       if (stop) {
         S.done = 1;
       } else if (o.r_safe < S.r_scr && (!a.screen_static || t == 1)) {
@@ -1141,7 +1175,8 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   const double r_keep = S.r_scr + S.marg_slack;
   const bool have_support = S.iter > 0;  // p_0 = 0
   if (!have_support) {  // theta = -y, Omega(p_0) = 0
-    if (static_cast<int>(blockIdx.x) < nrt) resid_finish_tile<T, V, VECTOR>(a, blockIdx.x, 0, sd);
+    if (static_cast<int>(blockIdx.x) < nrt)
+      resid_finish_tile<T, V, VECTOR, RULE == RULE_CP>(a, blockIdx.x, 0, sd, S.cp_sigma, true);
     if (blockIdx.x == 0)
       for (int k = tid; k < nsg; k += BLK) a.omp[a.par * MAXITEM + k] = 0.0;
     return;
@@ -1233,7 +1268,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       }
     }
     if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nsg), &s_last))
-      resid_finish_tile<T, V, VECTOR>(a, rt, nsg, sd);
+      resid_finish_tile<T, V, VECTOR, RULE == RULE_CP>(a, rt, nsg, sd, S.cp_sigma, false);
     __syncthreads();
   }
 }
@@ -1474,10 +1509,13 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   if (tid == 0) a.seg_cnt[vb] = nk;
 
   const double lam = st->lam, L = st->L;
-  const double invL = 1.0 / L, thr = lam / L;
+  // Chambolle-Pock: step tau instead of 1/L, prox from x_{t-1}, extrapolation weight phi
+  const double invL = RULE == RULE_CP ? st->cp_tau : 1.0 / L;
+  const double thr = RULE == RULE_CP ? lam * invL : lam / L;
   const double l_prev = st->l_prev;
   double beta = 0.0;
   if (RULE == RULE_FISTA) beta = (l_prev - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev)));
+  if (RULE == RULE_CP) beta = 1.0 / sqrt(1.0 + 2.0 * st->cp_gamma * st->cp_tau);
   double zsup = 0.0;  // max |z_i| (Lasso) or max ||z_g|| / w_g; rounding slack added later
   int nnz = 0, nsup = 0, natoms = 0;
   double dd = 0.0;    // backtracking: ||x' - p||^2 over this block's units
@@ -1500,10 +1538,10 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
       for (int c = 0; c < CPW; ++c) acc[c] = wave_sum(acc[c]);
       if (lane < nc) {
         const double z = pick(acc, lane);
-        const double vv = p - z * invL;
+        const double vv = (RULE == RULE_CP ? xo : p) - z * invL;
         const double mag = fabs(vv) - thr;
         const double xn = mag > 0.0 ? copysign(mag, vv) : 0.0;
-        const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo) : xn;
+        const double un = (RULE == RULE_FISTA || RULE == RULE_CP) ? xn + beta * (xn - xo) : xn;
         const V xs = static_cast<V>(xn), us = static_cast<V>(un);
         a.x[i_l] = xs;
         a.u[i_l] = us;
@@ -1561,7 +1599,7 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
               if (b0 + c == lane + s * WAVE) {
-                vreg[s] = p[s] - acc[c] * invL;
+                vreg[s] = (RULE == RULE_CP ? xo[s] : p[s]) - acc[c] * invL;
                 if constexpr (RULE == RULE_SPARSA) zk[s] = acc[c];
               }
           }
@@ -1582,7 +1620,8 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
         const int ak = lane + s * WAVE;  // atom of the group
         if (ak < m) {
           const double xn = scale * vreg[s];
-          const double un = RULE == RULE_FISTA ? xn + beta * (xn - xo[s]) : xn;
+          const double un =
+              (RULE == RULE_FISTA || RULE == RULE_CP) ? xn + beta * (xn - xo[s]) : xn;
           const V xs = static_cast<V>(xn), us = static_cast<V>(un);
           a.x[a0 + ak] = xs;
           a.u[a0 + ak] = us;
@@ -1707,10 +1746,11 @@ __global__ __launch_bounds__(BLK) void k_scatter_out(SingleArgs<T, V, A> a, V* _
   if (st->status != 0 || j >= st->n_active) return;
   const int unit = a.act[st->cur][j];
   if (a.marg[unit] > st->r_scr + st->marg_slack) return;  // screened, not yet compacted away
+  const V* src = a.rule == RULE_CP ? a.u : a.x;  // Chambolle-Pock returns u (certified)
   if (a.G > 0) {
-    for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) X[i] = a.x[i];
+    for (int64_t i = a.gptr[unit]; i < a.gptr[unit + 1]; ++i) X[i] = src[i];
   } else {
-    X[unit] = a.x[unit];
+    X[unit] = src[unit];
   }
 }
 

@@ -5,7 +5,7 @@
 namespace ds {
 
 enum TestKind { TEST_NONE = 0, TEST_SAFE = 1, TEST_DST3 = 2, TEST_DOME = 3 };
-enum RuleKind { RULE_ISTA = 0, RULE_FISTA = 1, RULE_SPARSA = 2 };
+enum RuleKind { RULE_ISTA = 0, RULE_FISTA = 1, RULE_SPARSA = 2, RULE_CP = 3 };
 constexpr int BB_MEM_MAX = 15;  // SpaRSA: earlier iterates kept in the acceptance memory
 
 // Every scalar of the iteration lives in device memory so that a whole chunk of
@@ -61,6 +61,8 @@ struct alignas(16) SolverState {
   int32_t bb_pad;
   double bb_sigma;     // sufficient-decrease constant
   double phi_mem[BB_MEM_MAX + 1];
+  // Chambolle-Pock: current primal and dual steps, acceleration
+  double cp_tau, cp_sigma, cp_gamma;
 };
 
 template <typename T, typename V, typename A>
@@ -119,6 +121,7 @@ struct SingleArgs {
   double* urec_dn;       // UCAP unit records per block: ||d_unit||^2
   double* bpd;           // ||d||^2 per correlation block
   double* bpe;           // SpaRSA: z^T d + lambda (Omega(x') - Omega(p)) per correlation block
+  double* rtr;           // Chambolle-Pock: 2 x MAXRT, per row tile ||D u - y||^2, [parity]
   double* dtn;           // ||D d||^2 per row tile (the check pass)
 };
 

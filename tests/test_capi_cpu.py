@@ -88,6 +88,31 @@ def test_invalid_sparsa_params_rejected(B, field, value):
     assert st == B.DS_EINVAL, field
 
 
+@pytest.mark.parametrize("field,value", [("cp_tau", -1.0), ("cp_sigma", float("inf")),
+                                         ("cp_gamma", -0.5), ("step_rule", 1)])
+def test_invalid_cp_params_rejected(B, field, value):
+    """Chambolle-Pock: steps and gamma finite and >= 0, no separate step rule."""
+    p = _problem(B)
+    prm = B.make_params(rule="cp")
+    setattr(prm, field, value)
+    lam = (C.c_double * 1)(0.5)
+    info = (B.Info * 1)()
+    assert B._lib.lasso_solve(C.byref(p), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                              C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
+
+
+def test_cp_steps_checked_against_the_given_bound(B):
+    """tau sigma L > 1 with all three given is refused (the method needs tau sigma ||D||^2
+    <= 1)."""
+    p = _problem(B)
+    prm = B.make_params(rule="cp", step_L=4.0, cp_tau=0.6, cp_sigma=0.5)
+    lam = (C.c_double * 1)(0.5)
+    info = (B.Info * 1)()
+    assert B._lib.lasso_solve(C.byref(p), C.c_void_p(0x2000), 1, 10, lam, C.byref(prm),
+                              C.c_void_p(0x3000), 20, info, None) == B.DS_EINVAL
+    assert "cp_tau * cp_sigma" in B.last_error()
+
+
 def test_dome_test_refused_for_groups(B):
     """The Dome test is stated for the Lasso: a grouped problem is refused before any
     device work (glasso_solve and the single-signal entry point)."""
