@@ -93,6 +93,11 @@ typedef struct {
   const double* w;           /* host, G positive weights; NULL means w_g = sqrt(|g|) */
 } ds_problem;
 
+/* Screening mode: DS_DYNAMIC runs the test at every iteration (Algorithm 3); DS_STATIC
+ * runs it once, with the dual point of the first iteration (Algorithms 1 and 4: the static
+ * SAFE / ST3 / Dome rules). */
+typedef enum { DS_DYNAMIC = 0, DS_STATIC = 1 } ds_mode;
+
 /* Step size L_t of the proximal update (Table 1). */
 typedef enum { DS_STEP_CONSTANT = 0, DS_STEP_BACKTRACK = 1 } ds_step_rule;
 
@@ -107,7 +112,7 @@ typedef struct {
   double gap_tol;    /* > 0: stop once the duality-gap certificate <= gap_tol * ||y||^2.
                         0: run exactly max_iter iterations. */
   int32_t max_iter;  /* >= 1 */
-  int32_t screening; /* 0: dynamic (Algorithm 3: the test is re-run at every iteration).
+  ds_mode screening; /* 0: dynamic (Algorithm 3: the test is re-run at every iteration).
                         1: static (Algorithms 1 and 4: the test is run once, with the dual
                         point of the first iteration, i.e. the static SAFE / ST3 rules). */
   int32_t step_rule; /* ds_step_rule.  DS_STEP_BACKTRACK: the rule of Beck and Teboulle that
