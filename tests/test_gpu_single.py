@@ -175,6 +175,33 @@ def test_group_fp32_fixed_iteration_parity(B, rule, test, ratio):
 
 
 @pytest.mark.parametrize("ratio", [0.3, 0.7])
+def test_group_full_size_workload(B, ratio):
+    """The Group-Lasso configuration at full size: 2000 x 10000 FP32, 1000 contiguous groups
+    of 10 (w_g = sqrt(10)), ISTA with the dynamic group sphere test.  A 30-iteration
+    trajectory matches the oracle's; the solve to gap 1e-6 is checked by a certificate the
+    oracle computes from the returned x alone (no full-size oracle solve): its duality gap,
+    and every screened atom provably inactive."""
+    D = datagen.gaussian_dictionary(2000, 10000, 0)
+    gp = datagen.contiguous_groups(10000, 10)
+    y, _ = datagen.group_signal(D, gp, 0)
+    w = np.sqrt(10.0) * np.ones(1000)
+    _fixed_iter_parity(B, D, y, "f32", ratio, "ista", "safe", 30, 1e-5, 1e-6, group=(gp, w))
+    Di, yi = instance(D, y, "f32")
+    L = oracle.spectral_norm_sq(Di)
+    x, info, scr, _ = B.solve_one(dev_matrix(D, "f32"), dev_vector(yi, "f32"), ratio,
+                                  group_ptr=gp, rule="ista", test="safe", step_L=L,
+                                  gap_tol=1e-6, max_iter=50000, trace=False)
+    assert info["status"] == 0 and info["gap"] <= 1e-6 * float(yi @ yi)
+    xs = x.cpu().numpy().astype(np.float64)
+    amask, gmask, gap_x = oracle.certified_inactive_group(Di, yi, info["lambda_"], xs, gp)
+    assert gap_x <= 2e-6 * float(yi @ yi)
+    scr = scr.cpu().numpy().astype(bool)
+    assert np.all(amask[scr]), np.flatnonzero(scr & ~amask)[:10]
+    if ratio == 0.7:
+        assert scr.sum() > 0
+
+
+@pytest.mark.parametrize("ratio", [0.3, 0.7])
 def test_group_solve_to_tolerance_is_certified(B, ratio):
     D = datagen.gaussian_dictionary(400, 2000, 8)
     gp = datagen.contiguous_groups(2000, 10)
