@@ -113,6 +113,44 @@ def test_results_same_alone_and_in_the_mix(B):
         assert star.primal <= info["primal"] + 1e-7 * star.primal
 
 
+def test_mixed_parameters_same_alone_and_in_the_mix(B):
+    """Requests with different update rules, screening tests and modes and step rules share
+    the workers: each result equals the one obtained with that request alone, bit for bit
+    (no state of one request reaches another)."""
+    dicts = _dicts()
+    reqs = _requests(dicts, 32, 3)
+    rng = np.random.default_rng(4)
+    prm = []
+    for d, _, _ in reqs:
+        group = dicts[d][3] is not None
+        rule = ["ista", "fista", "sparsa", "cp"][int(rng.integers(4))]
+        kw = dict(rule=rule, test=(["none", "safe", "dst3"] if group else
+                                   ["none", "safe", "dst3", "dome"])[int(rng.integers(3 if group else 4))],
+                  screening=["dynamic", "static"][int(rng.integers(2))], gap_tol=1e-6,
+                  max_iter=20000)
+        if rule in ("ista", "fista") and rng.random() < 0.5:
+            kw["step"] = "backtracking"
+        if rule == "sparsa":
+            kw["bb_memory"] = int(rng.integers(0, 6))
+        prm.append(kw)
+    S, ids = _server(B, dicts, max_slots=1)
+    alone = {}
+    for k, (d, y, r) in enumerate(reqs):
+        rid = S.submit(ids[d], y, r, **prm[k])
+        alone.update(_collect(S, ids, {k: (rid, d)}))
+    S.close()
+    S, ids = _server(B, dicts, max_slots=8)
+    rid_of = {k: (S.submit(ids[d], y, r, **prm[k]), d) for k, (d, y, r) in enumerate(reqs)}
+    mix = _collect(S, ids, rid_of)
+    S.close()
+    for k in range(len(reqs)):
+        xa, ia = alone[k]
+        xm, im = mix[k]
+        assert ia["status"] == 0 and im["status"] == 0, (k, prm[k])
+        assert np.array_equal(xa, xm), (k, prm[k])
+        assert ia["iters"] == im["iters"] and ia["gap"] == im["gap"] and ia["L"] == im["L"]
+
+
 def test_admission_under_a_tight_budget(B):
     """A budget that holds about two requests at a time: all finish, results unchanged."""
     dicts = _dicts()
