@@ -433,19 +433,21 @@ def large_leg(binding):
 
 
 def flops_leg(binding, Dd, ys, L, nsig=3, ratios=RATIOS,
-              workload="lasso_fista_dst3_gaussian_2000x10000_f32"):
+              workload="lasso_fista_dst3_gaussian_2000x10000_f32", rule="fista", group_ptr=None):
     """The experiments section's cost model, normalised by the unscreened run: per
     iteration (|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N flops, plus K N for the screening
     set-up, from the per-iteration trace of each solve; wall time normalised the same way.
-    Dynamic and static DST3 with FISTA, on the given dictionary (the headline workload by
-    default)."""
+    Dynamic and static DST3 (DGST3 with group_ptr) against the unscreened run, with the
+    given update rule (FISTA by default) on the given dictionary (the headline workload by
+    default).  SpaRSA takes its own step; the other rules take L."""
     import torch
 
     def run(y, r, test, screening):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info, _, tr = binding.solve_one(Dd, y, r, rule="fista", test=test, step_L=L,
-                                           gap_tol=GAP_TOL, max_iter=20000, trace=True,
+        _, info, _, tr = binding.solve_one(Dd, y, r, rule=rule, test=test, group_ptr=group_ptr,
+                                           step_L=0.0 if rule == "sparsa" else L,
+                                           gap_tol=GAP_TOL, max_iter=50000, trace=True,
                                            screened=False, screening=screening)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -487,6 +489,37 @@ def pnoise_flops_leg(binding):
     Lp = binding.spectral_norm_sq(Dd, 300)
     return flops_leg(binding, Dd, [yd], Lp, nsig=1, ratios=PNOISE_RATIOS,
                      workload="lasso_fista_dst3_pnoise_2000x10000_f32")
+
+
+def algorithms_flops_leg(binding, Dd, ys, L):
+    """The flops model for each update rule of Table 1 (ISTA, FISTA, SpaRSA, Chambolle-Pock)
+    with dynamic and static DST3, each normalised by its own unscreened run, on the
+    headline workload (one signal)."""
+    return {rule: flops_leg(binding, Dd, ys, L, nsig=1, rule=rule,
+                            workload=f"lasso_{rule}_dst3_gaussian_2000x10000_f32")
+            for rule in ("ista", "fista", "sparsa", "cp")}
+
+
+GROUP_SIZES = (5, 10, 50, 100)
+
+
+def group_sizes_flops_leg(binding):
+    """The Group-Lasso experiment: FISTA with dynamic and static DGST3 on the 2000 x 10000
+    FP32 Pnoise dictionary split into contiguous groups of 5, 10, 50 and 100 atoms (w_g =
+    sqrt(|g|)), one unit observation with 2% active groups and 20 dB noise per size."""
+    Dp = datagen.pnoise_dictionary(N, K, datagen.DICT_SEED)
+    D32 = datagen.to_storage(Dp, "f32")
+    out = {}
+    Dd = None
+    for gs in GROUP_SIZES:
+        gp = datagen.contiguous_groups(K, gs)
+        y32 = datagen.to_storage(datagen.group_signal(Dp, gp, 0)[0], "f32")
+        Dd, yd = _dev(D32, y32)
+        Lp = binding.spectral_norm_sq(Dd, 300)
+        out[str(gs)] = flops_leg(binding, Dd, [yd], Lp, nsig=1, ratios=PNOISE_RATIOS,
+                                 group_ptr=gp,
+                                 workload=f"group_lasso_fista_dgst3_pnoise_2000x10000_f32_size{gs}")
+    return out
 
 
 def kernel_source_sha(paths):
@@ -654,6 +687,8 @@ def main():
     if "flops" in legs:
         out["flops_model"] = flops_leg(binding, Dd, ys, L, nsig=min(3, len(ys)))
         out["flops_model_pnoise"] = pnoise_flops_leg(binding)
+        out["flops_model_algorithms"] = algorithms_flops_leg(binding, Dd, ys, L)
+        out["flops_model_group_sizes_pnoise"] = group_sizes_flops_leg(binding)
     if "backtracking" in legs:
         bt = backtracking_leg(binding, Dd, ys, args.steps)
         it_c = []
