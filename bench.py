@@ -456,6 +456,10 @@ def flops_leg(binding, Dd, ys, L, nsig=3, ratios=RATIOS,
             fl += K * N
         return fl, dt, info["iters"]
 
+    # untimed warm-up of each mode: the first launch of a kernel instantiation in the
+    # process is slower, and would otherwise be charged to the first ratio's first mode
+    for test, scr in (("dst3", "dynamic"), ("dst3", "static"), ("none", "dynamic")):
+        run(ys[0], ratios[0], test, scr)
     out = []
     for r in ratios:
         acc = {"dynamic": [0.0, 0.0], "static": [0.0, 0.0], "none": [0.0, 0.0]}
