@@ -180,3 +180,35 @@ def test_server_calls_need_a_server(B):
     assert B._lib.ds_submit(None, 0, y, 0.5, C.byref(prm), C.byref(rid)) == B.DS_EINVAL
     assert B._lib.lasso_poll(None, C.c_uint64(1), None, C.byref(info)) == B.DS_EINVAL
     assert B._lib.ds_server_destroy(None) == B.DS_EINVAL
+
+
+def test_plain_c_client_compiles_links_and_runs(B, tmp_path):
+    """The boundary is a C ABI: a C99 program that includes only include/dynscreen.h links
+    against the library, reads the version, and gets DS_EINVAL with its message for a
+    refused call (no device work happens before validation)."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.dirname(B.LIB_PATH)
+    src = tmp_path / "client.c"
+    src.write_text(
+        "#include <stdio.h>\n#include \"dynscreen.h\"\n"
+        "int main(void) {\n"
+        "  ds_params prm = {0};\n  ds_info info;\n  double lam = 0.5;\n"
+        "  ds_status st = lasso_solve(NULL, NULL, 1, 1, &lam, &prm, NULL, 1, &info, NULL);\n"
+        "  printf(\"%s|%d|%s\\n\", ds_version(), (int)st, ds_last_error());\n"
+        "  return st == DS_EINVAL ? 0 : 1;\n}\n")
+    exe = tmp_path / "client"
+    rocm_lib = "/opt/rocm/lib"
+    cmd = ["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"), str(src),
+           "-L", libdir, "-ldynscreen", f"-Wl,-rpath,{libdir}", f"-Wl,-rpath-link,{rocm_lib}",
+           "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    version, status, message = out.stdout.strip().split("|")
+    assert version.startswith("dynscreen") and int(status) == B.DS_EINVAL
+    assert "NULL" in message
