@@ -78,28 +78,31 @@ template <> __device__ __forceinline__ void widen<bf16_t>(const uint4& r, double
   o[4] = __uint_as_float(r.z << 16); o[5] = __uint_as_float(r.z & 0xffff0000u);
   o[6] = __uint_as_float(r.w << 16); o[7] = __uint_as_float(r.w & 0xffff0000u);
 }
-// VEC consecutive elements of a 16-byte aligned float / double vector, widened to FP64.
-template <int VEC> __device__ __forceinline__ void load_dv(const float* p, double (&o)[VEC]) {
-  static_assert(VEC % 4 == 0, "float vector loads come in fours");
+// FP64 values of TW raw 16-byte loads of a float or double vector.
+template <typename VV, int TW, int NV>
+__device__ __forceinline__ void widen_raw(const uint4 (&r)[TW], double (&o)[NV]) {
+  if constexpr (sizeof(VV) == 4) {
+    static_assert(NV == 4 * TW, "four floats per load");
 #pragma unroll
-  for (int k = 0; k < VEC / 4; ++k) {
-    const float4 f = reinterpret_cast<const float4*>(p)[k];
-    o[4 * k] = f.x; o[4 * k + 1] = f.y; o[4 * k + 2] = f.z; o[4 * k + 3] = f.w;
-  }
-}
-template <int VEC> __device__ __forceinline__ void load_dv(const double* p, double (&o)[VEC]) {
-  static_assert(VEC % 2 == 0, "double vector loads come in twos");
+    for (int w = 0; w < TW; ++w) {
+      o[4 * w] = __uint_as_float(r[w].x); o[4 * w + 1] = __uint_as_float(r[w].y);
+      o[4 * w + 2] = __uint_as_float(r[w].z); o[4 * w + 3] = __uint_as_float(r[w].w);
+    }
+  } else {
+    static_assert(NV == 2 * TW, "two doubles per load");
 #pragma unroll
-  for (int k = 0; k < VEC / 2; ++k) {
-    const double2 d = reinterpret_cast<const double2*>(p)[k];
-    o[2 * k] = d.x; o[2 * k + 1] = d.y;
+    for (int w = 0; w < TW; ++w) {
+      o[2 * w] = __hiloint2double(static_cast<int>(r[w].y), static_cast<int>(r[w].x));
+      o[2 * w + 1] = __hiloint2double(static_cast<int>(r[w].w), static_cast<int>(r[w].z));
+    }
   }
 }
 
 // FP64 dot products of NC columns with a vector v, by one wave.  Branch-free: every
-// column pointer must be valid (callers repeat a valid column for unused slots), so the
-// compiler issues all 2*NC 16-byte loads of an unrolled step before the FMAs.  With
-// VECTOR the columns and v are 16-byte aligned; the tail N % VEC is read element-wise.
+// column pointer must be valid (callers repeat a valid column for unused slots).  With
+// VECTOR the columns and v are 16-byte aligned and are read in batches of SB steps of
+// 64 x VEC elements whose loads are all in flight before the first FMA (a 2000-row FP32
+// column pair is one batch of 24 loads per lane); the tail N % VEC is read element-wise.
 template <typename T, typename VV, int NC, bool VECTOR>
 __device__ __forceinline__ void wave_dots(const T* const (&cols)[NC], const VV* __restrict__ v,
                                           int N, int lane, double (&acc)[NC]) {
@@ -107,40 +110,43 @@ __device__ __forceinline__ void wave_dots(const T* const (&cols)[NC], const VV* 
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if constexpr (VECTOR) {
     constexpr int VEC = Store<T>::VEC;
-    constexpr int US = 4;  // vector steps in flight per column
+    // Steps of 64 x VEC elements whose loads are all issued before the first FMA: eight
+    // when one step of v is one 16-byte load, else four.  A column of up to SB * 64 * VEC
+    // elements is one round trip; steps past the end re-read the last vector and get a
+    // zero weight.
+    constexpr int TW = VEC * static_cast<int>(sizeof(VV)) / 16;  // 16-byte loads of v per step
+    constexpr int SB = TW == 1 ? 8 : 4;
     const int nfull = N / VEC;
-    int q = lane;
-    for (; q + (US - 1) * WAVE < nfull; q += US * WAVE) {
-      uint4 r[US][NC];
+    for (int q0 = 0; q0 < nfull; q0 += SB * WAVE) {
+      uint4 tr[SB][TW];
+      uint4 r[SB][NC];
+      // v first: loads complete in issue order, so step k waits only for its own data
 #pragma unroll
-      for (int k = 0; k < US; ++k)
+      for (int k = 0; k < SB; ++k) {
+        const int q = min(q0 + lane + k * WAVE, nfull - 1);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) r[k][c] = ld16(cols[c] + static_cast<int64_t>(q + k * WAVE) * VEC);
-      double t[VEC];
+        for (int w = 0; w < TW; ++w) tr[k][w] = ld16(v + static_cast<int64_t>(q) * VEC + w * (16 / sizeof(VV)));
+      }
 #pragma unroll
-      for (int k = 0; k < US; ++k) {
-        load_dv<VEC>(v + (q + k * WAVE) * VEC, t);
+      for (int k = 0; k < SB; ++k) {
+        const int q = min(q0 + lane + k * WAVE, nfull - 1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[k][c] = ld16(cols[c] + static_cast<int64_t>(q) * VEC);
+      }
+      // keep the scheduler from interleaving the FMAs (and their waits) with the loads
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const bool ok = q0 + lane + k * WAVE < nfull;
+        double t[VEC];
+        widen_raw<VV>(tr[k], t);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           double d[VEC];
           widen<T>(r[k][c], d);
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[c] = fma(d[e], t[e], acc[c]);
+          for (int e = 0; e < VEC; ++e) acc[c] = fma(d[e], ok ? t[e] : 0.0, acc[c]);
         }
-      }
-    }
-    for (; q < nfull; q += WAVE) {
-      uint4 r0[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) r0[c] = ld16(cols[c] + static_cast<int64_t>(q) * VEC);
-      double t0[VEC];
-      load_dv<VEC>(v + q * VEC, t0);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        double d[VEC];
-        widen<T>(r0[c], d);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[c] = fma(d[e], t0[e], acc[c]);
       }
     }
     const int e = nfull * VEC + lane;
