@@ -1452,6 +1452,8 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ double kmarg[CBU];
   __shared__ double sred[NW][6];
   __shared__ SolverState S;
+  __shared__ int s_il[CBL];  // Lasso: the block's new x and u by list position
+  __shared__ V s_xs[CBL], s_us[CBL], s_xo[CBL], s_po[CBL];
   if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   // One round trip for the state (one word per thread into LDS) and for the list entries
@@ -1508,11 +1510,6 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   }
   __syncthreads();
   const int nk = s_nk;
-  if (compact && tid < nk) {
-    a.act[1 - cur][s_kpre + tid] = klist[tid];
-    a.act_m[1 - cur][s_kpre + tid] = kmarg[tid];
-  }
-  if (tid == 0) a.seg_cnt[vb] = nk;
 
   const double lam = st->lam, L = st->L;
   // Chambolle-Pock: step tau instead of 1/L, prox from x_{t-1}, extrapolation weight phi
@@ -1549,19 +1546,15 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
         const double xn = mag > 0.0 ? copysign(mag, vv) : 0.0;
         const double un = (RULE == RULE_FISTA || RULE == RULE_CP) ? xn + beta * (xn - xo) : xn;
         const V xs = static_cast<V>(xn), us = static_cast<V>(un);
-        a.x[i_l] = xs;
-        a.u[i_l] = us;
-        const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + jl;
-        a.seg_atom[slot] = i_l;
-        a.seg_val[slot] = us;
-        a.urec_marg[slot] = kmarg[jl];
-        a.urec_om[slot] = fabs(static_cast<double>(us));
+        // staged in LDS and written once the block's rounds are done: a global store
+        // here would hold up the next round's column loads until it completes
+        s_il[jl] = i_l;
+        s_xs[jl] = xs;
+        s_us[jl] = us;
         if (a.bt) {  // keep p and x_{t-1} so that a rejected step can be undone
           const double dv = static_cast<double>(xs) - p;  // exact: two stored values
-          a.seg_xo[slot] = static_cast<V>(xo);
-          a.seg_po[slot] = static_cast<V>(p);
-          a.seg_d[slot] = dv;
-          a.urec_omo[slot] = fabs(p);
+          s_xo[jl] = static_cast<V>(xo);
+          s_po[jl] = static_cast<V>(p);
           dd = fma(dv, dv, dd);
           // SpaRSA: z_i d_i + lambda (|x'_i| - |p_i|), the first-order and penalty parts of
           // phi(x') - phi(p), unit by unit
@@ -1699,6 +1692,33 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
     if (RULE == RULE_SPARSA) sred[wave][5] = cde;
   }
   __syncthreads();
+  // Global stores come after the column stream: a wave's loads wait for its earlier
+  // stores to complete.
+  if (compact && tid < nk) {
+    a.act[1 - cur][s_kpre + tid] = klist[tid];
+    a.act_m[1 - cur][s_kpre + tid] = kmarg[tid];
+  }
+  if (tid == 0) a.seg_cnt[vb] = nk;
+  if constexpr (!GROUP) {
+    if (tid < nk) {  // the kept units' x and u, and the block's support segment
+      const int i_l = s_il[tid];
+      const V xs = s_xs[tid], us = s_us[tid];
+      a.x[i_l] = xs;
+      a.u[i_l] = us;
+      const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + tid;
+      a.seg_atom[slot] = i_l;
+      a.seg_val[slot] = us;
+      a.urec_marg[slot] = kmarg[tid];
+      a.urec_om[slot] = fabs(static_cast<double>(us));
+      if (a.bt) {
+        const double p = static_cast<double>(s_po[tid]);
+        a.seg_xo[slot] = s_xo[tid];
+        a.seg_po[slot] = s_po[tid];
+        a.seg_d[slot] = static_cast<double>(xs) - p;
+        a.urec_omo[slot] = fabs(p);
+      }
+    }
+  }
   if (tid == 0) {  // read by the next residual pass only (after this kernel ends)
     double r0 = sred[0][0], r1 = sred[0][1], r2 = sred[0][2], r3 = sred[0][3], r4 = sred[0][4];
 #pragma unroll
