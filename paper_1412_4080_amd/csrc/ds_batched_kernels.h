@@ -366,9 +366,13 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int nw = a.Kp / MT;
   const float* u = Uin + static_cast<int64_t>(s) * a.Kp;
+  // mask words of the first round; each later round's words are fetched while the
+  // current round streams
+  uint32_t m_next =
+      (threadIdx.x < TW && threadIdx.x < nw) ? a.umask[static_cast<int64_t>(threadIdx.x) * a.Bp + s] : 0u;
   for (int w0 = 0; w0 < nw; w0 += TW) {
     const int w = w0 + threadIdx.x;
-    uint32_t m = (threadIdx.x < TW && w < nw) ? a.umask[static_cast<int64_t>(w) * a.Bp + s] : 0u;
+    uint32_t m = m_next;
     int total;
     int pos = block_exclusive_scan<NWB>(__popc(m), scan, &total);
     while (m != 0u) {
@@ -376,17 +380,34 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
       m &= m - 1u;
     }
     __syncthreads();
+    const int wn = w + TW;
+    m_next = (threadIdx.x < TW && wn < nw) ? a.umask[static_cast<int64_t>(wn) * a.Bp + s] : 0u;
     if (rows_ok) {
-#pragma unroll 2
-      for (int j = wave; j < total; j += NWB) {
-        const int at = sidx[j];
-        const double uv = u[at];
-        const uint4 d = ldg16(a.dcm + static_cast<int64_t>(at) * a.Np + nl);
-        const uint32_t wd[4] = {d.x, d.y, d.z, d.w};
+      // Wave w takes list entries w, w + 4, w + 8, ... in increasing order (GB of them
+      // per batch, every load of a batch issued before the first FMA).  Entries past the
+      // end re-read the last one with weight zero: the accumulators start at +0 and a sum
+      // never rounds to -0, so adding a zero product leaves them bit for bit unchanged.
+      constexpr int GB = 8;
+      for (int j0 = 0; j0 < total; j0 += NWB * GB) {
+        int at[GB];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          acc[2 * e] = fma(static_cast<double>(__uint_as_float(wd[e] << 16)), uv, acc[2 * e]);
-          acc[2 * e + 1] = fma(static_cast<double>(__uint_as_float(wd[e] & 0xffff0000u)), uv, acc[2 * e + 1]);
+        for (int g = 0; g < GB; ++g) at[g] = sidx[min(j0 + wave + NWB * g, total - 1)];
+        float uv[GB];
+        uint4 d[GB];
+#pragma unroll
+        for (int g = 0; g < GB; ++g) uv[g] = u[at[g]];
+#pragma unroll
+        for (int g = 0; g < GB; ++g) d[g] = ldg16(a.dcm + static_cast<int64_t>(at[g]) * a.Np + nl);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < GB; ++g) {
+          const double ug = j0 + wave + NWB * g < total ? static_cast<double>(uv[g]) : 0.0;
+          const uint32_t wd[4] = {d[g].x, d[g].y, d[g].z, d[g].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[2 * e] = fma(static_cast<double>(__uint_as_float(wd[e] << 16)), ug, acc[2 * e]);
+            acc[2 * e + 1] = fma(static_cast<double>(__uint_as_float(wd[e] & 0xffff0000u)), ug, acc[2 * e + 1]);
+          }
         }
       }
     }
