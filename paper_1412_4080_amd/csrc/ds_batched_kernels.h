@@ -665,8 +665,12 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   nact = wave_sum(nact);
   nsup = wave_sum(nsup);
   if (lane != 0) return;
+  // every field read before the first store: a load issued after a store waits for it
   const int t = st.iter + 1;
   const double lam = st.lam, yy = st.yy, rho2 = st.rho2;
+  const double act_sum = st.act_sum, sup_sum = st.sup_sum, r_min = st.r_min;
+  const double r_keep_old = st.r_keep, l_prev = st.l_prev, r_scr_old = st.r_scr;
+  const double marg_slack = st.marg_slack, gap_tol_abs = st.gap_tol_abs;
   const double sb = zm > 0.0 ? 1.0 / zm : 1e300;
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
@@ -689,26 +693,28 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   st.iter = t;
   st.tt = tt;
   st.ty = ty;
-  st.act_sum += nact;
-  st.sup_sum += nsup;
+  st.act_sum = act_sum + nact;
+  st.sup_sum = sup_sum + nsup;
   st.zmax = zm;
   st.omega = om;
   st.mu = mu;
   st.gap = primal - dual;
   st.primal = primal;
   st.dual = dual;
-  st.r_min = fmin(st.r_min, r);
-  st.r_prev = st.r_keep;
-  if (a.rule == 1) st.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.l_prev * st.l_prev));
-  if (r_safe < st.r_scr && (!a.screen_static || t == 1)) {  // static: first radius only
+  st.r_min = fmin(r_min, r);
+  st.r_prev = r_keep_old;
+  if (a.rule == 1) st.l_prev = 0.5 * (1.0 + sqrt(1.0 + 4.0 * l_prev * l_prev));
+  double r_scr = r_scr_old;
+  if (r_safe < r_scr && (!a.screen_static || t == 1)) {  // static: first radius only
+    r_scr = r_safe;
     st.r_scr = r_safe;
     st.r_slack = r_safe - r;
   }
-  st.r_keep = fmin(st.r_prev, st.r_scr + st.marg_slack);
+  st.r_keep = fmin(r_keep_old, r_scr + marg_slack);
   // the estimate differs from the exact gap only through max|z|: every iteration whose
   // estimate is within VWIN of tolerance is checked, so the solve ends at the first
   // iteration whose exact gap meets it
-  const bool flag = (st.gap_tol_abs > 0.0 && primal - dual <= VWIN * st.gap_tol_abs) || t >= a.max_iter;
+  const bool flag = (gap_tol_abs > 0.0 && primal - dual <= VWIN * gap_tol_abs) || t >= a.max_iter;
   st.verify = flag ? 1 : 0;
   if (flag) a.vlist[atomicAdd(a.vcount, 1)] = s;
 }
@@ -737,11 +743,18 @@ __global__ __launch_bounds__(TB) void k_b_vcand(BArgs a) {
     const float* mg = a.marg + static_cast<int64_t>(s) * a.Kp;
     int* out = a.cidx + static_cast<int64_t>(s) * a.Kp + i0;
     int mine[4], cnt = 0;
+    // the thread's four margins and correlations in two 16-byte loads (rows are Kp long,
+    // Kp a multiple of 64; the index is clamped into the row and entries past K ignored)
+    const int ib = i0 + threadIdx.x * 4;
+    const int ic = min(ib, a.Kp - 4);
+    const float4 m4 = *reinterpret_cast<const float4*>(mg + ic);
+    const float4 z4 = *reinterpret_cast<const float4*>(z + ic);
+    const float mv[4] = {m4.x, m4.y, m4.z, m4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int i = i0 + threadIdx.x * 4 + k;
-      const bool c = i < a.K && static_cast<double>(mg[i]) <= r_act &&
-                     fabs(static_cast<double>(z[i])) >= thr;
+      const int i = ib + k;
+      const bool c = i < a.K && static_cast<double>(mv[k]) <= r_act &&
+                     fabs(static_cast<double>(zv[k])) >= thr;
       mine[k] = c ? i : -1;
       cnt += c;
     }
@@ -840,20 +853,22 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
   zm = wave_max(zm);
   if (lane != 0) return;
   const double lam = st.lam, tt = st.tt, ty = st.ty;
+  const double primal = st.primal, gap_tol_abs = st.gap_tol_abs;  // read before any store
+  const int iter = st.iter;
   const double zs = zm + a.gamma64 * a.dsc[0] * sqrt(tt);
   const double sb = zs > 0.0 ? 1.0 / zs : 1e300;
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
   const double dual = lam * mu * ty - 0.5 * lam * lam * mu * mu * tt;
-  const double gap = st.primal - dual;
+  const double gap = primal - dual;
   st.zmax = zm;
   st.mu = mu;
   st.dual = dual;
   st.gap = gap;
   st.verify = 0;
-  const bool ok = st.gap_tol_abs > 0.0 && gap <= st.gap_tol_abs;
-  if (ok || st.iter >= a.max_iter) {
-    st.converged = (ok || st.gap_tol_abs <= 0.0) ? 1 : 0;
+  const bool ok = gap_tol_abs > 0.0 && gap <= gap_tol_abs;
+  if (ok || iter >= a.max_iter) {
+    st.converged = (ok || gap_tol_abs <= 0.0) ? 1 : 0;
     st.done = 2;
     atomicAdd(a.ndone, 1);
   }
