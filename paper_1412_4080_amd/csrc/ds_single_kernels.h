@@ -1454,6 +1454,13 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
   __shared__ SolverState S;
   __shared__ int s_il[CBL];  // Lasso: the block's new x and u by list position
   __shared__ V s_xs[CBL], s_us[CBL], s_xo[CBL], s_po[CBL];
+  // groups: the same by support slot (group j, atom k at j * GMAX + k), and per group its
+  // first atom, size, Omega term and backtracking sums
+  constexpr int GSL = GROUP ? SEGCAP_G : 1, GGR = GROUP ? CBG : 1;
+  __shared__ V g_xs[GSL], g_us[GSL], g_xo[GSL], g_po[GSL];
+  __shared__ int64_t g_a0[GGR];
+  __shared__ int g_m[GGR];
+  __shared__ double g_om[GGR], g_omo[GGR], g_dn[GGR];
   if (a.kclk != nullptr && threadIdx.x == 0) a.kclk[2 * blockIdx.x] = wall_clock64();
   const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
   // One round trip for the state (one word per thread into LDS) and for the list entries
@@ -1569,10 +1576,17 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
     natoms = tid == 0 ? nk : 0;
   } else {
     constexpr int NS = GMAX / WAVE;  // atoms per lane: atom k of the group sits on lane k % 64
-    for (int j = wave; j < nk; j += NW) {
+    // the offsets of the wave's (at most two) groups in one round trip: lane 2i + e reads
+    // gptr[g_i + e] (lanes past 3 repeat lane 3's address)
+    static_assert(CBG == 2 * NW, "two groups per wave");
+    const int jq = wave + (min(lane, 3) >> 1) * NW;
+    const int gq = nk > 0 ? klist[min(jq, nk - 1)] : 0;
+    const long long goff = static_cast<long long>(a.gptr[gq + (min(lane, 3) & 1)]);
+    int it = 0;
+    for (int j = wave; j < nk; j += NW, ++it) {
       const int g = klist[j];
-      const int64_t a0 = a.gptr[g];
-      const int m = static_cast<int>(a.gptr[g + 1] - a0);
+      const int64_t a0 = __shfl(goff, 2 * it);
+      const int m = static_cast<int>(__shfl(goff, 2 * it + 1) - a0);
       double p[NS], xo[NS], vreg[NS], zk[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -1597,13 +1611,15 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
             z2 = fma(acc[c], acc[c], z2);
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-              if (b0 + c == lane + s * WAVE) {
-                vreg[s] = (RULE == RULE_CP ? xo[s] : p[s]) - acc[c] * invL;
-                if constexpr (RULE == RULE_SPARSA) zk[s] = acc[c];
-              }
+              if (b0 + c == lane + s * WAVE) zk[s] = acc[c];
           }
         }
       }
+      // the gradient step after the stream, so that the u and x loads are not waited for
+      // before the first columns are requested
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (lane + s * WAVE < m) vreg[s] = (RULE == RULE_CP ? xo[s] : p[s]) - zk[s] * invL;
       double vsq = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) vsq += vreg[s] * vreg[s];
@@ -1622,16 +1638,15 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
           const double un =
               (RULE == RULE_FISTA || RULE == RULE_CP) ? xn + beta * (xn - xo[s]) : xn;
           const V xs = static_cast<V>(xn), us = static_cast<V>(un);
-          a.x[a0 + ak] = xs;
-          a.u[a0 + ak] = us;
-          const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + j * GMAX + ak;
-          a.seg_atom[slot] = static_cast<int32_t>(a0 + ak);
-          a.seg_val[slot] = us;
+          // staged in LDS and stored after the block's last group (a global store here
+          // would hold up the wave's next loads until it completed)
+          const int ls = j * GMAX + ak;
+          g_xs[ls] = xs;
+          g_us[ls] = us;
           if (a.bt) {
             const double dv = static_cast<double>(xs) - p[s];
-            a.seg_xo[slot] = static_cast<V>(xo[s]);
-            a.seg_po[slot] = static_cast<V>(p[s]);
-            a.seg_d[slot] = dv;
+            g_xo[ls] = static_cast<V>(xo[s]);
+            g_po[ls] = static_cast<V>(p[s]);
             dn = fma(dv, dv, dn);
             po2 = fma(p[s], p[s], po2);
             if constexpr (RULE == RULE_SPARSA) {
@@ -1656,13 +1671,12 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
         }
       }
       if (lane == 0) {
-        const int64_t rec = static_cast<int64_t>(vb) * CBU + j;
-        a.urec_marg[rec] = kmarg[j];
-        a.urec_om[rec] = wg * sqrt(un2);
-        a.urec_m[rec] = m;
+        g_a0[j] = a0;
+        g_m[j] = m;
+        g_om[j] = wg * sqrt(un2);
         if (a.bt) {
-          a.urec_omo[rec] = wg * sqrt(po2);
-          a.urec_dn[rec] = dn;
+          g_omo[j] = wg * sqrt(po2);
+          g_dn[j] = dn;
           dd += dn;
           if constexpr (RULE == RULE_SPARSA) {
             // ||x'_g|| - ||p_g|| = d_g^T (x'_g + p_g) / (||x'_g|| + ||p_g||): no cancellation
@@ -1699,6 +1713,37 @@ __global__ __launch_bounds__(BLK) void k_corr(SingleArgs<T, V, double> a) {
     a.act_m[1 - cur][s_kpre + tid] = kmarg[tid];
   }
   if (tid == 0) a.seg_cnt[vb] = nk;
+  if constexpr (GROUP) {
+    // the kept groups' x and u, support segment and group records
+    for (int ls = tid; ls < nk * GMAX; ls += BLK) {
+      const int j = ls / GMAX, ak = ls % GMAX;
+      if (ak < g_m[j]) {
+        const int64_t at = g_a0[j] + ak;
+        const V xs = g_xs[ls], us = g_us[ls];
+        a.x[at] = xs;
+        a.u[at] = us;
+        const int64_t slot = static_cast<int64_t>(vb) * SEGCAP + ls;
+        a.seg_atom[slot] = static_cast<int32_t>(at);
+        a.seg_val[slot] = us;
+        if (a.bt) {
+          const V po = g_po[ls];
+          a.seg_xo[slot] = g_xo[ls];
+          a.seg_po[slot] = po;
+          a.seg_d[slot] = static_cast<double>(xs) - static_cast<double>(po);
+        }
+      }
+    }
+    if (tid < nk) {
+      const int64_t rec = static_cast<int64_t>(vb) * CBU + tid;
+      a.urec_marg[rec] = kmarg[tid];
+      a.urec_om[rec] = g_om[tid];
+      a.urec_m[rec] = g_m[tid];
+      if (a.bt) {
+        a.urec_omo[rec] = g_omo[tid];
+        a.urec_dn[rec] = g_dn[tid];
+      }
+    }
+  }
   if constexpr (!GROUP) {
     if (tid < nk) {  // the kept units' x and u, and the block's support segment
       const int i_l = s_il[tid];
