@@ -523,6 +523,9 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
       f32x16 c;
 #pragma unroll
       for (int i = 0; i < 16; ++i) c[i] = 0.f;
+      // raised wave priority while the chunk's MFMAs issue: the waves staging the next
+      // chunk through LDS then yield to the ones that keep the matrix cores busy
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s16 = 0; s16 < ZR; s16 += 16) {
         const bf16x8 ad = as_bf16x8(*reinterpret_cast<const uint4*>(&sA[wa + lane % MT][s16 + kk]));
@@ -533,6 +536,7 @@ __global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
       }
+      __builtin_amdgcn_s_setprio(0);
 #pragma unroll
       for (int i = 0; i < 16; ++i) zacc[i] += static_cast<double>(c[i]);
     }
