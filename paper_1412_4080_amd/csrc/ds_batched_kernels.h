@@ -804,14 +804,30 @@ __global__ __launch_bounds__(TB) void k_b_vdot(BArgs a) {
         const int64_t slot = static_cast<int64_t>(s) * a.Kp + ch * VC + c;
         const uint16_t* col = a.dcm + static_cast<int64_t>(a.cidx[slot]) * a.Np;
         double acc = 0.0;
-        for (int n = lane * 8; n < a.Np; n += BW * 8) {
-          const uint4 d = ldg16(col + n);
-          const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+        // NB steps of 512 rows per batch, every load issued before the first FMA; steps
+        // past the end re-read the last rows with weight zero (acc starts at +0 and never
+        // becomes -0, so a zero product leaves it unchanged bit for bit)
+        constexpr int NB = 4;
+        for (int n0 = lane * 8; n0 < a.Np; n0 += NB * BW * 8) {
+          uint4 d[NB];
+          double2 t2[NB][4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const double2 t2 = *reinterpret_cast<const double2*>(th + n + 2 * q);
-            acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2.x, acc);
-            acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2.y, acc);
+          for (int k = 0; k < NB; ++k) {
+            const int n = min(n0 + k * BW * 8, a.Np - 8);
+            d[k] = ldg16(col + n);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t2[k][q] = *reinterpret_cast<const double2*>(th + n + 2 * q);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int k = 0; k < NB; ++k) {
+            const bool ok = n0 + k * BW * 8 < a.Np;
+            const uint32_t w[4] = {d[k].x, d[k].y, d[k].z, d[k].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), ok ? t2[k][q].x : 0.0, acc);
+              acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), ok ? t2[k][q].y : 0.0, acc);
+            }
           }
         }
         acc = wave_sum(acc);
