@@ -345,6 +345,186 @@ def test_group_screening_safe():
 
 
 # --------------------------------------------------------------------------
+# The certified-inactive sets against the optimality conditions (equations
+# (primaldual) and (primaldualKKT_glasso)): from a feasible dual point at gap g,
+# the dual optimum lies within sqrt(2 g)/lambda (the dual is lambda^2-strongly
+# concave), so a unit that is certified must be inactive at the exact solution,
+# and a unit whose exact correlation is below the threshold by twice that radius
+# must be certified.  The exact solution comes from brute-force enumeration
+# (Lasso) or from a KKT-verified solve (groups); the perturbed points give a
+# positive gap.
+# --------------------------------------------------------------------------
+
+def _perturbed(x, scale, seed):
+    rng = np.random.default_rng(seed)
+    return x + scale * rng.normal(size=x.shape)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("scale", [1e-2, 1e-4])
+def test_certified_inactive_lasso_against_brute_force(seed, scale):
+    D = datagen.gaussian_dictionary(7, 11, 80 + seed)
+    rng = np.random.default_rng(90 + seed)
+    y = rng.normal(size=7)
+    y /= np.linalg.norm(y)
+    lam = 0.3 * np.max(np.abs(D.T @ y))
+    xs = oracle.brute_force_lasso(D, y, lam)
+    support = xs != 0
+    assert support.any() and (~support).any()
+    theta_opt = (y - D @ xs) / lam                  # the dual optimum
+    p_opt = 0.5 * np.sum((D @ xs - y) ** 2) + lam * np.abs(xs).sum()
+    x = _perturbed(xs, scale, seed)
+    cert, gap = oracle.certified_inactive_lasso(D, y, lam, x)
+    p_x = 0.5 * np.sum((D @ x - y) ** 2) + lam * np.abs(x).sum()
+    # weak duality: the reported gap bounds the primal suboptimality
+    assert gap >= p_x - p_opt - 1e-15
+    # never certifies an atom of the exact support
+    assert not cert[support].any()
+    # certifies every atom whose exact correlation is below 1 by twice the radius
+    rad = np.sqrt(2.0 * gap) / lam
+    nu = np.linalg.norm(D, axis=0)
+    must = np.abs(D.T @ theta_opt) < 1.0 - 2.0 * nu * rad
+    assert np.all(cert[must])
+    if scale == 1e-4:
+        assert must.any()        # the check is not vacuous on these instances
+
+
+def test_certified_inactive_lasso_boundary_atom():
+    # D = I, y = (lambda + a, lambda), lambda = 1/2, a = 1/4: soft thresholding gives
+    # x = (a, 0) with d_2^T theta_opt = 1 exactly although x_2 = 0.  All values are
+    # dyadic, so the arithmetic is exact and the gap is 0: atom 2 sits on the
+    # threshold and must stay uncertified (strict test); the same holds at any
+    # perturbed point, where the radius is positive.
+    D = np.eye(2)
+    lam, a = 0.5, 0.25
+    y = np.array([lam + a, lam])
+    xs = np.array([a, 0.0])
+    cert, gap = oracle.certified_inactive_lasso(D, y, lam, xs)
+    assert gap == 0.0
+    assert not cert.any()
+    for seed in range(5):
+        cert, gap = oracle.certified_inactive_lasso(D, y, lam, _perturbed(xs, 1e-6, seed))
+        assert gap > 0 and not cert[1]
+    # a third atom orthogonal to the residual direction is certified at the optimum
+    D3 = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    y3 = np.array([lam + a, lam, 0.125])
+    cert, gap = oracle.certified_inactive_lasso(D3, y3, lam, np.array([a, 0.0, 0.0]))
+    assert gap == 0.0 and cert.tolist() == [False, False, True]
+
+
+def _kkt_group_ok(D, y, x, lam, groups, w, tol):
+    res = y - D @ x
+    for k, g in enumerate(groups):
+        corr = D[:, g].T @ res
+        xg = x[g]
+        if np.linalg.norm(xg) > 0:
+            if not np.allclose(corr, lam * w[k] * xg / np.linalg.norm(xg), atol=tol):
+                return False
+        elif np.linalg.norm(corr) > lam * w[k] + tol:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("scale", [1e-2, 1e-4])
+def test_certified_inactive_group_against_the_optimality_conditions(seed, scale):
+    D = datagen.gaussian_dictionary(12, 24, 110 + seed)
+    rng = np.random.default_rng(120 + seed)
+    y = rng.normal(size=12)
+    y /= np.linalg.norm(y)
+    gp = datagen.contiguous_groups(24, 3)
+    groups = [np.arange(gp[k], gp[k + 1]) for k in range(8)]
+    w = np.sqrt(3.0) * np.ones(8)
+    ref = oracle.solve_group_lasso(D, y, gp, w, lam_ratio=0.35, rule="fista", test="none",
+                                   max_iter=400000, gap_tol=1e-15)
+    lam, xs = ref.lam, ref.x
+    assert _kkt_group_ok(D, y, xs, lam, groups, w, 1e-9)
+    gsupp = np.array([np.linalg.norm(xs[g]) > 0 for g in groups])
+    assert gsupp.any() and (~gsupp).any()
+    theta_opt = (y - D @ xs) / lam
+    x = _perturbed(xs, scale, seed)
+    amask, gmask, gap = oracle.certified_inactive_group(D, y, lam, x, gp, w)
+    p_opt = 0.5 * np.sum((D @ xs - y) ** 2) + lam * sum(
+        w[k] * np.linalg.norm(xs[g]) for k, g in enumerate(groups))
+    p_x = 0.5 * np.sum((D @ x - y) ** 2) + lam * sum(
+        w[k] * np.linalg.norm(x[g]) for k, g in enumerate(groups))
+    assert gap >= p_x - p_opt - 1e-12
+    assert not gmask[gsupp].any()
+    assert not amask[xs != 0].any()
+    rad = np.sqrt(2.0 * gap) / lam
+    gn = np.array([np.linalg.norm(D[:, g], 2) for g in groups])
+    must = np.array([np.linalg.norm(D[:, g].T @ theta_opt) for g in groups]) < w - 2.0 * gn * rad
+    assert np.all(gmask[must])
+    for k in np.flatnonzero(gmask):
+        assert amask[groups[k]].all()
+    if scale == 1e-4:
+        assert must.any()
+
+
+def test_certified_inactive_group_boundary_group():
+    # D = I (4 atoms), groups {0,1} and {2,3}, weights 5/4, lambda = 1/2.  y_g = (3/2, 2)
+    # has norm 5/2 > lambda w, so x_g = (1 - 1/4) y_g; y_h = (3/8, 1/2) has norm exactly
+    # lambda w = 5/8, so x_h = 0 while ||D_h^T theta_opt|| = w_h.  Dyadic values: the gap is
+    # exactly 0 and group h sits on the threshold, so it must stay uncertified.
+    D = np.eye(4)
+    gp = np.array([0, 2, 4])
+    w = np.array([1.25, 1.25])
+    lam = 0.5
+    y = np.array([1.5, 2.0, 0.375, 0.5])
+    xs = np.array([1.125, 1.5, 0.0, 0.0])
+    amask, gmask, gap = oracle.certified_inactive_group(D, y, lam, xs, gp, w)
+    assert gap == 0.0
+    assert not gmask.any() and not amask.any()
+    for seed in range(5):
+        amask, gmask, gap = oracle.certified_inactive_group(D, y, lam, _perturbed(xs, 1e-6, seed),
+                                                            gp, w)
+        assert gap > 0 and not gmask[1]
+
+
+# --------------------------------------------------------------------------
+# Warm start (the initialisation X_0 of Algorithm 3)
+# --------------------------------------------------------------------------
+
+def test_warm_start_continues_the_ista_trajectory():
+    # ISTA's iterate depends on the previous iterate only, so T iterations from x_T
+    # land where 2T iterations from 0 land (no screening: nothing else is carried)
+    D, y = _problem(N=50, K=150, seed=31)
+    a = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="ista", test="none", max_iter=60,
+                           gap_tol=0.0)
+    b = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="ista", test="none", max_iter=30,
+                           gap_tol=0.0)
+    c = oracle.solve_lasso(D, y, lam_ratio=0.4, rule="ista", test="none", max_iter=30,
+                           gap_tol=0.0, x0=b.x)
+    assert np.allclose(c.x, a.x, rtol=0, atol=1e-14)
+    gp = datagen.contiguous_groups(150, 5)
+    a = oracle.solve_group_lasso(D, y, gp, None, lam_ratio=0.4, rule="ista", test="none",
+                                 max_iter=60, gap_tol=0.0)
+    b = oracle.solve_group_lasso(D, y, gp, None, lam_ratio=0.4, rule="ista", test="none",
+                                 max_iter=30, gap_tol=0.0)
+    c = oracle.solve_group_lasso(D, y, gp, None, lam_ratio=0.4, rule="ista", test="none",
+                                 max_iter=30, gap_tol=0.0, x0=b.x)
+    assert np.allclose(c.x, a.x, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("rule", ["ista", "fista", "cp"])
+def test_warm_start_at_the_solution_stops_at_once_and_any_start_reaches_it(rule):
+    D = datagen.gaussian_dictionary(6, 10, 70)
+    rng = np.random.default_rng(71)
+    y = rng.normal(size=6)
+    y /= np.linalg.norm(y)
+    lam = 0.3 * oracle.lambda_max_lasso(D, y)[0]
+    xb = oracle.brute_force_lasso(D, y, lam)
+    # from the exact solution the first gap certificate is (rounding) zero
+    r = oracle.solve_lasso(D, y, lam=lam, rule=rule, test="dst3", max_iter=50, gap_tol=1e-12,
+                           x0=xb)
+    assert r.converged and r.iters == 1
+    # from an arbitrary start the method reaches the same solution (Theorem 1)
+    r = oracle.solve_lasso(D, y, lam=lam, rule=rule, test="dst3", max_iter=400000,
+                           gap_tol=1e-15, x0=rng.normal(size=10))
+    assert r.converged and np.allclose(r.x, xb, atol=1e-7)
+
+
+# --------------------------------------------------------------------------
 # Spectral norms against the SVD
 # --------------------------------------------------------------------------
 
