@@ -131,6 +131,14 @@ typedef struct {
                         method needs tau_0 sigma_0 ||D||_2^2 <= 1 (checked against step_L
                         when both steps and step_L are given) */
   double cp_gamma;   /* DS_CP: acceleration gamma >= 0 (0: constant steps) */
+  const void* x0;    /* optional initial point X_0, the input of Algorithm 3 (NULL: x_0 = 0).
+                        Element type as x.  lasso_solve / glasso_solve / ds_solve_batch: DEVICE,
+                        K x B with the leading dimension ldx of X; ds_solve_one: DEVICE, K
+                        values; ds_submit / lasso_submit: HOST, K values, copied at submit.
+                        The first iteration then starts from x_0 = u_0 = X_0 (l_0 = 1; the
+                        Chambolle-Pock dual iterate still starts at 0).  A non-finite entry
+                        makes the solve return DS_EINVAL.  The batched bfloat16 path (B > 1,
+                        DS_BF16 Lasso) returns DS_EINVAL when x0 is given. */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which
@@ -226,6 +234,10 @@ typedef struct {
   int32_t reserved;         /* must be 0 */
 } ds_server_config;
 
+/* Starts max_slots worker threads.  Failure-path testing: when the environment variable
+ * DS_SERVE_FAIL_REQUEST holds a request id at creation, that request's slot is marked
+ * failed once its solve has run; lasso_poll then returns DS_EDEVICE for it (no x), while
+ * every other request completes as it would have (host side only, no device fault). */
 ds_status ds_server_create(const ds_server_config* config, void** server);
 /* Copies D (device or host pointer, detected) into server memory, converting to `store`
  * precision (DS_F32 or DS_BF16 from DS_F32 input; same type otherwise), and computes and

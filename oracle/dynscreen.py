@@ -42,7 +42,8 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   ||D_t d||^2 / ||d||^2 (kept when d = 0), clamped to [1e-30, 1e30]; the stopping
   iteration changes L in neither case.  d is the unscreened step (atoms removed by
   this iteration's test are cleared afterwards).  L_0 defaults as for backtracking.
-* Initialisation X_0: x_0 = u_0 = 0 and l_0 = 1.
+* Initialisation X_0: x_0 = u_0 = 0 and l_0 = 1 by default; a caller's x0 gives
+  x_0 = u_0 = x0 (the input X_0 of Algorithm 3).
 * Dual scaling uses the correlations z_t = D_{t-1}^T theta_t of the current,
   already reduced dictionary, as the turnkey instance (Algorithm 5) does.
 * Stopping: the paper stops on a relative objective change.  Here the
@@ -366,8 +367,11 @@ def _bb_step(Dd, d, L):
 def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
                 max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic",
                 step="constant", eta=2.0, bb_memory=0, bb_sigma=1e-5, cp_tau=None,
-                cp_sigma=None, cp_gamma=0.0) -> OracleResult:
+                cp_sigma=None, cp_gamma=0.0, x0=None) -> OracleResult:
     """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
+
+    x0: the initial point X_0 of Algorithm 3 (default 0): x_0 = u_0 = x0, l_0 = 1 (the
+    Chambolle-Pock dual iterate still starts at 0).
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
     x_t = prox(p - z_t / L, lambda / L), FISTA momentum), the dual point
@@ -407,8 +411,8 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     screened = np.zeros(K, dtype=bool)          # I_0 = empty set
     active = np.arange(K)                       # complement of I_0
     Dt = D                                      # D_0 = D
-    x = np.zeros(K)                             # x_0
-    u = np.zeros(K)                             # u_0
+    x = np.zeros(K) if x0 is None else np.array(x0, dtype=np.float64)   # x_0
+    u = x.copy()                                # u_0
     l_prev = 1.0                                # l_0
     r_min = np.inf
     hist = []
@@ -526,8 +530,10 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
                       test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
                       record=False, screening="dynamic", step="constant",
                       eta=2.0, bb_memory=0, bb_sigma=1e-5, cp_tau=None, cp_sigma=None,
-                      cp_gamma=0.0) -> OracleResult:
+                      cp_gamma=0.0, x0=None) -> OracleResult:
     """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
+
+    x0: the initial point X_0 (default 0), as in solve_lasso.
 
     groups: a partition of range(K) (list of index arrays, or contiguous CSR
     offsets); w: group weights, default sqrt(|g|).  Tests: GSAFE (Lemma 4),
@@ -575,8 +581,8 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
 
     cols, local = layout(act_g)
     Dt = D[:, cols]
-    x = np.zeros(cols.size)
-    u = np.zeros(cols.size)
+    x = np.zeros(cols.size) if x0 is None else np.asarray(x0, dtype=np.float64)[cols]
+    u = x.copy()
     l_prev = 1.0
     r_min = np.inf
     hist = []

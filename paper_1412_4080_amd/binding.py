@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("step_L", C.c_double), ("gap_tol", C.c_double), ("max_iter", C.c_int32),
                 ("screening", C.c_int32), ("step_rule", C.c_int32), ("bt_eta", C.c_double),
                 ("bb_memory", C.c_int32), ("bb_sigma", C.c_double), ("cp_tau", C.c_double),
-                ("cp_sigma", C.c_double), ("cp_gamma", C.c_double)]
+                ("cp_sigma", C.c_double), ("cp_gamma", C.c_double), ("x0", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -179,21 +179,23 @@ SCREENING = {"dynamic": 0, "static": 1}
 
 def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap_tol=1e-6,
                 max_iter=10000, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
+                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0_ptr=None):
     return Params(RULES[rule], TESTS[test], 1 if lambda_relative else 0, float(step_L),
                   float(gap_tol), int(max_iter), SCREENING[screening], STEPS[step], float(bt_eta),
                   int(bb_memory), float(bb_sigma), float(cp_tau), float(cp_sigma),
-                  float(cp_gamma))
+                  float(cp_gamma), None if x0_ptr is None else C.c_void_p(x0_ptr))
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
           lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
           screened=False, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
+          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
-    lambda_relative).  Returns (X, infos) with X K x B column-major (or (K,) for 1-D Y);
+    lambda_relative); x0: optional warm start laid out as X (device, K x B column-major
+    with X's leading dimension, or (K,)).  Returns (X, infos) with X K x B column-major (or
+    (K,) for 1-D Y);
     with screened=True (Lasso only) returns (X, infos, mask), mask a K x B uint8 device
     tensor (1 = screened) from ds_solve_batch.
     """
@@ -213,11 +215,17 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     else:
         X = out.reshape(-1, 1) if out.dim() == 1 else out
     ldx = X.stride(1) if B > 1 else K
+    if x0 is not None:
+        x0c = x0.reshape(-1, 1) if x0.dim() == 1 else x0
+        if x0c.dtype != vdt or x0c.stride(0) != 1 or tuple(x0c.shape) != (K, B) or \
+                (B > 1 and x0c.stride(1) != ldx):
+            raise ValueError("x0 must have X's dtype, shape and layout")
     lam = (C.c_double * B)(*[float(v) for v in (lambdas if hasattr(lambdas, "__len__") else [lambdas])])
     infos = (Info * B)()
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
-                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma)
+                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
+                      None if x0 is None else x0.data_ptr())
     if screened:
         if group_ptr is not None:
             raise ValueError("screened masks of batched solves are for the Lasso")
@@ -239,13 +247,17 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
 def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="dst3",
               lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, trace=True,
               screened=True, stream=None, screening="dynamic", step="constant", bt_eta=0.0,
-              bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
-    """Single-signal solve returning (x, info, screened_mask or None, trace list or None)."""
+              bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None):
+    """Single-signal solve returning (x, info, screened_mask or None, trace list or None).
+    x0: optional warm start, a contiguous 1-D device tensor of K values (x's dtype)."""
     torch = _torch()
     K = D.shape[1]
     vdt = torch.float64 if D.dtype == torch.float64 else torch.float32
     if y.dtype != vdt or y.dim() != 1 or not y.is_contiguous():
         raise ValueError(f"y must be a contiguous 1-D {vdt} tensor")
+    if x0 is not None and (x0.dtype != vdt or x0.dim() != 1 or not x0.is_contiguous()
+                           or x0.numel() != K):
+        raise ValueError(f"x0 must be a contiguous 1-D {vdt} tensor of {K} values")
     x = torch.empty(K, dtype=vdt, device=y.device)
     scr = torch.empty(K, dtype=torch.uint8, device=y.device) if screened else None
     cap = int(max_iter) if trace else 0
@@ -253,7 +265,8 @@ def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="ds
     info = Info()
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
-                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma)
+                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
+                      None if x0 is None else x0.data_ptr())
     st = _lib.ds_solve_one(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam), C.byref(prm),
                            C.c_void_p(x.data_ptr()),
                            C.c_void_p(scr.data_ptr()) if scr is not None else None,
@@ -322,13 +335,19 @@ class Server:
 
     def submit(self, dict_id, y_host, lam, *, rule="fista", test="dst3", lambda_relative=True,
                step_L=0.0, gap_tol=1e-6, max_iter=10000, screening="dynamic", step="constant",
-               bt_eta=0.0, bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0):
+               bt_eta=0.0, bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0,
+               x0=None):
+        """x0: optional warm start on the host (K values), copied at submit."""
         import numpy as np
         N, K, dt, store = self._dicts[dict_id]
-        y = np.ascontiguousarray(y_host, dtype=np.float64 if store == 0 else np.float32)
+        vt = np.float64 if store == 0 else np.float32
+        y = np.ascontiguousarray(y_host, dtype=vt)
         assert y.size == N
+        x0h = None if x0 is None else np.ascontiguousarray(x0, dtype=vt)
+        assert x0h is None or x0h.size == K
         prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step,
-                          bt_eta, bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma)
+                          bt_eta, bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
+                          None if x0h is None else x0h.ctypes.data)
         rid = C.c_uint64()
         st = _lib.lasso_submit(self._h, int(dict_id), y.ctypes.data_as(C.c_void_p), float(lam),
                                C.byref(prm), C.byref(rid))

@@ -236,6 +236,10 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
       set_error("backtracking, SpaRSA and Chambolle-Pock are available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
     }
+    if (params->x0 != nullptr) {
+      set_error("a warm start (x0) is available on the single-signal path (B = 1 or FP32/FP64 D)");
+      return DS_EINVAL;
+    }
     return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, screened, s);
   }
   DeviceCtx& ctx = device_ctx(dev);
@@ -246,7 +250,9 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
     const char* yb = static_cast<const char*>(Y) + b * ldy * vsz;
     char* xb = static_cast<char*>(X) + b * ldx * vsz;
     std::memset(&info[b], 0, sizeof(ds_info));
-    e = solve_single(*problem, yb, lambdas[b], *params, xb, &info[b], s, ctx.ws, nullptr,
+    ds_params pb = *params;  // column b of the warm start, laid out as X
+    if (pb.x0 != nullptr) pb.x0 = static_cast<const char*>(params->x0) + b * ldx * vsz;
+    e = solve_single(*problem, yb, lambdas[b], pb, xb, &info[b], s, ctx.ws, nullptr,
                      screened != nullptr ? screened + b * problem->K : nullptr);
     if (e < 0) return e;
     if (e == DS_NOT_CONVERGED) worst = DS_NOT_CONVERGED;

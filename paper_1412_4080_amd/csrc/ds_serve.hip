@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -70,7 +71,7 @@ enum ReqState { QUEUED, RUNNING, DONE };
 struct Request {
   uint64_t id;
   int dict;
-  std::vector<char> y, x;
+  std::vector<char> y, x, x0;  // x0: the warm start when one was given (else empty)
   double lam;
   ds_params prm;
   size_t need;  // device bytes while it runs
@@ -95,10 +96,11 @@ size_t vec_size(ds_dtype t) { return t == DS_F64 ? 8 : 4; }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Device bytes a worker holds to run request r: the solver workspace (reserved with the
-// 25% headroom Workspace::reserve adds) plus y and x.
+// 25% headroom Workspace::reserve adds) plus y, x and the warm start.
 size_t request_need(const Dict& d, const ds_params& prm) {
   const size_t ws = single_workspace_bytes(d.view(), prm);
-  const size_t io = align256(d.N * vec_size(d.store)) + align256(d.K * vec_size(d.store));
+  const size_t xb = align256(d.K * vec_size(d.store));
+  const size_t io = align256(d.N * vec_size(d.store)) + xb + (prm.x0 != nullptr ? xb : 0);
   return ws + ws / 4 + io;
 }
 
@@ -115,6 +117,11 @@ struct Server {
   uint64_t next_id = 1;
   size_t held = 0;  // sum of the workers' charged bytes
   bool stop = false;
+  // Failure injection for tests of the failure path: the request with this id (0: none,
+  // read from DS_SERVE_FAIL_REQUEST at creation) has its slot marked failed after its solve
+  // ran; it completes with DS_EDEVICE and no x, the other requests are unaffected.  Host
+  // side only: no device fault is involved.
+  uint64_t fail_request = 0;
   std::vector<std::unique_ptr<Worker>> workers;
   hipStream_t admin = nullptr;  // registration work
 
@@ -126,36 +133,47 @@ void Server::run(Worker* w, Request* r, const Dict& d) {
   const ds_problem P = d.view();
   const size_t vsz = vec_size(d.store);
   const size_t yb = align256(d.N * vsz), xb = align256(d.K * vsz);
+  const size_t x0b = r->x0.empty() ? 0 : xb;
   auto fail = [&](ds_status st) {
     r->status = st;
     r->error = ds_last_error();
   };
-  if (w->io_bytes < yb + xb) {
+  if (w->io_bytes < yb + xb + x0b) {
     if (w->io != nullptr) {
       (void)hipStreamSynchronize(w->stream);
       (void)hipFree(w->io);
       w->io = nullptr;
       w->io_bytes = 0;
     }
-    if (hipMalloc(&w->io, yb + xb) != hipSuccess) {
+    if (hipMalloc(&w->io, yb + xb + x0b) != hipSuccess) {
       (void)hipGetLastError();
-      set_error("hipMalloc of %zu request bytes failed", yb + xb);
+      set_error("hipMalloc of %zu request bytes failed", yb + xb + x0b);
       return fail(DS_ENOMEM);
     }
-    w->io_bytes = yb + xb;
+    w->io_bytes = yb + xb + x0b;
   }
   char* y = static_cast<char*>(w->io);
   char* x = y + yb;
-  if (hipMemcpyAsync(y, r->y.data(), d.N * vsz, hipMemcpyHostToDevice, w->stream) != hipSuccess) {
-    set_error("upload of y failed");
+  char* x0 = x + xb;
+  if (hipMemcpyAsync(y, r->y.data(), d.N * vsz, hipMemcpyHostToDevice, w->stream) != hipSuccess ||
+      (x0b > 0 && hipMemcpyAsync(x0, r->x0.data(), d.K * vsz, hipMemcpyHostToDevice, w->stream) !=
+                      hipSuccess)) {
+    set_error("upload of y or x0 failed");
     return fail(DS_EDEVICE);
   }
   ds_params prm = r->prm;
+  prm.x0 = x0b > 0 ? x0 : nullptr;
   if (!(prm.step_L > 0.0) && prm.step_rule == DS_STEP_CONSTANT && prm.rule != DS_SPARSA)
     prm.step_L = d.L;
   ds_info info{};
   const ds_status st = solve_single(P, y, r->lam, prm, x, &info, w->stream, w->ws, nullptr);
   if (st < 0) return fail(st);
+  if (r->id == fail_request) {
+    (void)hipStreamSynchronize(w->stream);
+    set_error("the slot of request %llu was marked failed (DS_SERVE_FAIL_REQUEST)",
+              static_cast<unsigned long long>(r->id));
+    return fail(DS_EDEVICE);
+  }
   r->x.resize(d.K * vsz);
   if (hipMemcpyAsync(r->x.data(), x, d.K * vsz, hipMemcpyDeviceToHost, w->stream) != hipSuccess ||
       hipStreamSynchronize(w->stream) != hipSuccess) {
@@ -259,14 +277,20 @@ ds_status submit_impl(void* server, int32_t dict_id, const void* y_host, double 
   r->dict = dict_id;
   const size_t vsz = vec_size(d.store);
   r->y.assign(static_cast<const char*>(y_host), static_cast<const char*>(y_host) + d.N * vsz);
+  if (params->x0 != nullptr)
+    r->x0.assign(static_cast<const char*>(params->x0), static_cast<const char*>(params->x0) + d.K * vsz);
   r->lam = lambda;
   r->prm = *params;
+  r->prm.x0 = nullptr;  // the copy above is uploaded by the worker
   r->need = need;
   r->t_submit = Clock::now();
   *request_id = r->id;
   S->queue.push_back(r->id);
   S->reqs.emplace(r->id, std::move(r));
-  S->cv_work.notify_one();
+  // every worker looks: an idle worker that still holds memory must see a request that
+  // does not fit next to it (and give the memory back), which a worker holding nothing
+  // woken alone would leave waiting
+  S->cv_work.notify_all();
   return DS_OK;
 }
 
@@ -296,6 +320,7 @@ ds_status ds_server_create(const ds_server_config* config, void** server) {
   DS_HIP(hipSetDevice(config->device));
   auto S = std::make_unique<Server>();
   S->cfg = *config;
+  if (const char* f = std::getenv("DS_SERVE_FAIL_REQUEST")) S->fail_request = std::strtoull(f, nullptr, 10);
   DS_HIP(hipStreamCreateWithFlags(&S->admin, hipStreamNonBlocking));
   for (int k = 0; k < config->max_slots; ++k) {
     auto w = std::make_unique<Worker>();

@@ -282,7 +282,8 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, lam,
                      relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z, eta,
                      RULE == RULE_SPARSA ? prm.bb_memory : 0,
-                     prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5, cp_tau, cp_sigma, prm.cp_gamma);
+                     prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5, cp_tau, cp_sigma, prm.cp_gamma,
+                     prm.x0 != nullptr ? 1 : 0);
   DS_HIP(hipGetLastError());
   if (prm.test == DS_TEST_DST3 || prm.test == DS_TEST_DOME) {
     hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
@@ -299,6 +300,11 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   DS_HIP(hipGetLastError());
   hipLaunchKernelGGL((k_setup_slack<T, V, A>), dim3(1), dim3(CBLK), 0, s, a);
   DS_HIP(hipGetLastError());
+  if (prm.x0 != nullptr) {  // warm start: x_0 = u_0 = x0 and its support records
+    hipLaunchKernelGGL((k_warm_seed<T, V, A>), dim3(grid_for(units, BLK, 1 << 20)), dim3(BLK), 0, s,
+                       a, static_cast<const V*>(prm.x0));
+    DS_HIP(hipGetLastError());
+  }
 
   // ---- iterations ----
   constexpr int VR = VEC ? Store<T>::VEC : 1;
@@ -440,7 +446,8 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   if (tele_out) *tele_out = std::move(tl);
 
   if (hst->status < 0) {
-    set_error("observation contains NaN or Inf");
+    set_error(prm.x0 != nullptr ? "observation or initial point contains NaN or Inf"
+                                : "observation contains NaN or Inf");
     return DS_EINVAL;
   }
   info->iters = hst->iter;
@@ -516,7 +523,7 @@ ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t
                                : launch_setup_corr<T, false>(P, y, base, l, s);
   if (e != DS_OK) return e;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, 1.0, 1, 1.0, 0.0,
-                     1, 0.0, 0.0, 0, 1e-5, 1.0, 1.0, 0.0);
+                     1, 0.0, 0.0, 0, 1e-5, 1.0, 1.0, 0.0, 0);
   DS_HIP(hipGetLastError());
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));

@@ -443,7 +443,7 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
                                                          double gamma_z, double bt_eta,
                                                          int bb_mem, double bb_sigma,
                                                          double cp_tau, double cp_sigma,
-                                                         double cp_gamma) {
+                                                         double cp_gamma, int warm) {
   __shared__ double sd[CNW];
   __shared__ int si[CNW];
   __shared__ double s_lmax;
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     st->bb_mem = bb_mem;
     st->phi_n = 0;
     st->bb_new = 1;
-    st->bb_pad = 0;
+    st->warm = warm;
     st->bb_sigma = bb_sigma;
     for (int j = 0; j <= BB_MEM_MAX; ++j) st->phi_mem[j] = 0.0;
     st->cp_tau = cp_tau;
@@ -715,6 +715,15 @@ __global__ __launch_bounds__(CBLK) void k_setup_slack(SingleArgs<T, V, A> a) {
   }
 }
 
+// Warm start (the initial point X_0 of Algorithm 3): x = u = x0 on every atom, and the
+// support records of the first residual pass written as a correlation pass over the
+// initial list (unit i in block i / units-per-block, every unit kept, in order) would
+// write them, so that theta_1 = D x0 - y and Omega(x0) come out of the ordinary residual
+// pass.  Run after k_setup_margins (which clears x and u).  A non-finite entry marks the
+// instance invalid.  One thread per unit.
+template <typename T, typename V, typename A>
+__global__ __launch_bounds__(BLK) void k_warm_seed(SingleArgs<T, V, A> a, const V* __restrict__ x0);
+
 // ============================================================== iteration kernels ===
 //
 // Iteration t runs two kernels.  k_resid(t) forms theta_t = D p_{t-1} - y (p = x for
@@ -736,6 +745,52 @@ constexpr int SGL = 32;               // correlation segments per residual item 
 constexpr int SGG = 32;               // correlation blocks per residual item (groups)
 constexpr int LCAP = 512;             // residual list entries streamed per chunk
 constexpr int MAXITEM = 8192;         // residual segment groups
+
+template <typename T, typename V, typename A>
+__global__ __launch_bounds__(BLK) void k_warm_seed(SingleArgs<T, V, A> a, const V* __restrict__ x0) {
+  const int units = a.G > 0 ? a.G : a.K;
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  if (i >= units) return;
+  bool bad = false;
+  if (a.G > 0) {
+    const int b = i / CBG, j = i % CBG;
+    const int64_t g0 = a.gptr[i], g1 = a.gptr[i + 1];
+    double s2 = 0.0;
+    for (int64_t k = g0; k < g1; ++k) {
+      const V v = x0[k];
+      const double d = static_cast<double>(v);
+      if (!isfinite(d)) bad = true;
+      s2 = fma(d, d, s2);
+      a.x[k] = v;
+      a.u[k] = v;
+      const int64_t slot = static_cast<int64_t>(b) * SEGCAP_G + j * GMAX + (k - g0);
+      a.seg_atom[slot] = static_cast<int32_t>(k);
+      a.seg_val[slot] = v;
+    }
+    const int64_t rec = static_cast<int64_t>(b) * CBG + j;
+    a.urec_marg[rec] = a.marg[i];
+    a.urec_om[rec] = a.w[i] * sqrt(s2);
+    a.urec_m[rec] = static_cast<int32_t>(g1 - g0);
+    if (j == 0) a.seg_cnt[b] = min(CBG, units - b * CBG);
+  } else {
+    const int b = i / CBL, k = i % CBL;
+    const V v = x0[i];
+    const double d = static_cast<double>(v);
+    if (!isfinite(d)) bad = true;
+    a.x[i] = v;
+    a.u[i] = v;
+    const int64_t slot = static_cast<int64_t>(b) * SEGCAP_L + k;
+    a.seg_atom[slot] = i;
+    a.seg_val[slot] = v;
+    a.urec_marg[slot] = a.marg[i];
+    a.urec_om[slot] = fabs(d);
+    if (k == 0) a.seg_cnt[b] = min(CBL, units - b * CBL);
+  }
+  if (bad) {  // every writer stores the same values
+    a.st->status = -1;
+    a.st->done = 1;
+  }
+}
 
 // FP64 scalars of one iteration from the reduced partials (same arithmetic in every
 // block): dual scaling (Lemma 7), dual point v = mu theta, gap certificate, radius of
@@ -1179,7 +1234,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     a.counters[CNT_VID] = 0u;  // the correlation pass that used it has ended
   }
   const double r_keep = S.r_scr + S.marg_slack;
-  const bool have_support = S.iter > 0;  // p_0 = 0
+  const bool have_support = S.iter > 0 || S.warm;  // p_0 = 0 unless a warm start seeded it
   if (!have_support) {  // theta = -y, Omega(p_0) = 0
     if (static_cast<int>(blockIdx.x) < nrt)
       resid_finish_tile<T, V, VECTOR, RULE == RULE_CP>(a, blockIdx.x, 0, sd, S.cp_sigma, true);
@@ -1274,7 +1329,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       }
     }
     if (arrive_last(&a.rt_cnt[rt], static_cast<unsigned>(nsg), &s_last))
-      resid_finish_tile<T, V, VECTOR, RULE == RULE_CP>(a, rt, nsg, sd, S.cp_sigma, false);
+      resid_finish_tile<T, V, VECTOR, RULE == RULE_CP>(a, rt, nsg, sd, S.cp_sigma, S.iter == 0);
     __syncthreads();
   }
 }

@@ -58,7 +58,7 @@ struct alignas(16) SolverState {
   int32_t bb_mem;      // earlier iterates kept
   int32_t phi_n;       // entries in phi_mem
   int32_t bb_new;      // 1: the primal point of the next scalar stage is a new iterate
-  int32_t bb_pad;
+  int32_t warm;        // 1: the first pass starts from a caller's x_0 (its support is seeded)
   double bb_sigma;     // sufficient-decrease constant
   double phi_mem[BB_MEM_MAX + 1];
   // Chambolle-Pock: current primal and dual steps, acceleration

@@ -98,6 +98,7 @@ def test_batched_solve_to_tolerance_is_certified(B):
         cert, gstar = oracle.certified_inactive_lasso(Dbf, y, star.lam, star.x)
         assert gstar < 1e-11
         assert np.all(cert[mask[:, j]]), np.flatnonzero(mask[:, j] & ~cert)[:10]
+        assert not star.x[mask[:, j]].any()
         assert not X[mask[:, j], j].any()
         # the MFMA run stops where the FP64 run's gap reaches tolerance (within the bracket
         # of its oscillating gap)

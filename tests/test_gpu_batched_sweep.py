@@ -66,4 +66,5 @@ def test_random_batch(B, i):
         cert, _ = oracle.certified_inactive_lasso(Dbf, yb, lam, star.x)
         scr = mask[:, b]
         assert np.all(cert[scr]), (b, np.flatnonzero(scr & ~cert)[:10])
+        assert not star.x[scr].any()
         assert not xb[scr].any()

@@ -84,6 +84,7 @@ def test_fp32_to_gap_is_certified(B, ratio):
     assert p_x == pytest.approx(info["primal"], rel=1e-5)   # the returned point is the certified one
     cert, _ = oracle.certified_inactive_lasso(Di, yi, ref.lam, star.x)
     assert np.all(cert[scr.cpu().numpy().astype(bool)])
+    assert not star.x[scr.cpu().numpy().astype(bool)].any()
     assert abs(info["iters"] - ref.iters) <= max(5, ref.iters // 10)
 
 

@@ -93,4 +93,5 @@ def test_random_case(B, i):
     assert star.converged
     assert p_x - star.primal <= 1.01e-6 * yy + 1e-12
     assert np.all(cert[scr]), np.flatnonzero(scr & ~cert)[:10]
+    assert not star.x[scr].any()
     assert not xs[scr].any()
