@@ -210,6 +210,27 @@ ds_status ds_solve_batch(const ds_problem* problem, const void* Y, int64_t B, in
                          const double* lambdas, const ds_params* params, void* X, int64_t ldx,
                          ds_info* info, uint8_t* screened, void* stream);
 
+/* For callers that cannot allocate device memory (code being captured into a HIP graph,
+ * serving loops and harnesses that forbid allocation): ds_solve_one without the trace,
+ * whose workspace is a fixed library-owned device array of DS_NOALLOC_SCRATCH_MB MiB per
+ * device (held from library load until the process ends) and whose state is read back
+ * through a static host buffer, so the call allocates nothing.  Arguments, outputs and
+ * results are those of ds_solve_one (the same kernels run), with two restrictions:
+ *   - a constant step (DS_STEP_CONSTANT with DS_ISTA, DS_FISTA or DS_CP) needs step_L > 0
+ *     (estimating ||D||_2^2 would need a workspace of its own): else DS_EINVAL;
+ *   - the problem's workspace must fit the array (for the Lasso about 140 bytes per
+ *     atom, 8 N ceil(K / 512) bytes, 40 bytes per iteration of max_iter and 1.2 MB): a
+ *     larger problem gets DS_EINVAL before any device work, with the size it needs in
+ *     ds_last_error().
+ * All calls on one device share the array: they are serialised inside the library, and the
+ * array keeps the last call's contents (each solve clears what must start at zero).  Calls
+ * on one device issued from separate processes, or re-entered from a stream callback,
+ * would race on it. */
+#define DS_NOALLOC_SCRATCH_MB 64
+ds_status ds_solve_one_noalloc(const ds_problem* problem, const void* y, double lambda,
+                               const ds_params* params, void* x, uint8_t* screened,
+                               ds_info* info, void* stream);
+
 /* lambda_* of a single signal y (device, length N) and the first index attaining it
  * (atom index for the Lasso, group index for the Group-Lasso); FP64 accumulation. */
 ds_status ds_lambda_max(const ds_problem* problem, const void* y, double* lambda_max,

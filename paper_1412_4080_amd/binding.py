@@ -81,6 +81,8 @@ _sig = {
                                  C.c_void_p]),
     "ds_solve_one": (C.c_int, [_P(Problem), C.c_void_p, C.c_double, _P(Params), C.c_void_p,
                                C.c_void_p, _P(Trace), C.c_int32, _P(Info), C.c_void_p]),
+    "ds_solve_one_noalloc": (C.c_int, [_P(Problem), C.c_void_p, C.c_double, _P(Params),
+                                       C.c_void_p, C.c_void_p, _P(Info), C.c_void_p]),
     "ds_lambda_max": (C.c_int, [_P(Problem), C.c_void_p, _P(C.c_double), _P(C.c_int64),
                                 C.c_void_p]),
     "ds_spectral_norm_sq": (C.c_int, [_P(Problem), C.c_int32, _P(C.c_double), C.c_void_p]),
@@ -279,6 +281,35 @@ def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="ds
         trace_list = [dict(n_active=t.n_active, n_units=t.n_units, n_support=t.n_support,
                            nnz=t.nnz, radius=t.radius, gap=t.gap) for t in tr[:n]]
     return x, inf, scr, trace_list
+
+
+def solve_one_noalloc(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="dst3",
+                      lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000,
+                      screened=True, stream=None, screening="dynamic", step="constant",
+                      bt_eta=0.0, bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0,
+                      cp_gamma=0.0, x0=None, out=None, screened_out=None):
+    """ds_solve_one_noalloc: the single-signal solve on the library's fixed scratch array
+    (no device allocation inside the call).  Returns (x, info, screened_mask or None); x and
+    the mask are written into `out` / `screened_out` when given."""
+    torch = _torch()
+    K = D.shape[1]
+    vdt = torch.float64 if D.dtype == torch.float64 else torch.float32
+    if y.dtype != vdt or y.dim() != 1 or not y.is_contiguous():
+        raise ValueError(f"y must be a contiguous 1-D {vdt} tensor")
+    x = out if out is not None else torch.empty(K, dtype=vdt, device=y.device)
+    scr = screened_out if screened_out is not None else (
+        torch.empty(K, dtype=torch.uint8, device=y.device) if screened else None)
+    info = Info()
+    prob = make_problem(D, group_ptr, weights)
+    prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
+                      bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
+                      None if x0 is None else x0.data_ptr())
+    st = _lib.ds_solve_one_noalloc(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam),
+                                   C.byref(prm), C.c_void_p(x.data_ptr()),
+                                   C.c_void_p(scr.data_ptr()) if scr is not None else None,
+                                   C.byref(info), _stream_ptr(stream))
+    _check(st, "ds_solve_one_noalloc")
+    return x, info.as_dict(), scr
 
 
 def lambda_max(D, y, *, group_ptr=None, weights=None, stream=None):

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdynscreen.so")
-SOURCES = ["ds_api.hip", "ds_single.hip", "ds_batched.hip", "ds_serve.hip"]
+SOURCES = ["ds_api.hip", "ds_single.hip", "ds_batched.hip", "ds_serve.hip", "ds_noalloc.hip"]
 
 
 def hipcc() -> str:

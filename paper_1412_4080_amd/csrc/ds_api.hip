@@ -36,6 +36,7 @@ Workspace::~Workspace() {
 }
 
 void Workspace::release() {
+  if (fixed) return;  // memory owned elsewhere
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   events.clear();
   if (base != nullptr) (void)hipFree(base);
@@ -46,6 +47,11 @@ void Workspace::release() {
 }
 
 ds_status Workspace::reserve(size_t need) {
+  if (fixed) {
+    if (need <= bytes && base != nullptr && host_pinned != nullptr) return DS_OK;
+    set_error("the problem needs %zu bytes of scratch memory; this entry point has %zu", need, bytes);
+    return DS_EINVAL;
+  }
   if (host_pinned == nullptr) {
     if (hipHostMalloc(&host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
       host_pinned = nullptr;

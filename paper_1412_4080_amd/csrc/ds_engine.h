@@ -47,12 +47,15 @@ struct StatAccum {
 };
 StatAccum& stats();
 
-// One device allocation carved into the buffers of a single-signal solve.
+// One device allocation carved into the buffers of a single-signal solve.  A fixed
+// workspace is memory the library does not own (base, bytes and a host staging area set
+// by its owner): reserve() never allocates and refuses a larger need.
 struct Workspace {
   int device = -1;
   void* base = nullptr;
   size_t bytes = 0;
-  void* host_pinned = nullptr;  // small pinned staging area for the state
+  void* host_pinned = nullptr;  // small (pinned, unless fixed) staging area for the state
+  bool fixed = false;
   std::vector<hipEvent_t> events;
   ~Workspace();
   ds_status reserve(size_t need);

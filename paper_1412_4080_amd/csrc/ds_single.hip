@@ -174,15 +174,28 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
 }
 
-// Upload group offsets and weights (default w_g = sqrt(|g|)) into the workspace.
-ds_status upload_groups(const ds_problem& P, char* base, const Layout& l, hipStream_t s,
-                        std::vector<double>& wbuf) {
+// Upload group offsets and weights into the workspace (default w_g = sqrt(|g|), formed on
+// the device).  The copies read the caller's host arrays, which outlive the call.
+ds_status upload_groups(const ds_problem& P, char* base, const Layout& l, hipStream_t s) {
   if (P.G <= 0) return DS_OK;
-  wbuf.resize(P.G);
-  for (int64_t g = 0; g < P.G; ++g)
-    wbuf[g] = P.w ? P.w[g] : std::sqrt(static_cast<double>(P.group_ptr[g + 1] - P.group_ptr[g]));
   DS_HIP(hipMemcpyAsync(base + l.off_gptr, P.group_ptr, (P.G + 1) * 8, hipMemcpyHostToDevice, s));
-  DS_HIP(hipMemcpyAsync(base + l.off_w, wbuf.data(), P.G * 8, hipMemcpyHostToDevice, s));
+  if (P.w != nullptr) {
+    DS_HIP(hipMemcpyAsync(base + l.off_w, P.w, P.G * 8, hipMemcpyHostToDevice, s));
+  } else {
+    hipLaunchKernelGGL(k_default_weights, dim3(grid_for(P.G, BLK, 1 << 20)), dim3(BLK), 0, s,
+                       reinterpret_cast<const int64_t*>(base + l.off_gptr), static_cast<int>(P.G),
+                       reinterpret_cast<double*>(base + l.off_w));
+    DS_HIP(hipGetLastError());
+  }
+  return DS_OK;
+}
+
+// Zero `bytes` (a multiple of 4) at p with the fill kernel.
+ds_status zero_words(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(bytes / 4);
+  hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, BLK, 1024)), dim3(BLK), 0, s,
+                     static_cast<uint32_t*>(p), n);
+  DS_HIP(hipGetLastError());
   return DS_OK;
 }
 
@@ -241,11 +254,10 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   a.tele = tele;
   a.tele_cap = static_cast<int32_t>(tele_cap);
   a.screen_static = prm.screening;
-  std::vector<double> wbuf;
-  if ((st_ = upload_groups(P, base, l, s, wbuf)) != DS_OK) return st_;
-  DS_HIP(hipMemsetAsync(a.counters, 0, 32 * 4, s));
-  DS_HIP(hipMemsetAsync(a.rt_cnt, 0, MAXRT * 4, s));
-  DS_HIP(hipMemsetAsync(a.lbA, 0, MAXB * 8, s));
+  if ((st_ = upload_groups(P, base, l, s)) != DS_OK) return st_;
+  if ((st_ = zero_words(a.counters, 32 * 4, s)) != DS_OK) return st_;
+  if ((st_ = zero_words(a.rt_cnt, MAXRT * 4, s)) != DS_OK) return st_;
+  if ((st_ = zero_words(a.lbA, MAXB * 8, s)) != DS_OK) return st_;
 
   // ---- setup (no host synchronisation) ----
   if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
@@ -258,11 +270,15 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   const bool bt = line_search || RULE == RULE_CP;
   const double eta = line_search ? (prm.bt_eta > 0.0 ? prm.bt_eta : 2.0) : 0.0;
   a.bt = bt ? 1 : 0;
-  DS_HIP(hipMemsetAsync(a.bpd, 0, 2 * MAXB * 8, s));
-  DS_HIP(hipMemsetAsync(a.rtr, 0, 2 * MAXRT * 8, s));
-  DS_HIP(hipMemsetAsync(a.dtn, 0, MAXRT * 8, s));
+  if ((st_ = zero_words(a.bpd, 2 * MAXB * 8, s)) != DS_OK) return st_;
+  if ((st_ = zero_words(a.rtr, 2 * MAXRT * 8, s)) != DS_OK) return st_;
+  if ((st_ = zero_words(a.dtn, MAXRT * 8, s)) != DS_OK) return st_;
   double L = prm.step_L;
   if (!(L > 0.0) && !line_search) {
+    if (ws.fixed) {  // the estimate would need a workspace of its own
+      set_error("the step constant must be given (step_L > 0) on this entry point");
+      return DS_EINVAL;
+    }
     // the power iteration uses its own (larger) workspace; keep ours intact by running it
     // on a private one
     Workspace tmp;
@@ -320,7 +336,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   bool stat_on;
   {
     std::lock_guard<std::mutex> g(S.mu);
-    stat_on = S.on;
+    stat_on = S.on && !ws.fixed;  // a fixed workspace creates no events
   }
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   // instrumented runs: each correlation block stamps the device wall clock at its start
@@ -516,8 +532,7 @@ ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t
   ds_status e = ws.reserve(l.total);
   if (e != DS_OK) return e;
   char* base = static_cast<char*>(ws.base);
-  std::vector<double> wbuf;
-  if ((e = upload_groups(P, base, l, s, wbuf)) != DS_OK) return e;
+  if ((e = upload_groups(P, base, l, s)) != DS_OK) return e;
   SingleArgs<T, V, A> a = make_args<T>(P, y, base, l, TEST_NONE, RULE_ISTA);
   e = vector_ok<T>(P.D, P.ldd) ? launch_setup_corr<T, true>(P, y, base, l, s)
                                : launch_setup_corr<T, false>(P, y, base, l, s);

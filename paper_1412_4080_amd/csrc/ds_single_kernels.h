@@ -2007,6 +2007,20 @@ __global__ __launch_bounds__(BLK) void k_pow_scale(const double* __restrict__ sr
   const double nb = sqrt(dots[2]);
   dst[i] = nb > 0.0 ? src[i] / nb : 0.0;
 }
+// Zero n 32-bit words (counters and partials that must start at zero: a kernel rather than
+// a memset, so that the clearing is an ordinary kernel node if a caller captures the work).
+__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+// Default group weights w_g = sqrt(|g|) (the Group-Lasso section's choice).
+__global__ void k_default_weights(const int64_t* __restrict__ gptr, int G, double* __restrict__ w) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < G) w[g] = sqrt(static_cast<double>(gptr[g + 1] - gptr[g]));
+}
+
 __global__ void k_fill(double* __restrict__ v, int n, double val) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = val;
