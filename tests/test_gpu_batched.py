@@ -6,7 +6,8 @@ import pytest
 
 import oracle
 from paper_1412_4080_amd import datagen
-from tests._util import dev_matrix, lasso_margins_ref, rel_err, stop_iteration_bracket
+from tests._util import (GAP_DELTA_BATCHED, dev_matrix, lasso_margins_ref, rel_err,
+                         stop_iteration_bracket)
 
 pytestmark = pytest.mark.gpu
 
@@ -102,7 +103,8 @@ def test_batched_solve_to_tolerance_is_certified(B):
         assert not X[mask[:, j], j].any()
         # the MFMA run stops where the FP64 run's gap reaches tolerance (within the bracket
         # of its oscillating gap)
-        t_lo, t_hi = stop_iteration_bracket(Dbf, y, info["lambda_"], L, 1e-6 * yy)
+        t_lo, t_hi = stop_iteration_bracket(Dbf, y, info["lambda_"], L, 1e-6 * yy,
+                                            delta=GAP_DELTA_BATCHED)
         assert t_lo <= info["iters"] <= t_hi, (j, info["iters"], t_lo, t_hi)
 
 

@@ -4,8 +4,9 @@ import pytest
 
 import oracle
 from paper_1412_4080_amd import datagen
-from tests._util import (dev_matrix, dev_vector, group_margins_ref, instance, lasso_margins_ref,
-                         rel_err, screened_sets_agree, stop_iteration_bracket)
+from tests._util import (GAP_DELTA_SINGLE, dev_matrix, dev_vector, gap_difference_near_stop,
+                         group_margins_ref, instance, lasso_margins_ref, rel_err,
+                         screened_sets_agree, stop_iteration_bracket)
 
 pytestmark = pytest.mark.gpu
 
@@ -116,7 +117,13 @@ def test_fp32_solve_to_tolerance_is_certified(B, ratio, test):
     assert gstar < 1e-11
     assert np.all(cert[scr]), np.flatnonzero(scr & ~cert)[:10]
     assert not star.x[scr].any()
-    t_lo, t_hi = stop_iteration_bracket(Di, yi, info["lambda_"], L, 1e-6 * float(yi @ yi))
+    # the device gap stays within GAP_DELTA_SINGLE tol of the oracle's near the stop, so the
+    # stopping iteration lies in the bracket that bound implies
+    tol_abs = 1e-6 * float(yi @ yi)
+    ref = oracle.solve_lasso(Di, yi, lam=info["lambda_"], rule="fista", test=test, L=L,
+                             max_iter=info["iters"], gap_tol=0.0, record=True)
+    assert gap_difference_near_stop(tr, ref.history, tol_abs) <= GAP_DELTA_SINGLE * tol_abs
+    t_lo, t_hi = stop_iteration_bracket(Di, yi, info["lambda_"], L, tol_abs, test=test)
     assert t_lo <= info["iters"] <= t_hi, (info["iters"], t_lo, t_hi)
 
 
