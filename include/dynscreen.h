@@ -139,6 +139,11 @@ typedef struct {
                         Chambolle-Pock dual iterate still starts at 0).  A non-finite entry
                         makes the solve return DS_EINVAL.  The batched bfloat16 path (B > 1,
                         DS_BF16 Lasso) returns DS_EINVAL when x0 is given. */
+  double obj_tol;    /* >= 0.  > 0: also stop once the primal objective of the certified point
+                        changes by at most obj_tol relative between two consecutive iterations
+                        (|P_{t-1} - P_t| <= obj_tol P_t), the stopping rule of the paper's
+                        experiments section (there with 1e-7 and max_iter = 200).  Such a
+                        stop returns DS_OK.  The batched bfloat16 path returns DS_EINVAL. */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which

@@ -34,5 +34,7 @@ from .dynscreen import (  # noqa: F401
     certified_inactive_lasso,
     certified_inactive_group,
     flops_dynamic,
+    flops_none,
+    flops_static,
 )
 from .brute import brute_force_lasso  # noqa: F401

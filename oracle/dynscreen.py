@@ -46,7 +46,9 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   x_0 = u_0 = x0 (the input X_0 of Algorithm 3).
 * Dual scaling uses the correlations z_t = D_{t-1}^T theta_t of the current,
   already reduced dictionary, as the turnkey instance (Algorithm 5) does.
-* Stopping: the paper stops on a relative objective change.  Here the
+* Stopping: the paper's experiments stop after 200 iterations or when the objective's
+  relative change falls below 1e-7; that rule is available (obj_tol, on the objective of
+  the certified primal point of consecutive iterations).  By default the
   iteration stops when the duality gap between the primal point at which
   theta_t was evaluated (x_{t-1} for ISTA, u_{t-1} for FISTA) and the dual
   point v_t falls below gap_tol * ||y||^2, or after max_iter iterations.  The
@@ -367,11 +369,14 @@ def _bb_step(Dd, d, L):
 def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=None,
                 max_iter=1000, gap_tol=1e-6, record=False, screening="dynamic",
                 step="constant", eta=2.0, bb_memory=0, bb_sigma=1e-5, cp_tau=None,
-                cp_sigma=None, cp_gamma=0.0, x0=None) -> OracleResult:
+                cp_sigma=None, cp_gamma=0.0, x0=None, obj_tol=0.0) -> OracleResult:
     """Lasso (equation (lasso)) by Algorithm 3 with the ISTA or FISTA update of Table 1.
 
     x0: the initial point X_0 of Algorithm 3 (default 0): x_0 = u_0 = x0, l_0 = 1 (the
     Chambolle-Pock dual iterate still starts at 0).
+    obj_tol > 0 adds the stopping rule of the experiments section: stop once the objective
+    of the certified primal point changes by at most obj_tol relative between two
+    consecutive accepted iterations.
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
     x_t = prox(p - z_t / L, lambda / L), FISTA momentum), the dual point
@@ -422,6 +427,7 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         sigma = float(cp_sigma) if cp_sigma else 1.0 / (tau * L)
         theta_cp = np.zeros(N)
     converged = False
+    primal_prev, prev_accepted = 0.0, True      # the objective-change rule (obj_tol)
     for t in range(1, max_iter + 1):
         # ---- optimisation update (Table 1) ----
         p = u if rule in ("fista", "cp") else x
@@ -483,7 +489,10 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
                 hist[-1].update(phi_new=phi_new, phi_ref=max(phis))
             if rule == "cp":
                 hist[-1].update(theta=theta.copy(), tau=tau, sigma=sigma, x_prev=x.copy())
-        converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
+        obj_stop = (obj_tol > 0.0 and accepted and prev_accepted and t > 1
+                    and abs(primal_prev - primal_p) <= obj_tol * primal_p)
+        primal_prev, prev_accepted = primal_p, accepted
+        converged = (gap_tol > 0.0 and gap <= gap_tol * yy and accepted) or obj_stop
         if not accepted:
             # rejected step: keep p, grow L; at the iteration limit return the last accepted x
             x_new, u_new, l_new = x, u, l_prev
@@ -530,10 +539,10 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
                       test="dgst3", L=None, max_iter=1000, gap_tol=1e-6,
                       record=False, screening="dynamic", step="constant",
                       eta=2.0, bb_memory=0, bb_sigma=1e-5, cp_tau=None, cp_sigma=None,
-                      cp_gamma=0.0, x0=None) -> OracleResult:
+                      cp_gamma=0.0, x0=None, obj_tol=0.0) -> OracleResult:
     """Group-Lasso (equation (group-lasso)) by Algorithm 3 with ISTA / FISTA.
 
-    x0: the initial point X_0 (default 0), as in solve_lasso.
+    x0: the initial point X_0 (default 0) and obj_tol, as in solve_lasso.
 
     groups: a partition of range(K) (list of index arrays, or contiguous CSR
     offsets); w: group weights, default sqrt(|g|).  Tests: GSAFE (Lemma 4),
@@ -592,6 +601,7 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         sigma = float(cp_sigma) if cp_sigma else 1.0 / (tau * L)
         theta_cp = np.zeros(N)
     converged = False
+    primal_prev, prev_accepted = 0.0, True      # the objective-change rule (obj_tol)
     for t in range(1, max_iter + 1):
         wa = w[act_g]
         p = u if rule in ("fista", "cp") else x
@@ -655,7 +665,10 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
                 hist[-1].update(phi_new=phi_new, phi_ref=max(phis))
             if rule == "cp":
                 hist[-1].update(theta=theta.copy(), tau=tau, sigma=sigma, x_prev=x.copy())
-        converged = gap_tol > 0.0 and gap <= gap_tol * yy and accepted
+        obj_stop = (obj_tol > 0.0 and accepted and prev_accepted and t > 1
+                    and abs(primal_prev - primal_p) <= obj_tol * primal_p)
+        primal_prev, prev_accepted = primal_p, accepted
+        converged = (gap_tol > 0.0 and gap <= gap_tol * yy and accepted) or obj_stop
         if not accepted:
             x_new, u_new, l_new = x, u, l_prev
             if t < max_iter:
@@ -739,6 +752,31 @@ def certified_inactive_group(D, y, lam, x, groups, w=None):
     for k in np.flatnonzero(gmask):
         amask[groups[k]] = True
     return amask, gmask, gap
+
+
+def flops_none(history, N, K, n_groups=None):
+    """Flops model of the experiments section without screening (flops_N).
+
+    Lasso: sum_t [(K + ||x_t||_0) N + 4 K + N];
+    Group-Lasso: sum_t [(K + ||x_t||_0) N + 4 K + N + 3 |G|].
+    """
+    tot = 0
+    for h in history:
+        tot += (K + h["nnz"]) * N + 4 * K + N + (0 if n_groups is None else 3 * n_groups)
+    return tot
+
+
+def flops_static(history, N, K, n_kept, n_groups=None):
+    """Flops model of the experiments section for static screening (flops_S): K N for the
+    test, then every iteration on the |I^c_0| = n_kept atoms the test kept.
+
+    Lasso: K N + sum_t [(|I^c_0| + ||x_t||_0) N + 4 |I^c_0| + N];
+    Group-Lasso: the same plus 3 |G| per iteration.
+    """
+    tot = K * N
+    for h in history:
+        tot += (n_kept + h["nnz"]) * N + 4 * n_kept + N + (0 if n_groups is None else 3 * n_groups)
+    return tot
 
 
 def flops_dynamic(history, N, n_groups=None):

@@ -41,7 +41,8 @@ class Params(C.Structure):
                 ("step_L", C.c_double), ("gap_tol", C.c_double), ("max_iter", C.c_int32),
                 ("screening", C.c_int32), ("step_rule", C.c_int32), ("bt_eta", C.c_double),
                 ("bb_memory", C.c_int32), ("bb_sigma", C.c_double), ("cp_tau", C.c_double),
-                ("cp_sigma", C.c_double), ("cp_gamma", C.c_double), ("x0", C.c_void_p)]
+                ("cp_sigma", C.c_double), ("cp_gamma", C.c_double), ("x0", C.c_void_p),
+                ("obj_tol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -181,17 +182,18 @@ SCREENING = {"dynamic": 0, "static": 1}
 
 def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap_tol=1e-6,
                 max_iter=10000, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0_ptr=None):
+                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0_ptr=None, obj_tol=0.0):
     return Params(RULES[rule], TESTS[test], 1 if lambda_relative else 0, float(step_L),
                   float(gap_tol), int(max_iter), SCREENING[screening], STEPS[step], float(bt_eta),
                   int(bb_memory), float(bb_sigma), float(cp_tau), float(cp_sigma),
-                  float(cp_gamma), None if x0_ptr is None else C.c_void_p(x0_ptr))
+                  float(cp_gamma), None if x0_ptr is None else C.c_void_p(x0_ptr),
+                  float(obj_tol))
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
           lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
           screened=False, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None):
+          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None, obj_tol=0.0):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
@@ -227,7 +229,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
                       bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
-                      None if x0 is None else x0.data_ptr())
+                      None if x0 is None else x0.data_ptr(), obj_tol)
     if screened:
         if group_ptr is not None:
             raise ValueError("screened masks of batched solves are for the Lasso")
@@ -249,7 +251,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
 def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="dst3",
               lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, trace=True,
               screened=True, stream=None, screening="dynamic", step="constant", bt_eta=0.0,
-              bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None):
+              bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None, obj_tol=0.0):
     """Single-signal solve returning (x, info, screened_mask or None, trace list or None).
     x0: optional warm start, a contiguous 1-D device tensor of K values (x's dtype)."""
     torch = _torch()
@@ -268,7 +270,7 @@ def solve_one(D, y, lam, *, group_ptr=None, weights=None, rule="fista", test="ds
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
                       bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
-                      None if x0 is None else x0.data_ptr())
+                      None if x0 is None else x0.data_ptr(), obj_tol)
     st = _lib.ds_solve_one(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam), C.byref(prm),
                            C.c_void_p(x.data_ptr()),
                            C.c_void_p(scr.data_ptr()) if scr is not None else None,
@@ -287,7 +289,7 @@ def solve_one_noalloc(D, y, lam, *, group_ptr=None, weights=None, rule="fista", 
                       lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000,
                       screened=True, stream=None, screening="dynamic", step="constant",
                       bt_eta=0.0, bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0,
-                      cp_gamma=0.0, x0=None, out=None, screened_out=None):
+                      cp_gamma=0.0, x0=None, out=None, screened_out=None, obj_tol=0.0):
     """ds_solve_one_noalloc: the single-signal solve on the library's fixed scratch array
     (no device allocation inside the call).  Returns (x, info, screened_mask or None); x and
     the mask are written into `out` / `screened_out` when given."""
@@ -303,7 +305,7 @@ def solve_one_noalloc(D, y, lam, *, group_ptr=None, weights=None, rule="fista", 
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
                       bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
-                      None if x0 is None else x0.data_ptr())
+                      None if x0 is None else x0.data_ptr(), obj_tol)
     st = _lib.ds_solve_one_noalloc(C.byref(prob), C.c_void_p(y.data_ptr()), float(lam),
                                    C.byref(prm), C.c_void_p(x.data_ptr()),
                                    C.c_void_p(scr.data_ptr()) if scr is not None else None,
@@ -367,7 +369,7 @@ class Server:
     def submit(self, dict_id, y_host, lam, *, rule="fista", test="dst3", lambda_relative=True,
                step_L=0.0, gap_tol=1e-6, max_iter=10000, screening="dynamic", step="constant",
                bt_eta=0.0, bb_memory=0, bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0,
-               x0=None):
+               x0=None, obj_tol=0.0):
         """x0: optional warm start on the host (K values), copied at submit."""
         import numpy as np
         N, K, dt, store = self._dicts[dict_id]
@@ -378,7 +380,7 @@ class Server:
         assert x0h is None or x0h.size == K
         prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step,
                           bt_eta, bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
-                          None if x0h is None else x0h.ctypes.data)
+                          None if x0h is None else x0h.ctypes.data, obj_tol)
         rid = C.c_uint64()
         st = _lib.lasso_submit(self._h, int(dict_id), y.ctypes.data_as(C.c_void_p), float(lam),
                                C.byref(prm), C.byref(rid))

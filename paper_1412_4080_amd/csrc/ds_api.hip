@@ -152,6 +152,7 @@ ds_status validate_params(const ds_params* p) {
     return DS_EINVAL;
   }
   if (!(p->gap_tol >= 0.0) || !std::isfinite(p->gap_tol)) { set_error("gap_tol must be >= 0"); return DS_EINVAL; }
+  if (!(p->obj_tol >= 0.0) || !std::isfinite(p->obj_tol)) { set_error("obj_tol must be >= 0"); return DS_EINVAL; }
   if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return DS_EINVAL; }
   if (!std::isfinite(p->step_L)) { set_error("step_L must be finite"); return DS_EINVAL; }
   if (p->screening != 0 && p->screening != 1) { set_error("screening must be 0 (dynamic) or 1 (static)"); return DS_EINVAL; }
@@ -242,8 +243,8 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
       set_error("backtracking, SpaRSA and Chambolle-Pock are available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
     }
-    if (params->x0 != nullptr) {
-      set_error("a warm start (x0) is available on the single-signal path (B = 1 or FP32/FP64 D)");
+    if (params->x0 != nullptr || params->obj_tol > 0.0) {
+      set_error("a warm start (x0) and the objective-change stop (obj_tol) are available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
     }
     return solve_batched_bf16(*problem, Y, B, ldy, lambdas, *params, X, ldx, info, screened, s);

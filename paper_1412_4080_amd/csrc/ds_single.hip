@@ -299,7 +299,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
                      relative ? 1 : 0, L, prm.gap_tol, prm.max_iter, gamma_z, eta,
                      RULE == RULE_SPARSA ? prm.bb_memory : 0,
                      prm.bb_sigma > 0.0 ? prm.bb_sigma : 1e-5, cp_tau, cp_sigma, prm.cp_gamma,
-                     prm.x0 != nullptr ? 1 : 0);
+                     prm.x0 != nullptr ? 1 : 0, prm.obj_tol);
   DS_HIP(hipGetLastError());
   if (prm.test == DS_TEST_DST3 || prm.test == DS_TEST_DOME) {
     hipLaunchKernelGGL((k_setup_normal<T, V, A>), dim3(grid_for(P.N, BLK, 1 << 20)), dim3(BLK),
@@ -392,7 +392,14 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   // iteration t: corr(t) with parity t%2, then resid(t+1) (scalars of t, theta_{t+1});
   // resid(1) forms theta_1 = -y.
   launch_resid(1);
-  int t = 0, chunk = 4, last_par = 1;
+  // Chunk sizes.  Iterations enqueued past the stop return at once but still cost a
+  // launch each, and every chunk costs a host round trip.  A fixed iteration count is
+  // enqueued whole (up to 64 at a time); a gap target takes the iterations the gap's
+  // geometric trend over the last chunk predicts (plus a quarter), between 4 and 64;
+  // instrumented runs take one iteration per chunk, so that no launch runs past the stop.
+  int t = 0, chunk = stat_on ? 1 : 4, last_par = 1;
+  int t_prev = 0;
+  double gap_prev = 0.0;
   bool finished = false;
   while (!finished && t < prm.max_iter) {
     const int nrun = std::min(chunk, prm.max_iter - t);
@@ -407,8 +414,22 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     DS_HIP(hipMemcpyAsync(hst, a.st + last_par, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     DS_HIP(hipStreamSynchronize(s));
     finished = hst->done != 0;
-    // instrumented runs keep short chunks: at most 3 launches past the last iteration
-    chunk = stat_on ? 4 : std::min(chunk * 2, 64);
+    if (stat_on) {
+      chunk = 1;
+    } else if (prm.gap_tol <= 0.0 && prm.obj_tol <= 0.0) {
+      chunk = 64;
+    } else {
+      int next = std::min(chunk * 2, 64);
+      const double gap = hst->gap, tol = hst->gap_tol_abs;
+      if (prm.obj_tol <= 0.0 && t_prev > 0 && gap > tol && gap < gap_prev && tol > 0.0) {
+        const double rate = std::log(gap / gap_prev) / static_cast<double>(t - t_prev);
+        const double need = std::log(tol / gap) / rate;  // iterations to the target
+        if (need > 0.0 && need < 1e6) next = static_cast<int>(std::ceil(1.25 * need)) + 2;
+      }
+      chunk = std::max(4, std::min(next, 64));
+      t_prev = t;
+      gap_prev = gap;
+    }
   }
   a.par = last_par;
 
@@ -478,7 +499,8 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   info->mu = hst->mu;
   info->L = hst->L;
   info->radius_slack = hst->r_slack + hst->marg_slack;
-  const bool converged = hst->status == 1 || prm.gap_tol <= 0.0 || hst->gap <= hst->gap_tol_abs;
+  const bool converged = hst->status == 1 || hst->stop_obj != 0 || prm.gap_tol <= 0.0 ||
+                         hst->gap <= hst->gap_tol_abs;
   info->status = converged ? DS_OK : DS_NOT_CONVERGED;
   return converged ? DS_OK : DS_NOT_CONVERGED;
 }
@@ -538,7 +560,7 @@ ds_status lambda_max_t(const ds_problem& P, const void* y, double* lmax, int64_t
                                : launch_setup_corr<T, false>(P, y, base, l, s);
   if (e != DS_OK) return e;
   hipLaunchKernelGGL((k_setup_scalars<T, V, A>), dim3(1), dim3(CBLK), 0, s, a, 1.0, 1, 1.0, 0.0,
-                     1, 0.0, 0.0, 0, 1e-5, 1.0, 1.0, 0.0, 0);
+                     1, 0.0, 0.0, 0, 1e-5, 1.0, 1.0, 0.0, 0, 0.0);
   DS_HIP(hipGetLastError());
   SolverState* hst = static_cast<SolverState*>(ws.host_pinned);
   DS_HIP(hipMemcpyAsync(hst, a.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));

@@ -443,7 +443,8 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
                                                          double gamma_z, double bt_eta,
                                                          int bb_mem, double bb_sigma,
                                                          double cp_tau, double cp_sigma,
-                                                         double cp_gamma, int warm) {
+                                                         double cp_gamma, int warm,
+                                                         double obj_tol) {
   __shared__ double sd[CNW];
   __shared__ int si[CNW];
   __shared__ double s_lmax;
@@ -550,6 +551,9 @@ __global__ __launch_bounds__(CBLK) void k_setup_scalars(SingleArgs<T, V, A> a, d
     st->phi_n = 0;
     st->bb_new = 1;
     st->warm = warm;
+    st->stop_obj = 0;
+    st->pad_ = 0;
+    st->obj_tol = obj_tol;
     st->bb_sigma = bb_sigma;
     for (int j = 0; j <= BB_MEM_MAX; ++j) st->phi_mem[j] = 0.0;
     st->cp_tau = cp_tau;
@@ -1133,7 +1137,12 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       const double dphi = v[NV - 1] + 0.5 * v[9];
       rej = !(dphi + (o.primal - phi_ref) <= -0.5 * S.bb_sigma * S.L * v[8]);
     }
-    const bool stop = (!rej && S.gap_tol_abs > 0.0 && o.gap <= S.gap_tol_abs) || t >= S.max_iter;
+    // the experiments section's rule, optionally: the relative change of the objective
+    // between the primal points of two consecutive accepted passes
+    const bool obj_stop = !rej && !S.rejected && S.obj_tol > 0.0 && t > 1 &&
+                          fabs(o.primal - S.primal) <= S.obj_tol * o.primal;
+    const bool stop = (!rej && S.gap_tol_abs > 0.0 && o.gap <= S.gap_tol_abs) || obj_stop ||
+                      t >= S.max_iter;
     __syncthreads();
     if (tid == 0) {
       const int n_old = S.n_active;
@@ -1187,6 +1196,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
           S.cp_sigma /= phi;
         }
       }
+      if (obj_stop) S.stop_obj = 1;
       if (stop) {
         S.done = 1;
       } else if (o.r_safe < S.r_scr && (!a.screen_static || t == 1)) {

@@ -59,10 +59,13 @@ struct alignas(16) SolverState {
   int32_t phi_n;       // entries in phi_mem
   int32_t bb_new;      // 1: the primal point of the next scalar stage is a new iterate
   int32_t warm;        // 1: the first pass starts from a caller's x_0 (its support is seeded)
+  int32_t stop_obj;    // 1: the solve ended on the relative objective change (obj_tol)
+  int32_t pad_;
   double bb_sigma;     // sufficient-decrease constant
   double phi_mem[BB_MEM_MAX + 1];
   // Chambolle-Pock: current primal and dual steps, acceleration
   double cp_tau, cp_sigma, cp_gamma;
+  double obj_tol;      // > 0: also stop when |P_{t-1} - P_t| <= obj_tol P_t (the experiments' rule)
 };
 
 template <typename T, typename V, typename A>

@@ -287,3 +287,21 @@ def test_a_slot_marked_failed_leaves_the_others_unchanged(B):
     assert "marked failed" in str(got[2])
     for k in (0, 1, 3, 4, 5):
         assert np.array_equal(got[k][0], ref[k][0]) and got[k][1]["iters"] == ref[k][1]["iters"]
+
+
+# ------------------------------------------------------------ the experiments' stopping rule
+@pytest.mark.parametrize("rule,test", [("ista", "safe"), ("fista", "dst3"), ("sparsa", "safe")])
+def test_objective_change_stop_follows_the_oracle(B, rule, test):
+    """obj_tol (the experiments section's relative objective change): FP64, the device stops
+    at the oracle's iteration with the same iterate."""
+    c = datagen.lasso_small_fp64()
+    D, y = c["D"], c["y"]
+    L = oracle.spectral_norm_sq(D)
+    ref = oracle.solve_lasso(D, y, lam_ratio=0.5, rule=rule, test=test, L=L, max_iter=5000,
+                             gap_tol=0.0, obj_tol=1e-7)
+    assert ref.converged and ref.iters < 5000
+    Dd, yd = dev_matrix(D, "f64"), dev_vector(y, "f64")
+    x, info, _, tr = B.solve_one(Dd, yd, 0.5, rule=rule, test=test, step_L=L, gap_tol=0.0,
+                                 max_iter=5000, obj_tol=1e-7)
+    assert info["status"] == 0 and info["iters"] == ref.iters
+    assert rel_err(x.cpu().numpy(), ref.x) <= 1e-10

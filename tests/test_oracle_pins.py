@@ -1097,3 +1097,55 @@ def test_small_fp64_configuration_matches_stored_values():
     assert sorted(np.flatnonzero(r.x).tolist()) == sorted(gx)
     for i, v in gx.items():
         assert r.x[i] == pytest.approx(v, rel=1e-9, abs=1e-13)
+
+
+# --------------------------------------------------------------------------
+# The experiments section's stopping rule and the rest of its flops model
+# --------------------------------------------------------------------------
+
+def test_objective_change_stop_on_a_scalar_problem_computed_by_hand():
+    """D = [1], y = 1, lambda = 1/2, ISTA with L = 2: x_t = 1/2 - 2^-(t+1), so the objective
+    at the point of iteration t (x_{t-1}) is P_t = 3/8 + 4^-t / 2 and the change between two
+    iterations is 3/2 4^-t.  The rule |P_{t-1} - P_t| <= tol P_t first holds at the t below."""
+    D = np.array([[1.0]])
+    y = np.array([1.0])
+    for tol in (1e-3, 1e-7, 1e-10):
+        t = 2
+        while not 1.5 * 0.25 ** t <= tol * (0.375 + 0.5 * 0.25 ** t):
+            t += 1
+        r = oracle.solve_lasso(D, y, lam=0.5, rule="ista", test="none", L=2.0, max_iter=200,
+                               gap_tol=0.0, obj_tol=tol)
+        assert r.iters == t and r.converged
+        assert r.x[0] == 0.5 - 0.5 ** (t + 1)
+    # without the rule the run goes to max_iter
+    r = oracle.solve_lasso(D, y, lam=0.5, rule="ista", test="none", L=2.0, max_iter=50,
+                           gap_tol=0.0)
+    assert r.iters == 50
+
+
+def test_flops_none_and_static_match_hand_counts():
+    hist = [dict(n_active=100, nnz=3), dict(n_active=40, nnz=5)]
+    N, K = 30, 100
+    assert oracle.flops_none(hist, N, K) == (103 * 30 + 400 + 30) + (105 * 30 + 400 + 30)
+    assert oracle.flops_none(hist, N, K, n_groups=7) == \
+        (103 * 30 + 400 + 30 + 21) + (105 * 30 + 400 + 30 + 21)
+    # static: K N once, then every iteration on the 60 atoms the test kept
+    assert oracle.flops_static(hist, N, K, 60) == 3000 + (63 * 30 + 240 + 30) + (65 * 30 + 240 + 30)
+    assert oracle.flops_static(hist, N, K, 60, n_groups=7) == \
+        3000 + (63 * 30 + 240 + 30 + 21) + (65 * 30 + 240 + 30 + 21)
+
+
+def test_flops_models_ordered_as_the_experiments_section_reads_them():
+    """Nothing screened: flops_D exceeds flops_N by the screening's own cost, 2 K + 4 N per
+    iteration (Lasso), and flops_S = flops_N + K N.  Screening that removes most atoms
+    makes flops_D far smaller than flops_N (the paper's normalised curves)."""
+    D, y = _problem(N=40, K=200, seed=35)
+    r = oracle.solve_lasso(D, y, lam_ratio=0.5, rule="fista", test="none", max_iter=30,
+                           gap_tol=0.0, record=True)
+    T = len(r.history)
+    assert oracle.flops_dynamic(r.history, 40) == oracle.flops_none(r.history, 40, 200) + \
+        T * (2 * 200 + 4 * 40)
+    assert oracle.flops_static(r.history, 40, 200, 200) == oracle.flops_none(r.history, 40, 200) + 200 * 40
+    r = oracle.solve_lasso(D, y, lam_ratio=0.9, rule="fista", test="dst3", max_iter=60,
+                           gap_tol=0.0, record=True)
+    assert oracle.flops_dynamic(r.history, 40) < 0.5 * oracle.flops_none(r.history, 40, 200)
