@@ -80,10 +80,10 @@ def batched_setup(binding, D):
     L = binding.spectral_norm_sq(Dd, 300)
 
     def one():
-        _, infos = binding.solve(Dd, Y, ratios, step_L=L, gap_tol=GAP_TOL, max_iter=20000)
+        X, infos = binding.solve(Dd, Y, ratios, step_L=L, gap_tol=GAP_TOL, max_iter=20000)
         if any(i["status"] != 0 for i in infos):
             raise RuntimeError("batched solve did not converge")
-        return infos
+        return X, infos
     return one
 
 
@@ -119,11 +119,12 @@ def batched_leg(binding, D, steps, warmup):
     t0 = time.perf_counter()
     for _ in range(steps):
         t1 = time.perf_counter()
-        infos = one()
+        X, infos = one()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t1)
     dt = time.perf_counter() - t0
     iters = [i["iters"] for i in infos]
+    ratios = datagen.lambda_ratios(NB, 0.1, 0.9, datagen.LAMBDA_SEED0)
     return {
         "workload": "lasso_fista_dst3_gaussian_2000x10000_bf16_batch256",
         "signals": NB, "solves_per_s": round(NB * steps / dt, 2),
@@ -132,27 +133,59 @@ def batched_leg(binding, D, steps, warmup):
                              "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
         "iterations": {"max": int(max(iters)), "mean": round(float(np.mean(iters)), 1)},
         "roofline": batched_roofline(binding, one),
+        "precision": batched_precision(binding, D, infos, X, ratios),
     }
 
 
-def single_roofline(binding, Dd, ys, steps, L):
-    """Instrumented pass over the timed solves: HBM roofline of the correlation kernel."""
+INSTR_SIGNALS = 6   # signals of the instrumented pass (x 5 ratios), whatever --steps is
+A_BUCKETS = (0, 1000, 2500, 5000, 7500, 10001)
+
+
+def single_roofline(binding, Dd, ys, L):
+    """Instrumented pass over a fixed sample (INSTR_SIGNALS signals x RATIOS, one iteration
+    per chunk so that no launch runs past a solve's stop): HBM roofline of the correlation
+    kernel from the device-clock spans of every launch, and per range of active atoms."""
     binding.stats_reset()
     binding.stats_enable(True)
-    run_steps(binding, Dd, ys, steps, "dst3", L)
+    run_steps(binding, Dd, ys[:INSTR_SIGNALS], INSTR_SIGNALS, "dst3", L)
     binding.stats_enable(False)
     st = binding.stats_read()[binding.STAT_CORR]
+    recs = binding.stats_launches()
     avg_ms = st["ms"] / max(st["launches"], 1)
     ev_ms = st["ms_event"] / max(st["launches"], 1)
     bytes_per = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    return {"bound": "hbm", "kernel": "k_corr_lasso",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_record(),
-            "avg_launch_us": round(avg_ms * 1e3, 3),
-            "event_avg_launch_us": round(ev_ms * 1e3, 3),
-            "algorithmic_bytes_per_launch": round(bytes_per, 1),
-            "launches": st["launches"]}
+    buckets = []
+    for lo, hi in zip(A_BUCKETS[:-1], A_BUCKETS[1:]):
+        sel = [r for r in recs if lo <= r["n_atoms"] < hi]
+        if sel:
+            b = sum(r["bytes"] for r in sel)
+            t = sum(r["ms"] for r in sel) * 1e-3
+            buckets.append({"active_atoms": [lo, hi - 1], "launches": len(sel),
+                            "avg_launch_us": round(t / len(sel) * 1e6, 3),
+                            "achieved": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)})
+    out = {"bound": "hbm", "kernel": "k_corr_lasso",
+           "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+           "avg_launch_us": round(avg_ms * 1e3, 3),
+           "event_avg_launch_us": round(ev_ms * 1e3, 3),
+           "algorithmic_bytes_per_launch": round(bytes_per, 1),
+           "launches": st["launches"],
+           "sample": f"{INSTR_SIGNALS} signals x {len(RATIOS)} lambda ratios, one iteration per chunk",
+           "by_active_atoms": buckets}
+    prof = profile_record()
+    if prof is not None:
+        # counters and rocprof durations of the same sample (profiles/): HBM bytes per launch
+        # next to that run's own algorithmic bytes, and the frac from rocprof's average
+        out["traffic"] = prof["traffic_bytes_per_launch"]
+        out["traffic_run_algorithmic_bytes_per_launch"] = prof["algorithmic_bytes_per_launch"]
+        out["traffic_over_algorithmic"] = round(prof["traffic_bytes_per_launch"] /
+                                                prof["algorithmic_bytes_per_launch"], 4)
+        r_us = prof["rocprof_avg_launch_us"]
+        out["rocprof_avg_launch_us"] = r_us
+        out["rocprof_frac"] = round(prof["algorithmic_bytes_per_launch"] / (r_us * 1e-6) / 1e9
+                                    / HBM_PEAK_GBS, 4)
+    return out
 
 
 # Serving mix: (N, K, group size or 0, stored dtype) of the eight resident dictionaries.
@@ -432,98 +465,306 @@ def large_leg(binding):
     return out
 
 
-def flops_leg(binding, Dd, ys, L, nsig=3, ratios=RATIOS,
-              workload="lasso_fista_dst3_gaussian_2000x10000_f32", rule="fista", group_ptr=None):
-    """The experiments section's cost model, normalised by the unscreened run: per
-    iteration (|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N flops, plus K N for the screening
-    set-up, from the per-iteration trace of each solve; wall time normalised the same way.
-    Dynamic and static DST3 (DGST3 with group_ptr) against the unscreened run, with the
-    given update rule (FISTA by default) on the given dictionary (the headline workload by
-    default).  SpaRSA takes its own step; the other rules take L."""
-    import torch
+# ---------------------------------------------------------------- the paper's experiments
+# Flops model of the experiments section ("How to evaluate"), from the per-iteration trace
+# of a solve (|I^c_t| = the atoms the update of iteration t used, ||x_t||_0 = the non-zeros
+# of its result).  Bookkeeping only; tests check it against the oracle's statement of it.
+def flops_none(trace, n, k, n_groups=0):
+    """flops_N: sum_t [(K + ||x_t||_0) N + 4 K + N (+ 3 |G|)]."""
+    return sum((k + t["nnz"]) * n + 4 * k + n + 3 * n_groups for t in trace)
 
-    def run(y, r, test, screening):
+
+def flops_static(trace, n, k, n_kept, n_groups=0):
+    """flops_S: K N + sum_t [(|I^c_0| + ||x_t||_0) N + 4 |I^c_0| + N (+ 3 |G|)]."""
+    return k * n + sum((n_kept + t["nnz"]) * n + 4 * n_kept + n + 3 * n_groups for t in trace)
+
+
+def flops_dynamic(trace, n, n_groups=0):
+    """flops_D: sum_t [(|I^c_t| + ||x_t||_0) N + 6 |I^c_t| + 5 N] (Lasso), or with
+    7 |I^c_t| and + 5 |G| (Group-Lasso)."""
+    c = 7 if n_groups else 6
+    return sum((t["n_active"] + t["nnz"]) * n + c * t["n_active"] + 5 * n + 5 * n_groups
+               for t in trace)
+
+
+# The experiments' stopping rule: t > 200 or a relative objective change below 1e-7.
+PAPER_MAX_ITER = 200
+PAPER_OBJ_TOL = 1e-7
+PAPER_RUNS = 30
+PAPER_RATIOS = (0.1, 0.3, 0.5, 0.7, 0.9)
+PAPER_RULES = ("ista", "fista", "sparsa", "cp")
+
+
+def _quantiles(v):
+    v = np.asarray(v, dtype=np.float64)
+    return {"median": round(float(np.median(v)), 4), "p25": round(float(np.percentile(v, 25)), 4),
+            "p75": round(float(np.percentile(v, 75)), 4)}
+
+
+def paper_runs(binding, Dd, ys, L, rules, ratios, group_ptr=None, test="dst3"):
+    """No screening, static and dynamic screening (the given test) for every observation,
+    rule and ratio, under the experiments' stopping rule; normalised flops and times of
+    every run, summarised by the median and the 25 / 75 % percentiles."""
+    import torch
+    n, k = Dd.shape
+    n_groups = 0 if group_ptr is None else group_ptr.size - 1
+
+    def run(y, r, rule, tst, screening):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info, _, tr = binding.solve_one(Dd, y, r, rule=rule, test=test, group_ptr=group_ptr,
-                                           step_L=0.0 if rule == "sparsa" else L,
-                                           gap_tol=GAP_TOL, max_iter=50000, trace=True,
-                                           screened=False, screening=screening)
+        _, info, _, tr = binding.solve_one(Dd, y, r, rule=rule, test=tst, group_ptr=group_ptr,
+                                           step_L=0.0 if rule == "sparsa" else L, gap_tol=0.0,
+                                           obj_tol=PAPER_OBJ_TOL, max_iter=PAPER_MAX_ITER,
+                                           trace=True, screened=False, screening=screening)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        fl = sum((t["n_active"] + t["nnz"]) * N + 6 * t["n_active"] + 5 * N for t in tr)
-        if test != "none":
-            fl += K * N
-        return fl, dt, info["iters"]
+        return tr, time.perf_counter() - t0
 
-    # untimed warm-up of each mode: the first launch of a kernel instantiation in the
-    # process is slower, and would otherwise be charged to the first ratio's first mode
-    for test, scr in (("dst3", "dynamic"), ("dst3", "static"), ("none", "dynamic")):
-        run(ys[0], ratios[0], test, scr)
-    out = []
-    for r in ratios:
-        acc = {"dynamic": [0.0, 0.0], "static": [0.0, 0.0], "none": [0.0, 0.0]}
-        for j in range(nsig):
-            for mode, test, scr in (("dynamic", "dst3", "dynamic"), ("static", "dst3", "static"),
-                                    ("none", "none", "dynamic")):
-                fl, dt, _ = run(ys[j], r, test, scr)
-                acc[mode][0] += fl
-                acc[mode][1] += dt
-        out.append({"lambda_ratio": r,
-                    "flops_dynamic_over_plain": round(acc["dynamic"][0] / acc["none"][0], 4),
-                    "flops_static_over_plain": round(acc["static"][0] / acc["none"][0], 4),
-                    "time_dynamic_over_plain": round(acc["dynamic"][1] / acc["none"][1], 4),
-                    "time_static_over_plain": round(acc["static"][1] / acc["none"][1], 4)})
-    return {"workload": workload, "signals": nsig, "per_ratio": out}
-
-
-# The Pnoise panel: the coherent dictionary of the experiments section (atoms e_1 plus small
-# Gaussian perturbations) is ill-conditioned, so FISTA needs thousands of iterations; the
-# panel takes lambda/lambda_* >= 0.3 and one signal to stay within the benchmark's budget.
-PNOISE_RATIOS = (0.3, 0.5, 0.7, 0.9)
+    for rule in rules:  # untimed warm-up of every kernel instantiation
+        for tst, scr in ((test, "dynamic"), (test, "static"), ("none", "dynamic")):
+            run(ys[0], ratios[0], rule, tst, scr)
+    out = {}
+    for rule in rules:
+        rows = []
+        for r in ratios:
+            fd, fs, td, ts, iters = [], [], [], [], []
+            for y in ys:
+                trn, tn = run(y, r, rule, "none", "dynamic")
+                trd, td_ = run(y, r, rule, test, "dynamic")
+                trs, ts_ = run(y, r, rule, test, "static")
+                kept = trs[1]["n_active"] if len(trs) > 1 else k
+                fnone = flops_none(trn, n, k, n_groups)
+                fd.append(flops_dynamic(trd, n, n_groups) / fnone)
+                fs.append(flops_static(trs, n, k, kept, n_groups) / fnone)
+                td.append(td_ / tn)
+                ts.append(ts_ / tn)
+                iters.append(len(trn))
+            rows.append({"lambda_ratio": r, "flops_dynamic_over_none": _quantiles(fd),
+                         "flops_static_over_none": _quantiles(fs),
+                         "time_dynamic_over_none": _quantiles(td),
+                         "time_static_over_none": _quantiles(ts),
+                         "iterations": _quantiles(iters)})
+        out[rule] = rows
+    return out
 
 
-def pnoise_flops_leg(binding):
-    """flops_leg on the 2000 x 10000 FP32 Pnoise dictionary (unit observation with 2%
-    active atoms and 20 dB noise, as for the Gaussian workload)."""
+def paper_lasso_leg(binding, runs=PAPER_RUNS):
+    """The Lasso experiment (the paper's normalised running times and flops on Pnoise): the
+    2000 x 10000 FP32 Pnoise dictionary, observations drawn from the atoms' distribution,
+    ISTA, FISTA, SpaRSA and Chambolle-Pock with no / static / dynamic ST3 screening, the
+    experiments' stopping rule, medians and percentiles over `runs` observations."""
     Dp = datagen.pnoise_dictionary(N, K, datagen.DICT_SEED)
     D32 = datagen.to_storage(Dp, "f32")
-    y32 = datagen.to_storage(datagen.lasso_signal(Dp, 0)[0], "f32")
-    Dd, yd = _dev(D32, y32)
-    Lp = binding.spectral_norm_sq(Dd, 300)
-    return flops_leg(binding, Dd, [yd], Lp, nsig=1, ratios=PNOISE_RATIOS,
-                     workload="lasso_fista_dst3_pnoise_2000x10000_f32")
-
-
-def algorithms_flops_leg(binding, Dd, ys, L):
-    """The flops model for each update rule of Table 1 (ISTA, FISTA, SpaRSA, Chambolle-Pock)
-    with dynamic and static DST3, each normalised by its own unscreened run, on the
-    headline workload (one signal)."""
-    return {rule: flops_leg(binding, Dd, ys, L, nsig=1, rule=rule,
-                            workload=f"lasso_{rule}_dst3_gaussian_2000x10000_f32")
-            for rule in ("ista", "fista", "sparsa", "cp")}
+    ys_h = [datagen.to_storage(datagen.atom_like_observation(N, j, "pnoise"), "f32")
+            for j in range(runs)]
+    Dd, _ = _dev(D32, ys_h[0])
+    import torch
+    ys = [torch.from_numpy(y.astype(np.float32)).cuda() for y in ys_h]
+    L = binding.spectral_norm_sq(Dd, 300)
+    return {"workload": "lasso_pnoise_2000x10000_f32_atomlike_observations",
+            "runs": runs, "stop": f"t > {PAPER_MAX_ITER} or relative objective change < "
+                                  f"{PAPER_OBJ_TOL:g}", "test": "dst3",
+            "per_rule": paper_runs(binding, Dd, ys, L, PAPER_RULES, PAPER_RATIOS)}
 
 
 GROUP_SIZES = (5, 10, 50, 100)
 
 
-def group_sizes_flops_leg(binding):
-    """The Group-Lasso experiment: FISTA with dynamic and static DGST3 on the 2000 x 10000
-    FP32 Pnoise dictionary split into contiguous groups of 5, 10, 50 and 100 atoms (w_g =
-    sqrt(|g|)), one unit observation with 2% active groups and 20 dB noise per size."""
+def paper_group_leg(binding, runs=PAPER_RUNS):
+    """The Group-Lasso experiment: FISTA with no / static / dynamic DGST3 on the 2000 x 10000
+    FP32 Pnoise dictionary in groups of 5, 10, 50 and 100 atoms (w_g = sqrt(|g|)), each
+    group active with probability 0.05 (Gaussian coefficients, 20 dB noise, unit y), the
+    experiments' stopping rule, medians and percentiles over `runs` observations.  The atoms
+    are i.i.d., so contiguous groups are a uniformly random equal-size partition."""
+    import torch
     Dp = datagen.pnoise_dictionary(N, K, datagen.DICT_SEED)
     D32 = datagen.to_storage(Dp, "f32")
+    Dd, _ = _dev(D32, np.zeros(N))
+    L = binding.spectral_norm_sq(Dd, 300)
     out = {}
-    Dd = None
     for gs in GROUP_SIZES:
         gp = datagen.contiguous_groups(K, gs)
-        y32 = datagen.to_storage(datagen.group_signal(Dp, gp, 0)[0], "f32")
-        Dd, yd = _dev(D32, y32)
-        Lp = binding.spectral_norm_sq(Dd, 300)
-        out[str(gs)] = flops_leg(binding, Dd, [yd], Lp, nsig=1, ratios=PNOISE_RATIOS,
-                                 group_ptr=gp,
-                                 workload=f"group_lasso_fista_dgst3_pnoise_2000x10000_f32_size{gs}")
+        ys = [torch.from_numpy(datagen.to_storage(datagen.group_signal(Dp, gp, j, p=0.05)[0],
+                                                  "f32").astype(np.float32)).cuda()
+              for j in range(runs)]
+        out[str(gs)] = paper_runs(binding, Dd, ys, L, ("fista",), PAPER_RATIOS,
+                                  group_ptr=gp)["fista"]
+    return {"workload": "group_lasso_fista_pnoise_2000x10000_f32", "runs": runs,
+            "stop": f"t > {PAPER_MAX_ITER} or relative objective change < {PAPER_OBJ_TOL:g}",
+            "test": "dgst3", "per_group_size": out}
+
+
+FIG1 = (5000, 50000)
+
+
+def paper_illustration_leg(binding):
+    """The introduction's illustration: ISTA with the dynamic SAFE test against plain ISTA,
+    atoms and observation uniform on the unit sphere in dimension 5000, K = 50000 atoms
+    (1 GB in FP32, drawn on the device from a seeded generator), lambda = 0.75 lambda_*,
+    solved to gap 1e-6: the screened dictionary's size per iteration and the times."""
+    import torch
+    n, k = FIG1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(datagen.DICT_SEED * 1000 + 200)
+    D = torch.randn(k, n, generator=g, device="cuda")
+    D /= D.norm(dim=1, keepdim=True)
+    y = torch.randn(n, generator=g, device="cuda")
+    y /= y.norm()
+    Dt = D.T
+    L = binding.spectral_norm_sq(Dt, 300)
+    res = {}
+    for test in ("safe", "none"):
+        binding.solve_one(Dt, y, 0.75, rule="ista", test=test, step_L=L, gap_tol=GAP_TOL,
+                          max_iter=5, trace=False, screened=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, _, tr = binding.solve_one(Dt, y, 0.75, rule="ista", test=test, step_L=L,
+                                           gap_tol=GAP_TOL, max_iter=20000, trace=True,
+                                           screened=False)
+        torch.cuda.synchronize()
+        res[test] = (time.perf_counter() - t0, info, tr)
+    t_s, info_s, tr_s = res["safe"]
+    t_n, info_n, tr_n = res["none"]
+    act = [t["n_active"] for t in tr_s]
+    first = next((i + 1 for i, a in enumerate(act) if a < k), None)
+    five = next((i + 1 for i, a in enumerate(act) if a <= 0.05 * k), None)
+    marks = sorted({1, 10, 20, 25, 30, 40, 50, 100, len(act)} & set(range(1, len(act) + 1)))
+    del D, Dt
+    return {"workload": "lasso_ista_safe_sphere_5000x50000_f32", "lambda_ratio": 0.75,
+            "iters": info_s["iters"], "iters_unscreened": info_n["iters"],
+            "ms_dynamic_safe": round(t_s * 1e3, 3), "ms_unscreened": round(t_n * 1e3, 3),
+            "time_dynamic_over_none": round(t_s / t_n, 4),
+            "flops_dynamic_over_none": round(flops_dynamic(tr_s, n) / flops_none(tr_n, n, k), 4),
+            "first_iteration_screening": first, "first_iteration_at_5_percent": five,
+            "dictionary_size_at": {str(t): act[t - 1] for t in marks},
+            "paper_context": "4.6 s screened vs 11.8 s unscreened (0.39), Python, hardware unstated"}
+
+
+SEEDS = 30
+
+
+def seeds_leg(binding, D, Dd, L, seeds=SEEDS):
+    """The headline workload per lambda / lambda_* over `seeds` signals: screened (DST3) and
+    plain solves timed one by one; median and 25 / 75 % percentiles of the solve time, of
+    the plain / screened time ratio and of the iterations."""
+    import torch
+    ys = [torch.from_numpy(datagen.to_storage(datagen.lasso_signal(D, j)[0], "f32")
+                           .astype(np.float32)).cuda() for j in range(seeds)]
+
+    def timed(y, r, test):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, _, _ = binding.solve_one(Dd, y, r, rule="fista", test=test, step_L=L,
+                                          gap_tol=GAP_TOL, max_iter=20000, trace=False,
+                                          screened=False)
+        torch.cuda.synchronize()
+        if info["status"] != 0:
+            raise RuntimeError(f"solve did not converge: {info}")
+        return time.perf_counter() - t0, info["iters"]
+
+    timed(ys[0], RATIOS[0], "dst3")
+    timed(ys[0], RATIOS[0], "none")
+    rows = []
+    for r in RATIOS:
+        ts, tp, it = [], [], []
+        for y in ys:
+            a, n_it = timed(y, r, "dst3")
+            b, _ = timed(y, r, "none")
+            ts.append(a * 1e3)
+            tp.append(b * 1e3)
+            it.append(n_it)
+        rows.append({"lambda_ratio": r, "screened_ms": _quantiles(ts), "plain_ms": _quantiles(tp),
+                     "plain_over_screened": _quantiles(np.array(tp) / np.array(ts)),
+                     "iterations": _quantiles(it)})
+    return {"workload": "lasso_fista_dst3_gaussian_2000x10000_f32", "signals": seeds,
+            "per_ratio": rows}
+
+
+def small_fp64_leg(binding, reps=20):
+    """The small FP64 configuration: 100 x 500, ISTA + dynamic SAFE, lambda = 0.5 lambda_*,
+    exactly 500 iterations; microseconds per iteration (whole solve / 500, median)."""
+    import torch
+    c = datagen.lasso_small_fp64()
+    Dd = torch.from_numpy(np.ascontiguousarray(c["D"].T)).cuda().T
+    yd = torch.from_numpy(c["y"]).cuda()
+    L = binding.spectral_norm_sq(Dd, 300)
+    ts = []
+    for k in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, _, _ = binding.solve_one(Dd, yd, 0.5, rule="ista", test="safe", step_L=L,
+                                          gap_tol=0.0, max_iter=500, trace=False,
+                                          screened=False)
+        torch.cuda.synchronize()
+        if k:
+            ts.append(time.perf_counter() - t0)
+    return {"workload": "lasso_ista_safe_gaussian_100x500_f64_500_iterations",
+            "us_per_iteration": round(float(np.median(ts)) / 500 * 1e6, 3),
+            "ms_per_solve": round(float(np.median(ts)) * 1e3, 3), "solves": reps,
+            "n_active_final": info["n_active"]}
+
+
+GROUP_RATIOS = (0.3, 0.7)
+
+
+def groups_leg(binding, D, Dd, L, signals=5):
+    """The Group-Lasso workload: 2000 x 10000 FP32, 1000 contiguous groups of 10, w_g =
+    sqrt(10), 2 % active groups, ISTA with dynamic DGST3, GSAFE or no screening, lambda /
+    lambda_* in {0.3, 0.7}, gap 1e-6: solves/s and iterations per test."""
+    import torch
+    gp = datagen.contiguous_groups(K, 10)
+    ys = [torch.from_numpy(datagen.to_storage(datagen.group_signal(D, gp, j)[0], "f32")
+                           .astype(np.float32)).cuda() for j in range(signals)]
+    out = {"workload": "group_lasso_ista_gaussian_2000x10000_f32_groups10", "signals": signals,
+           "lambda_ratios": list(GROUP_RATIOS)}
+    for test in ("dgst3", "gsafe", "none"):
+        binding.solve_one(Dd, ys[0], GROUP_RATIOS[0], group_ptr=gp, rule="ista", test=test,
+                          step_L=L, gap_tol=GAP_TOL, max_iter=50000, trace=False, screened=False)
+        it = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        for y in ys:
+            for r in GROUP_RATIOS:
+                _, info, _, _ = binding.solve_one(Dd, y, r, group_ptr=gp, rule="ista", test=test,
+                                                  step_L=L, gap_tol=GAP_TOL, max_iter=50000,
+                                                  trace=False, screened=False)
+                if info["status"] != 0:
+                    raise RuntimeError(f"group solve did not converge: {info}")
+                it.append(info["iters"])
+                n += 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[test] = {"solves_per_s": round(n / dt, 3), "mean_iters": round(float(np.mean(it)), 1)}
+    out["dgst3_over_none"] = round(out["dgst3"]["solves_per_s"] / out["none"]["solves_per_s"], 4)
+    out["gsafe_over_none"] = round(out["gsafe"]["solves_per_s"] / out["none"]["solves_per_s"], 4)
     return out
+
+
+def batched_precision(binding, D, infos, X, ratios, sample=16):
+    """Per result, the error of the bfloat16-instance solution against the optimum of the
+    unrounded dictionary, which the device's FP64 single-signal path computes to a gap of
+    1e-12 ||y||^2 (that path matches the FP64 oracle to 1e-10): relative objective error
+    P_D(x) / P*_D - 1 and relative iterate error ||x - x*||_inf / ||x*||_inf."""
+    import torch
+    D64 = torch.from_numpy(np.ascontiguousarray(D.T)).cuda().T
+    L64 = binding.spectral_norm_sq(D64, 300)
+    idx = np.random.default_rng(11).choice(len(infos), sample, replace=False)
+    rel_obj, rel_it = [], []
+    for j in idx:
+        y = torch.from_numpy(datagen.to_storage(datagen.lasso_signal(D, int(j))[0], "f32")).cuda()
+        lam = infos[j]["lambda_"]
+        xs, info, _, _ = binding.solve_one(D64, y, lam, lambda_relative=False, rule="fista",
+                                           test="dst3", step_L=L64, gap_tol=1e-12,
+                                           max_iter=200000, trace=False, screened=False)
+        x = X[:, int(j)].to(torch.float64)
+        r = D64 @ x - y
+        p = 0.5 * float(r @ r) + lam * float(x.abs().sum())
+        rel_obj.append((p - info["primal"]) / info["primal"])
+        rel_it.append(float((x - xs).abs().max() / xs.abs().max().clamp_min(1e-300)))
+    del D64
+    return {"reference": "FP64 solve of the unrounded dictionary on the device, gap 1e-12",
+            "signals": sample, "rel_objective_error": _quantiles(rel_obj) | {"max": float(max(rel_obj))},
+            "rel_iterate_error": _quantiles(rel_it) | {"max": float(max(rel_it))}}
 
 
 def kernel_source_sha(paths):
@@ -536,26 +777,23 @@ def kernel_source_sha(paths):
     return h.hexdigest()
 
 
-def traffic_record():
-    """HBM bytes per launch of the correlation kernel from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
+def profile_record():
+    """The committed counter and rocprof record of the instrumented sample (HBM bytes per
+    launch from FETCH_SIZE and WRITE_SIZE, rocprof's average duration, the run's algorithmic
+    bytes per launch), or None when the kernel sources changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
         sha = kernel_source_sha(rec["sources"])
+        ok = sha == rec["sources_sha256"]
+        need = ("traffic_bytes_per_launch", "algorithmic_bytes_per_launch", "rocprof_avg_launch_us")
+        return rec if ok and all(k in rec for k in need) else None
     except (OSError, KeyError, ValueError):
         return None
-    return rec["bytes_per_launch"] if sha == rec["sources_sha256"] else None
 
 
-def cpu_baseline(D, D32, L, budget_s=20.0, max_signals=30):
-    """FP64 oracle on the host cores: whole sweeps of consecutive signals until ~budget."""
+def _oracle_sweeps(D, D32, L, budget_s, max_signals):
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count()
     n = 0
     sig = 0
     dt = 0.0  # oracle time only (signal generation excluded)
@@ -570,9 +808,28 @@ def cpu_baseline(D, D32, L, budget_s=20.0, max_signals=30):
         sig += 1
         if dt > budget_s or sig >= max_signals:
             break
-    return {"value": n / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{sig} signal(s) x {len(RATIOS)} lambda ratios of the same workload, "
-                      f"FP64 NumPy, FISTA + DST3 to gap {GAP_TOL:g}, {dt:.1f} s"}
+    return n, sig, dt
+
+
+def cpu_baseline(D, D32, L, budget_s=20.0, max_signals=30, one_thread_budget_s=8.0):
+    """FP64 oracle on the host cores: whole sweeps of consecutive signals until ~budget;
+    then the same with one BLAS thread (a shorter budget)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threadpool_limits = None
+        cores = os.cpu_count()
+    n, sig, dt = _oracle_sweeps(D, D32, L, budget_s, max_signals)
+    out = {"value": n / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{sig} signal(s) x {len(RATIOS)} lambda ratios of the same workload, "
+                     f"FP64 NumPy, FISTA + DST3 to gap {GAP_TOL:g}, {dt:.1f} s"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, sig1, dt1 = _oracle_sweeps(D, D32, L, one_thread_budget_s, max_signals)
+        out["one_thread"] = {"value": n1 / dt1, "unit": "solves/s", "cores": 1,
+                             "sample": f"{sig1} signal(s) x {len(RATIOS)} lambda ratios, {dt1:.1f} s"}
+    return out
 
 
 def main():
@@ -582,8 +839,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,batched,served,flops,large,backtracking,sparsa,dome,cp",
-                    help="comma list of legs: single (headline), batched, served, flops, large "
+    ap.add_argument("--legs", default="single,seeds,small,groups,batched,served,paper_lasso,"
+                                      "paper_group,paper_illustration,large,backtracking,"
+                                      "sparsa,dome,cp",
+                    help="comma list of legs: single (headline), seeds (the headline per lambda "
+                         "over 30 signals), small (100 x 500 FP64, microseconds per iteration), "
+                         "groups (groups of 10, ISTA + DGST3 / GSAFE), batched, served, "
+                         "paper_lasso (the paper's Pnoise Lasso experiment: normalised flops "
+                         "and times of 4 rules x 3 strategies over 30 runs), paper_group (its "
+                         "Group-Lasso group-size experiment), paper_illustration (its "
+                         "introduction's 5000 x 50000 ISTA + SAFE run), large "
                          "(correlation roofline on 4096 x 40000 FP32), backtracking (the headline "
                          "workload with backtracking steps), sparsa (the headline workload with "
                          "SpaRSA's Barzilai-Borwein steps), dome (the headline workload with "
@@ -627,7 +892,7 @@ def main():
                           "roofline": batched_roofline(binding, batched_setup(binding, D))}),
               flush=True)
         return
-    nsig = max(args.steps, args.warmup, 1)
+    nsig = max(args.steps, args.warmup, INSTR_SIGNALS)
     ys_host = [datagen.to_storage(datagen.lasso_signal(D, j)[0], "f32") for j in range(nsig)]
     Dd, _ = _dev(D32, ys_host[0])
     ys = [torch.from_numpy(y.astype(np.float32)).cuda() for y in ys_host]
@@ -636,7 +901,7 @@ def main():
 
     if legs == {"instrumented"}:
         print(json.dumps({"leg": "instrumented",
-                          "roofline": single_roofline(binding, Dd, ys, args.steps, L)}), flush=True)
+                          "roofline": single_roofline(binding, Dd, ys, L)}), flush=True)
         return
     run_steps(binding, Dd, ys, args.warmup, "dst3", L)
     if legs == {"screened"}:
@@ -659,7 +924,7 @@ def main():
     plain = n_plain / (time.perf_counter() - t1)
 
     # ---- instrumented pass: kernel execution spans of every correlation launch ----
-    roof = single_roofline(binding, Dd, ys, args.steps, L)
+    roof = single_roofline(binding, Dd, ys, L)
 
     out = {
         "metric": "Lasso solves/sec to gap 1e-6, screened vs plain; HBM GB/s; p50/p99 latency",
@@ -688,11 +953,18 @@ def main():
         b = batched_leg(binding, D, max(1, args.steps // 2), 1)
         b["over_plain_single"] = round(b["solves_per_s"] / plain, 2)
         out["batched"] = b
-    if "flops" in legs:
-        out["flops_model"] = flops_leg(binding, Dd, ys, L, nsig=min(3, len(ys)))
-        out["flops_model_pnoise"] = pnoise_flops_leg(binding)
-        out["flops_model_algorithms"] = algorithms_flops_leg(binding, Dd, ys, L)
-        out["flops_model_group_sizes_pnoise"] = group_sizes_flops_leg(binding)
+    if "seeds" in legs:
+        out["per_lambda_30_signals"] = seeds_leg(binding, D, Dd, L)
+    if "small" in legs:
+        out["small_fp64"] = small_fp64_leg(binding)
+    if "groups" in legs:
+        out["groups"] = groups_leg(binding, D, Dd, L)
+    if "paper_lasso" in legs:
+        out["paper_lasso_pnoise"] = paper_lasso_leg(binding)
+    if "paper_group" in legs:
+        out["paper_group_sizes_pnoise"] = paper_group_leg(binding)
+    if "paper_illustration" in legs:
+        out["paper_illustration"] = paper_illustration_leg(binding)
     if "backtracking" in legs:
         bt = backtracking_leg(binding, Dd, ys, args.steps)
         it_c = []

@@ -306,12 +306,25 @@ typedef struct {
 enum { DS_STAT_CORR = 0, DS_STAT_RESID = 1, DS_STAT_SETUP = 2, DS_STAT_BATCH = 3,
        DS_STAT_BATCH_THETA = 4, DS_STAT_COUNT = 5 };
 
+/* One launch of the single-signal correlation pass (DS_STAT_CORR) as accounted by the
+ * statistics: the active atoms it streamed, its algorithmic bytes and its execution time
+ * (device wall clock, as ds_kernel_stat.ms). */
+typedef struct {
+  int32_t kernel;     /* DS_STAT_CORR */
+  int32_t n_atoms;    /* active atoms |I^c_t| of the launch */
+  double bytes;       /* algorithmic bytes */
+  double ms;          /* execution time */
+} ds_launch_stat;
+
 /* When enabled, each launch of the instrumented kernels is bracketed by HIP events on
  * its stream and its algorithmic bytes/flops are added to the counters. */
 void ds_stats_enable(int on);
 void ds_stats_reset(void);
 /* Copies min(n, DS_STAT_COUNT) counters into out; returns the number copied. */
 int ds_stats_read(ds_kernel_stat* out, int n);
+/* Copies up to n per-launch records of the correlation pass accounted since the last
+ * ds_stats_reset (the first 2^20 are kept, in launch order); returns the number copied. */
+int ds_stats_launches(ds_launch_stat* out, int n);
 
 const char* ds_last_error(void);
 const char* ds_version(void);

@@ -376,7 +376,7 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
     Chambolle-Pock dual iterate still starts at 0).
     obj_tol > 0 adds the stopping rule of the experiments section: stop once the objective
     of the certified primal point changes by at most obj_tol relative between two
-    consecutive accepted iterations.
+    consecutive accepted iterations whose primal points are both non-zero.
 
     Each iteration: the update (theta_t = D_{t-1} p - y, z_t = D_{t-1}^T theta_t,
     x_t = prox(p - z_t / L, lambda / L), FISTA momentum), the dual point
@@ -427,22 +427,23 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
         sigma = float(cp_sigma) if cp_sigma else 1.0 / (tau * L)
         theta_cp = np.zeros(N)
     converged = False
-    primal_prev, prev_accepted = 0.0, True      # the objective-change rule (obj_tol)
+    primal_prev, prev_accepted, omega_prev = 0.0, True, 0.0   # the objective-change rule
     for t in range(1, max_iter + 1):
         # ---- optimisation update (Table 1) ----
         p = u if rule in ("fista", "cp") else x
+        omega_p = float(np.abs(p).sum())
         if rule == "cp":
             res = Dt @ p - y
             theta = (theta_cp + sigma * res) / (1.0 + sigma)
             z = Dt.T @ theta
             x_new = soft_threshold(x - tau * z, lam * tau)
             phi = 1.0 / np.sqrt(1.0 + 2.0 * cp_gamma * tau)
-            primal_p = 0.5 * float(res @ res) + lam * float(np.abs(p).sum())
+            primal_p = 0.5 * float(res @ res) + lam * omega_p
         else:
             theta = Dt @ p - y
             z = Dt.T @ theta
             x_new = soft_threshold(p - z / L, lam / L)
-            primal_p = 0.5 * float(theta @ theta) + lam * float(np.abs(p).sum())
+            primal_p = 0.5 * float(theta @ theta) + lam * omega_p
         accepted = True
         if step == "backtracking":  # F(x_new) <= Q_L(x_new, p)  <=>  ||D d||^2 <= L ||d||^2
             d = x_new - p
@@ -490,8 +491,9 @@ def solve_lasso(D, y, *, lam=None, lam_ratio=None, rule="fista", test="dst3", L=
             if rule == "cp":
                 hist[-1].update(theta=theta.copy(), tau=tau, sigma=sigma, x_prev=x.copy())
         obj_stop = (obj_tol > 0.0 and accepted and prev_accepted and t > 1
+                    and omega_p > 0.0 and omega_prev > 0.0
                     and abs(primal_prev - primal_p) <= obj_tol * primal_p)
-        primal_prev, prev_accepted = primal_p, accepted
+        primal_prev, prev_accepted, omega_prev = primal_p, accepted, omega_p
         converged = (gap_tol > 0.0 and gap <= gap_tol * yy and accepted) or obj_stop
         if not accepted:
             # rejected step: keep p, grow L; at the iteration limit return the last accepted x
@@ -601,7 +603,7 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
         sigma = float(cp_sigma) if cp_sigma else 1.0 / (tau * L)
         theta_cp = np.zeros(N)
     converged = False
-    primal_prev, prev_accepted = 0.0, True      # the objective-change rule (obj_tol)
+    primal_prev, prev_accepted, omega_prev = 0.0, True, 0.0   # the objective-change rule
     for t in range(1, max_iter + 1):
         wa = w[act_g]
         p = u if rule in ("fista", "cp") else x
@@ -666,8 +668,9 @@ def solve_group_lasso(D, y, groups, w=None, *, lam=None, lam_ratio=None, rule="i
             if rule == "cp":
                 hist[-1].update(theta=theta.copy(), tau=tau, sigma=sigma, x_prev=x.copy())
         obj_stop = (obj_tol > 0.0 and accepted and prev_accepted and t > 1
+                    and omega_p > 0.0 and omega_prev > 0.0
                     and abs(primal_prev - primal_p) <= obj_tol * primal_p)
-        primal_prev, prev_accepted = primal_p, accepted
+        primal_prev, prev_accepted, omega_prev = primal_p, accepted, omega_p
         converged = (gap_tol > 0.0 and gap <= gap_tol * yy and accepted) or obj_stop
         if not accepted:
             x_new, u_new, l_new = x, u, l_prev

@@ -66,6 +66,11 @@ class ServerConfig(C.Structure):
                 ("max_queue", C.c_int32), ("reserved", C.c_int32)]
 
 
+class LaunchStat(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("n_atoms", C.c_int32), ("bytes", C.c_double),
+                ("ms", C.c_double)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double),
                 ("flops", C.c_double), ("ms_event", C.c_double)]
@@ -98,6 +103,7 @@ _sig = {
     "ds_stats_enable": (None, [C.c_int]),
     "ds_stats_reset": (None, []),
     "ds_stats_read": (C.c_int, [_P(KernelStat), C.c_int]),
+    "ds_stats_launches": (C.c_int, [_P(LaunchStat), C.c_int]),
     "ds_last_error": (C.c_char_p, []),
     "ds_version": (C.c_char_p, []),
 }
@@ -344,6 +350,13 @@ def stats_read():
     n = _lib.ds_stats_read(arr, STAT_COUNT)
     return [dict(launches=a.launches, ms=a.ms, bytes=a.bytes, flops=a.flops, ms_event=a.ms_event)
             for a in arr[:n]]
+
+
+def stats_launches(cap=1 << 20):
+    """Per-launch records (n_atoms, bytes, ms) of the correlation pass since the last reset."""
+    arr = (LaunchStat * cap)()
+    n = _lib.ds_stats_launches(arr, cap)
+    return [dict(n_atoms=a.n_atoms, bytes=a.bytes, ms=a.ms) for a in arr[:n]]
 
 
 # ------------------------------------------------------------------ serving

@@ -362,6 +362,16 @@ void ds_stats_reset(void) {
   StatAccum& S = stats();
   std::lock_guard<std::mutex> g(S.mu);
   for (auto& k : S.s) k = ds_kernel_stat{};
+  S.launches.clear();
+}
+
+int ds_stats_launches(ds_launch_stat* out, int n) {
+  if (out == nullptr || n <= 0) return 0;
+  StatAccum& S = stats();
+  std::lock_guard<std::mutex> g(S.mu);
+  const size_t m = std::min(S.launches.size(), static_cast<size_t>(n));
+  for (size_t k = 0; k < m; ++k) out[k] = S.launches[k];
+  return static_cast<int>(m);
 }
 
 int ds_stats_read(ds_kernel_stat* out, int n) {

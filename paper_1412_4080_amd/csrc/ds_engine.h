@@ -44,6 +44,8 @@ struct StatAccum {
   std::mutex mu;
   bool on = false;
   ds_kernel_stat s[DS_STAT_COUNT] = {};
+  std::vector<ds_launch_stat> launches;  // per-launch records of the correlation pass
+  static constexpr size_t MAX_LAUNCHES = size_t(1) << 20;
 };
 StatAccum& stats();
 

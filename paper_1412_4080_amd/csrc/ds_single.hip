@@ -462,18 +462,24 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     double ms = 0.0, ms_ev = 0.0, bytes = 0.0, flops = 0.0;
     const size_t used = std::min({ev.size(), tl.size(), static_cast<size_t>(nspan)});
     std::vector<uint64_t> ticks(used);
+    std::vector<ds_launch_stat> recs(used);
     int rate_khz = 0;
     DS_HIP(hipMemcpy(ticks.data(), spans, used * sizeof(uint64_t), hipMemcpyDeviceToHost));
     DS_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ws.device));
     for (size_t k = 0; k < used; ++k) {
       float f = 0.f;
       if (hipEventElapsedTime(&f, ev[k].first, ev[k].second) == hipSuccess) ms_ev += f;
-      if (rate_khz > 0) ms += static_cast<double>(ticks[k]) / rate_khz;
+      const double mk = rate_khz > 0 ? static_cast<double>(ticks[k]) / rate_khz : 0.0;
+      ms += mk;
       const double na = tl[k].n_atoms, nu = tl[k].n_units;
-      bytes += na * P.N * sizeof(T) + P.N * sizeof(V) + 4.0 * na * sizeof(V) + 4.0 * nu;
+      const double bk = na * P.N * sizeof(T) + P.N * sizeof(V) + 4.0 * na * sizeof(V) + 4.0 * nu;
+      bytes += bk;
       flops += 2.0 * na * P.N;
+      recs[k] = ds_launch_stat{DS_STAT_CORR, tl[k].n_atoms, bk, mk};
     }
     std::lock_guard<std::mutex> g(S.mu);
+    for (const ds_launch_stat& r : recs)
+      if (S.launches.size() < StatAccum::MAX_LAUNCHES) S.launches.push_back(r);
     S.s[DS_STAT_CORR].launches += static_cast<int64_t>(used);
     S.s[DS_STAT_CORR].ms += ms;
     S.s[DS_STAT_CORR].ms_event += ms_ev;

@@ -1138,9 +1138,11 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
       rej = !(dphi + (o.primal - phi_ref) <= -0.5 * S.bb_sigma * S.L * v[8]);
     }
     // the experiments section's rule, optionally: the relative change of the objective
-    // between the primal points of two consecutive accepted passes
-    const bool obj_stop = !rej && !S.rejected && S.obj_tol > 0.0 && t > 1 &&
-                          fabs(o.primal - S.primal) <= S.obj_tol * o.primal;
+    // between the primal points of two consecutive accepted passes, once both are non-zero
+    // (a method whose first steps leave x at 0, such as Chambolle-Pock from a zero dual
+    // iterate, would otherwise stop before it starts)
+    const bool obj_stop = !rej && !S.rejected && S.obj_tol > 0.0 && t > 1 && om > 0.0 &&
+                          S.omega > 0.0 && fabs(o.primal - S.primal) <= S.obj_tol * o.primal;
     const bool stop = (!rej && S.gap_tol_abs > 0.0 && o.gap <= S.gap_tol_abs) || obj_stop ||
                       t >= S.max_iter;
     __syncthreads();

@@ -158,5 +158,19 @@ def group_signal(D: np.ndarray, group_ptr: np.ndarray, j: int, p: float = 0.02,
     return observation(D, x0, rng, snr_db=snr_db), x0
 
 
+def atom_like_observation(N: int, j: int, kind: str = "gaussian") -> np.ndarray:
+    """Observation j of the Lasso experiments, drawn from the same distribution as the atoms
+    ("Data material"): uniform on the unit sphere (Gaussian), or e_1 + 0.1 kappa g with
+    kappa ~ U(0, 1) (Pnoise); normalised."""
+    rng = np.random.default_rng(SIGNAL_SEED0 + j)
+    v = rng.standard_normal(N)
+    if kind == "pnoise":
+        v = 0.1 * rng.uniform(0.0, 1.0) * v
+        v[0] += 1.0
+    elif kind != "gaussian":
+        raise ValueError(kind)
+    return v / np.linalg.norm(v)
+
+
 LASSO_SWEEP = (0.1, 0.3, 0.5, 0.7, 0.9)
 GROUP_SWEEP = (0.3, 0.7)

@@ -1149,3 +1149,17 @@ def test_flops_models_ordered_as_the_experiments_section_reads_them():
     r = oracle.solve_lasso(D, y, lam_ratio=0.9, rule="fista", test="dst3", max_iter=60,
                            gap_tol=0.0, record=True)
     assert oracle.flops_dynamic(r.history, 40) < 0.5 * oracle.flops_none(r.history, 40, 200)
+
+
+def test_objective_change_stop_waits_for_a_nonzero_primal_point():
+    """Chambolle-Pock from zero on D = [1], y = 1, lambda = 1/2 with tau = sigma = 0.1: the
+    dual iterate needs several steps before the prox leaves 0, so the objective is constant
+    at first; the rule counts only iterations whose primal points are non-zero, and the run
+    reaches the minimiser 1/2."""
+    D = np.array([[1.0]])
+    y = np.array([1.0])
+    r = oracle.solve_lasso(D, y, lam=0.5, rule="cp", test="none", L=1.0, cp_tau=0.1,
+                           cp_sigma=0.1, max_iter=20000, gap_tol=0.0, obj_tol=1e-7, record=True)
+    zero_steps = sum(1 for h in r.history if h["nnz_p"] == 0)
+    assert zero_steps >= 3 and r.iters > zero_steps + 1 and r.converged
+    assert abs(r.x[0] - 0.5) < 1e-3
