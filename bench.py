@@ -98,7 +98,9 @@ def batched_roofline(binding, one):
     z_ms = z["ms"] / max(z["launches"], 1)
     z_flops = z["flops"] / max(z["launches"], 1)
     achieved = z_flops / (z_ms * 1e-3) / 1e12 if z_ms > 0 else 0.0
-    return {"bound": "mfma", "kernel": "k_b_zgemm", "achieved": round(achieved, 2),
+    k, ta, ts = binding.batch_shape()
+    return {"bound": "mfma", "kernel": "k_b_zgemm", "block": f"{ta} atoms x {ts} signals",
+            "block_shape_index": k, "achieved": round(achieved, 2),
             "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None,
             "avg_launch_us": round(z_ms * 1e3, 3),

@@ -326,6 +326,13 @@ int ds_stats_read(ds_kernel_stat* out, int n);
  * ds_stats_reset (the first 2^20 are kept, in launch order); returns the number copied. */
 int ds_stats_launches(ds_launch_stat* out, int n);
 
+/* Block shape of the batched path's Z = D^T Theta kernel in the last batched solve on the
+ * current device: its index, and (when the pointers are non-NULL) the atoms and signals a
+ * block covers.  The shape is chosen per (N, K, B) by timing every eligible one once (the
+ * results do not depend on it); DS_BATCH_TILE=<index> forces one, and DS_AUTOTUNE_CACHE
+ * names a file that keeps the choices across processes.  -1 before any batched solve. */
+int ds_batch_shape(int* atoms, int* signals);
+
 const char* ds_last_error(void);
 const char* ds_version(void);
 

@@ -104,6 +104,7 @@ _sig = {
     "ds_stats_reset": (None, []),
     "ds_stats_read": (C.c_int, [_P(KernelStat), C.c_int]),
     "ds_stats_launches": (C.c_int, [_P(LaunchStat), C.c_int]),
+    "ds_batch_shape": (C.c_int, [_P(C.c_int), _P(C.c_int)]),
     "ds_last_error": (C.c_char_p, []),
     "ds_version": (C.c_char_p, []),
 }
@@ -335,6 +336,13 @@ def spectral_norm_sq(D, iters=0, *, stream=None):
     _check(_lib.ds_spectral_norm_sq(C.byref(prob), int(iters), C.byref(out), _stream_ptr(stream)),
            "ds_spectral_norm_sq")
     return out.value
+
+
+def batch_shape():
+    """(index, atoms, signals) of the Z-GEMM block shape of the last batched solve."""
+    a, b = C.c_int(0), C.c_int(0)
+    k = _lib.ds_batch_shape(C.byref(a), C.byref(b))
+    return k, a.value, b.value
 
 
 def stats_enable(on=True):

@@ -1,15 +1,21 @@
 // Batched path for many signals sharing one bfloat16 dictionary (Lasso, B > 1): host
 // side.  Buffers live in one per-device workspace; a run of ITERS_PER_GRAPH iterations
 // (an even number, so that it starts on the same parity of the u double buffer each time)
-// is captured once as a HIP graph and replayed until every signal has finished.
+// is captured once as a HIP graph and replayed until every signal has finished.  The block
+// shape of the Z = D^T Theta kernel is chosen per (N, K, B) by timing every eligible shape
+// once (all shapes give the same results bit for bit), cached in memory and optionally in
+// the file named by DS_AUTOTUNE_CACHE; DS_BATCH_TILE=<index> forces a shape.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #include "ds_batched_kernels.h"
@@ -28,7 +34,8 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 struct BLayout {
   int N, K, B, Np, Kp, Bp, nrb;
   size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
-      inst, ctr, vlist, perm, lam, z0, gn, Vn, kclk, spans, total;
+      inst, ctr, vlist, perm, lam, z0, gn, Vn, kclk, spans, tX, tU, tZ, tpz, tpom, tpact, tmask,
+      total;
   int nspan;
 };
 
@@ -36,7 +43,7 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   BLayout l{};
   l.N = N; l.K = K; l.B = B;
   l.Np = round_up(N, 64);
-  l.Kp = round_up(K, 64);
+  l.Kp = round_up(K, KP_ALIGN);
   l.Bp = round_up(B, 64);
   l.nrb = (l.Np + TR - 1) / TR;
   const size_t np = l.Np, kp = l.Kp, bp = l.Bp, nt = l.Kp / MT;
@@ -74,8 +81,47 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.kclk = take(2 * static_cast<size_t>(l.Kp / 64) * (l.Bp / 64) * NWB * 8);
   l.nspan = max_iter + ITERS_PER_GRAPH;
   l.spans = take(static_cast<size_t>(l.nspan) * 8);
+  // the autotuner's outputs (its trial launches write here instead of the solve's state)
+  l.tX = take(bp * kp * 4);
+  l.tU = take(bp * kp * 4);
+  l.tZ = take(bp * kp * 4);
+  l.tpz = take(nt * bp * 8);
+  l.tpom = take(nt * bp * 8);
+  l.tpact = take(nt * bp * 4);
+  l.tmask = take(nt * bp * 4);
   l.total = o;
   return l;
+}
+
+bool shape_fits(int k, const BLayout& l) {
+  const ZShapeDesc& z = ZSHAPES[k];
+  return l.Kp % (MT * z.ra * z.wa) == 0 && l.Bp % (MT * z.rb * z.wb) == 0;
+}
+
+template <int RA, int RB, int WA, int WB>
+void launch_zgemm_t(const BLayout& l, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const BArgs& a,
+                    const float* Uin, float* Uout) {
+  const dim3 g(l.Kp / (MT * RA * WA), l.Bp / (MT * RB * WB)), blk(BW * RA * RB);
+  if (e0 != nullptr)
+    hipExtLaunchKernelGGL((k_b_zgemm<RA, RB, WA, WB>), g, blk, 0, s, e0, e1, 0, a, Uin, Uout);
+  else
+    hipLaunchKernelGGL((k_b_zgemm<RA, RB, WA, WB>), g, blk, 0, s, a, Uin, Uout);
+}
+
+// Launch the Z-GEMM with block shape k (an index into ZSHAPES); returns its wave count.
+int launch_zgemm(int k, const BLayout& l, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                 const BArgs& a, const float* Uin, float* Uout) {
+  switch (k) {
+    case 1: launch_zgemm_t<4, 2, 1, 1>(l, s, e0, e1, a, Uin, Uout); break;
+    case 2: launch_zgemm_t<4, 1, 1, 1>(l, s, e0, e1, a, Uin, Uout); break;
+    case 3: launch_zgemm_t<2, 4, 1, 1>(l, s, e0, e1, a, Uin, Uout); break;
+    case 4: launch_zgemm_t<1, 4, 1, 1>(l, s, e0, e1, a, Uin, Uout); break;
+    case 5: launch_zgemm_t<2, 2, 2, 1>(l, s, e0, e1, a, Uin, Uout); break;
+    case 6: launch_zgemm_t<4, 1, 2, 1>(l, s, e0, e1, a, Uin, Uout); break;
+    default: launch_zgemm_t<2, 2, 1, 1>(l, s, e0, e1, a, Uin, Uout); break;
+  }
+  const ZShapeDesc& z = ZSHAPES[k];
+  return (l.Kp / (MT * z.ra * z.wa)) * (l.Bp / (MT * z.rb * z.wb)) * z.ra * z.rb;
 }
 
 // Per-device state of the batched engine: workspace, a private stream (graph capture
@@ -87,6 +133,10 @@ struct BatchCtx {
   hipEvent_t ev = nullptr;
   hipGraphExec_t exec = nullptr;
   BArgs key{};
+  int key_shape = -1;
+  hipEvent_t tune0 = nullptr, tune1 = nullptr;  // timing events of the autotuner
+  int last_shape = -1;                           // shape of the last solve (diagnostics)
+  std::map<std::tuple<int, int, int>, int> tuned;  // (N, K, B) -> Z-GEMM block shape
   int* host_ctr = nullptr;  // pinned: ndone
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evpool;
   size_t ev_used = 0;
@@ -102,6 +152,70 @@ BatchCtx& batch_ctx(int device) {
     p->ws.device = device;
   }
   return *p;
+}
+
+// Autotuner: the Z-GEMM block shape for this (N, K, B).  DS_BATCH_TILE forces one; else the
+// in-memory cache, then the file named by DS_AUTOTUNE_CACHE (lines "N K B bf16 shape"),
+// then a timing of every shape that fits: one warm-up and three launches each, on the
+// solve's first theta with every active tile of every signal in play, writing to scratch
+// outputs so that the solve's state is untouched.  Returns the shape index.
+int choose_shape(BatchCtx& C, const BLayout& l, char* base, const BArgs& a, hipStream_t s,
+                 hipEvent_t e0, hipEvent_t e1) {
+  if (const char* f = std::getenv("DS_BATCH_TILE")) {
+    const int k = std::atoi(f);
+    if (k >= 0 && k < NZSHAPE && shape_fits(k, l)) return k;
+  }
+  const auto key = std::make_tuple(l.N, l.K, l.B);
+  auto it = C.tuned.find(key);
+  if (it != C.tuned.end()) return it->second;
+  const char* path = std::getenv("DS_AUTOTUNE_CACHE");
+  if (path != nullptr) {
+    if (FILE* fp = std::fopen(path, "r")) {
+      int n, k, b, sh;
+      char dt[16];
+      int found = -1;
+      while (std::fscanf(fp, "%d %d %d %15s %d", &n, &k, &b, dt, &sh) == 5)
+        if (n == l.N && k == l.K && b == l.B && std::strcmp(dt, "bf16") == 0 && sh >= 0 &&
+            sh < NZSHAPE && shape_fits(sh, l))
+          found = sh;
+      std::fclose(fp);
+      if (found >= 0) return C.tuned[key] = found;
+    }
+  }
+  BArgs t = a;
+  t.X = reinterpret_cast<float*>(base + l.tX);
+  t.Z = reinterpret_cast<float*>(base + l.tZ);
+  t.pz = reinterpret_cast<double*>(base + l.tpz);
+  t.pom = reinterpret_cast<double*>(base + l.tpom);
+  t.pact = reinterpret_cast<int*>(base + l.tpact);
+  t.umask = reinterpret_cast<uint32_t*>(base + l.tmask);
+  t.kclk = nullptr;
+  float* tU = reinterpret_cast<float*>(base + l.tU);
+  if (hipMemsetAsync(t.X, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s) != hipSuccess) return 0;
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int k = 0; k < NZSHAPE; ++k) {
+    if (!shape_fits(k, l)) continue;
+    launch_zgemm(k, l, s, nullptr, nullptr, t, a.U0, tU);
+    if (hipEventRecord(e0, s) != hipSuccess) return 0;
+    for (int r = 0; r < 3; ++r) launch_zgemm(k, l, s, nullptr, nullptr, t, a.U0, tU);
+    float ms = 1e30f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+      return 0;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = k;
+    }
+  }
+  C.tuned[key] = best;
+  if (path != nullptr) {
+    if (FILE* fp = std::fopen(path, "a")) {
+      std::fprintf(fp, "%d %d %d bf16 %d\n", l.N, l.K, l.B, best);
+      std::fclose(fp);
+    }
+  }
+  return best;
 }
 
 BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
@@ -169,6 +283,8 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     DS_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
     DS_HIP(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming));
     DS_HIP(hipHostMalloc(reinterpret_cast<void**>(&C.host_ctr), 64, hipHostMallocDefault));
+    DS_HIP(hipEventCreate(&C.tune0));
+    DS_HIP(hipEventCreate(&C.tune1));
   }
   hipStream_t s = C.stream;
   // inputs written on the caller's stream are visible to ours
@@ -247,7 +363,19 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
 
   // ---------------------------------------------------------------- iteration
   const dim3 g_theta(l.nrb, l.Bp);
-  const dim3 g_z(l.Kp / 64, l.Bp / 64);
+  // block shape of the Z-GEMM; tuning needs the first theta (theta_1 = -y; the first
+  // iteration recomputes it identically)
+  int shape = -1;
+  {
+    const auto key = std::make_tuple(l.N, l.K, l.B);
+    if (std::getenv("DS_BATCH_TILE") == nullptr && C.tuned.find(key) == C.tuned.end()) {
+      hipLaunchKernelGGL(k_b_theta, g_theta, dim3(TB), 0, s, a, static_cast<const float*>(a.U0));
+      DS_HIP(hipGetLastError());
+    }
+    shape = choose_shape(C, l, base, a, s, C.tune0, C.tune1);
+    DS_HIP(hipGetLastError());
+    C.last_shape = shape;
+  }
   const dim3 g_slot4(l.Bp / NWB);
   const dim3 g_vca((l.K + VC - 1) / VC, VG), g_vdot(512);
   const dim3 g_scr((l.Kp / 4 + TB - 1) / TB, l.Bp);
@@ -256,7 +384,8 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   // end; a one-block pass after the launch reduces the stamps to the launch's span
   uint64_t* spans = reinterpret_cast<uint64_t*>(base + l.spans);
   int nspan = 0;
-  const int zwaves = static_cast<int>(g_z.x * g_z.y) * NWB;
+  const ZShapeDesc& zs = ZSHAPES[shape];
+  const int zwaves = (l.Kp / (MT * zs.ra * zs.wa)) * (l.Bp / (MT * zs.rb * zs.wb)) * zs.ra * zs.rb;
   if (stat_on) a.kclk = reinterpret_cast<uint64_t*>(base + l.kclk);
   auto events = [&]() -> std::pair<hipEvent_t, hipEvent_t> {
     if (C.ev_used == C.evpool.size()) {
@@ -277,11 +406,8 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
                             static_cast<const float*>(Uin));
     else
       hipLaunchKernelGGL(k_b_theta, g_theta, dim3(TB), 0, s, a, static_cast<const float*>(Uin));
-    if (timed)
-      hipExtLaunchKernelGGL(k_b_zgemm, g_z, dim3(TB), 0, s, ez.first, ez.second, 0, a,
-                            static_cast<const float*>(Uin), Uout);
-    else
-      hipLaunchKernelGGL(k_b_zgemm, g_z, dim3(TB), 0, s, a, static_cast<const float*>(Uin), Uout);
+    launch_zgemm(shape, l, s, timed ? ez.first : nullptr, timed ? ez.second : nullptr, a, Uin,
+                 Uout);
     if (timed && nspan < l.nspan) {
       hipLaunchKernelGGL(k_clock_span<0>, dim3(1), dim3(256), 0, s, a.kclk, zwaves, spans + nspan);
       ++nspan;
@@ -306,7 +432,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
       if (*C.host_ctr >= B) break;
     }
   } else {
-    if (C.exec == nullptr || std::memcmp(&C.key, &a, sizeof a) != 0) {
+    if (C.exec == nullptr || std::memcmp(&C.key, &a, sizeof a) != 0 || C.key_shape != shape) {
       if (C.exec != nullptr) {
         DS_HIP(hipGraphExecDestroy(C.exec));
         C.exec = nullptr;
@@ -324,6 +450,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
         DS_HIP(ie);
       }
       C.key = a;
+      C.key_shape = shape;
     }
     while (t < prm.max_iter) {
       DS_HIP(hipGraphLaunch(C.exec, s));
@@ -411,3 +538,17 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
 }
 
 }  // namespace ds
+
+extern "C" int ds_batch_shape(int* atoms, int* signals) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  ds::BatchCtx& C = ds::batch_ctx(dev);
+  std::lock_guard<std::mutex> g(C.mu);
+  const int k = C.last_shape;
+  if (k >= 0) {
+    const ds::batch::ZShapeDesc& z = ds::batch::ZSHAPES[k];
+    if (atoms != nullptr) *atoms = ds::batch::MT * z.ra * z.wa;
+    if (signals != nullptr) *signals = ds::batch::MT * z.rb * z.wb;
+  }
+  return k;
+}

@@ -445,172 +445,243 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
 constexpr int ZR = 64;       // rows of D and Theta staged in LDS per step
 constexpr int ZP = ZR + 8;   // padded LDS row (144 bytes: fragment reads free of bank conflicts)
 
-__global__ __launch_bounds__(TB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
-                                                float* __restrict__ Uout) {
-  __shared__ __align__(16) uint16_t sA[64][ZP];     // 64 atoms x 64 rows
-  __shared__ __align__(16) uint16_t sB[3][64][ZP];  // 3 parts x 64 signals x 64 rows
-  __shared__ int s_on[NWB];
+// Z = D^T Theta with the update of Table 1 in the epilogue.  Block shapes: RA x RB waves
+// (atoms x signals), each computing WA x WB output tiles of 32 atoms x 32 signals, so a
+// block covers TA = 32 RA WA atoms and TS = 32 RB WB signals.  Every 32 x 32
+// output tile is accumulated by the same instruction sequence whatever the shape (64-row
+// chunks in order, the three parts of theta, four k steps of 16 per chunk), so the results
+// are the same bit for bit; the shape only changes how often each piece of D and Theta is
+// staged (D once per block of signals, Theta once per block of atoms) and the parallelism.
+// The block stages 64-row chunks of its atoms and of the three parts of its signals' theta
+// through LDS with 16-byte loads while the next chunk is fetched into registers.  Each
+// chunk is accumulated in FP32 on the matrix cores from zero and then added to FP64
+// registers, so an FP32 rounding chain spans 3 x 64 products.  Output tiles without an
+// active pair are skipped; a block without any returns at once.
+template <int RA, int RB, int WA, int WB>
+__global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
+                                                          float* __restrict__ Uout) {
+  constexpr int NWV = RA * RB, NT = BW * NWV;  // waves and threads of a block
+  constexpr int TA = MT * RA * WA, TS = MT * RB * WB;
+  constexpr int PA = TA * 8 / NT;       // 16-byte pieces of a D chunk per thread
+  constexpr int PB = 3 * TS * 8 / NT;   // 16-byte pieces of a Theta chunk per thread
+  static_assert(PA * NT == TA * 8 && PB * NT == 3 * TS * 8, "pieces tile the block");
+  __shared__ __align__(16) uint16_t sA[TA][ZP];     // TA atoms x 64 rows
+  __shared__ __align__(16) uint16_t sB[3][TS][ZP];  // 3 parts x TS signals x 64 rows
+  __shared__ int s_on[NWV];
   const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
-  const int64_t gw = (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * NWB + wave;
+  const int64_t gw = (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * NWV + wave;
   if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw] = wall_clock64();
-  const int a0b = blockIdx.x * 64, b0b = blockIdx.y * 64;
-  const int wa = (wave / 2) * MT, wb = (wave % 2) * MT;  // this wave's 32 x 32 sub-tile
-  const int a0 = a0b + wa;
-  const int b0 = b0b + wb;
-  const int bl = b0 + (lane % MT);  // signal of this lane's accumulator column
-  const int at = a0 / MT;
-  const Inst& sl = a.inst[bl];
-  const bool alive = sl.done == 0;
-  const double r_act = sl.r_keep;  // active pairs: margin <= r_act
-  const int64_t tix = static_cast<int64_t>(at) * a.Bp + bl;
-  const bool tile_on = alive && static_cast<double>(a.tminm[tix]) <= r_act;
-  const bool wave_on = __ballot(tile_on) != 0;
+  const int a0b = blockIdx.x * TA, b0b = blockIdx.y * TS;
+  const int wal = (wave / RB) * (MT * WA), wbl = (wave % RB) * (MT * WB);  // in the block
+  // this lane's signal in output tile column ib, and the tiles' activity
+  const Inst* sl[WB];
+  bool alive[WB];
+  double r_act[WB];
+#pragma unroll
+  for (int ib = 0; ib < WB; ++ib) {
+    sl[ib] = a.inst + (b0b + wbl + MT * ib + lane % MT);
+    alive[ib] = sl[ib]->done == 0;
+    r_act[ib] = sl[ib]->r_keep;  // active pairs: margin <= r_act
+  }
+  bool tile_on[WA][WB], sub_on[WA][WB];
+  bool wave_on = false;
+#pragma unroll
+  for (int ia = 0; ia < WA; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < WB; ++ib) {
+      const int at = (a0b + wal + MT * ia) / MT;
+      const int64_t tix = static_cast<int64_t>(at) * a.Bp + (b0b + wbl + MT * ib + lane % MT);
+      tile_on[ia][ib] = alive[ib] && static_cast<double>(a.tminm[tix]) <= r_act[ib];
+      sub_on[ia][ib] = __ballot(tile_on[ia][ib]) != 0;
+      wave_on |= sub_on[ia][ib];
+      if (!sub_on[ia][ib] && lane < MT) {
+        a.pz[tix] = 0.0;
+        a.pom[tix] = 0.0;
+        a.pact[tix] = 0;
+        a.umask[tix] = 0u;
+      }
+    }
   if (lane == 0) s_on[wave] = wave_on ? 1 : 0;
   __syncthreads();
-  const bool block_on = (s_on[0] | s_on[1] | s_on[2] | s_on[3]) != 0;
-  if (!wave_on) {
-    if (lane < MT) {
-      a.pz[tix] = 0.0;
-      a.pom[tix] = 0.0;
-      a.pact[tix] = 0;
-      a.umask[tix] = 0u;
-    }
-  }
+  bool block_on = false;
+#pragma unroll
+  for (int w = 0; w < NWV; ++w) block_on |= s_on[w] != 0;
   if (!block_on) {
     if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
     return;
   }
-  // The block stages 64-row chunks of its 64 atoms and of the three parts of its 64
-  // signals' theta through LDS with 128-byte coalesced loads; each wave reads its MFMA
-  // fragments from LDS.  Each chunk is accumulated in FP32 on the matrix cores from zero
-  // and then added to FP64 registers, so an FP32 rounding chain spans 3 x 64 products.
   const int64_t plane = static_cast<int64_t>(a.Bp) * a.Np;
   const int kk = (lane / MT) * 8;
-  double zacc[16];
+  double zacc[WA][WB][16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) zacc[i] = 0.0;
+  for (int ia = 0; ia < WA; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < WB; ++ib)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) zacc[ia][ib][i] = 0.0;
   // chunk n0 + ZR is fetched into registers while chunk n0 is multiplied
-  uint4 pa[2], pb[6];
+  uint4 pa[PA], pb[PB];
   auto fetch = [&](int n0) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {  // 64 rows x 128 bytes of D: 512 16-byte pieces
-      const int e = threadIdx.x + r * TB;
+    for (int r = 0; r < PA; ++r) {  // TA rows x 128 bytes of D
+      const int e = threadIdx.x + r * NT;
       pa[r] = ldg16(a.dcm + static_cast<int64_t>(a0b + e / 8) * a.Np + n0 + (e % 8) * 8);
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {  // 3 x 64 rows x 128 bytes of theta
-      const int e = threadIdx.x + r * TB;
-      pb[r] = ldg16(a.Ths + (e / 512) * plane + static_cast<int64_t>(b0b + (e % 512) / 8) * a.Np + n0 +
-                    (e % 8) * 8);
+    for (int r = 0; r < PB; ++r) {  // 3 x TS rows x 128 bytes of theta
+      const int e = threadIdx.x + r * NT;
+      pb[r] = ldg16(a.Ths + (e / (TS * 8)) * plane +
+                    static_cast<int64_t>(b0b + (e % (TS * 8)) / 8) * a.Np + n0 + (e % 8) * 8);
     }
   };
   fetch(0);
   for (int n0 = 0; n0 < a.Np; n0 += ZR) {
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int e = threadIdx.x + r * TB;
+    for (int r = 0; r < PA; ++r) {
+      const int e = threadIdx.x + r * NT;
       *reinterpret_cast<uint4*>(&sA[e / 8][(e % 8) * 8]) = pa[r];
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      const int e = threadIdx.x + r * TB;
-      *reinterpret_cast<uint4*>(&sB[e / 512][(e % 512) / 8][(e % 8) * 8]) = pb[r];
+    for (int r = 0; r < PB; ++r) {
+      const int e = threadIdx.x + r * NT;
+      *reinterpret_cast<uint4*>(&sB[e / (TS * 8)][(e % (TS * 8)) / 8][(e % 8) * 8]) = pb[r];
     }
     __syncthreads();
     if (n0 + ZR < a.Np) fetch(n0 + ZR);
     if (wave_on) {
-      f32x16 c;
+      f32x16 c[WA][WB];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) c[i] = 0.f;
+      for (int ia = 0; ia < WA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < WB; ++ib)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) c[ia][ib][i] = 0.f;
       // raised wave priority while the chunk's MFMAs issue: the waves staging the next
       // chunk through LDS then yield to the ones that keep the matrix cores busy
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s16 = 0; s16 < ZR; s16 += 16) {
-        const bf16x8 ad = as_bf16x8(*reinterpret_cast<const uint4*>(&sA[wa + lane % MT][s16 + kk]));
-        const bf16x8 h = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[0][wb + lane % MT][s16 + kk]));
-        const bf16x8 m = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[1][wb + lane % MT][s16 + kk]));
-        const bf16x8 l = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[2][wb + lane % MT][s16 + kk]));
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, h, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, m, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad, l, c, 0, 0, 0);
+        bf16x8 ad[WA], h[WB], m[WB], l[WB];
+#pragma unroll
+        for (int ia = 0; ia < WA; ++ia)
+          ad[ia] = as_bf16x8(*reinterpret_cast<const uint4*>(&sA[wal + MT * ia + lane % MT][s16 + kk]));
+#pragma unroll
+        for (int ib = 0; ib < WB; ++ib) {
+          const int sr = wbl + MT * ib + lane % MT;
+          h[ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[0][sr][s16 + kk]));
+          m[ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[1][sr][s16 + kk]));
+          l[ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[2][sr][s16 + kk]));
+        }
+#pragma unroll
+        for (int ia = 0; ia < WA; ++ia)
+#pragma unroll
+          for (int ib = 0; ib < WB; ++ib) {
+            if (!sub_on[ia][ib]) continue;
+            c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], h[ib], c[ia][ib], 0, 0, 0);
+            c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], m[ib], c[ia][ib], 0, 0, 0);
+            c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], l[ib], c[ia][ib], 0, 0, 0);
+          }
       }
       __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) zacc[i] += static_cast<double>(c[i]);
+      for (int ia = 0; ia < WA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < WB; ++ib)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) zacc[ia][ib][i] += static_cast<double>(c[ia][ib][i]);
     }
   }
   if (!wave_on) {
     if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
     return;
   }
-  // epilogue: lane holds signal bl, atoms a0 + 8 q + (lane / 32) * 4 + e
-  double zm = 0.0;
-  double om = 0.0;
-  int nact = 0, nsup = 0;
-  uint32_t bits = 0u;
-  if (tile_on) {
-    const double invL = 1.0 / a.L, thr = sl.lam / a.L;
+  // epilogue per output tile: lane holds signal bl, atoms a0 + 8 q + (lane / 32) * 4 + e
+#pragma unroll
+  for (int ib = 0; ib < WB; ++ib) {
+    const int bl = b0b + wbl + MT * ib + lane % MT;
+    const Inst& st = *sl[ib];
+    const double invL = 1.0 / a.L, thr = st.lam / a.L;
     double beta = 0.0;
     if (a.rule == 1) {
-      const double lp = sl.l_prev;
+      const double lp = st.l_prev;
       beta = (lp - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * lp * lp)));
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ab = a0 + 8 * q + (lane / MT) * 4;
-      const int64_t o = static_cast<int64_t>(bl) * a.Kp + ab;
-      const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
-      const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
-      bool any = false;
+    for (int ia = 0; ia < WA; ++ia) {
+      if (!sub_on[ia][ib]) continue;
+      const int a0 = a0b + wal + MT * ia;
+      const int64_t tix = static_cast<int64_t>(a0 / MT) * a.Bp + bl;
+      double zm = 0.0;
+      double om = 0.0;
+      int nact = 0, nsup = 0;
+      uint32_t bits = 0u;
+      if (tile_on[ia][ib]) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) any |= static_cast<double>(mm[e]) <= r_act;
-      if (!any) continue;
-      *reinterpret_cast<float4*>(a.Z + o) =
-          make_float4(static_cast<float>(zacc[4 * q]), static_cast<float>(zacc[4 * q + 1]),
-                      static_cast<float>(zacc[4 * q + 2]), static_cast<float>(zacc[4 * q + 3]));
-      const float4 u4 = *reinterpret_cast<const float4*>(Uin + o);
-      const float4 x4 = *reinterpret_cast<const float4*>(a.X + o);
-      float uu[4] = {u4.x, u4.y, u4.z, u4.w};
-      float xx[4] = {x4.x, x4.y, x4.z, x4.w};
+        for (int q = 0; q < 4; ++q) {
+          const int ab = a0 + 8 * q + (lane / MT) * 4;
+          const int64_t o = static_cast<int64_t>(bl) * a.Kp + ab;
+          const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
+          const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
+          bool any = false;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (!(static_cast<double>(mm[e]) <= r_act)) continue;
-        const double z = zacc[4 * q + e];
-        zm = fmax(zm, fabs(z));
-        const double p = uu[e];
-        om += fabs(p);
-        ++nact;
-        nsup += uu[e] != 0.f;
-        const double v = p - z * invL;
-        const double mag = fabs(v) - thr;
-        const double xn = mag > 0.0 ? copysign(mag, v) : 0.0;
-        const double un = xn + beta * (xn - static_cast<double>(xx[e]));
-        xx[e] = static_cast<float>(xn);
-        uu[e] = static_cast<float>(un);
+          for (int e = 0; e < 4; ++e) any |= static_cast<double>(mm[e]) <= r_act[ib];
+          if (!any) continue;
+          const double* zq = &zacc[ia][ib][4 * q];
+          *reinterpret_cast<float4*>(a.Z + o) =
+              make_float4(static_cast<float>(zq[0]), static_cast<float>(zq[1]),
+                          static_cast<float>(zq[2]), static_cast<float>(zq[3]));
+          const float4 u4 = *reinterpret_cast<const float4*>(Uin + o);
+          const float4 x4 = *reinterpret_cast<const float4*>(a.X + o);
+          float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+          float xx[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (!(static_cast<double>(mm[e]) <= r_act[ib])) continue;
+            const double z = zq[e];
+            zm = fmax(zm, fabs(z));
+            const double p = uu[e];
+            om += fabs(p);
+            ++nact;
+            nsup += uu[e] != 0.f;
+            const double v = p - z * invL;
+            const double mag = fabs(v) - thr;
+            const double xn = mag > 0.0 ? copysign(mag, v) : 0.0;
+            const double un = xn + beta * (xn - static_cast<double>(xx[e]));
+            xx[e] = static_cast<float>(xn);
+            uu[e] = static_cast<float>(un);
+          }
+          *reinterpret_cast<float4*>(a.X + o) = make_float4(xx[0], xx[1], xx[2], xx[3]);
+          *reinterpret_cast<float4*>(Uout + o) = make_float4(uu[0], uu[1], uu[2], uu[3]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (uu[e] != 0.f) bits |= 1u << (8 * q + (lane / MT) * 4 + e);
+        }
       }
-      *reinterpret_cast<float4*>(a.X + o) = make_float4(xx[0], xx[1], xx[2], xx[3]);
-      *reinterpret_cast<float4*>(Uout + o) = make_float4(uu[0], uu[1], uu[2], uu[3]);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (uu[e] != 0.f) bits |= 1u << (8 * q + (lane / MT) * 4 + e);
+      // the two half-waves hold the same signals on different atoms of the tile
+      zm = fmax(zm, __shfl_xor(zm, 32, BW));
+      om += __shfl_xor(om, 32, BW);
+      int cnt = nact | (nsup << 8);
+      cnt += __shfl_xor(cnt, 32, BW);
+      bits |= __shfl_xor(bits, 32, BW);
+      if (lane < MT) {
+        a.pz[tix] = zm;
+        a.pom[tix] = om;
+        a.pact[tix] = cnt;
+        a.umask[tix] = bits;
+      }
     }
-  }
-  // the two half-waves hold the same signals on different atoms of the tile
-  zm = fmax(zm, __shfl_xor(zm, 32, BW));
-  om += __shfl_xor(om, 32, BW);
-  int cnt = nact | (nsup << 8);
-  cnt += __shfl_xor(cnt, 32, BW);
-  bits |= __shfl_xor(bits, 32, BW);
-  if (lane < MT) {
-    a.pz[tix] = zm;
-    a.pom[tix] = om;
-    a.pact[tix] = cnt;
-    a.umask[tix] = bits;
   }
   if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
 }
+
+// The block shapes the autotuner chooses from: {RA, RB, WA, WB} (RA x RB waves, each
+// WA x WB output tiles of 32 x 32).
+struct ZShapeDesc { int ra, rb, wa, wb; };
+constexpr ZShapeDesc ZSHAPES[] = {{2, 2, 1, 1}, {4, 2, 1, 1}, {4, 1, 1, 1}, {2, 4, 1, 1},
+                                  {1, 4, 1, 1}, {2, 2, 2, 1}, {4, 1, 2, 1}};
+constexpr int NZSHAPE = sizeof(ZSHAPES) / sizeof(ZSHAPES[0]);
+constexpr int KP_ALIGN = 128;  // Kp is a multiple of it; larger atom extents need Kp % TA == 0
 
 // FP64 scalars of iteration t, one wave per slot: dual scaling (Lemma 7) from the MFMA
 // correlations, gap estimate, sphere radius (SAFE: R; DST3: sqrt(R^2 - rho^2)) grown by
