@@ -87,6 +87,42 @@ def batched_setup(binding, D):
     return one
 
 
+STREAM_SIGNALS = 1024
+
+
+def batched_stream_leg(binding, D, steps=2):
+    """Continuous batching: 1024 signals of the batched workload's generator through the
+    default 256 resident slots of the bfloat16 path (a finished signal's slot takes the next
+    waiting one), lambda / lambda_* uniform in [0.1, 0.9], gap 1e-6: solves/s."""
+    import torch
+    Dbf = datagen.to_storage(D, "bf16")
+    Dd = torch.from_numpy(np.ascontiguousarray(Dbf.T)).to(device="cuda", dtype=torch.bfloat16).T
+    ys = np.stack([datagen.to_storage(datagen.lasso_signal(D, j)[0], "f32")
+                   for j in range(STREAM_SIGNALS)])
+    Y = torch.from_numpy(ys.astype(np.float32)).cuda().T
+    ratios = datagen.lambda_ratios(STREAM_SIGNALS, 0.1, 0.9, datagen.LAMBDA_SEED0)
+    L = binding.spectral_norm_sq(Dd, 300)
+
+    def one():
+        _, infos = binding.solve(Dd, Y, ratios, step_L=L, gap_tol=GAP_TOL, max_iter=20000)
+        if any(i["status"] != 0 for i in infos):
+            raise RuntimeError("streamed batched solve did not converge")
+        return infos
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = one()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = [i["iters"] for i in infos]
+    return {"workload": "lasso_fista_dst3_gaussian_2000x10000_bf16_stream1024_slots256",
+            "signals": STREAM_SIGNALS, "slots": 256,
+            "solves_per_s": round(STREAM_SIGNALS * steps / dt, 2),
+            "ms_per_stream": round(dt * 1e3 / steps, 3),
+            "iterations": {"max": int(max(it)), "mean": round(float(np.mean(it)), 1)}}
+
+
 def batched_roofline(binding, one):
     """One instrumented batched solve: matrix-core roofline of the Z = D^T Theta GEMM."""
     binding.stats_reset()
@@ -954,6 +990,8 @@ def main():
     if "batched" in legs:
         b = batched_leg(binding, D, max(1, args.steps // 2), 1)
         b["over_plain_single"] = round(b["solves_per_s"] / plain, 2)
+        b["stream"] = batched_stream_leg(binding, D)
+        b["stream"]["over_plain_single"] = round(b["stream"]["solves_per_s"] / plain, 2)
         out["batched"] = b
     if "seeds" in legs:
         out["per_lambda_30_signals"] = seeds_leg(binding, D, Dd, L)

@@ -144,6 +144,10 @@ typedef struct {
                         (|P_{t-1} - P_t| <= obj_tol P_t), the stopping rule of the paper's
                         experiments section (there with 1e-7 and max_iter = 200).  Such a
                         stop returns DS_OK.  The batched bfloat16 path returns DS_EINVAL. */
+  int32_t batch_slots; /* batched bfloat16 path: signals resident on the device at once
+                        (0: min(B, 256)).  When B exceeds it, the other signals wait and take
+                        the slots of finished ones (continuous batching); results do not depend
+                        on it.  Ignored elsewhere; must be >= 0. */
 } ds_params;
 
 /* Per-signal result.  The gap certificate of iteration t pairs the primal point at which

@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("screening", C.c_int32), ("step_rule", C.c_int32), ("bt_eta", C.c_double),
                 ("bb_memory", C.c_int32), ("bb_sigma", C.c_double), ("cp_tau", C.c_double),
                 ("cp_sigma", C.c_double), ("cp_gamma", C.c_double), ("x0", C.c_void_p),
-                ("obj_tol", C.c_double)]
+                ("obj_tol", C.c_double), ("batch_slots", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -189,18 +189,20 @@ SCREENING = {"dynamic": 0, "static": 1}
 
 def make_params(rule="fista", test="dst3", lambda_relative=True, step_L=0.0, gap_tol=1e-6,
                 max_iter=10000, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0_ptr=None, obj_tol=0.0):
+                bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0_ptr=None, obj_tol=0.0,
+                batch_slots=0):
     return Params(RULES[rule], TESTS[test], 1 if lambda_relative else 0, float(step_L),
                   float(gap_tol), int(max_iter), SCREENING[screening], STEPS[step], float(bt_eta),
                   int(bb_memory), float(bb_sigma), float(cp_tau), float(cp_sigma),
                   float(cp_gamma), None if x0_ptr is None else C.c_void_p(x0_ptr),
-                  float(obj_tol))
+                  float(obj_tol), int(batch_slots))
 
 
 def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="dst3",
           lambda_relative=True, step_L=0.0, gap_tol=1e-6, max_iter=10000, stream=None, out=None,
           screened=False, screening="dynamic", step="constant", bt_eta=0.0, bb_memory=0,
-          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None, obj_tol=0.0):
+          bb_sigma=0.0, cp_tau=0.0, cp_sigma=0.0, cp_gamma=0.0, x0=None, obj_tol=0.0,
+          batch_slots=0):
     """Solve B Lasso (or Group-Lasso if group_ptr is given) problems sharing D.
 
     Y: device tensor (N,) or N x B column-major; lambdas: B floats (ratios to lambda_* when
@@ -236,7 +238,7 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     prob = make_problem(D, group_ptr, weights)
     prm = make_params(rule, test, lambda_relative, step_L, gap_tol, max_iter, screening, step, bt_eta,
                       bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
-                      None if x0 is None else x0.data_ptr(), obj_tol)
+                      None if x0 is None else x0.data_ptr(), obj_tol, batch_slots)
     if screened:
         if group_ptr is not None:
             raise ValueError("screened masks of batched solves are for the Lasso")

@@ -153,6 +153,7 @@ ds_status validate_params(const ds_params* p) {
   }
   if (!(p->gap_tol >= 0.0) || !std::isfinite(p->gap_tol)) { set_error("gap_tol must be >= 0"); return DS_EINVAL; }
   if (!(p->obj_tol >= 0.0) || !std::isfinite(p->obj_tol)) { set_error("obj_tol must be >= 0"); return DS_EINVAL; }
+  if (p->batch_slots < 0) { set_error("batch_slots must be >= 0"); return DS_EINVAL; }
   if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return DS_EINVAL; }
   if (!std::isfinite(p->step_L)) { set_error("step_L must be finite"); return DS_EINVAL; }
   if (p->screening != 0 && p->screening != 1) { set_error("screening must be 0 (dynamic) or 1 (static)"); return DS_EINVAL; }

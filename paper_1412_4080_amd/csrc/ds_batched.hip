@@ -27,6 +27,7 @@ namespace {
 using namespace batch;
 
 constexpr int ITERS_PER_GRAPH = 8;  // iterations per graph replay (even)
+constexpr int MAX_SLOTS = 256;      // resident signals when the caller does not set batch_slots
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -34,8 +35,8 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 struct BLayout {
   int N, K, B, Np, Kp, Bp, nrb;
   size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
-      inst, ctr, vlist, perm, lam, z0, gn, Vn, kclk, spans, tX, tU, tZ, tpz, tpom, tpact, tmask,
-      total;
+      inst, ctr, vlist, perm, slist, dflag, lam, z0, gn, Vn, kclk, spans, tX, tU, tZ, tpz, tpom,
+      tpact, tmask, total;
   int nspan;
 };
 
@@ -74,6 +75,8 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.ctr = take(4 * sizeof(int));
   l.vlist = take(bp * 4);
   l.perm = take(bp * 4);
+  l.slist = take(bp * 4);
+  l.dflag = take(bp * 4);
   l.lam = take(bp * 8);
   l.z0 = take(bp * kp * 8);
   l.gn = take(bp * kp * 8);
@@ -267,16 +270,19 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
 ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
                              const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
                              ds_info* info, uint8_t* screened, hipStream_t stream) {
-  if (P.N > (1 << 24) || P.K > (1 << 24) || B > 32768) {
-    set_error("batched path: N, K must be <= 2^24 and B <= 32768");
+  // resident slots: all signals up to MAX_SLOTS, or the caller's batch_slots; the rest wait
+  // and take the slots of finished signals (continuous batching)
+  const int64_t want = prm.batch_slots > 0 ? prm.batch_slots : std::min<int64_t>(B, MAX_SLOTS);
+  const int nslot = static_cast<int>(std::min<int64_t>(want, B));
+  if (P.N > (1 << 24) || P.K > (1 << 24) || nslot > 32768 || B > (int64_t(1) << 30)) {
+    set_error("batched path: N, K must be <= 2^24, batch_slots <= 32768 and B <= 2^30");
     return DS_EINVAL;
   }
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   BatchCtx& C = batch_ctx(dev);
   std::lock_guard<std::mutex> guard(C.mu);
-  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), static_cast<int>(B),
-                                prm.max_iter);
+  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), nslot, prm.max_iter);
   ds_status e = C.ws.reserve(l.total);
   if (e != DS_OK) return e;
   if (C.stream == nullptr) {
@@ -304,18 +310,29 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   char* base = static_cast<char*>(C.ws.base);
   BArgs a = make_args(l, base, prm, L);
 
-  // slots ordered by penalty so that signals finishing together share tiles
-  std::vector<int> perm(l.Bp);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.begin() + B,
-                   [&](int i, int j) { return lambdas[i] > lambdas[j]; });
+  // signals in order of increasing penalty: neighbouring slots hold signals that finish
+  // together (whole tiles fall idle), and when signals wait for slots the slow ones (small
+  // lambda needs the most iterations) start first, which keeps the end of the run short;
+  // slot k starts with signal order[k], and finished slots take the next ones
+  std::vector<int> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return lambdas[i] < lambdas[j]; });
+  std::vector<int> slot_sig(l.Bp, -1);
   std::vector<double> lam_slot(l.Bp, 1.0);
-  for (int64_t k = 0; k < B; ++k) lam_slot[k] = lambdas[perm[k]];
-  for (int k = static_cast<int>(B); k < l.Bp; ++k) perm[k] = 0;
+  int64_t next = 0;
+  for (int k = 0; k < nslot; ++k) {
+    slot_sig[k] = order[next];
+    lam_slot[k] = lambdas[order[next]];
+    ++next;
+  }
   int* d_perm = reinterpret_cast<int*>(base + l.perm);
   double* d_lam = reinterpret_cast<double*>(base + l.lam);
-  DS_HIP(hipMemcpyAsync(d_perm, perm.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
+  int* d_list = reinterpret_cast<int*>(base + l.slist);
+  std::vector<int> list(l.Bp);
+  std::iota(list.begin(), list.end(), 0);
+  DS_HIP(hipMemcpyAsync(d_perm, slot_sig.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
   DS_HIP(hipMemcpyAsync(d_lam, lam_slot.data(), l.Bp * sizeof(double), hipMemcpyHostToDevice, s));
+  DS_HIP(hipMemcpyAsync(d_list, list.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
 
   // ---------------------------------------------------------------- setup
   StatAccum& S = stats();
@@ -331,10 +348,6 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     DS_HIP(hipEventRecord(su0, s));
   }
   DS_HIP(hipMemsetAsync(base + l.ctr, 0, 4 * sizeof(int), s));
-  DS_HIP(hipMemsetAsync(base + l.X, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s));
-  DS_HIP(hipMemsetAsync(base + l.U0, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s));
-  DS_HIP(hipMemsetAsync(base + l.U1, 0, static_cast<size_t>(l.Bp) * l.Kp * 4, s));
-  DS_HIP(hipMemsetAsync(base + l.umask, 0, static_cast<size_t>(l.Kp / MT) * l.Bp * 4, s));
   uint16_t* dcm = reinterpret_cast<uint16_t*>(base + l.dcm);
   hipLaunchKernelGGL(k_b_prep, dim3(l.Kp, (l.Np + TB - 1) / TB), dim3(TB), 0, s,
                      static_cast<const uint16_t*>(P.D), P.ldd, l.N, l.K, l.Np, dcm);
@@ -343,22 +356,40 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   hipLaunchKernelGGL(k_b_dict_scalars, dim3(1), dim3(TB), 0, s,
                      reinterpret_cast<const double*>(base + l.nu), l.K,
                      reinterpret_cast<double*>(base + l.dsc));
-  hipLaunchKernelGGL(k_b_load_y, dim3((l.Np + TB - 1) / TB, l.Bp), dim3(TB), 0, s,
-                     static_cast<const float*>(Y), ldy, d_perm, l.N, l.B, l.Np,
-                     reinterpret_cast<float*>(base + l.Y));
   double* z0 = reinterpret_cast<double*>(base + l.z0);
   double* gn = reinterpret_cast<double*>(base + l.gn);
   float* Vn = reinterpret_cast<float*>(base + l.Vn);
-  hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 64), dim3(TB), 0, s, dcm, a.Y, l.Np, l.Kp, z0);
-  hipLaunchKernelGGL(k_b_inst_init, dim3(l.Bp), dim3(TB), 0, s, a, z0, d_lam,
-                     prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0, prm.gap_tol, Vn);
-  if (prm.test == DS_TEST_DST3)
-    hipLaunchKernelGGL(k_b_dtv64, dim3(l.Kp / 64, l.Bp / 64), dim3(TB), 0, s, dcm, Vn, l.Np, l.Kp, gn);
-  hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a, z0, gn,
-                     reinterpret_cast<float*>(base + l.marg));
-  hipLaunchKernelGGL(k_b_tile_min, dim3((l.Kp / MT + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a,
-                     reinterpret_cast<float*>(base + l.tminm));
-  DS_HIP(hipGetLastError());
+  float* Yp = reinterpret_cast<float*>(base + l.Y);
+  // per-slot set-up of the first n entries of d_list: y, cleared x / u / masks, D^T y,
+  // lambda_* and the centre, D^T n (DST3), margins and their tile minima
+  auto setup_slots = [&](int n) -> ds_status {
+    hipLaunchKernelGGL(k_b_load_slots, dim3(std::max(1, (l.Kp + TB - 1) / TB), n), dim3(TB), 0, s, a,
+                       static_cast<const float*>(Y), ldy, static_cast<const int*>(d_perm),
+                       static_cast<const int*>(d_list), Yp);
+    // FP64 D^T v for the listed slots: 64-slot tiles for the whole batch, 16-slot tiles for
+    // a few refilled slots (the same sums either way)
+    auto dtv = [&](const float* V, double* out) {
+      if (n > 16)
+        hipLaunchKernelGGL(k_b_dtv64<64>, dim3(l.Kp / 64, (n + 63) / 64), dim3(TB), 0, s, dcm, V,
+                           l.Np, l.Kp, out, static_cast<const int*>(d_list), n);
+      else
+        hipLaunchKernelGGL(k_b_dtv64<16>, dim3(l.Kp / 64, 1), dim3(TB), 0, s, dcm, V, l.Np, l.Kp,
+                           out, static_cast<const int*>(d_list), n);
+    };
+    dtv(a.Y, z0);
+    hipLaunchKernelGGL(k_b_inst_init, dim3(n), dim3(TB), 0, s, a, z0, d_lam,
+                       prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0, prm.gap_tol, Vn,
+                       static_cast<const int*>(d_perm), static_cast<const int*>(d_list));
+    if (prm.test == DS_TEST_DST3) dtv(Vn, gn);
+    hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, n), dim3(TB), 0, s, a, z0, gn,
+                       reinterpret_cast<float*>(base + l.marg), static_cast<const int*>(d_perm),
+                       static_cast<const int*>(d_list));
+    hipLaunchKernelGGL(k_b_tile_min, dim3((l.Kp / MT + TB - 1) / TB, n), dim3(TB), 0, s, a,
+                       reinterpret_cast<float*>(base + l.tminm), static_cast<const int*>(d_list));
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+  };
+  if ((e = setup_slots(l.Bp)) != DS_OK) return e;
   if (stat_on) DS_HIP(hipEventRecord(su1, s));
 
   // ---------------------------------------------------------------- iteration
@@ -420,55 +451,87 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     if (timed && et.first) { evt.push_back(et); evz.push_back(ez); }
   };
 
+  if (!stat_on &&
+      (C.exec == nullptr || std::memcmp(&C.key, &a, sizeof a) != 0 || C.key_shape != shape)) {
+    if (C.exec != nullptr) {
+      DS_HIP(hipGraphExecDestroy(C.exec));
+      C.exec = nullptr;
+    }
+    hipGraph_t graph;
+    DS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 1; k <= ITERS_PER_GRAPH; ++k) iteration(k, false);
+    const hipError_t ce = hipGetLastError();
+    DS_HIP(hipStreamEndCapture(s, &graph));
+    DS_HIP(ce);
+    const hipError_t ie = hipGraphInstantiate(&C.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      C.exec = nullptr;
+      DS_HIP(ie);
+    }
+    C.key = a;
+    C.key_shape = shape;
+  }
+  if (stat_on) C.ev_used = 0;
+
+  // Runs of ITERS_PER_GRAPH iterations (graph replays, or direct launches when instrumented)
+  // until every signal has finished.  After each run the slots' states are read; finished
+  // slots report (counts, x scattered to the caller's X) and take the next waiting signals.
+  std::vector<Inst> hs(l.Bp);
+  std::vector<Inst> result(B);
+  std::vector<int> hflag(l.Bp);
+  int* d_flag = reinterpret_cast<int*>(base + l.dflag);
+  std::vector<int> fin, refill;
+  double act = 0.0, sup = 0.0;  // work of the finished signals (statistics)
+  int64_t nactive = nslot;      // slots holding a signal
   int t = 0;
-  if (stat_on) {
-    // instrumented run: direct launches with events in the dispatches
-    C.ev_used = 0;
-    while (t < prm.max_iter) {
+  while (nactive > 0) {
+    if (stat_on) {
       for (int k = 0; k < ITERS_PER_GRAPH; ++k) iteration(++t, true);
       DS_HIP(hipGetLastError());
-      DS_HIP(hipMemcpyAsync(C.host_ctr, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
-      DS_HIP(hipStreamSynchronize(s));
-      if (*C.host_ctr >= B) break;
-    }
-  } else {
-    if (C.exec == nullptr || std::memcmp(&C.key, &a, sizeof a) != 0 || C.key_shape != shape) {
-      if (C.exec != nullptr) {
-        DS_HIP(hipGraphExecDestroy(C.exec));
-        C.exec = nullptr;
-      }
-      hipGraph_t graph;
-      DS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      for (int k = 1; k <= ITERS_PER_GRAPH; ++k) iteration(k, false);
-      const hipError_t ce = hipGetLastError();
-      DS_HIP(hipStreamEndCapture(s, &graph));
-      DS_HIP(ce);
-      const hipError_t ie = hipGraphInstantiate(&C.exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        C.exec = nullptr;
-        DS_HIP(ie);
-      }
-      C.key = a;
-      C.key_shape = shape;
-    }
-    while (t < prm.max_iter) {
+    } else {
       DS_HIP(hipGraphLaunch(C.exec, s));
       t += ITERS_PER_GRAPH;
-      DS_HIP(hipMemcpyAsync(C.host_ctr, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
-      DS_HIP(hipStreamSynchronize(s));
-      if (*C.host_ctr >= B) break;
+    }
+    hipLaunchKernelGGL(k_b_done_flags, dim3((l.Bp + TB - 1) / TB), dim3(TB), 0, s, a, d_flag);
+    DS_HIP(hipMemcpyAsync(hflag.data(), d_flag, l.Bp * sizeof(int), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipStreamSynchronize(s));
+    fin.clear();
+    for (int k = 0; k < l.Bp; ++k)
+      if (slot_sig[k] >= 0 && hflag[k] != 0) fin.push_back(k);
+    if (fin.empty()) continue;
+    // report the finished slots
+    DS_HIP(hipMemcpyAsync(d_list, fin.data(), fin.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const int nf = static_cast<int>(fin.size());
+    hipLaunchKernelGGL(k_b_counts, dim3(nf), dim3(TB), 0, s, a, static_cast<const int*>(d_list));
+    hipLaunchKernelGGL(k_b_scatter, dim3((l.K + TB - 1) / TB, nf), dim3(TB), 0, s, a,
+                       static_cast<const int*>(d_perm), static_cast<float*>(X), ldx, screened,
+                       static_cast<const int*>(d_list));
+    DS_HIP(hipGetLastError());
+    DS_HIP(hipMemcpyAsync(hs.data(), a.inst, l.Bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipStreamSynchronize(s));
+    refill.clear();
+    for (int k : fin) {
+      result[slot_sig[k]] = hs[k];
+      act += hs[k].act_sum;
+      sup += hs[k].sup_sum;
+      if (next < B) {
+        slot_sig[k] = order[next];
+        lam_slot[k] = lambdas[order[next]];
+        ++next;
+        refill.push_back(k);
+      } else {
+        slot_sig[k] = -1;
+        --nactive;
+      }
+    }
+    if (!refill.empty()) {
+      DS_HIP(hipMemcpyAsync(d_perm, slot_sig.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
+      DS_HIP(hipMemcpyAsync(d_lam, lam_slot.data(), l.Bp * sizeof(double), hipMemcpyHostToDevice, s));
+      DS_HIP(hipMemcpyAsync(d_list, refill.data(), refill.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      if ((e = setup_slots(static_cast<int>(refill.size()))) != DS_OK) return e;
     }
   }
-
-  // ---------------------------------------------------------------- output
-  hipLaunchKernelGGL(k_b_counts, dim3(l.Bp), dim3(TB), 0, s, a);
-  hipLaunchKernelGGL(k_b_scatter, dim3((l.K + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a, d_perm,
-                     static_cast<float*>(X), ldx, screened);
-  DS_HIP(hipGetLastError());
-  std::vector<Inst> hs(l.Bp);
-  DS_HIP(hipMemcpyAsync(hs.data(), a.inst, l.Bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
-  DS_HIP(hipStreamSynchronize(s));
 
   if (stat_on) {
     double ms_z = 0.0, ms_zev = 0.0, ms_t = 0.0, ms_s = 0.0;
@@ -480,8 +543,6 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     for (auto& p : evz) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_zev += m; }
     for (auto& p : evt) { float m = 0.f; if (hipEventElapsedTime(&m, p.first, p.second) == hipSuccess) ms_t += m; }
     { float m = 0.f; if (hipEventElapsedTime(&m, su0, su1) == hipSuccess) ms_s = m; }
-    double act = 0.0, sup = 0.0;
-    for (int k = 0; k < l.Bp; ++k) { act += hs[k].act_sum; sup += hs[k].sup_sum; }
     std::lock_guard<std::mutex> g(S.mu);
     // algorithmic work: 2 N flops per active (atom, signal) pair for Z, per support entry
     // of the primal point for Theta; bytes: D once plus the per-signal vectors
@@ -505,9 +566,9 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
 
   ds_status worst = DS_OK;
   bool bad = false;
-  for (int k = 0; k < B; ++k) {
-    const Inst& h = hs[k];
-    ds_info& r = info[perm[k]];
+  for (int64_t b = 0; b < B; ++b) {
+    const Inst& h = result[b];
+    ds_info& r = info[b];
     std::memset(&r, 0, sizeof r);
     if (h.status < 0) {
       bad = true;

@@ -141,59 +141,85 @@ __global__ __launch_bounds__(TB) void k_b_dict_scalars(const double* __restrict_
   }
 }
 
-// Observations in slot order: Yp[s][n] = Y[perm[s] * ldy + n] (zero padded).
-__global__ __launch_bounds__(TB) void k_b_load_y(const float* __restrict__ Yin, int64_t ldy,
-                                                 const int* __restrict__ perm, int N, int B,
-                                                 int Np, float* __restrict__ Yp) {
-  const int s = blockIdx.y;
-  const int n = blockIdx.x * TB + threadIdx.x;
-  if (n >= Np) return;
-  float v = 0.f;
-  if (s < B && n < N) v = Yin[static_cast<int64_t>(perm[s]) * ldy + n];
-  Yp[static_cast<int64_t>(s) * Np + n] = v;
+// The set-up and output kernels work on a list of slots (blockIdx.y or blockIdx.x indexes
+// `slots`): the whole batch at the start, the refilled or finished slots later.
+// perm[s] is the signal held by slot s, or -1 for an idle slot.
+
+// Observations of the listed slots: Yp[s][n] = Y[perm[s] * ldy + n] (zero padded; zero
+// for an idle slot); x, both u buffers and the non-zero masks of the slot are cleared.
+__global__ __launch_bounds__(TB) void k_b_load_slots(BArgs a, const float* __restrict__ Yin,
+                                                     int64_t ldy, const int* __restrict__ perm,
+                                                     const int* __restrict__ slots,
+                                                     float* __restrict__ Yp) {
+  const int s = slots[blockIdx.y];
+  const int sig = perm[s];
+  for (int n = blockIdx.x * TB + threadIdx.x; n < a.Np; n += gridDim.x * TB) {
+    float v = 0.f;
+    if (sig >= 0 && n < a.N) v = Yin[static_cast<int64_t>(sig) * ldy + n];
+    Yp[static_cast<int64_t>(s) * a.Np + n] = v;
+  }
+  const int64_t row = static_cast<int64_t>(s) * a.Kp;
+  for (int i = blockIdx.x * TB + threadIdx.x; i < a.Kp; i += gridDim.x * TB) {
+    a.X[row + i] = 0.f;
+    a.U0[row + i] = 0.f;
+    a.U1[row + i] = 0.f;
+    if (i < a.Kp / MT) a.umask[static_cast<int64_t>(i) * a.Bp + s] = 0u;
+  }
 }
 
-// FP64 batched products out[b][a] = d_a^T v_b (exact bfloat16 x float products, FP64
-// accumulation).  Block: 64 atoms x 64 signals; thread: 4 atoms x 4 signals (atoms
-// ta + 16 i, signals tb + 16 j); each output sums its products in row order.
+// FP64 batched products out[b][a] = d_a^T v_b for the listed slots b = slots[j], j < nsl
+// (exact bfloat16 x float products, FP64 accumulation).  Block: 64 atoms x BS list entries;
+// thread: 4 atoms x BS/16 entries (atoms ta + 16 i, entries tb + 16 j); each output sums its
+// products in row order, so the value does not depend on BS.
+template <int BS>
 __global__ __launch_bounds__(TB) void k_b_dtv64(const uint16_t* __restrict__ dcm,
                                                 const float* __restrict__ V, int Np, int Kp,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out,
+                                                const int* __restrict__ slots, int nsl) {
+  constexpr int JS = BS / 16;  // entries per thread
   __shared__ double sd[64][33];
-  __shared__ double sv[64][33];
-  const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+  __shared__ double sv[BS][33];
+  __shared__ int sslot[BS];
+  const int a0 = blockIdx.x * 64, b0 = blockIdx.y * BS;
+  if (threadIdx.x < BS) sslot[threadIdx.x] = slots[min(b0 + static_cast<int>(threadIdx.x), nsl - 1)];
+  __syncthreads();
   const int ta = threadIdx.x % 16, tb = threadIdx.x / 16;
-  double acc[4][4];
+  double acc[4][JS];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < JS; ++j) acc[i][j] = 0.0;
   for (int n0 = 0; n0 < Np; n0 += 32) {
     for (int e = threadIdx.x; e < 64 * 32; e += TB) {
       const int r = e / 32, nn = e % 32;
       sd[r][nn] = bf16f(dcm[static_cast<int64_t>(a0 + r) * Np + n0 + nn]);
-      sv[r][nn] = V[static_cast<int64_t>(b0 + r) * Np + n0 + nn];
+    }
+    for (int e = threadIdx.x; e < BS * 32; e += TB) {
+      const int r = e / 32, nn = e % 32;
+      sv[r][nn] = V[static_cast<int64_t>(sslot[r]) * Np + n0 + nn];
     }
     __syncthreads();
 #pragma unroll 4
     for (int nn = 0; nn < 32; ++nn) {
-      double dv[4], vv[4];
+      double dv[4], vv[JS];
 #pragma unroll
       for (int i = 0; i < 4; ++i) dv[i] = sd[ta + 16 * i][nn];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) vv[j] = sv[tb + 16 * j][nn];
+      for (int j = 0; j < JS; ++j) vv[j] = sv[tb + 16 * j][nn];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(dv[i], vv[j], acc[i][j]);
+        for (int j = 0; j < JS; ++j) acc[i][j] = fma(dv[i], vv[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < JS; ++j) {
+    if (b0 + tb + 16 * j >= nsl) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      out[static_cast<int64_t>(b0 + tb + 16 * j) * Kp + a0 + ta + 16 * i] = acc[i][j];
+    for (int i = 0; i < 4; ++i)
+      out[static_cast<int64_t>(sslot[tb + 16 * j]) * Kp + a0 + ta + 16 * i] = acc[i][j];
+  }
 }
 
 // Per-signal setup (one block per slot): ||y||^2, finiteness, lambda_* = max_i |z0_i|
@@ -204,15 +230,17 @@ __global__ __launch_bounds__(TB) void k_b_dtv64(const uint16_t* __restrict__ dcm
 __global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __restrict__ z0,
                                                     const double* __restrict__ lam_in,
                                                     int lam_relative, double gap_tol,
-                                                    float* __restrict__ Vn) {
+                                                    float* __restrict__ Vn,
+                                                    const int* __restrict__ perm,
+                                                    const int* __restrict__ slots) {
   __shared__ double sd[NWB];
   __shared__ int si[NWB];
   __shared__ double s_best;
   __shared__ int s_arg;
-  const int s = blockIdx.x, tid = threadIdx.x;
+  const int s = slots[blockIdx.x], tid = threadIdx.x;
   Inst* st = a.inst + s;
   const float* y = a.Y + static_cast<int64_t>(s) * a.Np;
-  if (s >= a.B) {
+  if (perm[s] < 0) {  // idle slot
     for (int n = tid; n < a.Np; n += TB) Vn[static_cast<int64_t>(s) * a.Np + n] = 0.f;
     if (tid == 0) {
       Inst z = {};
@@ -306,14 +334,16 @@ __global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __res
 // Zero atoms and padding: +inf (screened from the start); no test: -inf.
 __global__ __launch_bounds__(TB) void k_b_margins(BArgs a, const double* __restrict__ z0,
                                                   const double* __restrict__ gn,
-                                                  float* __restrict__ marg) {
-  const int s = blockIdx.y;
+                                                  float* __restrict__ marg,
+                                                  const int* __restrict__ perm,
+                                                  const int* __restrict__ slots) {
+  const int s = slots[blockIdx.y];
   const int i = blockIdx.x * TB + threadIdx.x;
   if (i >= a.Kp) return;
   const Inst& st = a.inst[s];
   const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
   float m;
-  if (i >= a.K || s >= a.B || st.done) {
+  if (i >= a.K || perm[s] < 0 || st.done) {
     m = INFINITY;
   } else if (a.test == 0) {
     m = -INFINITY;
@@ -326,8 +356,9 @@ __global__ __launch_bounds__(TB) void k_b_margins(BArgs a, const double* __restr
 }
 
 // Smallest margin of each 32-atom tile: tminm[tile][s].
-__global__ __launch_bounds__(TB) void k_b_tile_min(BArgs a, float* __restrict__ tminm) {
-  const int s = blockIdx.y;
+__global__ __launch_bounds__(TB) void k_b_tile_min(BArgs a, float* __restrict__ tminm,
+                                                   const int* __restrict__ slots) {
+  const int s = slots[blockIdx.y];
   const int tile = blockIdx.x * TB + threadIdx.x;
   if (tile >= a.Kp / MT) return;
   const float* m = a.marg + static_cast<int64_t>(s) * a.Kp + tile * MT;
@@ -991,11 +1022,17 @@ __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
   }
 }
 
+// done flag of every slot (the host reads these after each run of iterations)
+__global__ __launch_bounds__(TB) void k_b_done_flags(BArgs a, int* __restrict__ flags) {
+  const int s = blockIdx.x * TB + threadIdx.x;
+  if (s < a.Bp) flags[s] = a.inst[s].done;
+}
+
 // ============================================================== output
 // Per-slot counts for the report: non-zeros of x and atoms active in the last iteration.
-__global__ __launch_bounds__(TB) void k_b_counts(BArgs a) {
+__global__ __launch_bounds__(TB) void k_b_counts(BArgs a, const int* __restrict__ slots) {
   __shared__ int si[NWB];
-  const int s = blockIdx.x;
+  const int s = slots[blockIdx.x];
   Inst& st = a.inst[s];
   const bool trivial = st.status != 0;
   int nz = 0, na = 0;
@@ -1016,10 +1053,11 @@ __global__ __launch_bounds__(TB) void k_b_counts(BArgs a) {
 // dimension K.
 __global__ __launch_bounds__(TB) void k_b_scatter(BArgs a, const int* __restrict__ perm,
                                                   float* __restrict__ Xout, int64_t ldx,
-                                                  uint8_t* __restrict__ scr) {
-  const int s = blockIdx.y;
+                                                  uint8_t* __restrict__ scr,
+                                                  const int* __restrict__ slots) {
+  const int s = slots[blockIdx.y];
   const int i = blockIdx.x * TB + threadIdx.x;
-  if (s >= a.B || i >= a.K) return;
+  if (perm[s] < 0 || i >= a.K) return;
   const Inst& st = a.inst[s];
   const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
   const int b = perm[s];

@@ -200,3 +200,45 @@ def test_batched_static_screening(B):
         tol = 1e-6 + infos[j]["radius_slack"] + 1e-9
         assert np.all(np.abs(m[diff] - ref.history[0]["r"]) <= tol), (j, diff[:5])
         assert not X[mask[:, j], j].any()
+
+
+@pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe")])
+def test_refilled_slots_give_the_same_results(B, rule, test):
+    """Continuous batching: with fewer resident slots than signals, finished signals hand
+    their slot to waiting ones.  Each signal's arithmetic does not depend on its slot or on
+    the other residents, so the results equal the all-resident solve bit for bit."""
+    D, Dbf, ys, ratios = _batch(320, 1500, 100, 9)
+    Dd, Y = dev_matrix(D, "bf16"), _dev_Y(ys)
+    L = oracle.spectral_norm_sq(Dbf)
+    X0, i0, m0 = B.solve(Dd, Y, ratios, rule=rule, test=test, step_L=L, gap_tol=1e-6,
+                         max_iter=20000, screened=True)
+    X0, m0 = X0.cpu().numpy(), m0.cpu().numpy()
+    assert all(i["status"] == 0 for i in i0)
+    for slots in (64, 17, 1):
+        X, infos, mask = B.solve(Dd, Y, ratios, rule=rule, test=test, step_L=L, gap_tol=1e-6,
+                                 max_iter=20000, screened=True, batch_slots=slots)
+        assert np.array_equal(X.cpu().numpy(), X0), slots
+        assert np.array_equal(mask.cpu().numpy(), m0), slots
+        assert [i["iters"] for i in infos] == [i["iters"] for i in i0], slots
+        assert [i["gap"] for i in infos] == [i["gap"] for i in i0], slots
+        assert [i["nnz"] for i in infos] == [i["nnz"] for i in i0], slots
+
+
+def test_more_signals_than_slots_by_default(B):
+    """300 signals: 256 resident (the default), the rest refilled; the results equal a solve
+    with every signal resident, and a few are certified against the oracle."""
+    D, Dbf, ys, ratios = _batch(200, 900, 300, 10)
+    Dd, Y = dev_matrix(D, "bf16"), _dev_Y(ys)
+    L = oracle.spectral_norm_sq(Dbf)
+    X, infos = B.solve(Dd, Y, ratios, step_L=L, gap_tol=1e-6, max_iter=20000)
+    Xa, ia = B.solve(Dd, Y, ratios, step_L=L, gap_tol=1e-6, max_iter=20000, batch_slots=300)
+    assert np.array_equal(X.cpu().numpy(), Xa.cpu().numpy())
+    assert [i["iters"] for i in infos] == [i["iters"] for i in ia]
+    X = X.cpu().numpy().astype(np.float64)
+    for j in (0, 150, 299):
+        y = ys[j]
+        assert infos[j]["status"] == 0 and infos[j]["gap"] <= 1e-6 * float(y @ y)
+        star = oracle.solve_lasso(Dbf, y, lam=infos[j]["lambda_"], rule="fista", test="none",
+                                  L=L, max_iter=200000, gap_tol=1e-13)
+        p = oracle.primal_objective(Dbf, y, X[:, j], infos[j]["lambda_"], float(np.abs(X[:, j]).sum()))
+        assert p - star.primal <= infos[j]["gap"] + 1e-9
