@@ -70,6 +70,28 @@ def run_steps(binding, Dd, ys, steps, test, L, lat=None, step="constant", iters=
     return n
 
 
+def columns_of(ys):
+    """Each signal repeated once per lambda ratio: the N x 5 column-major right-hand sides of
+    one step's lasso_solve call (built before any timed region, resident in HBM)."""
+    return [y.reshape(-1, 1).repeat(1, len(RATIOS)).T.contiguous().T for y in ys]
+
+
+def run_steps_concurrent(binding, Dd, Ys, steps, test, L):
+    """One step = one signal at the five lambda ratios through one lasso_solve call: the five
+    independent single-signal solves run concurrently on the library's solve lanes."""
+    import torch
+    n = 0
+    for s in range(steps):
+        _, infos = binding.solve(Dd, Ys[s % len(Ys)], RATIOS, rule="fista", test=test,
+                                 step_L=L, gap_tol=GAP_TOL, max_iter=20000)
+        bad = [i for i in infos if i["status"] != 0]
+        if bad:
+            raise RuntimeError(f"solve did not converge: {bad[0]}")
+        n += len(infos)
+    torch.cuda.synchronize()
+    return n
+
+
 def batched_setup(binding, D):
     import torch
     Dbf = datagen.to_storage(D, "bf16")
@@ -941,25 +963,38 @@ def main():
         print(json.dumps({"leg": "instrumented",
                           "roofline": single_roofline(binding, Dd, ys, L)}), flush=True)
         return
+    Ys = columns_of(ys)
+    run_steps_concurrent(binding, Dd, Ys, args.warmup, "dst3", L)
     run_steps(binding, Dd, ys, args.warmup, "dst3", L)
     if legs == {"screened"}:
-        run_steps(binding, Dd, ys, args.steps, "dst3", L)
+        run_steps_concurrent(binding, Dd, Ys, args.steps, "dst3", L)
         return
-    # ---- timed region: screened solves ----
-    lat = []
+    # ---- timed region: screened solves, the five solves of a step concurrently ----
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n = run_steps(binding, Dd, ys, args.steps, "dst3", L, lat)
+    n = run_steps_concurrent(binding, Dd, Ys, args.steps, "dst3", L)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = n / dt
 
-    # ---- plain (unscreened) solves on the same inputs ----
+    # ---- plain (unscreened) solves on the same inputs, measured the same way ----
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n_plain = run_steps(binding, Dd, ys, args.steps, "none", L)
+    n_plain = run_steps_concurrent(binding, Dd, Ys, args.steps, "none", L)
     torch.cuda.synchronize()
     plain = n_plain / (time.perf_counter() - t1)
+
+    # ---- one solve at a time: per-solve latency, and the sequential rates ----
+    lat = []
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n_seq = run_steps(binding, Dd, ys, args.steps, "dst3", L, lat)
+    torch.cuda.synchronize()
+    seq = n_seq / (time.perf_counter() - t2)
+    t3 = time.perf_counter()
+    n_seq_plain = run_steps(binding, Dd, ys, args.steps, "none", L)
+    torch.cuda.synchronize()
+    seq_plain = n_seq_plain / (time.perf_counter() - t3)
 
     # ---- instrumented pass: kernel execution spans of every correlation launch ----
     roof = single_roofline(binding, Dd, ys, L)
@@ -980,9 +1015,13 @@ def main():
         "config": {"workload": "lasso_fista_dst3_gaussian_2000x10000_f32",
                    "N": N, "K": K, "lambda_ratios": list(RATIOS), "gap_tol": GAP_TOL,
                    "signals_per_step": 1, "solves_per_step": len(RATIOS),
+                   "solves_in_flight": "the 5 of a step (lasso_solve, 5 columns)",
                    "snr_db": 20, "active_fraction": 0.02},
         "plain_solves_per_s": round(plain, 3),
         "screened_over_plain": round(value / plain, 4),
+        "sequential": {"solves_per_s": round(seq, 3), "plain_solves_per_s": round(seq_plain, 3),
+                       "screened_over_plain": round(seq / seq_plain, 4),
+                       "note": "the same solves one at a time (latency is measured here)"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
         "roofline": roof,
@@ -1010,19 +1049,19 @@ def main():
         it_c = []
         run_steps(binding, Dd, ys, 1, "dst3", L, iters=it_c)
         bt["constant_step_mean_iters"] = round(float(np.mean(it_c)), 1)
-        bt["over_constant_step"] = round(bt["screened_solves_per_s"] / value, 3)
+        bt["over_constant_step"] = round(bt["screened_solves_per_s"] / seq, 3)
         out["backtracking"] = bt
     if "dome" in legs:
         dm = dome_leg(binding, Dd, ys, args.steps, L)
-        dm["over_dst3"] = round(dm["solves_per_s"] / value, 3)
+        dm["over_dst3"] = round(dm["solves_per_s"] / seq, 3)
         out["dome"] = dm
     if "cp" in legs:
         cp = cp_leg(binding, Dd, ys, args.steps, L)
-        cp["over_constant_step_fista"] = round(cp["screened_solves_per_s"] / value, 3)
+        cp["over_constant_step_fista"] = round(cp["screened_solves_per_s"] / seq, 3)
         out["cp"] = cp
     if "sparsa" in legs:
         sp = sparsa_leg(binding, Dd, ys, args.steps)
-        sp["over_constant_step_fista"] = round(sp["memory0_screened_solves_per_s"] / value, 3)
+        sp["over_constant_step_fista"] = round(sp["memory0_screened_solves_per_s"] / seq, 3)
         out["sparsa"] = sp
     if "large" in legs:
         out["roofline_large_dictionary"] = large_leg(binding)

@@ -178,7 +178,10 @@ typedef struct {
  *   column b of X (K x B, leading dim ldx >= K, device) and info[b] (host).
  *   lasso_solve requires problem->G == 0; glasso_solve requires problem->G > 0.
  *   B = 1 runs the single-signal streaming path (one GEMV per iteration); B > 1 with
- *   DS_BF16 storage runs the batched MFMA path; other B > 1 cases run B single solves.
+ *   DS_BF16 storage runs the batched MFMA path; other B > 1 cases run B single solves,
+ *   up to four at a time on streams of the library's own (each waits for the work queued
+ *   on `stream` before the call; each column's result equals its B = 1 solve bit for bit).
+ *   The call returns when every column is written.
  *   Returns DS_OK if every signal reached its tolerance (or ran max_iter when gap_tol = 0),
  *   DS_NOT_CONVERGED if some did not (see info[b].status), or an error code. */
 ds_status lasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,

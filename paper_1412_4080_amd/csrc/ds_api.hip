@@ -5,8 +5,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <memory>
+#include <string>
+#include <thread>
 
 #include "ds_engine.h"
 
@@ -253,17 +256,67 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   DeviceCtx& ctx = device_ctx(dev);
   std::lock_guard<std::mutex> g(ctx.mu);
   const size_t vsz = problem->dtype == DS_F64 ? 8 : 4;
-  ds_status worst = DS_OK;
-  for (int64_t b = 0; b < B; ++b) {
+  auto one = [&](int64_t b, hipStream_t st, Workspace& ws) {
     const char* yb = static_cast<const char*>(Y) + b * ldy * vsz;
     char* xb = static_cast<char*>(X) + b * ldx * vsz;
     std::memset(&info[b], 0, sizeof(ds_info));
     ds_params pb = *params;  // column b of the warm start, laid out as X
     if (pb.x0 != nullptr) pb.x0 = static_cast<const char*>(params->x0) + b * ldx * vsz;
-    e = solve_single(*problem, yb, lambdas[b], pb, xb, &info[b], s, ctx.ws, nullptr,
-                     screened != nullptr ? screened + b * problem->K : nullptr);
-    if (e < 0) return e;
-    if (e == DS_NOT_CONVERGED) worst = DS_NOT_CONVERGED;
+    return solve_single(*problem, yb, lambdas[b], pb, xb, &info[b], st, ws, nullptr,
+                        screened != nullptr ? screened + b * problem->K : nullptr);
+  };
+  const int nl = static_cast<int>(std::min<int64_t>(B, SOLVE_LANES));
+  if (nl == 1) return one(0, s, ctx.ws);
+  // B > 1: the signals are independent solves.  Each lane (its own stream and workspace, on
+  // a host thread of its own) takes the next waiting signal, smallest lambda first (those
+  // usually need the most iterations, so the long solves start early).  Each solve is the
+  // single-signal solve unchanged, so the results do not depend on the lanes.
+  std::vector<int64_t> order(B);
+  for (int64_t b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t c) { return lambdas[a] < lambdas[c]; });
+  std::atomic<int64_t> next{0};
+  hipEvent_t ready;
+  DS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  DS_HIP(hipEventRecord(ready, s));  // inputs written on the caller's stream
+  for (int k = 0; k < nl; ++k) {
+    SolveLane& ln = ctx.lanes[k];
+    ln.ws.device = dev;
+    if (ln.stream == nullptr) DS_HIP(hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking));
+    DS_HIP(hipStreamWaitEvent(ln.stream, ready, 0));
+  }
+  std::vector<ds_status> st(nl, DS_OK);
+  std::vector<std::string> msg(nl);
+  std::vector<std::thread> th;
+  for (int k = 0; k < nl; ++k) {
+    th.emplace_back([&, k] {
+      if (hipSetDevice(dev) != hipSuccess) {
+        st[k] = DS_EDEVICE;
+        msg[k] = "hipSetDevice failed in a solve lane";
+        return;
+      }
+      SolveLane& ln = ctx.lanes[k];
+      for (int64_t q = next++; q < B; q = next++) {
+        const ds_status r = one(order[q], ln.stream, ln.ws);
+        if (r < 0) {
+          st[k] = r;
+          msg[k] = ds_last_error();
+          next = B;  // the other lanes start no further signal
+          return;
+        }
+        if (r == DS_NOT_CONVERGED) st[k] = DS_NOT_CONVERGED;
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  (void)hipEventDestroy(ready);
+  ds_status worst = DS_OK;
+  for (int k = 0; k < nl; ++k) {
+    if (st[k] < 0) {
+      set_error("%s", msg[k].c_str());
+      return st[k];
+    }
+    if (st[k] == DS_NOT_CONVERGED) worst = DS_NOT_CONVERGED;
   }
   return worst;
 }

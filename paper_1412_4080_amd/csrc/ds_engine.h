@@ -64,10 +64,19 @@ struct Workspace {
   void release();  // frees everything (temporary workspaces; cached ones live until exit)
 };
 
+// A stream and workspace that run independent single-signal solves concurrently with the
+// other lanes of the device (the B > 1 single-signal path).
+struct SolveLane {
+  hipStream_t stream = nullptr;
+  Workspace ws;
+};
+constexpr int SOLVE_LANES = 4;  // one per hardware queue a process gets by default
+
 // Per-device cache of workspaces (one in use at a time per lock holder).
 struct DeviceCtx {
   std::mutex mu;
   Workspace ws;
+  SolveLane lanes[SOLVE_LANES];
 };
 DeviceCtx& device_ctx(int device);
 

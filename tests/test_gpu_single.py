@@ -391,6 +391,54 @@ def test_batched_call_matches_single(B):
         assert infos[j]["iters"] == i1["iters"]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_concurrent_columns_match_single_solves(B, dtype):
+    """lasso_solve with more columns than solve lanes (9 signals, lambdas out of order, one
+    the low ones capped by max_iter): every column, its info and its screened mask equal the
+    column's own single-signal solve bit for bit, DS_NOT_CONVERGED included."""
+    import torch
+    D, _ = _lasso_case(400, 2000, 23)
+    Ys = np.stack([datagen.lasso_signal(D, j)[0] for j in range(9)], axis=1)
+    Di = datagen.to_storage(D, dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    Dd = dev_matrix(D, dtype)
+    Yd = torch.from_numpy(np.ascontiguousarray(datagen.to_storage(Ys, dtype).T)).to(
+        device="cuda", dtype=tdt).T
+    L = oracle.spectral_norm_sq(Di)
+    ratios = [0.7, 0.2, 0.9, 0.4, 0.1, 0.6, 0.3, 0.8, 0.5]
+    X, infos, mask = B.solve(Dd, Yd, ratios, step_L=L, gap_tol=1e-8, max_iter=150,
+                             screened=True)
+    assert any(i["status"] != 0 for i in infos)     # the lowest ratios stop at max_iter
+    for j, r in enumerate(ratios):
+        x1, i1, s1, _ = B.solve_one(Dd, Yd[:, j].contiguous(), r, step_L=L, gap_tol=1e-8,
+                                    max_iter=150, trace=False)
+        assert np.array_equal(X[:, j].cpu().numpy(), x1.cpu().numpy()), j
+        assert np.array_equal(mask[:, j].cpu().numpy(), s1.cpu().numpy()), j
+        assert infos[j]["iters"] == i1["iters"] and infos[j]["status"] == i1["status"]
+        assert infos[j]["gap"] == i1["gap"]
+
+
+def test_concurrent_group_columns_match_single_solves(B):
+    """glasso_solve over 6 signals (groups of 10) runs the columns concurrently: each column
+    equals its own single-signal Group-Lasso solve bit for bit."""
+    import torch
+    D = datagen.gaussian_dictionary(300, 1500, 29)
+    gp = datagen.contiguous_groups(1500, 10)
+    Ys = np.stack([datagen.group_signal(D, gp, j)[0] for j in range(6)], axis=1)
+    Dd = dev_matrix(D, "f32")
+    Yd = torch.from_numpy(np.ascontiguousarray(Ys.T.astype(np.float32))).cuda().T
+    L = oracle.spectral_norm_sq(datagen.to_storage(D, "f32"))
+    ratios = [0.5, 0.3, 0.8, 0.2, 0.6, 0.4]
+    X, infos = B.solve(Dd, Yd, ratios, group_ptr=gp, rule="ista", test="dst3", step_L=L,
+                       gap_tol=1e-6, max_iter=20000)
+    for j, r in enumerate(ratios):
+        x1, i1, _, _ = B.solve_one(Dd, Yd[:, j].contiguous(), r, group_ptr=gp, rule="ista",
+                                   test="dst3", step_L=L, gap_tol=1e-6, max_iter=20000,
+                                   trace=False)
+        assert np.array_equal(X[:, j].cpu().numpy(), x1.cpu().numpy()), j
+        assert infos[j]["iters"] == i1["iters"]
+
+
 @pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe"), ("fista", "dome")])
 def test_static_screening_parity(B, rule, test):
     """Static mode (the test once, with the first dual point): same iterates, gap and
