@@ -63,7 +63,7 @@ class Trace(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
-                ("max_queue", C.c_int32), ("reserved", C.c_int32)]
+                ("max_queue", C.c_int32), ("batch_slots", C.c_int32)]
 
 
 class LaunchStat(C.Structure):
@@ -373,8 +373,11 @@ def stats_launches(cap=1 << 20):
 class Server:
     """Continuous-batching request loop (ds_server_* / lasso_submit / lasso_poll)."""
 
-    def __init__(self, device=0, max_slots=64, hbm_budget_bytes=8 << 30, max_queue=4096):
-        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, max_queue, 0)
+    def __init__(self, device=0, max_slots=64, hbm_budget_bytes=8 << 30, max_queue=4096,
+                 batch_slots=0):
+        """batch_slots > 0: bfloat16 Lasso dictionaries get a batched engine with this many
+        resident signals, which runs the requests whose parameters it supports."""
+        cfg = ServerConfig(device, max_slots, hbm_budget_bytes, max_queue, batch_slots)
         h = C.c_void_p()
         _check(_lib.ds_server_create(C.byref(cfg), C.byref(h)), "ds_server_create")
         self._h = h

@@ -127,9 +127,12 @@ int launch_zgemm(int k, const BLayout& l, hipStream_t s, hipEvent_t e0, hipEvent
   return (l.Kp / (MT * z.ra * z.wa)) * (l.Bp / (MT * z.rb * z.wb)) * z.ra * z.rb;
 }
 
-// Per-device state of the batched engine: workspace, a private stream (graph capture
-// needs one that is not the legacy default stream), and the last instantiated graph.
-struct BatchCtx {
+}  // namespace
+
+// State of one batched engine: workspace, a private stream (graph capture needs one that is
+// not the legacy default stream), the last instantiated graph and the tuned block shapes.
+// Each device has one for direct calls; a server has one per batched dictionary.
+struct BatchEngine {
   std::mutex mu;
   Workspace ws;
   hipStream_t stream = nullptr;
@@ -140,18 +143,53 @@ struct BatchCtx {
   hipEvent_t tune0 = nullptr, tune1 = nullptr;  // timing events of the autotuner
   int last_shape = -1;                           // shape of the last solve (diagnostics)
   std::map<std::tuple<int, int, int>, int> tuned;  // (N, K, B) -> Z-GEMM block shape
-  int* host_ctr = nullptr;  // pinned: ndone
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evpool;
   size_t ev_used = 0;
 };
 
-BatchCtx& batch_ctx(int device) {
+BatchEngine* batch_engine_create(int device) {
+  auto* E = new BatchEngine;
+  E->ws.device = device;
+  return E;
+}
+
+void batch_engine_destroy(BatchEngine* E) {
+  if (E == nullptr) return;
+  if (E->ws.device >= 0) (void)hipSetDevice(E->ws.device);
+  if (E->stream != nullptr) (void)hipStreamSynchronize(E->stream);
+  if (E->exec != nullptr) (void)hipGraphExecDestroy(E->exec);
+  for (auto& p : E->evpool) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  if (E->tune0 != nullptr) (void)hipEventDestroy(E->tune0);
+  if (E->tune1 != nullptr) (void)hipEventDestroy(E->tune1);
+  if (E->ev != nullptr) (void)hipEventDestroy(E->ev);
+  if (E->stream != nullptr) (void)hipStreamDestroy(E->stream);
+  E->ws.release();
+  delete E;
+}
+
+void batch_engine_trim(BatchEngine* E) {
+  if (E == nullptr) return;
+  std::lock_guard<std::mutex> g(E->mu);
+  if (E->ws.device >= 0) (void)hipSetDevice(E->ws.device);
+  if (E->stream != nullptr) (void)hipStreamSynchronize(E->stream);
+  if (E->exec != nullptr) (void)hipGraphExecDestroy(E->exec);
+  E->exec = nullptr;
+  E->key_shape = -1;
+  E->ws.release();
+}
+
+namespace {
+
+BatchEngine& batch_ctx(int device) {
   static std::mutex mu;
-  static std::map<int, std::unique_ptr<BatchCtx>> ctx;
+  static std::map<int, std::unique_ptr<BatchEngine>> ctx;
   std::lock_guard<std::mutex> g(mu);
   auto& p = ctx[device];
   if (!p) {
-    p = std::make_unique<BatchCtx>();
+    p = std::make_unique<BatchEngine>();
     p->ws.device = device;
   }
   return *p;
@@ -162,7 +200,7 @@ BatchCtx& batch_ctx(int device) {
 // then a timing of every shape that fits: one warm-up and three launches each, on the
 // solve's first theta with every active tile of every signal in play, writing to scratch
 // outputs so that the solve's state is untouched.  Returns the shape index.
-int choose_shape(BatchCtx& C, const BLayout& l, char* base, const BArgs& a, hipStream_t s,
+int choose_shape(BatchEngine& C, const BLayout& l, char* base, const BArgs& a, hipStream_t s,
                  hipEvent_t e0, hipEvent_t e1) {
   if (const char* f = std::getenv("DS_BATCH_TILE")) {
     const int k = std::atoi(f);
@@ -267,20 +305,47 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
 
 }  // namespace
 
-ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
-                             const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
-                             ds_info* info, uint8_t* screened, hipStream_t stream) {
-  // resident slots: all signals up to MAX_SLOTS, or the caller's batch_slots; the rest wait
-  // and take the slots of finished signals (continuous batching)
-  const int64_t want = prm.batch_slots > 0 ? prm.batch_slots : std::min<int64_t>(B, MAX_SLOTS);
-  const int nslot = static_cast<int>(std::min<int64_t>(want, B));
-  if (P.N > (1 << 24) || P.K > (1 << 24) || nslot > 32768 || B > (int64_t(1) << 30)) {
-    set_error("batched path: N, K must be <= 2^24, batch_slots <= 32768 and B <= 2^30");
+size_t batched_workspace_bytes(int64_t N, int64_t K, int slots, int max_iter) {
+  return make_layout(static_cast<int>(N), static_cast<int>(K), slots, max_iter).total;
+}
+
+namespace {
+
+// The caller's record of a finished signal.
+ds_info info_of(const Inst& h, double L) {
+  ds_info r;
+  std::memset(&r, 0, sizeof r);
+  if (h.status < 0) {  // observation with NaN or Inf
+    r.status = DS_EINVAL;
+    return r;
+  }
+  r.iters = h.iter;
+  r.n_active = h.n_active;
+  r.nnz = h.nnz;
+  r.lambda = h.lam;
+  r.lambda_max = h.lam_max;
+  r.primal = h.primal;
+  r.dual = h.dual;
+  r.gap = h.gap;
+  r.radius = h.r_min;
+  r.mu = h.mu;
+  r.L = L;
+  r.radius_slack = h.r_slack + h.marg_slack;
+  r.status = (h.status == 1 || h.converged) ? DS_OK : DS_NOT_CONVERGED;
+  return r;
+}
+
+}  // namespace
+
+ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64_t ldy,
+                      int nslot, const ds_params& prm, float* X, int64_t ldx,
+                      uint8_t* screened, BatchFeed& feed, hipStream_t stream) {
+  if (P.N > (1 << 24) || P.K > (1 << 24) || nslot < 1 || nslot > 32768) {
+    set_error("batched path: N, K must be <= 2^24 and 1 <= batch_slots <= 32768");
     return DS_EINVAL;
   }
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
-  BatchCtx& C = batch_ctx(dev);
   std::lock_guard<std::mutex> guard(C.mu);
   const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), nslot, prm.max_iter);
   ds_status e = C.ws.reserve(l.total);
@@ -288,7 +353,6 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   if (C.stream == nullptr) {
     DS_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
     DS_HIP(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming));
-    DS_HIP(hipHostMalloc(reinterpret_cast<void**>(&C.host_ctr), 64, hipHostMallocDefault));
     DS_HIP(hipEventCreate(&C.tune0));
     DS_HIP(hipEventCreate(&C.tune1));
   }
@@ -310,20 +374,17 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   char* base = static_cast<char*>(C.ws.base);
   BArgs a = make_args(l, base, prm, L);
 
-  // signals in order of increasing penalty: neighbouring slots hold signals that finish
-  // together (whole tiles fall idle), and when signals wait for slots the slow ones (small
-  // lambda needs the most iterations) start first, which keeps the end of the run short;
-  // slot k starts with signal order[k], and finished slots take the next ones
-  std::vector<int> order(B);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return lambdas[i] < lambdas[j]; });
+  // The feed hands out signals (a column of Y and X, and a penalty) as slots free up;
+  // slot k holds column slot_sig[k], or -1 when idle.
   std::vector<int> slot_sig(l.Bp, -1);
   std::vector<double> lam_slot(l.Bp, 1.0);
-  int64_t next = 0;
-  for (int k = 0; k < nslot; ++k) {
-    slot_sig[k] = order[next];
-    lam_slot[k] = lambdas[order[next]];
-    ++next;
+  std::vector<int> cols(nslot);
+  std::vector<double> lams(nslot);
+  const int n0 = feed.pull(nslot, cols.data(), lams.data(), s);
+  if (n0 <= 0) return DS_OK;
+  for (int k = 0; k < n0; ++k) {
+    slot_sig[k] = cols[k];
+    lam_slot[k] = lams[k];
   }
   int* d_perm = reinterpret_cast<int*>(base + l.perm);
   double* d_lam = reinterpret_cast<double*>(base + l.lam);
@@ -360,21 +421,21 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   double* gn = reinterpret_cast<double*>(base + l.gn);
   float* Vn = reinterpret_cast<float*>(base + l.Vn);
   float* Yp = reinterpret_cast<float*>(base + l.Y);
-  // per-slot set-up of the first n entries of d_list: y, cleared x / u / masks, D^T y,
+  // per-slot set-up of the first n entries of d_list, of which the first nact hold signals
+  // (the rest are idle slots, which need no products): y, cleared x / u / masks, D^T y,
   // lambda_* and the centre, D^T n (DST3), margins and their tile minima
-  auto setup_slots = [&](int n) -> ds_status {
+  auto setup_slots = [&](int n, int nact) -> ds_status {
     hipLaunchKernelGGL(k_b_load_slots, dim3(std::max(1, (l.Kp + TB - 1) / TB), n), dim3(TB), 0, s, a,
-                       static_cast<const float*>(Y), ldy, static_cast<const int*>(d_perm),
-                       static_cast<const int*>(d_list), Yp);
-    // FP64 D^T v for the listed slots: 64-slot tiles for the whole batch, 16-slot tiles for
-    // a few refilled slots (the same sums either way)
+                       Y, ldy, static_cast<const int*>(d_perm), static_cast<const int*>(d_list), Yp);
+    // FP64 D^T v for the listed slots: 64-slot tiles for many, 16-slot tiles for a few
+    // refilled slots (the same sums either way)
     auto dtv = [&](const float* V, double* out) {
-      if (n > 16)
-        hipLaunchKernelGGL(k_b_dtv64<64>, dim3(l.Kp / 64, (n + 63) / 64), dim3(TB), 0, s, dcm, V,
-                           l.Np, l.Kp, out, static_cast<const int*>(d_list), n);
-      else
+      if (nact > 16)
+        hipLaunchKernelGGL(k_b_dtv64<64>, dim3(l.Kp / 64, (nact + 63) / 64), dim3(TB), 0, s, dcm, V,
+                           l.Np, l.Kp, out, static_cast<const int*>(d_list), nact);
+      else if (nact > 0)
         hipLaunchKernelGGL(k_b_dtv64<16>, dim3(l.Kp / 64, 1), dim3(TB), 0, s, dcm, V, l.Np, l.Kp,
-                           out, static_cast<const int*>(d_list), n);
+                           out, static_cast<const int*>(d_list), nact);
     };
     dtv(a.Y, z0);
     hipLaunchKernelGGL(k_b_inst_init, dim3(n), dim3(TB), 0, s, a, z0, d_lam,
@@ -389,7 +450,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     DS_HIP(hipGetLastError());
     return DS_OK;
   };
-  if ((e = setup_slots(l.Bp)) != DS_OK) return e;
+  if ((e = setup_slots(l.Bp, n0)) != DS_OK) return e;
   if (stat_on) DS_HIP(hipEventRecord(su1, s));
 
   // ---------------------------------------------------------------- iteration
@@ -475,15 +536,16 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   if (stat_on) C.ev_used = 0;
 
   // Runs of ITERS_PER_GRAPH iterations (graph replays, or direct launches when instrumented)
-  // until every signal has finished.  After each run the slots' states are read; finished
-  // slots report (counts, x scattered to the caller's X) and take the next waiting signals.
+  // while any slot holds a signal.  After each run the slots' states are read; finished
+  // signals report (counts, x scattered to column perm[k] of X, the feed's finish), and
+  // free slots take the signals the feed has waiting.
   std::vector<Inst> hs(l.Bp);
-  std::vector<Inst> result(B);
   std::vector<int> hflag(l.Bp);
   int* d_flag = reinterpret_cast<int*>(base + l.dflag);
-  std::vector<int> fin, refill;
+  std::vector<int> fin, refill, fcols;
+  std::vector<ds_info> finfo;
   double act = 0.0, sup = 0.0;  // work of the finished signals (statistics)
-  int64_t nactive = nslot;      // slots holding a signal
+  int nactive = n0;             // slots holding a signal
   int t = 0;
   while (nactive > 0) {
     if (stat_on) {
@@ -499,37 +561,44 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
     fin.clear();
     for (int k = 0; k < l.Bp; ++k)
       if (slot_sig[k] >= 0 && hflag[k] != 0) fin.push_back(k);
-    if (fin.empty()) continue;
-    // report the finished slots
-    DS_HIP(hipMemcpyAsync(d_list, fin.data(), fin.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    const int nf = static_cast<int>(fin.size());
-    hipLaunchKernelGGL(k_b_counts, dim3(nf), dim3(TB), 0, s, a, static_cast<const int*>(d_list));
-    hipLaunchKernelGGL(k_b_scatter, dim3((l.K + TB - 1) / TB, nf), dim3(TB), 0, s, a,
-                       static_cast<const int*>(d_perm), static_cast<float*>(X), ldx, screened,
-                       static_cast<const int*>(d_list));
-    DS_HIP(hipGetLastError());
-    DS_HIP(hipMemcpyAsync(hs.data(), a.inst, l.Bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
-    DS_HIP(hipStreamSynchronize(s));
-    refill.clear();
-    for (int k : fin) {
-      result[slot_sig[k]] = hs[k];
-      act += hs[k].act_sum;
-      sup += hs[k].sup_sum;
-      if (next < B) {
-        slot_sig[k] = order[next];
-        lam_slot[k] = lambdas[order[next]];
-        ++next;
-        refill.push_back(k);
-      } else {
+    if (!fin.empty()) {
+      DS_HIP(hipMemcpyAsync(d_list, fin.data(), fin.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      const int nf = static_cast<int>(fin.size());
+      hipLaunchKernelGGL(k_b_counts, dim3(nf), dim3(TB), 0, s, a, static_cast<const int*>(d_list));
+      hipLaunchKernelGGL(k_b_scatter, dim3((l.K + TB - 1) / TB, nf), dim3(TB), 0, s, a,
+                         static_cast<const int*>(d_perm), X, ldx, screened,
+                         static_cast<const int*>(d_list));
+      DS_HIP(hipGetLastError());
+      DS_HIP(hipMemcpyAsync(hs.data(), a.inst, l.Bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
+      DS_HIP(hipStreamSynchronize(s));
+      fcols.clear();
+      finfo.clear();
+      for (int k : fin) {
+        fcols.push_back(slot_sig[k]);
+        finfo.push_back(info_of(hs[k], L));
+        act += hs[k].act_sum;
+        sup += hs[k].sup_sum;
         slot_sig[k] = -1;
         --nactive;
       }
+      feed.finish(fcols.data(), finfo.data(), nf, s);
     }
-    if (!refill.empty()) {
+    const int room = nslot - nactive;
+    const int got = room > 0 ? feed.pull(room, cols.data(), lams.data(), s) : 0;
+    if (got > 0) {
+      refill.clear();
+      for (int k = 0, q = 0; k < nslot && q < got; ++k) {
+        if (slot_sig[k] >= 0) continue;
+        slot_sig[k] = cols[q];
+        lam_slot[k] = lams[q];
+        ++q;
+        refill.push_back(k);
+      }
+      nactive += got;
       DS_HIP(hipMemcpyAsync(d_perm, slot_sig.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
       DS_HIP(hipMemcpyAsync(d_lam, lam_slot.data(), l.Bp * sizeof(double), hipMemcpyHostToDevice, s));
       DS_HIP(hipMemcpyAsync(d_list, refill.data(), refill.size() * sizeof(int), hipMemcpyHostToDevice, s));
-      if ((e = setup_slots(static_cast<int>(refill.size()))) != DS_OK) return e;
+      if ((e = setup_slots(got, got)) != DS_OK) return e;
     }
   }
 
@@ -564,33 +633,52 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
   if (su0) (void)hipEventDestroy(su0);
   if (su1) (void)hipEventDestroy(su1);
 
-  ds_status worst = DS_OK;
-  bool bad = false;
-  for (int64_t b = 0; b < B; ++b) {
-    const Inst& h = result[b];
-    ds_info& r = info[b];
-    std::memset(&r, 0, sizeof r);
-    if (h.status < 0) {
-      bad = true;
-      r.status = DS_EINVAL;
-      continue;
-    }
-    r.iters = h.iter;
-    r.n_active = h.n_active;
-    r.nnz = h.nnz;
-    r.lambda = h.lam;
-    r.lambda_max = h.lam_max;
-    r.primal = h.primal;
-    r.dual = h.dual;
-    r.gap = h.gap;
-    r.radius = h.r_min;
-    r.mu = h.mu;
-    r.L = L;
-    r.radius_slack = h.r_slack + h.marg_slack;
-    const bool ok = h.status == 1 || h.converged;
-    r.status = ok ? DS_OK : DS_NOT_CONVERGED;
-    if (!ok) worst = DS_NOT_CONVERGED;
+  return DS_OK;
+}
+
+ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
+                             const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
+                             ds_info* info, uint8_t* screened, hipStream_t stream) {
+  // resident slots: all signals up to MAX_SLOTS, or the caller's batch_slots; the rest wait
+  // and take the slots of finished signals (continuous batching)
+  const int64_t want = prm.batch_slots > 0 ? prm.batch_slots : std::min<int64_t>(B, MAX_SLOTS);
+  const int64_t nslot = std::min<int64_t>(want, B);
+  if (nslot > 32768 || B > (int64_t(1) << 30)) {
+    set_error("batched path: batch_slots must be <= 32768 and B <= 2^30");
+    return DS_EINVAL;
   }
+  // signals in order of increasing penalty: neighbouring slots hold signals that finish
+  // together (whole tiles fall idle), and when signals wait for slots the slow ones (small
+  // lambda needs the most iterations) start first, which keeps the end of the run short
+  std::vector<int> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return lambdas[i] < lambdas[j]; });
+  for (int64_t b = 0; b < B; ++b) std::memset(&info[b], 0, sizeof(ds_info));
+  int64_t next = 0;
+  bool bad = false;
+  ds_status worst = DS_OK;
+  BatchFeed feed;
+  feed.pull = [&](int room, int* cols, double* lams, hipStream_t) {
+    int n = 0;
+    for (; n < room && next < B; ++n, ++next) {
+      cols[n] = order[next];
+      lams[n] = lambdas[order[next]];
+    }
+    return n;
+  };
+  feed.finish = [&](const int* cols, const ds_info* inf, int n, hipStream_t) {
+    for (int j = 0; j < n; ++j) {
+      info[cols[j]] = inf[j];
+      if (inf[j].status == DS_EINVAL) bad = true;
+      if (inf[j].status == DS_NOT_CONVERGED) worst = DS_NOT_CONVERGED;
+    }
+  };
+  int dev = 0;
+  DS_HIP(hipGetDevice(&dev));
+  const ds_status e = run_batched(batch_ctx(dev), P, static_cast<const float*>(Y), ldy,
+                                  static_cast<int>(nslot), prm, static_cast<float*>(X), ldx,
+                                  screened, feed, stream);
+  if (e < 0) return e;
   if (bad) {
     set_error("observation contains NaN or Inf");
     return DS_EINVAL;
@@ -603,7 +691,7 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
 extern "C" int ds_batch_shape(int* atoms, int* signals) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
-  ds::BatchCtx& C = ds::batch_ctx(dev);
+  ds::BatchEngine& C = ds::batch_ctx(dev);
   std::lock_guard<std::mutex> g(C.mu);
   const int k = C.last_shape;
   if (k >= 0) {

@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -96,6 +97,30 @@ ds_status spectral_norm_impl(const ds_problem& P, int iters, double* L, hipStrea
 ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int64_t ldy,
                              const double* lambdas, const ds_params& prm, void* X, int64_t ldx,
                              ds_info* info, uint8_t* screened, hipStream_t stream);
+
+// The batched engine's source and sink of signals.  Between graph replays the engine asks
+// pull for up to `room` new signals (fills the Y / X column and the penalty of each, returns
+// how many; 0 when none is waiting; a copy into Y enqueued on the engine's stream `s` is
+// ordered before the signals' set-up) and hands finished ones to finish (their X columns
+// and masks are written and `s` is synchronized).  A run ends when no slot holds a signal
+// after a pull.
+struct BatchFeed {
+  std::function<int(int room, int* cols, double* lams, hipStream_t s)> pull;
+  std::function<void(const int* cols, const ds_info* infos, int n, hipStream_t s)> finish;
+};
+struct BatchEngine;  // workspace, stream, graph and tuned shapes of one engine
+BatchEngine* batch_engine_create(int device);
+void batch_engine_destroy(BatchEngine* engine);
+// Runs the signals the feed supplies with `nslot` resident slots on the bfloat16 dictionary
+// P (Lasso; ISTA or FISTA with a constant step; SAFE, DST3 or no test).  Y: N x columns FP32
+// (leading dimension ldy), X: K x columns FP32 (ldx), screened: K x columns or NULL.
+ds_status run_batched(BatchEngine& engine, const ds_problem& P, const float* Y, int64_t ldy,
+                      int nslot, const ds_params& prm, float* X, int64_t ldx,
+                      uint8_t* screened, BatchFeed& feed, hipStream_t stream);
+// Device bytes of a batched engine's workspace for this shape.
+size_t batched_workspace_bytes(int64_t N, int64_t K, int slots, int max_iter);
+// Gives an idle engine's device memory back (workspace and graph; tuned shapes are kept).
+void batch_engine_trim(BatchEngine* engine);
 
 size_t dtype_size(ds_dtype t);
 

@@ -7,6 +7,10 @@
 // y and x; a worker takes the oldest queued request whose device footprint fits the part
 // of the HBM budget not held by the other workers, so requests are admitted as slots and
 // memory free up, and the resident requests' kernels run concurrently on the device.
+// With batch_slots > 0 each bfloat16 Lasso dictionary also has a batched engine run by a
+// thread of its own: its requests wait in the dictionary's queue, join the engine's
+// resident signals whenever a slot is free at a graph-replay boundary (the ones with the
+// parameters of the running batch), and leave when they finish.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -71,6 +76,7 @@ enum ReqState { QUEUED, RUNNING, DONE };
 struct Request {
   uint64_t id;
   int dict;
+  bool batched = false;  // routed to the dictionary's batched engine
   std::vector<char> y, x, x0;  // x0: the warm start when one was given (else empty)
   double lam;
   ds_params prm;
@@ -92,8 +98,44 @@ struct Worker {
   size_t held = 0;  // device bytes charged to the budget for this worker
 };
 
+// The batched engine of one bfloat16 Lasso dictionary and its requests.
+struct BatchLane {
+  int dict = -1;
+  std::thread th;
+  BatchEngine* eng = nullptr;
+  std::deque<uint64_t> queue;  // requests waiting for this engine
+  float* Ys = nullptr;         // staging: column c of Y (leading dimension ldy) and of X (K)
+  float* Xs = nullptr;
+  int64_t ldy = 0;
+  size_t held = 0;             // device bytes charged to the budget for this engine
+  bool waiting = false;        // needs memory that others hold
+};
+
 size_t vec_size(ds_dtype t) { return t == DS_F64 ? 8 : 4; }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Requests the batched engine can run (the parameters lasso_solve's batched path takes).
+bool batch_eligible(const ds_params& p) {
+  return (p.rule == DS_ISTA || p.rule == DS_FISTA) && p.step_rule == DS_STEP_CONSTANT &&
+         (p.test == DS_TEST_NONE || p.test == DS_TEST_SAFE || p.test == DS_TEST_DST3) &&
+         p.x0 == nullptr && p.obj_tol == 0.0;
+}
+
+// Requests share a batched run when the engine's parameters agree.
+bool same_run(const ds_params& a, const ds_params& b) {
+  return a.rule == b.rule && a.test == b.test && a.screening == b.screening &&
+         a.lambda_mode == b.lambda_mode && a.gap_tol == b.gap_tol && a.max_iter == b.max_iter &&
+         a.step_L == b.step_L;
+}
+
+// Device bytes a batched engine holds: its workspace (with the 25% headroom of
+// Workspace::reserve) and the staging columns.
+size_t lane_need(int64_t N, int64_t K, int slots, int max_iter) {
+  const size_t ws = batched_workspace_bytes(N, K, slots, max_iter);
+  const int64_t ldy = (N + 3) / 4 * 4;
+  return ws + ws / 4 + align256(static_cast<size_t>(ldy) * slots * 4) +
+         align256(static_cast<size_t>(K) * slots * 4);
+}
 
 // Device bytes a worker holds to run request r: the solver workspace (reserved with the
 // 25% headroom Workspace::reserve adds) plus y, x and the warm start.
@@ -123,10 +165,26 @@ struct Server {
   // side only: no device fault is involved.
   uint64_t fail_request = 0;
   std::vector<std::unique_ptr<Worker>> workers;
+  std::map<int, std::unique_ptr<BatchLane>> lanes;  // by dictionary id
+  int lanes_waiting = 0;         // batched engines waiting for memory
   hipStream_t admin = nullptr;  // registration work
 
   void worker_loop(Worker* w);
   void run(Worker* w, Request* r, const Dict& d);
+  void lane_loop(BatchLane* b);
+  void run_lane(BatchLane* b, const Dict& d, const ds_params& key);
+  void release_lane(BatchLane* b, std::unique_lock<std::mutex>& lk);
+  size_t pending() const {
+    size_t n = queue.size();
+    for (const auto& kv : lanes) n += kv.second->queue.size();
+    return n;
+  }
+  void finish(Request* r, ds_status st, const std::string& err) {  // with mu held
+    r->status = st;
+    r->error = err;
+    r->t_end = Clock::now();
+    r->state = DONE;
+  }
 };
 
 void Server::run(Worker* w, Request* r, const Dict& d) {
@@ -205,9 +263,9 @@ void Server::worker_loop(Worker* w) {
         if (++r->skipped > SKIP_LIMIT) break;  // no overtaking a long-waiting request
       }
       if (pick != nullptr) break;
-      if (!queue.empty() && w->held > 0) {
-        // nothing queued fits next to what the workers hold: give this worker's memory
-        // back so that a waiting request can be admitted by whoever has room
+      if ((!queue.empty() || lanes_waiting > 0) && w->held > 0) {
+        // nothing queued fits next to what the workers hold (or a batched engine waits for
+        // memory): give this worker's memory back so that whoever has room can admit
         const size_t h = w->held;
         lk.unlock();
         (void)hipStreamSynchronize(w->stream);
@@ -238,6 +296,181 @@ void Server::worker_loop(Worker* w) {
   }
 }
 
+void Server::release_lane(BatchLane* b, std::unique_lock<std::mutex>& lk) {
+  const size_t h = b->held;
+  lk.unlock();
+  batch_engine_trim(b->eng);
+  if (b->Ys != nullptr) (void)hipFree(b->Ys);
+  if (b->Xs != nullptr) (void)hipFree(b->Xs);
+  b->Ys = b->Xs = nullptr;
+  lk.lock();
+  held -= h;
+  b->held = 0;
+  cv_work.notify_all();
+}
+
+void Server::lane_loop(BatchLane* b) {
+  (void)hipSetDevice(cfg.device);
+  std::unique_lock<std::mutex> lk(mu);
+  const Dict& d = *dicts.at(b->dict);
+  for (;;) {
+    if (stop) break;
+    if (b->queue.empty()) {
+      // idle: give the memory back when others wait for some
+      if (b->held > 0 && (!queue.empty() || lanes_waiting > 0)) {
+        release_lane(b, lk);
+        continue;
+      }
+      cv_work.wait(lk);
+      continue;
+    }
+    const ds_params key = reqs.at(b->queue.front())->prm;
+    const size_t need = lane_need(d.N, d.K, cfg.batch_slots, key.max_iter);
+    const size_t want = std::max(b->held, need);
+    if (held - b->held + want > cfg.hbm_budget_bytes) {
+      if (b->held > 0) {  // hold nothing while waiting
+        release_lane(b, lk);
+        continue;
+      }
+      if (!b->waiting) {
+        b->waiting = true;
+        ++lanes_waiting;
+        cv_work.notify_all();
+      }
+      cv_work.wait(lk);
+      continue;
+    }
+    if (b->waiting) {
+      b->waiting = false;
+      --lanes_waiting;
+    }
+    held += want - b->held;
+    b->held = want;
+    lk.unlock();
+    run_lane(b, d, key);
+    lk.lock();
+    cv_work.notify_all();
+  }
+  if (b->waiting) {
+    b->waiting = false;
+    --lanes_waiting;
+  }
+}
+
+// One run of the batched engine: requests with the parameters `key` join while slots are
+// free, until none holds a signal.
+void Server::run_lane(BatchLane* b, const Dict& d, const ds_params& key) {
+  const int slots = cfg.batch_slots;
+  const int64_t ldy = (d.N + 3) / 4 * 4;  // 16-byte columns
+  std::vector<Request*> in_col(slots, nullptr);
+  std::vector<int> free_cols;
+  for (int c = slots - 1; c >= 0; --c) free_cols.push_back(c);
+  auto fail_waiting = [&](ds_status st) {  // the requests of this run still queued
+    const std::string err = ds_last_error();
+    std::lock_guard<std::mutex> g(mu);
+    for (auto it = b->queue.begin(); it != b->queue.end();) {
+      Request* r = reqs.at(*it).get();
+      if (!same_run(r->prm, key)) {
+        ++it;
+        continue;
+      }
+      it = b->queue.erase(it);
+      r->t_start = Clock::now();
+      finish(r, st, err);
+    }
+    cv_work.notify_all();
+  };
+  if (b->eng == nullptr) b->eng = batch_engine_create(cfg.device);
+  if (b->Ys == nullptr) {
+    if (hipMalloc(reinterpret_cast<void**>(&b->Ys), static_cast<size_t>(ldy) * slots * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b->Xs), static_cast<size_t>(d.K) * slots * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      if (b->Ys != nullptr) (void)hipFree(b->Ys);
+      b->Ys = nullptr;
+      b->Xs = nullptr;
+      set_error("hipMalloc of the batched staging columns failed");
+      return fail_waiting(DS_ENOMEM);
+    }
+    b->ldy = ldy;
+  }
+  ds_params prm = key;
+  if (!(prm.step_L > 0.0)) prm.step_L = d.L;
+  const size_t vsz = 4;  // FP32 observations and solutions
+  BatchFeed feed;
+  feed.pull = [&](int room, int* cols, double* lams, hipStream_t s) -> int {
+    std::vector<Request*> got;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      if (stop) return 0;
+      for (auto it = b->queue.begin();
+           it != b->queue.end() && static_cast<int>(got.size()) < room &&
+           got.size() < free_cols.size();) {
+        Request* r = reqs.at(*it).get();
+        if (!same_run(r->prm, key)) {
+          ++it;
+          continue;
+        }
+        it = b->queue.erase(it);
+        r->state = RUNNING;
+        r->t_start = Clock::now();
+        got.push_back(r);
+      }
+    }
+    int n = 0;
+    for (Request* r : got) {
+      const int c = free_cols.back();
+      free_cols.pop_back();
+      in_col[c] = r;
+      // the request (and its host copy of y) lives until it is polled, after DONE
+      (void)hipMemcpyAsync(b->Ys + static_cast<int64_t>(c) * ldy, r->y.data(), d.N * vsz,
+                           hipMemcpyHostToDevice, s);
+      cols[n] = c;
+      lams[n] = r->lam;
+      ++n;
+    }
+    return n;
+  };
+  feed.finish = [&](const int* cols, const ds_info* infos, int n, hipStream_t s) {
+    bool copied = true;
+    for (int j = 0; j < n; ++j) {
+      Request* r = in_col[cols[j]];
+      r->x.resize(d.K * vsz);
+      if (hipMemcpyAsync(r->x.data(), b->Xs + static_cast<int64_t>(cols[j]) * d.K, d.K * vsz,
+                         hipMemcpyDeviceToHost, s) != hipSuccess)
+        copied = false;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) copied = false;
+    std::lock_guard<std::mutex> g(mu);
+    for (int j = 0; j < n; ++j) {
+      Request* r = in_col[cols[j]];
+      in_col[cols[j]] = nullptr;
+      free_cols.push_back(cols[j]);
+      r->info = infos[j];
+      if (!copied) {
+        finish(r, DS_EDEVICE, "download of x failed");
+      } else if (infos[j].status == DS_EINVAL) {
+        finish(r, DS_EINVAL, "observation contains NaN or Inf");
+      } else if (r->id == fail_request) {
+        finish(r, DS_EDEVICE,
+               "the slot of request " + std::to_string(r->id) + " was marked failed (DS_SERVE_FAIL_REQUEST)");
+      } else {
+        finish(r, static_cast<ds_status>(infos[j].status), std::string());
+      }
+    }
+    cv_work.notify_all();
+  };
+  const ds_problem P = d.view();
+  const ds_status e = run_batched(*b->eng, P, b->Ys, ldy, slots, prm, b->Xs, d.K, nullptr, feed,
+                                  nullptr);
+  if (e < 0) {  // the signals in the engine fail with the run
+    const std::string err = ds_last_error();
+    std::lock_guard<std::mutex> g(mu);
+    for (Request* r : in_col)
+      if (r != nullptr) finish(r, e, err);
+    cv_work.notify_all();
+  }
+}
+
 namespace {
 
 Server* as_server(void* s) { return static_cast<Server*>(s); }
@@ -263,11 +496,15 @@ ds_status submit_impl(void* server, int32_t dict_id, const void* y_host, double 
   }
   const Dict& d = *it->second;
   if ((e = validate_test_for(params, d.G > 0)) != DS_OK) return e;
-  if (static_cast<int64_t>(S->queue.size()) >= S->cfg.max_queue) {
+  if (static_cast<int64_t>(S->pending()) >= S->cfg.max_queue) {
     set_error("request queue full (%d waiting)", S->cfg.max_queue);
     return DS_EBUSY;
   }
-  const size_t need = request_need(d, *params);
+  auto lane = S->lanes.find(dict_id);
+  const bool batched = lane != S->lanes.end() && batch_eligible(*params) &&
+                       lane_need(d.N, d.K, S->cfg.batch_slots, params->max_iter) <=
+                           S->cfg.hbm_budget_bytes;
+  const size_t need = batched ? 0 : request_need(d, *params);
   if (need > S->cfg.hbm_budget_bytes) {
     set_error("request needs %zu device bytes, budget is %zu", need, S->cfg.hbm_budget_bytes);
     return DS_ENOMEM;
@@ -283,9 +520,13 @@ ds_status submit_impl(void* server, int32_t dict_id, const void* y_host, double 
   r->prm = *params;
   r->prm.x0 = nullptr;  // the copy above is uploaded by the worker
   r->need = need;
+  r->batched = batched;
   r->t_submit = Clock::now();
   *request_id = r->id;
-  S->queue.push_back(r->id);
+  if (batched)
+    lane->second->queue.push_back(r->id);
+  else
+    S->queue.push_back(r->id);
   S->reqs.emplace(r->id, std::move(r));
   // every worker looks: an idle worker that still holds memory must see a request that
   // does not fit next to it (and give the memory back), which a worker holding nothing
@@ -307,8 +548,9 @@ ds_status ds_server_create(const ds_server_config* config, void** server) {
     return DS_EINVAL;
   }
   if (config->max_slots < 1 || config->max_queue < 1 || config->hbm_budget_bytes == 0 ||
-      config->reserved != 0 || config->device < 0) {
-    set_error("bad server config (max_slots >= 1, max_queue >= 1, budget > 0, reserved = 0)");
+      config->batch_slots < 0 || config->batch_slots > 32768 || config->device < 0) {
+    set_error("bad server config (max_slots >= 1, max_queue >= 1, budget > 0, "
+              "0 <= batch_slots <= 32768)");
     return DS_EINVAL;
   }
   int ndev = 0;
@@ -418,9 +660,18 @@ ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype s
     (void)hipFree(d->D);
     return st;
   }
+  const bool lane = S->cfg.batch_slots > 0 && store == DS_BF16 && !group;
   std::lock_guard<std::mutex> g(S->mu);
   *dict_id = S->next_dict++;
   S->dicts.emplace(*dict_id, std::move(d));
+  if (lane) {
+    auto b = std::make_unique<BatchLane>();
+    b->dict = *dict_id;
+    BatchLane* bp = b.get();
+    Server* sp = S;
+    b->th = std::thread([sp, bp] { sp->lane_loop(bp); });
+    S->lanes.emplace(*dict_id, std::move(b));
+  }
   return DS_OK;
 }
 
@@ -478,7 +729,14 @@ ds_status ds_server_destroy(void* server) {
   S->cv_work.notify_all();
   for (auto& w : S->workers)
     if (w->th.joinable()) w->th.join();
+  for (auto& kv : S->lanes)
+    if (kv.second->th.joinable()) kv.second->th.join();
   (void)hipSetDevice(S->cfg.device);
+  for (auto& kv : S->lanes) {
+    batch_engine_destroy(kv.second->eng);
+    if (kv.second->Ys != nullptr) (void)hipFree(kv.second->Ys);
+    if (kv.second->Xs != nullptr) (void)hipFree(kv.second->Xs);
+  }
   for (auto& w : S->workers) {
     if (w->stream != nullptr) (void)hipStreamSynchronize(w->stream);
     w->ws.release();

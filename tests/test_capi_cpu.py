@@ -160,8 +160,8 @@ def test_invalid_lambda_and_groups_rejected(B):
 
 
 @pytest.mark.parametrize("field,value", [("max_slots", 0), ("max_queue", 0),
-                                         ("hbm_budget_bytes", 0), ("reserved", 1),
-                                         ("device", -1)])
+                                         ("hbm_budget_bytes", 0), ("batch_slots", -1),
+                                         ("batch_slots", 40000), ("device", -1)])
 def test_server_config_rejected(B, field, value):
     cfg = B.ServerConfig(0, 4, 1 << 30, 16, 0)
     setattr(cfg, field, value)
