@@ -145,6 +145,84 @@ def batched_stream_leg(binding, D, steps=2):
             "iterations": {"max": int(max(it)), "mean": round(float(np.mean(it)), 1)}}
 
 
+def served_batched_leg(binding, D, n_sat=1024, n_open=1500, warm=200, seed=datagen.ARRIVAL_SEED):
+    """Requests for the batched workload's dictionary (2000 x 10000, stored in bfloat16;
+    signals of its generator, lambda / lambda_* uniform in [0.1, 0.9], FISTA + DST3 to gap
+    1e-6) through the server: with a batched engine of 256 resident signals (requests join
+    it as slots free up) and with the eight single-signal workers alone.  Saturation (all
+    requests submitted at once), then Poisson arrivals at 0.5 x and 0.9 x the engine's
+    saturation rate: solves/s and p50/p99 latency (submit to result, server clock)."""
+    import torch
+    rng = np.random.default_rng(seed + 1)
+    ys = [datagen.to_storage(datagen.lasso_signal(D, j)[0], "f32").astype(np.float32)
+          for j in range(256)]
+    Dd = torch.from_numpy(np.ascontiguousarray(datagen.to_storage(D, "f32").T)).to(
+        device="cuda", dtype=torch.float32).T
+
+    def draw(n):
+        return [(int(rng.integers(len(ys))), float(rng.uniform(0.1, 0.9))) for _ in range(n)]
+
+    def run(S, did, reqs, gaps=None, skip=0):
+        pending, done = {}, []
+
+        def drain():
+            for rid in list(pending):
+                got = S.poll(rid, did)
+                if got is not None:
+                    if got[1]["status"] != 0:
+                        raise RuntimeError(f"served solve did not converge: {got[1]}")
+                    if pending[rid]:
+                        done.append(got[1])
+                    del pending[rid]
+        t_next = t_start = time.perf_counter()
+        for k, (j, r) in enumerate(reqs):
+            if gaps is not None:
+                t_next += gaps[k]
+                while time.perf_counter() < t_next:
+                    drain()
+            if k == skip:
+                t_start = time.perf_counter()
+            rid = S.submit(did, ys[j], r, test="dst3", gap_tol=GAP_TOL, max_iter=20000)
+            pending[rid] = k >= skip
+        while pending:
+            drain()
+            time.sleep(0.0002)
+        return done, time.perf_counter() - t_start
+
+    def summary(done, dt):
+        lat = np.array([i["queue_ms"] + i["run_ms"] for i in done])
+        return {"solves_per_s": round(len(done) / dt, 1), "requests": len(done),
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                               "p99": round(float(np.percentile(lat, 99)), 3)}}
+
+    out = {"workload": "serving_lasso_fista_dst3_gaussian_2000x10000_bf16",
+           "requests_saturation": n_sat}
+    sat_rate = None
+    for name, bslots in (("batched_engine", 256), ("workers_only", 0)):
+        S = binding.Server(max_slots=8, hbm_budget_bytes=24 << 30, max_queue=1 << 14,
+                           batch_slots=bslots)
+        did = S.add_dict(Dd, store="bf16")
+        torch.cuda.synchronize()
+        run(S, did, draw(64))                     # warm-up (autotuner, graph, workspaces)
+        done, dt = run(S, did, draw(n_sat))
+        leg = {"batch_slots": bslots, "worker_slots": 8, "saturation": summary(done, dt)}
+        if sat_rate is None:
+            sat_rate = len(done) / dt
+        opens = []
+        for frac in (0.5, 0.9):
+            reqs = draw(warm + n_open)
+            gaps = rng.exponential(1.0 / (frac * sat_rate), size=len(reqs))
+            done, dt = run(S, did, reqs, gaps, skip=warm)
+            opens.append(dict(offered_per_s=round(frac * sat_rate, 1), **summary(done, dt)))
+        leg["open_loop"] = opens
+        S.close()
+        out[name] = leg
+    out["saturation_engine_over_workers"] = round(
+        out["batched_engine"]["saturation"]["solves_per_s"] /
+        out["workers_only"]["saturation"]["solves_per_s"], 2)
+    return out
+
+
 def batched_roofline(binding, one):
     """One instrumented batched solve: matrix-core roofline of the Z = D^T Theta GEMM."""
     binding.stats_reset()
@@ -285,18 +363,21 @@ def serve_inputs(seed=datagen.DICT_SEED):
 
 
 def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96,
-               seed=datagen.ARRIVAL_SEED):
+               seed=datagen.ARRIVAL_SEED, batch_slots=0):
     """Closed-loop saturation, then open-loop Poisson arrivals at 0.5x and 0.9x of it; the
-    baseline is requests of the same mix solved one at a time without screening."""
+    baseline is requests of the same mix solved one at a time without screening.  With
+    batch_slots > 0 the two bfloat16 Lasso dictionaries of the mix run on batched engines
+    (the baseline is then not repeated)."""
     inputs = serve_inputs()
     rng = np.random.default_rng(seed)
 
-    def draw(n):
-        return [(int(rng.integers(len(inputs))), int(rng.integers(SERVE_POOL)),
-                 float(rng.uniform(0.1, 0.9))) for _ in range(n)]
+    def draw(n, g=rng):
+        return [(int(g.integers(len(inputs))), int(g.integers(SERVE_POOL)),
+                 float(g.uniform(0.1, 0.9))) for _ in range(n)]
 
-    def server(nslots):
-        S = binding.Server(max_slots=nslots, hbm_budget_bytes=24 << 30, max_queue=1 << 14)
+    def server(nslots, bslots=0):
+        S = binding.Server(max_slots=nslots, hbm_budget_bytes=24 << 30, max_queue=1 << 14,
+                           batch_slots=bslots)
         return S, [S.add_dict(Dt, group_ptr=gp, store=dt) for (Dt, gp, dt, _) in inputs]
 
     def drain(S, ids, pending, done):
@@ -334,7 +415,9 @@ def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96
                 "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                                "p99": round(float(np.percentile(lat, 99)), 3)}}
 
-    S, ids = server(slots)
+    S, ids = server(slots, batch_slots)
+    if batch_slots:
+        run(S, ids, draw(64, np.random.default_rng(seed + 7)))   # warm-up of the engines
     done, dt = run(S, ids, draw(n_closed))
     sat = len(done) / dt
     per_dict = []
@@ -351,6 +434,10 @@ def served_leg(binding, n_closed=320, n_open=1000, warm=100, slots=8, n_plain=96
         done, dt = run(S, ids, reqs, gaps, skip=warm)
         opens.append(dict(offered_per_s=round(frac * sat, 1), **summary(done, dt)))
     S.close()
+    if batch_slots:
+        return {"slots": slots, "batch_slots": batch_slots,
+                "saturation_solves_per_s": round(sat, 1), "open_loop": opens,
+                "per_dict_closed_loop": per_dict}
     # baseline: the plain (unscreened) single-signal path, one request at a time
     P, pids = server(1)
     pdone, pdt = [], 0.0
@@ -899,12 +986,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,seeds,small,groups,batched,served,paper_lasso,"
-                                      "paper_group,paper_illustration,large,backtracking,"
-                                      "sparsa,dome,cp",
+    ap.add_argument("--legs", default="single,seeds,small,groups,batched,served,served_batched,"
+                                      "paper_lasso,paper_group,paper_illustration,large,"
+                                      "backtracking,sparsa,dome,cp",
                     help="comma list of legs: single (headline), seeds (the headline per lambda "
                          "over 30 signals), small (100 x 500 FP64, microseconds per iteration), "
-                         "groups (groups of 10, ISTA + DGST3 / GSAFE), batched, served, "
+                         "groups (groups of 10, ISTA + DGST3 / GSAFE), batched, served (the eight-dictionary "
+                         "mix, workers only and with batched engines), served_batched (requests "
+                         "for the batched workload's bfloat16 dictionary: engine vs workers), "
                          "paper_lasso (the paper's Pnoise Lasso experiment: normalised flops "
                          "and times of 4 rules x 3 strategies over 30 runs), paper_group (its "
                          "Group-Lasso group-size experiment), paper_illustration (its "
@@ -1067,6 +1156,10 @@ def main():
         out["roofline_large_dictionary"] = large_leg(binding)
     if "served" in legs:
         out["served"] = served_leg(binding, slots=args.serve_slots)
+        out["served"]["batched_engine"] = served_leg(binding, slots=args.serve_slots,
+                                                     batch_slots=256)
+    if "served_batched" in legs:
+        out["served_bf16_one_dictionary"] = served_batched_leg(binding, D)
     if not args.no_cpu:
         import oracle
         L64 = oracle.spectral_norm_sq(D32)

@@ -123,6 +123,7 @@ SingleArgs<T, typename Types<T>::V, typename Types<T>::A> make_args(const ds_pro
   a.rule = rule;
   a.par = 0;
   a.grid_corr = static_cast<int32_t>(l.grid_corr);
+  a.nsg_prev = static_cast<int32_t>(l.nsg);
   a.gptr = P.G > 0 ? reinterpret_cast<const int64_t*>(base + l.off_gptr) : nullptr;
   a.w = P.G > 0 ? reinterpret_cast<const double*>(base + l.off_w) : nullptr;
   a.y = reinterpret_cast<const V*>(base + l.off_y);
@@ -325,8 +326,17 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   // ---- iterations ----
   constexpr int VR = VEC ? Store<T>::VEC : 1;
   const int nrt = static_cast<int>((P.N + WAVE * VR - 1) / (WAVE * VR));
-  const int grid_res = std::max(nrt, grid_for(static_cast<int64_t>(nrt) * l.nsg, 1, 2048));
-  const int grid_corr = static_cast<int>(l.grid_corr);
+  // The correlation grid covers the active list; the list never grows, so at each chunk
+  // boundary the host shrinks the grid to the list length it reads from the state.  Each
+  // residual pass reads the outputs of the correlation launch before it (its grid) and the
+  // Omega partials of the residual pass before it (the segment groups of that pass).
+  const int cbu = P.G > 0 ? CBG : CBL, sgu = P.G > 0 ? SGG : SGL;
+  auto nsg_of = [&](int g) { return (g + sgu - 1) / sgu; };
+  auto res_grid = [&](int g) {
+    return std::max(nrt, grid_for(static_cast<int64_t>(nrt) * nsg_of(g), 1, 2048));
+  };
+  int grid_corr = static_cast<int>(l.grid_corr);  // correlation launches of this chunk
+  int grid_res_read = grid_corr;                  // grid the last residual pass read
   if (nrt > MAXRT || l.grid_corr > MAXB || l.nsg > MAXITEM) {
     set_error("problem too large for one device solve (N <= %d, units <= %d)", MAXRT * WAVE,
               MAXB * (P.G > 0 ? CBG : CBL));
@@ -356,19 +366,24 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     ++ev_used;
     return p;
   };
-  auto launch_resid = [&](int par) {
+  // g: the grid of the correlation launch whose outputs the pass reads
+  auto launch_resid = [&](int par, int g) {
     a.par = par;
+    a.grid_corr = g;
+    a.nsg_prev = nsg_of(grid_res_read);
+    grid_res_read = g;
     if (P.G > 0)
-      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, true>), dim3(grid_res), dim3(BLK), 0, s, a);
+      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, true>), dim3(res_grid(g)), dim3(BLK), 0, s, a);
     else
-      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, false>), dim3(grid_res), dim3(BLK), 0, s, a);
+      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, false>), dim3(res_grid(g)), dim3(BLK), 0, s, a);
   };
-  auto launch_dcheck = [&](int par) {
+  auto launch_dcheck = [&](int par, int g) {
     a.par = par;
+    a.grid_corr = g;
     if (P.G > 0)
-      hipLaunchKernelGGL((k_dcheck<T, V, VEC, true>), dim3(grid_res), dim3(BLK), 0, s, a);
+      hipLaunchKernelGGL((k_dcheck<T, V, VEC, true>), dim3(res_grid(g)), dim3(BLK), 0, s, a);
     else
-      hipLaunchKernelGGL((k_dcheck<T, V, VEC, false>), dim3(grid_res), dim3(BLK), 0, s, a);
+      hipLaunchKernelGGL((k_dcheck<T, V, VEC, false>), dim3(res_grid(g)), dim3(BLK), 0, s, a);
   };
   auto launch_corr = [&](int par) {
     a.par = par;
@@ -391,7 +406,7 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
 
   // iteration t: corr(t) with parity t%2, then resid(t+1) (scalars of t, theta_{t+1});
   // resid(1) forms theta_1 = -y.
-  launch_resid(1);
+  launch_resid(1, grid_corr);  // a warm start seeds the segments of the full grid
   // Chunk sizes.  Iterations enqueued past the stop return at once but still cost a
   // launch each, and every chunk costs a host round trip.  A fixed iteration count is
   // enqueued whole (up to 64 at a time); a gap target takes the iterations the gap's
@@ -406,14 +421,15 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     for (int k = 0; k < nrun; ++k) {
       ++t;
       launch_corr(t % 2);
-      if (line_search) launch_dcheck(t % 2);
-      launch_resid((t + 1) % 2);
+      if (line_search) launch_dcheck(t % 2, grid_corr);
+      launch_resid((t + 1) % 2, grid_corr);
       last_par = (t + 1) % 2;
     }
     DS_HIP(hipGetLastError());
     DS_HIP(hipMemcpyAsync(hst, a.st + last_par, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     DS_HIP(hipStreamSynchronize(s));
     finished = hst->done != 0;
+    grid_corr = std::min(grid_corr, std::max(1, (hst->n_active + cbu - 1) / cbu));
     if (stat_on) {
       chunk = 1;
     } else if (prm.gap_tol <= 0.0 && prm.obj_tol <= 0.0) {

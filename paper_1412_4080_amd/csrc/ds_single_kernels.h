@@ -1049,7 +1049,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     p8[k] = a.bpd[b];
     if constexpr (RULE == RULE_SPARSA) p10[k] = a.bpe[b];
   }
-  const int kr = min(tid, nrt - 1), ko = min(tid, nsg - 1);
+  const int kr = min(tid, nrt - 1), ko = min(tid, a.nsg_prev - 1);
   const double q5 = rtp[2 * kr], q6 = rtp[2 * kr + 1], q7 = omp[ko], q9 = a.dtn[kr];
   double q10 = 0.0;  // Chambolle-Pock: ||D u - y||^2 of the row tile
   if constexpr (RULE == RULE_CP) q10 = a.rtr[(1 - a.par) * MAXRT + kr];
@@ -1068,7 +1068,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
   }
   v[5] += tid < nrt ? q5 : 0.0;
   v[6] += tid < nrt ? q6 : 0.0;
-  v[7] += tid < nsg ? q7 : 0.0;
+  v[7] += tid < a.nsg_prev ? q7 : 0.0;
   v[9] += tid < nrt ? q9 : 0.0;
   if constexpr (RULE == RULE_CP) v[NV - 1] += tid < nrt ? q10 : 0.0;
   // larger grids: the remaining partials, in the same order
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
     v[9] += a.dtn[k];
     if constexpr (RULE == RULE_CP) v[NV - 1] += a.rtr[(1 - a.par) * MAXRT + k];
   }
-  for (int k = BLK + tid; k < nsg; k += BLK) v[7] += omp[k];
+  for (int k = BLK + tid; k < a.nsg_prev; k += BLK) v[7] += omp[k];
   if (tid < NWORDS) reinterpret_cast<int32_t*>(&S)[tid] = sword;
   __syncthreads();
   if (S.done) {

@@ -76,7 +76,10 @@ struct SingleArgs {
   int32_t G;             // 0: Lasso; >0 groups
   int32_t test, rule;
   int32_t par;           // iteration parity (host-known): selects the state / partial buffers
-  int32_t grid_corr;     // blocks of the correlation kernel (= support segments)
+  int32_t grid_corr;     // blocks of the correlation launch whose outputs this kernel reads
+                         // (= its support segments); the host shrinks the correlation grid
+                         // between chunks as the active list shrinks
+  int32_t nsg_prev;      // residual pass: Omega partials the previous residual pass published
   const int64_t* gptr;   // device copy of group offsets (G+1), NULL for the Lasso
   const double* w;       // device group weights (G)
   const V* y;            // observation (16-byte aligned copy)
