@@ -178,7 +178,8 @@ typedef struct {
  *   column b of X (K x B, leading dim ldx >= K, device) and info[b] (host).
  *   lasso_solve requires problem->G == 0; glasso_solve requires problem->G > 0.
  *   B = 1 runs the single-signal streaming path (one GEMV per iteration); B > 1 with
- *   DS_BF16 storage runs the batched MFMA path; other B > 1 cases run B single solves,
+ *   DS_BF16 storage runs the batched MFMA path (Lasso and Group-Lasso); other B > 1 cases
+ *   run B single solves,
  *   up to four at a time on streams of the library's own (each waits for the work queued
  *   on `stream` before the call; each column's result equals its B = 1 solve bit for bit).
  *   The call returns when every column is written.
@@ -211,9 +212,10 @@ ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,
                        const ds_params* params, void* x, uint8_t* screened, ds_trace* trace,
                        int32_t trace_cap, ds_info* info, void* stream);
 
-/* lasso_solve with a diagnostic output: `screened` (DEVICE, K x B bytes, column b at
- * offset b * K, may be NULL) receives 1 for every atom of signal b's final screened set
- * and 0 otherwise.  For B > 1 with DS_BF16 storage (the batched MFMA path, Lasso only)
+/* lasso_solve (glasso_solve when problem->G > 0) with a diagnostic output: `screened`
+ * (DEVICE, K x B bytes, column b at offset b * K, may be NULL) receives 1 for every atom of
+ * signal b's final screened set (groups: every atom of a screened group) and 0 otherwise.
+ * For B > 1 with DS_BF16 storage (the batched MFMA path)
  * the correlations that drive the iteration are FP32-accumulated on the matrix cores;
  * the sphere radius carries their rounding bound (reported in info[b].radius_slack) and
  * the gap that ends each solve is recomputed in FP64 at that iteration's primal point.

@@ -209,8 +209,8 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
     lambda_relative); x0: optional warm start laid out as X (device, K x B column-major
     with X's leading dimension, or (K,)).  Returns (X, infos) with X K x B column-major (or
     (K,) for 1-D Y);
-    with screened=True (Lasso only) returns (X, infos, mask), mask a K x B uint8 device
-    tensor (1 = screened) from ds_solve_batch.
+    with screened=True returns (X, infos, mask), mask a K x B uint8 device tensor
+    (1 = screened) from ds_solve_batch.
     """
     torch = _torch()
     one = Y.dim() == 1
@@ -240,8 +240,6 @@ def solve(D, Y, lambdas, *, group_ptr=None, weights=None, rule="fista", test="ds
                       bb_memory, bb_sigma, cp_tau, cp_sigma, cp_gamma,
                       None if x0 is None else x0.data_ptr(), obj_tol, batch_slots)
     if screened:
-        if group_ptr is not None:
-            raise ValueError("screened masks of batched solves are for the Lasso")
         mask = torch.empty(B, K, dtype=torch.uint8, device=Y.device).T
         st = _lib.ds_solve_batch(C.byref(prob), C.c_void_p(Y2.data_ptr()), B, ldy, lam,
                                  C.byref(prm), C.c_void_p(X.data_ptr()), ldx, infos,

@@ -237,7 +237,7 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
-  if (B > 1 && problem->dtype == DS_BF16 && !group) {
+  if (B > 1 && problem->dtype == DS_BF16) {
     if (params->test == DS_TEST_DOME) {
       set_error("the Dome test is available on the single-signal path (B = 1 or FP32/FP64 D)");
       return DS_EINVAL;
@@ -337,7 +337,8 @@ ds_status lasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64
 ds_status ds_solve_batch(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,
                          const double* lambdas, const ds_params* params, void* X, int64_t ldx,
                          ds_info* info, uint8_t* screened, void* stream) {
-  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, screened, stream, false);
+  const bool group = problem != nullptr && problem->G > 0;
+  return solve_common(problem, Y, B, ldy, lambdas, params, X, ldx, info, screened, stream, group);
 }
 
 ds_status glasso_solve(const ds_problem* problem, const void* Y, int64_t B, int64_t ldy,

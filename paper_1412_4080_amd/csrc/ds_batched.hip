@@ -16,6 +16,7 @@
 #include <memory>
 #include <numeric>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "ds_batched_kernels.h"
@@ -33,16 +34,17 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 struct BLayout {
-  int N, K, B, Np, Kp, Bp, nrb;
+  int N, K, B, Np, Kp, Bp, nrb, G;
+  size_t gptr, agrp, gw, gspec, gfro, Vd;  // groups only (zero bytes for the Lasso)
   size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
       inst, ctr, vlist, perm, slist, dflag, lam, z0, gn, Vn, kclk, spans, tX, tU, tZ, tpz, tpom,
       tpact, tmask, total;
   int nspan;
 };
 
-BLayout make_layout(int N, int K, int B, int max_iter) {
+BLayout make_layout(int N, int K, int B, int max_iter, int G) {
   BLayout l{};
-  l.N = N; l.K = K; l.B = B;
+  l.N = N; l.K = K; l.B = B; l.G = G;
   l.Np = round_up(N, 64);
   l.Kp = round_up(K, KP_ALIGN);
   l.Bp = round_up(B, 64);
@@ -92,6 +94,13 @@ BLayout make_layout(int N, int K, int B, int max_iter) {
   l.tpom = take(nt * bp * 8);
   l.tpact = take(nt * bp * 4);
   l.tmask = take(nt * bp * 4);
+  const size_t ng = G > 0 ? static_cast<size_t>(G) : 0;
+  l.gptr = take(G > 0 ? (ng + 1) * 8 : 0);
+  l.agrp = take(G > 0 ? kp * 4 : 0);
+  l.gw = take(ng * 8);
+  l.gspec = take(ng * 8);
+  l.gfro = take(ng * 8);
+  l.Vd = take(G > 0 ? bp * np * 8 : 0);
   l.total = o;
   return l;
 }
@@ -300,13 +309,21 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
   a.ndone = reinterpret_cast<int*>(base + l.ctr);
   a.vcount = reinterpret_cast<int*>(base + l.ctr) + 1;
   a.vlist = reinterpret_cast<int*>(base + l.vlist);
+  a.G = l.G;
+  if (l.G > 0) {
+    a.gptr = reinterpret_cast<const int64_t*>(base + l.gptr);
+    a.agrp = reinterpret_cast<const int*>(base + l.agrp);
+    a.gw = reinterpret_cast<const double*>(base + l.gw);
+    a.gspec = reinterpret_cast<const double*>(base + l.gspec);
+    a.gfro = reinterpret_cast<const double*>(base + l.gfro);
+  }
   return a;
 }
 
 }  // namespace
 
-size_t batched_workspace_bytes(int64_t N, int64_t K, int slots, int max_iter) {
-  return make_layout(static_cast<int>(N), static_cast<int>(K), slots, max_iter).total;
+size_t batched_workspace_bytes(int64_t N, int64_t K, int slots, int max_iter, int64_t G) {
+  return make_layout(static_cast<int>(N), static_cast<int>(K), slots, max_iter, static_cast<int>(G)).total;
 }
 
 namespace {
@@ -347,7 +364,8 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> guard(C.mu);
-  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), nslot, prm.max_iter);
+  const BLayout l = make_layout(static_cast<int>(P.N), static_cast<int>(P.K), nslot, prm.max_iter,
+                                static_cast<int>(P.G));
   ds_status e = C.ws.reserve(l.total);
   if (e != DS_OK) return e;
   if (C.stream == nullptr) {
@@ -414,9 +432,35 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
                      static_cast<const uint16_t*>(P.D), P.ldd, l.N, l.K, l.Np, dcm);
   hipLaunchKernelGGL(k_b_norms, dim3(l.Kp / NWB), dim3(TB), 0, s, dcm, l.Np, l.Kp,
                      reinterpret_cast<double*>(base + l.nu));
-  hipLaunchKernelGGL(k_b_dict_scalars, dim3(1), dim3(TB), 0, s,
-                     reinterpret_cast<const double*>(base + l.nu), l.K,
-                     reinterpret_cast<double*>(base + l.dsc));
+  // groups: offsets, the group of each atom and the weights (default sqrt(|g|)) from the
+  // host, the group norms of the stored values on the device
+  std::vector<int64_t> h_gptr;
+  std::vector<int> h_agrp;
+  std::vector<double> h_gw;
+  if (l.G > 0) {
+    h_gptr.assign(P.group_ptr, P.group_ptr + l.G + 1);
+    h_agrp.assign(l.Kp, -1);
+    h_gw.resize(l.G);
+    int mmax = 1;
+    for (int g = 0; g < l.G; ++g) {
+      for (int64_t k = h_gptr[g]; k < h_gptr[g + 1]; ++k) h_agrp[k] = g;
+      mmax = std::max(mmax, static_cast<int>(h_gptr[g + 1] - h_gptr[g]));
+      h_gw[g] = P.w != nullptr ? P.w[g] : std::sqrt(static_cast<double>(h_gptr[g + 1] - h_gptr[g]));
+    }
+    DS_HIP(hipMemcpyAsync(base + l.gptr, h_gptr.data(), h_gptr.size() * 8, hipMemcpyHostToDevice, s));
+    DS_HIP(hipMemcpyAsync(base + l.agrp, h_agrp.data(), h_agrp.size() * 4, hipMemcpyHostToDevice, s));
+    DS_HIP(hipMemcpyAsync(base + l.gw, h_gw.data(), h_gw.size() * 8, hipMemcpyHostToDevice, s));
+    if ((e = group_norms_bf16(dcm, l.Np, l.N, l.G, reinterpret_cast<const int64_t*>(base + l.gptr),
+                              mmax, reinterpret_cast<double*>(base + l.gspec),
+                              reinterpret_cast<double*>(base + l.gfro), s)) != DS_OK)
+      return e;
+    hipLaunchKernelGGL(k_b_gdict_scalars, dim3(1), dim3(TB), 0, s, a,
+                       reinterpret_cast<double*>(base + l.dsc));
+  } else {
+    hipLaunchKernelGGL(k_b_dict_scalars, dim3(1), dim3(TB), 0, s,
+                       reinterpret_cast<const double*>(base + l.nu), l.K,
+                       reinterpret_cast<double*>(base + l.dsc));
+  }
   double* z0 = reinterpret_cast<double*>(base + l.z0);
   double* gn = reinterpret_cast<double*>(base + l.gn);
   float* Vn = reinterpret_cast<float*>(base + l.Vn);
@@ -429,22 +473,33 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
                        Y, ldy, static_cast<const int*>(d_perm), static_cast<const int*>(d_list), Yp);
     // FP64 D^T v for the listed slots: 64-slot tiles for many, 16-slot tiles for a few
     // refilled slots (the same sums either way)
-    auto dtv = [&](const float* V, double* out) {
+    auto dtv = [&](const auto* V, double* out) {
+      using VT = std::remove_const_t<std::remove_pointer_t<decltype(V)>>;
       if (nact > 16)
-        hipLaunchKernelGGL(k_b_dtv64<64>, dim3(l.Kp / 64, (nact + 63) / 64), dim3(TB), 0, s, dcm, V,
-                           l.Np, l.Kp, out, static_cast<const int*>(d_list), nact);
+        hipLaunchKernelGGL((k_b_dtv64<64, VT>), dim3(l.Kp / 64, (nact + 63) / 64), dim3(TB), 0, s,
+                           dcm, V, l.Np, l.Kp, out, static_cast<const int*>(d_list), nact);
       else if (nact > 0)
-        hipLaunchKernelGGL(k_b_dtv64<16>, dim3(l.Kp / 64, 1), dim3(TB), 0, s, dcm, V, l.Np, l.Kp,
-                           out, static_cast<const int*>(d_list), nact);
+        hipLaunchKernelGGL((k_b_dtv64<16, VT>), dim3(l.Kp / 64, 1), dim3(TB), 0, s, dcm, V, l.Np,
+                           l.Kp, out, static_cast<const int*>(d_list), nact);
     };
     dtv(a.Y, z0);
-    hipLaunchKernelGGL(k_b_inst_init, dim3(n), dim3(TB), 0, s, a, z0, d_lam,
-                       prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0, prm.gap_tol, Vn,
-                       static_cast<const int*>(d_perm), static_cast<const int*>(d_list));
-    if (prm.test == DS_TEST_DST3) dtv(Vn, gn);
-    hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, n), dim3(TB), 0, s, a, z0, gn,
-                       reinterpret_cast<float*>(base + l.marg), static_cast<const int*>(d_perm),
-                       static_cast<const int*>(d_list));
+    const int lrel = prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0;
+    if (l.G > 0) {
+      double* Vd = reinterpret_cast<double*>(base + l.Vd);
+      hipLaunchKernelGGL(k_b_ginst_init, dim3(n), dim3(TB), 0, s, a, z0, d_lam, lrel, prm.gap_tol,
+                         Vd, static_cast<const int*>(d_perm), static_cast<const int*>(d_list));
+      if (prm.test == DS_TEST_DST3) dtv(static_cast<const double*>(Vd), gn);
+      hipLaunchKernelGGL(k_b_gmargins, dim3((std::max(l.G, l.Kp) + TB - 1) / TB, n), dim3(TB), 0, s,
+                         a, z0, gn, reinterpret_cast<float*>(base + l.marg),
+                         static_cast<const int*>(d_perm), static_cast<const int*>(d_list));
+    } else {
+      hipLaunchKernelGGL(k_b_inst_init, dim3(n), dim3(TB), 0, s, a, z0, d_lam, lrel, prm.gap_tol,
+                         Vn, static_cast<const int*>(d_perm), static_cast<const int*>(d_list));
+      if (prm.test == DS_TEST_DST3) dtv(static_cast<const float*>(Vn), gn);
+      hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, n), dim3(TB), 0, s, a, z0, gn,
+                         reinterpret_cast<float*>(base + l.marg), static_cast<const int*>(d_perm),
+                         static_cast<const int*>(d_list));
+    }
     hipLaunchKernelGGL(k_b_tile_min, dim3((l.Kp / MT + TB - 1) / TB, n), dim3(TB), 0, s, a,
                        reinterpret_cast<float*>(base + l.tminm), static_cast<const int*>(d_list));
     DS_HIP(hipGetLastError());
@@ -504,9 +559,17 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
       hipLaunchKernelGGL(k_clock_span<0>, dim3(1), dim3(256), 0, s, a.kclk, zwaves, spans + nspan);
       ++nspan;
     }
+    if (l.G > 0)
+      hipLaunchKernelGGL(k_b_gprox, dim3((l.G + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a,
+                         static_cast<const float*>(Uin), Uout);
     hipLaunchKernelGGL(k_b_scalars, g_slot4, dim3(TB), 0, s, a);
-    hipLaunchKernelGGL(k_b_vcand, g_vca, dim3(TB), 0, s, a);
-    hipLaunchKernelGGL(k_b_vdot, g_vdot, dim3(TB), 0, s, a);
+    if (l.G > 0) {
+      hipLaunchKernelGGL(k_b_gvcand, g_vca, dim3(TB), 0, s, a);
+      hipLaunchKernelGGL(k_b_gvdot, g_vdot, dim3(TB), 0, s, a);
+    } else {
+      hipLaunchKernelGGL(k_b_vcand, g_vca, dim3(TB), 0, s, a);
+      hipLaunchKernelGGL(k_b_vdot, g_vdot, dim3(TB), 0, s, a);
+    }
     hipLaunchKernelGGL(k_b_vfin, g_slot4, dim3(TB), 0, s, a);
     hipLaunchKernelGGL(k_b_screen, g_scr, dim3(TB), 0, s, a);
     if (timed && et.first) { evt.push_back(et); evz.push_back(ez); }

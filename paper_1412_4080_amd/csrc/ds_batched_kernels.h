@@ -1,6 +1,7 @@
 // Batched path: B signals sharing one bfloat16 dictionary, Algorithm 3 with the ISTA /
-// FISTA update of Table 1 and the SAFE / DST3 sphere tests (Lemmas 1, 2).  Every signal
-// keeps its own penalty, dual point, radius and active set.
+// FISTA update of Table 1 and the SAFE / DST3 sphere tests (Lemmas 1, 2), or for the
+// Group-Lasso the group soft thresholding and the GSAFE / DGST3 tests (Lemmas 4, 5).
+// Every signal keeps its own penalty, dual point, radius and active set.
 //
 // Per iteration:
 //   theta = D_S p - y   sparse: each signal gathers the columns of its support S (the
@@ -10,8 +11,10 @@
 //                       accumulation) over the 32 x 32 (atom, signal) tiles that hold an
 //                       active pair.  theta enters as three bfloat16 parts (hi + mid + lo
 //                       reproduces its FP32 rounding), so every product is exact;
-//   the update of Table 1 in the GEMM epilogue, the FP64 scalars per signal, and the
-//   screening of the pairs whose margin passed the new radius.
+//   the update of Table 1 in the GEMM epilogue (groups: in a pass of its own, one thread
+//   per (group, signal), since a group's norm spans tiles), the FP64 scalars per signal,
+//   and the screening of the pairs whose margin passed the new radius.  A group's margin
+//   is stored on each of its atoms, so the tile masks and the screening work per atom.
 //
 // Precision.  ||theta||^2, theta^T y and Omega(p) are exact FP64 sums, so the primal
 // value is exact.  max|z| comes from the MFMA correlations of the FP32 rounding of theta;
@@ -68,9 +71,17 @@ struct alignas(16) Inst {
 struct BArgs {
   int N, K, B, Np, Kp, Bp, nrb;
   int test, rule, max_iter, screen_static;
+  int G;                // 0: Lasso; > 0: groups (contiguous, at most 128 atoms each)
+  const int64_t* gptr;  // G + 1 group offsets
+  const int* agrp;      // Kp: group of each atom (-1 past K)
+  const double* gw;     // G weights w_g
+  const double* gspec;  // G spectral norms ||D_g||_2 (FP64, of the stored values)
+  const double* gfro;   // G Frobenius norms ||D_g||_F
   double L, gamma_acc, gamma64;
   const uint16_t* dcm;  // Kp x Np, atom (column) major, zero padded
-  const double* dsc;    // dictionary scalars: [0] max nu_i, [1] max (1 + 1/nu_i)
+  const double* dsc;    // dictionary scalars: [0] correlation slack scale (max nu_i; groups
+                        // max ||D_g||_F / w_g), [1] margin slack scale (max (1 + 1/nu_i);
+                        // groups max (||D_g||_F + w_g) / ||D_g||_2)
   const double* nu;     // Kp atom norms
   const float* Y;       // Bp x Np observations (slot order, zero padded)
   float* X;             // Bp x Kp
@@ -85,7 +96,8 @@ struct BArgs {
   const float* tminm;   // (Kp/32) x Bp smallest margin of each 32-atom tile
   double* pz;           // (Kp/32) x Bp partial max |z| over active pairs
   double* pom;          // (Kp/32) x Bp partial Omega(p)
-  int* pact;            // (Kp/32) x Bp active pairs | (non-zeros of p << 8)
+  int* pact;            // (Kp/32) x Bp active pairs | (non-zeros of p << 8); groups: per
+                        // 64-group chunk, atoms active | (non-zeros of p << 16)
   float* Z;             // Bp x Kp correlations of the pairs computed this iteration
   int* ccount;          // Bp x (K/1024 rounded up) candidates per flagged signal and range
   int* cidx;            // Bp x Kp candidate atoms
@@ -168,12 +180,12 @@ __global__ __launch_bounds__(TB) void k_b_load_slots(BArgs a, const float* __res
 }
 
 // FP64 batched products out[b][a] = d_a^T v_b for the listed slots b = slots[j], j < nsl
-// (exact bfloat16 x float products, FP64 accumulation).  Block: 64 atoms x BS list entries;
-// thread: 4 atoms x BS/16 entries (atoms ta + 16 i, entries tb + 16 j); each output sums its
-// products in row order, so the value does not depend on BS.
-template <int BS>
+// (exact bfloat16 x FP32 / FP64 products, FP64 accumulation).  Block: 64 atoms x BS list
+// entries; thread: 4 atoms x BS/16 entries (atoms ta + 16 i, entries tb + 16 j); each output
+// sums its products in row order, so the value does not depend on BS.
+template <int BS, typename VT>
 __global__ __launch_bounds__(TB) void k_b_dtv64(const uint16_t* __restrict__ dcm,
-                                                const float* __restrict__ V, int Np, int Kp,
+                                                const VT* __restrict__ V, int Np, int Kp,
                                                 double* __restrict__ out,
                                                 const int* __restrict__ slots, int nsl) {
   constexpr int JS = BS / 16;  // entries per thread
@@ -365,6 +377,170 @@ __global__ __launch_bounds__(TB) void k_b_tile_min(BArgs a, float* __restrict__ 
   float v = INFINITY;
   for (int k = 0; k < MT; ++k) v = fminf(v, m[k]);
   tminm[static_cast<int64_t>(tile) * a.Bp + s] = v;
+}
+
+// ------------------------------------------------------------- groups: set-up
+// Dictionary scalars of a grouped dictionary (one block): max ||D_g||_F / w_g, the scale of
+// the correlation rounding slack, and max (||D_g||_F + w_g) / ||D_g||_2 over groups with
+// ||D_g||_2 > 0, the scale of the margins' rounding slack.
+__global__ __launch_bounds__(TB) void k_b_gdict_scalars(BArgs a, double* __restrict__ dsc) {
+  __shared__ double sd[NWB];
+  double m = 0.0, kap = 0.0;
+  for (int g = threadIdx.x; g < a.G; g += TB) {
+    m = fmax(m, a.gfro[g] / a.gw[g]);
+    if (a.gspec[g] > 0.0) kap = fmax(kap, (a.gfro[g] + a.gw[g]) / a.gspec[g]);
+  }
+  m = block_max<double, NWB>(m, sd);
+  kap = block_max<double, NWB>(kap, sd);
+  if (threadIdx.x == 0) {
+    dsc[0] = m;
+    dsc[1] = kap;
+  }
+}
+
+// Per-signal setup for groups (one block per listed slot): ||y||^2, finiteness,
+// lambda_* = max_g ||z0_g|| / w_g with the smallest-index tie break (eq. gstar), lambda,
+// the trivial case, and the DGST3 hyperplane of Lemma 5: n = D_g* D_g*^T y / lambda_*
+// (FP64, written to Vd for D^T n), ||n||^2, n^T y, alpha = (n^T y / lambda - w_g*^2) /
+// ||n||^2, rho^2 = alpha^2 ||n||^2.
+__global__ __launch_bounds__(TB) void k_b_ginst_init(BArgs a, const double* __restrict__ z0,
+                                                     const double* __restrict__ lam_in,
+                                                     int lam_relative, double gap_tol,
+                                                     double* __restrict__ Vd,
+                                                     const int* __restrict__ perm,
+                                                     const int* __restrict__ slots) {
+  __shared__ double sd[NWB];
+  __shared__ int si[NWB];
+  __shared__ double s_best;
+  __shared__ int s_arg;
+  const int s = slots[blockIdx.x], tid = threadIdx.x;
+  Inst* st = a.inst + s;
+  const float* y = a.Y + static_cast<int64_t>(s) * a.Np;
+  double* vd = Vd + static_cast<int64_t>(s) * a.Np;
+  if (perm[s] < 0) {  // idle slot
+    for (int n = tid; n < a.Np; n += TB) vd[n] = 0.0;
+    if (tid == 0) {
+      Inst z = {};
+      z.done = 1;
+      z.status = 1;
+      *st = z;
+    }
+    return;
+  }
+  double yy = 0.0;
+  int bad = 0;
+  for (int n = tid; n < a.N; n += TB) {
+    const double v = y[n];
+    if (!isfinite(v)) bad = 1;
+    yy = fma(v, v, yy);
+  }
+  yy = block_sum<double, NWB>(yy, sd);
+  bad = block_sum<int, NWB>(bad, si);
+  const double* z = z0 + static_cast<int64_t>(s) * a.Kp;
+  double best = -1.0;
+  int barg = 0x7fffffff;
+  for (int g = tid; g < a.G; g += TB) {  // increasing g per thread: strict > keeps the first
+    double s2 = 0.0;
+    for (int64_t k = a.gptr[g]; k < a.gptr[g + 1]; ++k) s2 = fma(z[k], z[k], s2);
+    const double v = sqrt(s2) / a.gw[g];
+    if (v > best) { best = v; barg = g; }
+  }
+  for (int o = BW / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, BW);
+    const int oa = __shfl_xor(barg, o, BW);
+    if (ob > best || (ob == best && oa < barg)) { best = ob; barg = oa; }
+  }
+  __syncthreads();
+  if (tid % BW == 0) { sd[tid / BW] = best; si[tid / BW] = barg; }
+  __syncthreads();
+  if (tid == 0) {
+    double b = sd[0];
+    int ba = si[0];
+    for (int k = 1; k < NWB; ++k)
+      if (sd[k] > b || (sd[k] == b && si[k] < ba)) { b = sd[k]; ba = si[k]; }
+    s_best = b;
+    s_arg = ba;
+  }
+  __syncthreads();
+  const double lam_max = s_best;
+  const int arg = s_arg;
+  if (!(arg >= 0 && arg < a.G) || !isfinite(lam_max)) bad = 1;
+  const double lam = lam_relative ? lam_in[s] * lam_max : lam_in[s];
+  const bool trivial = !(lam < lam_max);
+  const bool dst3 = a.test == 2 && !trivial && !bad;
+  double nn = 0.0, ny = 0.0;
+  const int64_t g0 = dst3 ? a.gptr[arg] : 0, g1 = dst3 ? a.gptr[arg + 1] : 0;
+  for (int n = tid; n < a.Np; n += TB) {
+    double v = 0.0;
+    if (dst3) {
+      for (int64_t k = g0; k < g1; ++k) v = fma(bf16f(a.dcm[k * a.Np + n]), z[k], v);
+      v /= lam_max;
+      nn = fma(v, v, nn);
+      ny = fma(v, static_cast<double>(y[n]), ny);
+    }
+    vd[n] = v;
+  }
+  nn = block_sum<double, NWB>(nn, sd);
+  ny = block_sum<double, NWB>(ny, sd);
+  if (tid == 0) {
+    Inst t = {};
+    const double ws2 = dst3 ? a.gw[arg] * a.gw[arg] : 1.0;
+    const double alpha = (dst3 && nn > 0.0) ? (ny / lam - ws2) / nn : 0.0;
+    t.lam = lam;
+    t.lam_max = lam_max;
+    t.yy = yy;
+    t.alpha = alpha;
+    t.nn = nn;
+    t.rho2 = alpha * alpha * nn;
+    t.gap_tol_abs = gap_tol * yy;
+    t.r_min = 1e300;
+    t.r_scr = 1e300;
+    t.r_keep = 1e300;
+    t.r_prev = 1e300;
+    t.l_prev = 1.0;
+    t.i_star = bad ? 0 : arg;
+    t.status = bad ? -1 : (trivial ? 1 : 0);
+    t.done = (bad || trivial) ? 1 : 0;
+    t.converged = t.done;
+    const double eps = (a.N + 16) * 0x1p-53;
+    t.marg_slack = eps * a.dsc[1] * (sqrt(yy) / lam + fabs(alpha) * sqrt(nn) + 1.0);
+    *st = t;
+    if (t.done) atomicAdd(a.ndone, 1);
+  }
+}
+
+// Group margins m_g = (w_g - ||D_g^T c||) / ||D_g||_2 (Lemmas 4, 5 through the sphere bound
+// of Lemma 6) with D_g^T c = z0_g / lambda - alpha D_g^T n (GSAFE: alpha = 0), rounded
+// towards -inf and stored on every atom of the group.  Padding atoms, idle and finished
+// slots, groups with ||D_g||_2 = 0: +inf; no test: -inf.  Thread: one group (and one
+// padding atom) of one listed slot.
+__global__ __launch_bounds__(TB) void k_b_gmargins(BArgs a, const double* __restrict__ z0,
+                                                   const double* __restrict__ gn,
+                                                   float* __restrict__ marg,
+                                                   const int* __restrict__ perm,
+                                                   const int* __restrict__ slots) {
+  const int s = slots[blockIdx.y];
+  const int j = blockIdx.x * TB + threadIdx.x;
+  const int64_t row = static_cast<int64_t>(s) * a.Kp;
+  if (j >= a.K && j < a.Kp) marg[row + j] = INFINITY;
+  if (j >= a.G) return;
+  const Inst& st = a.inst[s];
+  const int64_t g0 = a.gptr[j], g1 = a.gptr[j + 1];
+  float m;
+  if (perm[s] < 0 || st.done) {
+    m = INFINITY;
+  } else if (a.test == 0) {
+    m = -INFINITY;
+  } else {
+    double s2 = 0.0;
+    for (int64_t k = g0; k < g1; ++k) {
+      const double ck = z0[row + k] / st.lam - (a.test == 2 ? st.alpha * gn[row + k] : 0.0);
+      s2 = fma(ck, ck, s2);
+    }
+    const double sp = a.gspec[j];
+    m = sp > 0.0 ? __double2float_rd((a.gw[j] - sqrt(s2)) / sp) : INFINITY;
+  }
+  for (int64_t k = g0; k < g1; ++k) marg[row + k] = m;
 }
 
 // ============================================================== iteration kernels
@@ -627,6 +803,36 @@ __global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* 
     if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
     return;
   }
+  if (a.G > 0) {
+    // groups: z of the active atoms for the group update; the tile masks are cleared for
+    // k_b_gprox to OR the new non-zero bits into
+#pragma unroll
+    for (int ib = 0; ib < WB; ++ib) {
+      const int bl = b0b + wbl + MT * ib + lane % MT;
+#pragma unroll
+      for (int ia = 0; ia < WA; ++ia) {
+        if (!sub_on[ia][ib]) continue;
+        const int a0 = a0b + wal + MT * ia;
+        if (tile_on[ia][ib]) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t o = static_cast<int64_t>(bl) * a.Kp + a0 + 8 * q + (lane / MT) * 4;
+            const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
+            if (!(static_cast<double>(m4.x) <= r_act[ib] || static_cast<double>(m4.y) <= r_act[ib] ||
+                  static_cast<double>(m4.z) <= r_act[ib] || static_cast<double>(m4.w) <= r_act[ib]))
+              continue;
+            const double* zq = &zacc[ia][ib][4 * q];
+            *reinterpret_cast<float4*>(a.Z + o) =
+                make_float4(static_cast<float>(zq[0]), static_cast<float>(zq[1]),
+                            static_cast<float>(zq[2]), static_cast<float>(zq[3]));
+          }
+        }
+        if (lane < MT) a.umask[static_cast<int64_t>(a0 / MT) * a.Bp + bl] = 0u;
+      }
+    }
+    if (a.kclk != nullptr && lane == 0) a.kclk[2 * gw + 1] = wall_clock64();
+    return;
+  }
   // epilogue per output tile: lane holds signal bl, atoms a0 + 8 q + (lane / 32) * 4 + e
 #pragma unroll
   for (int ib = 0; ib < WB; ++ib) {
@@ -714,6 +920,78 @@ constexpr ZShapeDesc ZSHAPES[] = {{2, 2, 1, 1}, {4, 2, 1, 1}, {4, 1, 1, 1}, {2, 
 constexpr int NZSHAPE = sizeof(ZSHAPES) / sizeof(ZSHAPES[0]);
 constexpr int KP_ALIGN = 128;  // Kp is a multiple of it; larger atom extents need Kp % TA == 0
 
+constexpr int GCH = BW;  // groups per partial entry (one wave)
+
+// The update of Table 1 for the Group-Lasso (one thread per (group, signal), for the groups
+// active in this iteration): v_g = p_g - z_g / L, x_g = max(0, 1 - (lambda / L) w_g /
+// ||v_g||) v_g (eq. gr_softTh, FP64), FISTA momentum u_g = x_g + beta (x_g - x_{t-1,g}).
+// Per 64-group chunk (one wave): max ||z_g|| / w_g, Omega(p) = sum w_g ||p_g||, the active
+// atoms and the non-zeros of p.  The new non-zero bits of u are OR-ed into the tile masks,
+// which the GEMM cleared (a group can span tiles).
+__global__ __launch_bounds__(TB) void k_b_gprox(BArgs a, const float* __restrict__ Uin,
+                                                float* __restrict__ Uout) {
+  const int s = blockIdx.y, g = blockIdx.x * TB + threadIdx.x, lane = threadIdx.x % BW;
+  const Inst& st = a.inst[s];
+  if (st.done != 0) return;  // the whole block: one signal
+  const double invL = 1.0 / a.L, thr = st.lam / a.L, r_act = st.r_keep;
+  double beta = 0.0;
+  if (a.rule == 1) {
+    const double lp = st.l_prev;
+    beta = (lp - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * lp * lp)));
+  }
+  const int64_t row = static_cast<int64_t>(s) * a.Kp;
+  double zs = 0.0, om = 0.0;
+  int nact = 0, nsup = 0;
+  if (g < a.G) {
+    const int64_t g0 = a.gptr[g], g1 = a.gptr[g + 1];
+    if (g1 > g0 && static_cast<double>(a.marg[row + g0]) <= r_act) {
+      double zz = 0.0, vv = 0.0, pp = 0.0;
+      for (int64_t k = g0; k < g1; ++k) {
+        const double z = a.Z[row + k], p = Uin[row + k];
+        const double v = p - z * invL;
+        zz = fma(z, z, zz);
+        vv = fma(v, v, vv);
+        pp = fma(p, p, pp);
+        nsup += p != 0.0;
+      }
+      const double w = a.gw[g];
+      nact = static_cast<int>(g1 - g0);
+      zs = sqrt(zz) / w;
+      om = w * sqrt(pp);
+      const double nv = sqrt(vv);
+      const double sc = nv > 0.0 ? fmax(0.0, 1.0 - thr * w / nv) : 0.0;
+      uint32_t bits = 0u;
+      int64_t tile = g0 / MT;
+      for (int64_t k = g0; k < g1; ++k) {
+        if (k / MT != tile) {
+          if (bits != 0u) atomicOr(&a.umask[tile * a.Bp + s], bits);
+          bits = 0u;
+          tile = k / MT;
+        }
+        const double z = a.Z[row + k], p = Uin[row + k];
+        const double xn = sc * (p - z * invL);
+        const double un = xn + beta * (xn - static_cast<double>(a.X[row + k]));
+        const float uf = static_cast<float>(un);
+        a.X[row + k] = static_cast<float>(xn);
+        Uout[row + k] = uf;
+        if (uf != 0.f) bits |= 1u << (k % MT);
+      }
+      if (bits != 0u) atomicOr(&a.umask[tile * a.Bp + s], bits);
+    }
+  }
+  zs = wave_max(zs);
+  om = wave_sum(om);
+  nact = wave_sum(nact);
+  nsup = wave_sum(nsup);
+  const int ch = g / GCH;
+  if (lane == 0 && ch * GCH < a.G) {
+    const int64_t o = static_cast<int64_t>(ch) * a.Bp + s;
+    a.pz[o] = zs;
+    a.pom[o] = om;
+    a.pact[o] = nact | (nsup << 16);
+  }
+}
+
 // FP64 scalars of iteration t, one wave per slot: dual scaling (Lemma 7) from the MFMA
 // correlations, gap estimate, sphere radius (SAFE: R; DST3: sqrt(R^2 - rho^2)) grown by
 // the accumulation slack, screening threshold for the next iteration.  Flags the signal
@@ -724,11 +1002,15 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   if (s >= a.Bp) return;
   Inst& st = a.inst[s];
   if (st.done != 0) return;
-  const int ntile = a.Kp / MT;
+  // partial entries: 32-atom tiles (Lasso) or 64-group chunks, whose counts pack the
+  // active atoms and the non-zeros of p in 8- or 16-bit fields
+  const int ntile = a.G > 0 ? (a.G + GCH - 1) / GCH : a.Kp / MT;
+  const int cb = a.G > 0 ? 16 : 8;
+  const int cm = (1 << cb) - 1;
   double zm = 0.0, om = 0.0;
   int nact = 0, nsup = 0;
-  // the first QT tiles of every lane (K <= 16384) in one round trip: unconditional loads
-  // at clamped indices, then the lane's sums in tile order
+  // the first QT entries of every lane (K <= 16384) in one round trip: unconditional loads
+  // at clamped indices, then the lane's sums in entry order
   constexpr int QT = 8;
   double qz[QT], qo[QT];
   int qa[QT];
@@ -747,8 +1029,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     if (lane + q * BW < ntile) {
       zm = fmax(zm, qz[q]);
       om += qo[q];
-      nact += qa[q] & 0xff;
-      nsup += qa[q] >> 8;
+      nact += qa[q] & cm;
+      nsup += qa[q] >> cb;
     }
   }
   for (int t = lane + QT * BW; t < ntile; t += BW) {
@@ -756,8 +1038,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     zm = fmax(zm, a.pz[o]);
     om += a.pom[o];
     const int c = a.pact[o];
-    nact += c & 0xff;
-    nsup += c >> 8;
+    nact += c & cm;
+    nsup += c >> cb;
   }
   double tt = lane < a.nrb ? q_tt : 0.0, ty = lane < a.nrb ? q_ty : 0.0;
   for (int c = lane + BW; c < a.nrb; c += BW) {
@@ -789,7 +1071,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   const double R2 = a1 - a2 + a3;
   const double E = (a.N + 16) * 0x1p-53 * (a1 + fabs(a2) + a3 + rr);
   const double nth = sqrt(tt);
-  const double eps = zm > 0.0 ? a.gamma_acc * a.dsc[0] * nth / zm : 0.0;
+  // relative error of max|z| (groups: of max ||z_g|| / w_g, from the stored FP32 z)
+  const double eps = zm > 0.0 ? a.gamma_acc * a.dsc[0] * nth / zm + (a.G > 0 ? 0x1p-23 : 0.0) : 0.0;
   const double Rup = sqrt(fmax(R2 + E, 0.0)) + eps * fabs(mu) * nth;
   double r = 1e300, r_safe = 1e300;
   if (a.test != 0) {
@@ -940,6 +1223,110 @@ __global__ __launch_bounds__(TB) void k_b_vdot(BArgs a) {
   }
 }
 
+// Verification for groups, step 1: candidate groups for the FP64 maximum of
+// ||D_g^T theta|| / w_g over the groups active in this iteration.  ||z_hat_g|| / w_g is
+// within e = gamma_acc dsc[0] ||theta|| + 2^-23 zmax of the exact value (the accumulation
+// bound summed over the group's atoms, and the FP32 rounding of the stored z), so a group
+// below zmax - 2 e cannot attain the maximum.  Block: the groups whose first atom lies in
+// a 1024-atom range of one flagged signal, listed in group order.
+__global__ __launch_bounds__(TB) void k_b_gvcand(BArgs a) {
+  __shared__ int scan[NWB];
+  const int nflag = *a.vcount;
+  const int nch = (a.K + VC - 1) / VC;
+  const int i0 = blockIdx.x * VC;
+  for (int j = blockIdx.y; j < nflag; j += gridDim.y) {
+    const int s = a.vlist[j];
+    const Inst& st = a.inst[s];
+    const double r_act = st.r_prev;
+    const double zmax = st.zmax;
+    const double e = a.gamma_acc * a.dsc[0] * sqrt(st.tt) + 0x1p-23 * zmax;
+    const double thr = zmax - 2.0 * e;
+    const int64_t row = static_cast<int64_t>(s) * a.Kp;
+    int* out = a.cidx + row + i0;
+    int mine[4], cnt = 0;
+    const int ib = i0 + threadIdx.x * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = ib + k;
+      mine[k] = -1;
+      if (i >= a.K) continue;
+      const int g = a.agrp[i];
+      const int64_t g0 = a.gptr[g], g1 = a.gptr[g + 1];
+      if (g0 != i || !(static_cast<double>(a.marg[row + i]) <= r_act)) continue;
+      double zz = 0.0;
+      for (int64_t q = g0; q < g1; ++q) {
+        const double z = a.Z[row + q];
+        zz = fma(z, z, zz);
+      }
+      if (sqrt(zz) / a.gw[g] >= thr) {
+        mine[k] = g;
+        ++cnt;
+      }
+    }
+    int total;
+    int pos = block_exclusive_scan<NWB>(cnt, scan, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (mine[k] >= 0) out[pos++] = mine[k];
+    if (threadIdx.x == 0) a.ccount[static_cast<int64_t>(s) * nch + blockIdx.x] = total;
+    __syncthreads();
+  }
+}
+
+// Verification for groups, step 2: exact FP64 ||D_g^T theta|| / w_g of every candidate
+// group, one wave per candidate (each atom's dot product with the rows across the lanes,
+// the squares summed in atom order), all waves of the grid sharing the work in a fixed
+// order.
+__global__ __launch_bounds__(TB) void k_b_gvdot(BArgs a) {
+  __shared__ int ssig[VLDS];
+  __shared__ int scnt[VLDS];
+  const int nflag = *a.vcount;
+  const int lane = threadIdx.x % BW;
+  const int nw = gridDim.x * NWB;
+  const int gw = blockIdx.x * NWB + threadIdx.x / BW;
+  const int nch = (a.K + VC - 1) / VC;
+  const int npair = nflag * nch;
+  int off = 0;
+  for (int p0 = 0; p0 < npair; p0 += VLDS) {
+    const int np = min(VLDS, npair - p0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < np; e += TB) {
+      const int jc = p0 + e;
+      const int sg = a.vlist[jc / nch];
+      ssig[e] = sg;
+      scnt[e] = a.ccount[static_cast<int64_t>(sg) * nch + jc % nch];
+    }
+    __syncthreads();
+    for (int e = 0; e < np; ++e) {
+      const int s = ssig[e], ch = (p0 + e) % nch, cnt = scnt[e];
+      const double* th = a.th64 + static_cast<int64_t>(s) * a.Np;
+      for (int c = ((gw - off) % nw + nw) % nw; c < cnt; c += nw) {
+        const int64_t slot = static_cast<int64_t>(s) * a.Kp + ch * VC + c;
+        const int g = a.cidx[slot];
+        double s2 = 0.0;
+        for (int64_t k = a.gptr[g]; k < a.gptr[g + 1]; ++k) {
+          const uint16_t* col = a.dcm + k * a.Np;
+          double acc = 0.0;
+          for (int n0 = lane * 8; n0 < a.Np; n0 += BW * 8) {
+            const uint4 d = ldg16(col + n0);
+            const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double2 t2 = *reinterpret_cast<const double2*>(th + n0 + 2 * q);
+              acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2.x, acc);
+              acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2.y, acc);
+            }
+          }
+          acc = wave_sum(acc);
+          s2 = fma(acc, acc, s2);
+        }
+        if (lane == 0) a.cval[slot] = sqrt(s2) / a.gw[g];
+      }
+      off += cnt;
+    }
+  }
+}
+
 // Exact gap of the flagged signals (one wave per slot) at the feasible dual point
 // v = mu theta, mu = clip(theta^T y / (lambda ||theta||^2), +-1/zs) with zs the FP64
 // maximum plus the rounding bound of that pass (Lemma 7).  Finishes the signal when the
@@ -977,7 +1364,9 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
   const double lam = st.lam, tt = st.tt, ty = st.ty;
   const double primal = st.primal, gap_tol_abs = st.gap_tol_abs;  // read before any store
   const int iter = st.iter;
-  const double zs = zm + a.gamma64 * a.dsc[0] * sqrt(tt);
+  // groups: the sum of squares, the square root and the division add a few units of
+  // rounding to each candidate's value (at most 132 atoms: below 2^-44 relative)
+  const double zs = zm * (a.G > 0 ? 1.0 + 0x1p-44 : 1.0) + a.gamma64 * a.dsc[0] * sqrt(tt);
   const double sb = zs > 0.0 ? 1.0 / zs : 1e300;
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);

@@ -117,8 +117,12 @@ void batch_engine_destroy(BatchEngine* engine);
 ds_status run_batched(BatchEngine& engine, const ds_problem& P, const float* Y, int64_t ldy,
                       int nslot, const ds_params& prm, float* X, int64_t ldx,
                       uint8_t* screened, BatchFeed& feed, hipStream_t stream);
-// Device bytes of a batched engine's workspace for this shape.
-size_t batched_workspace_bytes(int64_t N, int64_t K, int slots, int max_iter);
+// Device bytes of a batched engine's workspace for this shape (G > 0: grouped).
+size_t batched_workspace_bytes(int64_t N, int64_t K, int slots, int max_iter, int64_t G = 0);
+// ||D_g||_2 and ||D_g||_F of the contiguous groups gptr_dev (device, G + 1 offsets) of a
+// bfloat16 dictionary with leading dimension ldd; max_group: the largest group (<= 128).
+ds_status group_norms_bf16(const uint16_t* D, int64_t ldd, int N, int G, const int64_t* gptr_dev,
+                           int max_group, double* gnorm, double* fro, hipStream_t s);
 // Gives an idle engine's device memory back (workspace and graph; tuned shapes are kept).
 void batch_engine_trim(BatchEngine* engine);
 

@@ -238,6 +238,28 @@ ds_status launch_setup_corr(const ds_problem& P, const void* y, char* base, cons
   return DS_OK;
 }
 
+}  // namespace
+
+// Spectral and Frobenius norms of contiguous groups of a bfloat16 dictionary (the batched
+// path's padded copy), with the single-signal path's kernel.
+ds_status group_norms_bf16(const uint16_t* D, int64_t ldd, int N, int G, const int64_t* gptr_dev,
+                           int max_group, double* gnorm, double* fro, hipStream_t s) {
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(grid_for(G, 1, 4096)), dim3(BLK), 0, s, D, ldd, N, G, gptr_dev,
+                       gnorm, fro);
+  };
+  switch (gram_edge(max_group)) {
+    case 16: launch(k_group_norms<bf16_t, 16>); break;
+    case 32: launch(k_group_norms<bf16_t, 32>); break;
+    case 64: launch(k_group_norms<bf16_t, 64>); break;
+    default: launch(k_group_norms<bf16_t, 128>); break;
+  }
+  DS_HIP(hipGetLastError());
+  return DS_OK;
+}
+
+namespace {
+
 template <typename T, bool VEC, int RULE>
 ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
                      void* x, ds_info* info, hipStream_t s, Workspace& ws,
