@@ -275,6 +275,57 @@ def batched_leg(binding, D, steps, warmup):
     }
 
 
+def batched_groups_leg(binding, D, steps=2, n_plain=8):
+    """The Group-Lasso on the bfloat16 matrix-core path: the group workload's dictionary
+    (2000 x 10000, 1000 contiguous groups of 10, w_g = sqrt(10)) stored in bfloat16, 256
+    signals of its generator with lambda / lambda_* uniform in [0.1, 0.9], FISTA + DGST3 to
+    gap 1e-6: solves/s, against the same solves one at a time on the FP32 single-signal
+    path without screening (a sample of n_plain of them)."""
+    import torch
+    gp = datagen.contiguous_groups(K, 10)
+    Dbf = datagen.to_storage(D, "bf16")
+    Dd = torch.from_numpy(np.ascontiguousarray(Dbf.T)).to(device="cuda", dtype=torch.bfloat16).T
+    ys = np.stack([datagen.to_storage(datagen.group_signal(D, gp, j)[0], "f32") for j in range(NB)])
+    Y = torch.from_numpy(ys.astype(np.float32)).cuda().T
+    ratios = datagen.lambda_ratios(NB, 0.1, 0.9, datagen.LAMBDA_SEED0)
+    L = binding.spectral_norm_sq(Dd, 300)
+
+    def one():
+        X, infos = binding.solve(Dd, Y, ratios, group_ptr=gp, rule="fista", test="dst3",
+                                 step_L=L, gap_tol=GAP_TOL, max_iter=20000)
+        if any(i["status"] != 0 for i in infos):
+            raise RuntimeError("batched group solve did not converge")
+        return infos
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = one()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = [i["iters"] for i in infos]
+    # plain single-signal FP32 solves of a sample of the same signals
+    D32 = torch.from_numpy(np.ascontiguousarray(datagen.to_storage(D, "f32").T)).to(
+        device="cuda", dtype=torch.float32).T
+    L32 = binding.spectral_norm_sq(D32, 300)
+    yd = [torch.from_numpy(ys[j].astype(np.float32)).cuda() for j in range(n_plain)]
+    binding.solve_one(D32, yd[0], float(ratios[0]), group_ptr=gp, rule="fista", test="none",
+                      step_L=L32, gap_tol=GAP_TOL, max_iter=50000, trace=False, screened=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for j in range(n_plain):
+        binding.solve_one(D32, yd[j], float(ratios[j]), group_ptr=gp, rule="fista", test="none",
+                          step_L=L32, gap_tol=GAP_TOL, max_iter=50000, trace=False, screened=False)
+    torch.cuda.synchronize()
+    plain = n_plain / (time.perf_counter() - t1)
+    sps = NB * steps / dt
+    return {"workload": "group_lasso_fista_dgst3_gaussian_2000x10000_bf16_groups10_batch256",
+            "signals": NB, "solves_per_s": round(sps, 2), "ms_per_batch": round(dt * 1e3 / steps, 3),
+            "iterations": {"max": int(max(it)), "mean": round(float(np.mean(it)), 1)},
+            "plain_single_fp32_solves_per_s": round(plain, 2),
+            "over_plain_single": round(sps / plain, 2)}
+
+
 INSTR_SIGNALS = 6   # signals of the instrumented pass (x 5 ratios), whatever --steps is
 A_BUCKETS = (0, 1000, 2500, 5000, 7500, 10001)
 
@@ -986,12 +1037,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--legs", default="single,seeds,small,groups,batched,served,served_batched,"
+    ap.add_argument("--legs", default="single,seeds,small,groups,batched,batched_groups,served,"
+                                      "served_batched,"
                                       "paper_lasso,paper_group,paper_illustration,large,"
                                       "backtracking,sparsa,dome,cp",
                     help="comma list of legs: single (headline), seeds (the headline per lambda "
                          "over 30 signals), small (100 x 500 FP64, microseconds per iteration), "
-                         "groups (groups of 10, ISTA + DGST3 / GSAFE), batched, served (the eight-dictionary "
+                         "groups (groups of 10, ISTA + DGST3 / GSAFE), batched, batched_groups (256 signals of "
+                         "the group workload on the bfloat16 matrix-core path), served (the "
+                         "eight-dictionary "
                          "mix, workers only and with batched engines), served_batched (requests "
                          "for the batched workload's bfloat16 dictionary: engine vs workers), "
                          "paper_lasso (the paper's Pnoise Lasso experiment: normalised flops "
@@ -1121,6 +1175,8 @@ def main():
         b["stream"] = batched_stream_leg(binding, D)
         b["stream"]["over_plain_single"] = round(b["stream"]["solves_per_s"] / plain, 2)
         out["batched"] = b
+    if "batched_groups" in legs:
+        out["batched_groups"] = batched_groups_leg(binding, D)
     if "seeds" in legs:
         out["per_lambda_30_signals"] = seeds_leg(binding, D, Dd, L)
     if "small" in legs:
@@ -1157,7 +1213,7 @@ def main():
     if "served" in legs:
         out["served"] = served_leg(binding, slots=args.serve_slots)
         out["served"]["batched_engine"] = served_leg(binding, slots=args.serve_slots,
-                                                     batch_slots=256)
+                                                     batch_slots=64)
     if "served_batched" in legs:
         out["served_bf16_one_dictionary"] = served_batched_leg(binding, D)
     if not args.no_cpu:

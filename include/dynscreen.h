@@ -261,12 +261,14 @@ ds_status ds_spectral_norm_sq(const ds_problem* problem, int32_t iters, double* 
  * memory at registration; requests carry y on the host, are admitted when their device
  * footprint fits the HBM budget and a slot is free, and run interleaved with other
  * requests on the device.
- * With batch_slots > 0, every bfloat16 Lasso dictionary also gets a batched engine (the
- * matrix-core path of lasso_solve): a request for it whose parameters that path supports
+ * With batch_slots > 0, every bfloat16 dictionary also gets a batched engine (the
+ * matrix-core path of lasso_solve / glasso_solve): a request for it whose parameters that
+ * path supports
  * (ISTA or FISTA, constant step, SAFE / DST3 / no test, no x0, obj_tol = 0) joins the
  * engine's resident signals at the next graph-replay boundary where a slot is free, and
  * leaves as soon as it has finished; requests with the same parameters share a run.  Its
- * result equals lasso_solve's batched result for the same y and lambda bit for bit, alone
+ * result equals the batched result of lasso_solve (glasso_solve) for the same y and lambda
+ * bit for bit, alone
  * or in any mix.  Other requests run as single-signal solves on the worker slots. */
 typedef struct {
   int32_t device;           /* HIP device ordinal */
@@ -274,7 +276,7 @@ typedef struct {
   size_t hbm_budget_bytes;  /* device memory the server may use for requests (> 0) */
   int32_t max_queue;        /* maximum pending requests before DS_EBUSY (>= 1) */
   int32_t batch_slots;      /* 0: no batched engines; else signals resident in each
-                               bfloat16 Lasso dictionary's batched engine (<= 32768) */
+                               bfloat16 dictionary's batched engine (<= 32768) */
 } ds_server_config;
 
 /* Starts max_slots worker threads.  Failure-path testing: when the environment variable

@@ -7,7 +7,7 @@
 // y and x; a worker takes the oldest queued request whose device footprint fits the part
 // of the HBM budget not held by the other workers, so requests are admitted as slots and
 // memory free up, and the resident requests' kernels run concurrently on the device.
-// With batch_slots > 0 each bfloat16 Lasso dictionary also has a batched engine run by a
+// With batch_slots > 0 each bfloat16 dictionary also has a batched engine run by a
 // thread of its own: its requests wait in the dictionary's queue, join the engine's
 // resident signals whenever a slot is free at a graph-replay boundary (the ones with the
 // parameters of the running batch), and leave when they finish.
@@ -98,7 +98,7 @@ struct Worker {
   size_t held = 0;  // device bytes charged to the budget for this worker
 };
 
-// The batched engine of one bfloat16 Lasso dictionary and its requests.
+// The batched engine of one bfloat16 dictionary (Lasso or groups) and its requests.
 struct BatchLane {
   int dict = -1;
   std::thread th;
@@ -130,8 +130,8 @@ bool same_run(const ds_params& a, const ds_params& b) {
 
 // Device bytes a batched engine holds: its workspace (with the 25% headroom of
 // Workspace::reserve) and the staging columns.
-size_t lane_need(int64_t N, int64_t K, int slots, int max_iter) {
-  const size_t ws = batched_workspace_bytes(N, K, slots, max_iter);
+size_t lane_need(int64_t N, int64_t K, int64_t G, int slots, int max_iter) {
+  const size_t ws = batched_workspace_bytes(N, K, slots, max_iter, G);
   const int64_t ldy = (N + 3) / 4 * 4;
   return ws + ws / 4 + align256(static_cast<size_t>(ldy) * slots * 4) +
          align256(static_cast<size_t>(K) * slots * 4);
@@ -325,7 +325,7 @@ void Server::lane_loop(BatchLane* b) {
       continue;
     }
     const ds_params key = reqs.at(b->queue.front())->prm;
-    const size_t need = lane_need(d.N, d.K, cfg.batch_slots, key.max_iter);
+    const size_t need = lane_need(d.N, d.K, d.G, cfg.batch_slots, key.max_iter);
     const size_t want = std::max(b->held, need);
     if (held - b->held + want > cfg.hbm_budget_bytes) {
       if (b->held > 0) {  // hold nothing while waiting
@@ -502,7 +502,7 @@ ds_status submit_impl(void* server, int32_t dict_id, const void* y_host, double 
   }
   auto lane = S->lanes.find(dict_id);
   const bool batched = lane != S->lanes.end() && batch_eligible(*params) &&
-                       lane_need(d.N, d.K, S->cfg.batch_slots, params->max_iter) <=
+                       lane_need(d.N, d.K, d.G, S->cfg.batch_slots, params->max_iter) <=
                            S->cfg.hbm_budget_bytes;
   const size_t need = batched ? 0 : request_need(d, *params);
   if (need > S->cfg.hbm_budget_bytes) {
@@ -660,7 +660,7 @@ ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype s
     (void)hipFree(d->D);
     return st;
   }
-  const bool lane = S->cfg.batch_slots > 0 && store == DS_BF16 && !group;
+  const bool lane = S->cfg.batch_slots > 0 && store == DS_BF16;
   std::lock_guard<std::mutex> g(S->mu);
   *dict_id = S->next_dict++;
   S->dicts.emplace(*dict_id, std::move(d));

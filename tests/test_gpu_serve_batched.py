@@ -21,19 +21,21 @@ def B():
 
 
 def _dicts():
-    """(D values (f64), stored dtype, group_ptr): two bfloat16 Lasso dictionaries (engines),
-    an FP32 Lasso and an FP32 grouped one (single-signal workers)."""
+    """(D values (f64), stored dtype, group_ptr): two bfloat16 Lasso dictionaries and a
+    bfloat16 grouped one (engines), an FP32 Lasso and an FP32 grouped one (single-signal
+    workers)."""
     return [(datagen.gaussian_dictionary(512, 3000, 31), "bf16", None),
             (datagen.gaussian_dictionary(300, 1700, 32), "bf16", None),
             (datagen.gaussian_dictionary(256, 1000, 33), "f32", None),
-            (datagen.gaussian_dictionary(300, 2000, 34), "f32", datagen.contiguous_groups(2000, 10))]
+            (datagen.gaussian_dictionary(300, 2000, 34), "f32", datagen.contiguous_groups(2000, 10)),
+            (datagen.gaussian_dictionary(320, 2400, 37), "bf16", datagen.contiguous_groups(2400, 8))]
 
 
 def _requests(dicts, n, seed):
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n):
-        d = (0, 1, 2, 0, 1, 3)[k % 6]   # two thirds for the engines
+        d = (0, 1, 2, 0, 4, 1, 3, 4)[k % 8]   # three quarters for the engines
         D, _, gp = dicts[d]
         y = datagen.lasso_signal(D, 700 + k)[0] if gp is None else datagen.group_signal(D, gp, 700 + k)[0]
         out.append((d, datagen.to_storage(y, "f32").astype(np.float32), float(rng.uniform(0.1, 0.9))))
@@ -68,18 +70,19 @@ def _wait(S, pending, ids, timeout=180.0):
     return out
 
 
-def _direct_batched(B, D, ys, ratios, L, **kw):
-    """lasso_solve on the bfloat16 dictionary with every signal at once (batched path)."""
+def _direct_batched(B, D, ys, ratios, L, group_ptr=None, **kw):
+    """lasso_solve (glasso_solve) on the bfloat16 dictionary with every signal at once
+    (batched path)."""
     import torch
     Dd = dev_matrix(D, "bf16")
     Y = torch.from_numpy(np.ascontiguousarray(np.stack(ys))).cuda().T
-    X, infos = B.solve(Dd, Y, ratios, step_L=L, **kw)
+    X, infos = B.solve(Dd, Y, ratios, step_L=L, group_ptr=group_ptr, **kw)
     return X.cpu().numpy(), infos
 
 
 def test_served_batched_equals_lasso_solve_alone_and_in_the_mix(B):
     dicts = _dicts()
-    reqs = _requests(dicts, 48, 5)
+    reqs = _requests(dicts, 64, 5)
     kw = dict(gap_tol=1e-6, max_iter=20000)
     # mix: four worker slots and 8-signal engines (more bfloat16 requests than slots, so
     # finished signals hand their slots on), everything submitted at once
@@ -98,13 +101,14 @@ def test_served_batched_equals_lasso_solve_alone_and_in_the_mix(B):
         assert im["status"] == 0 and ia["status"] == 0, k
         assert np.array_equal(xm, xa), k
         assert im["iters"] == ia["iters"] and im["gap"] == ia["gap"], k
-    # every bfloat16 request equals the batched lasso_solve of its dictionary's signals
-    for d in (0, 1):
+    # every bfloat16 request equals the batched lasso_solve (glasso_solve) of its
+    # dictionary's signals
+    for d in (0, 1, 4):
         ks = [k for k, (dd, _, _) in enumerate(reqs) if dd == d]
         assert len(ks) > 8
         L = mix[ks[0]][1]["L"]
         X, infos = _direct_batched(B, dicts[d][0], [reqs[k][1] for k in ks],
-                                   [reqs[k][2] for k in ks], L, **kw)
+                                   [reqs[k][2] for k in ks], L, group_ptr=dicts[d][2], **kw)
         for j, k in enumerate(ks):
             assert np.array_equal(mix[k][0], X[:, j]), (d, k)
             assert mix[k][1]["iters"] == infos[j]["iters"]
