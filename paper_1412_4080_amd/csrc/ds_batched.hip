@@ -60,7 +60,7 @@ BLayout make_layout(int N, int K, int B, int max_iter, int G) {
   l.U0 = take(bp * kp * 4);
   l.U1 = take(bp * kp * 4);
   l.umask = take(nt * bp * 4);
-  l.Ths = take(3 * bp * np * 2);
+  l.Ths = take(THP * bp * np * 2);
   l.th64 = take(bp * np * 8);
   l.ptt = take(static_cast<size_t>(l.nrb) * bp * 8);
   l.pty = take(static_cast<size_t>(l.nrb) * bp * 8);
@@ -277,12 +277,14 @@ BArgs make_args(const BLayout& l, char* base, const ds_params& prm, double L) {
   a.max_iter = prm.max_iter;
   a.screen_static = prm.screening;
   a.L = L;
-  // |z_hat - d^T theta| <= gamma_acc ||d|| ||theta||: FP32 accumulation of the 3 x 64
+  // |z_hat - d^T theta| <= gamma_acc ||d|| ||theta||: FP32 accumulation of the THP x 64
   // exact products of a row chunk (and the MFMA's internal sums) bounded with unit
-  // roundoff 2^-23, the factor 1.02 covering |hi| + |mid| + |lo| <= (1 + 2^-7) |v|; the
-  // FP64 sum of the chunk results; the FP32 rounding of theta
-  const double n = 3.0 * 64 + 32.0, u = 0x1p-23;
-  a.gamma_acc = 1.02 * n * u / (1.0 - n * u) + (l.Np / 64 + 2) * 0x1p-52 + 0x1p-23;
+  // roundoff 2^-23, the factor 1.02 covering the sum of the parts' magnitudes (at most
+  // (1 + 2^-7) |v|); the FP64 sum of the chunk results; the FP32 rounding of theta; with
+  // two parts, the part left out (at most 2^-16 of the FP32 theta, elementwise)
+  const double n = THP * 64.0 + 32.0, u = 0x1p-23;
+  a.gamma_acc = 1.02 * n * u / (1.0 - n * u) + (l.Np / 64 + 2) * 0x1p-52 + 0x1p-23 +
+                (THP == 2 ? 0x1p-16 * (1.0 + 0x1p-20) : 0.0);
   a.gamma64 = 1.01 * (l.Np + 16) * 0x1p-53;
   a.dcm = reinterpret_cast<const uint16_t*>(base + l.dcm);
   a.dsc = reinterpret_cast<const double*>(base + l.dsc);

@@ -9,8 +9,9 @@
 //                       products, so theta is exact up to FP64 rounding;
 //   Z = D^T Theta       dense GEMM on the matrix cores (v_mfma_f32_32x32x16_bf16, FP32
 //                       accumulation) over the 32 x 32 (atom, signal) tiles that hold an
-//                       active pair.  theta enters as three bfloat16 parts (hi + mid + lo
-//                       reproduces its FP32 rounding), so every product is exact;
+//                       active pair.  theta enters as THP bfloat16 parts (hi + mid agrees
+//                       with its FP32 rounding to 2^-16 relative; a third part would make
+//                       it exact), and every product of parts is exact;
 //   the update of Table 1 in the GEMM epilogue (groups: in a pass of its own, one thread
 //   per (group, signal), since a group's norm spans tiles), the FP64 scalars per signal,
 //   and the screening of the pairs whose margin passed the new radius.  A group's margin
@@ -49,14 +50,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return static_cast<uint16_t>((u + 0x7fffu + lsb) >> 16);
 }
 __device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
-// Three-part split v = hi + mid + lo, exact for normal FP32 values: each remainder is
-// a multiple of ulp(v) and needs at most 8 significant bits by the third part.
-__device__ __forceinline__ void split3(float v, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
-  hi = f32_to_bf16(v);
-  const float r1 = v - bf16f(hi);
-  mid = f32_to_bf16(r1);
-  const float r2 = r1 - bf16f(mid);
-  lo = f32_to_bf16(r2);
+// Parts of theta that enter the GEMM.  The split v = hi + mid + lo is exact for normal
+// FP32 values (each remainder is a multiple of ulp(v) and needs at most 8 significant bits
+// by the third part); with two parts |v - hi - mid| <= 2^-8 |v - hi| <= 2^-16 |v| (round to
+// nearest in 8-bit precision, twice), a term the correlation slack carries.  Two parts
+// cost two thirds of the matrix-core work and of the LDS traffic of three.
+constexpr int THP = 2;
+__device__ __forceinline__ void split_parts(float v, uint16_t (&part)[THP]) {
+  float r = v;
+#pragma unroll
+  for (int k = 0; k < THP; ++k) {
+    part[k] = f32_to_bf16(r);
+    r -= bf16f(part[k]);
+  }
 }
 
 // done: 0 running, 2 finished in the iteration in flight, 1 finished earlier.
@@ -88,7 +94,7 @@ struct BArgs {
   float* U0;            // Bp x Kp: u_{t-1} on odd t
   float* U1;            // Bp x Kp: u_{t-1} on even t
   uint32_t* umask;      // (Kp/32) x Bp non-zero bits of u_t per 32-atom tile
-  uint16_t* Ths;        // 3 x Bp x Np bfloat16 parts of theta
+  uint16_t* Ths;        // THP x Bp x Np bfloat16 parts of theta
   double* th64;         // Bp x Np theta in FP64
   double* ptt;          // nrb x Bp partial ||theta||^2
   double* pty;          // nrb x Bp partial theta^T y
@@ -633,11 +639,10 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
     const double yv = a.Y[o];
     const double th = n < a.N ? v - yv : 0.0;
     a.th64[o] = th;
-    uint16_t h, mm, l;
-    split3(static_cast<float>(th), h, mm, l);
-    a.Ths[o] = h;
-    a.Ths[plane + o] = mm;
-    a.Ths[2 * plane + o] = l;
+    uint16_t part[THP];
+    split_parts(static_cast<float>(th), part);
+#pragma unroll
+    for (int k = 0; k < THP; ++k) a.Ths[k * plane + o] = part[k];
     tt = fma(th, th, tt);
     ty = fma(th, yv, ty);
   }
@@ -656,13 +661,13 @@ constexpr int ZP = ZR + 8;   // padded LDS row (144 bytes: fragment reads free o
 // (atoms x signals), each computing WA x WB output tiles of 32 atoms x 32 signals, so a
 // block covers TA = 32 RA WA atoms and TS = 32 RB WB signals.  Every 32 x 32
 // output tile is accumulated by the same instruction sequence whatever the shape (64-row
-// chunks in order, the three parts of theta, four k steps of 16 per chunk), so the results
+// chunks in order, the parts of theta, four k steps of 16 per chunk), so the results
 // are the same bit for bit; the shape only changes how often each piece of D and Theta is
 // staged (D once per block of signals, Theta once per block of atoms) and the parallelism.
-// The block stages 64-row chunks of its atoms and of the three parts of its signals' theta
+// The block stages 64-row chunks of its atoms and of the parts of its signals' theta
 // through LDS with 16-byte loads while the next chunk is fetched into registers.  Each
 // chunk is accumulated in FP32 on the matrix cores from zero and then added to FP64
-// registers, so an FP32 rounding chain spans 3 x 64 products.  Output tiles without an
+// registers, so an FP32 rounding chain spans THP x 64 products.  Output tiles without an
 // active pair are skipped; a block without any returns at once.
 template <int RA, int RB, int WA, int WB>
 __global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
@@ -670,10 +675,10 @@ __global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* 
   constexpr int NWV = RA * RB, NT = BW * NWV;  // waves and threads of a block
   constexpr int TA = MT * RA * WA, TS = MT * RB * WB;
   constexpr int PA = TA * 8 / NT;       // 16-byte pieces of a D chunk per thread
-  constexpr int PB = 3 * TS * 8 / NT;   // 16-byte pieces of a Theta chunk per thread
-  static_assert(PA * NT == TA * 8 && PB * NT == 3 * TS * 8, "pieces tile the block");
+  constexpr int PB = THP * TS * 8 / NT;   // 16-byte pieces of a Theta chunk per thread
+  static_assert(PA * NT == TA * 8 && PB * NT == THP * TS * 8, "pieces tile the block");
   __shared__ __align__(16) uint16_t sA[TA][ZP];     // TA atoms x 64 rows
-  __shared__ __align__(16) uint16_t sB[3][TS][ZP];  // 3 parts x TS signals x 64 rows
+  __shared__ __align__(16) uint16_t sB[THP][TS][ZP];  // THP parts x TS signals x 64 rows
   __shared__ int s_on[NWV];
   const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
   const int64_t gw = (static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x) * NWV + wave;
@@ -735,7 +740,7 @@ __global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* 
       pa[r] = ldg16(a.dcm + static_cast<int64_t>(a0b + e / 8) * a.Np + n0 + (e % 8) * 8);
     }
 #pragma unroll
-    for (int r = 0; r < PB; ++r) {  // 3 x TS rows x 128 bytes of theta
+    for (int r = 0; r < PB; ++r) {  // THP x TS rows x 128 bytes of theta
       const int e = threadIdx.x + r * NT;
       pb[r] = ldg16(a.Ths + (e / (TS * 8)) * plane +
                     static_cast<int64_t>(b0b + (e % (TS * 8)) / 8) * a.Np + n0 + (e % 8) * 8);
@@ -769,25 +774,25 @@ __global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* 
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s16 = 0; s16 < ZR; s16 += 16) {
-        bf16x8 ad[WA], h[WB], m[WB], l[WB];
+        bf16x8 ad[WA], bp[THP][WB];
 #pragma unroll
         for (int ia = 0; ia < WA; ++ia)
           ad[ia] = as_bf16x8(*reinterpret_cast<const uint4*>(&sA[wal + MT * ia + lane % MT][s16 + kk]));
 #pragma unroll
         for (int ib = 0; ib < WB; ++ib) {
           const int sr = wbl + MT * ib + lane % MT;
-          h[ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[0][sr][s16 + kk]));
-          m[ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[1][sr][s16 + kk]));
-          l[ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[2][sr][s16 + kk]));
+#pragma unroll
+          for (int k = 0; k < THP; ++k)
+            bp[k][ib] = as_bf16x8(*reinterpret_cast<const uint4*>(&sB[k][sr][s16 + kk]));
         }
 #pragma unroll
         for (int ia = 0; ia < WA; ++ia)
 #pragma unroll
           for (int ib = 0; ib < WB; ++ib) {
             if (!sub_on[ia][ib]) continue;
-            c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], h[ib], c[ia][ib], 0, 0, 0);
-            c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], m[ib], c[ia][ib], 0, 0, 0);
-            c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], l[ib], c[ia][ib], 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < THP; ++k)
+              c[ia][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ad[ia], bp[k][ib], c[ia][ib], 0, 0, 0);
           }
       }
       __builtin_amdgcn_s_setprio(0);
