@@ -670,7 +670,7 @@ constexpr int ZP = ZR + 8;   // padded LDS row (144 bytes: fragment reads free o
 // registers, so an FP32 rounding chain spans THP x 64 products.  Output tiles without an
 // active pair are skipped; a block without any returns at once.
 template <int RA, int RB, int WA, int WB>
-__global__ __launch_bounds__(BW * RA * RB) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
+__global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA * WB > 1 ? 2 : 1))) void k_b_zgemm(BArgs a, const float* __restrict__ Uin,
                                                           float* __restrict__ Uout) {
   constexpr int NWV = RA * RB, NT = BW * NWV;  // waves and threads of a block
   constexpr int TA = MT * RA * WA, TS = MT * RB * WB;
