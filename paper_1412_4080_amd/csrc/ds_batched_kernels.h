@@ -656,6 +656,7 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
 
 constexpr int ZR = 64;       // rows of D and Theta staged in LDS per step
 constexpr int ZP = ZR + 8;   // padded LDS row (144 bytes: fragment reads free of bank conflicts)
+constexpr int RP = ZR / 8;   // 16-byte pieces of a staged row
 
 // Z = D^T Theta with the update of Table 1 in the epilogue.  Block shapes: RA x RB waves
 // (atoms x signals), each computing WA x WB output tiles of 32 atoms x 32 signals, so a
@@ -674,9 +675,9 @@ __global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA
                                                           float* __restrict__ Uout) {
   constexpr int NWV = RA * RB, NT = BW * NWV;  // waves and threads of a block
   constexpr int TA = MT * RA * WA, TS = MT * RB * WB;
-  constexpr int PA = TA * 8 / NT;       // 16-byte pieces of a D chunk per thread
-  constexpr int PB = THP * TS * 8 / NT;   // 16-byte pieces of a Theta chunk per thread
-  static_assert(PA * NT == TA * 8 && PB * NT == THP * TS * 8, "pieces tile the block");
+  constexpr int PA = TA * RP / NT;       // 16-byte pieces of a D chunk per thread
+  constexpr int PB = THP * TS * RP / NT;   // 16-byte pieces of a Theta chunk per thread
+  static_assert(PA * NT == TA * RP && PB * NT == THP * TS * RP, "pieces tile the block");
   __shared__ __align__(16) uint16_t sA[TA][ZP];     // TA atoms x 64 rows
   __shared__ __align__(16) uint16_t sB[THP][TS][ZP];  // THP parts x TS signals x 64 rows
   __shared__ int s_on[NWV];
@@ -737,13 +738,13 @@ __global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA
 #pragma unroll
     for (int r = 0; r < PA; ++r) {  // TA rows x 128 bytes of D
       const int e = threadIdx.x + r * NT;
-      pa[r] = ldg16(a.dcm + static_cast<int64_t>(a0b + e / 8) * a.Np + n0 + (e % 8) * 8);
+      pa[r] = ldg16(a.dcm + static_cast<int64_t>(a0b + e / RP) * a.Np + n0 + (e % RP) * 8);
     }
 #pragma unroll
     for (int r = 0; r < PB; ++r) {  // THP x TS rows x 128 bytes of theta
       const int e = threadIdx.x + r * NT;
-      pb[r] = ldg16(a.Ths + (e / (TS * 8)) * plane +
-                    static_cast<int64_t>(b0b + (e % (TS * 8)) / 8) * a.Np + n0 + (e % 8) * 8);
+      pb[r] = ldg16(a.Ths + (e / (TS * RP)) * plane +
+                    static_cast<int64_t>(b0b + (e % (TS * RP)) / RP) * a.Np + n0 + (e % RP) * 8);
     }
   };
   fetch(0);
@@ -752,12 +753,12 @@ __global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA
 #pragma unroll
     for (int r = 0; r < PA; ++r) {
       const int e = threadIdx.x + r * NT;
-      *reinterpret_cast<uint4*>(&sA[e / 8][(e % 8) * 8]) = pa[r];
+      *reinterpret_cast<uint4*>(&sA[e / RP][(e % RP) * 8]) = pa[r];
     }
 #pragma unroll
     for (int r = 0; r < PB; ++r) {
       const int e = threadIdx.x + r * NT;
-      *reinterpret_cast<uint4*>(&sB[e / (TS * 8)][(e % (TS * 8)) / 8][(e % 8) * 8]) = pb[r];
+      *reinterpret_cast<uint4*>(&sB[e / (TS * RP)][(e % (TS * RP)) / RP][(e % RP) * 8]) = pb[r];
     }
     __syncthreads();
     if (n0 + ZR < a.Np) fetch(n0 + ZR);
