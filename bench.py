@@ -339,7 +339,10 @@ def single_roofline(binding, Dd, ys, L):
     run_steps(binding, Dd, ys[:INSTR_SIGNALS], INSTR_SIGNALS, "dst3", L)
     binding.stats_enable(False)
     st = binding.stats_read()[binding.STAT_CORR]
-    recs = binding.stats_launches()
+    allrecs = binding.stats_launches()
+    recs = [r for r in allrecs if r["kernel"] == binding.STAT_CORR]
+    rres = [r for r in allrecs if r["kernel"] == binding.STAT_RESID]
+    rit = [r for r in allrecs if r["kernel"] == binding.STAT_ITER]
     avg_ms = st["ms"] / max(st["launches"], 1)
     ev_ms = st["ms_event"] / max(st["launches"], 1)
     bytes_per = st["bytes"] / max(st["launches"], 1)
@@ -350,9 +353,17 @@ def single_roofline(binding, Dd, ys, L):
         if sel:
             b = sum(r["bytes"] for r in sel)
             t = sum(r["ms"] for r in sel) * 1e-3
-            buckets.append({"active_atoms": [lo, hi - 1], "launches": len(sel),
-                            "avg_launch_us": round(t / len(sel) * 1e6, 3),
-                            "achieved": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)})
+            row = {"active_atoms": [lo, hi - 1], "launches": len(sel),
+                   "avg_launch_us": round(t / len(sel) * 1e6, 3),
+                   "achieved": round(b / t / 1e9, 1), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+            # the iteration: the correlation and the residual pass after it (HIP event times
+            # of the two dispatches, which include the dispatch overhead)
+            sr = [r["ms"] for r in rres if lo <= r["n_atoms"] < hi]
+            si = [r["ms"] for r in rit if lo <= r["n_atoms"] < hi]
+            if sr and si:
+                row["resid_event_us"] = round(float(np.mean(sr)) * 1e3, 3)
+                row["iteration_event_us"] = round(float(np.mean(si)) * 1e3, 3)
+            buckets.append(row)
     out = {"bound": "hbm", "kernel": "k_corr_lasso",
            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

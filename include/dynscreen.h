@@ -321,17 +321,21 @@ typedef struct {
 
 /* CORR: single-signal correlation pass; RESID: single-signal residual pass; SETUP:
  * setup passes; BATCH: batched Z = D^T Theta GEMM with the fused update; BATCH_THETA:
- * batched Theta = D U GEMM. */
+ * batched Theta = D U GEMM; ITER: one single-signal iteration (its correlation and the
+ * residual pass after it). */
 enum { DS_STAT_CORR = 0, DS_STAT_RESID = 1, DS_STAT_SETUP = 2, DS_STAT_BATCH = 3,
-       DS_STAT_BATCH_THETA = 4, DS_STAT_COUNT = 5 };
+       DS_STAT_BATCH_THETA = 4, DS_STAT_ITER = 5, DS_STAT_COUNT = 6 };
 
-/* One launch of the single-signal correlation pass (DS_STAT_CORR) as accounted by the
- * statistics: the active atoms it streamed, its algorithmic bytes and its execution time
- * (device wall clock, as ds_kernel_stat.ms). */
+/* One launch record of an instrumented single-signal solve: DS_STAT_CORR (a correlation
+ * pass: its execution time on the device wall clock, as ds_kernel_stat.ms, and its
+ * algorithmic bytes), DS_STAT_RESID (the residual pass after it: time between the HIP
+ * events of its dispatch, bytes of the support columns it streams) or DS_STAT_ITER (the
+ * two together: the sum of their event times).  n_atoms is the correlation's active atoms
+ * |I^c_t| in all three. */
 typedef struct {
-  int32_t kernel;     /* DS_STAT_CORR */
-  int32_t n_atoms;    /* active atoms |I^c_t| of the launch */
-  double bytes;       /* algorithmic bytes */
+  int32_t kernel;     /* DS_STAT_CORR, DS_STAT_RESID or DS_STAT_ITER */
+  int32_t n_atoms;    /* active atoms |I^c_t| of the iteration */
+  double bytes;       /* algorithmic bytes (0 for DS_STAT_ITER) */
   double ms;          /* execution time */
 } ds_launch_stat;
 
@@ -341,8 +345,9 @@ void ds_stats_enable(int on);
 void ds_stats_reset(void);
 /* Copies min(n, DS_STAT_COUNT) counters into out; returns the number copied. */
 int ds_stats_read(ds_kernel_stat* out, int n);
-/* Copies up to n per-launch records of the correlation pass accounted since the last
- * ds_stats_reset (the first 2^20 are kept, in launch order); returns the number copied. */
+/* Copies up to n per-launch records (correlation, residual, iteration) accounted since the
+ * last ds_stats_reset (the first 2^20 are kept, in launch order); returns the number
+ * copied. */
 int ds_stats_launches(ds_launch_stat* out, int n);
 
 /* Block shape of the batched path's Z = D^T Theta kernel in the last batched solve on the

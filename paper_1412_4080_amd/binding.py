@@ -27,7 +27,7 @@ TESTS = {"none": 0, "safe": 1, "dst3": 2, "gsafe": 1, "dgst3": 2, "dome": 3}
 STATUS_NAMES = {0: "DS_OK", 1: "DS_PENDING", 2: "DS_NOT_CONVERGED", -1: "DS_EINVAL",
                 -2: "DS_ENOMEM", -3: "DS_EDEVICE", -4: "DS_ENOTFOUND", -5: "DS_EBUSY"}
 STEPS = {"constant": 0, "backtracking": 1}
-STAT_CORR, STAT_RESID, STAT_SETUP, STAT_BATCH, STAT_BATCH_THETA, STAT_COUNT = 0, 1, 2, 3, 4, 5
+STAT_CORR, STAT_RESID, STAT_SETUP, STAT_BATCH, STAT_BATCH_THETA, STAT_ITER, STAT_COUNT = 0, 1, 2, 3, 4, 5, 6
 
 
 class Problem(C.Structure):
@@ -361,10 +361,11 @@ def stats_read():
 
 
 def stats_launches(cap=1 << 20):
-    """Per-launch records (n_atoms, bytes, ms) of the correlation pass since the last reset."""
+    """Per-launch records (kernel: STAT_CORR / STAT_RESID / STAT_ITER, n_atoms, bytes, ms) of
+    the instrumented single-signal solves since the last reset."""
     arr = (LaunchStat * cap)()
     n = _lib.ds_stats_launches(arr, cap)
-    return [dict(n_atoms=a.n_atoms, bytes=a.bytes, ms=a.ms) for a in arr[:n]]
+    return [dict(kernel=a.kernel, n_atoms=a.n_atoms, bytes=a.bytes, ms=a.ms) for a in arr[:n]]
 
 
 # ------------------------------------------------------------------ serving

@@ -389,15 +389,21 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     return p;
   };
   // g: the grid of the correlation launch whose outputs the pass reads
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evr;  // instrumented residual passes
   auto launch_resid = [&](int par, int g) {
     a.par = par;
     a.grid_corr = g;
     a.nsg_prev = nsg_of(grid_res_read);
     grid_res_read = g;
+    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+    if (stat_on) e = get_events();
     if (P.G > 0)
-      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, true>), dim3(res_grid(g)), dim3(BLK), 0, s, a);
+      hipExtLaunchKernelGGL((k_resid<T, V, VEC, RULE, true>), dim3(res_grid(g)), dim3(BLK), 0, s,
+                            e.first, e.second, 0, a);
     else
-      hipLaunchKernelGGL((k_resid<T, V, VEC, RULE, false>), dim3(res_grid(g)), dim3(BLK), 0, s, a);
+      hipExtLaunchKernelGGL((k_resid<T, V, VEC, RULE, false>), dim3(res_grid(g)), dim3(BLK), 0, s,
+                            e.first, e.second, 0, a);
+    if (stat_on && e.first) evr.push_back(e);
   };
   auto launch_dcheck = [&](int par, int g) {
     a.par = par;
@@ -504,6 +510,10 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
     int rate_khz = 0;
     DS_HIP(hipMemcpy(ticks.data(), spans, used * sizeof(uint64_t), hipMemcpyDeviceToHost));
     DS_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ws.device));
+    // residual pass k + 1 follows correlation pass k (pass 0 forms theta_1 = -y); it
+    // streams the support of the new primal point, recorded with iteration k + 1
+    double r_ms = 0.0, r_bytes = 0.0;
+    int64_t r_n = 0;
     for (size_t k = 0; k < used; ++k) {
       float f = 0.f;
       if (hipEventElapsedTime(&f, ev[k].first, ev[k].second) == hipSuccess) ms_ev += f;
@@ -514,10 +524,24 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
       bytes += bk;
       flops += 2.0 * na * P.N;
       recs[k] = ds_launch_stat{DS_STAT_CORR, tl[k].n_atoms, bk, mk};
+      float fr = 0.f;
+      if (k + 1 < evr.size() &&
+          hipEventElapsedTime(&fr, evr[k + 1].first, evr[k + 1].second) == hipSuccess) {
+        const double ns = k + 1 < tl.size() ? tl[k + 1].n_support : 0.0;
+        const double rb = ns * P.N * sizeof(T) + 2.0 * P.N * sizeof(V);
+        recs.push_back(ds_launch_stat{DS_STAT_RESID, tl[k].n_atoms, rb, fr});
+        recs.push_back(ds_launch_stat{DS_STAT_ITER, tl[k].n_atoms, 0.0, f + fr});
+        r_ms += fr;
+        r_bytes += rb;
+        ++r_n;
+      }
     }
     std::lock_guard<std::mutex> g(S.mu);
     for (const ds_launch_stat& r : recs)
       if (S.launches.size() < StatAccum::MAX_LAUNCHES) S.launches.push_back(r);
+    S.s[DS_STAT_RESID].launches += r_n;
+    S.s[DS_STAT_RESID].ms_event += r_ms;
+    S.s[DS_STAT_RESID].bytes += r_bytes;
     S.s[DS_STAT_CORR].launches += static_cast<int64_t>(used);
     S.s[DS_STAT_CORR].ms += ms;
     S.s[DS_STAT_CORR].ms_event += ms_ev;

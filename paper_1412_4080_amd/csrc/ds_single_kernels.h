@@ -832,10 +832,13 @@ __device__ inline IterScalars iter_scalars(const SolverState& s, int N, int test
 // Row tile rt of the residual: r = D p - y from the items' partials.  theta = r, except for
 // Chambolle-Pock (CP), where the dual iterate is carried: theta = (theta_prev + sigma r) /
 // (1 + sigma) (theta_prev = 0 at the first pass) and ||r||^2 is published for the primal
-// objective.  Publishes ||theta||^2 and theta^T y per row tile.
+// objective.  Publishes ||theta||^2 and theta^T y per row tile.  With `rows` (a single
+// item per row tile) the item's row sums are read from its LDS wave sums (NW x RT, summed
+// in wave order as the item would have published them) instead of the published partials.
 template <typename T, typename V, bool VECTOR, bool CP = false>
 __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitems_rt,
-                                  double* sd, double sigma = 0.0, bool first = false) {
+                                  double* sd, double sigma = 0.0, bool first = false,
+                                  const double* rows = nullptr) {
   constexpr int VR = VECTOR ? Store<T>::VEC : 1;
   constexpr int RT = WAVE * VR;
   constexpr int FB = 32;  // item partials loaded at once
@@ -846,13 +849,21 @@ __device__ void resid_finish_tile(SingleArgs<T, V, double>& a, int rt, int nitem
     // item partials in item order, FB loads in flight (unconditional loads at clamped
     // indices: a guarded load would wait for its value before the next one is issued)
     double s = 0.0;
-    for (int c = 0; c < nitems_rt; c += FB) {
-      double v[FB];
+    if (rows != nullptr) {
+      const int rr = r - rt * RT;
+      double v = rows[rr];
 #pragma unroll
-      for (int k = 0; k < FB; ++k)
-        v[k] = consume(&a.partial[static_cast<int64_t>(min(c + k, nitems_rt - 1)) * a.npad + r]);
+      for (int w = 1; w < NW; ++w) v += rows[w * RT + rr];
+      s += v;
+    } else {
+      for (int c = 0; c < nitems_rt; c += FB) {
+        double v[FB];
 #pragma unroll
-      for (int k = 0; k < FB; ++k) s += c + k < nitems_rt ? v[k] : 0.0;
+        for (int k = 0; k < FB; ++k)
+          v[k] = consume(&a.partial[static_cast<int64_t>(min(c + k, nitems_rt - 1)) * a.npad + r]);
+#pragma unroll
+        for (int k = 0; k < FB; ++k) s += c + k < nitems_rt ? v[k] : 0.0;
+      }
     }
     double res = s - yv;
     if constexpr (CP) {
@@ -1331,6 +1342,14 @@ __global__ __launch_bounds__(BLK) void k_resid(SingleArgs<T, V, double> a) {
 #pragma unroll
     for (int e = 0; e < VR; ++e) red[wave][lane * VR + e] = acc[e];
     __syncthreads();
+    if (nsg == 1) {
+      // one segment group (a short active list): the item holds its row tile's whole sum
+      // and finishes the tile itself, without the publication and arrival round trips
+      resid_finish_tile<T, V, VECTOR, RULE == RULE_CP>(a, rt, 1, sd, S.cp_sigma, S.iter == 0,
+                                                       &red[0][0]);
+      __syncthreads();
+      continue;
+    }
     for (int rr = tid; rr < RT; rr += BLK) {
       const int r = rt * RT + rr;
       if (r < a.N) {

@@ -391,6 +391,36 @@ def test_batched_call_matches_single(B):
         assert infos[j]["iters"] == i1["iters"]
 
 
+def test_instrumented_launch_records(B):
+    """An instrumented solve records, per iteration, its correlation pass (active atoms,
+    algorithmic bytes, device-clock time), the residual pass after it and the iteration as a
+    whole, in launch order; the counters agree with the records."""
+    D, y = _lasso_case(300, 1500, 41)
+    Di, yi = instance(D, y, "f32")
+    L = oracle.spectral_norm_sq(Di)
+    B.stats_reset()
+    B.stats_enable(True)
+    try:
+        _, info, _, tr = B.solve_one(dev_matrix(D, "f32"), dev_vector(yi, "f32"), 0.5, step_L=L,
+                                     gap_tol=1e-6, max_iter=2000)
+    finally:
+        B.stats_enable(False)
+    recs = B.stats_launches()
+    st = B.stats_read()
+    T = info["iters"]
+    corr = [r for r in recs if r["kernel"] == B.STAT_CORR]
+    res = [r for r in recs if r["kernel"] == B.STAT_RESID]
+    it = [r for r in recs if r["kernel"] == B.STAT_ITER]
+    assert len(corr) == len(res) == len(it) == T == st[B.STAT_CORR]["launches"] == st[B.STAT_RESID]["launches"]
+    assert [r["n_atoms"] for r in corr] == [t["n_active"] for t in tr]
+    assert [r["n_atoms"] for r in res] == [r["n_atoms"] for r in corr] == [r["n_atoms"] for r in it]
+    assert all(r["ms"] > 0 for r in corr + res + it)
+    assert all(i["ms"] >= r["ms"] for i, r in zip(it, res))
+    assert all(r["bytes"] >= 2 * 300 * 4 for r in res)
+    assert sum(r["bytes"] for r in corr) == pytest.approx(st[B.STAT_CORR]["bytes"], rel=1e-12)
+    B.stats_reset()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_concurrent_columns_match_single_solves(B, dtype):
     """lasso_solve with more columns than solve lanes (9 signals, lambdas out of order, one
