@@ -192,3 +192,28 @@ def test_served_batched_failed_slot_and_bad_observation(B):
     assert isinstance(got[6], B.DsError) and got[6].status == B.DS_EINVAL
     for k in (0, 1, 2, 4, 5, 7, 8, 9):
         assert np.array_equal(got[k][0], ref[k][0]) and got[k][1]["iters"] == ref[k][1]["iters"]
+
+
+def test_engine_that_cannot_fit_the_budget_leaves_requests_to_the_workers(B):
+    """With a budget below the batched engine's footprint (256 resident signals) but above a
+    single solve's, requests for a bfloat16 dictionary run on the single-signal workers:
+    their results equal ds_solve_one on the same stored dictionary."""
+    import torch
+    D = datagen.gaussian_dictionary(512, 3000, 38)
+    ys = [datagen.to_storage(datagen.lasso_signal(D, 950 + k)[0], "f32").astype(np.float32)
+          for k in range(4)]
+    S = B.Server(max_slots=2, batch_slots=256, hbm_budget_bytes=32 << 20)
+    did = S.add_dict(dev_matrix(D, "f32"), store="bf16")
+    torch.cuda.synchronize()
+    pend = {k: (S.submit(did, ys[k], 0.3 + 0.1 * k, gap_tol=1e-6, max_iter=20000), 0)
+            for k in range(len(ys))}
+    got = _wait(S, pend, [did])
+    S.close()
+    Dd = dev_matrix(D, "bf16")
+    for k in range(len(ys)):
+        assert got[k][1]["status"] == 0
+        x1, i1, _, _ = B.solve_one(Dd, torch.from_numpy(ys[k]).cuda(), 0.3 + 0.1 * k,
+                                   step_L=got[k][1]["L"], gap_tol=1e-6, max_iter=20000,
+                                   trace=False, screened=False)
+        assert np.array_equal(got[k][0], x1.cpu().numpy()), k
+        assert got[k][1]["iters"] == i1["iters"]
