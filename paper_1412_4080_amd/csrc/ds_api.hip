@@ -287,27 +287,37 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   }
   std::vector<ds_status> st(nl, DS_OK);
   std::vector<std::string> msg(nl);
-  std::vector<std::thread> th;
-  for (int k = 0; k < nl; ++k) {
-    th.emplace_back([&, k] {
-      if (hipSetDevice(dev) != hipSuccess) {
-        st[k] = DS_EDEVICE;
-        msg[k] = "hipSetDevice failed in a solve lane";
+  auto lane = [&](int k) {
+    if (hipSetDevice(dev) != hipSuccess) {
+      st[k] = DS_EDEVICE;
+      msg[k] = "hipSetDevice failed in a solve lane";
+      return;
+    }
+    SolveLane& ln = ctx.lanes[k];
+    for (int64_t q = next++; q < B; q = next++) {
+      const ds_status r = one(order[q], ln.stream, ln.ws);
+      if (r < 0) {
+        st[k] = r;
+        msg[k] = ds_last_error();
+        next = B;  // the other lanes start no further signal
         return;
       }
-      SolveLane& ln = ctx.lanes[k];
-      for (int64_t q = next++; q < B; q = next++) {
-        const ds_status r = one(order[q], ln.stream, ln.ws);
-        if (r < 0) {
-          st[k] = r;
-          msg[k] = ds_last_error();
-          next = B;  // the other lanes start no further signal
-          return;
-        }
-        if (r == DS_NOT_CONVERGED) st[k] = DS_NOT_CONVERGED;
-      }
-    });
+      if (r == DS_NOT_CONVERGED) st[k] = DS_NOT_CONVERGED;
+    }
+  };
+  // lanes 1 .. nl - 1 on threads of their own, lane 0 on the caller's thread; a lane whose
+  // thread cannot be started runs on the caller's thread after lane 0 (no exception
+  // crosses the boundary)
+  std::vector<std::thread> th;
+  std::vector<int> inline_lanes{0};
+  for (int k = 1; k < nl; ++k) {
+    try {
+      th.emplace_back(lane, k);
+    } catch (...) {
+      inline_lanes.push_back(k);
+    }
   }
+  for (int k : inline_lanes) lane(k);
   for (auto& t : th) t.join();
   (void)hipEventDestroy(ready);
   ds_status worst = DS_OK;

@@ -573,7 +573,22 @@ ds_status ds_server_create(const ds_server_config* config, void** server) {
   for (auto& w : S->workers) {
     Worker* wp = w.get();
     Server* sp = S.get();
-    w->th = std::thread([sp, wp] { sp->worker_loop(wp); });
+    try {
+      w->th = std::thread([sp, wp] { sp->worker_loop(wp); });
+    } catch (...) {  // stop the workers already running; no exception crosses the boundary
+      {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+      }
+      S->cv_work.notify_all();
+      for (auto& v : S->workers) {
+        if (v->th.joinable()) v->th.join();
+        if (v->stream != nullptr) (void)hipStreamDestroy(v->stream);
+      }
+      (void)hipStreamDestroy(S->admin);
+      set_error("could not start the server's worker threads");
+      return DS_EDEVICE;
+    }
   }
   *server = S.release();
   return DS_OK;
@@ -669,7 +684,11 @@ ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype s
     b->dict = *dict_id;
     BatchLane* bp = b.get();
     Server* sp = S;
-    b->th = std::thread([sp, bp] { sp->lane_loop(bp); });
+    try {
+      b->th = std::thread([sp, bp] { sp->lane_loop(bp); });
+    } catch (...) {  // no engine: the dictionary's requests run on the workers
+      return DS_OK;
+    }
     S->lanes.emplace(*dict_id, std::move(b));
   }
   return DS_OK;
