@@ -71,8 +71,8 @@ typedef enum { DS_ISTA = 0, DS_FISTA = 1, DS_SPARSA = 2, DS_CP = 3 } ds_rule;
 /* Screening test.  For Group-Lasso problems SAFE means GSAFE (Lemma 4) and DST3 means
  * DGST3 (Lemma 5).  DS_TEST_DOME is the dynamic Dome test (the dome lemma: the SAFE ball
  * B(y/lambda, ||y/lambda - v_t||) cut by the half-space d_*^T theta <= 1 of the atom
- * attaining lambda_*); Lasso only (glasso_solve and the batched bfloat16 path return
- * DS_EINVAL).  DS_TEST_NONE runs the plain, unscreened algorithm. */
+ * attaining lambda_*); Lasso only (glasso_solve returns DS_EINVAL).  DS_TEST_NONE runs the
+ * plain, unscreened algorithm. */
 typedef enum { DS_TEST_NONE = 0, DS_TEST_SAFE = 1, DS_TEST_DST3 = 2, DS_TEST_DOME = 3 } ds_test;
 
 /* How `lambdas` is read: absolute penalties, or ratios lambda / lambda_* where
@@ -264,7 +264,7 @@ ds_status ds_spectral_norm_sq(const ds_problem* problem, int32_t iters, double* 
  * With batch_slots > 0, every bfloat16 dictionary also gets a batched engine (the
  * matrix-core path of lasso_solve / glasso_solve): a request for it whose parameters that
  * path supports
- * (ISTA or FISTA, constant step, SAFE / DST3 / no test, no x0, obj_tol = 0) joins the
+ * (ISTA or FISTA, constant step, SAFE / DST3 / Dome / no test, no x0, obj_tol = 0) joins the
  * engine's resident signals at the next graph-replay boundary where a slot is free, and
  * leaves as soon as it has finished; requests with the same parameters share a run.  Its
  * result equals the batched result of lasso_solve (glasso_solve) for the same y and lambda

@@ -238,10 +238,6 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   if (B > 1 && problem->dtype == DS_BF16) {
-    if (params->test == DS_TEST_DOME) {
-      set_error("the Dome test is available on the single-signal path (B = 1 or FP32/FP64 D)");
-      return DS_EINVAL;
-    }
     if (params->step_rule == DS_STEP_BACKTRACK || params->rule == DS_SPARSA ||
         params->rule == DS_CP) {
       set_error("backtracking, SpaRSA and Chambolle-Pock are available on the single-signal path (B = 1 or FP32/FP64 D)");

@@ -497,7 +497,7 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
     } else {
       hipLaunchKernelGGL(k_b_inst_init, dim3(n), dim3(TB), 0, s, a, z0, d_lam, lrel, prm.gap_tol,
                          Vn, static_cast<const int*>(d_perm), static_cast<const int*>(d_list));
-      if (prm.test == DS_TEST_DST3) dtv(static_cast<const float*>(Vn), gn);
+      if (prm.test == DS_TEST_DST3 || prm.test == DS_TEST_DOME) dtv(static_cast<const float*>(Vn), gn);
       hipLaunchKernelGGL(k_b_margins, dim3((l.Kp + TB - 1) / TB, n), dim3(TB), 0, s, a, z0, gn,
                          reinterpret_cast<float*>(base + l.marg), static_cast<const int*>(d_perm),
                          static_cast<const int*>(d_list));

@@ -1,5 +1,6 @@
 // Batched path: B signals sharing one bfloat16 dictionary, Algorithm 3 with the ISTA /
-// FISTA update of Table 1 and the SAFE / DST3 sphere tests (Lemmas 1, 2), or for the
+// FISTA update of Table 1 and the SAFE / DST3 sphere tests (Lemmas 1, 2) or the dynamic
+// Dome test, or for the
 // Group-Lasso the group soft thresholding and the GSAFE / DGST3 tests (Lemmas 4, 5).
 // Every signal keeps its own penalty, dual point, radius and active set.
 //
@@ -67,7 +68,7 @@ __device__ __forceinline__ void split_parts(float v, uint16_t (&part)[THP]) {
 
 // done: 0 running, 2 finished in the iteration in flight, 1 finished earlier.
 struct alignas(16) Inst {
-  double lam, lam_max, yy, rho2, alpha, nn, marg_slack, gap_tol_abs;
+  double lam, lam_max, yy, rho2, alpha, nn, ny, marg_slack, gap_tol_abs;
   double tt, ty, omega, zmax, mu, gap, primal, dual;
   double r_min, r_scr, r_keep, r_prev, r_slack, l_prev;
   double act_sum, sup_sum;  // sums over iterations of |A_t| and |S_t| (work accounting)
@@ -306,12 +307,14 @@ __global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __res
   if (!(arg >= 0 && arg < a.K) || !isfinite(lam_max)) bad = 1;
   const double lam = lam_relative ? lam_in[s] * lam_max : lam_in[s];
   const bool trivial = !(lam < lam_max);
-  const bool dst3 = a.test == 2 && !trivial && !bad;
+  // the hyperplane n = sign(z0_i*) d_i* of DST3, and of the Dome test's half-space
+  const bool hyp = (a.test == 2 || a.test == 3) && !trivial && !bad;
+  const bool dst3 = a.test == 2 && hyp;
   const double sgn = (!bad && z[arg] < 0.0) ? -1.0 : 1.0;
   double nn = 0.0, ny = 0.0;
   for (int n = tid; n < a.Np; n += TB) {
     float v = 0.f;
-    if (dst3) {
+    if (hyp) {
       v = static_cast<float>(sgn * bf16f(a.dcm[static_cast<int64_t>(arg) * a.Np + n]));
       nn = fma(static_cast<double>(v), static_cast<double>(v), nn);
       ny = fma(static_cast<double>(v), static_cast<double>(y[n]), ny);
@@ -328,6 +331,7 @@ __global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __res
     t.yy = yy;
     t.alpha = alpha;
     t.nn = nn;
+    t.ny = ny;
     t.rho2 = alpha * alpha * nn;
     t.gap_tol_abs = gap_tol * yy;
     t.r_min = 1e300;
@@ -365,6 +369,15 @@ __global__ __launch_bounds__(TB) void k_b_margins(BArgs a, const double* __restr
     m = INFINITY;
   } else if (a.test == 0) {
     m = -INFINITY;
+  } else if (a.test == 3) {
+    // the dynamic Dome test: the largest SAFE radius at which the dome still screens the
+    // atom (a lower bound, covering the rounding of its FP64 inputs)
+    const double nu = a.nu[i], nrm_n = sqrt(st.nn);
+    const double delta = (st.ny / st.lam - 1.0) / nrm_n;
+    const double gam = (a.N + 16) * 0x1p-53;
+    m = nu > 0.0 ? __double2float_rd(dome_margin(z0[o], gn[o], nu, st.lam, nrm_n, delta,
+                                                 sqrt(st.yy) / st.lam, gam))
+                 : INFINITY;
   } else {
     const double nu = a.nu[i];
     const double ci = z0[o] / st.lam - (a.test == 2 ? st.alpha * gn[o] : 0.0);

@@ -230,4 +230,52 @@ __global__ void k_clock_span(const uint64_t* __restrict__ clk, int nblk, uint64_
   }
 }
 
+__device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
+
+// Dynamic Dome test: the largest radius R at which max |d_i^T theta| < 1 over the dome,
+// the ball B(y/lambda, R) cut by the half-space n^T theta <= 1 (n = d_*, signed so that
+// n^T y = lambda_*); the test screens atom i when the SAFE radius is below it.  With
+// nh = n/||n||, the plane lies at distance delta = (n^T y/lambda - 1)/||n|| from the centre
+// and cuts from the ball a disc of centre c' = y/lambda - delta nh and radius
+// sqrt(R^2 - delta^2).  For u = +-d_i, s = u^T nh/||u||: while the ball's own maximiser is
+// outside the half-space (delta + R s > 0) the maximum is u^T c' + sqrt(R^2 - delta^2)
+// ||u - (u^T nh) nh||, else it is the ball's, u^T y/lambda + R ||u|| (the SAFE bound).  The
+// two meet with equal slope at R = delta/(-s), and the threshold solves the branch in force:
+// ra = sqrt(delta^2 + (a / ||u_perp||)^2), a = 1 - u^T c', or the SAFE margin.
+// Returned as a lower bound that covers the FP64 rounding of the inputs (z = d_i^T y,
+// g = d_i^T n, nu = ||d_i||, ||n||, n^T y, each with relative error at most gam, the
+// rounding unit times N + 16): the disc branch is taken only when it is certainly in force
+// at its (upper-bounded) threshold, and then with pessimistic inputs; otherwise the SAFE
+// margin (never above the threshold), whose own rounding the global slack covers.  An
+// atom whose bound can reach 1 at the smallest radius (d_* itself) gets -inf.
+__device__ inline double dome_margin(double z, double g, double nu, double lam, double nrm_n,
+                                     double delta, double ry, double gam) {
+  const double ed = 2.0 * gam * (ry + delta);          // error bound of delta
+  const double d_lo = fmax(delta - ed, 0.0), d_hi = delta + ed;
+  double m = dinf();
+  for (int k = 0; k < 2; ++k) {
+    const double sg = k == 0 ? 1.0 : -1.0;
+    const double un = sg * g / nrm_n;                    // u^T nh
+    const double a = 1.0 - (sg * z / lam - delta * un);  // 1 - u^T c'
+    const double ea = 5.0 * gam * nu * (ry + delta + 1.0);
+    const double rb = (1.0 - sg * z / lam) / nu;         // the SAFE branch
+    double r;
+    if (!(a - ea > 0.0)) {
+      r = -dinf();
+    } else {
+      const double p2 = fma(nu, nu, -un * un), ep2 = 8.0 * gam * nu * nu;
+      const double p_hi = sqrt(fmax(p2, 0.0) + ep2), p_lo = sqrt(fmax(p2 - ep2, 0.0));
+      const double q_lo = (a - ea) / p_hi;
+      const double ra_lo = sqrt(fma(d_lo, d_lo, q_lo * q_lo)) * (1.0 - 0x1p-49);
+      const double q_hi = p_lo > 0.0 ? (a + ea) / p_lo : dinf();
+      const double ra_hi = sqrt(fma(d_hi, d_hi, q_hi * q_hi)) * (1.0 + 0x1p-49);
+      const double s = un / nu;
+      const double rs_lo = d_lo / (fmax(-s, 0.0) + 4.0 * gam);  // switch radius, lower bound
+      r = ra_hi < rs_lo ? ra_lo : rb;
+    }
+    m = fmin(m, r);
+  }
+  return m;
+}
+
 }  // namespace ds

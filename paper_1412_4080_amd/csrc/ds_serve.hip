@@ -117,7 +117,8 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Requests the batched engine can run (the parameters lasso_solve's batched path takes).
 bool batch_eligible(const ds_params& p) {
   return (p.rule == DS_ISTA || p.rule == DS_FISTA) && p.step_rule == DS_STEP_CONSTANT &&
-         (p.test == DS_TEST_NONE || p.test == DS_TEST_SAFE || p.test == DS_TEST_DST3) &&
+         (p.test == DS_TEST_NONE || p.test == DS_TEST_SAFE || p.test == DS_TEST_DST3 ||
+          p.test == DS_TEST_DOME) &&
          p.x0 == nullptr && p.obj_tol == 0.0;
 }
 

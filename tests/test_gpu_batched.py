@@ -51,7 +51,7 @@ def _check_mask(mask, ref, Dbf, y, ratio, test, info, hist):
 
 
 @pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe"), ("fista", "none"),
-                                       ("ista", "dst3")])
+                                       ("ista", "dst3"), ("fista", "dome")])
 def test_batched_fixed_iterations(B, rule, test):
     T = 30
     D, Dbf, ys, ratios = _batch(320, 1500, 12, 3)
@@ -242,3 +242,45 @@ def test_more_signals_than_slots_by_default(B):
                                   L=L, max_iter=200000, gap_tol=1e-13)
         p = oracle.primal_objective(Dbf, y, X[:, j], infos[j]["lambda_"], float(np.abs(X[:, j]).sum()))
         assert p - star.primal <= infos[j]["gap"] + 1e-9
+
+
+def _correlated_case(N, K, seed, nsig, corr=0.8):
+    """Unit atoms sharing a common direction (where the dome's cut removes most), rounded to
+    bfloat16, and unit observations from five atoms each."""
+    rng = np.random.default_rng(seed)
+    D = corr * rng.standard_normal((N, 1)) + rng.standard_normal((N, K))
+    D /= np.linalg.norm(D, axis=0)
+    Dbf = datagen.to_storage(D, "bf16")
+    ys = []
+    for j in range(nsig):
+        y = Dbf[:, rng.choice(K, 5, replace=False)] @ rng.standard_normal(5) + 0.1 * rng.standard_normal(N)
+        ys.append(datagen.to_storage(y / np.linalg.norm(y), "f32"))
+    return D, Dbf, ys
+
+
+def test_batched_dome_is_certified_and_screens_at_least_dst3(B):
+    """The dynamic Dome test on the batched path (correlated atoms): every signal reaches the
+    tolerance with its screened atoms certified inactive at the FP64 optimum, and ends with
+    no more active atoms than the same batch under DST3."""
+    D, Dbf, ys = _correlated_case(300, 1500, 43, 12)
+    ratios = np.linspace(0.3, 0.9, 12)
+    L = oracle.spectral_norm_sq(Dbf)
+    Dd, Y = dev_matrix(D, "bf16"), _dev_Y(ys)
+    kw = dict(rule="fista", step_L=L, gap_tol=1e-6, max_iter=20000, screened=True)
+    X, infos, mask = B.solve(Dd, Y, ratios, test="dome", **kw)
+    _, infos3, mask3 = B.solve(Dd, Y, ratios, test="dst3", **kw)
+    X = X.cpu().numpy().astype(np.float64)
+    mask = mask.cpu().numpy().astype(bool)
+    mask3 = mask3.cpu().numpy().astype(bool)
+    assert mask.sum() >= mask3.sum() > 0
+    for j, (y, r) in enumerate(zip(ys, ratios)):
+        info = infos[j]
+        yy = float(y @ y)
+        assert info["status"] == 0 and info["gap"] <= 1e-6 * yy, (j, info)
+        star = oracle.solve_lasso(Dbf, y, lam=info["lambda_"], rule="fista", test="none", L=L,
+                                  max_iter=200000, gap_tol=1e-13)
+        assert info["primal"] - star.primal <= info["gap"] + 1e-9
+        cert, gstar = oracle.certified_inactive_lasso(Dbf, y, star.lam, star.x)
+        assert gstar < 1e-11
+        assert np.all(cert[mask[:, j]]), np.flatnonzero(mask[:, j] & ~cert)[:10]
+        assert not X[mask[:, j], j].any()

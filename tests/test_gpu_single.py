@@ -154,7 +154,9 @@ def test_dome_follows_the_oracle_and_screens_at_least_dst3(B, ratio):
     assert np.all(na_dome <= na_dst3)
 
 
-def test_dome_refused_for_groups_and_on_the_batched_path(B):
+def test_dome_refused_for_groups(B):
+    """The Dome test is stated for the Lasso: grouped problems are refused, single-signal
+    and batched."""
     import torch
     D = datagen.gaussian_dictionary(256, 1000, 15)
     gp = datagen.contiguous_groups(1000, 10)
@@ -165,7 +167,7 @@ def test_dome_refused_for_groups_and_on_the_batched_path(B):
     Dd = dev_matrix(D, "bf16")
     Y = torch.from_numpy(np.stack([y, y]).astype(np.float32)).cuda().T
     with pytest.raises(B.DsError) as e:
-        B.solve(Dd, Y, [0.5, 0.6], test="dome")
+        B.solve(Dd, Y, [0.5, 0.6], group_ptr=gp, test="dome")
     assert e.value.status == B.DS_EINVAL
 
 
