@@ -450,6 +450,28 @@ def test_concurrent_columns_match_single_solves(B, dtype):
         assert infos[j]["gap"] == i1["gap"]
 
 
+def test_concurrent_columns_report_a_bad_column(B):
+    """A non-finite observation in one column of a concurrent multi-signal call ends the call
+    with DS_EINVAL and its message, and the next call on the same lanes runs normally."""
+    import torch
+    D, _ = _lasso_case(200, 900, 47)
+    Ys = np.stack([datagen.lasso_signal(D, j)[0] for j in range(6)], axis=1).astype(np.float32)
+    Ys[5, 3] = np.nan
+    Dd = dev_matrix(D, "f32")
+    L = oracle.spectral_norm_sq(datagen.to_storage(D, "f32"))
+    Yd = torch.from_numpy(np.ascontiguousarray(Ys.T)).cuda().T
+    with pytest.raises(B.DsError) as e:
+        B.solve(Dd, Yd, [0.5] * 6, step_L=L, gap_tol=1e-6, max_iter=5000)
+    assert e.value.status == B.DS_EINVAL and "NaN" in str(e.value)
+    Ys[5, 3] = 0.0
+    Yd = torch.from_numpy(np.ascontiguousarray(Ys.T)).cuda().T
+    X, infos = B.solve(Dd, Yd, [0.5] * 6, step_L=L, gap_tol=1e-6, max_iter=5000)
+    x1, i1, _, _ = B.solve_one(Dd, Yd[:, 3].contiguous(), 0.5, step_L=L, gap_tol=1e-6,
+                               max_iter=5000, trace=False)
+    assert all(i["status"] == 0 for i in infos)
+    assert np.array_equal(X[:, 3].cpu().numpy(), x1.cpu().numpy())
+
+
 def test_concurrent_group_columns_match_single_solves(B):
     """glasso_solve over 6 signals (groups of 10) runs the columns concurrently: each column
     equals its own single-signal Group-Lasso solve bit for bit."""
