@@ -11,7 +11,8 @@ import os
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdynscreen.so")
+# DS_LIBRARY: another build of the same library (the sanitizer tests load one)
+LIB_PATH = os.environ.get("DS_LIBRARY") or os.path.join(HERE, "libdynscreen.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1412_4080_amd.build` "

@@ -49,5 +49,49 @@ def build(jobs: int = 4) -> str:
     return LIB
 
 
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer (device code unchanged):
+# the library a sanitizer test loads in place of the product build (DS_LIBRARY).
+SAN_BUILD = os.path.join(HERE, "_build_asan")
+SAN_FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Wno-unused-result",
+             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def sanitizer_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (LD_PRELOAD for a process that loads
+    the sanitized library)."""
+    llvm = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "lib", "clang")
+    for ver in sorted(os.listdir(llvm)) if os.path.isdir(llvm) else []:
+        p = os.path.join(llvm, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(p):
+            return os.path.realpath(p)
+    raise RuntimeError("libclang_rt.asan-x86_64.so not found")
+
+
+def build_sanitized(jobs: int = 4) -> str:
+    """Builds _build_asan/libdynscreen.so (host code sanitized) and returns its path."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+
+    def one(src):
+        obj = os.path.join(SAN_BUILD, os.path.splitext(src)[0] + ".o")
+        r = subprocess.run([hipcc(), *SAN_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, SOURCES))
+    lib = os.path.join(SAN_BUILD, "libdynscreen.so")
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-shared-libsan", *objs, "-o", lib]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    return lib
+
+
 if __name__ == "__main__":
     print(build())

@@ -101,10 +101,21 @@ size_t dtype_size(ds_dtype t) {
   return 0;
 }
 
+// The integer a caller stored in an enumeration field: a C caller may store any int32 there,
+// and reading a value outside the enumerators as the enumeration type is undefined in C++.
+template <typename E>
+int32_t enum_raw(const E& e) {
+  static_assert(sizeof(E) == sizeof(int32_t), "enumerations of the boundary are 32-bit");
+  int32_t v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
+
 ds_status validate_problem(const ds_problem* p, bool group) {
   if (p == nullptr) { set_error("problem is NULL"); return DS_EINVAL; }
-  if (p->dtype != DS_F64 && p->dtype != DS_F32 && p->dtype != DS_BF16) {
-    set_error("unknown dtype %d", static_cast<int>(p->dtype));
+  const int32_t dt = enum_raw(p->dtype);
+  if (dt != DS_F64 && dt != DS_F32 && dt != DS_BF16) {
+    set_error("unknown dtype %d", static_cast<int>(dt));
     return DS_EINVAL;
   }
   if (p->N < 1 || p->K < 1 || p->N > (1ll << 24) || p->K > (1ll << 30)) {
@@ -141,16 +152,17 @@ ds_status validate_problem(const ds_problem* p, bool group) {
 
 ds_status validate_params(const ds_params* p) {
   if (p == nullptr) { set_error("params is NULL"); return DS_EINVAL; }
-  if (p->rule != DS_ISTA && p->rule != DS_FISTA && p->rule != DS_SPARSA && p->rule != DS_CP) {
+  const int32_t rule = enum_raw(p->rule), test = enum_raw(p->test);
+  const int32_t lmode = enum_raw(p->lambda_mode), smode = enum_raw(p->screening);
+  if (rule != DS_ISTA && rule != DS_FISTA && rule != DS_SPARSA && rule != DS_CP) {
     set_error("unknown rule");
     return DS_EINVAL;
   }
-  if (p->test != DS_TEST_NONE && p->test != DS_TEST_SAFE && p->test != DS_TEST_DST3 &&
-      p->test != DS_TEST_DOME) {
+  if (test != DS_TEST_NONE && test != DS_TEST_SAFE && test != DS_TEST_DST3 && test != DS_TEST_DOME) {
     set_error("unknown test");
     return DS_EINVAL;
   }
-  if (p->lambda_mode != DS_LAMBDA_ABSOLUTE && p->lambda_mode != DS_LAMBDA_RELATIVE) {
+  if (lmode != DS_LAMBDA_ABSOLUTE && lmode != DS_LAMBDA_RELATIVE) {
     set_error("unknown lambda mode");
     return DS_EINVAL;
   }
@@ -159,7 +171,7 @@ ds_status validate_params(const ds_params* p) {
   if (p->batch_slots < 0) { set_error("batch_slots must be >= 0"); return DS_EINVAL; }
   if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return DS_EINVAL; }
   if (!std::isfinite(p->step_L)) { set_error("step_L must be finite"); return DS_EINVAL; }
-  if (p->screening != 0 && p->screening != 1) { set_error("screening must be 0 (dynamic) or 1 (static)"); return DS_EINVAL; }
+  if (smode != 0 && smode != 1) { set_error("screening must be 0 (dynamic) or 1 (static)"); return DS_EINVAL; }
   if (p->step_rule != DS_STEP_CONSTANT && p->step_rule != DS_STEP_BACKTRACK) {
     set_error("step_rule must be DS_STEP_CONSTANT or DS_STEP_BACKTRACK");
     return DS_EINVAL;

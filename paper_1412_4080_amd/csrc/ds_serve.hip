@@ -605,6 +605,12 @@ ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype s
   const bool group = problem != nullptr && problem->G > 0;
   ds_status e = validate_problem(problem, group);
   if (e != DS_OK) return e;
+  int32_t store_raw;  // a C caller may pass any int32 here
+  std::memcpy(&store_raw, &store, sizeof store_raw);
+  if (store_raw != DS_F64 && store_raw != DS_F32 && store_raw != DS_BF16) {
+    set_error("unknown store precision %d", static_cast<int>(store_raw));
+    return DS_EINVAL;
+  }
   const bool convert = problem->dtype == DS_F32 && store == DS_BF16;
   if (store != problem->dtype && !convert) {
     set_error("store precision must equal the input's, or be DS_BF16 for DS_F32 input");
