@@ -117,9 +117,9 @@ def test_served_batched_equals_lasso_solve_alone_and_in_the_mix(B):
 
 def test_served_batched_mixed_parameters(B):
     """Requests with different rules, tests and modes on one bfloat16 dictionary: the ones
-    the engine supports run in batches of equal parameters and equal lasso_solve's batched
-    result with those parameters; the others (backtracking steps, the Dome test) run on the
-    single-signal workers and equal ds_solve_one."""
+    the engine supports (the Dome test among them) run in batches of equal parameters and
+    equal lasso_solve's batched result with those parameters; the others (backtracking
+    steps) run on the single-signal workers and equal ds_solve_one."""
     import torch
     D = datagen.gaussian_dictionary(400, 2500, 35)
     ys = [datagen.to_storage(datagen.lasso_signal(D, 800 + k)[0], "f32").astype(np.float32)
@@ -141,7 +141,7 @@ def test_served_batched_mixed_parameters(B):
         ks = [k for k in range(len(ys)) if k % len(variants) == v]
         for k in ks:
             assert got[k][1]["status"] == 0, (var, k)
-        if var.get("test") == "dome" or var.get("step") == "backtracking":
+        if var.get("step") == "backtracking":
             for k in ks:
                 step_L = 0.0 if var.get("step") == "backtracking" else L
                 x1, i1, _, _ = B.solve_one(Dd, torch.from_numpy(ys[k]).cuda(), lam[k],
