@@ -266,10 +266,11 @@ ds_status ds_spectral_norm_sq(const ds_problem* problem, int32_t iters, double* 
  * path supports
  * (ISTA or FISTA, constant step, SAFE / DST3 / Dome / no test, no x0, obj_tol = 0) joins the
  * engine's resident signals at the next graph-replay boundary where a slot is free, and
- * leaves as soon as it has finished; requests with the same parameters share a run.  Its
- * result equals the batched result of lasso_solve (glasso_solve) for the same y and lambda
- * bit for bit, alone
- * or in any mix.  Other requests run as single-signal solves on the worker slots. */
+ * leaves as soon as it has finished; requests with the same parameters share a run (a
+ * request with other parameters is overtaken at no more than 16 slot refills, then the run drains
+ * and the next one starts with it).  Its result equals the batched result of lasso_solve
+ * (glasso_solve) for the same y and lambda bit for bit, alone or in any mix.  Other
+ * requests run as single-signal solves on the worker slots. */
 typedef struct {
   int32_t device;           /* HIP device ordinal */
   int32_t max_slots;        /* single-signal requests resident on the device at once (>= 1) */

@@ -403,11 +403,18 @@ void Server::run_lane(BatchLane* b, const Dict& d, const ds_params& key) {
     {
       std::lock_guard<std::mutex> g(mu);
       if (stop) return 0;
+      // Requests of other parameters wait for this run to end.  The ones queued behind them
+      // may overtake them, but a waiting request is overtaken by at most SKIP_LIMIT pulls;
+      // then this run admits nothing more, drains, and the next run starts with it.
+      std::vector<Request*> passed;
+      size_t overtaken = 0;  // the first `overtaken` of `passed` were overtaken here
       for (auto it = b->queue.begin();
            it != b->queue.end() && static_cast<int>(got.size()) < room &&
            got.size() < free_cols.size();) {
         Request* r = reqs.at(*it).get();
         if (!same_run(r->prm, key)) {
+          if (r->skipped >= SKIP_LIMIT) break;
+          passed.push_back(r);
           ++it;
           continue;
         }
@@ -415,7 +422,9 @@ void Server::run_lane(BatchLane* b, const Dict& d, const ds_params& key) {
         r->state = RUNNING;
         r->t_start = Clock::now();
         got.push_back(r);
+        overtaken = passed.size();
       }
+      for (size_t k = 0; k < overtaken; ++k) ++passed[k]->skipped;
     }
     int n = 0;
     for (Request* r : got) {

@@ -217,3 +217,36 @@ def test_engine_that_cannot_fit_the_budget_leaves_requests_to_the_workers(B):
                                    trace=False, screened=False)
         assert np.array_equal(got[k][0], x1.cpu().numpy()), k
         assert got[k][1]["iters"] == i1["iters"]
+
+
+def test_request_of_other_parameters_is_not_starved(B):
+    """One engine, four slots: a request (ISTA + SAFE) queued behind the first of 80 FISTA +
+    DST3 requests is overtaken at no more than 16 slot refills (at most 64 requests), so it
+    starts before the last FISTA request does; every result equals the batched lasso_solve
+    with its parameters."""
+    import torch
+    D = datagen.gaussian_dictionary(256, 1200, 39)
+    ys = [datagen.to_storage(datagen.lasso_signal(D, 1100 + k)[0], "f32").astype(np.float32)
+          for k in range(82)]
+    lam = [0.3 + 0.005 * k for k in range(len(ys))]
+    S = B.Server(max_slots=1, batch_slots=4)
+    did = S.add_dict(dev_matrix(D, "f32"), store="bf16")
+    torch.cuda.synchronize()
+    kw = dict(gap_tol=1e-6, max_iter=20000)
+    odd = dict(rule="ista", test="safe")
+    t_sub, pend = {}, {}
+    for k in range(len(ys)):
+        var = odd if k == 1 else dict(rule="fista", test="dst3")
+        t_sub[k] = time.perf_counter()
+        pend[k] = (S.submit(did, ys[k], lam[k], **kw, **var), 0)
+    got = _wait(S, pend, [did])
+    S.close()
+    start = {k: t_sub[k] + got[k][1]["queue_ms"] * 1e-3 for k in range(len(ys))}
+    assert start[1] < max(start[k] for k in range(len(ys)) if k != 1)
+    L = got[0][1]["L"]
+    ks = [k for k in range(len(ys)) if k != 1]
+    X, infos = _direct_batched(B, D, [ys[k] for k in ks], [lam[k] for k in ks], L, **kw)
+    for j, k in enumerate(ks):
+        assert got[k][1]["status"] == 0 and np.array_equal(got[k][0], X[:, j]), k
+    X1, _ = _direct_batched(B, D, [ys[1], ys[1]], [lam[1], lam[1]], L, **kw, **odd)
+    assert np.array_equal(got[1][0], X1[:, 0])
