@@ -154,6 +154,11 @@ struct BatchEngine {
   std::map<std::tuple<int, int, int>, int> tuned;  // (N, K, B) -> Z-GEMM block shape
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evpool;
   size_t ev_used = 0;
+  // pinned host staging of what a run exchanges with the device between replays (the
+  // harvest flags and slot states, the slot assignment, penalties and set-up list), so
+  // that those copies are plain asynchronous DMA
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
 };
 
 BatchEngine* batch_engine_create(int device) {
@@ -175,6 +180,7 @@ void batch_engine_destroy(BatchEngine* E) {
   if (E->tune1 != nullptr) (void)hipEventDestroy(E->tune1);
   if (E->ev != nullptr) (void)hipEventDestroy(E->ev);
   if (E->stream != nullptr) (void)hipStreamDestroy(E->stream);
+  if (E->pin != nullptr) (void)hipHostFree(E->pin);
   E->ws.release();
   delete E;
 }
@@ -394,10 +400,29 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   char* base = static_cast<char*>(C.ws.base);
   BArgs a = make_args(l, base, prm, L);
 
+  // Pinned staging (the engine's stream is idle between runs, so an old block can go).  The
+  // host writes these arrays only after a synchronization that followed their last copy.
+  const size_t bp = static_cast<size_t>(l.Bp);
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t pin_need = al(bp * 4) + al(bp * sizeof(Inst)) + al(bp * 4) + al(bp * 8) + al(bp * 4);
+  if (C.pin_bytes < pin_need) {
+    if (C.pin != nullptr) (void)hipHostFree(C.pin);
+    C.pin = nullptr;
+    C.pin_bytes = 0;
+    DS_HIP(hipHostMalloc(&C.pin, pin_need, hipHostMallocDefault));
+    C.pin_bytes = pin_need;
+  }
+  char* pp = static_cast<char*>(C.pin);
+  int* h_flag = reinterpret_cast<int*>(pp);
+  Inst* h_inst = reinterpret_cast<Inst*>(pp + al(bp * 4));
+  int* slot_sig = reinterpret_cast<int*>(pp + al(bp * 4) + al(bp * sizeof(Inst)));
+  double* lam_slot = reinterpret_cast<double*>(pp + al(bp * 4) + al(bp * sizeof(Inst)) + al(bp * 4));
+  int* h_list = reinterpret_cast<int*>(pp + al(bp * 4) + al(bp * sizeof(Inst)) + al(bp * 4) + al(bp * 8));
+
   // The feed hands out signals (a column of Y and X, and a penalty) as slots free up;
   // slot k holds column slot_sig[k], or -1 when idle.
-  std::vector<int> slot_sig(l.Bp, -1);
-  std::vector<double> lam_slot(l.Bp, 1.0);
+  std::fill(slot_sig, slot_sig + bp, -1);
+  std::fill(lam_slot, lam_slot + bp, 1.0);
   std::vector<int> cols(nslot);
   std::vector<double> lams(nslot);
   const int n0 = feed.pull(nslot, cols.data(), lams.data(), s);
@@ -409,11 +434,10 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   int* d_perm = reinterpret_cast<int*>(base + l.perm);
   double* d_lam = reinterpret_cast<double*>(base + l.lam);
   int* d_list = reinterpret_cast<int*>(base + l.slist);
-  std::vector<int> list(l.Bp);
-  std::iota(list.begin(), list.end(), 0);
-  DS_HIP(hipMemcpyAsync(d_perm, slot_sig.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
-  DS_HIP(hipMemcpyAsync(d_lam, lam_slot.data(), l.Bp * sizeof(double), hipMemcpyHostToDevice, s));
-  DS_HIP(hipMemcpyAsync(d_list, list.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
+  std::iota(h_list, h_list + bp, 0);
+  DS_HIP(hipMemcpyAsync(d_perm, slot_sig, bp * sizeof(int), hipMemcpyHostToDevice, s));
+  DS_HIP(hipMemcpyAsync(d_lam, lam_slot, bp * sizeof(double), hipMemcpyHostToDevice, s));
+  DS_HIP(hipMemcpyAsync(d_list, h_list, bp * sizeof(int), hipMemcpyHostToDevice, s));
 
   // ---------------------------------------------------------------- setup
   StatAccum& S = stats();
@@ -473,16 +497,12 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   auto setup_slots = [&](int n, int nact) -> ds_status {
     hipLaunchKernelGGL(k_b_load_slots, dim3(std::max(1, (l.Kp + TB - 1) / TB), n), dim3(TB), 0, s, a,
                        Y, ldy, static_cast<const int*>(d_perm), static_cast<const int*>(d_list), Yp);
-    // FP64 D^T v for the listed slots: 64-slot tiles for many, 16-slot tiles for a few
-    // refilled slots (the same sums either way)
+    // FP64 D^T v for the listed slots (tiles of 16 atoms x 16 slots on the matrix cores)
     auto dtv = [&](const auto* V, double* out) {
       using VT = std::remove_const_t<std::remove_pointer_t<decltype(V)>>;
-      if (nact > 16)
-        hipLaunchKernelGGL((k_b_dtv64<64, VT>), dim3(l.Kp / 64, (nact + 63) / 64), dim3(TB), 0, s,
-                           dcm, V, l.Np, l.Kp, out, static_cast<const int*>(d_list), nact);
-      else if (nact > 0)
-        hipLaunchKernelGGL((k_b_dtv64<16, VT>), dim3(l.Kp / 64, 1), dim3(TB), 0, s, dcm, V, l.Np,
-                           l.Kp, out, static_cast<const int*>(d_list), nact);
+      if (nact > 0)
+        hipLaunchKernelGGL((k_b_dtv<VT>), dim3(l.Kp / 16, (nact + 15) / 16), dim3(TB), 0, s, dcm,
+                           V, l.Np, l.Kp, out, static_cast<const int*>(d_list), nact);
     };
     dtv(a.Y, z0);
     const int lrel = prm.lambda_mode == DS_LAMBDA_RELATIVE ? 1 : 0;
@@ -601,13 +621,12 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   if (stat_on) C.ev_used = 0;
 
   // Runs of ITERS_PER_GRAPH iterations (graph replays, or direct launches when instrumented)
-  // while any slot holds a signal.  After each run the slots' states are read; finished
-  // signals report (counts, x scattered to column perm[k] of X, the feed's finish), and
-  // free slots take the signals the feed has waiting.
-  std::vector<Inst> hs(l.Bp);
-  std::vector<int> hflag(l.Bp);
+  // while any slot holds a signal.  After each run the device harvests the signals that
+  // finished (counts, x into column perm[k] of X, the screened mask) and one round trip
+  // brings back the harvest flags and the slots' states; the finished signals report (the
+  // feed's finish) and free slots take the signals the feed has waiting.
   int* d_flag = reinterpret_cast<int*>(base + l.dflag);
-  std::vector<int> fin, refill, fcols;
+  std::vector<int> fcols;
   std::vector<ds_info> finfo;
   double act = 0.0, sup = 0.0;  // work of the finished signals (statistics)
   int nactive = n0;             // slots holding a signal
@@ -620,49 +639,38 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
       DS_HIP(hipGraphLaunch(C.exec, s));
       t += ITERS_PER_GRAPH;
     }
-    hipLaunchKernelGGL(k_b_done_flags, dim3((l.Bp + TB - 1) / TB), dim3(TB), 0, s, a, d_flag);
-    DS_HIP(hipMemcpyAsync(hflag.data(), d_flag, l.Bp * sizeof(int), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_b_harvest, dim3(l.Bp), dim3(TB), 0, s, a, d_perm, X, ldx, screened, d_flag);
+    DS_HIP(hipGetLastError());
+    DS_HIP(hipMemcpyAsync(h_flag, d_flag, bp * sizeof(int), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipMemcpyAsync(h_inst, a.inst, bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
     DS_HIP(hipStreamSynchronize(s));
-    fin.clear();
-    for (int k = 0; k < l.Bp; ++k)
-      if (slot_sig[k] >= 0 && hflag[k] != 0) fin.push_back(k);
-    if (!fin.empty()) {
-      DS_HIP(hipMemcpyAsync(d_list, fin.data(), fin.size() * sizeof(int), hipMemcpyHostToDevice, s));
-      const int nf = static_cast<int>(fin.size());
-      hipLaunchKernelGGL(k_b_counts, dim3(nf), dim3(TB), 0, s, a, static_cast<const int*>(d_list));
-      hipLaunchKernelGGL(k_b_scatter, dim3((l.K + TB - 1) / TB, nf), dim3(TB), 0, s, a,
-                         static_cast<const int*>(d_perm), X, ldx, screened,
-                         static_cast<const int*>(d_list));
-      DS_HIP(hipGetLastError());
-      DS_HIP(hipMemcpyAsync(hs.data(), a.inst, l.Bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
-      DS_HIP(hipStreamSynchronize(s));
-      fcols.clear();
-      finfo.clear();
-      for (int k : fin) {
-        fcols.push_back(slot_sig[k]);
-        finfo.push_back(info_of(hs[k], L));
-        act += hs[k].act_sum;
-        sup += hs[k].sup_sum;
-        slot_sig[k] = -1;
-        --nactive;
-      }
-      feed.finish(fcols.data(), finfo.data(), nf, s);
+    fcols.clear();
+    finfo.clear();
+    for (int k = 0; k < l.Bp; ++k) {
+      if (h_flag[k] == 0) continue;
+      fcols.push_back(slot_sig[k]);
+      finfo.push_back(info_of(h_inst[k], L));
+      act += h_inst[k].act_sum;
+      sup += h_inst[k].sup_sum;
+      slot_sig[k] = -1;
+      --nactive;
     }
+    if (!fcols.empty()) feed.finish(fcols.data(), finfo.data(), static_cast<int>(fcols.size()), s);
     const int room = nslot - nactive;
     const int got = room > 0 ? feed.pull(room, cols.data(), lams.data(), s) : 0;
     if (got > 0) {
-      refill.clear();
+      int nref = 0;
       for (int k = 0, q = 0; k < nslot && q < got; ++k) {
         if (slot_sig[k] >= 0) continue;
         slot_sig[k] = cols[q];
         lam_slot[k] = lams[q];
         ++q;
-        refill.push_back(k);
+        h_list[nref++] = k;
       }
       nactive += got;
-      DS_HIP(hipMemcpyAsync(d_perm, slot_sig.data(), l.Bp * sizeof(int), hipMemcpyHostToDevice, s));
-      DS_HIP(hipMemcpyAsync(d_lam, lam_slot.data(), l.Bp * sizeof(double), hipMemcpyHostToDevice, s));
-      DS_HIP(hipMemcpyAsync(d_list, refill.data(), refill.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      DS_HIP(hipMemcpyAsync(d_perm, slot_sig, bp * sizeof(int), hipMemcpyHostToDevice, s));
+      DS_HIP(hipMemcpyAsync(d_lam, lam_slot, bp * sizeof(double), hipMemcpyHostToDevice, s));
+      DS_HIP(hipMemcpyAsync(d_list, h_list, nref * sizeof(int), hipMemcpyHostToDevice, s));
       if ((e = setup_slots(got, got)) != DS_OK) return e;
     }
   }

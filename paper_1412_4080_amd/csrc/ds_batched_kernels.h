@@ -187,58 +187,81 @@ __global__ __launch_bounds__(TB) void k_b_load_slots(BArgs a, const float* __res
 }
 
 // FP64 batched products out[b][a] = d_a^T v_b for the listed slots b = slots[j], j < nsl
-// (exact bfloat16 x FP32 / FP64 products, FP64 accumulation).  Block: 64 atoms x BS list
-// entries; thread: 4 atoms x BS/16 entries (atoms ta + 16 i, entries tb + 16 j); each output
-// sums its products in row order, so the value does not depend on BS.
-template <int BS, typename VT>
-__global__ __launch_bounds__(TB) void k_b_dtv64(const uint16_t* __restrict__ dcm,
-                                                const VT* __restrict__ V, int Np, int Kp,
-                                                double* __restrict__ out,
-                                                const int* __restrict__ slots, int nsl) {
-  constexpr int JS = BS / 16;  // entries per thread
-  __shared__ double sd[64][33];
-  __shared__ double sv[BS][33];
-  __shared__ int sslot[BS];
-  const int a0 = blockIdx.x * 64, b0 = blockIdx.y * BS;
-  if (threadIdx.x < BS) sslot[threadIdx.x] = slots[min(b0 + static_cast<int>(threadIdx.x), nsl - 1)];
+// (exact bfloat16 x FP32 / FP64 products, FP64 accumulation on the matrix cores,
+// v_mfma_f64_16x16x4_f64).  The summation order is fixed by Np alone, so a value depends
+// neither on the grid nor on which or how many slots are listed: with Q = Np / 4 the rows
+// form Q groups {s, Q + s, 2Q + s, 3Q + s}; a group is one k-step of the instruction (its
+// four products added to the accumulator); wave w of a block chains the groups
+// s = wQ/4 .. (w + 1)Q/4 - 1 in order, and the block adds the four waves' sums in wave order.
+// Block: a tile of 16 atoms x 16 list entries (entries past nsl repeat the last slot and
+// are not stored).  Operands: lane l holds A[i][k] = d_{a0+i}[kQ + s] and B[k][j] =
+// v_{b0+j}[kQ + s] (i = j = l % 16, k = l / 16); the accumulator's element r of lane l is
+// C[4r + l / 16][l % 16].  Each lane reads its own rows of D and V contiguously, 4 groups
+// per load.
+typedef double dtv_acc __attribute__((ext_vector_type(4)));
+template <typename VT>
+__global__ __launch_bounds__(TB) void k_b_dtv(const uint16_t* __restrict__ dcm,
+                                              const VT* __restrict__ V, int Np, int Kp,
+                                              double* __restrict__ out,
+                                              const int* __restrict__ slots, int nsl) {
+  constexpr int GB = 32;  // groups per batch of loads (GB / 4 loads of A and of B in flight)
+  __shared__ dtv_acc part[NWB - 1][BW];
+  const int tid = threadIdx.x, lane = tid % BW, wave = tid / BW;
+  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
+  const int q16 = lane % 16, k = lane / 16;
+  const int Q = Np / 4, S = Q / NWB;  // groups per wave (a multiple of 4: Np % 64 == 0)
+  const int s0 = wave * S;
+  const uint16_t* pa = dcm + static_cast<int64_t>(a0 + q16) * Np + k * Q + s0;
+  const VT* pb = V + static_cast<int64_t>(slots[min(b0 + q16, nsl - 1)]) * Np + k * Q + s0;
+  dtv_acc acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < S; s += GB) {
+    uint2 qa[GB / 4];
+    VT vb[GB / 4][4];
+#pragma unroll
+    for (int q = 0; q < GB / 4; ++q) {
+      const int g = min(s + 4 * q, S - 4);  // past the end: re-read the last 4 groups, unused
+      qa[q] = *reinterpret_cast<const uint2*>(pa + g);
+      if constexpr (sizeof(VT) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(pb + g);
+        vb[q][0] = v.x;
+        vb[q][1] = v.y;
+        vb[q][2] = v.z;
+        vb[q][3] = v.w;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2*>(pb + g);
+        const double2 v1 = *reinterpret_cast<const double2*>(pb + g + 2);
+        vb[q][0] = v0.x;
+        vb[q][1] = v0.y;
+        vb[q][2] = v1.x;
+        vb[q][3] = v1.y;
+      }
+    }
+    // every load of the batch is issued before the first product (a branch past the end
+    // would let the compiler sink each load to its use); groups past the end multiply zeros
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < GB / 4; ++q) {
+      const bool live = s + 4 * q < S;
+      const uint32_t w0 = live ? qa[q].x : 0u, w1 = live ? qa[q].y : 0u;
+      const float af[4] = {__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xffff0000u),
+                           __uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(af[r]),
+                                                   live ? static_cast<double>(vb[q][r]) : 0.0,
+                                                   acc, 0, 0, 0);
+    }
+  }
+  if (wave > 0) part[wave - 1][lane] = acc;
   __syncthreads();
-  const int ta = threadIdx.x % 16, tb = threadIdx.x / 16;
-  double acc[4][JS];
+  if (wave != 0) return;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int w = 0; w < NWB - 1; ++w) acc += part[w][lane];
+  const int e = b0 + q16;
+  if (e >= nsl) return;
+  const int64_t row = static_cast<int64_t>(slots[e]) * Kp + a0 + k;
 #pragma unroll
-    for (int j = 0; j < JS; ++j) acc[i][j] = 0.0;
-  for (int n0 = 0; n0 < Np; n0 += 32) {
-    for (int e = threadIdx.x; e < 64 * 32; e += TB) {
-      const int r = e / 32, nn = e % 32;
-      sd[r][nn] = bf16f(dcm[static_cast<int64_t>(a0 + r) * Np + n0 + nn]);
-    }
-    for (int e = threadIdx.x; e < BS * 32; e += TB) {
-      const int r = e / 32, nn = e % 32;
-      sv[r][nn] = V[static_cast<int64_t>(sslot[r]) * Np + n0 + nn];
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int nn = 0; nn < 32; ++nn) {
-      double dv[4], vv[JS];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dv[i] = sd[ta + 16 * i][nn];
-#pragma unroll
-      for (int j = 0; j < JS; ++j) vv[j] = sv[tb + 16 * j][nn];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < JS; ++j) acc[i][j] = fma(dv[i], vv[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < JS; ++j) {
-    if (b0 + tb + 16 * j >= nsl) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      out[static_cast<int64_t>(sslot[tb + 16 * j]) * Kp + a0 + ta + 16 * i] = acc[i][j];
-  }
+  for (int r = 0; r < 4; ++r) out[row + 4 * r] = acc[r];
 }
 
 // Per-signal setup (one block per slot): ||y||^2, finiteness, lambda_* = max_i |z0_i|
@@ -1430,49 +1453,43 @@ __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
   }
 }
 
-// done flag of every slot (the host reads these after each run of iterations)
-__global__ __launch_bounds__(TB) void k_b_done_flags(BArgs a, int* __restrict__ flags) {
-  const int s = blockIdx.x * TB + threadIdx.x;
-  if (s < a.Bp) flags[s] = a.inst[s].done;
-}
-
 // ============================================================== output
-// Per-slot counts for the report: non-zeros of x and atoms active in the last iteration.
-__global__ __launch_bounds__(TB) void k_b_counts(BArgs a, const int* __restrict__ slots) {
+// After each run of iterations, one block per slot: a slot that holds a signal (perm[s] >= 0)
+// and has finished is harvested: its counts for the report (non-zeros of x, atoms active in
+// the last iteration), x_t into column perm[s] of Xout (leading dimension ldx), the optional
+// screened mask (1 = screened, leading dimension K); then perm[s] = -1 (the host clears its
+// copy when it reads the flag).  flags[s] = 1 for the slots harvested here, else 0.  A
+// finished signal's x and state are no longer changed by the iteration kernels.
+__global__ __launch_bounds__(TB) void k_b_harvest(BArgs a, int* __restrict__ perm,
+                                                  float* __restrict__ Xout, int64_t ldx,
+                                                  uint8_t* __restrict__ scr,
+                                                  int* __restrict__ flags) {
   __shared__ int si[NWB];
-  const int s = slots[blockIdx.x];
+  const int s = blockIdx.x;
+  const int b = perm[s];
   Inst& st = a.inst[s];
+  const bool fin = b >= 0 && st.done != 0;
+  if (threadIdx.x == 0) flags[s] = fin ? 1 : 0;
+  if (!fin) return;
   const bool trivial = st.status != 0;
+  const double rp = st.r_prev;
   int nz = 0, na = 0;
   for (int i = threadIdx.x; i < a.K; i += TB) {
     const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
-    nz += a.X[o] != 0.f;
-    na += static_cast<double>(a.marg[o]) <= st.r_prev;
+    const float xv = a.X[o];
+    const bool act = static_cast<double>(a.marg[o]) <= rp;
+    nz += xv != 0.f;
+    na += act;
+    Xout[static_cast<int64_t>(b) * ldx + i] = trivial ? 0.f : xv;
+    if (scr != nullptr) scr[static_cast<int64_t>(b) * a.K + i] = (trivial || !act) ? 1 : 0;
   }
-  nz = block_sum<int, NWB>(nz, si);
+  nz = block_sum<int, NWB>(nz, si);  // every thread has read perm[s] before this barrier
   na = block_sum<int, NWB>(na, si);
   if (threadIdx.x == 0) {
     st.nnz = trivial ? 0 : nz;
     st.n_active = trivial ? 0 : na;
+    perm[s] = -1;
   }
-}
-
-// X_out[perm[s] * ldx + i] = X[s][i]; optional screened mask (1 = screened) with leading
-// dimension K.
-__global__ __launch_bounds__(TB) void k_b_scatter(BArgs a, const int* __restrict__ perm,
-                                                  float* __restrict__ Xout, int64_t ldx,
-                                                  uint8_t* __restrict__ scr,
-                                                  const int* __restrict__ slots) {
-  const int s = slots[blockIdx.y];
-  const int i = blockIdx.x * TB + threadIdx.x;
-  if (perm[s] < 0 || i >= a.K) return;
-  const Inst& st = a.inst[s];
-  const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
-  const int b = perm[s];
-  Xout[static_cast<int64_t>(b) * ldx + i] = st.status != 0 ? 0.f : a.X[o];
-  if (scr != nullptr)
-    scr[static_cast<int64_t>(b) * a.K + i] =
-        (st.status != 0 || !(static_cast<double>(a.marg[o]) <= st.r_prev)) ? 1 : 0;
 }
 
 }  // namespace batch

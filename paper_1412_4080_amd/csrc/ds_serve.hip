@@ -104,8 +104,12 @@ struct BatchLane {
   std::thread th;
   BatchEngine* eng = nullptr;
   std::deque<uint64_t> queue;  // requests waiting for this engine
-  float* Ys = nullptr;         // staging: column c of Y (leading dimension ldy) and of X (K)
+  // staging in coherent pinned host memory, read and written by the engine's kernels
+  // directly: column c of Y (leading dimension ldy) and of X (K)
+  float* Ys = nullptr;
   float* Xs = nullptr;
+  float* Ys_dev = nullptr;  // the same memory as the device addresses it
+  float* Xs_dev = nullptr;
   int64_t ldy = 0;
   size_t held = 0;             // device bytes charged to the budget for this engine
   bool waiting = false;        // needs memory that others hold
@@ -129,8 +133,8 @@ bool same_run(const ds_params& a, const ds_params& b) {
          a.step_L == b.step_L;
 }
 
-// Device bytes a batched engine holds: its workspace (with the 25% headroom of
-// Workspace::reserve) and the staging columns.
+// Bytes a batched engine is charged: its device workspace (with the 25% headroom of
+// Workspace::reserve) and its staging columns (pinned host memory, counted as well).
 size_t lane_need(int64_t N, int64_t K, int64_t G, int slots, int max_iter) {
   const size_t ws = batched_workspace_bytes(N, K, slots, max_iter, G);
   const int64_t ldy = (N + 3) / 4 * 4;
@@ -301,9 +305,9 @@ void Server::release_lane(BatchLane* b, std::unique_lock<std::mutex>& lk) {
   const size_t h = b->held;
   lk.unlock();
   batch_engine_trim(b->eng);
-  if (b->Ys != nullptr) (void)hipFree(b->Ys);
-  if (b->Xs != nullptr) (void)hipFree(b->Xs);
-  b->Ys = b->Xs = nullptr;
+  if (b->Ys != nullptr) (void)hipHostFree(b->Ys);
+  if (b->Xs != nullptr) (void)hipHostFree(b->Xs);
+  b->Ys = b->Xs = b->Ys_dev = b->Xs_dev = nullptr;
   lk.lock();
   held -= h;
   b->held = 0;
@@ -383,15 +387,23 @@ void Server::run_lane(BatchLane* b, const Dict& d, const ds_params& key) {
   };
   if (b->eng == nullptr) b->eng = batch_engine_create(cfg.device);
   if (b->Ys == nullptr) {
-    if (hipMalloc(reinterpret_cast<void**>(&b->Ys), static_cast<size_t>(ldy) * slots * 4) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&b->Xs), static_cast<size_t>(d.K) * slots * 4) != hipSuccess) {
+    // coherent: a column is rewritten by the host for each new request, so the device must
+    // not read it through a cache that could hold the previous request's values
+    void *py = nullptr, *px = nullptr, *dy = nullptr, *dx = nullptr;
+    if (hipHostMalloc(&py, static_cast<size_t>(ldy) * slots * 4, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&px, static_cast<size_t>(d.K) * slots * 4, hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(&dy, py, 0) != hipSuccess ||
+        hipHostGetDevicePointer(&dx, px, 0) != hipSuccess) {
       (void)hipGetLastError();
-      if (b->Ys != nullptr) (void)hipFree(b->Ys);
-      b->Ys = nullptr;
-      b->Xs = nullptr;
-      set_error("hipMalloc of the batched staging columns failed");
+      if (py != nullptr) (void)hipHostFree(py);
+      if (px != nullptr) (void)hipHostFree(px);
+      set_error("pinned host staging columns of the batched engine could not be allocated");
       return fail_waiting(DS_ENOMEM);
     }
+    b->Ys = static_cast<float*>(py);
+    b->Xs = static_cast<float*>(px);
+    b->Ys_dev = static_cast<float*>(dy);
+    b->Xs_dev = static_cast<float*>(dx);
     b->ldy = ldy;
   }
   ds_params prm = key;
@@ -431,34 +443,28 @@ void Server::run_lane(BatchLane* b, const Dict& d, const ds_params& key) {
       const int c = free_cols.back();
       free_cols.pop_back();
       in_col[c] = r;
-      // the request (and its host copy of y) lives until it is polled, after DONE
-      (void)hipMemcpyAsync(b->Ys + static_cast<int64_t>(c) * ldy, r->y.data(), d.N * vsz,
-                           hipMemcpyHostToDevice, s);
+      // the column is free: no kernel reads it until the set-up this pull precedes
+      std::memcpy(b->Ys + static_cast<int64_t>(c) * ldy, r->y.data(), d.N * vsz);
       cols[n] = c;
       lams[n] = r->lam;
       ++n;
     }
     return n;
   };
-  feed.finish = [&](const int* cols, const ds_info* infos, int n, hipStream_t s) {
-    bool copied = true;
+  feed.finish = [&](const int* cols, const ds_info* infos, int n, hipStream_t) {
+    // the engine's stream has been synchronized after the harvest wrote these columns
     for (int j = 0; j < n; ++j) {
       Request* r = in_col[cols[j]];
       r->x.resize(d.K * vsz);
-      if (hipMemcpyAsync(r->x.data(), b->Xs + static_cast<int64_t>(cols[j]) * d.K, d.K * vsz,
-                         hipMemcpyDeviceToHost, s) != hipSuccess)
-        copied = false;
+      std::memcpy(r->x.data(), b->Xs + static_cast<int64_t>(cols[j]) * d.K, d.K * vsz);
     }
-    if (hipStreamSynchronize(s) != hipSuccess) copied = false;
     std::lock_guard<std::mutex> g(mu);
     for (int j = 0; j < n; ++j) {
       Request* r = in_col[cols[j]];
       in_col[cols[j]] = nullptr;
       free_cols.push_back(cols[j]);
       r->info = infos[j];
-      if (!copied) {
-        finish(r, DS_EDEVICE, "download of x failed");
-      } else if (infos[j].status == DS_EINVAL) {
+      if (infos[j].status == DS_EINVAL) {
         finish(r, DS_EINVAL, "observation contains NaN or Inf");
       } else if (r->id == fail_request) {
         finish(r, DS_EDEVICE,
@@ -470,8 +476,8 @@ void Server::run_lane(BatchLane* b, const Dict& d, const ds_params& key) {
     cv_work.notify_all();
   };
   const ds_problem P = d.view();
-  const ds_status e = run_batched(*b->eng, P, b->Ys, ldy, slots, prm, b->Xs, d.K, nullptr, feed,
-                                  nullptr);
+  const ds_status e = run_batched(*b->eng, P, b->Ys_dev, ldy, slots, prm, b->Xs_dev, d.K, nullptr,
+                                  feed, nullptr);
   if (e < 0) {  // the signals in the engine fail with the run
     const std::string err = ds_last_error();
     std::lock_guard<std::mutex> g(mu);
@@ -769,8 +775,8 @@ ds_status ds_server_destroy(void* server) {
   (void)hipSetDevice(S->cfg.device);
   for (auto& kv : S->lanes) {
     batch_engine_destroy(kv.second->eng);
-    if (kv.second->Ys != nullptr) (void)hipFree(kv.second->Ys);
-    if (kv.second->Xs != nullptr) (void)hipFree(kv.second->Xs);
+    if (kv.second->Ys != nullptr) (void)hipHostFree(kv.second->Ys);
+    if (kv.second->Xs != nullptr) (void)hipHostFree(kv.second->Xs);
   }
   for (auto& w : S->workers) {
     if (w->stream != nullptr) (void)hipStreamSynchronize(w->stream);
