@@ -37,7 +37,7 @@ struct BLayout {
   int N, K, B, Np, Kp, Bp, nrb, G;
   size_t gptr, agrp, gw, gspec, gfro, Vd;  // groups only (zero bytes for the Lasso)
   size_t dcm, nu, dsc, Y, X, U0, U1, umask, Ths, th64, ptt, pty, marg, tminm, pz, pom, pact, Z, ccount, cidx, cval,
-      inst, ctr, vlist, perm, slist, dflag, lam, z0, gn, Vn, kclk, spans, tX, tU, tZ, tpz, tpom,
+      inst, ctr, vlist, perm, slist, asig, alam, dflag, lam, z0, gn, Vn, kclk, spans, tX, tU, tZ, tpz, tpom,
       tpact, tmask, total;
   int nspan;
 };
@@ -76,10 +76,12 @@ BLayout make_layout(int N, int K, int B, int max_iter, int G) {
   l.inst = take(bp * sizeof(Inst));
   l.ctr = take(4 * sizeof(int));
   l.vlist = take(bp * 4);
+  l.dflag = take(2 * bp * 4);  // harvest flags, two replays
   l.perm = take(bp * 4);
-  l.slist = take(bp * 4);
-  l.dflag = take(bp * 4);
   l.lam = take(bp * 8);
+  l.slist = take(bp * 4);  // slist, asig and alam are adjacent: one upload from the host
+  l.asig = take(bp * 4);
+  l.alam = take(bp * 8);
   l.z0 = take(bp * kp * 8);
   l.gn = take(bp * kp * 8);
   l.Vn = take(bp * np * 4);
@@ -146,6 +148,8 @@ struct BatchEngine {
   Workspace ws;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
+  hipEvent_t evh[2] = {nullptr, nullptr};  // a replay's harvest results are on the host
+  hipEvent_t evu = nullptr;                 // the last slot assignment has been uploaded
   hipGraphExec_t exec = nullptr;
   BArgs key{};
   int key_shape = -1;
@@ -179,6 +183,9 @@ void batch_engine_destroy(BatchEngine* E) {
   if (E->tune0 != nullptr) (void)hipEventDestroy(E->tune0);
   if (E->tune1 != nullptr) (void)hipEventDestroy(E->tune1);
   if (E->ev != nullptr) (void)hipEventDestroy(E->ev);
+  for (hipEvent_t h : E->evh)
+    if (h != nullptr) (void)hipEventDestroy(h);
+  if (E->evu != nullptr) (void)hipEventDestroy(E->evu);
   if (E->stream != nullptr) (void)hipStreamDestroy(E->stream);
   if (E->pin != nullptr) (void)hipHostFree(E->pin);
   E->ws.release();
@@ -379,6 +386,9 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   if (C.stream == nullptr) {
     DS_HIP(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
     DS_HIP(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming));
+    DS_HIP(hipEventCreateWithFlags(&C.evh[0], hipEventDisableTiming));
+    DS_HIP(hipEventCreateWithFlags(&C.evh[1], hipEventDisableTiming));
+    DS_HIP(hipEventCreateWithFlags(&C.evu, hipEventDisableTiming));
     DS_HIP(hipEventCreate(&C.tune0));
     DS_HIP(hipEventCreate(&C.tune1));
   }
@@ -400,11 +410,19 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
   char* base = static_cast<char*>(C.ws.base);
   BArgs a = make_args(l, base, prm, L);
 
-  // Pinned staging (the engine's stream is idle between runs, so an old block can go).  The
-  // host writes these arrays only after a synchronization that followed their last copy.
+  // Pinned staging (the engine's stream is idle between runs, so an old block can go):
+  // harvest flags and slot states of two replays, and a slot assignment (slots, signals,
+  // penalties) that mirrors the adjacent device arrays slist | asig | alam, so that one copy
+  // uploads it.  The host writes the assignment only after a synchronization that followed
+  // its last upload.
   const size_t bp = static_cast<size_t>(l.Bp);
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
-  const size_t pin_need = al(bp * 4) + al(bp * sizeof(Inst)) + al(bp * 4) + al(bp * 8) + al(bp * 4);
+  const size_t pin_need = 2 * al(bp * 4) + 2 * al(bp * sizeof(Inst)) + 2 * al(bp * 4) + al(bp * 8);
+  const size_t up_bytes = 2 * al(bp * 4) + bp * 8;
+  if (l.asig != l.slist + al(bp * 4) || l.alam != l.asig + al(bp * 4)) {
+    set_error("batched path: internal layout error");
+    return DS_EDEVICE;
+  }
   if (C.pin_bytes < pin_need) {
     if (C.pin != nullptr) (void)hipHostFree(C.pin);
     C.pin = nullptr;
@@ -413,31 +431,42 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
     C.pin_bytes = pin_need;
   }
   char* pp = static_cast<char*>(C.pin);
-  int* h_flag = reinterpret_cast<int*>(pp);
-  Inst* h_inst = reinterpret_cast<Inst*>(pp + al(bp * 4));
-  int* slot_sig = reinterpret_cast<int*>(pp + al(bp * 4) + al(bp * sizeof(Inst)));
-  double* lam_slot = reinterpret_cast<double*>(pp + al(bp * 4) + al(bp * sizeof(Inst)) + al(bp * 4));
-  int* h_list = reinterpret_cast<int*>(pp + al(bp * 4) + al(bp * sizeof(Inst)) + al(bp * 4) + al(bp * 8));
+  int* h_flag[2] = {reinterpret_cast<int*>(pp), reinterpret_cast<int*>(pp + al(bp * 4))};
+  pp += 2 * al(bp * 4);
+  Inst* h_inst[2] = {reinterpret_cast<Inst*>(pp), reinterpret_cast<Inst*>(pp + al(bp * sizeof(Inst)))};
+  pp += 2 * al(bp * sizeof(Inst));
+  int* h_list = reinterpret_cast<int*>(pp);
+  int* h_asig = reinterpret_cast<int*>(pp + al(bp * 4));
+  double* h_alam = reinterpret_cast<double*>(pp + 2 * al(bp * 4));
 
   // The feed hands out signals (a column of Y and X, and a penalty) as slots free up;
-  // slot k holds column slot_sig[k], or -1 when idle.
-  std::fill(slot_sig, slot_sig + bp, -1);
-  std::fill(lam_slot, lam_slot + bp, 1.0);
+  // slot k holds column slot_sig[k], or -1 when idle (the device's perm, which the harvest
+  // clears and k_b_assign sets, mirrors it).
+  std::vector<int> slot_sig(bp, -1);
   std::vector<int> cols(nslot);
   std::vector<double> lams(nslot);
   const int n0 = feed.pull(nslot, cols.data(), lams.data(), s);
   if (n0 <= 0) return DS_OK;
-  for (int k = 0; k < n0; ++k) {
-    slot_sig[k] = cols[k];
-    lam_slot[k] = lams[k];
+  for (int k = 0; k < l.Bp; ++k) {
+    slot_sig[k] = k < n0 ? cols[k] : -1;
+    h_list[k] = k;
+    h_asig[k] = slot_sig[k];
+    h_alam[k] = k < n0 ? lams[k] : 1.0;
   }
   int* d_perm = reinterpret_cast<int*>(base + l.perm);
   double* d_lam = reinterpret_cast<double*>(base + l.lam);
   int* d_list = reinterpret_cast<int*>(base + l.slist);
-  std::iota(h_list, h_list + bp, 0);
-  DS_HIP(hipMemcpyAsync(d_perm, slot_sig, bp * sizeof(int), hipMemcpyHostToDevice, s));
-  DS_HIP(hipMemcpyAsync(d_lam, lam_slot, bp * sizeof(double), hipMemcpyHostToDevice, s));
-  DS_HIP(hipMemcpyAsync(d_list, h_list, bp * sizeof(int), hipMemcpyHostToDevice, s));
+  // upload an assignment of n slots and apply it to perm and lam
+  auto assign = [&](int n) -> ds_status {
+    DS_HIP(hipMemcpyAsync(d_list, h_list, up_bytes, hipMemcpyHostToDevice, s));
+    DS_HIP(hipEventRecord(C.evu, s));
+    hipLaunchKernelGGL(k_b_assign, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d_perm, d_lam,
+                       static_cast<const int*>(d_list), reinterpret_cast<const int*>(base + l.asig),
+                       reinterpret_cast<const double*>(base + l.alam), n);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+  };
+  if ((e = assign(l.Bp)) != DS_OK) return e;
 
   // ---------------------------------------------------------------- setup
   StatAccum& S = stats();
@@ -622,16 +651,19 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
 
   // Runs of ITERS_PER_GRAPH iterations (graph replays, or direct launches when instrumented)
   // while any slot holds a signal.  After each run the device harvests the signals that
-  // finished (counts, x into column perm[k] of X, the screened mask) and one round trip
-  // brings back the harvest flags and the slots' states; the finished signals report (the
-  // feed's finish) and free slots take the signals the feed has waiting.
+  // finished (counts, x into column perm[k] of X, the screened mask) and the harvest flags
+  // and slot states go to the host; the finished signals report (the feed's finish) and
+  // free slots take the signals the feed has waiting.  When the feed had nothing waiting
+  // at the last pull, the next run is enqueued before the host waits for the current one
+  // (finished signals are frozen and harvested once, so the extra run only delays the
+  // refill of their slots); instrumented runs do not overlap.
   int* d_flag = reinterpret_cast<int*>(base + l.dflag);
   std::vector<int> fcols;
   std::vector<ds_info> finfo;
   double act = 0.0, sup = 0.0;  // work of the finished signals (statistics)
   int nactive = n0;             // slots holding a signal
   int t = 0;
-  while (nactive > 0) {
+  auto enqueue_run = [&](int buf) -> ds_status {
     if (stat_on) {
       for (int k = 0; k < ITERS_PER_GRAPH; ++k) iteration(++t, true);
       DS_HIP(hipGetLastError());
@@ -639,41 +671,69 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
       DS_HIP(hipGraphLaunch(C.exec, s));
       t += ITERS_PER_GRAPH;
     }
-    hipLaunchKernelGGL(k_b_harvest, dim3(l.Bp), dim3(TB), 0, s, a, d_perm, X, ldx, screened, d_flag);
+    int* fl = d_flag + buf * l.Bp;
+    hipLaunchKernelGGL(k_b_harvest, dim3(l.Bp), dim3(TB), 0, s, a, d_perm, X, ldx, screened, fl);
     DS_HIP(hipGetLastError());
-    DS_HIP(hipMemcpyAsync(h_flag, d_flag, bp * sizeof(int), hipMemcpyDeviceToHost, s));
-    DS_HIP(hipMemcpyAsync(h_inst, a.inst, bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
-    DS_HIP(hipStreamSynchronize(s));
+    DS_HIP(hipMemcpyAsync(h_flag[buf], fl, bp * sizeof(int), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipMemcpyAsync(h_inst[buf], a.inst, bp * sizeof(Inst), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipEventRecord(C.evh[buf], s));
+    return DS_OK;
+  };
+  // the host's part of a run whose results are in buffer buf
+  auto collect = [&](int buf) -> ds_status {
+    DS_HIP(hipEventSynchronize(C.evh[buf]));
     fcols.clear();
     finfo.clear();
     for (int k = 0; k < l.Bp; ++k) {
-      if (h_flag[k] == 0) continue;
+      if (h_flag[buf][k] == 0) continue;
       fcols.push_back(slot_sig[k]);
-      finfo.push_back(info_of(h_inst[k], L));
-      act += h_inst[k].act_sum;
-      sup += h_inst[k].sup_sum;
+      finfo.push_back(info_of(h_inst[buf][k], L));
+      act += h_inst[buf][k].act_sum;
+      sup += h_inst[buf][k].sup_sum;
       slot_sig[k] = -1;
       --nactive;
     }
     if (!fcols.empty()) feed.finish(fcols.data(), finfo.data(), static_cast<int>(fcols.size()), s);
+    return DS_OK;
+  };
+  bool waiting = true;  // the feed may have signals waiting
+  int cur = 0;
+  if ((e = enqueue_run(cur)) != DS_OK) return e;
+  for (;;) {
+    const bool ahead = !stat_on && !waiting;
+    if (ahead && (e = enqueue_run(cur ^ 1)) != DS_OK) return e;
+    if ((e = collect(cur)) != DS_OK) return e;
     const int room = nslot - nactive;
     const int got = room > 0 ? feed.pull(room, cols.data(), lams.data(), s) : 0;
+    waiting = room > 0 && got == room;
     if (got > 0) {
+      DS_HIP(hipEventSynchronize(C.evu));  // the staging of the previous assignment is free
       int nref = 0;
       for (int k = 0, q = 0; k < nslot && q < got; ++k) {
         if (slot_sig[k] >= 0) continue;
         slot_sig[k] = cols[q];
-        lam_slot[k] = lams[q];
+        h_list[nref] = k;
+        h_asig[nref] = cols[q];
+        h_alam[nref] = lams[q];
+        ++nref;
         ++q;
-        h_list[nref++] = k;
       }
       nactive += got;
-      DS_HIP(hipMemcpyAsync(d_perm, slot_sig, bp * sizeof(int), hipMemcpyHostToDevice, s));
-      DS_HIP(hipMemcpyAsync(d_lam, lam_slot, bp * sizeof(double), hipMemcpyHostToDevice, s));
-      DS_HIP(hipMemcpyAsync(d_list, h_list, nref * sizeof(int), hipMemcpyHostToDevice, s));
+      if ((e = assign(nref)) != DS_OK) return e;
       if ((e = setup_slots(got, got)) != DS_OK) return e;
     }
+    cur ^= 1;
+    if (ahead) {
+      if (nactive == 0) {  // the run enqueued ahead found nothing to do
+        if ((e = collect(cur)) != DS_OK) return e;
+        break;
+      }
+    } else {
+      if (nactive == 0) break;
+      if ((e = enqueue_run(cur)) != DS_OK) return e;
+    }
   }
+  DS_HIP(hipStreamSynchronize(s));
 
   if (stat_on) {
     double ms_z = 0.0, ms_zev = 0.0, ms_t = 0.0, ms_s = 0.0;

@@ -1453,6 +1453,17 @@ __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
   }
 }
 
+// A slot assignment: perm[list[j]] = sig[j] (-1: idle) and lam[list[j]] = lamv[j], j < n.
+__global__ __launch_bounds__(TB) void k_b_assign(int* __restrict__ perm, double* __restrict__ lam,
+                                                 const int* __restrict__ list,
+                                                 const int* __restrict__ sig,
+                                                 const double* __restrict__ lamv, int n) {
+  const int j = blockIdx.x * TB + threadIdx.x;
+  if (j >= n) return;
+  perm[list[j]] = sig[j];
+  lam[list[j]] = lamv[j];
+}
+
 // ============================================================== output
 // After each run of iterations, one block per slot: a slot that holds a signal (perm[s] >= 0)
 // and has finished is harvested: its counts for the report (non-zeros of x, atoms active in
@@ -1473,15 +1484,27 @@ __global__ __launch_bounds__(TB) void k_b_harvest(BArgs a, int* __restrict__ per
   if (!fin) return;
   const bool trivial = st.status != 0;
   const double rp = st.r_prev;
+  constexpr int HU = 8;  // atoms per thread whose loads are issued before the first store
   int nz = 0, na = 0;
-  for (int i = threadIdx.x; i < a.K; i += TB) {
-    const int64_t o = static_cast<int64_t>(s) * a.Kp + i;
-    const float xv = a.X[o];
-    const bool act = static_cast<double>(a.marg[o]) <= rp;
-    nz += xv != 0.f;
-    na += act;
-    Xout[static_cast<int64_t>(b) * ldx + i] = trivial ? 0.f : xv;
-    if (scr != nullptr) scr[static_cast<int64_t>(b) * a.K + i] = (trivial || !act) ? 1 : 0;
+  const int64_t o = static_cast<int64_t>(s) * a.Kp;
+  for (int i0 = threadIdx.x; i0 < a.K; i0 += TB * HU) {
+    float xv[HU], mv[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int i = min(i0 + u * TB, a.K - 1);
+      xv[u] = a.X[o + i];
+      mv[u] = a.marg[o + i];
+    }
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int i = i0 + u * TB;
+      if (i >= a.K) break;
+      const bool act = static_cast<double>(mv[u]) <= rp;
+      nz += xv[u] != 0.f;
+      na += act;
+      Xout[static_cast<int64_t>(b) * ldx + i] = trivial ? 0.f : xv[u];
+      if (scr != nullptr) scr[static_cast<int64_t>(b) * a.K + i] = (trivial || !act) ? 1 : 0;
+    }
   }
   nz = block_sum<int, NWB>(nz, si);  // every thread has read perm[s] before this barrier
   na = block_sum<int, NWB>(na, si);
