@@ -196,60 +196,95 @@ __global__ __launch_bounds__(TB) void k_b_load_slots(BArgs a, const float* __res
 // Block: a tile of 16 atoms x 16 list entries (entries past nsl repeat the last slot and
 // are not stored).  Operands: lane l holds A[i][k] = d_{a0+i}[kQ + s] and B[k][j] =
 // v_{b0+j}[kQ + s] (i = j = l % 16, k = l / 16); the accumulator's element r of lane l is
-// C[4r + l / 16][l % 16].  Each lane reads its own rows of D and V contiguously, 4 groups
-// per load.
+// C[4r + l / 16][l % 16].  A wave's operand rows form 64 segments of A (atom, k) and 64 of
+// B (entry, k); per batch of GB groups the wave loads each segment whole (8-byte pieces,
+// consecutive lanes on consecutive pieces) into its own LDS area, padded so that the 64
+// lanes' operand reads fall in different banks, and the next batch's loads are in flight
+// while the matrix cores consume one.
 typedef double dtv_acc __attribute__((ext_vector_type(4)));
 template <typename VT>
 __global__ __launch_bounds__(TB) void k_b_dtv(const uint16_t* __restrict__ dcm,
                                               const VT* __restrict__ V, int Np, int Kp,
                                               double* __restrict__ out,
                                               const int* __restrict__ slots, int nsl) {
-  constexpr int GB = 32;  // groups per batch of loads (GB / 4 loads of A and of B in flight)
+  constexpr int VB = static_cast<int>(sizeof(VT));
+  constexpr int GB = 128 / VB;          // groups per batch (a B segment is 128 bytes)
+  constexpr int SA = GB * 2 + 4;        // LDS bytes per A segment (bfloat16, padded)
+  constexpr int SB = GB * VB + (VB == 4 ? 4 : 8);  // LDS bytes per B segment (padded, VT-aligned)
+  constexpr int RA = 4, RB = 8 / VB;    // rows per 8-byte piece of A and of B
+  constexpr int PA = GB / RA, PB = GB / RB;  // pieces per segment (= pieces per lane)
+  constexpr int WL = 64 * (SA + SB);    // LDS bytes per wave
+  __shared__ __align__(16) unsigned char lds[NWB * WL];
   __shared__ dtv_acc part[NWB - 1][BW];
   const int tid = threadIdx.x, lane = tid % BW, wave = tid / BW;
   const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
   const int q16 = lane % 16, k = lane / 16;
   const int Q = Np / 4, S = Q / NWB;  // groups per wave (a multiple of 4: Np % 64 == 0)
   const int s0 = wave * S;
-  const uint16_t* pa = dcm + static_cast<int64_t>(a0 + q16) * Np + k * Q + s0;
-  const VT* pb = V + static_cast<int64_t>(slots[min(b0 + q16, nsl - 1)]) * Np + k * Q + s0;
-  dtv_acc acc = {0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < S; s += GB) {
-    uint2 qa[GB / 4];
-    VT vb[GB / 4][4];
+  unsigned char* la = lds + wave * WL;
+  unsigned char* lb = la + 64 * SA;
+  // piece q of this lane: p = q * 64 + lane, segment p / P (atom or entry seg / 4, k =
+  // seg % 4), rows (p % P) * R .. + R - 1 of the batch
+  const uint16_t* ga[PA];
+  const VT* gb[PB];
 #pragma unroll
-    for (int q = 0; q < GB / 4; ++q) {
-      const int g = min(s + 4 * q, S - 4);  // past the end: re-read the last 4 groups, unused
-      qa[q] = *reinterpret_cast<const uint2*>(pa + g);
-      if constexpr (sizeof(VT) == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(pb + g);
-        vb[q][0] = v.x;
-        vb[q][1] = v.y;
-        vb[q][2] = v.z;
-        vb[q][3] = v.w;
-      } else {
-        const double2 v0 = *reinterpret_cast<const double2*>(pb + g);
-        const double2 v1 = *reinterpret_cast<const double2*>(pb + g + 2);
-        vb[q][0] = v0.x;
-        vb[q][1] = v0.y;
-        vb[q][2] = v1.x;
-        vb[q][3] = v1.y;
-      }
+  for (int q = 0; q < PA; ++q) {
+    const int seg = (q * BW + lane) / PA;
+    ga[q] = dcm + static_cast<int64_t>(a0 + seg / 4) * Np + (seg % 4) * Q + s0;
+  }
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    const int seg = (q * BW + lane) / PB;
+    const int slot = slots[min(b0 + seg / 4, nsl - 1)];
+    gb[q] = V + static_cast<int64_t>(slot) * Np + (seg % 4) * Q + s0;
+  }
+  uint2 ra[PA], rb[PB];
+  // the pieces of the batch starting at group s; a piece past the wave's range re-reads its
+  // last rows (staged but never multiplied), so every load stays inside the range
+  auto load = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int r = min(s + ((q * BW + lane) % PA) * RA, S - RA);
+      ra[q] = *reinterpret_cast<const uint2*>(ga[q] + r);
     }
-    // every load of the batch is issued before the first product (a branch past the end
-    // would let the compiler sink each load to its use); groups past the end multiply zeros
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < GB / 4; ++q) {
-      const bool live = s + 4 * q < S;
-      const uint32_t w0 = live ? qa[q].x : 0u, w1 = live ? qa[q].y : 0u;
-      const float af[4] = {__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xffff0000u),
-                           __uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
+    for (int q = 0; q < PB; ++q) {
+      const int r = min(s + ((q * BW + lane) % PB) * RB, S - RB);
+      rb[q] = *reinterpret_cast<const uint2*>(gb[q] + r);
+    }
+  };
+  dtv_acc acc = {0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int s = 0; s < S; s += GB) {
+    __syncthreads();  // the previous batch has been consumed
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(af[r]),
-                                                   live ? static_cast<double>(vb[q][r]) : 0.0,
-                                                   acc, 0, 0, 0);
+    for (int q = 0; q < PA; ++q) {
+      const int p = q * BW + lane;
+      uint32_t* d = reinterpret_cast<uint32_t*>(la + (p / PA) * SA + (p % PA) * 8);
+      d[0] = ra[q].x;
+      d[1] = ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int p = q * BW + lane;
+      uint32_t* d = reinterpret_cast<uint32_t*>(lb + (p / PB) * SB + (p % PB) * 8);
+      d[0] = rb[q].x;
+      d[1] = rb[q].y;
+    }
+    __syncthreads();
+    if (s + GB < S) load(s + GB);
+    const unsigned char* pa = la + (q16 * 4 + k) * SA;
+    const unsigned char* pb = lb + (q16 * 4 + k) * SB;
+    const int n = min(GB, S - s);  // a multiple of 4
+    for (int g = 0; g < n; g += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint16_t av = *reinterpret_cast<const uint16_t*>(pa + (g + u) * 2);
+        const VT bv = *reinterpret_cast<const VT*>(pb + (g + u) * VB);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            static_cast<double>(__uint_as_float(static_cast<uint32_t>(av) << 16)),
+            static_cast<double>(bv), acc, 0, 0, 0);
+      }
     }
   }
   if (wave > 0) part[wave - 1][lane] = acc;
