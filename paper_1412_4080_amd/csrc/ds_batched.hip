@@ -705,7 +705,7 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
     if ((e = collect(cur)) != DS_OK) return e;
     const int room = nslot - nactive;
     const int got = room > 0 ? feed.pull(room, cols.data(), lams.data(), s) : 0;
-    waiting = room > 0 && got == room;
+    if (room > 0) waiting = got == room;  // (no room: as after the last pull)
     if (got > 0) {
       DS_HIP(hipEventSynchronize(C.evu));  // the staging of the previous assignment is free
       int nref = 0;

@@ -339,9 +339,14 @@ __global__ __launch_bounds__(TB) void k_b_inst_init(BArgs a, const double* __res
   const double* z = z0 + static_cast<int64_t>(s) * a.Kp;
   double best = -1.0;
   int barg = 0x7fffffff;
-  for (int i = tid; i < a.K; i += TB) {
-    const double v = fabs(z[i]);
-    if (v > best) { best = v; barg = i; }
+  constexpr int IU = 8;  // loads issued before the first comparison (same order of i)
+  for (int i0 = tid; i0 < a.K; i0 += TB * IU) {
+    double v[IU];
+#pragma unroll
+    for (int u = 0; u < IU; ++u) v[u] = fabs(z[min(i0 + u * TB, a.K - 1)]);
+#pragma unroll
+    for (int u = 0; u < IU; ++u)
+      if (i0 + u * TB < a.K && v[u] > best) { best = v[u]; barg = i0 + u * TB; }
   }
   for (int o = BW / 2; o > 0; o >>= 1) {
     const double ob = __shfl_xor(best, o, BW);
