@@ -102,8 +102,9 @@ ds_status solve_batched_bf16(const ds_problem& P, const void* Y, int64_t B, int6
 // pull for up to `room` new signals (fills the Y / X column and the penalty of each, returns
 // how many; 0 when none is waiting; a copy into Y enqueued on the engine's stream `s` is
 // ordered before the signals' set-up) and hands finished ones to finish (their X columns
-// and masks are written and `s` is synchronized).  A run ends when no slot holds a signal
-// after a pull.
+// and masks are written: the harvest that wrote them has completed).  The engine's stream
+// may already run the next replay when finish is called.  A run ends when no slot holds a
+// signal after a pull.
 struct BatchFeed {
   std::function<int(int room, int* cols, double* lams, hipStream_t s)> pull;
   std::function<void(const int* cols, const ds_info* infos, int n, hipStream_t s)> finish;
