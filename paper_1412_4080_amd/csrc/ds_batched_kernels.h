@@ -655,52 +655,109 @@ __global__ __launch_bounds__(TB) void k_b_theta(BArgs a, const float* __restrict
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int nw = a.Kp / MT;
   const float* u = Uin + static_cast<int64_t>(s) * a.Kp;
-  // mask words of the first round; each later round's words are fetched while the
-  // current round streams
-  uint32_t m_next =
-      (threadIdx.x < TW && threadIdx.x < nw) ? a.umask[static_cast<int64_t>(threadIdx.x) * a.Bp + s] : 0u;
-  for (int w0 = 0; w0 < nw; w0 += TW) {
-    const int w = w0 + threadIdx.x;
-    uint32_t m = m_next;
-    int total;
-    int pos = block_exclusive_scan<NWB>(__popc(m), scan, &total);
-    while (m != 0u) {
-      sidx[pos++] = w * MT + __ffs(m) - 1;
-      m &= m - 1u;
-    }
-    __syncthreads();
-    const int wn = w + TW;
-    m_next = (threadIdx.x < TW && wn < nw) ? a.umask[static_cast<int64_t>(wn) * a.Bp + s] : 0u;
-    if (rows_ok) {
-      // Wave w takes list entries w, w + 4, w + 8, ... in increasing order (GB of them
-      // per batch, every load of a batch issued before the first FMA).  Entries past the
-      // end re-read the last one with weight zero: the accumulators start at +0 and a sum
-      // never rounds to -0, so adding a zero product leaves them bit for bit unchanged.
-      constexpr int GB = 8;
-      for (int j0 = 0; j0 < total; j0 += NWB * GB) {
-        int at[GB];
+  // Stream the `total` entries of the support list in sidx: wave w takes entries w, w + 4,
+  // w + 8, ... in increasing order, GB of them per batch, every load of a batch issued before
+  // its first FMA and the next batch's loads in flight while a batch is multiplied.
+  // Entries past the end re-read the last one with weight zero: the accumulators start at
+  // +0 and a sum never rounds to -0, so adding a zero product leaves them bit for bit
+  // unchanged.
+  constexpr int GB = 8;
+  struct Batch {
+    float uv[GB];
+    uint4 d[GB];
+  };
+  auto stream = [&](int total) {
+    if (!rows_ok || total == 0) return;
+    const int nb = (total + NWB * GB - 1) / (NWB * GB);
+    auto issue = [&](Batch& X, int b) {
+      const int j0 = b * NWB * GB;
+      int at[GB];
 #pragma unroll
-        for (int g = 0; g < GB; ++g) at[g] = sidx[min(j0 + wave + NWB * g, total - 1)];
-        float uv[GB];
-        uint4 d[GB];
+      for (int g = 0; g < GB; ++g) at[g] = sidx[min(j0 + wave + NWB * g, total - 1)];
 #pragma unroll
-        for (int g = 0; g < GB; ++g) uv[g] = u[at[g]];
+      for (int g = 0; g < GB; ++g) X.uv[g] = u[at[g]];
 #pragma unroll
-        for (int g = 0; g < GB; ++g) d[g] = ldg16(a.dcm + static_cast<int64_t>(at[g]) * a.Np + nl);
-        __builtin_amdgcn_sched_barrier(0);
+      for (int g = 0; g < GB; ++g) X.d[g] = ldg16(a.dcm + static_cast<int64_t>(at[g]) * a.Np + nl);
+    };
+    auto compute = [&](const Batch& X, int b) {
+      const int j0 = b * NWB * GB;
 #pragma unroll
-        for (int g = 0; g < GB; ++g) {
-          const double ug = j0 + wave + NWB * g < total ? static_cast<double>(uv[g]) : 0.0;
-          const uint32_t wd[4] = {d[g].x, d[g].y, d[g].z, d[g].w};
+      for (int g = 0; g < GB; ++g) {
+        const double ug = j0 + wave + NWB * g < total ? static_cast<double>(X.uv[g]) : 0.0;
+        const uint32_t wd[4] = {X.d[g].x, X.d[g].y, X.d[g].z, X.d[g].w};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            acc[2 * e] = fma(static_cast<double>(__uint_as_float(wd[e] << 16)), ug, acc[2 * e]);
-            acc[2 * e + 1] = fma(static_cast<double>(__uint_as_float(wd[e] & 0xffff0000u)), ug, acc[2 * e + 1]);
-          }
+        for (int e = 0; e < 4; ++e) {
+          acc[2 * e] = fma(static_cast<double>(__uint_as_float(wd[e] << 16)), ug, acc[2 * e]);
+          acc[2 * e + 1] = fma(static_cast<double>(__uint_as_float(wd[e] & 0xffff0000u)), ug, acc[2 * e + 1]);
         }
       }
+    };
+    Batch A, Bt;
+    issue(A, 0);
+    for (int b = 0; b < nb; b += 2) {
+      if (b + 1 < nb) issue(Bt, b + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(A, b);
+      if (b + 1 >= nb) break;
+      if (b + 2 < nb) issue(A, b + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(Bt, b + 1);
+    }
+  };
+  // The whole support list in one pass when the mask words fit four per thread and the
+  // support fits sidx (the usual case): thread t scans words t*wpt .. t*wpt + wpt - 1, so
+  // the block scan of the counts places the atoms in increasing order.
+  bool listed = false;
+  constexpr int WPT = 4;
+  if (nw <= TB * WPT) {
+    const int wpt = (nw + TB - 1) / TB;
+    uint32_t mw[WPT];
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int w = threadIdx.x * wpt + q;
+      const uint32_t v = a.umask[static_cast<int64_t>(min(w, nw - 1)) * a.Bp + s];
+      mw[q] = (q < wpt && w < nw) ? v : 0u;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) cnt += __popc(mw[q]);
+    int total;
+    int pos = block_exclusive_scan<NWB>(cnt, scan, &total);
+    if (total <= TW * MT) {
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        uint32_t m = mw[q];
+        const int w = threadIdx.x * wpt + q;
+        while (m != 0u) {
+          sidx[pos++] = w * MT + __ffs(m) - 1;
+          m &= m - 1u;
+        }
+      }
+      __syncthreads();
+      stream(total);
+      listed = true;
     }
     __syncthreads();
+  }
+  if (!listed) {
+    // rounds of TW mask words; each later round's words are fetched while a round streams
+    uint32_t m_next =
+        (threadIdx.x < TW && threadIdx.x < nw) ? a.umask[static_cast<int64_t>(threadIdx.x) * a.Bp + s] : 0u;
+    for (int w0 = 0; w0 < nw; w0 += TW) {
+      const int w = w0 + threadIdx.x;
+      uint32_t m = m_next;
+      int total;
+      int pos = block_exclusive_scan<NWB>(__popc(m), scan, &total);
+      while (m != 0u) {
+        sidx[pos++] = w * MT + __ffs(m) - 1;
+        m &= m - 1u;
+      }
+      __syncthreads();
+      const int wn = w + TW;
+      m_next = (threadIdx.x < TW && wn < nw) ? a.umask[static_cast<int64_t>(wn) * a.Bp + s] : 0u;
+      stream(total);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) red[wave][lane * 8 + k] = acc[k];
