@@ -613,7 +613,7 @@ ds_status run_batched(BatchEngine& C, const ds_problem& P, const float* Y, int64
     if (l.G > 0)
       hipLaunchKernelGGL(k_b_gprox, dim3((l.G + TB - 1) / TB, l.Bp), dim3(TB), 0, s, a,
                          static_cast<const float*>(Uin), Uout);
-    hipLaunchKernelGGL(k_b_scalars, g_slot4, dim3(TB), 0, s, a);
+    hipLaunchKernelGGL(k_b_scalars, dim3(l.Bp / 16), dim3(TB), 0, s, a);
     if (l.G > 0) {
       hipLaunchKernelGGL(k_b_gvcand, g_vca, dim3(TB), 0, s, a);
       hipLaunchKernelGGL(k_b_gvdot, g_vdot, dim3(TB), 0, s, a);

@@ -1136,11 +1136,15 @@ __global__ __launch_bounds__(TB) void k_b_gprox(BArgs a, const float* __restrict
 // the accumulation slack, screening threshold for the next iteration.  Flags the signal
 // for the exact gap when the estimate meets tolerance or the budget is spent.
 __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
-  const int lane = threadIdx.x % BW;
-  const int s = blockIdx.x * NWB + threadIdx.x / BW;
-  if (s >= a.Bp) return;
-  Inst& st = a.inst[s];
-  if (st.done != 0) return;
+  // Block: SPB consecutive signals x TG tile groups.  Thread (tg, sl) sums the partial
+  // entries tg, tg + TG, ... of signal s0 + sl in that order (a wave reads SPB consecutive
+  // signals of four entries per load: whole cache lines), then the TG sums of a signal are
+  // combined in group order and one thread per signal forms its scalars.
+  constexpr int SPB = 16, TG = TB / SPB;
+  __shared__ double r_z[TG][SPB], r_o[TG][SPB], r_t[TG][SPB], r_y[TG][SPB];
+  __shared__ int r_a[TG][SPB], r_s[TG][SPB];
+  const int sl = threadIdx.x % SPB, tg = threadIdx.x / SPB;
+  const int s = blockIdx.x * SPB + sl;  // Bp is a multiple of 64
   // partial entries: 32-atom tiles (Lasso) or 64-group chunks, whose counts pack the
   // active atoms and the non-zeros of p in 8- or 16-bit fields
   const int ntile = a.G > 0 ? (a.G + GCH - 1) / GCH : a.Kp / MT;
@@ -1148,50 +1152,53 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   const int cm = (1 << cb) - 1;
   double zm = 0.0, om = 0.0;
   int nact = 0, nsup = 0;
-  // the first QT entries of every lane (K <= 16384) in one round trip: unconditional loads
-  // at clamped indices, then the lane's sums in entry order
+  // QT entries per thread per round trip: unconditional loads at clamped indices, then the
+  // sums in entry order
   constexpr int QT = 8;
-  double qz[QT], qo[QT];
-  int qa[QT];
+  for (int t0 = tg; t0 < ntile; t0 += TG * QT) {
+    double qz[QT], qo[QT];
+    int qa[QT];
 #pragma unroll
-  for (int q = 0; q < QT; ++q) {
-    const int64_t o = static_cast<int64_t>(min(lane + q * BW, ntile - 1)) * a.Bp + s;
-    qz[q] = a.pz[o];
-    qo[q] = a.pom[o];
-    qa[q] = a.pact[o];
-  }
-  const int kr = min(lane, a.nrb - 1);
-  const double q_tt = a.ptt[static_cast<int64_t>(kr) * a.Bp + s];
-  const double q_ty = a.pty[static_cast<int64_t>(kr) * a.Bp + s];
+    for (int q = 0; q < QT; ++q) {
+      const int64_t o = static_cast<int64_t>(min(t0 + q * TG, ntile - 1)) * a.Bp + s;
+      qz[q] = a.pz[o];
+      qo[q] = a.pom[o];
+      qa[q] = a.pact[o];
+    }
 #pragma unroll
-  for (int q = 0; q < QT; ++q) {
-    if (lane + q * BW < ntile) {
-      zm = fmax(zm, qz[q]);
-      om += qo[q];
-      nact += qa[q] & cm;
-      nsup += qa[q] >> cb;
+    for (int q = 0; q < QT; ++q) {
+      if (t0 + q * TG < ntile) {
+        zm = fmax(zm, qz[q]);
+        om += qo[q];
+        nact += qa[q] & cm;
+        nsup += qa[q] >> cb;
+      }
     }
   }
-  for (int t = lane + QT * BW; t < ntile; t += BW) {
-    const int64_t o = static_cast<int64_t>(t) * a.Bp + s;
-    zm = fmax(zm, a.pz[o]);
-    om += a.pom[o];
-    const int c = a.pact[o];
-    nact += c & cm;
-    nsup += c >> cb;
-  }
-  double tt = lane < a.nrb ? q_tt : 0.0, ty = lane < a.nrb ? q_ty : 0.0;
-  for (int c = lane + BW; c < a.nrb; c += BW) {
+  double tt = 0.0, ty = 0.0;
+  for (int c = tg; c < a.nrb; c += TG) {
     tt += a.ptt[static_cast<int64_t>(c) * a.Bp + s];
     ty += a.pty[static_cast<int64_t>(c) * a.Bp + s];
   }
-  zm = wave_max(zm);
-  om = wave_sum(om);
-  tt = wave_sum(tt);
-  ty = wave_sum(ty);
-  nact = wave_sum(nact);
-  nsup = wave_sum(nsup);
-  if (lane != 0) return;
+  r_z[tg][sl] = zm;
+  r_o[tg][sl] = om;
+  r_t[tg][sl] = tt;
+  r_y[tg][sl] = ty;
+  r_a[tg][sl] = nact;
+  r_s[tg][sl] = nsup;
+  __syncthreads();
+  if (tg != 0) return;
+#pragma unroll
+  for (int k = 1; k < TG; ++k) {
+    zm = fmax(zm, r_z[k][sl]);
+    om += r_o[k][sl];
+    tt += r_t[k][sl];
+    ty += r_y[k][sl];
+    nact += r_a[k][sl];
+    nsup += r_s[k][sl];
+  }
+  Inst& st = a.inst[s];
+  if (st.done != 0) return;
   // every field read before the first store: a load issued after a store waits for it
   const int t = st.iter + 1;
   const double lam = st.lam, yy = st.yy, rho2 = st.rho2;
