@@ -1073,6 +1073,8 @@ def main():
                          "(no warmup); 'batched-instrumented' only one instrumented "
                          "batched solve; 'large-instrumented' only the large-dictionary leg")
     ap.add_argument("--serve-slots", type=int, default=8, help="worker slots of the serving leg")
+    ap.add_argument("--serve-batch-slots", type=int, default=64,
+                    help="resident signals of each batched engine in the serving mix's engine run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (a plain copy kernel of known "
                          "size, for scaling HBM counters)")
@@ -1224,7 +1226,7 @@ def main():
     if "served" in legs:
         out["served"] = served_leg(binding, slots=args.serve_slots)
         out["served"]["batched_engine"] = served_leg(binding, slots=args.serve_slots,
-                                                     batch_slots=64)
+                                                     batch_slots=args.serve_batch_slots)
     if "served_batched" in legs:
         out["served_bf16_one_dictionary"] = served_batched_leg(binding, D)
     if not args.no_cpu:
