@@ -114,7 +114,7 @@ STREAM_SIGNALS = 1024
 
 def batched_stream_leg(binding, D, steps=2):
     """Continuous batching: 1024 signals of the batched workload's generator through the
-    default 256 resident slots of the bfloat16 path (a finished signal's slot takes the next
+    default 512 resident slots of the bfloat16 path (a finished signal's slot takes the next
     waiting one), lambda / lambda_* uniform in [0.1, 0.9], gap 1e-6: solves/s."""
     import torch
     Dbf = datagen.to_storage(D, "bf16")
@@ -138,8 +138,8 @@ def batched_stream_leg(binding, D, steps=2):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     it = [i["iters"] for i in infos]
-    return {"workload": "lasso_fista_dst3_gaussian_2000x10000_bf16_stream1024_slots256",
-            "signals": STREAM_SIGNALS, "slots": 256,
+    return {"workload": "lasso_fista_dst3_gaussian_2000x10000_bf16_stream1024_slots512",
+            "signals": STREAM_SIGNALS, "slots": 512,
             "solves_per_s": round(STREAM_SIGNALS * steps / dt, 2),
             "ms_per_stream": round(dt * 1e3 / steps, 3),
             "iterations": {"max": int(max(it)), "mean": round(float(np.mean(it)), 1)}}
@@ -148,7 +148,7 @@ def batched_stream_leg(binding, D, steps=2):
 def served_batched_leg(binding, D, n_sat=1024, n_open=1500, warm=200, seed=datagen.ARRIVAL_SEED):
     """Requests for the batched workload's dictionary (2000 x 10000, stored in bfloat16;
     signals of its generator, lambda / lambda_* uniform in [0.1, 0.9], FISTA + DST3 to gap
-    1e-6) through the server: with a batched engine of 256 resident signals (requests join
+    1e-6) through the server: with a batched engine of 512 resident signals (requests join
     it as slots free up) and with the eight single-signal workers alone.  Saturation (all
     requests submitted at once), then Poisson arrivals at 0.5 x and 0.9 x the engine's
     saturation rate: solves/s and p50/p99 latency (submit to result, server clock)."""
@@ -198,7 +198,7 @@ def served_batched_leg(binding, D, n_sat=1024, n_open=1500, warm=200, seed=datag
     out = {"workload": "serving_lasso_fista_dst3_gaussian_2000x10000_bf16",
            "requests_saturation": n_sat}
     sat_rate = None
-    for name, bslots in (("batched_engine", 256), ("workers_only", 0)):
+    for name, bslots in (("batched_engine", 512), ("workers_only", 0)):
         S = binding.Server(max_slots=8, hbm_budget_bytes=24 << 30, max_queue=1 << 14,
                            batch_slots=bslots)
         did = S.add_dict(Dd, store="bf16")

@@ -145,7 +145,7 @@ typedef struct {
                         experiments section (there with 1e-7 and max_iter = 200).  Such a
                         stop returns DS_OK.  The batched bfloat16 path returns DS_EINVAL. */
   int32_t batch_slots; /* batched bfloat16 path: signals resident on the device at once
-                        (0: min(B, 256)).  When B exceeds it, the other signals wait and take
+                        (0: min(B, 512)).  When B exceeds it, the other signals wait and take
                         the slots of finished ones (continuous batching); results do not depend
                         on it.  Ignored elsewhere; must be >= 0. */
 } ds_params;

@@ -28,7 +28,7 @@ namespace {
 using namespace batch;
 
 constexpr int ITERS_PER_GRAPH = 8;  // iterations per graph replay (even)
-constexpr int MAX_SLOTS = 256;      // resident signals when the caller does not set batch_slots
+constexpr int MAX_SLOTS = 512;      // resident signals when the caller does not set batch_slots
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
