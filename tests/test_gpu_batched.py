@@ -202,12 +202,14 @@ def test_batched_static_screening(B):
         assert not X[mask[:, j], j].any()
 
 
-@pytest.mark.parametrize("rule,test", [("fista", "dst3"), ("ista", "safe")])
-def test_refilled_slots_give_the_same_results(B, rule, test):
+@pytest.mark.parametrize("rule,test,N,K", [("fista", "dst3", 320, 1500), ("ista", "safe", 320, 1500),
+                                           ("fista", "dst3", 40, 300)])
+def test_refilled_slots_give_the_same_results(B, rule, test, N, K):
     """Continuous batching: with fewer resident slots than signals, finished signals hand
     their slot to waiting ones.  Each signal's arithmetic does not depend on its slot or on
-    the other residents, so the results equal the all-resident solve bit for bit."""
-    D, Dbf, ys, ratios = _batch(320, 1500, 100, 9)
+    the other residents, so the results equal the all-resident solve bit for bit (also with
+    N below 64, where the set-up products' row groups are shortest)."""
+    D, Dbf, ys, ratios = _batch(N, K, 100, 9)
     Dd, Y = dev_matrix(D, "bf16"), _dev_Y(ys)
     L = oracle.spectral_norm_sq(Dbf)
     X0, i0, m0 = B.solve(Dd, Y, ratios, rule=rule, test=test, step_L=L, gap_tol=1e-6,
@@ -225,17 +227,17 @@ def test_refilled_slots_give_the_same_results(B, rule, test):
 
 
 def test_more_signals_than_slots_by_default(B):
-    """300 signals: 256 resident (the default), the rest refilled; the results equal a solve
+    """600 signals: 512 resident (the default), the rest refilled; the results equal a solve
     with every signal resident, and a few are certified against the oracle."""
-    D, Dbf, ys, ratios = _batch(200, 900, 300, 10)
+    D, Dbf, ys, ratios = _batch(200, 900, 600, 10)
     Dd, Y = dev_matrix(D, "bf16"), _dev_Y(ys)
     L = oracle.spectral_norm_sq(Dbf)
     X, infos = B.solve(Dd, Y, ratios, step_L=L, gap_tol=1e-6, max_iter=20000)
-    Xa, ia = B.solve(Dd, Y, ratios, step_L=L, gap_tol=1e-6, max_iter=20000, batch_slots=300)
+    Xa, ia = B.solve(Dd, Y, ratios, step_L=L, gap_tol=1e-6, max_iter=20000, batch_slots=600)
     assert np.array_equal(X.cpu().numpy(), Xa.cpu().numpy())
     assert [i["iters"] for i in infos] == [i["iters"] for i in ia]
     X = X.cpu().numpy().astype(np.float64)
-    for j in (0, 150, 299):
+    for j in (0, 300, 599):
         y = ys[j]
         assert infos[j]["status"] == 0 and infos[j]["gap"] <= 1e-6 * float(y @ y)
         star = oracle.solve_lasso(Dbf, y, lam=infos[j]["lambda_"], rule="fista", test="none",
