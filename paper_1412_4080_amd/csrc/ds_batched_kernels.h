@@ -1083,7 +1083,58 @@ __global__ __launch_bounds__(TB) void k_b_gprox(BArgs a, const float* __restrict
   int nact = 0, nsup = 0;
   if (g < a.G) {
     const int64_t g0 = a.gptr[g], g1 = a.gptr[g + 1];
-    if (g1 > g0 && static_cast<double>(a.marg[row + g0]) <= r_act) {
+    const int m = static_cast<int>(g1 - g0);
+    constexpr int GS = 16;  // groups up to this size: all loads issued before the first use
+    if (m > 0 && m <= GS && static_cast<double>(a.marg[row + g0]) <= r_act) {
+      // the same arithmetic, in the same order, as the loops below
+      float zl[GS], pl[GS], xl[GS];
+#pragma unroll
+      for (int k = 0; k < GS; ++k) {
+        const int64_t o = row + g0 + min(k, m - 1);
+        zl[k] = a.Z[o];
+        pl[k] = Uin[o];
+        xl[k] = a.X[o];
+      }
+      double zz = 0.0, vv = 0.0, pp = 0.0;
+#pragma unroll
+      for (int k = 0; k < GS; ++k) {
+        if (k < m) {
+          const double z = zl[k], p = pl[k];
+          const double v = p - z * invL;
+          zz = fma(z, z, zz);
+          vv = fma(v, v, vv);
+          pp = fma(p, p, pp);
+          nsup += p != 0.0;
+        }
+      }
+      const double w = a.gw[g];
+      nact = m;
+      zs = sqrt(zz) / w;
+      om = w * sqrt(pp);
+      const double nv = sqrt(vv);
+      const double sc = nv > 0.0 ? fmax(0.0, 1.0 - thr * w / nv) : 0.0;
+      uint32_t bits = 0u;
+      int64_t tile = g0 / MT;
+#pragma unroll
+      for (int k = 0; k < GS; ++k) {
+        if (k < m) {
+          const int64_t ka = g0 + k;
+          if (ka / MT != tile) {
+            if (bits != 0u) atomicOr(&a.umask[tile * a.Bp + s], bits);
+            bits = 0u;
+            tile = ka / MT;
+          }
+          const double z = zl[k], p = pl[k];
+          const double xn = sc * (p - z * invL);
+          const double un = xn + beta * (xn - static_cast<double>(xl[k]));
+          const float uf = static_cast<float>(un);
+          a.X[row + ka] = static_cast<float>(xn);
+          Uout[row + ka] = uf;
+          if (uf != 0.f) bits |= 1u << (ka % MT);
+        }
+      }
+      if (bits != 0u) atomicOr(&a.umask[tile * a.Bp + s], bits);
+    } else if (m > GS && static_cast<double>(a.marg[row + g0]) <= r_act) {
       double zz = 0.0, vv = 0.0, pp = 0.0;
       for (int64_t k = g0; k < g1; ++k) {
         const double z = a.Z[row + k], p = Uin[row + k];
