@@ -1500,22 +1500,41 @@ __global__ __launch_bounds__(TB) void k_b_gvdot(BArgs a) {
       for (int c = ((gw - off) % nw + nw) % nw; c < cnt; c += nw) {
         const int64_t slot = static_cast<int64_t>(s) * a.Kp + ch * VC + c;
         const int g = a.cidx[slot];
+        const int64_t g0 = a.gptr[g], g1 = a.gptr[g + 1];
         double s2 = 0.0;
-        for (int64_t k = a.gptr[g]; k < a.gptr[g + 1]; ++k) {
-          const uint16_t* col = a.dcm + k * a.Np;
-          double acc = 0.0;
-          for (int n0 = lane * 8; n0 < a.Np; n0 += BW * 8) {
-            const uint4 d = ldg16(col + n0);
-            const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+        // AB atoms of the group at a time, each with its own accumulator (the same FMA
+        // sequence per atom as one atom at a time): theta's rows are loaded once for all of
+        // them and their column loads are in flight together
+        constexpr int AB = 8;
+        for (int64_t k0 = g0; k0 < g1; k0 += AB) {
+          const int na = static_cast<int>(min(static_cast<int64_t>(AB), g1 - k0));
+          double acc[AB];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double2 t2 = *reinterpret_cast<const double2*>(th + n0 + 2 * q);
-              acc = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2.x, acc);
-              acc = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2.y, acc);
+          for (int j = 0; j < AB; ++j) acc[j] = 0.0;
+          for (int n0 = lane * 8; n0 < a.Np; n0 += BW * 8) {
+            double2 t2[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t2[q] = *reinterpret_cast<const double2*>(th + n0 + 2 * q);
+            uint4 d[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) d[j] = ldg16(a.dcm + (k0 + min(j, na - 1)) * a.Np + n0);
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+              const uint32_t w[4] = {d[j].x, d[j].y, d[j].z, d[j].w};
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                acc[j] = fma(static_cast<double>(__uint_as_float(w[q] << 16)), t2[q].x, acc[j]);
+                acc[j] = fma(static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)), t2[q].y, acc[j]);
+              }
             }
           }
-          acc = wave_sum(acc);
-          s2 = fma(acc, acc, s2);
+#pragma unroll
+          for (int j = 0; j < AB; ++j) {
+            if (j < na) {
+              const double v = wave_sum(acc[j]);
+              s2 = fma(v, v, s2);
+            }
+          }
         }
         if (lane == 0) a.cval[slot] = sqrt(s2) / a.gw[g];
       }
