@@ -993,11 +993,22 @@ __global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA
       int nact = 0, nsup = 0;
       uint32_t bits = 0u;
       if (tile_on[ia][ib]) {
+        // margins, momentum point and iterate of the lane's 16 atoms in one round trip
+        // (loaded whether or not an atom is active; a branch before them would let each
+        // wait for the previous group's)
+        float4 m4q[4], u4q[4], x4q[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t o = static_cast<int64_t>(bl) * a.Kp + a0 + 8 * q + (lane / MT) * 4;
+          m4q[q] = *reinterpret_cast<const float4*>(a.marg + o);
+          u4q[q] = *reinterpret_cast<const float4*>(Uin + o);
+          x4q[q] = *reinterpret_cast<const float4*>(a.X + o);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int ab = a0 + 8 * q + (lane / MT) * 4;
           const int64_t o = static_cast<int64_t>(bl) * a.Kp + ab;
-          const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
+          const float4 m4 = m4q[q];
           const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
           bool any = false;
 #pragma unroll
@@ -1007,8 +1018,8 @@ __global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA
           *reinterpret_cast<float4*>(a.Z + o) =
               make_float4(static_cast<float>(zq[0]), static_cast<float>(zq[1]),
                           static_cast<float>(zq[2]), static_cast<float>(zq[3]));
-          const float4 u4 = *reinterpret_cast<const float4*>(Uin + o);
-          const float4 x4 = *reinterpret_cast<const float4*>(a.X + o);
+          const float4 u4 = u4q[q];
+          const float4 x4 = x4q[q];
           float uu[4] = {u4.x, u4.y, u4.z, u4.w};
           float xx[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
