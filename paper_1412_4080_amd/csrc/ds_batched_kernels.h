@@ -953,10 +953,15 @@ __global__ __launch_bounds__(BW * RA * RB) __attribute__((amdgpu_waves_per_eu(WA
         if (!sub_on[ia][ib]) continue;
         const int a0 = a0b + wal + MT * ia;
         if (tile_on[ia][ib]) {
+          float4 m4q[4];  // the lane's margins in one round trip
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            m4q[q] = *reinterpret_cast<const float4*>(
+                a.marg + static_cast<int64_t>(bl) * a.Kp + a0 + 8 * q + (lane / MT) * 4);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t o = static_cast<int64_t>(bl) * a.Kp + a0 + 8 * q + (lane / MT) * 4;
-            const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
+            const float4 m4 = m4q[q];
             if (!(static_cast<double>(m4.x) <= r_act[ib] || static_cast<double>(m4.y) <= r_act[ib] ||
                   static_cast<double>(m4.z) <= r_act[ib] || static_cast<double>(m4.w) <= r_act[ib]))
               continue;
