@@ -224,16 +224,17 @@ __global__ __launch_bounds__(BLK) void k_setup_gemv(const T* __restrict__ D, int
     wave_dots<T, VV, CPW, VECTOR>(cols, v, N, lane, acc);
     double sq[CPW];
     if constexpr (NORMS) {
+      // columns past nc repeat the last one (their sums are never picked), so every load
+      // is unconditional and a row step's loads are in flight together
 #pragma unroll
       for (int c = 0; c < CPW; ++c) sq[c] = 0.0;
+#pragma unroll 4
       for (int e = lane; e < N; e += WAVE) {
+        double d[CPW];
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          if (c < nc) {
-            const double d = to_double(cols[c][e]);
-            sq[c] = fma(d, d, sq[c]);
-          }
-        }
+        for (int c = 0; c < CPW; ++c) d[c] = to_double(cols[c][e]);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) sq[c] = fma(d[c], d[c], sq[c]);
       }
     }
 #pragma unroll
