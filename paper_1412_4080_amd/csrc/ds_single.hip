@@ -191,14 +191,21 @@ ds_status upload_groups(const ds_problem& P, char* base, const Layout& l, hipStr
   return DS_OK;
 }
 
-// Zero `bytes` (a multiple of 4) at p with the fill kernel.
-ds_status zero_words(void* p, size_t bytes, hipStream_t s) {
-  const int64_t n = static_cast<int64_t>(bytes / 4);
-  hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, BLK, 1024)), dim3(BLK), 0, s,
-                     static_cast<uint32_t*>(p), n);
-  DS_HIP(hipGetLastError());
-  return DS_OK;
+// Several word ranges cleared by one launch (a fill kernel, not a memset: no memset node
+// if the caller captures the stream).
+struct ZeroRanges {
+  static constexpr int MAX = 8;
+  uint32_t* p[MAX];
+  int64_t n[MAX];
+  int count;
+};
+__global__ __launch_bounds__(BLK) void k_zero_ranges(ZeroRanges r) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * BLK + threadIdx.x;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * BLK;
+  for (int k = 0; k < r.count; ++k)
+    for (int64_t i = i0; i < r.n[k]; i += step) r.p[k][i] = 0u;
 }
+
 
 // Setup passes shared by lambda_max and the solve: z0 = D^T y, atom norms, group norms.
 template <typename T, bool VEC>
@@ -278,9 +285,24 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   a.tele_cap = static_cast<int32_t>(tele_cap);
   a.screen_static = prm.screening;
   if ((st_ = upload_groups(P, base, l, s)) != DS_OK) return st_;
-  if ((st_ = zero_words(a.counters, 32 * 4, s)) != DS_OK) return st_;
-  if ((st_ = zero_words(a.rt_cnt, MAXRT * 4, s)) != DS_OK) return st_;
-  if ((st_ = zero_words(a.lbA, MAXB * 8, s)) != DS_OK) return st_;
+  {
+    // counters, arrival counts, look-back words; the backtracking and Chambolle-Pock
+    // partials (read by the residual pass before a correlation pass writes them)
+    ZeroRanges zr{};
+    auto add = [&](void* ptr, size_t bytes) {
+      zr.p[zr.count] = static_cast<uint32_t*>(ptr);
+      zr.n[zr.count] = static_cast<int64_t>(bytes / 4);
+      ++zr.count;
+    };
+    add(a.counters, 32 * 4);
+    add(a.rt_cnt, MAXRT * 4);
+    add(a.lbA, MAXB * 8);
+    add(a.bpd, 2 * MAXB * 8);
+    add(a.rtr, 2 * MAXRT * 8);
+    add(a.dtn, MAXRT * 8);
+    hipLaunchKernelGGL(k_zero_ranges, dim3(64), dim3(BLK), 0, s, zr);
+    DS_HIP(hipGetLastError());
+  }
 
   // ---- setup (no host synchronisation) ----
   if ((st_ = launch_setup_corr<T, VEC>(P, y, base, l, s)) != DS_OK) return st_;
@@ -293,9 +315,6 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   const bool bt = line_search || RULE == RULE_CP;
   const double eta = line_search ? (prm.bt_eta > 0.0 ? prm.bt_eta : 2.0) : 0.0;
   a.bt = bt ? 1 : 0;
-  if ((st_ = zero_words(a.bpd, 2 * MAXB * 8, s)) != DS_OK) return st_;
-  if ((st_ = zero_words(a.rtr, 2 * MAXRT * 8, s)) != DS_OK) return st_;
-  if ((st_ = zero_words(a.dtn, MAXRT * 8, s)) != DS_OK) return st_;
   double L = prm.step_L;
   if (!(L > 0.0) && !line_search) {
     if (ws.fixed) {  // the estimate would need a workspace of its own
