@@ -84,6 +84,11 @@ typedef struct {
   ds_dtype dtype;
   int64_t N;                 /* signal dimension, >= 1 */
   int64_t K;                 /* number of atoms, >= 1 */
+                             /* Single-signal, multi-signal FP32/FP64 and served solves cover
+                                N <= 262144 * e rows, e = 16 bytes / element size when D and
+                                ldd * element size are 16-byte aligned (else e = 1), and at
+                                most 262144 atoms (Lasso) or 131072 groups; a larger problem
+                                returns DS_EINVAL before any device work. */
   int64_t ldd;               /* leading dimension of D, >= N */
   const void* D;             /* device pointer, column-major N x K */
   int64_t G;                 /* 0: Lasso.  > 0: Group-Lasso with G groups */

@@ -246,6 +246,9 @@ ds_status solve_common(const ds_problem* problem, const void* Y, int64_t B, int6
       return DS_EINVAL;
     }
   }
+  // every path but the batched bfloat16 one runs single-signal solves
+  if (!(B > 1 && problem->dtype == DS_BF16) && (e = single_shape_check(*problem)) != DS_OK)
+    return e;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
@@ -379,6 +382,7 @@ ds_status ds_solve_one(const ds_problem* problem, const void* y, double lambda,
   }
   if (!(lambda > 0.0) || !std::isfinite(lambda)) { set_error("lambda must be positive"); return DS_EINVAL; }
   if (trace != nullptr && trace_cap < 0) { set_error("trace_cap < 0"); return DS_EINVAL; }
+  if ((e = single_shape_check(*problem)) != DS_OK) return e;
   int dev = 0;
   DS_HIP(hipGetDevice(&dev));
   DeviceCtx& ctx = device_ctx(dev);

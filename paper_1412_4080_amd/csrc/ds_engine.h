@@ -86,6 +86,12 @@ ds_status validate_params(const ds_params* p);
 // The Dome test is stated for the Lasso: DS_EINVAL with a grouped problem.
 ds_status validate_test_for(const ds_params* p, bool group);
 
+// Whether the single-signal kernels cover a problem shape: the residual pass's row tiles
+// and the correlation pass's blocks have fixed maxima.  DS_EINVAL, with the limits in the
+// error string, otherwise.  Host arithmetic only; vec: the dictionary takes 16-byte loads
+// (16-byte aligned base and column stride).
+ds_status single_shape_check(int32_t dtype, int64_t N, int64_t K, int64_t G, bool vec);
+ds_status single_shape_check(const ds_problem& P);
 ds_status solve_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,
                        void* x, ds_info* info, hipStream_t stream, Workspace& ws,
                        std::vector<Telemetry>* tele_out, uint8_t* screened = nullptr);

@@ -57,6 +57,7 @@ extern "C" ds_status ds_solve_one_noalloc(const ds_problem* problem, const void*
               "ds_spectral_norm_sq gives it once per dictionary)");
     return DS_EINVAL;
   }
+  if ((e = single_shape_check(*problem)) != DS_OK) return e;
   const size_t need = single_workspace_bytes(*problem, *params);
   if (need > SCRATCH_BYTES) {
     set_error("the problem needs %zu bytes of scratch memory; ds_solve_one_noalloc has %zu "

@@ -631,6 +631,10 @@ ds_status ds_server_add_dict(void* server, const ds_problem* problem, ds_dtype s
     set_error("store precision must equal the input's, or be DS_BF16 for DS_F32 input");
     return DS_EINVAL;
   }
+  // the workers serve every dictionary with single-signal solves on the server's copy,
+  // whose base and column stride are 16-byte aligned
+  if ((e = single_shape_check(store_raw, problem->N, problem->K, problem->G, true)) != DS_OK)
+    return e;
   DS_HIP(hipSetDevice(S->cfg.device));
   auto d = std::make_unique<Dict>();
   d->store = store;

@@ -273,10 +273,11 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
                      std::vector<Telemetry>* tele_out, uint8_t* screened) {
   using V = typename Types<T>::V;
   using A = typename Types<T>::A;
+  ds_status st_ = single_shape_check(P.dtype, P.N, P.K, P.G, VEC);
+  if (st_ != DS_OK) return st_;
   const int64_t tele_cap = std::max<int32_t>(prm.max_iter, 1);
   const Layout l = make_layout(P.N, P.K, P.G, sizeof(V), sizeof(A), tele_cap, false);
-  ds_status st_ = ws.reserve(l.total);
-  if (st_ != DS_OK) return st_;
+  if ((st_ = ws.reserve(l.total)) != DS_OK) return st_;
   char* base = static_cast<char*>(ws.base);
   const int test = static_cast<int>(prm.test), rule = RULE;
   SingleArgs<T, V, A> a = make_args<T>(P, y, base, l, test, rule);
@@ -378,11 +379,6 @@ ds_status run_single(const ds_problem& P, const void* y, double lam, const ds_pa
   };
   int grid_corr = static_cast<int>(l.grid_corr);  // correlation launches of this chunk
   int grid_res_read = grid_corr;                  // grid the last residual pass read
-  if (nrt > MAXRT || l.grid_corr > MAXB || l.nsg > MAXITEM) {
-    set_error("problem too large for one device solve (N <= %d, units <= %d)", MAXRT * WAVE,
-              MAXB * (P.G > 0 ? CBG : CBL));
-    return DS_EINVAL;
-  }
   StatAccum& S = stats();
   bool stat_on;
   {
@@ -616,6 +612,28 @@ size_t single_workspace_bytes(const ds_problem& P, const ds_params& prm) {
   const size_t vsz = P.dtype == DS_F64 ? 8 : 4;
   const int64_t tele_cap = std::max<int32_t>(prm.max_iter, 1);
   return make_layout(P.N, P.K, P.G, vsz, sizeof(double), tele_cap, false).total;
+}
+
+ds_status single_shape_check(int32_t dtype, int64_t N, int64_t K, int64_t G, bool vec) {
+  const int64_t esz = dtype == DS_F64 ? 8 : dtype == DS_F32 ? 4 : 2;
+  const int64_t rows = static_cast<int64_t>(WAVE) * (vec ? 16 / esz : 1);  // rows of a row tile
+  const int64_t nrt = (N + rows - 1) / rows;
+  const int64_t gc = corr_blocks(K, G);
+  const int64_t nsg = (gc + (G > 0 ? SGG : SGL) - 1) / (G > 0 ? SGG : SGL);
+  if (nrt > MAXRT || gc > MAXB || nsg > MAXITEM) {
+    set_error("problem too large for one device solve: N <= %lld rows (%s), at most %lld %s",
+              static_cast<long long>(MAXRT) * rows,
+              vec ? "16-byte aligned D and ldd" : "unaligned D or ldd",
+              static_cast<long long>(MAXB) * (G > 0 ? CBG : CBL), G > 0 ? "groups" : "atoms");
+    return DS_EINVAL;
+  }
+  return DS_OK;
+}
+
+ds_status single_shape_check(const ds_problem& P) {
+  const size_t esz = P.dtype == DS_F64 ? 8 : P.dtype == DS_F32 ? 4 : 2;
+  const bool vec = reinterpret_cast<uintptr_t>(P.D) % 16 == 0 && (P.ldd * esz) % 16 == 0;
+  return single_shape_check(P.dtype, P.N, P.K, P.G, vec);
 }
 
 ds_status solve_single(const ds_problem& P, const void* y, double lam, const ds_params& prm,

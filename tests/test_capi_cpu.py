@@ -212,3 +212,40 @@ def test_plain_c_client_compiles_links_and_runs(B, tmp_path):
     version, status, message = out.stdout.strip().split("|")
     assert version.startswith("dynscreen") and int(status) == B.DS_EINVAL
     assert "NULL" in message
+
+
+@pytest.mark.parametrize("dtype,N,ldd,K,G,limit", [
+    ("f32", 1_048_577, 1_048_580, 10, 0, "N <= 1048576 rows"),  # 16-byte loads: 256-row tiles
+    ("f32", 262_145, 262_146, 10, 0, "N <= 262144 rows"),       # ldd * 4 not 16-byte aligned
+    ("f64", 524_289, 524_290, 10, 0, "N <= 524288 rows"),
+    ("bf16", 2_097_153, 2_097_160, 10, 0, "N <= 2097152 rows"),
+    ("f32", 100, 100, 262_145, 0, "at most 262144 atoms"),
+    ("f32", 100, 100, 131_073, 131_073, "at most 131072 groups"),
+])
+def test_shapes_beyond_the_single_signal_kernels_refused_before_device_work(B, dtype, N, ldd, K,
+                                                                          G, limit):
+    """The residual pass has at most 4096 row tiles and the correlation pass at most 16384
+    blocks (16 atoms or 8 groups each): a larger problem is refused on the host by every
+    entry point that runs single-signal solves, before any device call (here there is no
+    device, so reaching one would return DS_EDEVICE).  The pointers are never read."""
+    import numpy as np
+    gp = np.arange(G + 1, dtype=np.int64) if G else None
+    p = B.Problem(B.DTYPES[dtype], N, K, ldd, C.c_void_p(0x1000), G,
+                  gp.ctypes.data_as(C.POINTER(C.c_int64)) if G else None, None)
+    prm = B.make_params(step_L=1.0)
+    lam = (C.c_double * 2)(0.5, 0.5)
+    info = (B.Info * 2)()
+    solve = B._lib.glasso_solve if G else B._lib.lasso_solve
+    nb = 1 if dtype == "bf16" else 2  # more than one bfloat16 signal runs on the batched path
+    assert solve(C.byref(p), C.c_void_p(0x2000), nb, N, lam, C.byref(prm), C.c_void_p(0x3000),
+                 K, info, None) == B.DS_EINVAL
+    assert "too large" in B.last_error() and limit in B.last_error()
+    one = B.Info()
+    assert B._lib.ds_solve_one(C.byref(p), C.c_void_p(0x2000), C.c_double(0.5), C.byref(prm),
+                               C.c_void_p(0x3000), None, None, 0, C.byref(one),
+                               None) == B.DS_EINVAL
+    assert limit in B.last_error()
+    assert B._lib.ds_solve_one_noalloc(C.byref(p), C.c_void_p(0x2000), C.c_double(0.5),
+                                       C.byref(prm), C.c_void_p(0x3000), None, C.byref(one),
+                                       None) == B.DS_EINVAL
+    assert limit in B.last_error()

@@ -201,3 +201,21 @@ def test_error_codes(B):
     assert B.DS_EBUSY in codes, codes
     _collect(S, ids, {k: (r, 0) for k, r in enumerate(rids)})
     S.close()
+
+
+def test_dictionary_beyond_the_single_signal_kernels_refused(B):
+    """The workers serve every dictionary with single-signal solves, so a dictionary with more
+    atoms than the correlation pass covers (16384 blocks of 16) is refused when it is added,
+    before its copy is made (the dictionary pointer is never read); the server goes on
+    serving."""
+    import ctypes as C
+    dicts = _dicts()[:1]
+    S, ids = _server(B, dicts, max_slots=1)
+    p = B.Problem(B.DTYPES["f32"], 100, 262_145, 100, C.c_void_p(0x1000), 0, None, None)
+    did = C.c_int32()
+    st = B._lib.ds_server_add_dict(S._h, C.byref(p), B.DTYPES["bf16"], C.byref(did))
+    assert st == B.DS_EINVAL and "at most 262144 atoms" in B.last_error()
+    y = datagen.to_storage(datagen.lasso_signal(dicts[0][1], 3)[0], "f32").astype(np.float32)
+    rid = S.submit(ids[0], y, 0.5)
+    _collect(S, ids, {0: (rid, 0)})
+    S.close()

@@ -74,14 +74,14 @@ def test_noalloc_refusals(B):
     assert e.value.status == B.DS_EINVAL and "step_L" in str(e.value)
     # a problem whose workspace exceeds the array is refused on the host, before any launch
     # (the dictionary pointer is never read)
-    K = 4_000_000
-    prob = B.Problem(B.DTYPES["f32"], 200, K, 200, C.c_void_p(Dd.data_ptr()), 0, None, None)
     prm = B.make_params(step_L=L)
     x = torch.empty(16, dtype=torch.float32, device="cuda")
     info = B.Info()
-    st = B._lib.ds_solve_one_noalloc(C.byref(prob), C.c_void_p(yd.data_ptr()), 0.5, C.byref(prm),
-                                     C.c_void_p(x.data_ptr()), None, C.byref(info),
-                                     B._stream_ptr(None))
-    assert st == B.DS_EINVAL and "scratch" in B.last_error()
+    for N, K, why in ((100_000, 200_000, "scratch"), (200, 4_000_000, "too large")):
+        prob = B.Problem(B.DTYPES["f32"], N, K, N, C.c_void_p(Dd.data_ptr()), 0, None, None)
+        st = B._lib.ds_solve_one_noalloc(C.byref(prob), C.c_void_p(yd.data_ptr()), 0.5,
+                                         C.byref(prm), C.c_void_p(x.data_ptr()), None,
+                                         C.byref(info), B._stream_ptr(None))
+        assert st == B.DS_EINVAL and why in B.last_error()
     # the entry point still works afterwards
     _same(B, Dd, yd, L, 0.5, rule="fista", test="dst3", gap_tol=1e-6, max_iter=20000)
