@@ -1217,11 +1217,21 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
   const int ntile = a.G > 0 ? (a.G + GCH - 1) / GCH : a.Kp / MT;
   const int cb = a.G > 0 ? 16 : 8;
   const int cm = (1 << cb) - 1;
+  // Every load is issued before the first wait, at clamped indices: the signal's state
+  // (each of its TG threads reads the same words), the first row-block partials of theta
+  // and the first QT tile entries of this thread (all of them while ntile <= TG * QT).
+  // The sums then run in the same order as one entry at a time.
+  Inst& st = a.inst[s];
+  const int t_done = st.done, t_iter = st.iter;
+  const double lam = st.lam, yy = st.yy, rho2 = st.rho2;
+  const double act_sum = st.act_sum, sup_sum = st.sup_sum, r_min = st.r_min;
+  const double r_keep_old = st.r_keep, l_prev = st.l_prev, r_scr_old = st.r_scr;
+  const double marg_slack = st.marg_slack, gap_tol_abs = st.gap_tol_abs;
+  const int64_t oc = static_cast<int64_t>(min(tg, a.nrb - 1)) * a.Bp + s;
+  const double tt0 = a.ptt[oc], ty0 = a.pty[oc];
   double zm = 0.0, om = 0.0;
   int nact = 0, nsup = 0;
-  // QT entries per thread per round trip: unconditional loads at clamped indices, then the
-  // sums in entry order
-  constexpr int QT = 8;
+  constexpr int QT = 24;
   for (int t0 = tg; t0 < ntile; t0 += TG * QT) {
     double qz[QT], qo[QT];
     int qa[QT];
@@ -1242,8 +1252,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
       }
     }
   }
-  double tt = 0.0, ty = 0.0;
-  for (int c = tg; c < a.nrb; c += TG) {
+  double tt = tg < a.nrb ? tt0 : 0.0, ty = tg < a.nrb ? ty0 : 0.0;
+  for (int c = tg + TG; c < a.nrb; c += TG) {
     tt += a.ptt[static_cast<int64_t>(c) * a.Bp + s];
     ty += a.pty[static_cast<int64_t>(c) * a.Bp + s];
   }
@@ -1264,14 +1274,8 @@ __global__ __launch_bounds__(TB) void k_b_scalars(BArgs a) {
     nact += r_a[k][sl];
     nsup += r_s[k][sl];
   }
-  Inst& st = a.inst[s];
-  if (st.done != 0) return;
-  // every field read before the first store: a load issued after a store waits for it
-  const int t = st.iter + 1;
-  const double lam = st.lam, yy = st.yy, rho2 = st.rho2;
-  const double act_sum = st.act_sum, sup_sum = st.sup_sum, r_min = st.r_min;
-  const double r_keep_old = st.r_keep, l_prev = st.l_prev, r_scr_old = st.r_scr;
-  const double marg_slack = st.marg_slack, gap_tol_abs = st.gap_tol_abs;
+  if (t_done != 0) return;
+  const int t = t_iter + 1;
   const double sb = zm > 0.0 ? 1.0 / zm : 1e300;
   double mu = 0.0;
   if (tt > 0.0) mu = fmin(fmax(ty / (lam * tt), -sb), sb);
