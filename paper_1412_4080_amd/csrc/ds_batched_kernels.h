@@ -1628,11 +1628,13 @@ __global__ __launch_bounds__(TB) void k_b_vfin(BArgs a) {
 __global__ __launch_bounds__(TB) void k_b_screen(BArgs a) {
   const int s = blockIdx.y;
   const Inst& st = a.inst[s];
-  if (st.done != 0 || !(st.r_keep < st.r_prev)) return;
   const int i4 = (blockIdx.x * TB + threadIdx.x) * 4;
-  if (i4 >= a.Kp) return;
+  // the state and the tile's minimum margin in one round trip (index clamped into the row)
+  const float tm = a.tminm[static_cast<int64_t>(min(i4, a.Kp - 4) / MT) * a.Bp + s];
+  const int done = st.done;
   const double rk = st.r_keep, rp = st.r_prev;
-  if (!(static_cast<double>(a.tminm[static_cast<int64_t>(i4 / MT) * a.Bp + s]) <= rp)) return;
+  if (done != 0 || !(rk < rp) || i4 >= a.Kp) return;
+  if (!(static_cast<double>(tm) <= rp)) return;
   const int64_t o = static_cast<int64_t>(s) * a.Kp + i4;
   const float4 m4 = *reinterpret_cast<const float4*>(a.marg + o);
   const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
